@@ -1,0 +1,1217 @@
+/*
+ * ckks_oracle.c -- plain, slow CPU reference of RNS-CKKS and of the SecPE
+ * encrypted Argmax.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests/, the smoke check and the CPU-baseline
+ * leg of the benchmark may load this library.  It shares no code, headers or
+ * tables with the GPU library; the only things both sides agree on are the
+ * conventions written out below (each side implements them on its own).
+ *
+ * Paper: "SecPE: Secure Prompt Ensembling for Private and Robust Large Language
+ * Models" (arXiv 2502.00847).
+ *   - RNS-CKKS over R_Q = Z_Q[X]/(X^N+1), Q = prod q_i            (Sec. 2.2)
+ *   - homomorphic add/sub/mult, RotL/RotR                          (Sec. 2.2)
+ *   - Argmax z_i = Sign(y_i - y_max) + 1                           (Sec. 3.2, Eq. 2)
+ *   - Sign = f^{d_f}(g^{d_g}(x)), degree-9 f and g, BSGS evaluation (Sec. 3.2, Eq. 3-4)
+ *   - normalisation (x - D_min)/(D_max - D_min)                    (Sec. 3.2, Eq. 5)
+ *   - Max(a,b) = (a+b)/2 + (a-b)/2 * Sign(a-b)                     (Sec. 3.2, Eq. 6)
+ *   - ARGMAX / QuickMax                                            (Sec. 3.2, Algorithm 1)
+ *   - bootstrapping refreshes a low-level ciphertext               (Sec. 2.2; Sec. 4.1)
+ *
+ * Arithmetic is deliberately the most obvious kind: every modular product is a
+ * 128-bit product reduced with '%', every NTT is the textbook bit-reversed
+ * radix-2 transform of a psi-twisted vector, basis conversion and rescaling are
+ * the formulas themselves.  Ciphertexts are held in the coefficient domain with
+ * canonical residues in [0, q).
+ *
+ * Conventions the paper leaves open (each fixed here and in the GPU library
+ * independently):
+ *   primes   chain: primes = 1 mod 2N nearest 2^qbits, alternately the next one
+ *            below and the next one above (q0 below); special: the largest
+ *            primes = 1 mod 2N below 2^pbits.
+ *   PRNG     SplitMix64 (Steele, Lea, Flood 2014) used counter-based:
+ *            key = mix(seed ^ mix(tag)), draw(key,i) = mix(key + (i+1)*gamma).
+ *   samplers ternary secret mulhi64(r,3)-1; error = centred binomial eta=21;
+ *            uniform mod q = floor(((r0<<64)|r1) * q / 2^128).
+ *   encode   m_k = round-half-away(scale * 2/N * sum_j z_j cos(pi*(5^j k mod 2N)/N)),
+ *            evaluated in binary128.
+ *   rescale  c' = (c - [c]_{q_l}centred) * q_l^{-1}.
+ *   keyswitch hybrid: digits of alpha consecutive chain primes, gadget
+ *            P*(Q/D_j)*[(Q/D_j)^{-1}]_{D_j}; ModUp = approximate conversion
+ *            sum_i [x_i (D/q_i)^{-1}]_{q_i} (D/q_i); ModDown = (c - Conv_P(c)) * P^{-1}.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <stdio.h>
+#include <math.h>
+#include <quadmath.h>
+
+typedef unsigned __int128 u128;
+typedef __int128 i128;
+
+#define ORC_API __attribute__((visibility("default")))
+
+static void die(const char* msg) {
+  fprintf(stderr, "ckks_oracle: %s\n", msg);
+  abort();
+}
+
+/* ------------------------------------------------------------------------- */
+/* modular arithmetic                                                         */
+/* ------------------------------------------------------------------------- */
+static inline uint64_t mmul(uint64_t a, uint64_t b, uint64_t q) { return (uint64_t)(((u128)a * b) % q); }
+static inline uint64_t madd(uint64_t a, uint64_t b, uint64_t q) { return (uint64_t)(((u128)a + b) % q); }
+static inline uint64_t msub(uint64_t a, uint64_t b, uint64_t q) { return (uint64_t)(((u128)a + q - b) % q); }
+static inline uint64_t mneg(uint64_t a, uint64_t q) { return a == 0 ? 0 : q - a; }
+static uint64_t mpow(uint64_t a, uint64_t e, uint64_t q) {
+  uint64_t r = 1 % q;
+  a %= q;
+  while (e) {
+    if (e & 1) r = mmul(r, a, q);
+    a = mmul(a, a, q);
+    e >>= 1;
+  }
+  return r;
+}
+static uint64_t minv(uint64_t a, uint64_t q) { return mpow(a, q - 2, q); } /* q prime */
+static uint64_t from_i128(i128 x, uint64_t q) {
+  i128 r = x % (i128)q;
+  if (r < 0) r += q;
+  return (uint64_t)r;
+}
+
+static int is_prime(uint64_t n) {
+  static const uint64_t bases[12] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+  if (n < 2) return 0;
+  for (int i = 0; i < 12; ++i) {
+    if (n % bases[i] == 0) return n == bases[i];
+  }
+  uint64_t d = n - 1;
+  int s = 0;
+  while ((d & 1) == 0) { d >>= 1; ++s; }
+  for (int i = 0; i < 12; ++i) {
+    uint64_t x = mpow(bases[i], d, n);
+    if (x == 1 || x == n - 1) continue;
+    int composite = 1;
+    for (int r = 1; r < s; ++r) {
+      x = mmul(x, x, n);
+      if (x == n - 1) { composite = 0; break; }
+    }
+    if (composite) return 0;
+  }
+  return 1;
+}
+
+/* ------------------------------------------------------------------------- */
+/* counter-based SplitMix64                                                   */
+/* ------------------------------------------------------------------------- */
+#define SM_GAMMA 0x9E3779B97F4A7C15ULL
+static inline uint64_t sm_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+static inline uint64_t sm_key(uint64_t seed, uint64_t tag) { return sm_mix(seed ^ sm_mix(tag)); }
+static inline uint64_t sm_draw(uint64_t key, uint64_t i) { return sm_mix(key + (i + 1) * SM_GAMMA); }
+
+enum { PUR_SECRET = 1, PUR_RELIN = 2, PUR_GALOIS = 3, PUR_ENCRYPT = 4, PUR_REFRESH = 5 };
+#define LIMB_NONE 0xFFFu
+static inline uint64_t make_tag(uint64_t purpose, uint64_t obj, uint64_t sub, uint64_t limb) {
+  return (purpose << 56) | ((obj & 0xFFFFFFFFull) << 24) | ((sub & 0xFFFull) << 12) | (limb & 0xFFFull);
+}
+
+static int64_t sample_ternary(uint64_t key, uint64_t i) {
+  uint64_t r = sm_draw(key, i);
+  return (int64_t)(uint64_t)(((u128)r * 3) >> 64) - 1;
+}
+static int64_t sample_cbd21(uint64_t key, uint64_t i) {
+  uint64_t r = sm_draw(key, i);
+  const uint64_t m = (1ull << 21) - 1;
+  return (int64_t)__builtin_popcountll(r & m) - (int64_t)__builtin_popcountll((r >> 21) & m);
+}
+static uint64_t sample_uniform(uint64_t key, uint64_t i, uint64_t q) {
+  uint64_t hi = sm_draw(key, 2 * i), lo = sm_draw(key, 2 * i + 1);
+  u128 t = (u128)hi * q + (((u128)lo * q) >> 64);
+  return (uint64_t)(t >> 64);
+}
+
+/* ------------------------------------------------------------------------- */
+/* context                                                                    */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  uint64_t g;           /* Galois element; 0 marks the relinearisation key */
+  uint64_t*** b;        /* [digit][limb] NTT-domain vectors, limb over all primes */
+  uint64_t*** a;
+} orc_key;
+
+typedef struct {
+  int log_n, n;
+  int n_q, n_p, alpha, dnum;
+  int log_scale;
+  int dg, df;
+  int min_level;
+  uint64_t* mod;        /* n_q chain primes, then n_p special primes */
+  /* per prime NTT tables */
+  uint64_t** psi_pow;   /* psi^i */
+  uint64_t** psi_ipow;  /* psi^-i */
+  uint64_t** om_pow;    /* omega^i, omega = psi^2 */
+  uint64_t** om_ipow;   /* omega^-i */
+  uint64_t* n_inv;
+  __float128* cos_tab;  /* cos(pi t / N), t < 2N */
+  uint64_t* rot_group;  /* 5^j mod 2N, j < N/2 */
+  int64_t* s;           /* secret key, ternary */
+  orc_key* keys;
+  int n_keys;
+  int64_t counters[8];
+} orc_ctx;
+
+enum { CNT_SIGN = 0, CNT_ROT = 1, CNT_RELIN = 2, CNT_KS = 3, CNT_REFRESH = 4, CNT_POLY = 5, CNT_MAX = 6 };
+
+static void* xcalloc(size_t n, size_t sz) {
+  void* p = calloc(n, sz);
+  if (!p && n && sz) die("out of memory");
+  return p;
+}
+
+/* first prime = 1 mod 2N strictly below 'below', stepping down by 2N */
+static uint64_t prime_below(uint64_t start /* = 1 mod 2N */, uint64_t m2n, const uint64_t* taken, int n_taken) {
+  for (uint64_t c = start; c > m2n; c -= m2n) {
+    if (!is_prime(c)) continue;
+    int dup = 0;
+    for (int i = 0; i < n_taken; ++i) dup |= taken[i] == c;
+    if (!dup) return c;
+  }
+  die("no prime found");
+  return 0;
+}
+
+static void make_primes(orc_ctx* c, int q_bits, int p_bits) {
+  uint64_t m2n = 2ull * (uint64_t)c->n;
+  uint64_t base = 1ull << q_bits;
+  uint64_t below = base + 1 - m2n; /* next candidate below 2^qbits */
+  uint64_t above = base + 1;        /* next candidate above 2^qbits */
+  int k = 0;
+  while (k < c->n_q) {
+    if ((k & 1) == 0) {
+      while (!is_prime(below)) below -= m2n;
+      c->mod[k++] = below;
+      below -= m2n;
+    } else {
+      while (!is_prime(above)) above += m2n;
+      c->mod[k++] = above;
+      above += m2n;
+    }
+  }
+  uint64_t top = (1ull << p_bits) + 1 - m2n;
+  for (int j = 0; j < c->n_p; ++j) {
+    uint64_t p = prime_below(top, m2n, c->mod, c->n_q + j);
+    c->mod[c->n_q + j] = p;
+    top = p - m2n;
+  }
+}
+
+/* smallest quadratic non-residue x, psi = x^((q-1)/2N) has order exactly 2N */
+static uint64_t find_psi(uint64_t q, uint64_t n) {
+  for (uint64_t x = 2;; ++x) {
+    if (mpow(x, (q - 1) / 2, q) == q - 1) return mpow(x, (q - 1) / (2 * n), q);
+  }
+}
+
+ORC_API void* orc_create(int log_n, int n_q, int q_bits, int n_p, int p_bits, int log_scale,
+                         int dg, int df, int min_level) {
+  if (log_n < 3 || log_n > 17 || n_q < 2 || n_p < 1 || q_bits > 61 || p_bits > 61) die("bad parameters");
+  orc_ctx* c = (orc_ctx*)xcalloc(1, sizeof(orc_ctx));
+  c->log_n = log_n;
+  c->n = 1 << log_n;
+  c->n_q = n_q;
+  c->n_p = n_p;
+  c->alpha = n_p;
+  c->dnum = (n_q + n_p - 1) / n_p;
+  c->log_scale = log_scale;
+  c->dg = dg;
+  c->df = df;
+  c->min_level = min_level;
+  int np = n_q + n_p, n = c->n;
+  c->mod = (uint64_t*)xcalloc(np, sizeof(uint64_t));
+  make_primes(c, q_bits, p_bits);
+  c->psi_pow = (uint64_t**)xcalloc(np, sizeof(uint64_t*));
+  c->psi_ipow = (uint64_t**)xcalloc(np, sizeof(uint64_t*));
+  c->om_pow = (uint64_t**)xcalloc(np, sizeof(uint64_t*));
+  c->om_ipow = (uint64_t**)xcalloc(np, sizeof(uint64_t*));
+  c->n_inv = (uint64_t*)xcalloc(np, sizeof(uint64_t));
+  for (int t = 0; t < np; ++t) {
+    uint64_t q = c->mod[t];
+    uint64_t psi = find_psi(q, (uint64_t)n), psi_i = minv(psi, q);
+    uint64_t om = mmul(psi, psi, q), om_i = mmul(psi_i, psi_i, q);
+    c->psi_pow[t] = (uint64_t*)xcalloc(n, 8);
+    c->psi_ipow[t] = (uint64_t*)xcalloc(n, 8);
+    c->om_pow[t] = (uint64_t*)xcalloc(n, 8);
+    c->om_ipow[t] = (uint64_t*)xcalloc(n, 8);
+    uint64_t a = 1, b = 1, d = 1, e = 1;
+    for (int i = 0; i < n; ++i) {
+      c->psi_pow[t][i] = a; a = mmul(a, psi, q);
+      c->psi_ipow[t][i] = b; b = mmul(b, psi_i, q);
+      c->om_pow[t][i] = d; d = mmul(d, om, q);
+      c->om_ipow[t][i] = e; e = mmul(e, om_i, q);
+    }
+    c->n_inv[t] = minv((uint64_t)n, q);
+  }
+  c->cos_tab = (__float128*)xcalloc(2 * (size_t)n, sizeof(__float128));
+  for (int t = 0; t < 2 * n; ++t) c->cos_tab[t] = cosq(M_PIq * (__float128)t / (__float128)n);
+  c->rot_group = (uint64_t*)xcalloc(n / 2, 8);
+  uint64_t g = 1;
+  for (int j = 0; j < n / 2; ++j) { c->rot_group[j] = g; g = (g * 5) % (2 * (uint64_t)n); }
+  return c;
+}
+
+static void free_key(orc_ctx* c, orc_key* k) {
+  for (int j = 0; j < c->dnum; ++j) {
+    for (int t = 0; t < c->n_q + c->n_p; ++t) { free(k->b[j][t]); free(k->a[j][t]); }
+    free(k->b[j]); free(k->a[j]);
+  }
+  free(k->b); free(k->a);
+}
+
+ORC_API void orc_destroy(void* h) {
+  orc_ctx* c = (orc_ctx*)h;
+  if (!c) return;
+  int np = c->n_q + c->n_p;
+  for (int t = 0; t < np; ++t) { free(c->psi_pow[t]); free(c->psi_ipow[t]); free(c->om_pow[t]); free(c->om_ipow[t]); }
+  free(c->psi_pow); free(c->psi_ipow); free(c->om_pow); free(c->om_ipow); free(c->n_inv);
+  free(c->cos_tab); free(c->rot_group); free(c->s);
+  for (int i = 0; i < c->n_keys; ++i) free_key(c, &c->keys[i]);
+  free(c->keys); free(c->mod); free(c);
+}
+
+ORC_API int orc_num_primes(void* h) { orc_ctx* c = (orc_ctx*)h; return c->n_q + c->n_p; }
+ORC_API void orc_primes(void* h, uint64_t* out) {
+  orc_ctx* c = (orc_ctx*)h;
+  memcpy(out, c->mod, sizeof(uint64_t) * (size_t)(c->n_q + c->n_p));
+}
+ORC_API void orc_counters(void* h, int64_t* out) { memcpy(out, ((orc_ctx*)h)->counters, sizeof(int64_t) * 8); }
+ORC_API void orc_reset_counters(void* h) { memset(((orc_ctx*)h)->counters, 0, sizeof(int64_t) * 8); }
+
+/* ------------------------------------------------------------------------- */
+/* negacyclic NTT: twist by psi^i, textbook cyclic radix-2 transform          */
+/* ------------------------------------------------------------------------- */
+static void bit_reverse(uint64_t* a, int n) {
+  for (int i = 1, j = 0; i < n; ++i) {
+    int bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) { uint64_t t = a[i]; a[i] = a[j]; a[j] = t; }
+  }
+}
+static void cyclic_ntt(uint64_t* a, int n, const uint64_t* wpow, uint64_t q) {
+  bit_reverse(a, n);
+  for (int len = 2; len <= n; len <<= 1) {
+    int half = len >> 1, step = n / len;
+    for (int i = 0; i < n; i += len) {
+      for (int j = 0; j < half; ++j) {
+        uint64_t u = a[i + j], v = mmul(a[i + j + half], wpow[j * step], q);
+        a[i + j] = madd(u, v, q);
+        a[i + j + half] = msub(u, v, q);
+      }
+    }
+  }
+}
+/* forward: a(X) -> values a(psi * omega^k) in the cyclic transform's order */
+static void ntt_fwd(orc_ctx* c, int t, uint64_t* a) {
+  uint64_t q = c->mod[t];
+  for (int i = 0; i < c->n; ++i) a[i] = mmul(a[i], c->psi_pow[t][i], q);
+  cyclic_ntt(a, c->n, c->om_pow[t], q);
+}
+static void ntt_inv(orc_ctx* c, int t, uint64_t* a) {
+  uint64_t q = c->mod[t];
+  cyclic_ntt(a, c->n, c->om_ipow[t], q);
+  for (int i = 0; i < c->n; ++i) a[i] = mmul(mmul(a[i], c->n_inv[t], q), c->psi_ipow[t][i], q);
+}
+
+/* ring product in Z_q[X]/(X^N+1), coefficient domain in and out */
+static void ring_mul(orc_ctx* c, int t, const uint64_t* a, const uint64_t* b, uint64_t* out) {
+  int n = c->n;
+  uint64_t* x = (uint64_t*)xcalloc(n, 8);
+  uint64_t* y = (uint64_t*)xcalloc(n, 8);
+  memcpy(x, a, 8 * (size_t)n);
+  memcpy(y, b, 8 * (size_t)n);
+  ntt_fwd(c, t, x);
+  ntt_fwd(c, t, y);
+  for (int i = 0; i < n; ++i) x[i] = mmul(x[i], y[i], c->mod[t]);
+  ntt_inv(c, t, x);
+  memcpy(out, x, 8 * (size_t)n);
+  free(x);
+  free(y);
+}
+
+/* exported for the NTT pins: negacyclic product mod prime index t */
+ORC_API void orc_ring_mul(void* h, int t, const uint64_t* a, const uint64_t* b, uint64_t* out) {
+  ring_mul((orc_ctx*)h, t, a, b, out);
+}
+ORC_API void orc_ntt_roundtrip(void* h, int t, uint64_t* a) {
+  orc_ctx* c = (orc_ctx*)h;
+  ntt_fwd(c, t, a);
+  ntt_inv(c, t, a);
+}
+ORC_API uint64_t orc_psi(void* h, int t) { orc_ctx* c = (orc_ctx*)h; return c->psi_pow[t][1]; }
+
+/* ------------------------------------------------------------------------- */
+/* ciphertexts                                                                */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  int level;
+  double scale;
+  uint64_t* c[2]; /* (level+1) x N, coefficient domain, canonical residues */
+} orc_ct;
+
+static orc_ct* ct_new(orc_ctx* c, int level, double scale) {
+  orc_ct* x = (orc_ct*)xcalloc(1, sizeof(orc_ct));
+  x->level = level;
+  x->scale = scale;
+  for (int p = 0; p < 2; ++p) x->c[p] = (uint64_t*)xcalloc((size_t)(level + 1) * c->n, 8);
+  return x;
+}
+static void ct_free(orc_ct* x) {
+  if (!x) return;
+  free(x->c[0]);
+  free(x->c[1]);
+  free(x);
+}
+static orc_ct* ct_copy(orc_ctx* c, const orc_ct* a, int level) {
+  if (level > a->level) die("ct_copy: cannot raise level");
+  orc_ct* x = ct_new(c, level, a->scale);
+  for (int p = 0; p < 2; ++p) memcpy(x->c[p], a->c[p], 8 * (size_t)(level + 1) * c->n);
+  return x;
+}
+#define LIMB(ct, p, i, n) ((ct)->c[p] + (size_t)(i) * (n))
+
+ORC_API void* orc_ct_import(void* h, const uint64_t* data, int level, double scale) {
+  orc_ctx* c = (orc_ctx*)h;
+  orc_ct* x = ct_new(c, level, scale);
+  size_t sz = (size_t)(level + 1) * c->n;
+  memcpy(x->c[0], data, 8 * sz);
+  memcpy(x->c[1], data + sz, 8 * sz);
+  return x;
+}
+ORC_API void orc_ct_export(void* h, const void* ctp, uint64_t* data) {
+  orc_ctx* c = (orc_ctx*)h;
+  const orc_ct* x = (const orc_ct*)ctp;
+  size_t sz = (size_t)(x->level + 1) * c->n;
+  memcpy(data, x->c[0], 8 * sz);
+  memcpy(data + sz, x->c[1], 8 * sz);
+}
+ORC_API int orc_ct_level(const void* x) { return ((const orc_ct*)x)->level; }
+ORC_API double orc_ct_scale(const void* x) { return ((const orc_ct*)x)->scale; }
+ORC_API void orc_ct_free(void* x) { ct_free((orc_ct*)x); }
+
+/* ------------------------------------------------------------------------- */
+/* encoding: canonical embedding on the slots j <-> root zeta^(5^j)           */
+/* ------------------------------------------------------------------------- */
+static int64_t round_half_away_q(__float128 x) {
+  __float128 r = x >= 0 ? floorq(x + 0.5Q) : -floorq(-x + 0.5Q);
+  if (fabsq(r) > 9.2e18Q) die("encode: coefficient exceeds int64");
+  return (int64_t)r;
+}
+/* m_k = round(scale * 2/N * sum_j z_j cos(pi * (5^j * k mod 2N) / N)) for real slot values */
+static void encode_real(orc_ctx* c, const double* z, int nslots, double scale, int64_t* m) {
+  int n = c->n;
+  uint64_t m2n = 2ull * (uint64_t)n;
+  __float128 f = (__float128)scale * 2 / (__float128)n;
+  for (int k = 0; k < n; ++k) {
+    __float128 acc = 0;
+    for (int j = 0; j < nslots; ++j) {
+      if (z[j] == 0.0) continue;
+      uint64_t t = (c->rot_group[j] * (uint64_t)k) % m2n;
+      acc += (__float128)z[j] * c->cos_tab[t];
+    }
+    m[k] = round_half_away_q(f * acc);
+  }
+}
+ORC_API void orc_encode(void* h, const double* z, int nslots, double scale, int64_t* m) {
+  encode_real((orc_ctx*)h, z, nslots, scale, m);
+}
+/* real part of slot j: (1/scale) * sum_k m_k cos(pi * (5^j k mod 2N)/N) */
+static void decode_real(orc_ctx* c, const i128* m, double scale, int nslots, double* z) {
+  int n = c->n;
+  uint64_t m2n = 2ull * (uint64_t)n;
+  for (int j = 0; j < nslots; ++j) {
+    __float128 acc = 0;
+    for (int k = 0; k < n; ++k) {
+      if (m[k] == 0) continue;
+      uint64_t t = (c->rot_group[j] * (uint64_t)k) % m2n;
+      acc += (__float128)m[k] * c->cos_tab[t];
+    }
+    z[j] = (double)(acc / (__float128)scale);
+  }
+}
+ORC_API void orc_decode(void* h, const int64_t* m, double scale, int nslots, double* z) {
+  orc_ctx* c = (orc_ctx*)h;
+  i128* w = (i128*)xcalloc(c->n, sizeof(i128));
+  for (int k = 0; k < c->n; ++k) w[k] = m[k];
+  decode_real(c, w, scale, nslots, z);
+  free(w);
+}
+
+/* ------------------------------------------------------------------------- */
+/* key generation                                                             */
+/* ------------------------------------------------------------------------- */
+static void poly_from_small(orc_ctx* c, const int64_t* v, int t, uint64_t* out) {
+  for (int i = 0; i < c->n; ++i) out[i] = from_i128(v[i], c->mod[t]);
+}
+
+ORC_API void orc_gen_secret(void* h, uint64_t seed) {
+  orc_ctx* c = (orc_ctx*)h;
+  free(c->s);
+  c->s = (int64_t*)xcalloc(c->n, sizeof(int64_t));
+  uint64_t key = sm_key(seed, make_tag(PUR_SECRET, 0, 0, LIMB_NONE));
+  for (int i = 0; i < c->n; ++i) c->s[i] = sample_ternary(key, (uint64_t)i);
+}
+ORC_API void orc_get_secret(void* h, int64_t* out) { orc_ctx* c = (orc_ctx*)h; memcpy(out, c->s, 8 * (size_t)c->n); }
+
+/* sigma_g on an integer polynomial: X^i -> X^(i g mod 2N) with X^N = -1 */
+static void automorph_small(orc_ctx* c, const int64_t* in, uint64_t g, int64_t* out) {
+  uint64_t n = (uint64_t)c->n;
+  for (uint64_t i = 0; i < n; ++i) {
+    uint64_t j = (i * g) % (2 * n);
+    if (j < n) out[j] = in[i];
+    else out[j - n] = -in[i];
+  }
+}
+static void automorph_mod(orc_ctx* c, const uint64_t* in, uint64_t g, uint64_t q, uint64_t* out) {
+  uint64_t n = (uint64_t)c->n;
+  for (uint64_t i = 0; i < n; ++i) {
+    uint64_t j = (i * g) % (2 * n);
+    if (j < n) out[j] = in[i];
+    else out[j - n] = mneg(in[i], q);
+  }
+}
+
+/* P mod q_t, product of the special primes */
+static uint64_t p_mod(orc_ctx* c, int t) {
+  uint64_t r = 1 % c->mod[t];
+  for (int k = 0; k < c->n_p; ++k) r = mmul(r, c->mod[c->n_q + k] % c->mod[t], c->mod[t]);
+  return r;
+}
+
+/* switching key for s' -> s: per digit j (alpha consecutive chain primes at the
+   top level), b_j = -a_j s + e_j + P * T_j * s' (mod QP), T_j = 1 mod primes of
+   digit j and 0 mod the other chain primes. Stored in the NTT domain. */
+static void gen_switch_key(orc_ctx* c, orc_key* k, const int64_t* s_from, uint64_t seed, int purpose, uint64_t obj) {
+  int np = c->n_q + c->n_p, n = c->n;
+  k->b = (uint64_t***)xcalloc(c->dnum, sizeof(uint64_t**));
+  k->a = (uint64_t***)xcalloc(c->dnum, sizeof(uint64_t**));
+  uint64_t* sm = (uint64_t*)xcalloc(n, 8);
+  uint64_t* tmp = (uint64_t*)xcalloc(n, 8);
+  int64_t* e = (int64_t*)xcalloc(n, 8);
+  for (int j = 0; j < c->dnum; ++j) {
+    k->b[j] = (uint64_t**)xcalloc(np, sizeof(uint64_t*));
+    k->a[j] = (uint64_t**)xcalloc(np, sizeof(uint64_t*));
+    uint64_t ekey = sm_key(seed, make_tag((uint64_t)purpose, obj, (uint64_t)j, LIMB_NONE));
+    for (int i = 0; i < n; ++i) e[i] = sample_cbd21(ekey, (uint64_t)i);
+    for (int t = 0; t < np; ++t) {
+      uint64_t q = c->mod[t];
+      uint64_t* a = (uint64_t*)xcalloc(n, 8);
+      uint64_t* b = (uint64_t*)xcalloc(n, 8);
+      uint64_t akey = sm_key(seed, make_tag((uint64_t)purpose, obj, (uint64_t)j, (uint64_t)t));
+      for (int i = 0; i < n; ++i) a[i] = sample_uniform(akey, (uint64_t)i, q);
+      poly_from_small(c, c->s, t, sm);
+      ring_mul(c, t, a, sm, tmp);
+      int in_digit = t < c->n_q && t / c->alpha == j;
+      uint64_t pq = in_digit ? p_mod(c, t) : 0;
+      for (int i = 0; i < n; ++i) {
+        uint64_t v = msub(from_i128(e[i], q), tmp[i], q);
+        if (in_digit) v = madd(v, mmul(pq, from_i128(s_from[i], q), q), q);
+        b[i] = v;
+      }
+      ntt_fwd(c, t, a);
+      ntt_fwd(c, t, b);
+      k->a[j][t] = a;
+      k->b[j][t] = b;
+    }
+  }
+  free(sm);
+  free(tmp);
+  free(e);
+}
+
+static orc_key* find_key(orc_ctx* c, uint64_t g) {
+  for (int i = 0; i < c->n_keys; ++i)
+    if (c->keys[i].g == g) return &c->keys[i];
+  return NULL;
+}
+static orc_key* add_key(orc_ctx* c, uint64_t g) {
+  orc_key* old = find_key(c, g);
+  if (old) { free_key(c, old); return old; }
+  c->keys = (orc_key*)realloc(c->keys, sizeof(orc_key) * (size_t)(c->n_keys + 1));
+  orc_key* k = &c->keys[c->n_keys++];
+  memset(k, 0, sizeof(*k));
+  k->g = g;
+  return k;
+}
+
+static uint64_t galois_elt(orc_ctx* c, int64_t step) {
+  int64_t slots = c->n / 2;
+  int64_t r = ((step % slots) + slots) % slots;
+  return c->rot_group[r];
+}
+
+/* s is generated from the same seed; rotation keys for RotL(step) */
+ORC_API void orc_keygen(void* h, uint64_t seed, const int64_t* steps, int n_steps) {
+  orc_ctx* c = (orc_ctx*)h;
+  int n = c->n;
+  orc_gen_secret(h, seed);
+  /* relinearisation: s^2 -> s.  The coefficients of s^2 in Z[X]/(X^N+1) are
+     bounded by N < q_0/2, so the ring product mod q_0 lifted to (-q_0/2, q_0/2]
+     is s^2 itself. */
+  int64_t* s2 = (int64_t*)xcalloc(n, 8);
+  {
+    uint64_t q0 = c->mod[0];
+    uint64_t* sq = (uint64_t*)xcalloc(n, 8);
+    uint64_t* pr = (uint64_t*)xcalloc(n, 8);
+    poly_from_small(c, c->s, 0, sq);
+    ring_mul(c, 0, sq, sq, pr);
+    for (int i = 0; i < n; ++i) s2[i] = pr[i] > q0 / 2 ? (int64_t)pr[i] - (int64_t)q0 : (int64_t)pr[i];
+    free(sq);
+    free(pr);
+  }
+  orc_key* rk = add_key(c, 0);
+  rk->g = 0;
+  gen_switch_key(c, rk, s2, seed, PUR_RELIN, 0);
+  free(s2);
+  int64_t* sg = (int64_t*)xcalloc(n, 8);
+  for (int i = 0; i < n_steps; ++i) {
+    uint64_t g = galois_elt(c, steps[i]);
+    if (g == 1 || find_key(c, g)) continue;
+    automorph_small(c, c->s, g, sg);
+    orc_key* k = add_key(c, g);
+    gen_switch_key(c, k, sg, seed, PUR_GALOIS, g);
+  }
+  free(sg);
+}
+
+/* key limb in the coefficient domain (for parity checks) */
+ORC_API int orc_get_key(void* h, uint64_t g, int digit, int which, int t, uint64_t* out) {
+  orc_ctx* c = (orc_ctx*)h;
+  orc_key* k = find_key(c, g);
+  if (!k || digit >= c->dnum || t >= c->n_q + c->n_p) return -1;
+  memcpy(out, which ? k->a[digit][t] : k->b[digit][t], 8 * (size_t)c->n);
+  ntt_inv(c, t, out);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* encryption / decryption                                                    */
+/* ------------------------------------------------------------------------- */
+/* secret-key encryption of integer plaintext m at level 'level' */
+static orc_ct* encrypt_int(orc_ctx* c, const i128* m, double scale, uint64_t seed, int purpose, uint64_t sub, int level) {
+  int n = c->n;
+  orc_ct* x = ct_new(c, level, scale);
+  uint64_t ekey = sm_key(seed, make_tag((uint64_t)purpose, 0, sub, LIMB_NONE));
+  int64_t* e = (int64_t*)xcalloc(n, 8);
+  for (int i = 0; i < n; ++i) e[i] = sample_cbd21(ekey, (uint64_t)i);
+  uint64_t* sm = (uint64_t*)xcalloc(n, 8);
+  uint64_t* as = (uint64_t*)xcalloc(n, 8);
+  for (int t = 0; t <= level; ++t) {
+    uint64_t q = c->mod[t];
+    uint64_t* a = LIMB(x, 1, t, n);
+    uint64_t akey = sm_key(seed, make_tag((uint64_t)purpose, 0, sub, (uint64_t)t));
+    for (int i = 0; i < n; ++i) a[i] = sample_uniform(akey, (uint64_t)i, q);
+    poly_from_small(c, c->s, t, sm);
+    ring_mul(c, t, a, sm, as);
+    uint64_t* b = LIMB(x, 0, t, n);
+    for (int i = 0; i < n; ++i) b[i] = madd(msub(from_i128(m[i], q), as[i], q), from_i128(e[i], q), q);
+  }
+  free(e);
+  free(sm);
+  free(as);
+  return x;
+}
+
+ORC_API void* orc_encrypt(void* h, const int64_t* m, double scale, uint64_t seed) {
+  orc_ctx* c = (orc_ctx*)h;
+  i128* w = (i128*)xcalloc(c->n, sizeof(i128));
+  for (int i = 0; i < c->n; ++i) w[i] = m[i];
+  orc_ct* x = encrypt_int(c, w, scale, seed, PUR_ENCRYPT, 0, c->n_q - 1);
+  free(w);
+  return x;
+}
+
+/* m = c0 + c1 s, lifted to the centred integer from limbs 0 and 1 (CRT) */
+static void decrypt_int(orc_ctx* c, const orc_ct* x, i128* m) {
+  int n = c->n;
+  if (x->level < 1) die("decrypt needs at least two limbs");
+  uint64_t* sm = (uint64_t*)xcalloc(n, 8);
+  uint64_t* r[2];
+  for (int t = 0; t < 2; ++t) {
+    uint64_t q = c->mod[t];
+    r[t] = (uint64_t*)xcalloc(n, 8);
+    poly_from_small(c, c->s, t, sm);
+    ring_mul(c, t, LIMB(x, 1, t, n), sm, r[t]);
+    const uint64_t* b = LIMB(x, 0, t, n);
+    for (int i = 0; i < n; ++i) r[t][i] = madd(r[t][i], b[i], q);
+  }
+  uint64_t q0 = c->mod[0], q1 = c->mod[1];
+  uint64_t q0inv = minv(q0 % q1, q1);
+  i128 Q = (i128)q0 * (i128)q1;
+  for (int i = 0; i < n; ++i) {
+    /* x = r0 + q0 * ((r1 - r0) q0^-1 mod q1), in [0, q0 q1) */
+    uint64_t d = mmul(msub(r[1][i], r[0][i] % q1, q1), q0inv, q1);
+    i128 v = (i128)r[0][i] + (i128)q0 * (i128)d;
+    if (v > Q / 2) v -= Q;
+    m[i] = v;
+  }
+  free(sm);
+  free(r[0]);
+  free(r[1]);
+}
+
+ORC_API void orc_decrypt(void* h, const void* ctp, int64_t* m_out) {
+  orc_ctx* c = (orc_ctx*)h;
+  i128* m = (i128*)xcalloc(c->n, sizeof(i128));
+  decrypt_int(c, (const orc_ct*)ctp, m);
+  for (int i = 0; i < c->n; ++i) {
+    if (m[i] > (i128)INT64_MAX || m[i] < (i128)INT64_MIN) die("decrypt: message exceeds int64");
+    m_out[i] = (int64_t)m[i];
+  }
+  free(m);
+}
+
+ORC_API void orc_decrypt_decode(void* h, const void* ctp, int nslots, double* z) {
+  orc_ctx* c = (orc_ctx*)h;
+  const orc_ct* x = (const orc_ct*)ctp;
+  i128* m = (i128*)xcalloc(c->n, sizeof(i128));
+  decrypt_int(c, x, m);
+  decode_real(c, m, x->scale, nslots, z);
+  free(m);
+}
+
+/* ------------------------------------------------------------------------- */
+/* homomorphic operations                                                     */
+/* ------------------------------------------------------------------------- */
+static void check_scales(double a, double b) {
+  if (fabs(a - b) > 1e-9 * fabs(a)) die("scale mismatch in addition");
+}
+
+static orc_ct* op_add(orc_ctx* c, const orc_ct* a, const orc_ct* b, int sub) {
+  check_scales(a->scale, b->scale);
+  int lvl = a->level < b->level ? a->level : b->level;
+  orc_ct* x = ct_new(c, lvl, a->scale);
+  int n = c->n;
+  for (int p = 0; p < 2; ++p)
+    for (int t = 0; t <= lvl; ++t) {
+      uint64_t q = c->mod[t];
+      const uint64_t* u = LIMB(a, p, t, n);
+      const uint64_t* v = LIMB(b, p, t, n);
+      uint64_t* w = LIMB(x, p, t, n);
+      for (int i = 0; i < n; ++i) w[i] = sub ? msub(u[i], v[i], q) : madd(u[i], v[i], q);
+    }
+  return x;
+}
+
+/* add the real constant v to every slot: K = llround(v * scale) added to coefficient 0 */
+static void op_add_const_inplace(orc_ctx* c, orc_ct* x, double v) {
+  double kf = v * x->scale;
+  int64_t K = llround(kf);
+  for (int t = 0; t <= x->level; ++t) {
+    uint64_t q = c->mod[t];
+    uint64_t* w = LIMB(x, 0, t, c->n);
+    w[0] = madd(w[0], from_i128(K, q), q);
+  }
+}
+
+static void rescale_inplace(orc_ctx* c, orc_ct* x) {
+  int l = x->level, n = c->n;
+  if (l < 1) die("rescale at level 0");
+  uint64_t ql = c->mod[l];
+  for (int p = 0; p < 2; ++p) {
+    const uint64_t* top = LIMB(x, p, l, n);
+    for (int t = 0; t < l; ++t) {
+      uint64_t q = c->mod[t];
+      uint64_t inv = minv(ql % q, q);
+      uint64_t* w = LIMB(x, p, t, n);
+      for (int i = 0; i < n; ++i) {
+        i128 r = top[i] > ql / 2 ? (i128)top[i] - (i128)ql : (i128)top[i];
+        w[i] = mmul(msub(w[i], from_i128(r, q), q), inv, q);
+      }
+    }
+  }
+  x->level = l - 1;
+  x->scale = x->scale / (double)ql;
+}
+
+/* constant multiply with exact target scale: K = llround(v * T * q_l / s), then rescale;
+   the result is defined to carry scale T */
+static orc_ct* op_mul_const(orc_ctx* c, const orc_ct* a, double v, double target) {
+  orc_ct* x = ct_copy(c, a, a->level);
+  double ql = (double)c->mod[a->level];
+  double kf = v * target;
+  kf = kf * ql;
+  kf = kf / a->scale;
+  int64_t K = llround(kf);
+  int n = c->n;
+  for (int p = 0; p < 2; ++p)
+    for (int t = 0; t <= x->level; ++t) {
+      uint64_t q = c->mod[t], k = from_i128(K, q);
+      uint64_t* w = LIMB(x, p, t, n);
+      for (int i = 0; i < n; ++i) w[i] = mmul(w[i], k, q);
+    }
+  rescale_inplace(c, x);
+  x->scale = target;
+  return x;
+}
+
+/* multiply by the encoded real vector v (nslots values) with exact target scale */
+static orc_ct* op_mul_plain(orc_ctx* c, const orc_ct* a, const double* v, int nslots, double target) {
+  int n = c->n;
+  double ql = (double)c->mod[a->level];
+  double pscale = target * ql;
+  pscale = pscale / a->scale;
+  int64_t* m = (int64_t*)xcalloc(n, 8);
+  encode_real(c, v, nslots, pscale, m);
+  orc_ct* x = ct_new(c, a->level, a->scale);
+  uint64_t* mp = (uint64_t*)xcalloc(n, 8);
+  for (int t = 0; t <= a->level; ++t) {
+    poly_from_small(c, m, t, mp);
+    for (int p = 0; p < 2; ++p) ring_mul(c, t, LIMB(a, p, t, n), mp, LIMB(x, p, t, n));
+  }
+  free(m);
+  free(mp);
+  rescale_inplace(c, x);
+  x->scale = target;
+  return x;
+}
+
+/* hybrid key switch of d (coefficient domain, limbs 0..l) with key k:
+   returns (u0, u1) in R_{Q_l} with u0 + u1 s ~ d s' */
+static void key_switch(orc_ctx* c, const uint64_t* d, int l, const orc_key* k, uint64_t* u0, uint64_t* u1) {
+  int n = c->n, alpha = c->alpha, n_q = c->n_q, n_p = c->n_p;
+  int n_ext = l + 1 + n_p;
+  int* ext = (int*)xcalloc(n_ext, sizeof(int));
+  for (int i = 0; i <= l; ++i) ext[i] = i;
+  for (int i = 0; i < n_p; ++i) ext[l + 1 + i] = n_q + i;
+  uint64_t** acc0 = (uint64_t**)xcalloc(n_ext, sizeof(uint64_t*));
+  uint64_t** acc1 = (uint64_t**)xcalloc(n_ext, sizeof(uint64_t*));
+  for (int e = 0; e < n_ext; ++e) {
+    acc0[e] = (uint64_t*)xcalloc(n, 8);
+    acc1[e] = (uint64_t*)xcalloc(n, 8);
+  }
+  uint64_t* limb = (uint64_t*)xcalloc(n, 8);
+  int dn = (l + 1 + alpha - 1) / alpha;
+  for (int j = 0; j < dn; ++j) {
+    int lo = j * alpha, hi = (j + 1) * alpha < l + 1 ? (j + 1) * alpha : l + 1;
+    int sz = hi - lo;
+    /* y_i = [d_i * (D/q_i)^{-1}]_{q_i} for i in the digit */
+    uint64_t** y = (uint64_t**)xcalloc(sz, sizeof(uint64_t*));
+    for (int i = 0; i < sz; ++i) {
+      uint64_t qi = c->mod[lo + i];
+      uint64_t dhat = 1;
+      for (int i2 = 0; i2 < sz; ++i2)
+        if (i2 != i) dhat = mmul(dhat, c->mod[lo + i2] % qi, qi);
+      uint64_t inv = minv(dhat, qi);
+      y[i] = (uint64_t*)xcalloc(n, 8);
+      const uint64_t* di = d + (size_t)(lo + i) * n;
+      for (int x = 0; x < n; ++x) y[i][x] = mmul(di[x], inv, qi);
+    }
+    for (int e = 0; e < n_ext; ++e) {
+      int t = ext[e];
+      uint64_t q = c->mod[t];
+      if (t >= lo && t < hi) {
+        memcpy(limb, d + (size_t)t * n, 8 * (size_t)n);
+      } else {
+        for (int x = 0; x < n; ++x) limb[x] = 0;
+        for (int i = 0; i < sz; ++i) {
+          uint64_t dhat = 1; /* (D/q_i) mod q */
+          for (int i2 = 0; i2 < sz; ++i2)
+            if (i2 != i) dhat = mmul(dhat, c->mod[lo + i2] % q, q);
+          for (int x = 0; x < n; ++x) limb[x] = madd(limb[x], mmul(y[i][x] % q, dhat, q), q);
+        }
+      }
+      ntt_fwd(c, t, limb);
+      for (int x = 0; x < n; ++x) {
+        acc0[e][x] = madd(acc0[e][x], mmul(limb[x], k->b[j][t][x], q), q);
+        acc1[e][x] = madd(acc1[e][x], mmul(limb[x], k->a[j][t][x], q), q);
+      }
+    }
+    for (int i = 0; i < sz; ++i) free(y[i]);
+    free(y);
+  }
+  for (int e = 0; e < n_ext; ++e) {
+    ntt_inv(c, ext[e], acc0[e]);
+    ntt_inv(c, ext[e], acc1[e]);
+  }
+  /* ModDown: (u - Conv_{P->q}([u]_P)) * P^{-1} mod q */
+  for (int which = 0; which < 2; ++which) {
+    uint64_t** acc = which ? acc1 : acc0;
+    uint64_t* out = which ? u1 : u0;
+    uint64_t** y = (uint64_t**)xcalloc(n_p, sizeof(uint64_t*));
+    for (int kp = 0; kp < n_p; ++kp) {
+      uint64_t pk = c->mod[n_q + kp];
+      uint64_t phat = 1;
+      for (int k2 = 0; k2 < n_p; ++k2)
+        if (k2 != kp) phat = mmul(phat, c->mod[n_q + k2] % pk, pk);
+      uint64_t inv = minv(phat, pk);
+      y[kp] = (uint64_t*)xcalloc(n, 8);
+      for (int x = 0; x < n; ++x) y[kp][x] = mmul(acc[l + 1 + kp][x], inv, pk);
+    }
+    for (int t = 0; t <= l; ++t) {
+      uint64_t q = c->mod[t];
+      uint64_t pinv = minv(p_mod(c, t), q);
+      uint64_t* o = out + (size_t)t * n;
+      for (int x = 0; x < n; ++x) o[x] = 0;
+      for (int kp = 0; kp < n_p; ++kp) {
+        uint64_t phat = 1;
+        for (int k2 = 0; k2 < n_p; ++k2)
+          if (k2 != kp) phat = mmul(phat, c->mod[n_q + k2] % q, q);
+        for (int x = 0; x < n; ++x) o[x] = madd(o[x], mmul(y[kp][x] % q, phat, q), q);
+      }
+      for (int x = 0; x < n; ++x) o[x] = mmul(msub(acc[t][x], o[x], q), pinv, q);
+    }
+    for (int kp = 0; kp < n_p; ++kp) free(y[kp]);
+    free(y);
+  }
+  for (int e = 0; e < n_ext; ++e) { free(acc0[e]); free(acc1[e]); }
+  free(acc0); free(acc1); free(limb); free(ext);
+  c->counters[CNT_KS]++;
+}
+
+/* ct x ct: tensor, relinearise (key switch of the s^2 part); caller rescales */
+static orc_ct* op_mul_relin(orc_ctx* c, const orc_ct* a_in, const orc_ct* b_in) {
+  int l = a_in->level < b_in->level ? a_in->level : b_in->level;
+  int n = c->n;
+  orc_key* rk = find_key(c, 0);
+  if (!rk) die("no relinearisation key");
+  orc_ct* x = ct_new(c, l, a_in->scale * b_in->scale);
+  uint64_t* d2 = (uint64_t*)xcalloc((size_t)(l + 1) * n, 8);
+  uint64_t *a0 = (uint64_t*)xcalloc(n, 8), *a1 = (uint64_t*)xcalloc(n, 8);
+  uint64_t *b0 = (uint64_t*)xcalloc(n, 8), *b1 = (uint64_t*)xcalloc(n, 8);
+  for (int t = 0; t <= l; ++t) {
+    uint64_t q = c->mod[t];
+    memcpy(a0, LIMB(a_in, 0, t, n), 8 * (size_t)n);
+    memcpy(a1, LIMB(a_in, 1, t, n), 8 * (size_t)n);
+    memcpy(b0, LIMB(b_in, 0, t, n), 8 * (size_t)n);
+    memcpy(b1, LIMB(b_in, 1, t, n), 8 * (size_t)n);
+    ntt_fwd(c, t, a0); ntt_fwd(c, t, a1); ntt_fwd(c, t, b0); ntt_fwd(c, t, b1);
+    uint64_t* x0 = LIMB(x, 0, t, n);
+    uint64_t* x1 = LIMB(x, 1, t, n);
+    uint64_t* x2 = d2 + (size_t)t * n;
+    for (int i = 0; i < n; ++i) {
+      x0[i] = mmul(a0[i], b0[i], q);
+      x1[i] = madd(mmul(a0[i], b1[i], q), mmul(a1[i], b0[i], q), q);
+      x2[i] = mmul(a1[i], b1[i], q);
+    }
+    ntt_inv(c, t, x0); ntt_inv(c, t, x1); ntt_inv(c, t, x2);
+  }
+  free(a0); free(a1); free(b0); free(b1);
+  uint64_t* u0 = (uint64_t*)xcalloc((size_t)(l + 1) * n, 8);
+  uint64_t* u1 = (uint64_t*)xcalloc((size_t)(l + 1) * n, 8);
+  key_switch(c, d2, l, rk, u0, u1);
+  for (int t = 0; t <= l; ++t) {
+    uint64_t q = c->mod[t];
+    for (int i = 0; i < n; ++i) {
+      size_t o = (size_t)t * n + i;
+      x->c[0][o] = madd(x->c[0][o], u0[o], q);
+      x->c[1][o] = madd(x->c[1][o], u1[o], q);
+    }
+  }
+  free(d2); free(u0); free(u1);
+  c->counters[CNT_RELIN]++;
+  return x;
+}
+
+static orc_ct* op_mul_relin_rescale(orc_ctx* c, const orc_ct* a, const orc_ct* b) {
+  orc_ct* x = op_mul_relin(c, a, b);
+  rescale_inplace(c, x);
+  return x;
+}
+
+/* RotL(x, step): slot j <- slot j+step; automorphism X -> X^(5^step) then key switch */
+static orc_ct* op_rotate(orc_ctx* c, const orc_ct* a, int64_t step) {
+  uint64_t g = galois_elt(c, step);
+  if (g == 1) return ct_copy(c, a, a->level);
+  orc_key* k = find_key(c, g);
+  if (!k) die("missing Galois key");
+  int l = a->level, n = c->n;
+  orc_ct* x = ct_new(c, l, a->scale);
+  uint64_t* d = (uint64_t*)xcalloc((size_t)(l + 1) * n, 8);
+  for (int t = 0; t <= l; ++t) {
+    automorph_mod(c, LIMB(a, 0, t, n), g, c->mod[t], LIMB(x, 0, t, n));
+    automorph_mod(c, LIMB(a, 1, t, n), g, c->mod[t], d + (size_t)t * n);
+  }
+  uint64_t* u0 = (uint64_t*)xcalloc((size_t)(l + 1) * n, 8);
+  key_switch(c, d, l, k, u0, x->c[1]);
+  for (int t = 0; t <= l; ++t)
+    for (int i = 0; i < n; ++i) {
+      size_t o = (size_t)t * n + i;
+      x->c[0][o] = madd(x->c[0][o], u0[o], c->mod[t]);
+    }
+  free(d);
+  free(u0);
+  c->counters[CNT_ROT]++;
+  return x;
+}
+
+/* key-owner refresh, the stand-in for bootstrapping: decrypt, lift the message
+   exactly and re-encrypt at the top level with fresh randomness; scale kept */
+static orc_ct* op_refresh(orc_ctx* c, const orc_ct* a, uint64_t seed, uint64_t index) {
+  i128* m = (i128*)xcalloc(c->n, sizeof(i128));
+  decrypt_int(c, a, m);
+  orc_ct* x = encrypt_int(c, m, a->scale, seed, PUR_REFRESH, index, c->n_q - 1);
+  free(m);
+  c->counters[CNT_REFRESH]++;
+  return x;
+}
+
+/* exported primitive operations (handles in, new handle out) */
+ORC_API void* orc_add(void* h, const void* a, const void* b) { return op_add((orc_ctx*)h, (const orc_ct*)a, (const orc_ct*)b, 0); }
+ORC_API void* orc_sub(void* h, const void* a, const void* b) { return op_add((orc_ctx*)h, (const orc_ct*)a, (const orc_ct*)b, 1); }
+ORC_API void* orc_add_const(void* h, const void* a, double v) {
+  orc_ctx* c = (orc_ctx*)h;
+  orc_ct* x = ct_copy(c, (const orc_ct*)a, ((const orc_ct*)a)->level);
+  op_add_const_inplace(c, x, v);
+  return x;
+}
+ORC_API void* orc_rescale(void* h, const void* a) {
+  orc_ctx* c = (orc_ctx*)h;
+  orc_ct* x = ct_copy(c, (const orc_ct*)a, ((const orc_ct*)a)->level);
+  rescale_inplace(c, x);
+  return x;
+}
+ORC_API void* orc_lower(void* h, const void* a, int level) { return ct_copy((orc_ctx*)h, (const orc_ct*)a, level); }
+ORC_API void* orc_mul_const(void* h, const void* a, double v, double target) { return op_mul_const((orc_ctx*)h, (const orc_ct*)a, v, target); }
+ORC_API void* orc_mul_plain(void* h, const void* a, const double* v, int nslots, double target) {
+  return op_mul_plain((orc_ctx*)h, (const orc_ct*)a, v, nslots, target);
+}
+ORC_API void* orc_mul_relin(void* h, const void* a, const void* b) { return op_mul_relin((orc_ctx*)h, (const orc_ct*)a, (const orc_ct*)b); }
+ORC_API void* orc_mul_relin_rescale(void* h, const void* a, const void* b) {
+  return op_mul_relin_rescale((orc_ctx*)h, (const orc_ct*)a, (const orc_ct*)b);
+}
+ORC_API void* orc_rotate(void* h, const void* a, int64_t step) { return op_rotate((orc_ctx*)h, (const orc_ct*)a, step); }
+ORC_API void* orc_refresh(void* h, const void* a, uint64_t seed, uint64_t index) {
+  return op_refresh((orc_ctx*)h, (const orc_ct*)a, seed, index);
+}
+ORC_API void orc_key_switch(void* h, uint64_t g, const uint64_t* d, int level, uint64_t* u0, uint64_t* u1) {
+  orc_ctx* c = (orc_ctx*)h;
+  orc_key* k = find_key(c, g);
+  if (!k) die("missing key");
+  key_switch(c, d, level, k, u0, u1);
+}
+ORC_API void orc_automorph(void* h, int t, const uint64_t* in, uint64_t g, uint64_t* out) {
+  orc_ctx* c = (orc_ctx*)h;
+  automorph_mod(c, in, g, c->mod[t], out);
+}
+ORC_API uint64_t orc_galois_elt(void* h, int64_t step) { return galois_elt((orc_ctx*)h, step); }
+
+/* ------------------------------------------------------------------------- */
+/* Sign polynomials (Sec. 3.2, Eq. 4): f and g are odd, degree 9               */
+/* ------------------------------------------------------------------------- */
+/* f_4(x) = (315x - 420x^3 + 378x^5 - 180x^7 + 35x^9) / 2^7: the closed form
+   sum_{i<=4} binom(2i,i) 4^-i x (1-x^2)^i, whose derivative is c (1-x^2)^4. */
+static const double SIGN_F[5] = {315.0 / 128.0, -420.0 / 128.0, 378.0 / 128.0, -180.0 / 128.0, 35.0 / 128.0};
+/* g_4 of Cheon-Kim-Kim (ASIACRYPT 2020), odd coefficients of x, x^3, ..., x^9 over 2^10 */
+static const double SIGN_G[5] = {5850.0 / 1024.0, -34974.0 / 1024.0, 97015.0 / 1024.0, -113492.0 / 1024.0, 46623.0 / 1024.0};
+
+ORC_API void orc_sign_coeffs(double* f, double* g) {
+  memcpy(f, SIGN_F, sizeof(SIGN_F));
+  memcpy(g, SIGN_G, sizeof(SIGN_G));
+}
+
+/* p(x) = (c1 x + c3 x^3) + x^4 (c5 x + c7 x^3) + x^8 (c9 x), depth 4, six
+   ciphertext products. Output at level l-4 with scale 'target' (up to the FP64
+   rounding of the scale bookkeeping). c[] holds c1,c3,c5,c7,c9, times 'gain'. */
+static orc_ct* eval_odd9(orc_ctx* c, const orc_ct* x, const double* coef, double gain, double target) {
+  int l = x->level;
+  if (l - 4 < c->min_level) die("eval_odd9: not enough levels");
+  double k1 = coef[0] * gain, k3 = coef[1] * gain, k5 = coef[2] * gain, k7 = coef[3] * gain, k9 = coef[4] * gain;
+  orc_ct* x2 = op_mul_relin_rescale(c, x, x);                 /* l-1 */
+  orc_ct* xl1 = ct_copy(c, x, l - 1);
+  orc_ct* x3 = op_mul_relin_rescale(c, x2, xl1);              /* l-2 */
+  orc_ct* x4 = op_mul_relin_rescale(c, x2, x2);               /* l-2 */
+  orc_ct* x8 = op_mul_relin_rescale(c, x4, x4);               /* l-3 */
+  orc_ct* xl2 = ct_copy(c, x, l - 2);
+  double q3 = (double)c->mod[l - 3];
+  /* A = c1 x + c3 x^3 at scale target */
+  orc_ct* a3 = op_mul_const(c, x3, k3, target);
+  orc_ct* a1 = op_mul_const(c, xl2, k1, target);
+  orc_ct* A = op_add(c, a1, a3, 0);                            /* l-3 */
+  /* B = c5 x + c7 x^3 at scale target * q_{l-3} / s(x^4) */
+  double sb = target * q3;
+  sb = sb / x4->scale;
+  orc_ct* b3 = op_mul_const(c, x3, k7, sb);
+  orc_ct* b1 = op_mul_const(c, xl2, k5, sb);
+  orc_ct* B = op_add(c, b1, b3, 0);                            /* l-3 */
+  orc_ct* x4l = ct_copy(c, x4, l - 3);
+  orc_ct* x4B = op_mul_relin_rescale(c, x4l, B);               /* l-4 */
+  /* C = c9 x at scale target * q_{l-3} / s(x^8) */
+  double sc = target * q3;
+  sc = sc / x8->scale;
+  orc_ct* Cc = op_mul_const(c, xl2, k9, sc);                   /* l-3 */
+  orc_ct* x8C = op_mul_relin_rescale(c, x8, Cc);               /* l-4 */
+  orc_ct* Al = ct_copy(c, A, l - 4);
+  orc_ct* s1 = op_add(c, Al, x4B, 0);
+  orc_ct* p = op_add(c, s1, x8C, 0);
+  ct_free(x2); ct_free(xl1); ct_free(x3); ct_free(x4); ct_free(x8); ct_free(xl2);
+  ct_free(a3); ct_free(a1); ct_free(A); ct_free(b3); ct_free(b1); ct_free(B);
+  ct_free(x4l); ct_free(x4B); ct_free(Cc); ct_free(x8C); ct_free(Al); ct_free(s1);
+  c->counters[CNT_POLY]++;
+  return p;
+}
+
+ORC_API void* orc_eval_odd9(void* h, const void* x, const double* coef, double gain, double target) {
+  return eval_odd9((orc_ctx*)h, (const orc_ct*)x, coef, gain, target);
+}
+
+typedef struct {
+  uint64_t seed;
+  uint64_t next;
+} refresher;
+
+static orc_ct* maybe_refresh(orc_ctx* c, orc_ct* x, int need, refresher* rf) {
+  if (x->level - need >= c->min_level) return x;
+  if (c->n_q - 1 - need < c->min_level) die("modulus chain too short for one unit");
+  orc_ct* y = op_refresh(c, x, rf->seed, rf->next++);
+  ct_free(x);
+  return y;
+}
+
+/* Sign(x) = f^df(g^dg(x)); the last polynomial is scaled by 'gain' and lands on
+   scale 'last_target'; 'last_need' is the number of levels the caller needs
+   after the last polynomial beyond its own four. */
+static orc_ct* eval_sign(orc_ctx* c, const orc_ct* x_in, double gain, double last_target, int last_extra, refresher* rf,
+                         int* last_level_out) {
+  double delta = ldexp(1.0, c->log_scale);
+  orc_ct* x = ct_copy(c, x_in, x_in->level);
+  int total = c->dg + c->df;
+  for (int i = 0; i < total; ++i) {
+    int last = i == total - 1;
+    x = maybe_refresh(c, x, 4 + (last ? last_extra : 0), rf);
+    if (last && last_level_out) *last_level_out = x->level - 4;
+    const double* coef = i < c->dg ? SIGN_G : SIGN_F;
+    orc_ct* y = eval_odd9(c, x, coef, last ? gain : 1.0, last ? last_target : delta);
+    ct_free(x);
+    x = y;
+  }
+  c->counters[CNT_SIGN]++;
+  return x;
+}
+
+/* Max(a, b) = (a+b)/2 + (a-b)/2 * Sign(a-b)   (Eq. 6); a and b share level and scale */
+static orc_ct* op_max(orc_ctx* c, const orc_ct* a, const orc_ct* b, refresher* rf) {
+  double delta = ldexp(1.0, c->log_scale);
+  orc_ct* d = op_add(c, a, b, 1);
+  orc_ct* s = op_add(c, a, b, 0);
+  int ld = d->level;
+  /* the Sign output level is known once the refresh decision for the last
+     polynomial is taken; its target scale makes d * Sign/2 land on delta */
+  int ls = 0;
+  /* first pass: plan the level of the last polynomial without evaluating */
+  {
+    int lvl = d->level;
+    int total = c->dg + c->df;
+    for (int i = 0; i < total; ++i) {
+      int last = i == total - 1;
+      int need = 4 + (last ? 1 : 0);
+      if (lvl - need < c->min_level) lvl = c->n_q - 1;
+      if (lvl - need < c->min_level) die("modulus chain too short for one unit");
+      lvl -= 4;
+    }
+    ls = lvl;
+  }
+  int lp = ld < ls ? ld : ls;
+  double t_sign = delta * (double)c->mod[lp];
+  t_sign = t_sign / d->scale;
+  int ls_real = -1;
+  orc_ct* sg = eval_sign(c, d, 0.5, t_sign, 1, rf, &ls_real);
+  if (ls_real != ls) die("op_max: level plan mismatch");
+  orc_ct* dl = ct_copy(c, d, lp);
+  orc_ct* sgl = ct_copy(c, sg, lp);
+  orc_ct* prod = op_mul_relin_rescale(c, dl, sgl);
+  orc_ct* sl = ct_copy(c, s, lp);
+  orc_ct* half = op_mul_const(c, sl, 0.5, prod->scale);
+  orc_ct* out = op_add(c, half, prod, 0);
+  ct_free(d); ct_free(s); ct_free(sg); ct_free(dl); ct_free(sgl); ct_free(prod); ct_free(sl); ct_free(half);
+  c->counters[CNT_MAX]++;
+  return out;
+}
+
+static int ilog2_ceil(int v) {
+  int r = 0;
+  while ((1 << r) < v) ++r;
+  return r;
+}
+
+/* layout (Eq. 1 with the prompt axis): slot k*C' + c <- logits[k*C + c] */
+ORC_API void orc_layout(void* h, const double* logits, int K, int C, double* slots) {
+  orc_ctx* c = (orc_ctx*)h;
+  int cp = 1 << ilog2_ceil(C);
+  for (int j = 0; j < c->n / 2; ++j) slots[j] = 0.0;
+  for (int k = 0; k < K; ++k)
+    for (int cc = 0; cc < C; ++cc) slots[k * cp + cc] = logits[k * C + cc];
+}
+
+ORC_API void* orc_encrypt_logits(void* h, const double* logits, int K, int C, uint64_t seed) {
+  orc_ctx* c = (orc_ctx*)h;
+  int cp = 1 << ilog2_ceil(C), kp = 1 << ilog2_ceil(K);
+  if (kp * cp > c->n / 2) die("K' * C' exceeds the slot count");
+  double* slots = (double*)xcalloc(c->n / 2, sizeof(double));
+  orc_layout(h, logits, K, C, slots);
+  int64_t* m = (int64_t*)xcalloc(c->n, 8);
+  encode_real(c, slots, kp * cp, ldexp(1.0, c->log_scale), m);
+  void* x = orc_encrypt(h, m, ldexp(1.0, c->log_scale), seed);
+  free(slots);
+  free(m);
+  return x;
+}
+
+/* The encrypted Argmax (Algorithm 1) over the prompt-summed logits.
+   y[k*C'+c] holds the k-th prompt's score for class c.  Steps:
+     prompt sum   y <- y + RotL(y, C' 2^i), i < log K'   (sum by doubling, Sec. 3.2)
+     normalise    y <- mask_[0,C) * (y - D_min) / (D_max - D_min)   (Eq. 5)
+     line 2       y <- y + RotR(y, C')
+     line 3       y_max <- QuickMax(y): y <- Max(RotL(y, 2^i), y), i < log C'
+     line 4       y <- y - y_max
+     lines 5-6    z <- Sign(y) + 1                                   (Eq. 2) */
+ORC_API void* orc_eval_argmax(void* h, const void* ct_in, int K, int C, double d_min, double d_max, uint64_t refresh_seed) {
+  orc_ctx* c = (orc_ctx*)h;
+  double delta = ldexp(1.0, c->log_scale);
+  int lk = ilog2_ceil(K), lc = ilog2_ceil(C);
+  int cp = 1 << lc;
+  int slots = c->n / 2;
+  refresher rf = {refresh_seed, 0};
+  orc_ct* y = ct_copy(c, (const orc_ct*)ct_in, ((const orc_ct*)ct_in)->level);
+  for (int i = 0; i < lk; ++i) {
+    orc_ct* r = op_rotate(c, y, (int64_t)cp << i);
+    orc_ct* s = op_add(c, y, r, 0);
+    ct_free(r); ct_free(y);
+    y = s;
+  }
+  /* normalise; y must keep one level for the mask product */
+  y = maybe_refresh(c, y, 1, &rf);
+  op_add_const_inplace(c, y, -d_min);
+  double* mask = (double*)xcalloc(cp, sizeof(double));
+  double inv_range = 1.0 / (d_max - d_min);
+  for (int j = 0; j < C; ++j) mask[j] = inv_range;
+  orc_ct* yn = op_mul_plain(c, y, mask, cp, delta);
+  free(mask);
+  ct_free(y);
+  /* line 2: duplicate */
+  orc_ct* r = op_rotate(c, yn, (int64_t)slots - cp);
+  orc_ct* ydup = op_add(c, yn, r, 0);
+  ct_free(r); ct_free(yn);
+  /* line 3: QuickMax */
+  orc_ct* ym = ct_copy(c, ydup, ydup->level);
+  for (int i = 0; i < lc; ++i) {
+    ym = maybe_refresh(c, ym, 1, &rf);
+    orc_ct* rot = op_rotate(c, ym, (int64_t)1 << i);
+    orc_ct* mx = op_max(c, rot, ym, &rf);
+    ct_free(rot); ct_free(ym);
+    ym = mx;
+  }
+  /* line 4 */
+  orc_ct* d = op_add(c, ydup, ym, 1);
+  ct_free(ydup); ct_free(ym);
+  /* lines 5-6 */
+  orc_ct* z = eval_sign(c, d, 1.0, delta, 0, &rf, NULL);
+  ct_free(d);
+  op_add_const_inplace(c, z, 1.0);
+  return z;
+}

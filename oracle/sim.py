@@ -1,0 +1,93 @@
+"""FP64 tiers of the oracle (test infrastructure; see oracle/__init__.py).
+
+t0_*  the plain definition: argmax of the prompt sum (Sec. 2.3, prompt ensembling;
+      Sec. 3.2, Eq. 1: one-hot at the largest entry).
+t1_*  Algorithm 1 (Sec. 3.2) in FP64 on the full real slot vector, with the
+      composite polynomial Sign (Eq. 4), Max (Eq. 6) and normalisation (Eq. 5).
+      It follows the same data flow as the encrypted evaluation, rotations
+      included, so it shows the approximation error without encryption noise.
+"""
+import numpy as np
+
+# f_4 and g_4 (odd coefficients of x, x^3, x^5, x^7, x^9); the paper prints
+# neither, only "degree 9".  f_4 is the closed form sum_{i<=4} C(2i,i) 4^-i
+# x (1-x^2)^i; g_4 is Cheon-Kim-Kim's degree-9 g (ASIACRYPT 2020).
+F4 = np.array([315.0, -420.0, 378.0, -180.0, 35.0]) / 128.0
+G4 = np.array([5850.0, -34974.0, 97015.0, -113492.0, 46623.0]) / 1024.0
+
+
+def odd_poly(coef, x):
+    """sum_k coef[k] x^(2k+1)."""
+    x = np.asarray(x, dtype=np.float64)
+    x2 = x * x
+    acc = np.zeros_like(x) + coef[-1]
+    for c in coef[-2::-1]:
+        acc = acc * x2 + c
+    return acc * x
+
+
+def sign_composite(x, dg=2, df=2, f=F4, g=G4):
+    """Sign(x) ~ f^df(g^dg(x)) on [-1, 1]  (Eq. 4)."""
+    y = np.asarray(x, dtype=np.float64)
+    for _ in range(dg):
+        y = odd_poly(g, y)
+    for _ in range(df):
+        y = odd_poly(f, y)
+    return y
+
+
+def sign_threshold(dg=2, df=2, tol=1e-4, lo=-20.0, points=200001):
+    """Smallest eps (as log2) such that |S(x) - 1| <= tol on [eps, 1] (grid in log2 x)."""
+    e = np.linspace(lo, 0.0, points)
+    x = np.exp2(e)
+    bad = np.abs(sign_composite(x, dg, df) - 1.0) > tol
+    if not bad.any():
+        return lo
+    return float(e[np.nonzero(bad)[0].max() + 1]) if bad.nonzero()[0].max() + 1 < points else 0.0
+
+
+def t0_argmax(logits):
+    """Definition: y* = sum over prompts; index of the largest (lowest index on ties)."""
+    y = np.asarray(logits, dtype=np.float64).sum(axis=0)
+    idx = int(np.argmax(y))
+    srt = np.sort(y)
+    margin = float(srt[-1] - srt[-2]) if len(y) > 1 else float("inf")
+    return idx, y, margin
+
+
+def _pow2ceil(v):
+    return 1 << max(0, int(v - 1).bit_length())
+
+
+def t1_argmax(logits, d_min, d_max, slots, dg=2, df=2, exact_sign=False, return_all=False):
+    """Algorithm 1 on the real slot vector.  RotL(y, r)[j] = y[(j + r) mod slots]."""
+    logits = np.asarray(logits, dtype=np.float64)
+    K, C = logits.shape
+    Kp, Cp = _pow2ceil(K), _pow2ceil(C)
+    sgn = np.sign if exact_sign else (lambda v: sign_composite(v, dg, df))
+    y = np.zeros(slots)
+    for k in range(K):
+        y[k * Cp:k * Cp + C] = logits[k]
+    i = 1
+    while i < Kp:                                  # sum over prompts by doubling
+        y = y + np.roll(y, -Cp * i)
+        i <<= 1
+    mask = np.zeros(slots)
+    mask[:C] = 1.0
+    y = mask * (y - d_min) / (d_max - d_min)       # Eq. 5
+    y = y + np.roll(y, Cp)                          # line 2: y + RotR(y, n)
+    ym = y.copy()
+    i = 1
+    while i < Cp:                                  # line 3: QuickMax
+        r = np.roll(ym, -i)
+        ym = (r + ym) / 2 + (r - ym) / 2 * sgn(r - ym)   # Eq. 6
+        i <<= 1
+    d = y - ym                                     # line 4
+    z = sgn(d) + 1.0                               # lines 5-6, Eq. 2
+    if return_all:
+        return z, dict(y=y, ymax=ym)
+    return z[:C]
+
+
+def decoded_index(z):
+    return int(np.argmax(np.asarray(z)))

@@ -1,0 +1,94 @@
+"""Seeded synthetic workloads for the encrypted Argmax.
+
+Shared by the GPU path's tests/bench and by the CPU oracle's tests.  It holds
+no CKKS or Argmax arithmetic: only parameter sets, seeds, shapes and logits.
+
+The paper measures on GLUE/AdvGLUE, GSM8K/MultiArith and ImageNet/CIFAR with
+trained models (Sec. 4); none of that is needed for the Argmax, whose input is
+a K x C block of per-prompt class scores.  These generators stand in for it:
+i.i.d. N(0,1) logits, clipped at +-6, drawn from numpy's PCG64 seeded by
+SeedSequence([config_id, query]).
+"""
+import numpy as np
+
+# CKKS parameter sets.  n_q chain primes of q_bits, n_p special primes below
+# 2^p_bits (alpha = n_p primes per key-switch digit), scale 2^log_scale.
+PARAMS = {
+    # N=2^13, 8 x 30-bit primes + 1 special prime, scale 2^30 (correctness only)
+    "toy": dict(log_n=13, n_q=8, q_bits=30, n_p=1, p_bits=51, log_scale=30, dg=2, df=2, min_level=1),
+    # N=2^16, 24 x ~50-bit primes, 8 special primes (dnum = 3 digits), scale 2^50
+    "full": dict(log_n=16, n_q=24, q_bits=50, n_p=8, p_bits=51, log_scale=50, dg=2, df=2, min_level=1),
+    # N=2^16 with 3 special primes (dnum = 8 digits)
+    "full_a3": dict(log_n=16, n_q=24, q_bits=50, n_p=3, p_bits=51, log_scale=50, dg=2, df=2, min_level=1),
+    # small parameter sets for fast unit tests
+    "tiny": dict(log_n=10, n_q=8, q_bits=40, n_p=2, p_bits=51, log_scale=40, dg=2, df=2, min_level=1),
+    "mini": dict(log_n=11, n_q=10, q_bits=45, n_p=4, p_bits=51, log_scale=45, dg=2, df=2, min_level=1),
+}
+
+CLIP = 6.0
+KEYGEN_SEED = 0x5EC0_5EED_0000_0001
+
+
+def rng(config_id, query):
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(config_id), int(query)])))
+
+
+def logits(config_id, query, K, C, min_margin=None):
+    """K x C logits, N(0,1) clipped to +-6; redrawn until the top-2 margin of the
+    prompt sum is at least min_margin (when given)."""
+    g = rng(config_id, query)
+    while True:
+        y = np.clip(g.standard_normal((K, C)), -CLIP, CLIP)
+        if min_margin is None or C < 2:
+            return y
+        s = np.sort(y.sum(axis=0))
+        if s[-1] - s[-2] >= min_margin:
+            return y
+
+
+def d_bounds(K):
+    """Public normalisation bounds: the prompt sum of clipped logits lies in [-6K, 6K]."""
+    return -CLIP * K, CLIP * K
+
+
+def query_seeds(config_id, query):
+    """(encrypt_seed, refresh_seed) as uint64 values."""
+    g = rng(1000 + int(config_id), query)
+    s = g.integers(0, 2**63, size=2, dtype=np.int64)
+    return int(s[0]), int(s[1])
+
+
+def query_shape(config_id, query):
+    """(K, C) of a query for each workload."""
+    if config_id == 1:
+        return 4, 2
+    if config_id == 2:
+        return 8, 4
+    if config_id == 3:
+        g = rng(3, query)
+        return int(g.integers(3, 17)), int(g.integers(2, 15))
+    if config_id == 5:
+        g = rng(5, query)
+        return int(g.integers(4, 33)), int(g.integers(2, 21))
+    raise ValueError(config_id)
+
+
+def query(config_id, q):
+    """Everything that defines one query: shape, logits, seeds and bounds."""
+    K, C = query_shape(config_id, q)
+    y = logits(config_id, q, K, C, min_margin=0.05 if config_id == 2 else None)
+    enc, ref = query_seeds(config_id, q)
+    dmin, dmax = d_bounds(K)
+    return dict(K=K, C=C, logits=y, encrypt_seed=enc, refresh_seed=ref, d_min=dmin, d_max=dmax)
+
+
+def poisson_arrivals(qps, n, seed=(5, 0)):
+    """Arrival times (seconds) of n requests with exponential gaps at rate qps."""
+    g = rng(*seed)
+    return np.cumsum(g.exponential(1.0 / qps, size=n))
+
+
+def random_rotation_steps(n, slots, seed=(4, 0)):
+    """n rotation amounts uniform in [1, slots) for the rotation microbenchmark."""
+    g = rng(*seed)
+    return [int(v) for v in g.integers(1, slots, size=n)]
