@@ -1,0 +1,192 @@
+/*
+ * secpe.h -- C ABI of the MI355X (gfx950) encrypted-Argmax library.
+ *
+ * Paper: "SecPE: Secure Prompt Ensembling for Private and Robust Large
+ * Language Models", arXiv 2502.00847.
+ *
+ * The library evaluates the paper's private voting step (Sec. 3.1, step 3)
+ * under RNS-CKKS (Sec. 2.2): the server sums the encrypted per-prompt scores
+ * and turns the sum y* into an encrypted one-hot vector z with
+ * z_i = Sign(y_i - y_max) + 1 (Sec. 3.2, Eq. 2), y_max from Algorithm 1's
+ * QuickMax, Sign = f^{d_f}(g^{d_g}(x)) (Eq. 4), Max from Eq. 6 and inputs
+ * normalised by Eq. 5.  The client encrypts (step 1) and decrypts (step 4).
+ *
+ * Memory.  Every buffer passed as 'void* ..._dev' is device memory owned by
+ * the caller, sized with the secpe_*_bytes queries.  The library owns only its
+ * opaque context: parameter tables on the device, a descriptor arena and a
+ * small client scratch buffer, all released by secpe_ctx_destroy.
+ *
+ * Layouts.  A residue is an exact integer held in an IEEE binary64 (all primes
+ * are below 2^51).  A polynomial limb is N residues; a ciphertext buffer is
+ * [2][n_q][N] doubles (polynomial c0, then c1, each with room for all n_q chain
+ * limbs), stored in the NTT domain; limbs above the ciphertext's level are
+ * unused.  The secret key is [n_q + n_p][N] (NTT domain).  A switching key is
+ * [dnum][2][n_q + n_p][N] (NTT domain), dnum = ceil(n_q / n_p).
+ *
+ * Errors.  Functions return SECPE_OK (0) or a negative code; secpe_last_error
+ * returns a thread-local message.  Argument errors are reported before any
+ * work is queued.  Work is asynchronous on the context's stream unless stated;
+ * device faults surface at the next synchronising call (secpe_sync and the
+ * functions that return host data).
+ */
+#ifndef SECPE_H
+#define SECPE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SECPE_OK = 0,
+  SECPE_EINVAL = -1,   /* bad argument or parameter set */
+  SECPE_ENOMEM = -2,   /* workspace or device allocation too small / failed */
+  SECPE_ENOLEVEL = -3, /* the modulus chain is exhausted and no refresh key is registered */
+  SECPE_ENOKEY = -4,   /* no switching key for a needed rotation */
+  SECPE_EDEVICE = -5   /* a HIP call failed */
+};
+
+/* CKKS parameters (Sec. 2.2; Sec. 4.1 gives N = 2^16).
+   n_q chain primes = 1 mod 2N nearest 2^q_bits (alternately the next below
+   and the next above), n_p special primes: the largest = 1 mod 2N below 2^p_bits.
+   Key switching is hybrid with digits of alpha = n_p consecutive chain primes.
+   Scale 2^log_scale.  Sign = f^df(g^dg(x)).  min_level: lowest level a
+   ciphertext may reach (decryption needs two limbs, so 1). */
+typedef struct secpe_params {
+  int log_n, n_q, q_bits, n_p, p_bits, log_scale, dg, df, min_level;
+} secpe_params;
+
+/* A ciphertext: device buffer (layout above), its level and its scale. */
+typedef struct secpe_ct {
+  void* data;
+  int level;
+  double scale;
+} secpe_ct;
+
+typedef struct secpe_ctx secpe_ctx;
+
+const char* secpe_last_error(void);
+
+/* Create a context on HIP device 'device', issuing work on 'stream' (a
+   hipStream_t; NULL = the null stream).  Builds primes and device tables. */
+int secpe_ctx_create(const secpe_params* params, int device, void* stream, secpe_ctx** out);
+void secpe_ctx_destroy(secpe_ctx* ctx);
+
+/* Moduli: n_q chain primes then n_p special primes.  Returns the count; writes
+   at most 'cap' values. */
+int secpe_primes(const secpe_ctx* ctx, uint64_t* out, int cap);
+int secpe_slots(const secpe_ctx* ctx);
+size_t secpe_ct_bytes(const secpe_ctx* ctx);
+size_t secpe_sk_bytes(const secpe_ctx* ctx);
+size_t secpe_key_bytes(const secpe_ctx* ctx);
+
+/* Galois element 5^step mod 2N of RotL(step) (Sec. 2.2, RotL / RotR). */
+uint64_t secpe_galois_elt(const secpe_ctx* ctx, int64_t step);
+
+/* Rotation amounts Algorithm 1 needs for every K <= k_max, C <= c_max: the
+   prompt sum C'*2^i, RotR(C') = RotL(slots - C') and QuickMax 2^i.  Returns
+   the count; writes at most 'cap'. */
+int secpe_argmax_steps(const secpe_ctx* ctx, int k_max, int c_max, int64_t* out, int cap);
+
+/* Key generation (client).  Samples the ternary secret from 'seed' into
+   sk_dev, then 1 + n_steps switching keys into evk_dev: key 0 relinearises
+   s^2 -> s, key 1+i rotates by steps[i] (sigma_g(s) -> s).  The context
+   records which key serves which Galois element; evk_dev must stay alive while
+   the context evaluates.  Synchronous. */
+int secpe_keygen(secpe_ctx* ctx, uint64_t seed, const int64_t* steps, int n_steps, void* sk_dev, void* evk_dev);
+
+/* Register the key owner's secret key for the refresh stand-in of
+   bootstrapping (Sec. 2.2; Sec. 4.1): when a ciphertext runs out of levels the
+   evaluation decrypts and re-encrypts it at the top level.  NULL disables it. */
+int secpe_set_refresh_key(secpe_ctx* ctx, const void* sk_dev);
+
+/* Client encryption of a K x C block of logits (row k = prompt k) at the top
+   level with scale 2^log_scale.  Slot k*C' + c holds logits[k*C + c],
+   C' = next power of two >= C (Sec. 3.2, Eq. 1).  out->data is caller memory
+   of secpe_ct_bytes; level and scale are written. */
+int secpe_encrypt(secpe_ctx* ctx, const void* sk_dev, const double* logits, int K, int C, uint64_t seed, secpe_ct* out);
+
+/* Client encryption of an integer plaintext polynomial m[N] (coefficients). */
+int secpe_encrypt_coeffs(secpe_ctx* ctx, const void* sk_dev, const int64_t* m, double scale, uint64_t seed, secpe_ct* out);
+
+/* Client decryption: z_j for slots j < nslots (FP64) and the index of the
+   largest (lowest on ties).  Synchronous. */
+int secpe_decrypt(secpe_ctx* ctx, const void* sk_dev, const secpe_ct* ct, int nslots, double* z_out, int* argmax_out);
+
+/* Decrypted integer message m[N] (centred, from limbs 0 and 1). Synchronous. */
+int secpe_decrypt_coeffs(secpe_ctx* ctx, const void* sk_dev, const secpe_ct* ct, int64_t* m_out);
+
+/* Workspace bytes for one evaluation of n queries with the given shapes. */
+size_t secpe_workspace_bytes(secpe_ctx* ctx, int n, const int* K, const int* C);
+
+/* The encrypted Argmax (Algorithm 1) of one query: prompt sum by doubling
+   (Sec. 3.2, "applies to all associative operations"), normalisation with the
+   public bounds d_min, d_max (Eq. 5), duplication, QuickMax with Eq. 6, then
+   Sign(y - y_max) + 1 (Eq. 2).  'in' is read only.  refresh_seed keys the
+   randomness of the refresh stand-in.  Asynchronous. */
+int secpe_eval_argmax(secpe_ctx* ctx, const secpe_ct* in, int K, int C, double d_min, double d_max,
+                      uint64_t refresh_seed, void* ws_dev, size_t ws_bytes, secpe_ct* out);
+
+/* Many queries of uneven (K, C) at once: every step of every query is issued
+   in batched kernels (one launch per step kind for all queries at it).
+   flags: SECPE_GRAPH captures the launches in a hipGraph and replays it on
+   later calls with identical arguments.  Results are bit-identical to one
+   query at a time.  Asynchronous. */
+#define SECPE_GRAPH 1
+int secpe_eval_argmax_batch(secpe_ctx* ctx, int n, const secpe_ct* in, const int* K, const int* C,
+                            const double* d_min, const double* d_max, const uint64_t* refresh_seed,
+                            void* ws_dev, size_t ws_bytes, secpe_ct* out, int flags);
+
+/* Operation counts of the last evaluation: [sign, rotate, relin, key_switch,
+   refresh, poly, max, kernel launches]. */
+int secpe_counters(const secpe_ctx* ctx, int64_t* out8);
+
+/* Coefficient-domain canonical residues of a ciphertext, [2][level+1][N]
+   uint64 on the host (the format parity checks compare).  Synchronous. */
+int secpe_ct_export(secpe_ctx* ctx, const secpe_ct* ct, uint64_t* host_out);
+/* Inverse of export: host [2][level+1][N] coefficient residues -> out. */
+int secpe_ct_import(secpe_ctx* ctx, const uint64_t* host_in, int level, double scale, secpe_ct* out);
+
+/* Switching key limb in the coefficient domain (key index as in keygen,
+   digit < dnum, which 0 = b / 1 = a, prime index < n_q + n_p).  Synchronous. */
+int secpe_key_export(secpe_ctx* ctx, const void* evk_dev, int key, int digit, int which, int prime, uint64_t* host_out);
+/* Secret key in the coefficient domain as small integers. Synchronous. */
+int secpe_sk_export(secpe_ctx* ctx, const void* sk_dev, int64_t* host_out);
+
+/* Wait for all queued work. */
+int secpe_sync(secpe_ctx* ctx);
+
+/* ---- primitive operations (parity checks of single steps); ws sized by
+   secpe_op_workspace_bytes; outputs are caller buffers; asynchronous. ---- */
+size_t secpe_op_workspace_bytes(secpe_ctx* ctx);
+int secpe_op_add(secpe_ctx* ctx, const secpe_ct* a, const secpe_ct* b, secpe_ct* out);
+int secpe_op_sub(secpe_ctx* ctx, const secpe_ct* a, const secpe_ct* b, secpe_ct* out);
+int secpe_op_add_const(secpe_ctx* ctx, const secpe_ct* a, double v, secpe_ct* out);
+int secpe_op_mul_const(secpe_ctx* ctx, const secpe_ct* a, double v, double target, void* ws, size_t ws_bytes, secpe_ct* out);
+int secpe_op_mul_plain(secpe_ctx* ctx, const secpe_ct* a, const double* v, int nslots, double target, void* ws,
+                       size_t ws_bytes, secpe_ct* out);
+int secpe_op_rescale(secpe_ctx* ctx, const secpe_ct* a, void* ws, size_t ws_bytes, secpe_ct* out);
+int secpe_op_mul_relin(secpe_ctx* ctx, const secpe_ct* a, const secpe_ct* b, void* ws, size_t ws_bytes, secpe_ct* out);
+int secpe_op_mul_relin_rescale(secpe_ctx* ctx, const secpe_ct* a, const secpe_ct* b, void* ws, size_t ws_bytes, secpe_ct* out);
+int secpe_op_rotate(secpe_ctx* ctx, const secpe_ct* a, int64_t step, void* ws, size_t ws_bytes, secpe_ct* out);
+int secpe_op_refresh(secpe_ctx* ctx, const secpe_ct* a, uint64_t seed, uint64_t index, void* ws, size_t ws_bytes, secpe_ct* out);
+int secpe_op_eval_odd9(secpe_ctx* ctx, const secpe_ct* a, const double* coef5, double gain, double target, void* ws,
+                       size_t ws_bytes, secpe_ct* out);
+/* hybrid key switch of d (host, coefficient domain, [level+1][N]) with key
+   'key'; u0, u1 written to the host in the same format.  Synchronous. */
+int secpe_op_key_switch(secpe_ctx* ctx, int key, const uint64_t* d_host, int level, void* ws, size_t ws_bytes,
+                        uint64_t* u0_host, uint64_t* u1_host);
+/* forward then inverse NTT of limb data (host, [n][N] residues of prime
+   'prime'), for the NTT checks; out_fwd may be NULL.  Synchronous. */
+int secpe_op_ntt(secpe_ctx* ctx, int prime, const uint64_t* in_host, int n, uint64_t* out_fwd, uint64_t* out_roundtrip);
+/* negacyclic product of two limbs mod prime 'prime' through the NTT. Synchronous. */
+int secpe_op_ring_mul(secpe_ctx* ctx, int prime, const uint64_t* a_host, const uint64_t* b_host, uint64_t* out_host);
+/* encoder: m[N] for real slot values z[nslots] at 'scale'. Synchronous. */
+int secpe_op_encode(secpe_ctx* ctx, const double* z, int nslots, double scale, int64_t* m_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SECPE_H */

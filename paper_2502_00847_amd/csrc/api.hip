@@ -1,0 +1,883 @@
+// C ABI (include/secpe.h) over the runtime.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/secpe.h"
+#include "runtime.h"
+
+struct secpe_ctx {
+  secpe::Ctx c;
+  bool own_stream = false;
+  const double* evk = nullptr;
+  std::vector<const double*> key_list;
+};
+
+using namespace secpe;
+
+static thread_local std::string g_err;
+
+static int set_err(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+extern "C" const char* secpe_last_error(void) { return g_err.c_str(); }
+
+#define CHECK_CTX(ctx) \
+  if (!(ctx)) return set_err(SECPE_EINVAL, "null context")
+
+static int hip_fail(const char* where, hipError_t e) {
+  return set_err(SECPE_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+static int ensure_buffer(Ctx& c, char** buf, size_t* cap, size_t need) {
+  if (*cap >= need && *buf) return 0;
+  if (c.stream) (void)hipStreamSynchronize(c.stream);
+  if (*buf) (void)hipFree(*buf);
+  *buf = nullptr;
+  *cap = 0;
+  size_t n = std::max(need, (size_t)1 << 20);
+  hipError_t e = hipMalloc((void**)buf, n);
+  if (e != hipSuccess) {
+    *buf = nullptr;
+    return hip_fail("hipMalloc", e);
+  }
+  *cap = n;
+  return 0;
+}
+
+// Build with 'fn' into the context arena (growing it when needed) and submit.
+template <class F>
+static int run_build(secpe_ctx* x, char* ws, size_t ws_bytes, F fn) {
+  Ctx& c = x->c;
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    Builder b(c, ws, ws_bytes, c.arena, c.arena_bytes, false);
+    fn(b);
+    if (b.err_code) return set_err(b.err_code, b.err);
+    if (b.arena_overflow() || !c.arena) {
+      int rc = ensure_buffer(c, &c.arena, &c.arena_bytes, b.blob_bytes() + b.blob_bytes() / 4 + 4096);
+      if (rc) return rc;
+      continue;
+    }
+    int rc = submit(c, b, c.arena, c.arena_bytes);
+    if (rc) return set_err(SECPE_EDEVICE, "kernel submission failed");
+    memcpy(c.counters, b.counters, sizeof(c.counters));
+    return 0;
+  }
+  return set_err(SECPE_ENOMEM, "descriptor arena did not converge");
+}
+
+// client scratch sized by a dry run
+template <class F>
+static int run_client(secpe_ctx* x, F fn) {
+  Ctx& c = x->c;
+  Builder dry(c, (char*)(uintptr_t)0x100000000000ull, (size_t)1 << 44, (char*)(uintptr_t)0x400000000000ull, (size_t)1 << 40, true);
+  fn(dry);
+  if (dry.err_code) return set_err(dry.err_code, dry.err);
+  int rc = ensure_buffer(c, &c.client, &c.client_bytes, dry.need_bytes() + 4096);
+  if (rc) return rc;
+  return run_build(x, c.client, c.client_bytes, fn);
+}
+
+static int sync(Ctx& c) {
+  hipError_t e = c.stream ? hipStreamSynchronize(c.stream) : hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail("synchronize", e);
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+extern "C" int secpe_ctx_create(const secpe_params* p, int device, void* stream, secpe_ctx** out) {
+  if (!p || !out) return set_err(SECPE_EINVAL, "null argument");
+  *out = nullptr;
+  if (p->log_n < 10 || p->log_n > 16) return set_err(SECPE_EINVAL, "log_n must be in [10, 16]");
+  if (p->n_q < 2 || p->n_p < 1 || p->n_p > 16) return set_err(SECPE_EINVAL, "need n_q >= 2 and 1 <= n_p <= 16");
+  if (p->q_bits < 20 || p->q_bits > 50 || p->p_bits < 20 || p->p_bits > 51)
+    return set_err(SECPE_EINVAL, "prime sizes must keep every modulus below 2^51");
+  if (p->dg < 0 || p->df < 0 || p->dg + p->df < 1 || p->min_level < 1 || p->log_scale < 10 || p->log_scale > 60)
+    return set_err(SECPE_EINVAL, "bad Sign or scale parameters");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return set_err(SECPE_EDEVICE, "no such HIP device");
+  secpe_ctx* x = new secpe_ctx();
+  if (hipSetDevice(device) != hipSuccess) { delete x; return set_err(SECPE_EDEVICE, "hipSetDevice failed"); }
+  hipStream_t s = (hipStream_t)stream;
+  if (!s) {
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      delete x;
+      return set_err(SECPE_EDEVICE, "stream creation failed");
+    }
+    x->own_stream = true;
+  }
+  int rc = build_context(x->c, p->log_n, p->n_q, p->q_bits, p->n_p, p->p_bits, p->log_scale, p->dg, p->df,
+                         p->min_level, device, s);
+  if (rc) {
+    destroy_context(x->c);
+    if (x->own_stream) (void)hipStreamDestroy(s);
+    delete x;
+    return set_err(SECPE_EDEVICE, "context tables could not be built");
+  }
+  if ((x->c.mod.back() >> 51) != 0) {
+    secpe_ctx_destroy(x);
+    return set_err(SECPE_EINVAL, "a modulus reached 2^51");
+  }
+  *out = x;
+  return 0;
+}
+
+extern "C" void secpe_ctx_destroy(secpe_ctx* x) {
+  if (!x) return;
+  hipStream_t s = x->c.stream;
+  destroy_context(x->c);
+  if (x->own_stream && s) (void)hipStreamDestroy(s);
+  delete x;
+}
+
+extern "C" int secpe_primes(const secpe_ctx* x, uint64_t* out, int cap) {
+  CHECK_CTX(x);
+  const int n = (int)x->c.mod.size();
+  for (int i = 0; i < n && i < cap; ++i) out[i] = x->c.mod[i];
+  return n;
+}
+extern "C" int secpe_slots(const secpe_ctx* x) { return x ? x->c.N / 2 : 0; }
+extern "C" size_t secpe_ct_bytes(const secpe_ctx* x) { return x ? x->c.ct_bytes() : 0; }
+extern "C" size_t secpe_sk_bytes(const secpe_ctx* x) { return x ? x->c.sk_bytes() : 0; }
+extern "C" size_t secpe_key_bytes(const secpe_ctx* x) { return x ? x->c.key_bytes() : 0; }
+extern "C" uint64_t secpe_galois_elt(const secpe_ctx* x, int64_t step) { return x ? x->c.galois(step) : 0; }
+
+extern "C" int secpe_argmax_steps(const secpe_ctx* x, int k_max, int c_max, int64_t* out, int cap) {
+  CHECK_CTX(x);
+  const int slots = x->c.N / 2;
+  const int cpm = 1 << ilog2_ceil(std::max(1, c_max));
+  const int kpm = 1 << ilog2_ceil(std::max(1, k_max));
+  std::vector<int64_t> st;
+  for (int cp = 1; cp <= cpm; cp <<= 1) {
+    st.push_back(slots - cp);
+    for (int i = 1; i < kpm; i <<= 1) st.push_back((int64_t)cp * i);
+  }
+  for (int j = 1; j < cpm; j <<= 1) st.push_back(j);
+  std::sort(st.begin(), st.end());
+  st.erase(std::unique(st.begin(), st.end()), st.end());
+  st.erase(std::remove_if(st.begin(), st.end(), [&](int64_t v) { return v % slots == 0; }), st.end());
+  for (size_t i = 0; i < st.size() && (int)i < cap; ++i) out[i] = st[i];
+  return (int)st.size();
+}
+
+// ---------------------------------------------------------------------------
+// keys
+// ---------------------------------------------------------------------------
+extern "C" int secpe_keygen(secpe_ctx* x, uint64_t seed, const int64_t* steps, int n_steps, void* sk_dev,
+                            void* evk_dev) {
+  CHECK_CTX(x);
+  if (!sk_dev || !evk_dev || n_steps < 0 || (n_steps && !steps)) return set_err(SECPE_EINVAL, "bad keygen arguments");
+  Ctx& c = x->c;
+  const int N = c.N, nm = c.n_mod, nq = c.n_q;
+  double* sk = (double*)sk_dev;
+  double* evk = (double*)evk_dev;
+  const size_t key_doubles = c.key_bytes() / sizeof(double);
+  std::vector<uint64_t> gal(1 + n_steps, 0);
+  for (int i = 0; i < n_steps; ++i) gal[1 + i] = c.galois(steps[i]);
+  auto fn = [&](Builder& b) {
+    std::vector<SampleJob> js{SampleJob{sk, seed, (1ull << 56), nm, nq, SAMPLE_TERNARY, 0}};
+    b.sample(js);
+    b.ntt({NttJob{sk, sk, nm, nq, 0, 0}}, false);
+    double* s2 = b.scratch((size_t)nm * N);
+    double* sp = b.scratch((size_t)nm * N);
+    double* e = b.scratch((size_t)nm * N);
+    EwJob sq{};
+    sq.o0 = s2; sq.a0 = sk; sq.b0 = sk; sq.n_limbs = nm; sq.n_chain = nq; sq.op = EW_MUL;
+    b.ew({sq});
+    for (int kk = 0; kk <= n_steps; ++kk) {
+      double* key = evk + (size_t)kk * key_doubles;
+      const uint64_t purpose = kk == 0 ? 2 : 3;
+      const uint64_t obj = kk == 0 ? 0 : gal[kk];
+      const double* sfrom = s2;
+      if (kk > 0) {
+        b.automorph({AutoJob{sk, sp, nm, nq, (uint32_t)gal[kk], 0}});
+        sfrom = sp;
+      }
+      for (int j = 0; j < c.dnum; ++j) {
+        double* kb = key + (size_t)(2 * j) * nm * N;
+        double* ka = key + (size_t)(2 * j + 1) * nm * N;
+        const uint64_t tag = (purpose << 56) | ((obj & 0xFFFFFFFFull) << 24) | ((uint64_t)(j & 0xFFF) << 12);
+        b.sample({SampleJob{ka, seed, tag, nm, nq, SAMPLE_UNIFORM, 0}, SampleJob{e, seed, tag, nm, nq, SAMPLE_CBD, 0}});
+        b.ntt({NttJob{ka, ka, nm, nq, 0, 0}, NttJob{e, e, nm, nq, 0, 0}}, false);
+        std::vector<double> kv(nm, 0.0);
+        // the gadget P * T_j: T_j = 1 on the chain primes of digit j, 0 elsewhere
+        for (int t = 0; t < nq; ++t) {
+          if (t / c.alpha != j) continue;
+          uint64_t P = 1;
+          for (int k = 0; k < c.n_p; ++k) P = hmul(P, c.mod[nq + k] % c.mod[t], c.mod[t]);
+          kv[t] = (double)P;
+        }
+        EwJob w{};
+        w.o0 = kb; w.a1 = e; w.b0 = ka; w.b1 = sk; w.c0 = sfrom; w.k = b.put(kv);
+        w.n_limbs = nm; w.n_chain = nq; w.op = EW_KEYB;
+        b.ew({w});
+      }
+    }
+  };
+  int rc = run_client(x, fn);
+  if (rc) return rc;
+  rc = sync(c);
+  if (rc) return rc;
+  c.keys.clear();
+  x->key_list.clear();
+  x->evk = evk;
+  for (int kk = 0; kk <= n_steps; ++kk) {
+    const double* key = evk + (size_t)kk * key_doubles;
+    x->key_list.push_back(key);
+    if (kk == 0) c.keys[0] = key;
+    else if (gal[kk] != 1 && !c.keys.count(gal[kk])) c.keys[gal[kk]] = key;
+  }
+  return 0;
+}
+
+extern "C" int secpe_set_refresh_key(secpe_ctx* x, const void* sk_dev) {
+  CHECK_CTX(x);
+  x->c.refresh_sk = (const double*)sk_dev;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// client encryption / decryption
+// ---------------------------------------------------------------------------
+static int encrypt_impl(secpe_ctx* x, const void* sk_dev, const std::vector<double>& z, const int64_t* m_host,
+                        double scale, uint64_t seed, secpe_ct* out) {
+  Ctx& c = x->c;
+  const int N = c.N;
+  if (!sk_dev || !out || !out->data) return set_err(SECPE_EINVAL, "null buffer");
+  CT o;
+  o.d = (double*)out->data;
+  o.level = c.n_q - 1;
+  o.scale = scale;
+  auto fn = [&](Builder& b) {
+    int64_t* m = (int64_t*)b.scratch(N);
+    if (m_host) {
+      // the integer plaintext is uploaded through the descriptor arena
+      const int64_t* src = (const int64_t*)b.put_bytes(m_host, sizeof(int64_t) * N);
+      std::vector<const int64_t*> ms{src};
+      b.encrypt_into(ms, {seed}, 4, {0}, (const double*)sk_dev, {o});
+    } else {
+      EncodeJob ej{};
+      ej.z = b.put(z);
+      ej.m = m;
+      ej.scale_hi = scale * 2.0 / (double)N;
+      ej.scale_lo = 0.0;
+      ej.nnz = (int)z.size();
+      b.encode({ej});
+      b.encrypt_into({m}, {seed}, 4, {0}, (const double*)sk_dev, {o});
+    }
+  };
+  int rc = run_client(x, fn);
+  if (rc) return rc;
+  out->level = o.level;
+  out->scale = o.scale;
+  return 0;
+}
+
+extern "C" int secpe_encrypt(secpe_ctx* x, const void* sk_dev, const double* logits, int K, int C, uint64_t seed,
+                             secpe_ct* out) {
+  CHECK_CTX(x);
+  if (!logits || K < 1 || C < 1) return set_err(SECPE_EINVAL, "bad logits");
+  const int cp = 1 << ilog2_ceil(C), kp = 1 << ilog2_ceil(K);
+  if ((int64_t)cp * kp > x->c.N / 2) return set_err(SECPE_EINVAL, "K' * C' exceeds the slot count");
+  std::vector<double> z((size_t)kp * cp, 0.0);
+  for (int k = 0; k < K; ++k)
+    for (int j = 0; j < C; ++j) z[(size_t)k * cp + j] = logits[(size_t)k * C + j];
+  return encrypt_impl(x, sk_dev, z, nullptr, ldexp(1.0, x->c.log_scale), seed, out);
+}
+
+extern "C" int secpe_encrypt_coeffs(secpe_ctx* x, const void* sk_dev, const int64_t* m, double scale, uint64_t seed,
+                                    secpe_ct* out) {
+  CHECK_CTX(x);
+  if (!m) return set_err(SECPE_EINVAL, "null plaintext");
+  return encrypt_impl(x, sk_dev, {}, m, scale, seed, out);
+}
+
+static int decrypt_to_device(secpe_ctx* x, const void* sk_dev, const secpe_ct* ct, int nslots, int64_t** m_dev,
+                             double** z_dev) {
+  Ctx& c = x->c;
+  const int N = c.N;
+  if (!sk_dev || !ct || !ct->data) return set_err(SECPE_EINVAL, "null buffer");
+  if (ct->level < 1 || ct->level >= c.n_q) return set_err(SECPE_EINVAL, "decryption needs a level in [1, n_q)");
+  CT in;
+  in.d = (double*)ct->data;
+  in.level = ct->level;
+  in.scale = ct->scale;
+  auto fn = [&](Builder& b) {
+    double* r = b.scratch(2 * (size_t)N);
+    int64_t* m = (int64_t*)b.scratch(N);
+    double* z = b.scratch(std::max(nslots, 1));
+    EwJob d{};
+    d.o0 = r; d.a0 = b.c0(in); d.a1 = b.c1(in); d.b0 = (const double*)sk_dev;
+    d.n_limbs = 2; d.n_chain = 2; d.op = EW_DEC2;
+    b.ew({d});
+    b.ntt({NttJob{r, r, 2, 2, 0, 0}}, true);
+    b.lift({LiftJob{r, r + N, r, m, 0, 0}});
+    if (nslots > 0) b.decode(m, z, nslots, 1.0 / in.scale);
+    *m_dev = m;
+    *z_dev = z;
+  };
+  return run_client(x, fn);
+}
+
+extern "C" int secpe_decrypt(secpe_ctx* x, const void* sk_dev, const secpe_ct* ct, int nslots, double* z_out,
+                             int* argmax_out) {
+  CHECK_CTX(x);
+  if (nslots < 1 || nslots > x->c.N / 2 || !z_out) return set_err(SECPE_EINVAL, "bad slot count");
+  int64_t* m = nullptr;
+  double* z = nullptr;
+  int rc = decrypt_to_device(x, sk_dev, ct, nslots, &m, &z);
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(z_out, z, sizeof(double) * nslots, hipMemcpyDeviceToHost, x->c.stream);
+  if (e != hipSuccess) return hip_fail("hipMemcpyAsync", e);
+  rc = sync(x->c);
+  if (rc) return rc;
+  if (argmax_out) {
+    int best = 0;
+    for (int j = 1; j < nslots; ++j)
+      if (z_out[j] > z_out[best]) best = j;
+    *argmax_out = best;
+  }
+  return 0;
+}
+
+extern "C" int secpe_decrypt_coeffs(secpe_ctx* x, const void* sk_dev, const secpe_ct* ct, int64_t* m_out) {
+  CHECK_CTX(x);
+  if (!m_out) return set_err(SECPE_EINVAL, "null output");
+  int64_t* m = nullptr;
+  double* z = nullptr;
+  int rc = decrypt_to_device(x, sk_dev, ct, 0, &m, &z);
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(m_out, m, sizeof(int64_t) * x->c.N, hipMemcpyDeviceToHost, x->c.stream);
+  if (e != hipSuccess) return hip_fail("hipMemcpyAsync", e);
+  return sync(x->c);
+}
+
+// ---------------------------------------------------------------------------
+// evaluation
+// ---------------------------------------------------------------------------
+static std::vector<ArgmaxQuery> make_queries(secpe_ctx* x, int n, const secpe_ct* in, const int* K, const int* C,
+                                             const double* dmin, const double* dmax, const uint64_t* rs,
+                                             secpe_ct* out) {
+  std::vector<ArgmaxQuery> q(n);
+  for (int i = 0; i < n; ++i) {
+    q[i].in.d = (double*)in[i].data;
+    q[i].in.level = in[i].level;
+    q[i].in.scale = in[i].scale;
+    q[i].K = K[i];
+    q[i].C = C[i];
+    q[i].d_min = dmin[i];
+    q[i].d_max = dmax[i];
+    q[i].refresh_seed = rs[i];
+    q[i].out.d = out ? (double*)out[i].data : nullptr;
+  }
+  (void)x;
+  return q;
+}
+
+static int check_queries(secpe_ctx* x, int n, const secpe_ct* in, const int* K, const int* C, const double* dmin,
+                         const double* dmax) {
+  for (int i = 0; i < n; ++i) {
+    if (!in[i].data) return set_err(SECPE_EINVAL, "null input ciphertext");
+    if (in[i].level < 0 || in[i].level >= x->c.n_q) return set_err(SECPE_EINVAL, "input level out of range");
+    if (K[i] < 1 || C[i] < 1) return set_err(SECPE_EINVAL, "K and C must be positive");
+    const int cp = 1 << ilog2_ceil(C[i]), kp = 1 << ilog2_ceil(K[i]);
+    if ((int64_t)cp * kp > x->c.N / 2) return set_err(SECPE_EINVAL, "K' * C' exceeds the slot count");
+    if (!(dmax[i] > dmin[i])) return set_err(SECPE_EINVAL, "need d_max > d_min");
+  }
+  return 0;
+}
+
+extern "C" size_t secpe_workspace_bytes(secpe_ctx* x, int n, const int* K, const int* C) {
+  if (!x || n < 1 || !K || !C) return 0;
+  std::vector<secpe_ct> in(n), out(n);
+  std::vector<double> dmin(n, -1.0), dmax(n, 1.0);
+  std::vector<uint64_t> rs(n, 0);
+  Ctx& c = x->c;
+  for (int i = 0; i < n; ++i) {
+    in[i].data = (void*)(uintptr_t)0x200000000000ull;
+    in[i].level = c.n_q - 1;
+    in[i].scale = ldexp(1.0, c.log_scale);
+    out[i].data = (void*)(uintptr_t)0x300000000000ull;
+  }
+  if (check_queries(x, n, in.data(), K, C, dmin.data(), dmax.data())) return 0;
+  std::vector<ArgmaxQuery> q = make_queries(x, n, in.data(), K, C, dmin.data(), dmax.data(), rs.data(), out.data());
+  Builder dry(c, (char*)(uintptr_t)0x100000000000ull, (size_t)1 << 44, (char*)(uintptr_t)0x400000000000ull, (size_t)1 << 40, true);
+  build_argmax(dry, q);
+  if (dry.err_code) {
+    set_err(dry.err_code, dry.err);
+    return 0;
+  }
+  return dry.need_bytes() + 4096;
+}
+
+static uint64_t fnv(uint64_t h, const void* p, size_t n) {
+  const unsigned char* b = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
+  return h;
+}
+
+extern "C" int secpe_eval_argmax_batch(secpe_ctx* x, int n, const secpe_ct* in, const int* K, const int* C,
+                                       const double* dmin, const double* dmax, const uint64_t* rs, void* ws,
+                                       size_t ws_bytes, secpe_ct* out, int flags) {
+  CHECK_CTX(x);
+  if (n < 1 || !in || !K || !C || !dmin || !dmax || !rs || !ws || !out) return set_err(SECPE_EINVAL, "null argument");
+  int rc = check_queries(x, n, in, K, C, dmin, dmax);
+  if (rc) return rc;
+  for (int i = 0; i < n; ++i)
+    if (!out[i].data) return set_err(SECPE_EINVAL, "null output ciphertext");
+  Ctx& c = x->c;
+  std::vector<ArgmaxQuery> q = make_queries(x, n, in, K, C, dmin, dmax, rs, out);
+  if (!(flags & SECPE_GRAPH)) {
+    rc = run_build(x, (char*)ws, ws_bytes, [&](Builder& b) { build_argmax(b, q); });
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i) { out[i].level = q[i].out.level; out[i].scale = q[i].out.scale; }
+    return 0;
+  }
+  // graph mode: one captured graph per distinct argument set
+  uint64_t h = 1469598103934665603ull;
+  h = fnv(h, &n, sizeof(n));
+  for (int i = 0; i < n; ++i) {
+    h = fnv(h, &in[i], sizeof(secpe_ct));
+    h = fnv(h, &out[i].data, sizeof(void*));
+    h = fnv(h, &K[i], sizeof(int));
+    h = fnv(h, &C[i], sizeof(int));
+    h = fnv(h, &dmin[i], sizeof(double));
+    h = fnv(h, &dmax[i], sizeof(double));
+    h = fnv(h, &rs[i], sizeof(uint64_t));
+  }
+  h = fnv(h, &ws, sizeof(ws));
+  h = fnv(h, &ws_bytes, sizeof(ws_bytes));
+  for (GraphEntry& g : c.graphs) {
+    if (g.hash != h) continue;
+    hipError_t e = hipGraphLaunch(g.exec, c.stream);
+    if (e != hipSuccess) return hip_fail("hipGraphLaunch", e);
+    for (int i = 0; i < n; ++i) { out[i].level = g.out_level[i]; out[i].scale = g.out_scale[i]; }
+    memcpy(c.counters, g.counters, sizeof(c.counters));
+    return 0;
+  }
+  if (!c.stream) return set_err(SECPE_EINVAL, "graph capture needs a non-null stream");
+  GraphEntry g;
+  g.hash = h;
+  // size the graph's own descriptor arena with a dry run
+  {
+    Builder dry(c, (char*)ws, ws_bytes, (char*)(uintptr_t)0x400000000000ull, (size_t)1 << 40, true);
+    std::vector<ArgmaxQuery> qd = q;
+    build_argmax(dry, qd);
+    if (dry.err_code) return set_err(dry.err_code, dry.err);
+    g.arena_bytes = dry.blob_bytes() + 4096;
+  }
+  hipError_t e = hipMalloc((void**)&g.arena, g.arena_bytes);
+  if (e != hipSuccess) return hip_fail("hipMalloc", e);
+  Builder b(c, (char*)ws, ws_bytes, g.arena, g.arena_bytes, false);
+  build_argmax(b, q);
+  if (b.err_code) { (void)hipFree(g.arena); return set_err(b.err_code, b.err); }
+  e = hipMemcpy(g.arena, b.blob_.data(), b.blob_.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) { (void)hipFree(g.arena); return hip_fail("hipMemcpy", e); }
+  e = hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) { (void)hipFree(g.arena); return hip_fail("hipStreamBeginCapture", e); }
+  launch_cmds(c, b.cmds_, g.arena);
+  e = hipStreamEndCapture(c.stream, &g.graph);
+  if (e != hipSuccess) { (void)hipFree(g.arena); return hip_fail("hipStreamEndCapture", e); }
+  e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) { (void)hipGraphDestroy(g.graph); (void)hipFree(g.arena); return hip_fail("hipGraphInstantiate", e); }
+  for (int i = 0; i < n; ++i) { g.out_level.push_back(q[i].out.level); g.out_scale.push_back(q[i].out.scale); }
+  memcpy(g.counters, b.counters, sizeof(g.counters));
+  c.graphs.push_back(g);
+  e = hipGraphLaunch(g.exec, c.stream);
+  if (e != hipSuccess) return hip_fail("hipGraphLaunch", e);
+  for (int i = 0; i < n; ++i) { out[i].level = g.out_level[i]; out[i].scale = g.out_scale[i]; }
+  memcpy(c.counters, g.counters, sizeof(c.counters));
+  return 0;
+}
+
+extern "C" int secpe_eval_argmax(secpe_ctx* x, const secpe_ct* in, int K, int C, double d_min, double d_max,
+                                 uint64_t refresh_seed, void* ws, size_t ws_bytes, secpe_ct* out) {
+  return secpe_eval_argmax_batch(x, 1, in, &K, &C, &d_min, &d_max, &refresh_seed, ws, ws_bytes, out, 0);
+}
+
+extern "C" int secpe_counters(const secpe_ctx* x, int64_t* out8) {
+  CHECK_CTX(x);
+  memcpy(out8, x->c.counters, sizeof(int64_t) * 8);
+  return 0;
+}
+
+extern "C" int secpe_sync(secpe_ctx* x) {
+  CHECK_CTX(x);
+  return sync(x->c);
+}
+
+// ---------------------------------------------------------------------------
+// export / import
+// ---------------------------------------------------------------------------
+static int download_limbs(secpe_ctx* x, const double* dev, size_t n, uint64_t* host) {
+  std::vector<double> tmp(n);
+  hipError_t e = hipMemcpyAsync(tmp.data(), dev, n * sizeof(double), hipMemcpyDeviceToHost, x->c.stream);
+  if (e != hipSuccess) return hip_fail("hipMemcpyAsync", e);
+  int rc = sync(x->c);
+  if (rc) return rc;
+  for (size_t i = 0; i < n; ++i) host[i] = (uint64_t)tmp[i];
+  return 0;
+}
+
+extern "C" int secpe_ct_export(secpe_ctx* x, const secpe_ct* ct, uint64_t* host_out) {
+  CHECK_CTX(x);
+  if (!ct || !ct->data || !host_out || ct->level < 0 || ct->level >= x->c.n_q) return set_err(SECPE_EINVAL, "bad ciphertext");
+  Ctx& c = x->c;
+  const int N = c.N, nl = ct->level + 1;
+  double* out = nullptr;
+  auto fn = [&](Builder& b) {
+    out = b.scratch(2 * (size_t)nl * N);
+    const double* d = (const double*)ct->data;
+    b.ntt({NttJob{d, out, nl, nl, 0, 0}, NttJob{d + (size_t)c.n_q * N, out + (size_t)nl * N, nl, nl, 0, 0}}, true);
+  };
+  int rc = run_client(x, fn);
+  if (rc) return rc;
+  return download_limbs(x, out, 2 * (size_t)nl * N, host_out);
+}
+
+extern "C" int secpe_ct_import(secpe_ctx* x, const uint64_t* host_in, int level, double scale, secpe_ct* out) {
+  CHECK_CTX(x);
+  Ctx& c = x->c;
+  if (!host_in || !out || !out->data || level < 0 || level >= c.n_q) return set_err(SECPE_EINVAL, "bad import");
+  const int N = c.N, nl = level + 1;
+  std::vector<double> tmp(2 * (size_t)nl * N);
+  for (int p = 0; p < 2; ++p)
+    for (int l = 0; l < nl; ++l)
+      for (int k = 0; k < N; ++k) {
+        const uint64_t v = host_in[((size_t)p * nl + l) * N + k];
+        if (v >= c.mod[l]) return set_err(SECPE_EINVAL, "residue not canonical");
+        tmp[((size_t)p * nl + l) * N + k] = (double)v;
+      }
+  double* d = (double*)out->data;
+  double* stage = nullptr;
+  auto fn = [&](Builder& b) {
+    stage = b.scratch(tmp.size());
+    b.ntt({NttJob{stage, d, nl, nl, 0, 0}, NttJob{stage + (size_t)nl * N, d + (size_t)c.n_q * N, nl, nl, 0, 0}}, false);
+  };
+  // size the scratch, upload, then transform
+  Builder dry(c, (char*)(uintptr_t)0x100000000000ull, (size_t)1 << 44, (char*)(uintptr_t)0x400000000000ull, (size_t)1 << 40, true);
+  fn(dry);
+  int rc = ensure_buffer(c, &c.client, &c.client_bytes, dry.need_bytes() + 4096);
+  if (rc) return rc;
+  rc = sync(c);
+  if (rc) return rc;
+  Builder probe(c, c.client, c.client_bytes, (char*)(uintptr_t)0x400000000000ull, (size_t)1 << 40, true);
+  fn(probe);
+  hipError_t e = hipMemcpy(stage, tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail("hipMemcpy", e);
+  rc = run_build(x, c.client, c.client_bytes, fn);
+  if (rc) return rc;
+  out->level = level;
+  out->scale = scale;
+  return 0;
+}
+
+extern "C" int secpe_key_export(secpe_ctx* x, const void* evk_dev, int key, int digit, int which, int prime,
+                                uint64_t* host_out) {
+  CHECK_CTX(x);
+  Ctx& c = x->c;
+  if (!evk_dev || key < 0 || digit < 0 || digit >= c.dnum || which < 0 || which > 1 || prime < 0 || prime >= c.n_mod)
+    return set_err(SECPE_EINVAL, "bad key index");
+  const int N = c.N;
+  const double* src = (const double*)evk_dev + (size_t)key * (c.key_bytes() / sizeof(double)) +
+                      ((size_t)(2 * digit + which) * c.n_mod + prime) * N;
+  double* out = nullptr;
+  // a one-limb transform with the right prime: present it as limb 'prime' of a basis
+  const int nch = prime < c.n_q ? prime + 1 : c.n_q;
+  const int limb = prime < c.n_q ? prime : c.n_q + (prime - c.n_q);
+  auto fn = [&](Builder& b) {
+    out = b.scratch(N);
+    b.ntt({NttJob{src - (size_t)limb * N, out - (size_t)limb * N, limb + 1, nch, 0, limb}}, true);
+  };
+  int rc = run_client(x, fn);
+  if (rc) return rc;
+  return download_limbs(x, out, N, host_out);
+}
+
+extern "C" int secpe_sk_export(secpe_ctx* x, const void* sk_dev, int64_t* host_out) {
+  CHECK_CTX(x);
+  Ctx& c = x->c;
+  const int N = c.N;
+  double* out = nullptr;
+  auto fn = [&](Builder& b) {
+    out = b.scratch(N);
+    b.ntt({NttJob{(const double*)sk_dev, out, 1, 1, 0, 0}}, true);
+  };
+  int rc = run_client(x, fn);
+  if (rc) return rc;
+  std::vector<uint64_t> r(N);
+  rc = download_limbs(x, out, N, r.data());
+  if (rc) return rc;
+  const uint64_t q = c.mod[0];
+  for (int i = 0; i < N; ++i) host_out[i] = r[i] > q / 2 ? (int64_t)r[i] - (int64_t)q : (int64_t)r[i];
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// primitive operations
+// ---------------------------------------------------------------------------
+static CT to_ct(const secpe_ct* a) {
+  CT x;
+  x.d = (double*)a->data;
+  x.level = a->level;
+  x.scale = a->scale;
+  return x;
+}
+
+extern "C" size_t secpe_op_workspace_bytes(secpe_ctx* x) {
+  if (!x) return 0;
+  Ctx& c = x->c;
+  // a few ciphertexts plus one key switch at the top level, plus a refresh
+  const size_t limb = c.limb_bytes();
+  const size_t ks = (size_t)(c.n_q + (size_t)c.dnum * (c.n_q + c.n_p) + 2 * (c.n_q + c.n_p) + 2 * c.n_q) * limb;
+  return 24 * c.ct_bytes() + 2 * ks + 8 * c.n_q * limb + ((size_t)1 << 20);
+}
+
+// run a builder body whose result is one ciphertext copied into 'out'
+template <class F>
+static int op_to_out(secpe_ctx* x, void* ws, size_t ws_bytes, secpe_ct* out, F body) {
+  Ctx& c = x->c;
+  if (!out || !out->data) return set_err(SECPE_EINVAL, "null output");
+  CT res;
+  int rc = run_build(x, (char*)ws, ws_bytes, [&](Builder& b) {
+    std::vector<CT> rv = body(b);
+    if (b.err_code) return;
+    if (rv.empty()) { b.fail(SECPE_EINVAL, "operation produced no result"); return; }
+    CT r = rv[0];
+    EwJob e{};
+    e.o0 = (double*)out->data;
+    e.o1 = (double*)out->data + (size_t)c.n_q * c.N;
+    e.a0 = b.c0(r);
+    e.a1 = b.c1(r);
+    e.n_limbs = r.level + 1;
+    e.n_chain = r.level + 1;
+    e.op = EW_COPY;
+    b.ew({e});
+    res = r;
+  });
+  if (rc) return rc;
+  out->level = res.level;
+  out->scale = res.scale;
+  return 0;
+}
+
+extern "C" int secpe_op_add(secpe_ctx* x, const secpe_ct* a, const secpe_ct* b2, secpe_ct* out) {
+  CHECK_CTX(x);
+  size_t ws = secpe_op_workspace_bytes(x);
+  int rc = ensure_buffer(x->c, &x->c.client, &x->c.client_bytes, ws);
+  if (rc) return rc;
+  return op_to_out(x, x->c.client, x->c.client_bytes, out, [&](Builder& b) { return b.add({{to_ct(a), to_ct(b2)}}, false); });
+}
+extern "C" int secpe_op_sub(secpe_ctx* x, const secpe_ct* a, const secpe_ct* b2, secpe_ct* out) {
+  CHECK_CTX(x);
+  size_t ws = secpe_op_workspace_bytes(x);
+  int rc = ensure_buffer(x->c, &x->c.client, &x->c.client_bytes, ws);
+  if (rc) return rc;
+  return op_to_out(x, x->c.client, x->c.client_bytes, out, [&](Builder& b) { return b.add({{to_ct(a), to_ct(b2)}}, true); });
+}
+extern "C" int secpe_op_add_const(secpe_ctx* x, const secpe_ct* a, double v, secpe_ct* out) {
+  CHECK_CTX(x);
+  size_t ws = secpe_op_workspace_bytes(x);
+  int rc = ensure_buffer(x->c, &x->c.client, &x->c.client_bytes, ws);
+  if (rc) return rc;
+  return op_to_out(x, x->c.client, x->c.client_bytes, out, [&](Builder& b) { return b.add_const({to_ct(a)}, {v}); });
+}
+extern "C" int secpe_op_mul_const(secpe_ctx* x, const secpe_ct* a, double v, double target, void* ws, size_t wsb,
+                                  secpe_ct* out) {
+  CHECK_CTX(x);
+  return op_to_out(x, ws, wsb, out, [&](Builder& b) { return b.mul_const({to_ct(a)}, {v}, {target}); });
+}
+extern "C" int secpe_op_mul_plain(secpe_ctx* x, const secpe_ct* a, const double* v, int nslots, double target, void* ws,
+                                  size_t wsb, secpe_ct* out) {
+  CHECK_CTX(x);
+  std::vector<double> z(v, v + nslots);
+  return op_to_out(x, ws, wsb, out, [&](Builder& b) { return b.mul_plain({to_ct(a)}, {z}, {target}); });
+}
+extern "C" int secpe_op_rescale(secpe_ctx* x, const secpe_ct* a, void* ws, size_t wsb, secpe_ct* out) {
+  CHECK_CTX(x);
+  return op_to_out(x, ws, wsb, out, [&](Builder& b) {
+    CT in = to_ct(a);
+    CT o = b.new_ct(in.level, in.scale);
+    EwJob e{};
+    e.o0 = b.c0(o); e.o1 = b.c1(o); e.a0 = b.c0(in); e.a1 = b.c1(in);
+    e.n_limbs = in.level + 1; e.n_chain = in.level + 1; e.op = EW_COPY;
+    b.ew({e});
+    std::vector<CT> v{o};
+    b.rescale(v);
+    return v;
+  });
+}
+extern "C" int secpe_op_mul_relin(secpe_ctx* x, const secpe_ct* a, const secpe_ct* b2, void* ws, size_t wsb,
+                                  secpe_ct* out) {
+  CHECK_CTX(x);
+  return op_to_out(x, ws, wsb, out, [&](Builder& b) { return b.mul_relin({{to_ct(a), to_ct(b2)}}, false); });
+}
+extern "C" int secpe_op_mul_relin_rescale(secpe_ctx* x, const secpe_ct* a, const secpe_ct* b2, void* ws, size_t wsb,
+                                          secpe_ct* out) {
+  CHECK_CTX(x);
+  return op_to_out(x, ws, wsb, out, [&](Builder& b) { return b.mul_relin({{to_ct(a), to_ct(b2)}}, true); });
+}
+extern "C" int secpe_op_rotate(secpe_ctx* x, const secpe_ct* a, int64_t step, void* ws, size_t wsb, secpe_ct* out) {
+  CHECK_CTX(x);
+  return op_to_out(x, ws, wsb, out, [&](Builder& b) { return b.rotate({to_ct(a)}, {step}); });
+}
+extern "C" int secpe_op_refresh(secpe_ctx* x, const secpe_ct* a, uint64_t seed, uint64_t index, void* ws, size_t wsb,
+                                secpe_ct* out) {
+  CHECK_CTX(x);
+  return op_to_out(x, ws, wsb, out, [&](Builder& b) { return b.refresh({to_ct(a)}, {seed}, {index}); });
+}
+extern "C" int secpe_op_eval_odd9(secpe_ctx* x, const secpe_ct* a, const double* coef5, double gain, double target,
+                                  void* ws, size_t wsb, secpe_ct* out) {
+  CHECK_CTX(x);
+  if (!coef5) return set_err(SECPE_EINVAL, "null coefficients");
+  return op_to_out(x, ws, wsb, out, [&](Builder& b) { return b.eval_odd9({to_ct(a)}, {coef5}, {gain}, {target}); });
+}
+
+extern "C" int secpe_op_key_switch(secpe_ctx* x, int key, const uint64_t* d_host, int level, void* ws, size_t wsb,
+                                   uint64_t* u0_host, uint64_t* u1_host) {
+  CHECK_CTX(x);
+  Ctx& c = x->c;
+  if (key < 0 || key >= (int)x->key_list.size()) return set_err(SECPE_ENOKEY, "no such key");
+  if (level < 0 || level >= c.n_q || !d_host || !u0_host || !u1_host) return set_err(SECPE_EINVAL, "bad arguments");
+  const int N = c.N, nl = level + 1;
+  // stage d as a ciphertext (c0 = d, c1 = 0) through import, then switch c0
+  std::vector<uint64_t> h(2 * (size_t)nl * N, 0);
+  memcpy(h.data(), d_host, sizeof(uint64_t) * (size_t)nl * N);
+  char* wsc = (char*)ws;
+  if (wsb < 2 * c.ct_bytes()) return set_err(SECPE_ENOMEM, "workspace too small");
+  secpe_ct din{wsc, 0, 1.0};
+  int rc = secpe_ct_import(x, h.data(), level, 1.0, &din);
+  if (rc) return rc;
+  secpe_ct uo{wsc + c.ct_bytes(), level, 1.0};
+  const double* kp = x->key_list[key];
+  rc = run_build(x, wsc + 2 * c.ct_bytes(), wsb - 2 * c.ct_bytes(), [&](Builder& b) {
+    CT dd = to_ct(&din);
+    CT uu = to_ct(&uo);
+    b.key_switch({Builder::KsItem{b.c0(dd), level, kp, nullptr, nullptr, b.c0(uu), b.c1(uu)}});
+  });
+  if (rc) return rc;
+  std::vector<uint64_t> o(2 * (size_t)nl * N);
+  rc = secpe_ct_export(x, &uo, o.data());
+  if (rc) return rc;
+  memcpy(u0_host, o.data(), sizeof(uint64_t) * (size_t)nl * N);
+  memcpy(u1_host, o.data() + (size_t)nl * N, sizeof(uint64_t) * (size_t)nl * N);
+  return 0;
+}
+
+extern "C" int secpe_op_ntt(secpe_ctx* x, int prime, const uint64_t* in_host, int n, uint64_t* out_fwd,
+                            uint64_t* out_rt) {
+  CHECK_CTX(x);
+  Ctx& c = x->c;
+  if (prime < 0 || prime >= c.n_mod || n < 1 || !in_host) return set_err(SECPE_EINVAL, "bad arguments");
+  const int N = c.N;
+  const int nch = prime < c.n_q ? prime + 1 : c.n_q;
+  const int limb = prime;  // chain prime t sits at limb t; special prime n_q + k at limb n_q + k with n_chain = n_q
+  std::vector<double> tmp((size_t)n * N);
+  for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (double)in_host[i];
+  double *buf = nullptr, *fw = nullptr;
+  auto fn = [&](Builder& b) {
+    buf = b.scratch((size_t)n * N);
+    fw = b.scratch((size_t)n * N);
+    std::vector<NttJob> f, r;
+    for (int i = 0; i < n; ++i) {
+      double* s = buf + (size_t)i * N;
+      double* d = fw + (size_t)i * N;
+      f.push_back(NttJob{s - (size_t)limb * N, d - (size_t)limb * N, limb + 1, nch, 0, limb});
+      r.push_back(NttJob{d - (size_t)limb * N, s - (size_t)limb * N, limb + 1, nch, 0, limb});
+    }
+    b.ntt(f, false);
+    b.ntt(r, true);
+  };
+  Builder dry(c, (char*)(uintptr_t)0x100000000000ull, (size_t)1 << 44, (char*)(uintptr_t)0x400000000000ull, (size_t)1 << 40, true);
+  fn(dry);
+  int rc = ensure_buffer(c, &c.client, &c.client_bytes, dry.need_bytes() + 4096);
+  if (rc) return rc;
+  rc = sync(c);
+  if (rc) return rc;
+  Builder probe(c, c.client, c.client_bytes, (char*)(uintptr_t)0x400000000000ull, (size_t)1 << 40, true);
+  fn(probe);
+  hipError_t e = hipMemcpy(buf, tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail("hipMemcpy", e);
+  rc = run_build(x, c.client, c.client_bytes, fn);
+  if (rc) return rc;
+  if (out_fwd) {
+    rc = download_limbs(x, fw, (size_t)n * N, out_fwd);
+    if (rc) return rc;
+  }
+  if (out_rt) return download_limbs(x, buf, (size_t)n * N, out_rt);
+  return sync(c);
+}
+
+extern "C" int secpe_op_ring_mul(secpe_ctx* x, int prime, const uint64_t* a_host, const uint64_t* b_host,
+                                 uint64_t* out_host) {
+  CHECK_CTX(x);
+  Ctx& c = x->c;
+  if (prime < 0 || prime >= c.n_mod || !a_host || !b_host || !out_host) return set_err(SECPE_EINVAL, "bad arguments");
+  const int N = c.N;
+  const int nch = prime < c.n_q ? prime + 1 : c.n_q;
+  const int limb = prime;
+  std::vector<double> tmp(2 * (size_t)N);
+  for (int i = 0; i < N; ++i) { tmp[i] = (double)a_host[i]; tmp[N + i] = (double)b_host[i]; }
+  double* buf = nullptr;
+  // the views below present limb 'limb' of a basis; the element-wise product
+  // runs over limbs 0..limb of both views, which fn2 allocates in full
+  auto fn2 = [&](Builder& b) {
+    buf = b.scratch((size_t)(limb + 2) * N * 2);
+    double* a = buf + (size_t)limb * N;              // limb 'limb' of view A
+    double* bb = buf + (size_t)(2 * limb + 1) * N;   // limb 'limb' of view B
+    double* va = a - (size_t)limb * N;
+    double* vb = bb - (size_t)limb * N;
+    b.ntt({NttJob{va, va, limb + 1, nch, 0, limb}, NttJob{vb, vb, limb + 1, nch, 0, limb}}, false);
+    EwJob e{};
+    e.o0 = va; e.a0 = va; e.b0 = vb;
+    e.n_limbs = limb + 1; e.n_chain = nch; e.op = EW_MUL;
+    b.ew({e});
+    b.ntt({NttJob{va, va, limb + 1, nch, 0, limb}}, true);
+  };
+  Builder dry(c, (char*)(uintptr_t)0x100000000000ull, (size_t)1 << 44, (char*)(uintptr_t)0x400000000000ull, (size_t)1 << 40, true);
+  fn2(dry);
+  int rc = ensure_buffer(c, &c.client, &c.client_bytes, dry.need_bytes() + 4096);
+  if (rc) return rc;
+  rc = sync(c);
+  if (rc) return rc;
+  Builder probe(c, c.client, c.client_bytes, (char*)(uintptr_t)0x400000000000ull, (size_t)1 << 40, true);
+  fn2(probe);
+  double* a = buf + (size_t)limb * N;
+  double* bb = buf + (size_t)(2 * limb + 1) * N;
+  hipError_t e = hipMemcpy(a, tmp.data(), (size_t)N * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(bb, tmp.data() + N, (size_t)N * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail("hipMemcpy", e);
+  rc = run_build(x, c.client, c.client_bytes, fn2);
+  if (rc) return rc;
+  return download_limbs(x, a, N, out_host);
+}
+
+extern "C" int secpe_op_encode(secpe_ctx* x, const double* z, int nslots, double scale, int64_t* m_out) {
+  CHECK_CTX(x);
+  Ctx& c = x->c;
+  if (!z || nslots < 1 || nslots > c.N / 2 || !m_out) return set_err(SECPE_EINVAL, "bad arguments");
+  const int N = c.N;
+  std::vector<double> zz(z, z + nslots);
+  int64_t* m = nullptr;
+  auto fn = [&](Builder& b) {
+    m = (int64_t*)b.scratch(N);
+    EncodeJob ej{};
+    ej.z = b.put(zz);
+    ej.m = m;
+    ej.scale_hi = scale * 2.0 / (double)N;
+    ej.scale_lo = 0.0;
+    ej.nnz = nslots;
+    b.encode({ej});
+  };
+  int rc = run_client(x, fn);
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(m_out, m, sizeof(int64_t) * N, hipMemcpyDeviceToHost, c.stream);
+  if (e != hipSuccess) return hip_fail("hipMemcpyAsync", e);
+  return sync(c);
+}

@@ -1,0 +1,330 @@
+// The encrypted Argmax of arXiv 2502.00847 (Sec. 3.2, Algorithm 1) as a
+// batched program: each query is a sequence of steps; every round runs one
+// step kind for all queries waiting on it, in the same kernel launches.
+#include <math.h>
+
+#include <algorithm>
+
+#include "runtime.h"
+
+namespace secpe {
+
+// Sign polynomials (Eq. 4), odd coefficients of x, x^3, x^5, x^7, x^9.
+// f is the closed form sum_{i<=4} C(2i,i) 4^-i x (1-x^2)^i; g is the degree-9
+// g of Cheon, Kim and Kim (ASIACRYPT 2020).  The paper fixes only "degree 9".
+static const double kSignF[5] = {315.0 / 128.0, -420.0 / 128.0, 378.0 / 128.0, -180.0 / 128.0, 35.0 / 128.0};
+static const double kSignG[5] = {5850.0 / 1024.0, -34974.0 / 1024.0, 97015.0 / 1024.0, -113492.0 / 1024.0,
+                                 46623.0 / 1024.0};
+
+enum StepKind { S_ROTADD = 0, S_NORMALISE, S_DUP, S_MAXPRE, S_POLY, S_MAXPOST, S_FINALPRE, S_FINALPOST, S_NKINDS };
+
+struct Step {
+  int kind;
+  int arg;     // ROTADD: rotation; MAXPRE: QuickMax index i; POLY: polynomial index in the Sign
+  bool max;    // POLY: part of a Max step (true) or the final Sign (false)
+};
+
+struct QState {
+  ArgmaxQuery* q;
+  int kp, cp, lk, lc;
+  uint64_t rnext = 0;
+  CT y, ydup, ym, d, s, x;
+  int lp = 0, ls = 0;
+  double t_sign = 0.0;
+  std::vector<Step> prog;
+  size_t pc = 0;
+};
+
+static void free_owned(Builder& b, CT& x) {
+  if (x.slot >= 0) b.free_ct(x);
+  x = CT{};
+}
+
+static CT view(const CT& x) {
+  CT v = x;
+  v.slot = -1;
+  return v;
+}
+
+// refresh, in one batch, every item whose level cannot afford 'need' more levels
+static void maybe_refresh(Builder& b, std::vector<QState*>& qs, std::vector<CT*> cts, const std::vector<int>& need) {
+  std::vector<CT> in;
+  std::vector<uint64_t> seed, index;
+  std::vector<size_t> who;
+  const int top = b.C.n_q - 1;
+  for (size_t i = 0; i < qs.size(); ++i) {
+    CT& x = *cts[i];
+    if (x.level - need[i] >= b.C.min_level) continue;
+    if (top - need[i] < b.C.min_level) { b.fail(-3, "modulus chain too short for one unit"); return; }
+    in.push_back(x);
+    seed.push_back(qs[i]->q->refresh_seed);
+    index.push_back(qs[i]->rnext++);
+    who.push_back(i);
+  }
+  if (in.empty()) return;
+  std::vector<CT> out = b.refresh(in, seed, index);
+  if (b.err_code) return;
+  for (size_t k = 0; k < who.size(); ++k) {
+    CT& x = *cts[who[k]];
+    free_owned(b, x);
+    x = out[k];
+  }
+}
+
+static void run_step(Builder& b, int kind, std::vector<QState*>& qs) {
+  Ctx& C = b.C;
+  const double delta = ldexp(1.0, C.log_scale);
+  const int slots = C.N / 2;
+  const int total = C.dg + C.df;
+  const size_t n = qs.size();
+  std::vector<std::pair<CT, CT>> pr;
+  switch (kind) {
+    case S_ROTADD: {  // prompt sum by doubling: y <- y + RotL(y, C' 2^i)
+      std::vector<CT> in;
+      std::vector<int64_t> st;
+      for (QState* s : qs) { in.push_back(s->y); st.push_back(s->prog[s->pc].arg); }
+      std::vector<CT> r = b.rotate(in, st);
+      if (b.err_code) return;
+      for (size_t i = 0; i < n; ++i) pr.push_back({qs[i]->y, r[i]});
+      std::vector<CT> y = b.add(pr, false);
+      if (b.err_code) return;
+      for (size_t i = 0; i < n; ++i) {
+        b.free_ct(r[i]);
+        free_owned(b, qs[i]->y);
+        qs[i]->y = y[i];
+      }
+      break;
+    }
+    case S_NORMALISE: {  // Eq. 5 on [0, C): mask * (y - D_min) / (D_max - D_min)
+      std::vector<CT*> cts;
+      for (QState* s : qs) cts.push_back(&s->y);
+      maybe_refresh(b, qs, cts, std::vector<int>(n, 1));
+      if (b.err_code) return;
+      std::vector<CT> in;
+      std::vector<double> v;
+      for (QState* s : qs) { in.push_back(s->y); v.push_back(-s->q->d_min); }
+      std::vector<CT> y1 = b.add_const(in, v);
+      if (b.err_code) return;
+      std::vector<std::vector<double>> masks;
+      std::vector<double> tg;
+      for (QState* s : qs) {
+        std::vector<double> m(s->cp, 0.0);
+        const double inv_range = 1.0 / (s->q->d_max - s->q->d_min);
+        for (int j = 0; j < s->q->C; ++j) m[j] = inv_range;
+        masks.push_back(m);
+        tg.push_back(delta);
+      }
+      std::vector<CT> yn = b.mul_plain(y1, masks, tg);
+      if (b.err_code) return;
+      for (size_t i = 0; i < n; ++i) {
+        b.free_ct(y1[i]);
+        free_owned(b, qs[i]->y);
+        qs[i]->y = yn[i];
+      }
+      break;
+    }
+    case S_DUP: {  // Algorithm 1, line 2: y <- y + RotR(y, n), n = C'
+      std::vector<CT> in;
+      std::vector<int64_t> st;
+      for (QState* s : qs) { in.push_back(s->y); st.push_back((int64_t)slots - s->cp); }
+      std::vector<CT> r = b.rotate(in, st);
+      if (b.err_code) return;
+      for (size_t i = 0; i < n; ++i) pr.push_back({qs[i]->y, r[i]});
+      std::vector<CT> y = b.add(pr, false);
+      if (b.err_code) return;
+      for (size_t i = 0; i < n; ++i) {
+        b.free_ct(r[i]);
+        free_owned(b, qs[i]->y);
+        qs[i]->ydup = y[i];
+        qs[i]->ym = view(y[i]);
+      }
+      break;
+    }
+    case S_MAXPRE: {  // QuickMax step i: r = RotL(y, 2^i); d = r - y; s = r + y  (Eq. 6)
+      std::vector<CT*> cts;
+      for (QState* s : qs) cts.push_back(&s->ym);
+      maybe_refresh(b, qs, cts, std::vector<int>(n, 1));
+      if (b.err_code) return;
+      std::vector<CT> in;
+      std::vector<int64_t> st;
+      for (QState* s : qs) { in.push_back(s->ym); st.push_back((int64_t)1 << s->prog[s->pc].arg); }
+      std::vector<CT> r = b.rotate(in, st);
+      if (b.err_code) return;
+      for (size_t i = 0; i < n; ++i) pr.push_back({r[i], qs[i]->ym});
+      std::vector<CT> d = b.add(pr, true);
+      if (b.err_code) return;
+      std::vector<CT> sm = b.add(pr, false);
+      if (b.err_code) return;
+      for (size_t i = 0; i < n; ++i) {
+        QState* s = qs[i];
+        b.free_ct(r[i]);
+        free_owned(b, s->ym);
+        s->d = d[i];
+        s->s = sm[i];
+        s->x = view(d[i]);
+        // level plan of the Sign so that d * Sign/2 lands on the scale delta
+        int lvl = s->d.level;
+        for (int j = 0; j < total; ++j) {
+          const int need = 4 + (j == total - 1 ? 1 : 0);
+          if (lvl - need < C.min_level) lvl = C.n_q - 1;
+          if (lvl - need < C.min_level) { b.fail(-3, "modulus chain too short for one unit"); return; }
+          lvl -= 4;
+        }
+        s->ls = lvl;
+        s->lp = std::min(s->d.level, lvl);
+        double t = delta * (double)C.mod[s->lp];
+        t = t / s->d.scale;
+        s->t_sign = t;
+      }
+      b.counters[6] += (int64_t)n;
+      break;
+    }
+    case S_POLY: {  // one polynomial of Sign = f^df(g^dg(x))  (Eq. 4)
+      std::vector<CT*> cts;
+      std::vector<int> need;
+      for (QState* s : qs) {
+        const Step& st = s->prog[s->pc];
+        cts.push_back(&s->x);
+        need.push_back(4 + ((st.max && st.arg == total - 1) ? 1 : 0));
+      }
+      maybe_refresh(b, qs, cts, need);
+      if (b.err_code) return;
+      std::vector<CT> in;
+      std::vector<const double*> coef;
+      std::vector<double> gain, tg;
+      for (QState* s : qs) {
+        const Step& st = s->prog[s->pc];
+        const bool last = st.arg == total - 1;
+        if (last && st.max && s->x.level - 4 != s->ls) { b.fail(-1, "level plan mismatch"); return; }
+        in.push_back(s->x);
+        coef.push_back(st.arg < C.dg ? kSignG : kSignF);
+        gain.push_back(last && st.max ? 0.5 : 1.0);
+        tg.push_back(last && st.max ? s->t_sign : delta);
+      }
+      std::vector<CT> y = b.eval_odd9(in, coef, gain, tg);
+      if (b.err_code) return;
+      for (size_t i = 0; i < n; ++i) {
+        free_owned(b, qs[i]->x);
+        qs[i]->x = y[i];
+        if (qs[i]->prog[qs[i]->pc].arg == total - 1) b.counters[0]++;
+      }
+      break;
+    }
+    case S_MAXPOST: {  // Max = (a+b)/2 + (a-b)/2 * Sign(a-b)   (Eq. 6)
+      auto lower = [](CT x, int l) { x.level = l; x.slot = -1; return x; };
+      for (QState* s : qs) pr.push_back({lower(s->d, s->lp), lower(s->x, s->lp)});
+      std::vector<CT> prod = b.mul_relin(pr, true);
+      if (b.err_code) return;
+      std::vector<CT> in;
+      std::vector<double> v, tg;
+      for (size_t i = 0; i < n; ++i) {
+        in.push_back(lower(qs[i]->s, qs[i]->lp));
+        v.push_back(0.5);
+        tg.push_back(prod[i].scale);
+      }
+      std::vector<CT> half = b.mul_const(in, v, tg);
+      if (b.err_code) return;
+      pr.clear();
+      for (size_t i = 0; i < n; ++i) pr.push_back({half[i], prod[i]});
+      std::vector<CT> out = b.add(pr, false);
+      if (b.err_code) return;
+      for (size_t i = 0; i < n; ++i) {
+        QState* s = qs[i];
+        b.free_ct(prod[i]);
+        b.free_ct(half[i]);
+        free_owned(b, s->d);
+        free_owned(b, s->s);
+        free_owned(b, s->x);
+        s->ym = out[i];
+      }
+      break;
+    }
+    case S_FINALPRE: {  // Algorithm 1, line 4: y <- y - y_max
+      for (QState* s : qs) pr.push_back({s->ydup, s->ym});
+      std::vector<CT> d = b.add(pr, true);
+      if (b.err_code) return;
+      for (size_t i = 0; i < n; ++i) {
+        QState* s = qs[i];
+        free_owned(b, s->ym);
+        free_owned(b, s->ydup);
+        s->d = d[i];
+        s->x = view(d[i]);
+      }
+      break;
+    }
+    case S_FINALPOST: {  // lines 5-6: z <- Sign(y) + 1, written to the caller's buffer
+      std::vector<EwJob> j;
+      for (QState* s : qs) {
+        const CT& x = s->x;
+        double kf = 1.0 * x.scale;
+        const int64_t K = llround(kf);
+        EwJob e{};
+        e.o0 = s->q->out.d;
+        e.o1 = s->q->out.d + (size_t)C.n_q * C.N;
+        e.a0 = b.c0(x);
+        e.a1 = b.c1(x);
+        e.k = b.put_residues(K, x.level + 1);
+        e.n_limbs = x.level + 1;
+        e.n_chain = x.level + 1;
+        e.op = EW_ADD_CONST;
+        j.push_back(e);
+        s->q->out.level = x.level;
+        s->q->out.scale = x.scale;
+      }
+      b.ew(j);
+      for (QState* s : qs) {
+        free_owned(b, s->x);
+        free_owned(b, s->d);
+      }
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+void build_argmax(Builder& b, std::vector<ArgmaxQuery>& queries) {
+  Ctx& C = b.C;
+  const int total = C.dg + C.df;
+  std::vector<QState> st(queries.size());
+  for (size_t i = 0; i < queries.size(); ++i) {
+    QState& s = st[i];
+    ArgmaxQuery& q = queries[i];
+    s.q = &q;
+    s.lk = ilog2_ceil(q.K);
+    s.lc = ilog2_ceil(q.C);
+    s.kp = 1 << s.lk;
+    s.cp = 1 << s.lc;
+    if (q.K < 1 || q.C < 1 || (int64_t)s.kp * s.cp > C.N / 2) { b.fail(-1, "K' * C' exceeds the slot count"); return; }
+    s.y = view(q.in);
+    for (int k = 0; k < s.lk; ++k) s.prog.push_back({S_ROTADD, s.cp << k, false});
+    s.prog.push_back({S_NORMALISE, 0, false});
+    s.prog.push_back({S_DUP, 0, false});
+    for (int k = 0; k < s.lc; ++k) {
+      s.prog.push_back({S_MAXPRE, k, true});
+      for (int j = 0; j < total; ++j) s.prog.push_back({S_POLY, j, true});
+      s.prog.push_back({S_MAXPOST, k, true});
+    }
+    s.prog.push_back({S_FINALPRE, 0, false});
+    for (int j = 0; j < total; ++j) s.prog.push_back({S_POLY, j, false});
+    s.prog.push_back({S_FINALPOST, 0, false});
+  }
+  for (;;) {
+    int count[S_NKINDS] = {0};
+    int active = 0;
+    for (QState& s : st)
+      if (s.pc < s.prog.size()) { count[s.prog[s.pc].kind]++; active++; }
+    if (!active) break;
+    int kind = 0;
+    for (int k = 1; k < S_NKINDS; ++k)
+      if (count[k] > count[kind]) kind = k;
+    std::vector<QState*> qs;
+    for (QState& s : st)
+      if (s.pc < s.prog.size() && s.prog[s.pc].kind == kind) qs.push_back(&s);
+    run_step(b, kind, qs);
+    if (b.err_code) return;
+    for (QState* s : qs) s->pc++;
+  }
+}
+
+}  // namespace secpe

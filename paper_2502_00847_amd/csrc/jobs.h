@@ -1,0 +1,143 @@
+// Launch descriptors shared by the host runtime and the kernels.
+//
+// Every kernel is batched: blockIdx.z selects a job (one ciphertext or
+// polynomial of one query), blockIdx.y a limb, blockIdx.x a tile of
+// coefficients.  Jobs carry their own level, so one launch can mix queries at
+// different levels.  Limb l of a polynomial over the basis "n_chain chain
+// primes, then special primes" uses prime l when l < n_chain and prime
+// n_q + (l - n_chain) otherwise; its coefficients start at data + l * N.
+#pragma once
+#include <stdint.h>
+
+namespace secpe {
+
+struct DevTables {
+  const double* mod;    // [n_mod] primes as doubles
+  const double* minv;   // [n_mod] fl(1/p)
+  const double* psi;    // [n_mod][N] psi^bitrev(k), forward twiddles
+  const double* psiq;   // [n_mod][N] fl(psi/p)
+  const double* ipsi;   // [n_mod][N] psi^-bitrev(k), inverse twiddles
+  const double* ipsiq;  // [n_mod][N]
+  const double* ninv;   // [n_mod] N^-1 mod p
+  const double* ninvq;  // [n_mod]
+  const double* cos_hi; // [2N] cos(pi t / N) as a double-double (hi, lo)
+  const double* cos_lo;
+  int n_q, n_p, log_n, pad;
+};
+
+// NTT over limbs [0, n_limbs) of src (skipping [skip_lo, skip_hi)), written to dst.
+struct NttJob {
+  const double* src;
+  double* dst;
+  int n_limbs, n_chain, skip_lo, skip_hi;
+};
+
+enum EwOp : int {
+  EW_ADD = 0,        // o0 = a0 + b0, o1 = a1 + b1
+  EW_SUB = 1,        // o0 = a0 - b0, o1 = a1 - b1
+  EW_TENSOR = 2,     // o0 = a0 b0, o1 = a0 b1 + a1 b0, o2 = a1 b1
+  EW_CMUL = 3,       // o_i = a_i * k[l]
+  EW_ADD_CONST = 4,  // o0 = a0 + k[l], o1 = a1
+  EW_PMUL = 5,       // o_i = a_i * b0 (plaintext polynomial b0)
+  EW_MODDOWN = 6,    // o_i = (a_i ? a_i : 0) + (b_i - c_i) * k[l]   (c_i = Conv_P of b_i)
+  EW_RESCALE = 7,    // o_i = (a_i - b_i) * k[l]
+  EW_DEC2 = 8,       // o0 = a0 + a1 * b0   (b0 = secret key limb)
+  EW_ENC = 9,        // o0 = m + e - a s   with a0 = m, a1 = e, b0 = a, b1 = s
+  EW_KEYB = 10,      // o0 = e - a s + k[l] s'   with a1 = e, b0 = a, b1 = s, c0 = s'
+  EW_MUL = 11,       // o0 = a0 * b0 (single polynomial)
+  EW_COPY = 12,      // o0 = a0, o1 = a1
+};
+
+struct EwJob {
+  double* o0;
+  double* o1;
+  double* o2;
+  const double* a0;
+  const double* a1;
+  const double* b0;
+  const double* b1;
+  const double* c0;
+  const double* c1;
+  const double* k;   // per-limb constants (canonical residues) or null
+  int n_limbs, n_chain;
+  int op, pad;
+};
+
+// ModUp of one digit: src (coefficient domain, limbs 0..level) -> dst limbs of
+// the extended basis Q_level u P outside the digit, coefficient domain.
+struct ModUpJob {
+  const double* src;
+  double* dst;          // [n_ext][N], limb index = extended-basis index
+  const double* cinv;   // [digit size] (D/q_i)^-1 mod q_i
+  const double* chat;   // [n_ext][digit size] (D/q_i) mod target
+  int digit_lo, digit_hi, n_chain, n_ext;
+};
+
+// Conv_{P->Q}: src = special limbs (coefficient domain) -> dst chain limbs 0..n_chain-1
+struct ModDownJob {
+  const double* src;    // [alpha][N]
+  double* dst;          // [n_chain][N]
+  const double* cinv;   // [alpha] (P/p_k)^-1 mod p_k
+  const double* chat;   // [n_chain][alpha] (P/p_k) mod q_i
+  int n_chain, pad;
+};
+
+// Inner product with a switching key: acc_w[t] = sum_j x_j[t] * key_j[w][t]
+struct InnerJob {
+  const double* d;      // NTT-domain input polynomial (chain limbs 0..level)
+  const double* ext;    // [dnum][n_ext][N] ModUp outputs, NTT domain
+  const double* key;    // [dnum_top][2][n_mod][N]
+  double* acc;          // [2][n_ext][N]
+  int n_chain, n_ext, n_digits, alpha;
+};
+
+// rescale: spread the centred top limb (coefficient domain) to limbs 0..n_chain-1
+struct SpreadJob {
+  const double* src;    // top limb, coefficient domain, residues mod src_prime
+  double* dst;          // [n_chain][N]
+  int src_prime, n_chain;
+};
+
+// Galois automorphism in the NTT domain (bit-reversed evaluation order)
+struct AutoJob {
+  const double* src;
+  double* dst;
+  int n_limbs, n_chain;
+  uint32_t galois, pad;
+};
+
+// refresh / encryption: CRT-lift m from limbs 0,1 (coefficient domain) and
+// write m mod q_t for t < n_out
+struct LiftJob {
+  const double* r0;
+  const double* r1;
+  double* dst;          // [n_out][N]
+  int64_t* m_out;       // optional: centred value as int64
+  int n_out, pad;
+};
+
+enum SampleKind : int { SAMPLE_UNIFORM = 0, SAMPLE_CBD = 1, SAMPLE_TERNARY = 2 };
+
+struct SampleJob {
+  double* dst;          // [n_limbs][N]
+  uint64_t seed;
+  uint64_t tag_base;    // tag with limb field 0; uniform adds the prime index
+  int n_limbs, n_chain, kind, pad;
+};
+
+// spread an int64 polynomial (host- or device-encoded) to limbs mod q_t
+struct IntSpreadJob {
+  const int64_t* src;
+  double* dst;
+  int n_limbs, n_chain;
+};
+
+// encode: m_k = round(scale * 2/N * sum_{j < nnz} z_j cos(pi (5^j k mod 2N)/N))
+struct EncodeJob {
+  const double* z;      // [nnz] slot values
+  int64_t* m;           // [N]
+  double scale_hi, scale_lo;   // scale * 2 / N as a double-double
+  int nnz, pad;
+};
+
+}  // namespace secpe

@@ -1,0 +1,718 @@
+// HIP kernels for RNS-CKKS on gfx950 (CDNA4, wave64).
+//
+// All kernels are batched through job descriptors (jobs.h) and use the exact
+// binary64 modular arithmetic of modarith.h.  Polynomials live in HBM limb by
+// limb (limb-major), each limb N canonical residues.
+//
+// Paper: arXiv 2502.00847, Sec. 2.2 (RNS-CKKS over Z_Q[X]/(X^N+1), the
+// homomorphic add / mult / rotate the Argmax is built from).
+#include "kernels.h"
+
+namespace secpe {
+
+// ---------------------------------------------------------------------------
+// negacyclic NTT
+//
+// Forward: merged Cooley-Tukey (natural order in, bit-reversed evaluation order
+// out): stage g pairs j and j + N/2^(g+1) with twiddle psi^bitrev(2^g + i),
+// i = j >> (logN - g).  Inverse: the Gentleman-Sande mirror with psi^-1, then
+// the factor N^-1.  For N > 2^12 the transform is split in two passes over a
+// 2^k1 x 2^k2 view of the limb: the first k1 stages only mix elements of one
+// column (stride 2^k2), the last k2 stages only elements of one row.  Each
+// workgroup stages a 4096-element tile in LDS; each round keeps up to 16
+// elements in registers and runs up to four radix-2 stages on them.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+
+enum { NTT_SINGLE = 0, NTT_COL = 1, NTT_ROW = 2 };
+
+template <int LOGS, int MODE>
+__device__ __forceinline__ int tw_index(int u, int v, int row, int k1) {
+  int idx = (1 << u) + (v >> (LOGS - u));
+  if (MODE == NTT_ROW) idx = (1 << (k1 + u)) + (row << u) + (v >> (LOGS - u));
+  return idx;
+}
+
+template <int LOGS, int G, int R, int MODE>
+__device__ __forceinline__ void fwd_round(double* lds, int u0, const double* __restrict__ tw,
+                                          const double* __restrict__ twq, const Mod& m, int row0, int k1) {
+  constexpr int S = 1 << LOGS;
+  constexpr int NG = (G * S) >> R;
+  const int b_hi = LOGS - 1 - u0;
+  const int b_lo = LOGS - u0 - R;
+  for (int grp = threadIdx.x; grp < NG; grp += blockDim.x) {
+    const int vec = grp / (S >> R);
+    const int rem = grp % (S >> R);
+    const int low = rem & ((1 << b_lo) - 1);
+    const int high = rem >> b_lo;
+    const int base = (high << (b_hi + 1)) | low;
+    double x[1 << R];
+#pragma unroll
+    for (int e = 0; e < (1 << R); ++e) x[e] = lds[lpad(vec * S + (base | (e << b_lo)))];
+#pragma unroll
+    for (int w = 0; w < R; ++w) {
+      const int u = u0 + w;
+      const int half = 1 << (R - 1 - w);
+#pragma unroll
+      for (int e0 = 0; e0 < (1 << R); ++e0) {
+        if (e0 & half) continue;
+        const int e1 = e0 + half;
+        const int v = base | (e0 << b_lo);
+        const int idx = tw_index<LOGS, MODE>(u, v, row0 + vec, k1);
+        const double U = red(x[e0], m);
+        const double T = mul_w(x[e1], tw[idx], twq[idx], m.p);
+        x[e0] = U + T;
+        x[e1] = U - T;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < (1 << R); ++e) lds[lpad(vec * S + (base | (e << b_lo)))] = x[e];
+  }
+}
+
+template <int LOGS, int G, int R, int MODE>
+__device__ __forceinline__ void inv_round(double* lds, int b_lo, const double* __restrict__ tw,
+                                          const double* __restrict__ twq, const Mod& m, int row0, int k1) {
+  constexpr int S = 1 << LOGS;
+  constexpr int NG = (G * S) >> R;
+  const int b_hi = b_lo + R - 1;
+  for (int grp = threadIdx.x; grp < NG; grp += blockDim.x) {
+    const int vec = grp / (S >> R);
+    const int rem = grp % (S >> R);
+    const int low = rem & ((1 << b_lo) - 1);
+    const int high = rem >> b_lo;
+    const int base = (high << (b_hi + 1)) | low;
+    double x[1 << R];
+#pragma unroll
+    for (int e = 0; e < (1 << R); ++e) x[e] = lds[lpad(vec * S + (base | (e << b_lo)))];
+#pragma unroll
+    for (int w = 0; w < R; ++w) {
+      const int u = LOGS - 1 - (b_lo + w);
+      const int half = 1 << w;
+#pragma unroll
+      for (int e0 = 0; e0 < (1 << R); ++e0) {
+        if (e0 & half) continue;
+        const int e1 = e0 + half;
+        const int v = base | (e0 << b_lo);
+        const int idx = tw_index<LOGS, MODE>(u, v, row0 + vec, k1);
+        const double U = red(x[e0], m);
+        const double V = red(x[e1], m);
+        x[e0] = U + V;
+        x[e1] = mul_w(U - V, tw[idx], twq[idx], m.p);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < (1 << R); ++e) lds[lpad(vec * S + (base | (e << b_lo)))] = x[e];
+  }
+}
+
+template <int LOGS, int G, int MODE, int U0>
+__device__ __forceinline__ void fwd_all(double* lds, const double* tw, const double* twq, const Mod& m, int row0, int k1) {
+  if constexpr (U0 < LOGS) {
+    constexpr int R = (LOGS - U0) < 4 ? (LOGS - U0) : 4;
+    fwd_round<LOGS, G, R, MODE>(lds, U0, tw, twq, m, row0, k1);
+    __syncthreads();
+    fwd_all<LOGS, G, MODE, U0 + R>(lds, tw, twq, m, row0, k1);
+  }
+}
+
+template <int LOGS, int G, int MODE, int B0>
+__device__ __forceinline__ void inv_all(double* lds, const double* tw, const double* twq, const Mod& m, int row0, int k1) {
+  if constexpr (B0 < LOGS) {
+    constexpr int R = (LOGS - B0) < 4 ? (LOGS - B0) : 4;
+    inv_round<LOGS, G, R, MODE>(lds, B0, tw, twq, m, row0, k1);
+    __syncthreads();
+    inv_all<LOGS, G, MODE, B0 + R>(lds, tw, twq, m, row0, k1);
+  }
+}
+
+template <int LOGS, int G, int MODE, bool INV>
+__global__ __launch_bounds__(256) void k_ntt(const NttJob* __restrict__ jobs, DevTables T, int second) {
+  extern __shared__ double lds[];
+  const NttJob J = jobs[blockIdx.z];
+  const int l = blockIdx.y;
+  if (l >= J.n_limbs || (l >= J.skip_lo && l < J.skip_hi)) return;
+  const int pr = l < J.n_chain ? l : T.n_q + (l - J.n_chain);
+  const int log_n = T.log_n;
+  const int N = 1 << log_n;
+  constexpr int S = 1 << LOGS;
+  const Mod m{T.mod[pr], T.minv[pr]};
+  const double* tw = (INV ? T.ipsi : T.psi) + (size_t)pr * N;
+  const double* twq = (INV ? T.ipsiq : T.psiq) + (size_t)pr * N;
+  const double* src = (second ? J.dst : J.src) + (size_t)l * N;
+  double* dst = J.dst + (size_t)l * N;
+  const int tid = threadIdx.x;
+  const int k1 = log_n - LOGS;
+  const int C = N >> LOGS;            // number of vectors of length S
+  int row0 = 0;
+  if (MODE == NTT_COL) {
+    const int c0 = blockIdx.x * G;
+    for (int i = tid; i < G * S / 2; i += blockDim.x) {
+      const int cp = i % (G / 2);
+      const int v = i / (G / 2);
+      const double2 val = *reinterpret_cast<const double2*>(src + (size_t)v * C + c0 + 2 * cp);
+      lds[lpad((2 * cp) * S + v)] = val.x;
+      lds[lpad((2 * cp + 1) * S + v)] = val.y;
+    }
+  } else {
+    row0 = blockIdx.x * G;
+    const double2* s2 = reinterpret_cast<const double2*>(src + (size_t)row0 * S);
+    for (int i = tid; i < G * S / 2; i += blockDim.x) {
+      const double2 val = s2[i];
+      lds[lpad(2 * i)] = val.x;
+      lds[lpad(2 * i + 1)] = val.y;
+    }
+  }
+  __syncthreads();
+  if (INV) inv_all<LOGS, G, MODE, 0>(lds, tw, twq, m, row0, k1);
+  else fwd_all<LOGS, G, MODE, 0>(lds, tw, twq, m, row0, k1);
+  const bool scale = INV && MODE != NTT_ROW;
+  const double ni = T.ninv[pr], niq = T.ninvq[pr];
+  if (MODE == NTT_COL) {
+    const int c0 = blockIdx.x * G;
+    for (int i = tid; i < G * S / 2; i += blockDim.x) {
+      const int cp = i % (G / 2);
+      const int v = i / (G / 2);
+      double a = lds[lpad((2 * cp) * S + v)];
+      double b = lds[lpad((2 * cp + 1) * S + v)];
+      if (scale) { a = mul_w(red(a, m), ni, niq, m.p); b = mul_w(red(b, m), ni, niq, m.p); }
+      *reinterpret_cast<double2*>(dst + (size_t)v * C + c0 + 2 * cp) = make_double2(canon(a, m), canon(b, m));
+    }
+  } else {
+    double2* d2 = reinterpret_cast<double2*>(dst + (size_t)row0 * S);
+    for (int i = tid; i < G * S / 2; i += blockDim.x) {
+      double a = lds[lpad(2 * i)];
+      double b = lds[lpad(2 * i + 1)];
+      if (scale) { a = mul_w(red(a, m), ni, niq, m.p); b = mul_w(red(b, m), ni, niq, m.p); }
+      d2[i] = make_double2(canon(a, m), canon(b, m));
+    }
+  }
+}
+
+size_t ntt_lds_bytes(int logs, int g) {
+  const int n = g << logs;
+  return (size_t)(n + (n >> 4)) * sizeof(double);
+}
+
+#define NTT_INST(LOGS, G, MODE)                                                                  \
+  template __global__ void k_ntt<LOGS, G, MODE, false>(const NttJob* __restrict__, DevTables, int); \
+  template __global__ void k_ntt<LOGS, G, MODE, true>(const NttJob* __restrict__, DevTables, int);
+
+// single pass (N <= 2^12) and two-pass halves for N = 2^13 .. 2^16
+NTT_INST(10, 1, NTT_SINGLE)
+NTT_INST(11, 1, NTT_SINGLE)
+NTT_INST(12, 1, NTT_SINGLE)
+NTT_INST(6, 64, NTT_COL)
+NTT_INST(7, 32, NTT_COL)
+NTT_INST(8, 16, NTT_COL)
+NTT_INST(7, 32, NTT_ROW)
+NTT_INST(8, 16, NTT_ROW)
+
+void* ntt_kernel(int logs, int mode, bool inv, int* g_out) {
+#define PICK(LOGS, G, MODE)                                                                       \
+  if (logs == LOGS && mode == MODE) {                                                             \
+    *g_out = G;                                                                                   \
+    return inv ? (void*)&k_ntt<LOGS, G, MODE, true> : (void*)&k_ntt<LOGS, G, MODE, false>;        \
+  }
+  PICK(10, 1, NTT_SINGLE)
+  PICK(11, 1, NTT_SINGLE)
+  PICK(12, 1, NTT_SINGLE)
+  PICK(6, 64, NTT_COL)
+  PICK(7, 32, NTT_COL)
+  PICK(8, 16, NTT_COL)
+  PICK(7, 32, NTT_ROW)
+  PICK(8, 16, NTT_ROW)
+#undef PICK
+  return nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// elementwise operations on limbs (NTT domain unless stated)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_ew(const EwJob* __restrict__ jobs, DevTables T) {
+  const EwJob J = jobs[blockIdx.z];
+  const int l = blockIdx.y;
+  if (l >= J.n_limbs) return;
+  const int pr = l < J.n_chain ? l : T.n_q + (l - J.n_chain);
+  const Mod m{T.mod[pr], T.minv[pr]};
+  const int N = 1 << T.log_n;
+  const size_t off = (size_t)l * N;
+  const double kk = J.k ? J.k[l] : 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    const size_t o = off + i;
+    switch (J.op) {
+      case EW_ADD:
+        J.o0[o] = add_mod(J.a0[o], J.b0[o], m);
+        J.o1[o] = add_mod(J.a1[o], J.b1[o], m);
+        break;
+      case EW_SUB:
+        J.o0[o] = sub_mod(J.a0[o], J.b0[o], m);
+        J.o1[o] = sub_mod(J.a1[o], J.b1[o], m);
+        break;
+      case EW_TENSOR: {
+        const double a0 = J.a0[o], a1 = J.a1[o], b0 = J.b0[o], b1 = J.b1[o];
+        const double t0 = mul_mod(a0, b0, m);
+        const double t1 = mul_mod(a0, b1, m) + mul_mod(a1, b0, m);
+        const double t2 = mul_mod(a1, b1, m);
+        J.o0[o] = canon(t0, m);
+        J.o1[o] = canon(t1, m);
+        J.o2[o] = canon(t2, m);
+        break;
+      }
+      case EW_CMUL:
+        J.o0[o] = canon(mul_mod(J.a0[o], kk, m), m);
+        J.o1[o] = canon(mul_mod(J.a1[o], kk, m), m);
+        break;
+      case EW_ADD_CONST:
+        J.o0[o] = add_mod(J.a0[o], kk, m);
+        if (J.o1 != J.a1) J.o1[o] = J.a1[o];
+        break;
+      case EW_PMUL: {
+        const double p = J.b0[o];
+        J.o0[o] = canon(mul_mod(J.a0[o], p, m), m);
+        J.o1[o] = canon(mul_mod(J.a1[o], p, m), m);
+        break;
+      }
+      case EW_MODDOWN: {
+        const double d0 = mul_mod(J.b0[o] - J.c0[o], kk, m);
+        const double d1 = mul_mod(J.b1[o] - J.c1[o], kk, m);
+        J.o0[o] = canon((J.a0 ? J.a0[o] : 0.0) + d0, m);
+        J.o1[o] = canon((J.a1 ? J.a1[o] : 0.0) + d1, m);
+        break;
+      }
+      case EW_RESCALE:
+        J.o0[o] = canon(mul_mod(J.a0[o] - J.b0[o], kk, m), m);
+        J.o1[o] = canon(mul_mod(J.a1[o] - J.b1[o], kk, m), m);
+        break;
+      case EW_DEC2:
+        J.o0[o] = canon(J.a0[o] + mul_mod(J.a1[o], J.b0[o], m), m);
+        break;
+      case EW_ENC: {
+        const double as = mul_mod(J.b0[o], J.b1[o], m);
+        J.o0[o] = canon(J.a0[o] + J.a1[o] - as, m);
+        break;
+      }
+      case EW_KEYB: {
+        const double as = mul_mod(J.b0[o], J.b1[o], m);
+        double v = J.a1[o] - as;
+        if (kk != 0.0) v += mul_mod(kk, J.c0[o], m);
+        J.o0[o] = canon(v, m);
+        break;
+      }
+      case EW_MUL:
+        J.o0[o] = canon(mul_mod(J.a0[o], J.b0[o], m), m);
+        break;
+      case EW_COPY:
+        J.o0[o] = J.a0[o];
+        if (J.o1) J.o1[o] = J.a1[o];
+        break;
+      default:
+        break;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// basis conversion (hybrid key switching)
+// ModUp for one digit D = prod_{i in digit} q_i:
+//   y_i = [x_i (D/q_i)^-1]_{q_i},  out_t = sum_i y_i (D/q_i) mod t
+// ---------------------------------------------------------------------------
+constexpr int MAX_DIGIT = 16;
+
+__global__ __launch_bounds__(256) void k_modup(const ModUpJob* __restrict__ jobs, DevTables T) {
+  const ModUpJob J = jobs[blockIdx.z];
+  const int N = 1 << T.log_n;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const int dsz = J.digit_hi - J.digit_lo;
+  double y[MAX_DIGIT];
+#pragma unroll
+  for (int i = 0; i < MAX_DIGIT; ++i) {
+    if (i < dsz) {
+      const int pr = J.digit_lo + i;
+      const Mod mi{T.mod[pr], T.minv[pr]};
+      y[i] = canon(mul_mod(J.src[(size_t)pr * N + k], J.cinv[i], mi), mi);
+    }
+  }
+  for (int t = 0; t < J.n_ext; ++t) {
+    if (t >= J.digit_lo && t < J.digit_hi) continue;
+    const int pr = t < J.n_chain ? t : T.n_q + (t - J.n_chain);
+    const Mod mt{T.mod[pr], T.minv[pr]};
+    const double* ch = J.chat + (size_t)pr * dsz;
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < MAX_DIGIT; ++i) {
+      if (i < dsz) {
+        acc += mul_mod(y[i], ch[i], mt);
+        if (i & 1) acc = red(acc, mt);
+      }
+    }
+    J.dst[(size_t)t * N + k] = canon(acc, mt);
+  }
+}
+
+// Conv_{P -> Q_l}: y_k = [x_k (P/p_k)^-1]_{p_k},  out_i = sum_k y_k (P/p_k) mod q_i
+__global__ __launch_bounds__(256) void k_moddown_conv(const ModDownJob* __restrict__ jobs, DevTables T) {
+  const ModDownJob J = jobs[blockIdx.z];
+  const int N = 1 << T.log_n;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const int alpha = T.n_p;
+  double y[MAX_DIGIT];
+#pragma unroll
+  for (int i = 0; i < MAX_DIGIT; ++i) {
+    if (i < alpha) {
+      const int pr = T.n_q + i;
+      const Mod mi{T.mod[pr], T.minv[pr]};
+      y[i] = canon(mul_mod(J.src[(size_t)i * N + k], J.cinv[i], mi), mi);
+    }
+  }
+  for (int t = 0; t < J.n_chain; ++t) {
+    const Mod mt{T.mod[t], T.minv[t]};
+    const double* ch = J.chat + (size_t)t * alpha;
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < MAX_DIGIT; ++i) {
+      if (i < alpha) {
+        acc += mul_mod(y[i], ch[i], mt);
+        if (i & 1) acc = red(acc, mt);
+      }
+    }
+    J.dst[(size_t)t * N + k] = canon(acc, mt);
+  }
+}
+
+// acc_w[t] = sum_j x_j[t] key_j[w][t]; x_j[t] = d[t] inside digit j, else ModUp output
+__global__ __launch_bounds__(256) void k_inner(const InnerJob* __restrict__ jobs, DevTables T) {
+  const InnerJob J = jobs[blockIdx.z];
+  const int t = blockIdx.y;
+  if (t >= J.n_ext) return;
+  const int N = 1 << T.log_n;
+  const int n_mod = T.n_q + T.n_p;
+  const int pr = t < J.n_chain ? t : T.n_q + (t - J.n_chain);
+  const Mod m{T.mod[pr], T.minv[pr]};
+  const int own = t < J.n_chain ? t / J.alpha : -1;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < N; k += gridDim.x * blockDim.x) {
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int j = 0; j < J.n_digits; ++j) {
+      const double x = (j == own) ? J.d[(size_t)t * N + k] : J.ext[((size_t)j * J.n_ext + t) * N + k];
+      const double kb = J.key[(((size_t)j * 2 + 0) * n_mod + pr) * N + k];
+      const double ka = J.key[(((size_t)j * 2 + 1) * n_mod + pr) * N + k];
+      acc0 += mul_mod(x, kb, m);
+      acc1 += mul_mod(x, ka, m);
+      if (j & 1) { acc0 = red(acc0, m); acc1 = red(acc1, m); }
+    }
+    J.acc[(size_t)t * N + k] = canon(acc0, m);
+    J.acc[((size_t)J.n_ext + t) * N + k] = canon(acc1, m);
+  }
+}
+
+// rescale: centred top limb -> residues mod q_i, i < n_chain (coefficient domain)
+__global__ __launch_bounds__(256) void k_spread_centred(const SpreadJob* __restrict__ jobs, DevTables T) {
+  const SpreadJob J = jobs[blockIdx.z];
+  const int N = 1 << T.log_n;
+  const int i = blockIdx.y;
+  if (i >= J.n_chain) return;
+  const double qt = T.mod[J.src_prime];
+  const Mod m{T.mod[i], T.minv[i]};
+  const double half = (qt - 1.0) * 0.5;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < N; k += gridDim.x * blockDim.x) {
+    double v = J.src[k];
+    if (v > half) v -= qt;
+    J.dst[(size_t)i * N + k] = canon(v, m);
+  }
+}
+
+// X -> X^g in the bit-reversed NTT domain: out[k] = in[brv(((2 brv(k) + 1) g mod 2N - 1) / 2)]
+__global__ __launch_bounds__(256) void k_automorph(const AutoJob* __restrict__ jobs, DevTables T) {
+  const AutoJob J = jobs[blockIdx.z];
+  const int l = blockIdx.y;
+  if (l >= J.n_limbs) return;
+  const int log_n = T.log_n;
+  const int N = 1 << log_n;
+  const uint32_t mask = 2u * N - 1u;
+  const double* src = J.src + (size_t)l * N;
+  double* dst = J.dst + (size_t)l * N;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < N; k += gridDim.x * blockDim.x) {
+    const uint32_t kr = __builtin_bitreverse32((uint32_t)k) >> (32 - log_n);
+    const uint32_t e = ((2u * kr + 1u) * J.galois) & mask;
+    const uint32_t j = (e - 1u) >> 1;
+    const uint32_t s = __builtin_bitreverse32(j) >> (32 - log_n);
+    dst[k] = src[s];
+  }
+}
+
+// CRT lift of m from residues r0 mod q0, r1 mod q1 (coefficient domain) to the
+// centred integer, then m mod q_t for t < n_out; optionally the int64 value.
+// ctab: [n_out][2] = (q0 mod q_t, q0 q1 mod q_t); cinv = q0^-1 mod q1.
+__global__ __launch_bounds__(256) void k_lift(const LiftJob* __restrict__ jobs, DevTables T, const double* __restrict__ ctab,
+                                              double q0inv_q1) {
+  const LiftJob J = jobs[blockIdx.z];
+  const int N = 1 << T.log_n;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const Mod m0{T.mod[0], T.minv[0]};
+  const Mod m1{T.mod[1], T.minv[1]};
+  const double r0 = J.r0[k], r1 = J.r1[k];
+  const double diff = r1 - red(r0, m1);
+  const double d = canon(mul_mod(diff, q0inv_q1, m1), m1);
+  const double h = (m1.p - 1.0) * 0.5;
+  const bool neg = d > h || (d == h && r0 > (m0.p - 1.0) * 0.5);
+  for (int t = 0; t < J.n_out; ++t) {
+    const Mod mt{T.mod[t], T.minv[t]};
+    double v = red(r0, mt) + mul_mod(d, ctab[2 * t], mt);
+    if (neg) v -= ctab[2 * t + 1];
+    J.dst[(size_t)t * N + k] = canon(v, mt);
+  }
+  if (J.m_out) {
+    const uint64_t q0 = (uint64_t)m0.p, q1 = (uint64_t)m1.p;
+    const uint64_t di = (uint64_t)d, ri = (uint64_t)r0;
+    uint64_t lo = q0 * di;
+    uint64_t hi = __umul64hi(q0, di);
+    const uint64_t lo2 = lo + ri;
+    hi += lo2 < lo;
+    lo = lo2;
+    if (neg) {
+      const uint64_t Qlo = q0 * q1, Qhi = __umul64hi(q0, q1);
+      const uint64_t nlo = lo - Qlo;
+      hi = hi - Qhi - (lo < Qlo);
+      lo = nlo;
+    }
+    // (hi, lo) is a two's-complement 128-bit value; keep it when it fits int64
+    const int64_t v = (int64_t)lo;
+    const bool fits = (hi == 0 && v >= 0) || (hi == ~0ull && v < 0);
+    J.m_out[k] = fits ? v : INT64_MIN;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// counter-based SplitMix64 (Steele, Lea, Flood 2014) and samplers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t sm_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ uint64_t sm_draw(uint64_t key, uint64_t i) { return sm_mix(key + (i + 1) * 0x9E3779B97F4A7C15ull); }
+
+__global__ __launch_bounds__(256) void k_sample(const SampleJob* __restrict__ jobs, DevTables T) {
+  const SampleJob J = jobs[blockIdx.z];
+  const int l = blockIdx.y;
+  if (l >= J.n_limbs) return;
+  const int pr = l < J.n_chain ? l : T.n_q + (l - J.n_chain);
+  const int N = 1 << T.log_n;
+  const Mod m{T.mod[pr], T.minv[pr]};
+  const uint64_t tag = J.kind == SAMPLE_UNIFORM ? (J.tag_base | (uint64_t)pr) : (J.tag_base | 0xFFFull);
+  const uint64_t key = sm_mix(J.seed ^ sm_mix(tag));
+  const uint64_t q = (uint64_t)m.p;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    double v;
+    if (J.kind == SAMPLE_UNIFORM) {
+      const uint64_t hi = sm_draw(key, 2 * (uint64_t)i), lo = sm_draw(key, 2 * (uint64_t)i + 1);
+      const uint64_t a = __umul64hi(lo, q);
+      const uint64_t b_lo = hi * q;
+      const uint64_t b_hi = __umul64hi(hi, q);
+      const uint64_t s = b_lo + a;
+      v = (double)(b_hi + (s < b_lo));
+    } else if (J.kind == SAMPLE_CBD) {
+      const uint64_t r = sm_draw(key, (uint64_t)i);
+      const uint64_t mk = (1ull << 21) - 1;
+      v = (double)((int)__popcll(r & mk) - (int)__popcll((r >> 21) & mk));
+      v = v < 0.0 ? v + m.p : v;
+    } else {
+      const uint64_t r = sm_draw(key, (uint64_t)i);
+      v = (double)(int64_t)__umul64hi(r, 3ull) - 1.0;
+      v = v < 0.0 ? v + m.p : v;
+    }
+    J.dst[(size_t)l * N + i] = v;
+  }
+}
+
+// int64 polynomial -> canonical residues per limb
+__global__ __launch_bounds__(256) void k_int_spread(const IntSpreadJob* __restrict__ jobs, DevTables T) {
+  const IntSpreadJob J = jobs[blockIdx.z];
+  const int l = blockIdx.y;
+  if (l >= J.n_limbs) return;
+  const int pr = l < J.n_chain ? l : T.n_q + (l - J.n_chain);
+  const int N = 1 << T.log_n;
+  const int64_t q = (int64_t)T.mod[pr];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    int64_t r = J.src[i] % q;
+    if (r < 0) r += q;
+    J.dst[(size_t)l * N + i] = (double)r;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// canonical-embedding encode in double-double (Dekker 1971; Shewchuk 1997):
+// m_k = round-half-away(scale * 2/N * sum_j z_j cos(pi (5^j k mod 2N) / N))
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ void dd_add(double& ah, double& al, double bh, double bl) {
+  double s, e;
+  two_sum(ah, bh, s, e);
+  e += al + bl;
+  ah = s + e;
+  al = e - (ah - s);
+}
+__device__ __forceinline__ void dd_mul(double ah, double al, double bh, double bl, double& ph, double& pl) {
+  const double p = ah * bh;
+  double e = fma_rn(ah, bh, -p);
+  e = fma_rn(ah, bl, e);
+  e = fma_rn(al, bh, e);
+  ph = p + e;
+  pl = e - (ph - p);
+}
+
+__global__ __launch_bounds__(256) void k_encode(const EncodeJob* __restrict__ jobs, DevTables T) {
+  const EncodeJob J = jobs[blockIdx.z];
+  const int log_n = T.log_n;
+  const int N = 1 << log_n;
+  const uint32_t mask = 2u * N - 1u;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  double sh = 0.0, sl = 0.0;
+  uint32_t g = 1;
+  for (int j = 0; j < J.nnz; ++j) {
+    const double z = J.z[j];
+    if (z != 0.0) {
+      const uint32_t t = (g * (uint32_t)k) & mask;
+      double ph, pl;
+      dd_mul(z, 0.0, T.cos_hi[t], T.cos_lo[t], ph, pl);
+      dd_add(sh, sl, ph, pl);
+    }
+    g = (g * 5u) & mask;
+  }
+  double yh, yl;
+  dd_mul(sh, sl, J.scale_hi, J.scale_lo, yh, yl);
+  const bool negv = yh < 0.0 || (yh == 0.0 && yl < 0.0);
+  if (negv) { yh = -yh; yl = -yl; }
+  const double f = floor(yh);
+  const double frac = (yh - f) + yl + 0.5;
+  const int64_t v = (int64_t)f + (int64_t)floor(frac);
+  J.m[k] = negv ? -v : v;
+}
+
+// decode of slots [0, nslots): z_j = (1/scale) sum_k m_k cos(pi (5^j k mod 2N) / N)
+__global__ __launch_bounds__(256) void k_decode(const int64_t* __restrict__ m, double* __restrict__ z, double inv_scale,
+                                                DevTables T) {
+  __shared__ double part[256];
+  const int log_n = T.log_n;
+  const int N = 1 << log_n;
+  const uint32_t mask = 2u * N - 1u;
+  const int j = blockIdx.x;
+  uint32_t g = 1;
+  for (int i = 0; i < j; ++i) g = (g * 5u) & mask;
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < N; k += blockDim.x) {
+    const uint32_t t = (g * (uint32_t)k) & mask;
+    acc += (double)m[k] * T.cos_hi[t];
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) z[j] = part[0] * inv_scale;
+}
+
+}  // namespace secpe
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+namespace secpe {
+
+static inline int ew_blocks(int n) { return (n + 256 * 2 - 1) / (256 * 2); }
+
+void launch_ntt(const DevTables& T, bool inverse, const NttJob* jobs, int n_jobs, int max_limbs, hipStream_t s) {
+  if (n_jobs <= 0 || max_limbs <= 0) return;
+  const int log_n = T.log_n;
+  const int N = 1 << log_n;
+  auto run = [&](int logs, int mode, int second) {
+    int g = 0;
+    void* fn = ntt_kernel(logs, mode, inverse, &g);
+    const int tiles = (N >> logs) / g;
+    dim3 grid(tiles, max_limbs, n_jobs);
+    const NttJob* jp = jobs;
+    DevTables t = T;
+    int sec = second;
+    void* args[] = {(void*)&jp, (void*)&t, (void*)&sec};
+    (void)hipLaunchKernel(fn, grid, dim3(256), args, ntt_lds_bytes(logs, g), s);
+  };
+  if (log_n <= 12) {
+    run(log_n, NTT_SINGLE, 0);
+    return;
+  }
+  // the second pass works in place on what the first wrote to dst
+  const int k1 = log_n / 2, k2 = log_n - k1;
+  if (!inverse) {
+    run(k1, NTT_COL, 0);
+    run(k2, NTT_ROW, 1);
+  } else {
+    run(k2, NTT_ROW, 0);
+    run(k1, NTT_COL, 1);
+  }
+}
+
+void launch_ew(const DevTables& T, const EwJob* jobs, int n_jobs, int max_limbs, hipStream_t s) {
+  if (n_jobs <= 0 || max_limbs <= 0) return;
+  dim3 grid(ew_blocks(1 << T.log_n), max_limbs, n_jobs);
+  hipLaunchKernelGGL(k_ew, grid, dim3(256), 0, s, jobs, T);
+}
+void launch_modup(const DevTables& T, const ModUpJob* jobs, int n_jobs, hipStream_t s) {
+  if (n_jobs <= 0) return;
+  dim3 grid((1 << T.log_n) / 256, 1, n_jobs);
+  hipLaunchKernelGGL(k_modup, grid, dim3(256), 0, s, jobs, T);
+}
+void launch_moddown_conv(const DevTables& T, const ModDownJob* jobs, int n_jobs, hipStream_t s) {
+  if (n_jobs <= 0) return;
+  dim3 grid((1 << T.log_n) / 256, 1, n_jobs);
+  hipLaunchKernelGGL(k_moddown_conv, grid, dim3(256), 0, s, jobs, T);
+}
+void launch_inner(const DevTables& T, const InnerJob* jobs, int n_jobs, int max_ext, hipStream_t s) {
+  if (n_jobs <= 0 || max_ext <= 0) return;
+  dim3 grid(ew_blocks(1 << T.log_n), max_ext, n_jobs);
+  hipLaunchKernelGGL(k_inner, grid, dim3(256), 0, s, jobs, T);
+}
+void launch_spread_centred(const DevTables& T, const SpreadJob* jobs, int n_jobs, int max_chain, hipStream_t s) {
+  if (n_jobs <= 0 || max_chain <= 0) return;
+  dim3 grid(ew_blocks(1 << T.log_n), max_chain, n_jobs);
+  hipLaunchKernelGGL(k_spread_centred, grid, dim3(256), 0, s, jobs, T);
+}
+void launch_automorph(const DevTables& T, const AutoJob* jobs, int n_jobs, int max_limbs, hipStream_t s) {
+  if (n_jobs <= 0 || max_limbs <= 0) return;
+  dim3 grid(ew_blocks(1 << T.log_n), max_limbs, n_jobs);
+  hipLaunchKernelGGL(k_automorph, grid, dim3(256), 0, s, jobs, T);
+}
+void launch_lift(const DevTables& T, const LiftJob* jobs, int n_jobs, const double* ctab, double q0inv_q1, hipStream_t s) {
+  if (n_jobs <= 0) return;
+  dim3 grid((1 << T.log_n) / 256, 1, n_jobs);
+  hipLaunchKernelGGL(k_lift, grid, dim3(256), 0, s, jobs, T, ctab, q0inv_q1);
+}
+void launch_sample(const DevTables& T, const SampleJob* jobs, int n_jobs, int max_limbs, hipStream_t s) {
+  if (n_jobs <= 0 || max_limbs <= 0) return;
+  dim3 grid(ew_blocks(1 << T.log_n), max_limbs, n_jobs);
+  hipLaunchKernelGGL(k_sample, grid, dim3(256), 0, s, jobs, T);
+}
+void launch_int_spread(const DevTables& T, const IntSpreadJob* jobs, int n_jobs, int max_limbs, hipStream_t s) {
+  if (n_jobs <= 0 || max_limbs <= 0) return;
+  dim3 grid(ew_blocks(1 << T.log_n), max_limbs, n_jobs);
+  hipLaunchKernelGGL(k_int_spread, grid, dim3(256), 0, s, jobs, T);
+}
+void launch_encode(const DevTables& T, const EncodeJob* jobs, int n_jobs, hipStream_t s) {
+  if (n_jobs <= 0) return;
+  dim3 grid((1 << T.log_n) / 256, 1, n_jobs);
+  hipLaunchKernelGGL(k_encode, grid, dim3(256), 0, s, jobs, T);
+}
+void launch_decode(const DevTables& T, const int64_t* m, double* z, int nslots, double inv_scale, hipStream_t s) {
+  if (nslots <= 0) return;
+  hipLaunchKernelGGL(k_decode, dim3(nslots), dim3(256), 0, s, m, z, inv_scale, T);
+}
+
+}  // namespace secpe

@@ -1,0 +1,240 @@
+// Host runtime: context, device tables, command lists and batched CKKS ops.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+namespace secpe {
+
+using u128 = unsigned __int128;
+
+// ---------------------------------------------------------------------------
+// host modular arithmetic for table construction
+// ---------------------------------------------------------------------------
+inline uint64_t hmul(uint64_t a, uint64_t b, uint64_t q) { return (uint64_t)((u128)a * b % q); }
+inline uint64_t hpow(uint64_t a, uint64_t e, uint64_t q) {
+  uint64_t r = 1 % q;
+  a %= q;
+  for (; e; e >>= 1) {
+    if (e & 1) r = hmul(r, a, q);
+    a = hmul(a, a, q);
+  }
+  return r;
+}
+inline uint64_t hinv(uint64_t a, uint64_t q) { return hpow(a % q, q - 2, q); }
+inline uint64_t hmod_i64(int64_t v, uint64_t q) {
+  int64_t r = v % (int64_t)q;
+  return (uint64_t)(r < 0 ? r + (int64_t)q : r);
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct DigitTable {
+  const double* cinv;  // [dsz]
+  const double* chat;  // [n_mod][dsz], indexed by absolute prime
+};
+
+struct KeyRef {
+  const double* base;  // [dnum][2][n_mod][N]
+};
+
+struct Ctx;
+
+struct GraphEntry {
+  uint64_t hash = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  std::vector<int> out_level;
+  std::vector<double> out_scale;
+  int64_t counters[8] = {0};
+};
+
+struct Ctx {
+  // parameters
+  int log_n = 0, N = 0, n_q = 0, n_p = 0, alpha = 0, dnum = 0, n_mod = 0;
+  int q_bits = 0, p_bits = 0, log_scale = 0, dg = 2, df = 2, min_level = 1;
+  std::vector<uint64_t> mod;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  // device tables
+  double* d_tab = nullptr;
+  size_t tab_bytes = 0;
+  DevTables T{};
+  std::map<std::pair<int, int>, DigitTable> digits;  // (digit_lo, size)
+  const double* md_cinv = nullptr;   // [alpha]
+  const double* md_chat = nullptr;   // [n_q][alpha]
+  const double* md_pinv = nullptr;   // [n_q] P^-1 mod q_t
+  const double* p_mod_q = nullptr;   // [n_q] P mod q_t
+  const double* rs_tab = nullptr;    // [n_q][n_q] q_l^-1 mod q_i at [l][i]
+  const double* crt_tab = nullptr;   // [n_q][2]
+  double q0inv_q1 = 0.0;
+  // keys
+  std::map<uint64_t, const double*> keys;  // Galois element -> key; 0 = relinearisation
+  const double* refresh_sk = nullptr;
+  // descriptor arena
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  char* staging = nullptr;  // pinned
+  size_t staging_bytes = 0;
+  hipEvent_t staging_done = nullptr;
+  // client scratch
+  char* client = nullptr;
+  size_t client_bytes = 0;
+  // statistics of the last evaluation
+  int64_t counters[8] = {0};
+  std::vector<GraphEntry> graphs;
+
+  size_t limb_bytes() const { return (size_t)N * sizeof(double); }
+  size_t ct_bytes() const { return 2 * (size_t)n_q * limb_bytes(); }
+  size_t key_bytes() const { return (size_t)dnum * 2 * n_mod * limb_bytes(); }
+  size_t sk_bytes() const { return (size_t)n_mod * limb_bytes(); }
+  uint64_t galois(int64_t step) const;
+};
+
+int build_context(Ctx& c, int log_n, int n_q, int q_bits, int n_p, int p_bits, int log_scale, int dg, int df,
+                  int min_level, int device, hipStream_t stream);
+void destroy_context(Ctx& c);
+
+// ---------------------------------------------------------------------------
+// command list: descriptors in one blob, launches replayed in order
+// ---------------------------------------------------------------------------
+enum CmdKind { C_NTT, C_EW, C_MODUP, C_MODDOWN, C_INNER, C_SPREAD, C_AUTO, C_LIFT, C_SAMPLE, C_INTSPREAD, C_ENCODE, C_DECODE };
+
+struct Cmd {
+  int kind;
+  int n;
+  int max_y;
+  size_t off;
+  bool inv;
+  const int64_t* m;
+  double* z;
+  double inv_scale;
+};
+
+// ciphertext handle inside a build: device data [2][n_q][N], level, scale, pool slot
+struct CT {
+  double* d = nullptr;
+  int level = -1;
+  double scale = 0.0;
+  int slot = -1;   // -1: not owned by the pool
+};
+
+class Builder {
+ public:
+  Builder(Ctx& c, char* ws, size_t ws_bytes, char* arena, size_t arena_bytes, bool dry);
+
+  Ctx& C;
+  bool dry;
+  std::string err;
+  int err_code = 0;
+
+  // memory
+  CT new_ct(int level, double scale);
+  void free_ct(CT& x);
+  double* scratch(size_t n_doubles);
+  size_t scratch_mark() const { return scratch_cur_; }
+  void scratch_release(size_t mark) { scratch_cur_ = mark; }
+  size_t need_bytes() const { return need_max_; }
+  size_t blob_bytes() const { return blob_.size(); }
+  bool arena_overflow() const { return blob_.size() > arena_bytes_; }
+
+  double* c0(const CT& x) const { return x.d; }
+  double* c1(const CT& x) const { return x.d + (size_t)C.n_q * C.N; }
+
+  // descriptor / constant uploads (returns device addresses inside the arena)
+  template <class J>
+  const J* put(const std::vector<J>& v) {
+    return (const J*)put_bytes(v.data(), v.size() * sizeof(J));
+  }
+  const void* put_bytes(const void* p, size_t n);
+  const double* put_residues(int64_t K, int n_limbs);  // K mod q_t, t < n_limbs (chain)
+
+  // raw launches
+  void ntt(const std::vector<NttJob>& v, bool inverse);
+  void ew(const std::vector<EwJob>& v);
+  void modup(const std::vector<ModUpJob>& v);
+  void moddown(const std::vector<ModDownJob>& v);
+  void inner(const std::vector<InnerJob>& v);
+  void spread(const std::vector<SpreadJob>& v);
+  void automorph(const std::vector<AutoJob>& v);
+  void lift(const std::vector<LiftJob>& v);
+  void sample(const std::vector<SampleJob>& v);
+  void intspread(const std::vector<IntSpreadJob>& v);
+  void encode(const std::vector<EncodeJob>& v);
+  void decode(const int64_t* m, double* z, int nslots, double inv_scale);
+
+  // CKKS operations over batches of items
+  struct KsItem {
+    const double* d;      // NTT domain, chain limbs 0..level
+    int level;
+    const double* key;
+    const double* base0;  // may be null
+    const double* base1;
+    double* out0;
+    double* out1;
+  };
+  void key_switch(const std::vector<KsItem>& items);
+  void rescale(std::vector<CT>& in_out);                    // in place
+  std::vector<CT> mul_relin(const std::vector<std::pair<CT, CT>>& ab, bool do_rescale);
+  std::vector<CT> rotate(const std::vector<CT>& in, const std::vector<int64_t>& steps);
+  std::vector<CT> add(const std::vector<std::pair<CT, CT>>& ab, bool sub);
+  std::vector<CT> add_const(const std::vector<CT>& in, const std::vector<double>& v);
+  std::vector<CT> mul_const(const std::vector<CT>& in, const std::vector<double>& v, const std::vector<double>& target);
+  std::vector<CT> mul_plain(const std::vector<CT>& in, const std::vector<std::vector<double>>& z,
+                            const std::vector<double>& target);
+  std::vector<CT> refresh(const std::vector<CT>& in, const std::vector<uint64_t>& seed,
+                          const std::vector<uint64_t>& index);
+  std::vector<CT> eval_odd9(const std::vector<CT>& x, const std::vector<const double*>& coef,
+                            const std::vector<double>& gain, const std::vector<double>& target);
+  // client-side helpers
+  void encrypt_into(const std::vector<const int64_t*>& m_dev, const std::vector<uint64_t>& seed, int purpose,
+                    const std::vector<uint64_t>& sub, const double* sk, const std::vector<CT>& out);
+
+  void fail(int code, const std::string& msg) {
+    if (!err_code) { err_code = code; err = msg; }
+  }
+
+  std::vector<char> blob_;
+  std::vector<Cmd> cmds_;
+  int64_t counters[8] = {0};
+
+ private:
+  char* ws_;
+  size_t ws_bytes_;
+  char* arena_;
+  size_t arena_bytes_;
+  size_t slot_bytes_;
+  std::vector<int> free_slots_;
+  int n_slots_ = 0;
+  size_t scratch_cur_ = 0;
+  size_t need_max_ = 0;
+  void note_need();
+  void push(int kind, int n, int max_y, size_t off, bool inv = false);
+};
+
+// Submit a command list: upload the descriptor blob to 'arena' and launch all
+// commands in order on the context's stream.
+int submit(Ctx& c, Builder& b, char* arena, size_t arena_bytes);
+void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena);
+
+// the encrypted Argmax program over a batch of queries
+struct ArgmaxQuery {
+  CT in;
+  int K, C;
+  double d_min, d_max;
+  uint64_t refresh_seed;
+  CT out;  // caller buffer (d set), level/scale written
+};
+void build_argmax(Builder& b, std::vector<ArgmaxQuery>& q);
+
+int ilog2_ceil(int v);
+
+}  // namespace secpe

@@ -1,0 +1,893 @@
+// Host runtime: RNS-CKKS context, command lists and batched homomorphic
+// operations (arXiv 2502.00847, Sec. 2.2).
+#include "runtime.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+extern "C" void secpe_cos_table_dd(int log_n, double* hi, double* lo);
+
+namespace secpe {
+
+// ---------------------------------------------------------------------------
+// primes: chain = 1 mod 2N nearest 2^q_bits, alternately below and above;
+// special = the largest = 1 mod 2N below 2^p_bits not already used
+// ---------------------------------------------------------------------------
+static bool miller_rabin(uint64_t n) {
+  if (n < 2) return false;
+  const uint64_t small[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+  for (uint64_t p : small)
+    if (n % p == 0) return n == p;
+  uint64_t d = n - 1;
+  int s = 0;
+  while (!(d & 1)) { d >>= 1; ++s; }
+  for (uint64_t a : small) {
+    uint64_t x = hpow(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (int r = 1; r < s && comp; ++r) {
+      x = hmul(x, x, n);
+      if (x == n - 1) comp = false;
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+
+static std::vector<uint64_t> choose_primes(int log_n, int n_q, int q_bits, int n_p, int p_bits) {
+  const uint64_t step = 2ull << log_n;
+  std::vector<uint64_t> out;
+  uint64_t below = (1ull << q_bits) + 1 - step, above = (1ull << q_bits) + 1;
+  for (int k = 0; k < n_q; ++k) {
+    if (k % 2 == 0) {
+      while (!miller_rabin(below)) below -= step;
+      out.push_back(below);
+      below -= step;
+    } else {
+      while (!miller_rabin(above)) above += step;
+      out.push_back(above);
+      above += step;
+    }
+  }
+  uint64_t c = (1ull << p_bits) + 1 - step;
+  for (int k = 0; k < n_p; ++k) {
+    while (!miller_rabin(c) || std::find(out.begin(), out.end(), c) != out.end()) c -= step;
+    out.push_back(c);
+    c -= step;
+  }
+  return out;
+}
+
+static uint64_t psi_root(uint64_t q, uint64_t n) {
+  // psi = x^((q-1)/2N) for a quadratic non-residue x has order exactly 2N
+  for (uint64_t x = 3;; ++x)
+    if (hpow(x, (q - 1) / 2, q) == q - 1) return hpow(x, (q - 1) / (2 * n), q);
+}
+
+static uint32_t bitrev(uint32_t x, int bits) {
+  uint32_t r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1u) << (bits - 1 - i);
+  return r;
+}
+
+uint64_t Ctx::galois(int64_t step) const {
+  const int64_t slots = N / 2;
+  const int64_t r = ((step % slots) + slots) % slots;
+  return hpow(5, (uint64_t)r, 2 * (uint64_t)N);
+}
+
+int ilog2_ceil(int v) {
+  int r = 0;
+  while ((1 << r) < v) ++r;
+  return r;
+}
+
+static const int SECPE_EDEVICE_INTERNAL = -5;
+#define HIPCHK(x)                                         \
+  do {                                                    \
+    if ((x) != hipSuccess) return SECPE_EDEVICE_INTERNAL; \
+  } while (0)
+
+int build_context(Ctx& c, int log_n, int n_q, int q_bits, int n_p, int p_bits, int log_scale, int dg, int df,
+                  int min_level, int device, hipStream_t stream) {
+  c.log_n = log_n;
+  c.N = 1 << log_n;
+  c.n_q = n_q;
+  c.n_p = n_p;
+  c.alpha = n_p;
+  c.dnum = (n_q + n_p - 1) / n_p;
+  c.n_mod = n_q + n_p;
+  c.q_bits = q_bits;
+  c.p_bits = p_bits;
+  c.log_scale = log_scale;
+  c.dg = dg;
+  c.df = df;
+  c.min_level = min_level;
+  c.device = device;
+  c.stream = stream;
+  c.mod = choose_primes(log_n, n_q, q_bits, n_p, p_bits);
+  const int N = c.N, nm = c.n_mod;
+  // ----- host tables -----
+  std::vector<double> h;
+  auto alloc = [&](size_t n) {
+    size_t off = h.size();
+    h.resize(off + ((n + 31) & ~size_t(31)), 0.0);
+    return off;
+  };
+  size_t o_mod = alloc(nm), o_minv = alloc(nm), o_ninv = alloc(nm), o_ninvq = alloc(nm);
+  size_t o_psi = alloc((size_t)nm * N), o_psiq = alloc((size_t)nm * N);
+  size_t o_ipsi = alloc((size_t)nm * N), o_ipsiq = alloc((size_t)nm * N);
+  size_t o_cos_hi = alloc(2 * (size_t)N), o_cos_lo = alloc(2 * (size_t)N);
+  for (int t = 0; t < nm; ++t) {
+    const uint64_t q = c.mod[t];
+    const double qd = (double)q;
+    h[o_mod + t] = qd;
+    h[o_minv + t] = 1.0 / qd;
+    const uint64_t ni = hinv((uint64_t)N, q);
+    h[o_ninv + t] = (double)ni;
+    h[o_ninvq + t] = (double)ni / qd;
+    const uint64_t psi = psi_root(q, (uint64_t)N), ipsi = hinv(psi, q);
+    std::vector<uint64_t> pw(N), ipw(N);
+    uint64_t a = 1, b = 1;
+    for (int i = 0; i < N; ++i) { pw[i] = a; ipw[i] = b; a = hmul(a, psi, q); b = hmul(b, ipsi, q); }
+    for (int k = 0; k < N; ++k) {
+      const uint32_t r = bitrev((uint32_t)k, log_n);
+      h[o_psi + (size_t)t * N + k] = (double)pw[r];
+      h[o_psiq + (size_t)t * N + k] = (double)pw[r] / qd;
+      h[o_ipsi + (size_t)t * N + k] = (double)ipw[r];
+      h[o_ipsiq + (size_t)t * N + k] = (double)ipw[r] / qd;
+    }
+  }
+  secpe_cos_table_dd(log_n, &h[o_cos_hi], &h[o_cos_lo]);
+  // digit tables for every (lo, size) a level can produce
+  struct DOff { size_t cinv, chat; };
+  std::map<std::pair<int, int>, DOff> doff;
+  for (int lo = 0; lo < n_q; lo += c.alpha) {
+    for (int sz = 1; sz <= c.alpha && lo + sz <= n_q; ++sz) {
+      DOff d;
+      d.cinv = alloc(sz);
+      d.chat = alloc((size_t)nm * sz);
+      for (int i = 0; i < sz; ++i) {
+        const uint64_t qi = c.mod[lo + i];
+        uint64_t dh = 1;
+        for (int i2 = 0; i2 < sz; ++i2)
+          if (i2 != i) dh = hmul(dh, c.mod[lo + i2] % qi, qi);
+        h[d.cinv + i] = (double)hinv(dh, qi);
+        for (int t = 0; t < nm; ++t) {
+          const uint64_t qt = c.mod[t];
+          uint64_t v = 1;
+          for (int i2 = 0; i2 < sz; ++i2)
+            if (i2 != i) v = hmul(v, c.mod[lo + i2] % qt, qt);
+          h[d.chat + (size_t)t * sz + i] = (double)v;
+        }
+      }
+      doff[{lo, sz}] = d;
+    }
+  }
+  // ModDown / P tables
+  size_t o_mdc = alloc(c.alpha), o_mdh = alloc((size_t)n_q * c.alpha), o_mdp = alloc(n_q), o_pmq = alloc(n_q);
+  for (int k = 0; k < c.alpha; ++k) {
+    const uint64_t pk = c.mod[n_q + k];
+    uint64_t ph = 1;
+    for (int k2 = 0; k2 < c.alpha; ++k2)
+      if (k2 != k) ph = hmul(ph, c.mod[n_q + k2] % pk, pk);
+    h[o_mdc + k] = (double)hinv(ph, pk);
+  }
+  for (int t = 0; t < n_q; ++t) {
+    const uint64_t q = c.mod[t];
+    uint64_t P = 1;
+    for (int k = 0; k < c.alpha; ++k) P = hmul(P, c.mod[n_q + k] % q, q);
+    h[o_mdp + t] = (double)hinv(P, q);
+    h[o_pmq + t] = (double)P;
+    for (int k = 0; k < c.alpha; ++k) {
+      uint64_t ph = 1;
+      for (int k2 = 0; k2 < c.alpha; ++k2)
+        if (k2 != k) ph = hmul(ph, c.mod[n_q + k2] % q, q);
+      h[o_mdh + (size_t)t * c.alpha + k] = (double)ph;
+    }
+  }
+  // rescale: q_l^-1 mod q_i
+  size_t o_rs = alloc((size_t)n_q * n_q);
+  for (int l = 1; l < n_q; ++l)
+    for (int i = 0; i < l; ++i) h[o_rs + (size_t)l * n_q + i] = (double)hinv(c.mod[l] % c.mod[i], c.mod[i]);
+  // CRT from limbs 0, 1
+  size_t o_crt = alloc(2 * (size_t)n_q);
+  for (int t = 0; t < n_q; ++t) {
+    const uint64_t q = c.mod[t];
+    h[o_crt + 2 * t] = (double)(c.mod[0] % q);
+    h[o_crt + 2 * t + 1] = (double)hmul(c.mod[0] % q, c.mod[1] % q, q);
+  }
+  c.q0inv_q1 = (double)hinv(c.mod[0] % c.mod[1], c.mod[1]);
+  // ----- upload -----
+  if (hipSetDevice(device) != hipSuccess) return SECPE_EDEVICE_INTERNAL;
+  c.tab_bytes = h.size() * sizeof(double);
+  HIPCHK(hipMalloc(&c.d_tab, c.tab_bytes));
+  HIPCHK(hipMemcpy(c.d_tab, h.data(), c.tab_bytes, hipMemcpyHostToDevice));
+  const double* B = c.d_tab;
+  c.T.mod = B + o_mod;
+  c.T.minv = B + o_minv;
+  c.T.psi = B + o_psi;
+  c.T.psiq = B + o_psiq;
+  c.T.ipsi = B + o_ipsi;
+  c.T.ipsiq = B + o_ipsiq;
+  c.T.ninv = B + o_ninv;
+  c.T.ninvq = B + o_ninvq;
+  c.T.cos_hi = B + o_cos_hi;
+  c.T.cos_lo = B + o_cos_lo;
+  c.T.n_q = n_q;
+  c.T.n_p = n_p;
+  c.T.log_n = log_n;
+  for (auto& kv : doff) c.digits[kv.first] = DigitTable{B + kv.second.cinv, B + kv.second.chat};
+  c.md_cinv = B + o_mdc;
+  c.md_chat = B + o_mdh;
+  c.md_pinv = B + o_mdp;
+  c.p_mod_q = B + o_pmq;
+  c.rs_tab = B + o_rs;
+  c.crt_tab = B + o_crt;
+  HIPCHK(hipEventCreateWithFlags(&c.staging_done, hipEventDisableTiming));
+  return 0;
+}
+
+void destroy_context(Ctx& c) {
+  if (c.stream) (void)hipStreamSynchronize(c.stream);
+  else (void)hipDeviceSynchronize();
+  for (auto& g : c.graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    if (g.arena) (void)hipFree(g.arena);
+  }
+  c.graphs.clear();
+  if (c.d_tab) (void)hipFree(c.d_tab);
+  if (c.arena) (void)hipFree(c.arena);
+  if (c.staging) (void)hipHostFree(c.staging);
+  if (c.client) (void)hipFree(c.client);
+  if (c.staging_done) (void)hipEventDestroy(c.staging_done);
+  c.d_tab = nullptr;
+  c.arena = nullptr;
+  c.staging = nullptr;
+  c.client = nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// builder: memory
+// ---------------------------------------------------------------------------
+Builder::Builder(Ctx& c, char* ws, size_t ws_bytes, char* arena, size_t arena_bytes, bool dry_)
+    : C(c), dry(dry_), ws_(ws), ws_bytes_(ws_bytes & ~size_t(255)), arena_(arena), arena_bytes_(arena_bytes) {
+  slot_bytes_ = c.ct_bytes();
+}
+
+void Builder::note_need() {
+  const size_t need = (size_t)n_slots_ * slot_bytes_ + scratch_cur_;
+  need_max_ = std::max(need_max_, need);
+  if (!dry && need > ws_bytes_) fail(-2, "workspace too small");
+}
+
+CT Builder::new_ct(int level, double scale) {
+  CT x;
+  if (!free_slots_.empty()) {
+    x.slot = free_slots_.back();
+    free_slots_.pop_back();
+  } else {
+    x.slot = n_slots_++;
+    note_need();
+  }
+  x.d = (double*)(ws_ + (size_t)x.slot * slot_bytes_);
+  x.level = level;
+  x.scale = scale;
+  return x;
+}
+
+void Builder::free_ct(CT& x) {
+  if (x.slot >= 0) free_slots_.push_back(x.slot);
+  x.slot = -1;
+  x.d = nullptr;
+}
+
+double* Builder::scratch(size_t n) {
+  n = (n + 31) & ~size_t(31);
+  scratch_cur_ += n * sizeof(double);
+  note_need();
+  // scratch grows downward from the end of the workspace
+  return (double*)(ws_ + ws_bytes_ - scratch_cur_);
+}
+
+const void* Builder::put_bytes(const void* p, size_t n) {
+  size_t off = (blob_.size() + 15) & ~size_t(15);
+  blob_.resize(off + n);
+  if (n) memcpy(blob_.data() + off, p, n);
+  return arena_ + off;
+}
+
+const double* Builder::put_residues(int64_t K, int n_limbs) {
+  std::vector<double> r(n_limbs);
+  for (int t = 0; t < n_limbs; ++t) r[t] = (double)hmod_i64(K, C.mod[t]);
+  return put(r);
+}
+
+void Builder::push(int kind, int n, int max_y, size_t off, bool inv) {
+  Cmd c{};
+  c.kind = kind;
+  c.n = n;
+  c.max_y = max_y;
+  c.off = off;
+  c.inv = inv;
+  cmds_.push_back(c);
+  counters[7]++;
+}
+
+#define PUSH_JOBS(KIND, V, MAXY, INV)                                           \
+  do {                                                                          \
+    if ((V).empty()) return;                                                    \
+    const char* p = (const char*)put(V);                                        \
+    push(KIND, (int)(V).size(), MAXY, (size_t)(p - arena_), INV);               \
+  } while (0)
+
+void Builder::ntt(const std::vector<NttJob>& v, bool inverse) {
+  int my = 0;
+  for (auto& j : v) my = std::max(my, j.n_limbs);
+  PUSH_JOBS(C_NTT, v, my, inverse);
+}
+void Builder::ew(const std::vector<EwJob>& v) {
+  int my = 0;
+  for (auto& j : v) my = std::max(my, j.n_limbs);
+  PUSH_JOBS(C_EW, v, my, false);
+}
+void Builder::modup(const std::vector<ModUpJob>& v) { PUSH_JOBS(C_MODUP, v, 1, false); }
+void Builder::moddown(const std::vector<ModDownJob>& v) { PUSH_JOBS(C_MODDOWN, v, 1, false); }
+void Builder::inner(const std::vector<InnerJob>& v) {
+  int my = 0;
+  for (auto& j : v) my = std::max(my, j.n_ext);
+  PUSH_JOBS(C_INNER, v, my, false);
+}
+void Builder::spread(const std::vector<SpreadJob>& v) {
+  int my = 0;
+  for (auto& j : v) my = std::max(my, j.n_chain);
+  PUSH_JOBS(C_SPREAD, v, my, false);
+}
+void Builder::automorph(const std::vector<AutoJob>& v) {
+  int my = 0;
+  for (auto& j : v) my = std::max(my, j.n_limbs);
+  PUSH_JOBS(C_AUTO, v, my, false);
+}
+void Builder::lift(const std::vector<LiftJob>& v) { PUSH_JOBS(C_LIFT, v, 1, false); }
+void Builder::sample(const std::vector<SampleJob>& v) {
+  int my = 0;
+  for (auto& j : v) my = std::max(my, j.n_limbs);
+  PUSH_JOBS(C_SAMPLE, v, my, false);
+}
+void Builder::intspread(const std::vector<IntSpreadJob>& v) {
+  int my = 0;
+  for (auto& j : v) my = std::max(my, j.n_limbs);
+  PUSH_JOBS(C_INTSPREAD, v, my, false);
+}
+void Builder::encode(const std::vector<EncodeJob>& v) { PUSH_JOBS(C_ENCODE, v, 1, false); }
+void Builder::decode(const int64_t* m, double* z, int nslots, double inv_scale) {
+  Cmd c{};
+  c.kind = C_DECODE;
+  c.n = nslots;
+  c.m = m;
+  c.z = z;
+  c.inv_scale = inv_scale;
+  cmds_.push_back(c);
+  counters[7]++;
+}
+
+// ---------------------------------------------------------------------------
+// submission
+// ---------------------------------------------------------------------------
+void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
+  const DevTables& T = c.T;
+  hipStream_t s = c.stream;
+  for (const Cmd& k : cmds) {
+    const void* j = arena + k.off;
+    switch (k.kind) {
+      case C_NTT: launch_ntt(T, k.inv, (const NttJob*)j, k.n, k.max_y, s); break;
+      case C_EW: launch_ew(T, (const EwJob*)j, k.n, k.max_y, s); break;
+      case C_MODUP: launch_modup(T, (const ModUpJob*)j, k.n, s); break;
+      case C_MODDOWN: launch_moddown_conv(T, (const ModDownJob*)j, k.n, s); break;
+      case C_INNER: launch_inner(T, (const InnerJob*)j, k.n, k.max_y, s); break;
+      case C_SPREAD: launch_spread_centred(T, (const SpreadJob*)j, k.n, k.max_y, s); break;
+      case C_AUTO: launch_automorph(T, (const AutoJob*)j, k.n, k.max_y, s); break;
+      case C_LIFT: launch_lift(T, (const LiftJob*)j, k.n, c.crt_tab, c.q0inv_q1, s); break;
+      case C_SAMPLE: launch_sample(T, (const SampleJob*)j, k.n, k.max_y, s); break;
+      case C_INTSPREAD: launch_int_spread(T, (const IntSpreadJob*)j, k.n, k.max_y, s); break;
+      case C_ENCODE: launch_encode(T, (const EncodeJob*)j, k.n, s); break;
+      case C_DECODE: launch_decode(T, k.m, k.z, k.n, k.inv_scale, s); break;
+      default: break;
+    }
+  }
+}
+
+int submit(Ctx& c, Builder& b, char* arena, size_t arena_bytes) {
+  const size_t n = b.blob_.size();
+  if (n > arena_bytes) return -2;
+  if (n) {
+    if (c.staging_bytes < n) {
+      if (c.staging) {
+        (void)hipEventSynchronize(c.staging_done);
+        (void)hipHostFree(c.staging);
+      }
+      c.staging_bytes = std::max(n, c.staging_bytes * 2);
+      if (hipHostMalloc((void**)&c.staging, c.staging_bytes, hipHostMallocDefault) != hipSuccess) {
+        c.staging = nullptr;
+        c.staging_bytes = 0;
+        return -5;
+      }
+    } else {
+      (void)hipEventSynchronize(c.staging_done);
+    }
+    memcpy(c.staging, b.blob_.data(), n);
+    if (hipMemcpyAsync(arena, c.staging, n, hipMemcpyHostToDevice, c.stream) != hipSuccess) return -5;
+    (void)hipEventRecord(c.staging_done, c.stream);
+  }
+  launch_cmds(c, b.cmds_, arena);
+  if (hipGetLastError() != hipSuccess) return -5;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// key switching (hybrid, digits of alpha chain primes)
+//   ModUp each digit -> inner product with the key over Q_l u P -> ModDown
+// ---------------------------------------------------------------------------
+void Builder::key_switch(const std::vector<KsItem>& items) {
+  const int N = C.N, alpha = C.alpha, n_p = C.n_p;
+  struct Tmp {
+    double* dcoef;
+    double* ext;
+    double* acc;
+    double* conv;
+    int n_ext, nd;
+  };
+  std::vector<Tmp> tmp(items.size());
+  std::vector<NttJob> j_inv, j_fwd_ext, j_inv_acc, j_fwd_conv;
+  std::vector<ModUpJob> j_up;
+  std::vector<InnerJob> j_in;
+  std::vector<ModDownJob> j_down;
+  std::vector<EwJob> j_comb;
+  for (size_t i = 0; i < items.size(); ++i) {
+    const KsItem& it = items[i];
+    const int l = it.level, nc = l + 1, n_ext = nc + n_p;
+    const int nd = (nc + alpha - 1) / alpha;
+    Tmp& t = tmp[i];
+    t.n_ext = n_ext;
+    t.nd = nd;
+    t.dcoef = scratch((size_t)nc * N);
+    t.ext = scratch((size_t)nd * n_ext * N);
+    t.acc = scratch((size_t)2 * n_ext * N);
+    t.conv = scratch((size_t)2 * nc * N);
+    j_inv.push_back(NttJob{it.d, t.dcoef, nc, nc, 0, 0});
+    for (int j = 0; j < nd; ++j) {
+      const int lo = j * alpha, hi = std::min((j + 1) * alpha, nc);
+      const DigitTable& dt = C.digits.at({lo, hi - lo});
+      double* e = t.ext + (size_t)j * n_ext * N;
+      j_up.push_back(ModUpJob{t.dcoef, e, dt.cinv, dt.chat, lo, hi, nc, n_ext});
+      j_fwd_ext.push_back(NttJob{e, e, n_ext, nc, lo, hi});
+    }
+    j_in.push_back(InnerJob{it.d, t.ext, it.key, t.acc, nc, n_ext, nd, alpha});
+    for (int w = 0; w < 2; ++w) {
+      double* sp = t.acc + ((size_t)w * n_ext + nc) * N;
+      j_inv_acc.push_back(NttJob{sp, sp, n_p, 0, 0, 0});
+      double* cv = t.conv + (size_t)w * nc * N;
+      j_down.push_back(ModDownJob{sp, cv, C.md_cinv, C.md_chat, nc, 0});
+      j_fwd_conv.push_back(NttJob{cv, cv, nc, nc, 0, 0});
+    }
+    EwJob e{};
+    e.o0 = it.out0;
+    e.o1 = it.out1;
+    e.a0 = it.base0;
+    e.a1 = it.base1;
+    e.b0 = t.acc;
+    e.b1 = t.acc + (size_t)n_ext * N;
+    e.c0 = t.conv;
+    e.c1 = t.conv + (size_t)nc * N;
+    e.k = C.md_pinv;
+    e.n_limbs = nc;
+    e.n_chain = nc;
+    e.op = EW_MODDOWN;
+    j_comb.push_back(e);
+  }
+  ntt(j_inv, true);
+  modup(j_up);
+  ntt(j_fwd_ext, false);
+  inner(j_in);
+  ntt(j_inv_acc, true);
+  moddown(j_down);
+  ntt(j_fwd_conv, false);
+  ew(j_comb);
+  counters[3] += (int64_t)items.size();
+}
+
+// rescale by the top prime q_l: c_i <- (c_i - [c_l]centred) * q_l^-1  (in place)
+void Builder::rescale(std::vector<CT>& xs) {
+  const int N = C.N;
+  std::vector<NttJob> j_top, j_fwd;
+  std::vector<SpreadJob> j_sp;
+  std::vector<EwJob> j_ew;
+  for (CT& x : xs) {
+    const int l = x.level;
+    if (l < 1) { fail(-3, "rescale below level 0"); return; }
+    double* top = scratch(2 * (size_t)N);
+    double* spr = scratch(2 * (size_t)l * N);
+    for (int w = 0; w < 2; ++w) {
+      const double* src = w ? c1(x) : c0(x);
+      double* tw = top + (size_t)w * N;
+      // transform only limb l: limbs [0, l) skipped; dst shifted so limb l lands in tw
+      j_top.push_back(NttJob{src, tw - (size_t)l * N, l + 1, l + 1, 0, l});
+      double* sw = spr + (size_t)w * l * N;
+      j_sp.push_back(SpreadJob{tw, sw, l, l});
+      j_fwd.push_back(NttJob{sw, sw, l, l, 0, 0});
+    }
+    EwJob e{};
+    e.o0 = c0(x);
+    e.o1 = c1(x);
+    e.a0 = c0(x);
+    e.a1 = c1(x);
+    e.b0 = spr;
+    e.b1 = spr + (size_t)l * N;
+    e.k = C.rs_tab + (size_t)l * C.n_q;
+    e.n_limbs = l;
+    e.n_chain = l;
+    e.op = EW_RESCALE;
+    j_ew.push_back(e);
+    x.scale = x.scale / (double)C.mod[l];
+    x.level = l - 1;
+  }
+  ntt(j_top, true);
+  spread(j_sp);
+  ntt(j_fwd, false);
+  ew(j_ew);
+}
+
+std::vector<CT> Builder::mul_relin(const std::vector<std::pair<CT, CT>>& ab, bool do_rescale) {
+  const int N = C.N;
+  auto it = C.keys.find(0);
+  const double* rk = it != C.keys.end() ? it->second : (dry ? C.T.mod : nullptr);
+  if (!rk) { fail(-4, "no relinearisation key"); return {}; }
+  const size_t mark = scratch_mark();
+  std::vector<CT> out;
+  std::vector<EwJob> j_t;
+  std::vector<KsItem> ks;
+  for (auto& p : ab) {
+    const int l = std::min(p.first.level, p.second.level);
+    CT o = new_ct(l, p.first.scale * p.second.scale);
+    double* d2 = scratch((size_t)(l + 1) * N);
+    EwJob e{};
+    e.o0 = c0(o);
+    e.o1 = c1(o);
+    e.o2 = d2;
+    e.a0 = c0(p.first);
+    e.a1 = c1(p.first);
+    e.b0 = c0(p.second);
+    e.b1 = c1(p.second);
+    e.n_limbs = l + 1;
+    e.n_chain = l + 1;
+    e.op = EW_TENSOR;
+    j_t.push_back(e);
+    ks.push_back(KsItem{d2, l, rk, c0(o), c1(o), c0(o), c1(o)});
+    out.push_back(o);
+  }
+  ew(j_t);
+  key_switch(ks);
+  counters[2] += (int64_t)ab.size();
+  if (do_rescale) rescale(out);
+  if (err_code) return {};
+  scratch_release(mark);
+  return out;
+}
+
+std::vector<CT> Builder::rotate(const std::vector<CT>& in, const std::vector<int64_t>& steps) {
+  const int N = C.N;
+  const size_t mark = scratch_mark();
+  std::vector<CT> out;
+  std::vector<AutoJob> j_a;
+  std::vector<KsItem> ks;
+  for (size_t i = 0; i < in.size(); ++i) {
+    const CT& x = in[i];
+    const uint64_t g = C.galois(steps[i]);
+    CT o = new_ct(x.level, x.scale);
+    const int nl = x.level + 1;
+    if (g == 1) {
+      EwJob e{};
+      e.o0 = c0(o); e.o1 = c1(o); e.a0 = c0(x); e.a1 = c1(x);
+      e.n_limbs = nl; e.n_chain = nl; e.op = EW_COPY;
+      ew({e});
+      out.push_back(o);
+      continue;
+    }
+    auto it = C.keys.find(g);
+    const double* gk = it != C.keys.end() ? it->second : (dry ? C.T.mod : nullptr);
+    if (!gk) { fail(-4, "no Galois key for rotation " + std::to_string(steps[i])); return {}; }
+    double* d = scratch((size_t)nl * N);
+    j_a.push_back(AutoJob{c0(x), c0(o), nl, nl, (uint32_t)g, 0});
+    j_a.push_back(AutoJob{c1(x), d, nl, nl, (uint32_t)g, 0});
+    ks.push_back(KsItem{d, x.level, gk, c0(o), nullptr, c0(o), c1(o)});
+    out.push_back(o);
+  }
+  automorph(j_a);
+  key_switch(ks);
+  counters[1] += (int64_t)ks.size();
+  scratch_release(mark);
+  return out;
+}
+
+std::vector<CT> Builder::add(const std::vector<std::pair<CT, CT>>& ab, bool sub) {
+  std::vector<CT> out;
+  std::vector<EwJob> j;
+  for (auto& p : ab) {
+    const double sa = p.first.scale, sb = p.second.scale;
+    if (fabs(sa - sb) > 1e-9 * fabs(sa)) { fail(-1, "scale mismatch in addition"); return {}; }
+    const int l = std::min(p.first.level, p.second.level);
+    CT o = new_ct(l, sa);
+    EwJob e{};
+    e.o0 = c0(o); e.o1 = c1(o);
+    e.a0 = c0(p.first); e.a1 = c1(p.first);
+    e.b0 = c0(p.second); e.b1 = c1(p.second);
+    e.n_limbs = l + 1; e.n_chain = l + 1;
+    e.op = sub ? EW_SUB : EW_ADD;
+    j.push_back(e);
+    out.push_back(o);
+  }
+  ew(j);
+  return out;
+}
+
+std::vector<CT> Builder::add_const(const std::vector<CT>& in, const std::vector<double>& v) {
+  std::vector<CT> out;
+  std::vector<EwJob> j;
+  for (size_t i = 0; i < in.size(); ++i) {
+    const CT& x = in[i];
+    double kf = v[i] * x.scale;
+    const int64_t K = llround(kf);
+    CT o = new_ct(x.level, x.scale);
+    EwJob e{};
+    e.o0 = c0(o); e.o1 = c1(o); e.a0 = c0(x); e.a1 = c1(x);
+    e.k = put_residues(K, x.level + 1);
+    e.n_limbs = x.level + 1; e.n_chain = x.level + 1;
+    e.op = EW_ADD_CONST;
+    j.push_back(e);
+    out.push_back(o);
+  }
+  ew(j);
+  return out;
+}
+
+// constant product with exact target scale: K = llround(v T q_l / s), rescale, scale := T
+std::vector<CT> Builder::mul_const(const std::vector<CT>& in, const std::vector<double>& v,
+                                   const std::vector<double>& target) {
+  std::vector<CT> out;
+  std::vector<EwJob> j;
+  for (size_t i = 0; i < in.size(); ++i) {
+    const CT& x = in[i];
+    const double ql = (double)C.mod[x.level];
+    double kf = v[i] * target[i];
+    kf = kf * ql;
+    kf = kf / x.scale;
+    const int64_t K = llround(kf);
+    CT o = new_ct(x.level, x.scale);
+    EwJob e{};
+    e.o0 = c0(o); e.o1 = c1(o); e.a0 = c0(x); e.a1 = c1(x);
+    e.k = put_residues(K, x.level + 1);
+    e.n_limbs = x.level + 1; e.n_chain = x.level + 1;
+    e.op = EW_CMUL;
+    j.push_back(e);
+    out.push_back(o);
+  }
+  ew(j);
+  const size_t mark = scratch_mark();
+  rescale(out);
+  scratch_release(mark);
+  if (err_code) return {};
+  for (size_t i = 0; i < out.size(); ++i) out[i].scale = target[i];
+  return out;
+}
+
+// product with the encoded real vector z (slots 0..len-1), exact target scale
+std::vector<CT> Builder::mul_plain(const std::vector<CT>& in, const std::vector<std::vector<double>>& z,
+                                   const std::vector<double>& target) {
+  const int N = C.N;
+  const size_t mark = scratch_mark();
+  std::vector<CT> out;
+  std::vector<EncodeJob> j_enc;
+  std::vector<IntSpreadJob> j_sp;
+  std::vector<NttJob> j_ntt;
+  std::vector<EwJob> j_mul;
+  for (size_t i = 0; i < in.size(); ++i) {
+    const CT& x = in[i];
+    const int nl = x.level + 1;
+    const double ql = (double)C.mod[x.level];
+    double ps = target[i] * ql;
+    ps = ps / x.scale;
+    int64_t* m = (int64_t*)scratch(N);
+    double* pt = scratch((size_t)nl * N);
+    EncodeJob ej{};
+    ej.z = put(z[i]);
+    ej.m = m;
+    ej.scale_hi = ps * 2.0 / (double)N;
+    ej.scale_lo = 0.0;
+    ej.nnz = (int)z[i].size();
+    j_enc.push_back(ej);
+    j_sp.push_back(IntSpreadJob{m, pt, nl, nl});
+    j_ntt.push_back(NttJob{pt, pt, nl, nl, 0, 0});
+    CT o = new_ct(x.level, x.scale);
+    EwJob e{};
+    e.o0 = c0(o); e.o1 = c1(o); e.a0 = c0(x); e.a1 = c1(x); e.b0 = pt;
+    e.n_limbs = nl; e.n_chain = nl;
+    e.op = EW_PMUL;
+    j_mul.push_back(e);
+    out.push_back(o);
+  }
+  encode(j_enc);
+  intspread(j_sp);
+  ntt(j_ntt, false);
+  ew(j_mul);
+  rescale(out);
+  if (err_code) return {};
+  for (size_t i = 0; i < out.size(); ++i) out[i].scale = target[i];
+  scratch_release(mark);
+  return out;
+}
+
+// encryption of integer plaintexts (device int64 coefficient arrays) at the top level
+void Builder::encrypt_into(const std::vector<const int64_t*>& m_dev, const std::vector<uint64_t>& seed, int purpose,
+                           const std::vector<uint64_t>& sub, const double* sk, const std::vector<CT>& out) {
+  const int N = C.N, L = C.n_q;
+  const size_t mark = scratch_mark();
+  std::vector<IntSpreadJob> j_sp;
+  std::vector<SampleJob> j_s;
+  std::vector<NttJob> j_ntt;
+  std::vector<EwJob> j_enc;
+  for (size_t i = 0; i < out.size(); ++i) {
+    double* mm = scratch((size_t)L * N);
+    double* e = scratch((size_t)L * N);
+    const uint64_t tag = ((uint64_t)purpose << 56) | ((sub[i] & 0xFFFull) << 12);
+    j_sp.push_back(IntSpreadJob{m_dev[i], mm, L, L});
+    j_s.push_back(SampleJob{c1(out[i]), seed[i], tag, L, L, SAMPLE_UNIFORM, 0});
+    j_s.push_back(SampleJob{e, seed[i], tag, L, L, SAMPLE_CBD, 0});
+    j_ntt.push_back(NttJob{mm, mm, L, L, 0, 0});
+    j_ntt.push_back(NttJob{e, e, L, L, 0, 0});
+    j_ntt.push_back(NttJob{c1(out[i]), c1(out[i]), L, L, 0, 0});
+    EwJob w{};
+    w.o0 = c0(out[i]); w.a0 = mm; w.a1 = e; w.b0 = c1(out[i]); w.b1 = sk;
+    w.n_limbs = L; w.n_chain = L; w.op = EW_ENC;
+    j_enc.push_back(w);
+  }
+  intspread(j_sp);
+  sample(j_s);
+  ntt(j_ntt, false);
+  ew(j_enc);
+  scratch_release(mark);
+}
+
+// refresh stand-in: decrypt with the key owner's secret, lift m exactly from
+// limbs 0 and 1, re-encrypt at the top level; scale kept
+std::vector<CT> Builder::refresh(const std::vector<CT>& in, const std::vector<uint64_t>& seed,
+                                 const std::vector<uint64_t>& index) {
+  const int N = C.N, L = C.n_q;
+  const double* rsk = C.refresh_sk ? C.refresh_sk : (dry ? C.T.mod : nullptr);
+  if (!rsk) { fail(-3, "modulus chain exhausted and no refresh key registered"); return {}; }
+  const size_t mark = scratch_mark();
+  std::vector<CT> out;
+  std::vector<EwJob> j_dec;
+  std::vector<NttJob> j_inv, j_fwd, j_fwd2;
+  std::vector<LiftJob> j_lift;
+  std::vector<SampleJob> j_s;
+  std::vector<EwJob> j_enc;
+  for (size_t i = 0; i < in.size(); ++i) {
+    const CT& x = in[i];
+    if (x.level < 1) { fail(-3, "refresh needs two limbs"); return {}; }
+    double* r = scratch(2 * (size_t)N);
+    double* mm = scratch((size_t)L * N);
+    double* e = scratch((size_t)L * N);
+    EwJob d{};
+    d.o0 = r; d.a0 = c0(x); d.a1 = c1(x); d.b0 = rsk;
+    d.n_limbs = 2; d.n_chain = 2; d.op = EW_DEC2;
+    j_dec.push_back(d);
+    j_inv.push_back(NttJob{r, r, 2, 2, 0, 0});
+    j_lift.push_back(LiftJob{r, r + N, mm, nullptr, L, 0});
+    CT o = new_ct(L - 1, x.scale);
+    const uint64_t tag = (5ull << 56) | ((index[i] & 0xFFFull) << 12);
+    j_s.push_back(SampleJob{c1(o), seed[i], tag, L, L, SAMPLE_UNIFORM, 0});
+    j_s.push_back(SampleJob{e, seed[i], tag, L, L, SAMPLE_CBD, 0});
+    j_fwd.push_back(NttJob{mm, mm, L, L, 0, 0});
+    j_fwd.push_back(NttJob{e, e, L, L, 0, 0});
+    j_fwd.push_back(NttJob{c1(o), c1(o), L, L, 0, 0});
+    EwJob w{};
+    w.o0 = c0(o); w.a0 = mm; w.a1 = e; w.b0 = c1(o); w.b1 = rsk;
+    w.n_limbs = L; w.n_chain = L; w.op = EW_ENC;
+    j_enc.push_back(w);
+    out.push_back(o);
+  }
+  ew(j_dec);
+  ntt(j_inv, true);
+  lift(j_lift);
+  sample(j_s);
+  ntt(j_fwd, false);
+  ew(j_enc);
+  counters[4] += (int64_t)in.size();
+  scratch_release(mark);
+  return out;
+}
+
+// odd degree-9 polynomial p(x) = (c1 x + c3 x^3) + x^4 (c5 x + c7 x^3) + x^8 (c9 x)
+// (baby-step giant-step, depth 4, six ciphertext products); output scale = target
+std::vector<CT> Builder::eval_odd9(const std::vector<CT>& xs, const std::vector<const double*>& coef,
+                                   const std::vector<double>& gain, const std::vector<double>& target) {
+  const size_t n = xs.size();
+  for (const CT& x : xs)
+    if (x.level - 4 < C.min_level) { fail(-3, "eval_odd9: not enough levels"); return {}; }
+  auto lower = [](CT x, int l) { x.level = l; x.slot = -1; return x; };
+  std::vector<std::pair<CT, CT>> p;
+  for (size_t i = 0; i < n; ++i) p.push_back({xs[i], xs[i]});
+  std::vector<CT> x2 = mul_relin(p, true);
+  if (err_code) return {};
+  p.clear();
+  for (size_t i = 0; i < n; ++i) p.push_back({x2[i], lower(xs[i], xs[i].level - 1)});
+  for (size_t i = 0; i < n; ++i) p.push_back({x2[i], x2[i]});
+  std::vector<CT> x34 = mul_relin(p, true);
+  if (err_code) return {};
+  std::vector<CT> x3(x34.begin(), x34.begin() + n), x4(x34.begin() + n, x34.end());
+  p.clear();
+  for (size_t i = 0; i < n; ++i) p.push_back({x4[i], x4[i]});
+  std::vector<CT> x8 = mul_relin(p, true);
+  if (err_code) return {};
+  for (auto& v : x2) free_ct(v);
+  // constants: a3 = c3 x^3, a1 = c1 x, b3 = c7 x^3, b1 = c5 x, cc = c9 x, all rescaled to level l-3
+  std::vector<CT> cin;
+  std::vector<double> cv, ct;
+  std::vector<double> sb(n), sc(n);
+  for (size_t i = 0; i < n; ++i) {
+    const int l = xs[i].level;
+    const double q3 = (double)C.mod[l - 3];
+    const double g = gain[i];
+    const double* c = coef[i];
+    sb[i] = target[i] * q3;
+    sb[i] = sb[i] / x4[i].scale;
+    sc[i] = target[i] * q3;
+    sc[i] = sc[i] / x8[i].scale;
+    const CT xl2 = lower(xs[i], l - 2);
+    cin.push_back(x3[i]); cv.push_back(c[1] * g); ct.push_back(target[i]);
+    cin.push_back(xl2); cv.push_back(c[0] * g); ct.push_back(target[i]);
+    cin.push_back(x3[i]); cv.push_back(c[3] * g); ct.push_back(sb[i]);
+    cin.push_back(xl2); cv.push_back(c[2] * g); ct.push_back(sb[i]);
+    cin.push_back(xl2); cv.push_back(c[4] * g); ct.push_back(sc[i]);
+  }
+  std::vector<CT> k = mul_const(cin, cv, ct);
+  if (err_code) return {};
+  for (auto& v : x3) free_ct(v);
+  p.clear();
+  for (size_t i = 0; i < n; ++i) p.push_back({k[5 * i + 1], k[5 * i + 0]});  // A = a1 + a3
+  for (size_t i = 0; i < n; ++i) p.push_back({k[5 * i + 3], k[5 * i + 2]});  // B = b1 + b3
+  std::vector<CT> AB = add(p, false);
+  if (err_code) return {};
+  p.clear();
+  for (size_t i = 0; i < n; ++i) p.push_back({lower(x4[i], xs[i].level - 3), AB[n + i]});
+  for (size_t i = 0; i < n; ++i) p.push_back({x8[i], k[5 * i + 4]});
+  std::vector<CT> prods = mul_relin(p, true);
+  if (err_code) return {};
+  for (size_t i = 0; i < n; ++i) {
+    for (int j = 0; j < 5; ++j) free_ct(k[5 * i + j]);
+    free_ct(x4[i]);
+    free_ct(x8[i]);
+    free_ct(AB[n + i]);
+  }
+  p.clear();
+  for (size_t i = 0; i < n; ++i) p.push_back({lower(AB[i], xs[i].level - 4), prods[i]});
+  std::vector<CT> s1 = add(p, false);
+  if (err_code) return {};
+  p.clear();
+  for (size_t i = 0; i < n; ++i) p.push_back({s1[i], prods[n + i]});
+  std::vector<CT> res = add(p, false);
+  if (err_code) return {};
+  for (size_t i = 0; i < n; ++i) {
+    free_ct(AB[i]);
+    free_ct(prods[i]);
+    free_ct(prods[n + i]);
+    free_ct(s1[i]);
+  }
+  counters[5] += (int64_t)n;
+  return res;
+}
+
+}  // namespace secpe

@@ -1,0 +1,392 @@
+"""Python binding of libsecpe.so (include/secpe.h): argument marshalling only.
+
+Every step runs in the library's HIP kernels; PyTorch provides device memory
+(float64 CUDA tensors holding exact residues) and the stream.  There is no CPU
+fallback: a missing library or GPU raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from .build import lib_path
+
+_lib = None
+
+SECPE_GRAPH = 1
+
+
+class SecpeError(RuntimeError):
+    pass
+
+
+class _Params(C.Structure):
+    _fields_ = [(n, C.c_int) for n in ("log_n", "n_q", "q_bits", "n_p", "p_bits", "log_scale", "dg", "df", "min_level")]
+
+
+class _Ct(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("level", C.c_int), ("scale", C.c_double)]
+
+
+def load():
+    """Load the built library (build it first with build.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # torch's bundled HIP runtime (soname libamdhip64.so.7) must be the one the
+    # library binds to, so load torch before the library
+    import torch  # noqa: F401
+    path = lib_path()
+    if not os.path.exists(path):
+        raise SecpeError(f"{path} is missing: run paper_2502_00847_amd.build.build() first")
+    lib = C.CDLL(path)
+    vp, i32, i64, u64, dbl, sz = C.c_void_p, C.c_int, C.c_int64, C.c_uint64, C.c_double, C.c_size_t
+    P = C.POINTER
+    ct = P(_Ct)
+    sig = {
+        "secpe_last_error": (C.c_char_p, []),
+        "secpe_ctx_create": (i32, [P(_Params), i32, vp, P(vp)]),
+        "secpe_ctx_destroy": (None, [vp]),
+        "secpe_primes": (i32, [vp, P(u64), i32]),
+        "secpe_slots": (i32, [vp]),
+        "secpe_ct_bytes": (sz, [vp]),
+        "secpe_sk_bytes": (sz, [vp]),
+        "secpe_key_bytes": (sz, [vp]),
+        "secpe_galois_elt": (u64, [vp, i64]),
+        "secpe_argmax_steps": (i32, [vp, i32, i32, P(i64), i32]),
+        "secpe_keygen": (i32, [vp, u64, P(i64), i32, vp, vp]),
+        "secpe_set_refresh_key": (i32, [vp, vp]),
+        "secpe_encrypt": (i32, [vp, vp, P(dbl), i32, i32, u64, ct]),
+        "secpe_encrypt_coeffs": (i32, [vp, vp, P(i64), dbl, u64, ct]),
+        "secpe_decrypt": (i32, [vp, vp, ct, i32, P(dbl), P(i32)]),
+        "secpe_decrypt_coeffs": (i32, [vp, vp, ct, P(i64)]),
+        "secpe_workspace_bytes": (sz, [vp, i32, P(i32), P(i32)]),
+        "secpe_eval_argmax": (i32, [vp, ct, i32, i32, dbl, dbl, u64, vp, sz, ct]),
+        "secpe_eval_argmax_batch": (i32, [vp, i32, ct, P(i32), P(i32), P(dbl), P(dbl), P(u64), vp, sz, ct, i32]),
+        "secpe_counters": (i32, [vp, P(i64)]),
+        "secpe_ct_export": (i32, [vp, ct, P(u64)]),
+        "secpe_ct_import": (i32, [vp, P(u64), i32, dbl, ct]),
+        "secpe_key_export": (i32, [vp, vp, i32, i32, i32, i32, P(u64)]),
+        "secpe_sk_export": (i32, [vp, vp, P(i64)]),
+        "secpe_sync": (i32, [vp]),
+        "secpe_op_workspace_bytes": (sz, [vp]),
+        "secpe_op_add": (i32, [vp, ct, ct, ct]),
+        "secpe_op_sub": (i32, [vp, ct, ct, ct]),
+        "secpe_op_add_const": (i32, [vp, ct, dbl, ct]),
+        "secpe_op_mul_const": (i32, [vp, ct, dbl, dbl, vp, sz, ct]),
+        "secpe_op_mul_plain": (i32, [vp, ct, P(dbl), i32, dbl, vp, sz, ct]),
+        "secpe_op_rescale": (i32, [vp, ct, vp, sz, ct]),
+        "secpe_op_mul_relin": (i32, [vp, ct, ct, vp, sz, ct]),
+        "secpe_op_mul_relin_rescale": (i32, [vp, ct, ct, vp, sz, ct]),
+        "secpe_op_rotate": (i32, [vp, ct, i64, vp, sz, ct]),
+        "secpe_op_refresh": (i32, [vp, ct, u64, u64, vp, sz, ct]),
+        "secpe_op_eval_odd9": (i32, [vp, ct, P(dbl), dbl, dbl, vp, sz, ct]),
+        "secpe_op_key_switch": (i32, [vp, i32, P(u64), i32, vp, sz, P(u64), P(u64)]),
+        "secpe_op_ntt": (i32, [vp, i32, P(u64), i32, P(u64), P(u64)]),
+        "secpe_op_ring_mul": (i32, [vp, i32, P(u64), P(u64), P(u64)]),
+        "secpe_op_encode": (i32, [vp, P(dbl), i32, dbl, P(i64)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    """Names the library must export (those declared in include/secpe.h)."""
+    return sorted(
+        ["secpe_last_error", "secpe_ctx_create", "secpe_ctx_destroy", "secpe_primes", "secpe_slots",
+         "secpe_ct_bytes", "secpe_sk_bytes", "secpe_key_bytes", "secpe_galois_elt", "secpe_argmax_steps",
+         "secpe_keygen", "secpe_set_refresh_key", "secpe_encrypt", "secpe_encrypt_coeffs", "secpe_decrypt",
+         "secpe_decrypt_coeffs", "secpe_workspace_bytes", "secpe_eval_argmax", "secpe_eval_argmax_batch",
+         "secpe_counters", "secpe_ct_export", "secpe_ct_import", "secpe_key_export", "secpe_sk_export",
+         "secpe_sync", "secpe_op_workspace_bytes", "secpe_op_add", "secpe_op_sub", "secpe_op_add_const",
+         "secpe_op_mul_const", "secpe_op_mul_plain", "secpe_op_rescale", "secpe_op_mul_relin",
+         "secpe_op_mul_relin_rescale", "secpe_op_rotate", "secpe_op_refresh", "secpe_op_eval_odd9",
+         "secpe_op_key_switch", "secpe_op_ntt", "secpe_op_ring_mul", "secpe_op_encode"])
+
+
+def _p(arr, ctype):
+    return arr.ctypes.data_as(C.POINTER(ctype))
+
+
+class Ciphertext:
+    """Device ciphertext: a float64 CUDA tensor [2, n_q, N] (NTT domain), level, scale."""
+
+    def __init__(self, buf, level, scale):
+        self.buf = buf
+        self.level = int(level)
+        self.scale = float(scale)
+
+    def _c(self):
+        return _Ct(C.c_void_p(self.buf.data_ptr()), self.level, self.scale)
+
+
+class Context:
+    """RNS-CKKS context on one GPU (params: a dict with the secpe_params fields)."""
+
+    def __init__(self, params, device=0):
+        import torch
+        if not torch.cuda.is_available():
+            raise SecpeError("no GPU visible: the HIP library needs an MI355X")
+        self.torch = torch
+        self.lib = load()
+        self.device = device
+        torch.cuda.set_device(device)
+        self.stream = torch.cuda.Stream(device=device)
+        p = _Params(**{k: int(params[k]) for k, _ in _Params._fields_})
+        h = C.c_void_p()
+        self._check(self.lib.secpe_ctx_create(C.byref(p), device, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.params = dict(params)
+        self.N = 1 << params["log_n"]
+        self.n_q, self.n_p = params["n_q"], params["n_p"]
+        self.slots = self.N // 2
+        self.sk = None
+        self.evk = None
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.secpe_ctx_destroy(self.h)
+            self.h = None
+
+    def _check(self, rc):
+        if rc != 0:
+            raise SecpeError(f"secpe error {rc}: {self.lib.secpe_last_error().decode()}")
+
+    def _empty(self, nbytes):
+        with self.torch.cuda.stream(self.stream):
+            return self.torch.empty(max(1, (nbytes + 7) // 8), dtype=self.torch.float64, device=f"cuda:{self.device}")
+
+    # -- sizes and tables ------------------------------------------------------
+    @property
+    def primes(self):
+        out = np.zeros(self.n_q + self.n_p, dtype=np.uint64)
+        self.lib.secpe_primes(self.h, _p(out, C.c_uint64), len(out))
+        return out
+
+    def ct_bytes(self):
+        return self.lib.secpe_ct_bytes(self.h)
+
+    def new_ct(self):
+        return Ciphertext(self._empty(self.ct_bytes()), -1, 0.0)
+
+    def galois_elt(self, step):
+        return int(self.lib.secpe_galois_elt(self.h, int(step)))
+
+    def argmax_steps(self, k_max, c_max):
+        out = np.zeros(256, dtype=np.int64)
+        n = self.lib.secpe_argmax_steps(self.h, k_max, c_max, _p(out, C.c_int64), len(out))
+        return [int(v) for v in out[:n]]
+
+    # -- keys ------------------------------------------------------------------
+    def keygen(self, seed, steps, refresh=True):
+        steps = list(steps)
+        self.sk = self._empty(self.lib.secpe_sk_bytes(self.h))
+        self.evk = self._empty(self.lib.secpe_key_bytes(self.h) * (1 + len(steps)))
+        st = np.ascontiguousarray(steps or [0], dtype=np.int64)
+        self._check(self.lib.secpe_keygen(self.h, int(seed), _p(st, C.c_int64), len(steps),
+                                          C.c_void_p(self.sk.data_ptr()), C.c_void_p(self.evk.data_ptr())))
+        self.steps = steps
+        if refresh:
+            self.set_refresh_key(self.sk)
+        return self.sk, self.evk
+
+    def set_refresh_key(self, sk):
+        self._check(self.lib.secpe_set_refresh_key(self.h, C.c_void_p(sk.data_ptr()) if sk is not None else None))
+
+    # -- client ------------------------------------------------------------------
+    def encrypt(self, logits, seed, sk=None):
+        sk = self.sk if sk is None else sk
+        logits = np.ascontiguousarray(logits, dtype=np.float64)
+        K, Cc = logits.shape
+        ct = self.new_ct()
+        c = ct._c()
+        self._check(self.lib.secpe_encrypt(self.h, C.c_void_p(sk.data_ptr()), _p(logits, C.c_double), K, Cc,
+                                           int(seed), C.byref(c)))
+        ct.level, ct.scale = c.level, c.scale
+        return ct
+
+    def encrypt_coeffs(self, m, scale, seed, sk=None):
+        sk = self.sk if sk is None else sk
+        m = np.ascontiguousarray(m, dtype=np.int64)
+        ct = self.new_ct()
+        c = ct._c()
+        self._check(self.lib.secpe_encrypt_coeffs(self.h, C.c_void_p(sk.data_ptr()), _p(m, C.c_int64), float(scale),
+                                                  int(seed), C.byref(c)))
+        ct.level, ct.scale = c.level, c.scale
+        return ct
+
+    def decrypt(self, ct, nslots, sk=None):
+        sk = self.sk if sk is None else sk
+        z = np.zeros(nslots)
+        idx = C.c_int(0)
+        c = ct._c()
+        self._check(self.lib.secpe_decrypt(self.h, C.c_void_p(sk.data_ptr()), C.byref(c), nslots,
+                                           _p(z, C.c_double), C.byref(idx)))
+        return z, int(idx.value)
+
+    def decrypt_coeffs(self, ct, sk=None):
+        sk = self.sk if sk is None else sk
+        m = np.zeros(self.N, dtype=np.int64)
+        c = ct._c()
+        self._check(self.lib.secpe_decrypt_coeffs(self.h, C.c_void_p(sk.data_ptr()), C.byref(c), _p(m, C.c_int64)))
+        return m
+
+    # -- evaluation ----------------------------------------------------------------
+    def workspace_bytes(self, Ks, Cs):
+        Ks = np.ascontiguousarray(Ks, dtype=np.int32)
+        Cs = np.ascontiguousarray(Cs, dtype=np.int32)
+        n = self.lib.secpe_workspace_bytes(self.h, len(Ks), _p(Ks, C.c_int), _p(Cs, C.c_int))
+        if n == 0:
+            raise SecpeError(self.lib.secpe_last_error().decode())
+        return n
+
+    def workspace(self, Ks, Cs):
+        return self._empty(self.workspace_bytes(Ks, Cs))
+
+    def eval_argmax_batch(self, cts, Ks, Cs, d_min, d_max, seeds, ws=None, outs=None, graph=False):
+        n = len(cts)
+        Ks = np.ascontiguousarray(Ks, dtype=np.int32)
+        Cs = np.ascontiguousarray(Cs, dtype=np.int32)
+        dmin = np.ascontiguousarray(d_min, dtype=np.float64)
+        dmax = np.ascontiguousarray(d_max, dtype=np.float64)
+        sd = np.ascontiguousarray([int(s) for s in seeds], dtype=np.uint64)
+        if ws is None:
+            ws = self.workspace(Ks, Cs)
+        if outs is None:
+            outs = [self.new_ct() for _ in range(n)]
+        cin = (_Ct * n)(*[c._c() for c in cts])
+        cout = (_Ct * n)(*[c._c() for c in outs])
+        self._check(self.lib.secpe_eval_argmax_batch(self.h, n, cin, _p(Ks, C.c_int), _p(Cs, C.c_int),
+                                                     _p(dmin, C.c_double), _p(dmax, C.c_double),
+                                                     _p(sd, C.c_uint64), C.c_void_p(ws.data_ptr()),
+                                                     ws.numel() * 8, cout, SECPE_GRAPH if graph else 0))
+        for o, c in zip(outs, cout):
+            o.level, o.scale = c.level, c.scale
+        return outs
+
+    def eval_argmax(self, ct, K, Cc, d_min, d_max, refresh_seed, ws=None):
+        return self.eval_argmax_batch([ct], [K], [Cc], [d_min], [d_max], [refresh_seed], ws=ws)[0]
+
+    def counters(self):
+        out = np.zeros(8, dtype=np.int64)
+        self._check(self.lib.secpe_counters(self.h, _p(out, C.c_int64)))
+        names = ["sign", "rotate", "relin", "key_switch", "refresh", "poly", "max", "launches"]
+        return {k: int(out[i]) for i, k in enumerate(names)}
+
+    def sync(self):
+        self._check(self.lib.secpe_sync(self.h))
+
+    # -- parity interfaces -------------------------------------------------------
+    def export(self, ct):
+        out = np.zeros((2, ct.level + 1, self.N), dtype=np.uint64)
+        c = ct._c()
+        self._check(self.lib.secpe_ct_export(self.h, C.byref(c), _p(out, C.c_uint64)))
+        return out
+
+    def import_(self, arr, scale):
+        arr = np.ascontiguousarray(arr, dtype=np.uint64)
+        ct = self.new_ct()
+        c = ct._c()
+        self._check(self.lib.secpe_ct_import(self.h, _p(arr, C.c_uint64), arr.shape[1] - 1, float(scale), C.byref(c)))
+        ct.level, ct.scale = c.level, c.scale
+        return ct
+
+    def key_limb(self, key, digit, which, prime):
+        out = np.zeros(self.N, dtype=np.uint64)
+        self._check(self.lib.secpe_key_export(self.h, C.c_void_p(self.evk.data_ptr()), key, digit, which, prime,
+                                              _p(out, C.c_uint64)))
+        return out
+
+    def secret(self):
+        out = np.zeros(self.N, dtype=np.int64)
+        self._check(self.lib.secpe_sk_export(self.h, C.c_void_p(self.sk.data_ptr()), _p(out, C.c_int64)))
+        return out
+
+    def _opws(self):
+        if getattr(self, "_ows", None) is None:
+            self._ows = self._empty(self.lib.secpe_op_workspace_bytes(self.h))
+        return self._ows
+
+    def _op(self, fn, *args, ws=True):
+        out = self.new_ct()
+        c = out._c()
+        if ws:
+            w = self._opws()
+            self._check(fn(self.h, *args, C.c_void_p(w.data_ptr()), w.numel() * 8, C.byref(c)))
+        else:
+            self._check(fn(self.h, *args, C.byref(c)))
+        out.level, out.scale = c.level, c.scale
+        return out
+
+    def add(self, a, b):
+        return self._op(self.lib.secpe_op_add, C.byref(a._c()), C.byref(b._c()), ws=False)
+
+    def sub(self, a, b):
+        return self._op(self.lib.secpe_op_sub, C.byref(a._c()), C.byref(b._c()), ws=False)
+
+    def add_const(self, a, v):
+        return self._op(self.lib.secpe_op_add_const, C.byref(a._c()), float(v), ws=False)
+
+    def mul_const(self, a, v, target):
+        return self._op(self.lib.secpe_op_mul_const, C.byref(a._c()), float(v), float(target))
+
+    def mul_plain(self, a, v, target):
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        self._keep = v
+        return self._op(self.lib.secpe_op_mul_plain, C.byref(a._c()), _p(v, C.c_double), len(v), float(target))
+
+    def rescale(self, a):
+        return self._op(self.lib.secpe_op_rescale, C.byref(a._c()))
+
+    def mul_relin(self, a, b):
+        return self._op(self.lib.secpe_op_mul_relin, C.byref(a._c()), C.byref(b._c()))
+
+    def mul_relin_rescale(self, a, b):
+        return self._op(self.lib.secpe_op_mul_relin_rescale, C.byref(a._c()), C.byref(b._c()))
+
+    def rotate(self, a, step):
+        return self._op(self.lib.secpe_op_rotate, C.byref(a._c()), int(step))
+
+    def refresh(self, a, seed, index):
+        return self._op(self.lib.secpe_op_refresh, C.byref(a._c()), int(seed), int(index))
+
+    def eval_odd9(self, a, coef, gain, target):
+        coef = np.ascontiguousarray(coef, dtype=np.float64)
+        self._keep = coef
+        return self._op(self.lib.secpe_op_eval_odd9, C.byref(a._c()), _p(coef, C.c_double), float(gain), float(target))
+
+    def key_switch(self, key, d):
+        d = np.ascontiguousarray(d, dtype=np.uint64)
+        level = d.shape[0] - 1
+        u0 = np.zeros_like(d)
+        u1 = np.zeros_like(d)
+        w = self._opws()
+        self._check(self.lib.secpe_op_key_switch(self.h, key, _p(d, C.c_uint64), level, C.c_void_p(w.data_ptr()),
+                                                 w.numel() * 8, _p(u0, C.c_uint64), _p(u1, C.c_uint64)))
+        return u0, u1
+
+    def ntt(self, prime, limbs):
+        limbs = np.ascontiguousarray(np.atleast_2d(limbs), dtype=np.uint64)
+        fw = np.zeros_like(limbs)
+        rt = np.zeros_like(limbs)
+        self._check(self.lib.secpe_op_ntt(self.h, prime, _p(limbs, C.c_uint64), limbs.shape[0], _p(fw, C.c_uint64),
+                                          _p(rt, C.c_uint64)))
+        return fw, rt
+
+    def ring_mul(self, prime, a, b):
+        a = np.ascontiguousarray(a, dtype=np.uint64)
+        b = np.ascontiguousarray(b, dtype=np.uint64)
+        out = np.zeros(self.N, dtype=np.uint64)
+        self._check(self.lib.secpe_op_ring_mul(self.h, prime, _p(a, C.c_uint64), _p(b, C.c_uint64),
+                                               _p(out, C.c_uint64)))
+        return out
+
+    def encode(self, z, scale):
+        z = np.ascontiguousarray(z, dtype=np.float64)
+        out = np.zeros(self.N, dtype=np.int64)
+        self._check(self.lib.secpe_op_encode(self.h, _p(z, C.c_double), len(z), float(scale), _p(out, C.c_int64)))
+        return out

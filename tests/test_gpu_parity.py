@@ -1,0 +1,318 @@
+"""GPU parity: every step of the HIP path is bit-exact with the CPU oracle on the
+same seeded inputs (coefficient-domain residues compared element by element),
+through the C ABI (include/secpe.h) via its Python binding.
+
+Parameter sets: 'tiny' (N=2^10, single-pass NTT), 'p13' (N=2^13, the toy's
+two-pass NTT split 2^6 x 2^7), 'p14' (2^7 x 2^7).  Full N=2^16 lives in
+test_gpu_full.py.
+"""
+import numpy as np
+import pytest
+
+import workload as W
+from oracle import sim
+from oracle.ckks import Oracle, sign_coeffs
+
+pytestmark = pytest.mark.gpu
+
+SEED = 0xC0FFEE
+EXTRA_STEPS = [3, 5]
+
+
+def _params(name):
+    if name == "p13":
+        return dict(log_n=13, n_q=8, q_bits=36, n_p=2, p_bits=51, log_scale=36, dg=2, df=2, min_level=1)
+    if name == "p14":
+        return dict(log_n=14, n_q=8, q_bits=40, n_p=3, p_bits=51, log_scale=40, dg=2, df=2, min_level=1)
+    return dict(W.PARAMS[name])
+
+
+def _pair(name, k_max=8, c_max=8):
+    from paper_2502_00847_amd.secpe import Context
+    p = _params(name)
+    g = Context(p)
+    o = Oracle.from_params(p)
+    steps = g.argmax_steps(k_max, c_max) + EXTRA_STEPS
+    print(f"[pair] {name} keygen {len(steps)} rotation keys", flush=True)
+    g.keygen(SEED, steps)
+    o.keygen(SEED, steps)
+    return g, o, steps
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return _pair("tiny")
+
+
+@pytest.fixture(scope="module")
+def p13():
+    return _pair("p13", 4, 4)
+
+
+def _rand_ct(o, seed, scale=None, level=None):
+    scale = scale or 2.0 ** o.log_scale
+    z = np.random.default_rng(seed).uniform(-1, 1, o.slots)
+    ct = o.encrypt(o.encode(z, scale), scale, seed)
+    if level is not None:
+        ct = o.lower(ct, level)
+    return ct, z
+
+
+def _same(g, gct, oct_):
+    assert gct.level == oct_.level, (gct.level, oct_.level)
+    assert gct.scale == oct_.scale, (gct.scale, oct_.scale)
+    a = g.export(gct)
+    b = oct_.export()
+    if not np.array_equal(a, b):
+        bad = np.argwhere(a != b)
+        raise AssertionError(f"{len(bad)} residues differ, first at {bad[:5].tolist()}")
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2502_00847_amd import secpe
+    lib = secpe.load()
+    for name in secpe.exported_symbols():
+        assert hasattr(lib, name)
+
+
+@pytest.mark.parametrize("name", ["tiny", "p13", "p14", "full"])
+def test_primes_match_oracle(name):
+    from paper_2502_00847_amd.secpe import Context
+    p = _params(name)
+    g = Context(p)
+    o = Oracle.from_params(p)
+    assert np.array_equal(g.primes, o.primes)
+
+
+@pytest.mark.parametrize("name", ["tiny", "p13", "p14", "full"])
+def test_ntt_roundtrip_and_negacyclic_product(name):
+    """NTT then inverse NTT is the identity; pointwise product in the NTT domain
+    equals the oracle's negacyclic product (itself pinned to schoolbook)."""
+    from paper_2502_00847_amd.secpe import Context
+    p = _params(name)
+    g = Context(p)
+    o = Oracle.from_params(p)
+    rng = np.random.default_rng(1)
+    primes = [int(v) for v in g.primes]
+    for t in [0, 1, len(primes) - 1]:
+        q = primes[t]
+        a = rng.integers(0, q, (3, g.N), dtype=np.uint64)
+        fw, rt = g.ntt(t, a)
+        assert np.array_equal(rt, a)
+        assert fw.max() < q
+        b = rng.integers(0, q, g.N, dtype=np.uint64)
+        assert np.array_equal(g.ring_mul(t, a[0], b), o.ring_mul(t, a[0], b))
+
+
+def test_ntt_edge_values():
+    """All-zero, all-(q-1) and a unit vector survive the round trip; X * X^(N-1) = -1."""
+    from paper_2502_00847_amd.secpe import Context
+    p = _params("p14")
+    g = Context(p)
+    q = int(g.primes[2])
+    for v in (np.zeros(g.N), np.full(g.N, q - 1), np.eye(1, g.N, 7)[0]):
+        v = v.astype(np.uint64)
+        assert np.array_equal(g.ntt(2, v)[1][0], v)
+    x = np.zeros(g.N, dtype=np.uint64)
+    x[1] = 1
+    y = np.zeros(g.N, dtype=np.uint64)
+    y[g.N - 1] = 1
+    r = g.ring_mul(2, x, y)
+    want = np.zeros(g.N, dtype=np.uint64)
+    want[0] = q - 1
+    assert np.array_equal(r, want)
+
+
+@pytest.mark.parametrize("nslots", [1, 7, 64, 512])
+def test_encode_matches_oracle(tiny, nslots):
+    g, o, _ = tiny
+    rng = np.random.default_rng(nslots)
+    for scale in (2.0**40, 2.0**40 * 1.0000123, 12345.678):
+        z = rng.uniform(-6, 6, nslots)
+        assert np.array_equal(g.encode(z, scale), o.encode(z, scale))
+
+
+def test_secret_and_switching_keys_match(tiny):
+    g, o, steps = tiny
+    assert np.array_equal(g.secret(), o.secret())
+    n_mod = o.n_q + o.n_p
+    for key, gal in [(0, 0), (1, o.galois_elt(steps[0])), (len(steps), o.galois_elt(steps[-1]))]:
+        for digit in range(o.dnum):
+            for which in (0, 1):
+                for t in (0, o.n_q - 1, n_mod - 1):
+                    assert np.array_equal(g.key_limb(key, digit, which, t), o.key_limb(gal, digit, which, t))
+
+
+def test_encrypt_bit_exact(tiny):
+    g, o, _ = tiny
+    d = W.query(3, 5)
+    _same(g, g.encrypt(d["logits"], d["encrypt_seed"]), o.encrypt_logits(d["logits"], d["encrypt_seed"]))
+    m = np.random.default_rng(3).integers(-2**45, 2**45, g.N)
+    _same(g, g.encrypt_coeffs(m, 2.0**40, 99), o.encrypt(m, 2.0**40, 99))
+
+
+def test_decrypt_matches(tiny):
+    g, o, _ = tiny
+    ct, z = _rand_ct(o, 4)
+    gct = g.import_(ct.export(), ct.scale)
+    assert np.array_equal(g.decrypt_coeffs(gct), o.decrypt(ct))
+    zz, idx = g.decrypt(gct, 16)
+    assert np.allclose(zz, o.decrypt_decode(ct, 16), rtol=0, atol=1e-12)
+    assert idx == int(np.argmax(zz))
+
+
+def test_import_export_roundtrip(tiny):
+    g, o, _ = tiny
+    ct, _ = _rand_ct(o, 5, level=3)
+    arr = ct.export()
+    assert np.array_equal(g.export(g.import_(arr, ct.scale)), arr)
+
+
+def test_elementwise_ops_bit_exact(tiny):
+    g, o, _ = tiny
+    a, _ = _rand_ct(o, 6)
+    b, _ = _rand_ct(o, 7)
+    bl = o.lower(b, 4)
+    ga, gb, gbl = (g.import_(c.export(), c.scale) for c in (a, b, bl))
+    _same(g, g.add(ga, gb), o.add(a, b))
+    _same(g, g.sub(ga, gbl), o.sub(a, bl))
+    _same(g, g.add_const(ga, -0.3125), o.add_const(a, -0.3125))
+    _same(g, g.mul_const(ga, 3.7, 2.0**40 * 1.001), o.mul_const(a, 3.7, 2.0**40 * 1.001))
+    _same(g, g.mul_const(gbl, -113.25, 2.0**39), o.mul_const(bl, -113.25, 2.0**39))
+    v = np.random.default_rng(8).uniform(-1, 1, 13)
+    _same(g, g.mul_plain(ga, v, 2.0**40), o.mul_plain(a, v, 2.0**40))
+    _same(g, g.rescale(ga), o.rescale(a))
+
+
+def test_products_and_rotations_bit_exact(tiny):
+    g, o, steps = tiny
+    a, _ = _rand_ct(o, 9)
+    b, _ = _rand_ct(o, 10, level=5)
+    ga, gb = g.import_(a.export(), a.scale), g.import_(b.export(), b.scale)
+    _same(g, g.mul_relin(ga, gb), o.mul_relin(a, b))
+    _same(g, g.mul_relin_rescale(ga, ga), o.mul_relin_rescale(a, a))
+    for st in [1, 3, 5, steps[-1], o.slots - 4]:
+        if st not in steps:
+            continue
+        _same(g, g.rotate(ga, st), o.rotate(a, st))
+        _same(g, g.rotate(gb, st), o.rotate(b, st))
+
+
+@pytest.mark.parametrize("level", [7, 4, 1, 0])
+def test_key_switch_bit_exact(tiny, level):
+    """Hybrid key switch at full and partial digit counts (ragged last digit)."""
+    g, o, _ = tiny
+    rng = np.random.default_rng(level)
+    primes = [int(v) for v in o.primes]
+    d = np.stack([rng.integers(0, primes[t], o.n, dtype=np.uint64) for t in range(level + 1)])
+    gu = g.key_switch(0, d)
+    ou = o.key_switch(0, d)
+    assert np.array_equal(gu[0], ou[0]) and np.array_equal(gu[1], ou[1])
+
+
+def test_refresh_bit_exact(tiny):
+    g, o, _ = tiny
+    a, _ = _rand_ct(o, 11, level=2)
+    ga = g.import_(a.export(), a.scale)
+    _same(g, g.refresh(ga, 1234, 3), o.refresh(a, 1234, 3))
+
+
+def test_eval_odd9_bit_exact(tiny):
+    g, o, _ = tiny
+    f, gg = sign_coeffs()
+    a, _ = _rand_ct(o, 12)
+    ga = g.import_(a.export(), a.scale)
+    _same(g, g.eval_odd9(ga, gg, 1.0, 2.0**40), o.eval_odd9(a, gg, 1.0, 2.0**40))
+    _same(g, g.eval_odd9(ga, f, 0.5, 2.0**40 * 0.999), o.eval_odd9(a, f, 0.5, 2.0**40 * 0.999))
+
+
+def _argmax_pair(g, o, K, C, cfg=9, q=0):
+    y = W.logits(cfg, q, K, C)
+    dmin, dmax = W.d_bounds(K)
+    enc, ref = W.query_seeds(cfg, q)
+    ct_o = o.encrypt_logits(y, enc)
+    ct_g = g.encrypt(y, enc)
+    zo = o.eval_argmax(ct_o, K, C, dmin, dmax, ref)
+    zg = g.eval_argmax(ct_g, K, C, dmin, dmax, ref)
+    return y, zo, zg
+
+
+@pytest.mark.parametrize("K,C", [(1, 1), (1, 2), (2, 2), (3, 5), (4, 3), (8, 8)])
+def test_argmax_bit_exact_tiny(tiny, K, C):
+    """The whole Algorithm 1 (prompt sum, Eq. 5, duplication, QuickMax, Eq. 2) matches
+    the oracle bit for bit, with padding (C, K not powers of two) and degenerate shapes."""
+    g, o, _ = tiny
+    y, zo, zg = _argmax_pair(g, o, K, C, q=K * 16 + C)
+    _same(g, zg, zo)
+    z, idx = g.decrypt(zg, C)
+    zs = sim.t1_argmax(y, *W.d_bounds(K), o.slots)
+    assert np.abs(z - zs).max() < 1e-3
+
+
+def test_argmax_toy_config(p13):
+    """Toy-shaped parameters with the two-pass NTT: K=4, C=2 (config 1 shape)."""
+    g, o, _ = p13
+    y, zo, zg = _argmax_pair(g, o, 4, 2, cfg=1, q=0)
+    _same(g, zg, zo)
+    z, idx = g.decrypt(zg, 2)
+    assert idx == sim.t0_argmax(y)[0]
+
+
+def test_batch_equals_one_at_a_time(tiny):
+    """Uneven (K, C) in one batched evaluation give the same bits as alone."""
+    g, o, _ = tiny
+    shapes = [(3, 5), (8, 2), (1, 7), (4, 4), (2, 3)]
+    cts, Ks, Cs, dmin, dmax, seeds = [], [], [], [], [], []
+    for i, (K, C) in enumerate(shapes):
+        y = W.logits(11, i, K, C)
+        enc, ref = W.query_seeds(11, i)
+        cts.append(g.encrypt(y, enc))
+        Ks.append(K)
+        Cs.append(C)
+        lo, hi = W.d_bounds(K)
+        dmin.append(lo)
+        dmax.append(hi)
+        seeds.append(ref)
+    outs = g.eval_argmax_batch(cts, Ks, Cs, dmin, dmax, seeds)
+    for i in range(len(shapes)):
+        alone = g.eval_argmax(cts[i], Ks[i], Cs[i], dmin[i], dmax[i], seeds[i])
+        assert outs[i].level == alone.level and outs[i].scale == alone.scale
+        assert np.array_equal(g.export(outs[i]), g.export(alone))
+
+
+def test_graph_replay_is_deterministic(tiny):
+    g, o, _ = tiny
+    shapes = [(3, 5), (8, 2), (2, 3)]
+    cts, Ks, Cs, dmin, dmax, seeds = [], [], [], [], [], []
+    for i, (K, C) in enumerate(shapes):
+        y = W.logits(12, i, K, C)
+        enc, ref = W.query_seeds(12, i)
+        cts.append(g.encrypt(y, enc))
+        Ks.append(K)
+        Cs.append(C)
+        lo, hi = W.d_bounds(K)
+        dmin.append(lo)
+        dmax.append(hi)
+        seeds.append(ref)
+    ws = g.workspace(Ks, Cs)
+    outs = [g.new_ct() for _ in shapes]
+    eager = [g.export(c) for c in g.eval_argmax_batch(cts, Ks, Cs, dmin, dmax, seeds, ws=ws, outs=outs)]
+    for rep in range(3):
+        got = g.eval_argmax_batch(cts, Ks, Cs, dmin, dmax, seeds, ws=ws, outs=outs, graph=True)
+        g.sync()
+        for e, c in zip(eager, got):
+            assert np.array_equal(g.export(c), e)
+        # eager work between replays
+        g.eval_argmax(cts[0], Ks[0], Cs[0], dmin[0], dmax[0], seeds[0])
+
+
+def test_errors_are_reported(tiny):
+    from paper_2502_00847_amd.secpe import SecpeError
+    g, o, _ = tiny
+    ct = g.encrypt(np.zeros((2, 2)), 1)
+    with pytest.raises(SecpeError):
+        g.rotate(ct, 1000)          # no key for this rotation
+    with pytest.raises(SecpeError):
+        g.eval_argmax(ct, 64, 64, -1, 1, 0)   # K' C' exceeds the slots
+    with pytest.raises(SecpeError):
+        g.eval_argmax(ct, 2, 2, 1.0, 1.0, 0)  # empty normalisation range
