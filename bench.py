@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Encrypted-Argmax throughput on one MI355X (SecPE, arXiv 2502.00847).
+
+One step = one pass of the whole server-side hot path over one batch of
+synthetic queries resident in HBM: for every query, the prompt sum, the
+normalisation (Eq. 5), the duplication and QuickMax of Algorithm 1 with Max
+(Eq. 6) and the final Sign + 1 (Eq. 2), including the refresh stand-in of
+bootstrapping.  Client encryption and decryption sit outside the timed region.
+
+Workload (default): 256 queries, K ~ U{3..16} prompts, C ~ U{2..14} classes,
+logits N(0,1) clipped at +-6, CKKS N = 2^16, 24 chain primes of ~50 bits,
+8 special primes (3 key-switch digits), scale 2^50.
+
+Prints one JSON line (see the "roofline" and "cpu_baseline" objects).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workload as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle as it stands on a bounded sample
+# ---------------------------------------------------------------------------
+def _cpu_worker(args):
+    seed, = args
+    from oracle.ckks import Oracle, sign_coeffs
+    o = Oracle.from_params(W.PARAMS["full"])
+    o.keygen(W.KEYGEN_SEED + seed, [])
+    z = np.random.default_rng(seed).uniform(-1, 1, 64)
+    ct = o.encrypt(o.encode(z, 2.0 ** 50), 2.0 ** 50, seed)
+    f, g = sign_coeffs()
+    t0 = time.perf_counter()
+    o.eval_odd9(ct, g, 1.0, 2.0 ** 50)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(ks_per_query, procs):
+    """Argmax/s of the oracle, from one degree-9 Sign polynomial (6 ciphertext
+    products with relinearisation at the top level) timed in 'procs' parallel
+    processes and scaled by key switches per query."""
+    import multiprocessing as mp
+    from oracle.build import build_oracle
+    build_oracle(force=False)
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(procs) as pool:
+        times = pool.map(_cpu_worker, [(i + 1,) for i in range(procs)])
+    wall = time.perf_counter() - t0
+    t_poly = float(np.mean(times))
+    per_query_s = t_poly * ks_per_query / 6.0
+    return {
+        "value": procs / per_query_s,
+        "unit": "Argmax/s",
+        "cores": procs,
+        "kind": "oracle",
+        "sample": (f"{procs} processes, each one CPU-oracle evaluation of a degree-9 Sign polynomial "
+                   f"(6 ct-ct products + relinearisation, 5 constant products) at the top level of the "
+                   f"N=2^16 chain, mean {t_poly:.2f} s; scaled by {ks_per_query:.1f} key switches per "
+                   f"query / 6; sample wall {wall:.1f} s"),
+    }
+
+
+# ---------------------------------------------------------------------------
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--queries", type=int, default=256)
+    ap.add_argument("--chunk", type=int, default=64, help="queries per batched launch sequence")
+    ap.add_argument("--graph", type=int, default=0, help="replay captured hipGraphs in the timed steps")
+    ap.add_argument("--cpu", type=int, default=1, help="run the CPU-oracle baseline")
+    ap.add_argument("--cpu-procs", type=int, default=0)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: the encrypted Argmax shards by query with no "
+              "communication, so a multi-GPU run is N independent copies of this one.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from oracle import sim
+    from paper_2502_00847_amd.secpe import Context
+
+    params = W.PARAMS["full"]
+    g = Context(params)
+    steps_rot = g.argmax_steps(16, 14)
+    g.keygen(W.KEYGEN_SEED, steps_rot)
+    _log(f"context + {len(steps_rot) + 1} switching keys ready")
+
+    B = args.queries
+    qs = [W.query(3, i) for i in range(B)]
+    cts = [g.encrypt(q["logits"], q["encrypt_seed"]) for q in qs]
+    g.sync()
+    Ks = [q["K"] for q in qs]
+    Cs = [q["C"] for q in qs]
+    chunk = max(1, min(args.chunk, B))
+    groups = [list(range(i, min(B, i + chunk))) for i in range(0, B, chunk)]
+    ws_bytes = max(g.workspace_bytes([Ks[i] for i in grp], [Cs[i] for i in grp]) for grp in groups)
+    ws = g._empty(ws_bytes)
+    outs = [g.new_ct() for _ in range(B)]
+    _log(f"{B} queries encrypted; workspace {ws_bytes / 2**30:.1f} GiB for chunks of {chunk}")
+
+    def run_step(graph, ends=None):
+        t_start = time.perf_counter()
+        for grp in groups:
+            g.eval_argmax_batch([cts[i] for i in grp], [Ks[i] for i in grp], [Cs[i] for i in grp],
+                                [qs[i]["d_min"] for i in grp], [qs[i]["d_max"] for i in grp],
+                                [qs[i]["refresh_seed"] for i in grp], ws=ws, outs=[outs[i] for i in grp],
+                                graph=graph)
+            if ends is not None:
+                g.sync()
+                ends.extend([time.perf_counter() - t_start] * len(grp))
+
+    for w in range(args.warmup):
+        run_step(bool(args.graph))
+        g.sync()
+    _log("warmup done")
+
+    # timed region: K steps; the forward NTT launches are bracketed by HIP events
+    g.profile_begin("ntt_fwd")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        run_step(bool(args.graph))
+    g.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = g.profile_end()
+    elapsed = t1 - t0
+    value = B * args.steps / elapsed
+    _log(f"timed {args.steps} steps: {elapsed:.3f} s -> {value:.1f} Argmax/s")
+
+    # per-query completion latency within a step (queries finish with their chunk)
+    ends = []
+    run_step(False, ends)
+    lat = np.array(ends) * 1e3
+
+    # correctness of the timed outputs: decrypted index vs the plaintext argmax
+    ok = ok_margin = n_margin = 0
+    for q, o in zip(qs, outs):
+        z, idx = g.decrypt(o, q["C"])
+        i0, _, margin = sim.t0_argmax(q["logits"])
+        ok += idx == i0
+        if margin / (q["d_max"] - q["d_min"]) >= 2.0 ** -10:
+            n_margin += 1
+            ok_margin += idx == i0
+
+    # single-query latency on the plain path (config 2: K=8, C=4, margin >= 0.05)
+    d2 = W.query(2, 0)
+    ct2 = g.encrypt(d2["logits"], d2["encrypt_seed"])
+    ws2 = g.workspace([d2["K"]], [d2["C"]])
+    single = []
+    for r in range(6):
+        g.sync()
+        ts = time.perf_counter()
+        z2 = g.eval_argmax(ct2, d2["K"], d2["C"], d2["d_min"], d2["d_max"], d2["refresh_seed"], ws=ws2)
+        g.sync()
+        single.append((time.perf_counter() - ts) * 1e3)
+    single = np.array(single[1:])
+    zz, idx2 = g.decrypt(z2, d2["C"])
+
+    N = 1 << params["log_n"]
+    ntt_bytes = prof["units"] * 2 * N * 8
+    achieved = ntt_bytes / (prof["ms"] * 1e-3) / 1e9 if prof["ms"] > 0 else 0.0
+    roofline = {
+        "bound": "hbm",
+        "kernel": "forward negacyclic NTT (k_ntt column pass + row pass)",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "launches": prof["launches"],
+        "avg_launch_us": round(prof["ms"] * 1e3 / max(1, prof["launches"]), 2),
+        "limb_transforms_per_launch": round(prof["units"] / max(1, prof["launches"]), 1),
+        "algorithmic_bytes_per_limb_transform": 2 * N * 8,
+    }
+    result = {
+        "metric": "encrypted Argmax/s (batched)",
+        "value": round(value, 2),
+        "unit": "Argmax/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "batched_argmax_N2^16_256q", "queries": B, "K": "U{3..16}", "C": "U{2..14}",
+                   "log_n": params["log_n"], "chain_primes": params["n_q"], "special_primes": params["n_p"],
+                   "dnum": (params["n_q"] + params["n_p"] - 1) // params["n_p"], "log_scale": params["log_scale"],
+                   "sign": f"f^{params['df']}(g^{params['dg']})", "chunk": chunk,
+                   "timed_launches": "graph" if args.graph else "eager"},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2), "p99": round(float(np.percentile(lat, 99)), 2),
+                       "what": "completion time of each query from the start of a step"},
+        "single_query_ms": {"p50": round(float(np.percentile(single, 50)), 3),
+                            "p99": round(float(np.percentile(single, 99)), 3),
+                            "what": "config K=8, C=4 alone on the plain path", "index_ok": bool(idx2 == sim.t0_argmax(d2["logits"])[0])},
+        "index_ok": f"{ok}/{B}",
+        "index_ok_at_margin_2^-10": f"{ok_margin}/{n_margin}",
+        "roofline": roofline,
+    }
+    if args.cpu:
+        # key switches per query from the counters of one chunk
+        ks_total = 0
+        for grp in groups:
+            g.eval_argmax_batch([cts[i] for i in grp], [Ks[i] for i in grp], [Cs[i] for i in grp],
+                                [qs[i]["d_min"] for i in grp], [qs[i]["d_max"] for i in grp],
+                                [qs[i]["refresh_seed"] for i in grp], ws=ws, outs=[outs[i] for i in grp])
+            g.sync()
+            ks_total += g.counters()["key_switch"]
+        ks_q = ks_total / B
+        procs = args.cpu_procs or min(16, os.cpu_count() or 1)
+        _log(f"CPU oracle sample on {procs} processes ({ks_q:.1f} key switches per query)")
+        result["cpu_baseline"] = cpu_baseline(ks_q, procs)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

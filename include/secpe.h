@@ -158,6 +158,32 @@ int secpe_sk_export(secpe_ctx* ctx, const void* sk_dev, int64_t* host_out);
 /* Wait for all queued work. */
 int secpe_sync(secpe_ctx* ctx);
 
+/* ---- measurement ---- */
+/* Event profiler: while enabled, every launch of the given kind is bracketed
+   by HIP events on the context's stream (eager launches only; graph replays
+   are not bracketed).  secpe_profile_end synchronises and returns the number
+   of launches, their summed duration in ms and the units they processed:
+   limb transforms for the NTT kinds (one limb transform reads and writes N
+   residues), limbs for the others.  Kinds: */
+enum {
+  SECPE_PROF_NTT_FWD = 0, SECPE_PROF_NTT_INV = 1, SECPE_PROF_EW = 2, SECPE_PROF_MODUP = 3,
+  SECPE_PROF_MODDOWN = 4, SECPE_PROF_INNER = 5, SECPE_PROF_AUTO = 6, SECPE_PROF_SPREAD = 7
+};
+int secpe_profile_begin(secpe_ctx* ctx, int kind);
+int secpe_profile_end(secpe_ctx* ctx, int64_t* launches, double* total_ms, int64_t* units);
+
+/* Batched negacyclic NTT (Sec. 2.2 ring) in place over limbs 0..level of both
+   polynomials of n ciphertexts, one launch per direction: inverse != 0 maps
+   the NTT domain to coefficients.  Asynchronous. */
+int secpe_ntt_cts(secpe_ctx* ctx, const secpe_ct* cts, int n, int inverse);
+
+/* Batched rotations out[i] = RotL(in[i], steps[i]) (Sec. 2.2), each a Galois
+   automorphism and a hybrid key switch with the key registered for its step.
+   ws sized by secpe_rotate_workspace_bytes.  Asynchronous. */
+size_t secpe_rotate_workspace_bytes(secpe_ctx* ctx, int n);
+int secpe_rotate_batch(secpe_ctx* ctx, int n, const secpe_ct* in, const int64_t* steps, void* ws, size_t ws_bytes,
+                       secpe_ct* out);
+
 /* ---- primitive operations (parity checks of single steps); ws sized by
    secpe_op_workspace_bytes; outputs are caller buffers; asynchronous. ---- */
 size_t secpe_op_workspace_bytes(secpe_ctx* ctx);

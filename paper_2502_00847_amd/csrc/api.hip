@@ -881,3 +881,104 @@ extern "C" int secpe_op_encode(secpe_ctx* x, const double* z, int nslots, double
   if (e != hipSuccess) return hip_fail("hipMemcpyAsync", e);
   return sync(c);
 }
+
+// ---------------------------------------------------------------------------
+// measurement
+// ---------------------------------------------------------------------------
+extern "C" int secpe_profile_begin(secpe_ctx* x, int kind) {
+  CHECK_CTX(x);
+  if (kind < 0 || kind >= PROF_NKINDS) return set_err(SECPE_EINVAL, "bad profile kind");
+  int rc = sync(x->c);
+  if (rc) return rc;
+  x->c.prof_kind = kind;
+  x->c.prof_used = 0;
+  x->c.prof_launches = 0;
+  x->c.prof_units = 0;
+  return 0;
+}
+
+extern "C" int secpe_profile_end(secpe_ctx* x, int64_t* launches, double* total_ms, int64_t* units) {
+  CHECK_CTX(x);
+  Ctx& c = x->c;
+  int rc = sync(c);
+  if (rc) return rc;
+  double ms = 0.0;
+  for (size_t i = 0; i + 1 < c.prof_used; i += 2) {
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, c.prof_pool[i], c.prof_pool[i + 1]) == hipSuccess) ms += t;
+  }
+  if (launches) *launches = c.prof_launches;
+  if (total_ms) *total_ms = ms;
+  if (units) *units = c.prof_units;
+  c.prof_kind = -1;
+  c.prof_used = 0;
+  return 0;
+}
+
+extern "C" int secpe_ntt_cts(secpe_ctx* x, const secpe_ct* cts, int n, int inverse) {
+  CHECK_CTX(x);
+  Ctx& c = x->c;
+  if (n < 1 || !cts) return set_err(SECPE_EINVAL, "bad arguments");
+  for (int i = 0; i < n; ++i)
+    if (!cts[i].data || cts[i].level < 0 || cts[i].level >= c.n_q) return set_err(SECPE_EINVAL, "bad ciphertext");
+  return run_build(x, nullptr, 0, [&](Builder& b) {
+    std::vector<NttJob> v;
+    for (int i = 0; i < n; ++i) {
+      double* d = (double*)cts[i].data;
+      const int nl = cts[i].level + 1;
+      v.push_back(NttJob{d, d, nl, nl, 0, 0});
+      v.push_back(NttJob{d + (size_t)c.n_q * c.N, d + (size_t)c.n_q * c.N, nl, nl, 0, 0});
+    }
+    b.ntt(v, inverse != 0);
+  });
+}
+
+extern "C" size_t secpe_rotate_workspace_bytes(secpe_ctx* x, int n) {
+  if (!x || n < 1) return 0;
+  Ctx& c = x->c;
+  std::vector<CT> in(n);
+  std::vector<int64_t> st(n, 1);
+  for (int i = 0; i < n; ++i) {
+    in[i].d = (double*)(uintptr_t)0x200000000000ull;
+    in[i].level = c.n_q - 1;
+    in[i].scale = 1.0;
+  }
+  Builder dry(c, (char*)(uintptr_t)0x100000000000ull, (size_t)1 << 44, (char*)(uintptr_t)0x400000000000ull,
+              (size_t)1 << 40, true);
+  dry.rotate(in, st);
+  return dry.need_bytes() + 4096;
+}
+
+extern "C" int secpe_rotate_batch(secpe_ctx* x, int n, const secpe_ct* in, const int64_t* steps, void* ws,
+                                  size_t ws_bytes, secpe_ct* out) {
+  CHECK_CTX(x);
+  Ctx& c = x->c;
+  if (n < 1 || !in || !steps || !out || !ws) return set_err(SECPE_EINVAL, "bad arguments");
+  for (int i = 0; i < n; ++i)
+    if (!in[i].data || !out[i].data || in[i].level < 0 || in[i].level >= c.n_q)
+      return set_err(SECPE_EINVAL, "bad ciphertext");
+  std::vector<CT> res;
+  int rc = run_build(x, (char*)ws, ws_bytes, [&](Builder& b) {
+    std::vector<CT> v;
+    std::vector<int64_t> st(steps, steps + n);
+    for (int i = 0; i < n; ++i) v.push_back(to_ct(&in[i]));
+    res = b.rotate(v, st);
+    if (b.err_code) return;
+    std::vector<EwJob> cp;
+    for (int i = 0; i < n; ++i) {
+      EwJob e{};
+      e.o0 = (double*)out[i].data;
+      e.o1 = (double*)out[i].data + (size_t)c.n_q * c.N;
+      e.a0 = b.c0(res[i]);
+      e.a1 = b.c1(res[i]);
+      e.n_limbs = res[i].level + 1;
+      e.n_chain = res[i].level + 1;
+      e.op = EW_COPY;
+      cp.push_back(e);
+    }
+    b.ew(cp);
+  });
+  if (rc) return rc;
+  for (int i = 0; i < n; ++i) { out[i].level = res[i].level; out[i].scale = res[i].scale; }
+  return 0;
+}

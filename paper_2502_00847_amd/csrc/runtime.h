@@ -90,6 +90,11 @@ struct Ctx {
   size_t client_bytes = 0;
   // statistics of the last evaluation
   int64_t counters[8] = {0};
+  // event profiler
+  int prof_kind = -1;
+  std::vector<hipEvent_t> prof_pool;
+  size_t prof_used = 0;
+  int64_t prof_launches = 0, prof_units = 0;
   std::vector<GraphEntry> graphs;
 
   size_t limb_bytes() const { return (size_t)N * sizeof(double); }
@@ -117,7 +122,12 @@ struct Cmd {
   const int64_t* m;
   double* z;
   double inv_scale;
+  int64_t units;   // limbs processed by the launch (limb transforms for the NTT)
 };
+
+// kinds the event profiler can bracket (secpe_profile_begin)
+enum ProfKind { PROF_NTT_FWD = 0, PROF_NTT_INV = 1, PROF_EW = 2, PROF_MODUP = 3, PROF_MODDOWN = 4, PROF_INNER = 5,
+                PROF_AUTO = 6, PROF_SPREAD = 7, PROF_NKINDS = 8 };
 
 // ciphertext handle inside a build: device data [2][n_q][N], level, scale, pool slot
 struct CT {
@@ -217,13 +227,14 @@ class Builder {
   size_t scratch_cur_ = 0;
   size_t need_max_ = 0;
   void note_need();
-  void push(int kind, int n, int max_y, size_t off, bool inv = false);
+  void push(int kind, int n, int max_y, size_t off, bool inv = false, int64_t units = 0);
 };
 
 // Submit a command list: upload the descriptor blob to 'arena' and launch all
 // commands in order on the context's stream.
 int submit(Ctx& c, Builder& b, char* arena, size_t arena_bytes);
 void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena);
+int prof_kind_of(const Cmd& k);
 
 // the encrypted Argmax program over a batch of queries
 struct ArgmaxQuery {

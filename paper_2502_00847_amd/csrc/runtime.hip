@@ -244,6 +244,8 @@ void destroy_context(Ctx& c) {
   if (c.staging) (void)hipHostFree(c.staging);
   if (c.client) (void)hipFree(c.client);
   if (c.staging_done) (void)hipEventDestroy(c.staging_done);
+  for (hipEvent_t e : c.prof_pool) (void)hipEventDestroy(e);
+  c.prof_pool.clear();
   c.d_tab = nullptr;
   c.arena = nullptr;
   c.staging = nullptr;
@@ -306,63 +308,81 @@ const double* Builder::put_residues(int64_t K, int n_limbs) {
   return put(r);
 }
 
-void Builder::push(int kind, int n, int max_y, size_t off, bool inv) {
+void Builder::push(int kind, int n, int max_y, size_t off, bool inv, int64_t units) {
   Cmd c{};
   c.kind = kind;
   c.n = n;
   c.max_y = max_y;
   c.off = off;
   c.inv = inv;
+  c.units = units;
   cmds_.push_back(c);
   counters[7]++;
 }
 
-#define PUSH_JOBS(KIND, V, MAXY, INV)                                           \
+#define PUSH_JOBS(KIND, V, MAXY, INV, UNITS)                                    \
   do {                                                                          \
     if ((V).empty()) return;                                                    \
     const char* p = (const char*)put(V);                                        \
-    push(KIND, (int)(V).size(), MAXY, (size_t)(p - arena_), INV);               \
+    push(KIND, (int)(V).size(), MAXY, (size_t)(p - arena_), INV, UNITS);        \
   } while (0)
 
 void Builder::ntt(const std::vector<NttJob>& v, bool inverse) {
   int my = 0;
-  for (auto& j : v) my = std::max(my, j.n_limbs);
-  PUSH_JOBS(C_NTT, v, my, inverse);
+  int64_t units = 0;
+  for (auto& j : v) {
+    my = std::max(my, j.n_limbs);
+    const int lo = std::max(0, std::min(j.skip_lo, j.n_limbs)), hi = std::max(lo, std::min(j.skip_hi, j.n_limbs));
+    units += j.n_limbs - (hi - lo);
+  }
+  PUSH_JOBS(C_NTT, v, my, inverse, units);
 }
 void Builder::ew(const std::vector<EwJob>& v) {
   int my = 0;
-  for (auto& j : v) my = std::max(my, j.n_limbs);
-  PUSH_JOBS(C_EW, v, my, false);
+  int64_t units = 0;
+  for (auto& j : v) { my = std::max(my, j.n_limbs); units += j.n_limbs; }
+  PUSH_JOBS(C_EW, v, my, false, units);
 }
-void Builder::modup(const std::vector<ModUpJob>& v) { PUSH_JOBS(C_MODUP, v, 1, false); }
-void Builder::moddown(const std::vector<ModDownJob>& v) { PUSH_JOBS(C_MODDOWN, v, 1, false); }
+void Builder::modup(const std::vector<ModUpJob>& v) {
+  int64_t units = 0;
+  for (auto& j : v) units += j.n_ext;
+  PUSH_JOBS(C_MODUP, v, 1, false, units);
+}
+void Builder::moddown(const std::vector<ModDownJob>& v) {
+  int64_t units = 0;
+  for (auto& j : v) units += j.n_chain + C.n_p;
+  PUSH_JOBS(C_MODDOWN, v, 1, false, units);
+}
 void Builder::inner(const std::vector<InnerJob>& v) {
   int my = 0;
-  for (auto& j : v) my = std::max(my, j.n_ext);
-  PUSH_JOBS(C_INNER, v, my, false);
+  int64_t units = 0;
+  for (auto& j : v) { my = std::max(my, j.n_ext); units += (int64_t)j.n_ext * (3 * j.n_digits + 2); }
+  PUSH_JOBS(C_INNER, v, my, false, units);
 }
 void Builder::spread(const std::vector<SpreadJob>& v) {
   int my = 0;
-  for (auto& j : v) my = std::max(my, j.n_chain);
-  PUSH_JOBS(C_SPREAD, v, my, false);
+  int64_t units = 0;
+  for (auto& j : v) { my = std::max(my, j.n_chain); units += j.n_chain + 1; }
+  PUSH_JOBS(C_SPREAD, v, my, false, units);
 }
 void Builder::automorph(const std::vector<AutoJob>& v) {
   int my = 0;
-  for (auto& j : v) my = std::max(my, j.n_limbs);
-  PUSH_JOBS(C_AUTO, v, my, false);
+  int64_t units = 0;
+  for (auto& j : v) { my = std::max(my, j.n_limbs); units += 2 * j.n_limbs; }
+  PUSH_JOBS(C_AUTO, v, my, false, units);
 }
-void Builder::lift(const std::vector<LiftJob>& v) { PUSH_JOBS(C_LIFT, v, 1, false); }
+void Builder::lift(const std::vector<LiftJob>& v) { PUSH_JOBS(C_LIFT, v, 1, false, 0); }
 void Builder::sample(const std::vector<SampleJob>& v) {
   int my = 0;
   for (auto& j : v) my = std::max(my, j.n_limbs);
-  PUSH_JOBS(C_SAMPLE, v, my, false);
+  PUSH_JOBS(C_SAMPLE, v, my, false, 0);
 }
 void Builder::intspread(const std::vector<IntSpreadJob>& v) {
   int my = 0;
   for (auto& j : v) my = std::max(my, j.n_limbs);
-  PUSH_JOBS(C_INTSPREAD, v, my, false);
+  PUSH_JOBS(C_INTSPREAD, v, my, false, 0);
 }
-void Builder::encode(const std::vector<EncodeJob>& v) { PUSH_JOBS(C_ENCODE, v, 1, false); }
+void Builder::encode(const std::vector<EncodeJob>& v) { PUSH_JOBS(C_ENCODE, v, 1, false, 0); }
 void Builder::decode(const int64_t* m, double* z, int nslots, double inv_scale) {
   Cmd c{};
   c.kind = C_DECODE;
@@ -377,11 +397,40 @@ void Builder::decode(const int64_t* m, double* z, int nslots, double inv_scale) 
 // ---------------------------------------------------------------------------
 // submission
 // ---------------------------------------------------------------------------
+int prof_kind_of(const Cmd& k) {
+  switch (k.kind) {
+    case C_NTT: return k.inv ? PROF_NTT_INV : PROF_NTT_FWD;
+    case C_EW: return PROF_EW;
+    case C_MODUP: return PROF_MODUP;
+    case C_MODDOWN: return PROF_MODDOWN;
+    case C_INNER: return PROF_INNER;
+    case C_AUTO: return PROF_AUTO;
+    case C_SPREAD: return PROF_SPREAD;
+    default: return -1;
+  }
+}
+
+static hipEvent_t prof_event(Ctx& c) {
+  if (c.prof_used == c.prof_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c.prof_pool.push_back(e);
+  }
+  return c.prof_pool[c.prof_used++];
+}
+
 void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
   const DevTables& T = c.T;
   hipStream_t s = c.stream;
   for (const Cmd& k : cmds) {
     const void* j = arena + k.off;
+    const bool prof = c.prof_kind >= 0 && prof_kind_of(k) == c.prof_kind;
+    if (prof) {
+      hipEvent_t e = prof_event(c);
+      if (e) (void)hipEventRecord(e, s);
+      c.prof_launches++;
+      c.prof_units += k.units;
+    }
     switch (k.kind) {
       case C_NTT: launch_ntt(T, k.inv, (const NttJob*)j, k.n, k.max_y, s); break;
       case C_EW: launch_ew(T, (const EwJob*)j, k.n, k.max_y, s); break;
@@ -396,6 +445,10 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
       case C_ENCODE: launch_encode(T, (const EncodeJob*)j, k.n, s); break;
       case C_DECODE: launch_decode(T, k.m, k.z, k.n, k.inv_scale, s); break;
       default: break;
+    }
+    if (prof) {
+      hipEvent_t e = prof_event(c);
+      if (e) (void)hipEventRecord(e, s);
     }
   }
 }

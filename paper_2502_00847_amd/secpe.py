@@ -85,6 +85,11 @@ def load():
         "secpe_op_ntt": (i32, [vp, i32, P(u64), i32, P(u64), P(u64)]),
         "secpe_op_ring_mul": (i32, [vp, i32, P(u64), P(u64), P(u64)]),
         "secpe_op_encode": (i32, [vp, P(dbl), i32, dbl, P(i64)]),
+        "secpe_profile_begin": (i32, [vp, i32]),
+        "secpe_profile_end": (i32, [vp, P(i64), P(dbl), P(i64)]),
+        "secpe_ntt_cts": (i32, [vp, ct, i32, i32]),
+        "secpe_rotate_workspace_bytes": (sz, [vp, i32]),
+        "secpe_rotate_batch": (i32, [vp, i32, ct, P(i64), vp, sz, ct]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -105,7 +110,8 @@ def exported_symbols():
          "secpe_sync", "secpe_op_workspace_bytes", "secpe_op_add", "secpe_op_sub", "secpe_op_add_const",
          "secpe_op_mul_const", "secpe_op_mul_plain", "secpe_op_rescale", "secpe_op_mul_relin",
          "secpe_op_mul_relin_rescale", "secpe_op_rotate", "secpe_op_refresh", "secpe_op_eval_odd9",
-         "secpe_op_key_switch", "secpe_op_ntt", "secpe_op_ring_mul", "secpe_op_encode"])
+         "secpe_op_key_switch", "secpe_op_ntt", "secpe_op_ring_mul", "secpe_op_encode", "secpe_profile_begin",
+         "secpe_profile_end", "secpe_ntt_cts", "secpe_rotate_workspace_bytes", "secpe_rotate_batch"])
 
 
 def _p(arr, ctype):
@@ -279,6 +285,38 @@ class Context:
 
     def sync(self):
         self._check(self.lib.secpe_sync(self.h))
+
+    # -- measurement -------------------------------------------------------------
+    PROF = dict(ntt_fwd=0, ntt_inv=1, ew=2, modup=3, moddown=4, inner=5, auto=6, spread=7)
+
+    def profile_begin(self, kind):
+        self._check(self.lib.secpe_profile_begin(self.h, self.PROF[kind] if isinstance(kind, str) else int(kind)))
+
+    def profile_end(self):
+        n = C.c_int64(0)
+        ms = C.c_double(0.0)
+        u = C.c_int64(0)
+        self._check(self.lib.secpe_profile_end(self.h, C.byref(n), C.byref(ms), C.byref(u)))
+        return dict(launches=int(n.value), ms=float(ms.value), units=int(u.value))
+
+    def ntt_cts(self, cts, inverse):
+        arr = (_Ct * len(cts))(*[c._c() for c in cts])
+        self._check(self.lib.secpe_ntt_cts(self.h, arr, len(cts), 1 if inverse else 0))
+
+    def rotate_batch(self, cts, steps, ws=None, outs=None):
+        n = len(cts)
+        if ws is None:
+            ws = self._empty(self.lib.secpe_rotate_workspace_bytes(self.h, n))
+        if outs is None:
+            outs = [self.new_ct() for _ in range(n)]
+        st = np.ascontiguousarray(steps, dtype=np.int64)
+        cin = (_Ct * n)(*[c._c() for c in cts])
+        cout = (_Ct * n)(*[c._c() for c in outs])
+        self._check(self.lib.secpe_rotate_batch(self.h, n, cin, _p(st, C.c_int64), C.c_void_p(ws.data_ptr()),
+                                                ws.numel() * 8, cout))
+        for o, c in zip(outs, cout):
+            o.level, o.scale = c.level, c.scale
+        return outs
 
     # -- parity interfaces -------------------------------------------------------
     def export(self, ct):
