@@ -76,6 +76,63 @@ def cpu_baseline(ks_per_query, procs):
 
 
 # ---------------------------------------------------------------------------
+# serving: Poisson arrivals into the continuous-batching server
+# ---------------------------------------------------------------------------
+def serve(g, n, warm, qps=None, frac=0.7, max_active=96):
+    """Config 5 mix (K ~ U{4..32}, C ~ U{2..20}).  With qps=None the rate is
+    'frac' x the saturated throughput of the same mix, measured first by
+    submitting every request at once."""
+    from paper_2502_00847_amd.secpe import Server
+    total = n + warm
+    qs = [W.query(5, i) for i in range(total)]
+    cts = [g.encrypt(q["logits"], q["encrypt_seed"]) for q in qs]
+    g.sync()
+    per = max(g.lib.secpe_server_request_bytes(g.h, q["K"], q["C"]) for q in qs)
+    srv = Server(g, int(per * max_active * 1.05), max_active=max_active)
+    outs = [g.new_ct() for _ in range(total)]
+
+    def run(arrivals):
+        t0 = time.perf_counter()
+        arrive, finish = {}, {}
+        nxt = 0
+        while len(finish) < total:
+            now = time.perf_counter() - t0
+            while nxt < total and arrivals[nxt] <= now:
+                q = qs[nxt]
+                t = srv.submit(cts[nxt], q["K"], q["C"], q["d_min"], q["d_max"], q["refresh_seed"], out=outs[nxt])
+                arrive[t] = arrivals[nxt]
+                nxt += 1
+            if len(arrive) > len(finish):
+                done, _, _ = srv.step()
+                now = time.perf_counter() - t0
+                for t in done:
+                    finish[t] = now
+            elif nxt < total:
+                time.sleep(max(0.0, arrivals[nxt] - now))
+        return arrive, finish
+
+    if qps is None:
+        arrive, finish = run(np.zeros(total))
+        span = max(finish.values())
+        qps = frac * total / span
+        sat = total / span
+    else:
+        sat = None
+    arrivals = W.poisson_arrivals(qps, total)
+    arrive, finish = run(arrivals)
+    order = sorted(arrive, key=lambda t: arrive[t])[warm:]
+    lat = np.array([(finish[t] - arrive[t]) * 1e3 for t in order])
+    span = max(finish[t] for t in order) - min(arrive[t] for t in order)
+    return {
+        "workload": "config5_poisson", "requests": n, "warmup_requests": warm, "qps": round(qps, 2),
+        "saturated_argmax_per_s": round(sat, 2) if sat else None,
+        "throughput_argmax_per_s": round(len(order) / span, 2),
+        "p50_ms": round(float(np.percentile(lat, 50)), 1), "p99_ms": round(float(np.percentile(lat, 99)), 1),
+        "max_active": max_active,
+    }
+
+
+# ---------------------------------------------------------------------------
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +143,7 @@ def main():
     ap.add_argument("--graph", type=int, default=0, help="replay captured hipGraphs in the timed steps")
     ap.add_argument("--cpu", type=int, default=1, help="run the CPU-oracle baseline")
     ap.add_argument("--cpu-procs", type=int, default=0)
+    ap.add_argument("--serve", type=int, default=160, help="requests in the serving run (0 = skip)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -99,7 +157,7 @@ def main():
 
     params = W.PARAMS["full"]
     g = Context(params)
-    steps_rot = g.argmax_steps(16, 14)
+    steps_rot = g.argmax_steps(32, 20)
     g.keygen(W.KEYGEN_SEED, steps_rot)
     _log(f"context + {len(steps_rot) + 1} switching keys ready")
 
@@ -218,6 +276,9 @@ def main():
         "index_ok_at_margin_2^-10": f"{ok_margin}/{n_margin}",
         "roofline": roofline,
     }
+    if args.serve:
+        _log(f"serving run: {args.serve} requests, Poisson arrivals at 0.7x the saturated rate")
+        result["serving"] = serve(g, args.serve, max(8, args.serve // 8))
     if args.cpu:
         # key switches per query from the counters of one chunk
         ks_total = 0

@@ -158,6 +158,28 @@ int secpe_sk_export(secpe_ctx* ctx, const void* sk_dev, int64_t* host_out);
 /* Wait for all queued work. */
 int secpe_sync(secpe_ctx* ctx);
 
+/* ---- serving: continuous batching ---- */
+/* A server keeps evaluation state for many in-flight Argmax requests in one
+   workspace (caller-owned device memory).  Requests are submitted at any time;
+   each call to secpe_server_step admits pending requests while the estimated
+   workspace of the admitted set fits (and at most max_active run), then
+   advances every admitted request by one step of Algorithm 1 (the steps of
+   different requests run in the same kernel launches), waits for the GPU and
+   returns the requests that completed.  A request's result is bit-identical
+   to evaluating it alone.  The input ciphertext must stay valid until its
+   request completes; out_data receives z (secpe_ct_bytes). */
+typedef struct secpe_server secpe_server;
+int secpe_server_create(secpe_ctx* ctx, void* ws_dev, size_t ws_bytes, int max_active, secpe_server** out);
+void secpe_server_destroy(secpe_server* srv);
+/* Estimated workspace one request of shape (K, C) holds while active. */
+size_t secpe_server_request_bytes(secpe_ctx* ctx, int K, int C);
+int secpe_server_submit(secpe_server* srv, const secpe_ct* in, int K, int C, double d_min, double d_max,
+                        uint64_t refresh_seed, void* out_data, uint64_t* ticket);
+/* One round.  Writes up to 'cap' completed tickets with the level and scale of
+   their results; n_active / n_pending report the queue after the round. */
+int secpe_server_step(secpe_server* srv, int cap, int* n_done, uint64_t* tickets, int* levels, double* scales,
+                      int* n_active, int* n_pending);
+
 /* ---- measurement ---- */
 /* Event profiler: while enabled, every launch of the given kind is bracketed
    by HIP events on the context's stream (eager launches only; graph replays

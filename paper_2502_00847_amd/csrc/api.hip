@@ -3,6 +3,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <deque>
+#include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -52,7 +55,7 @@ static int ensure_buffer(Ctx& c, char** buf, size_t* cap, size_t need) {
 
 // Build with 'fn' into the context arena (growing it when needed) and submit.
 template <class F>
-static int run_build(secpe_ctx* x, char* ws, size_t ws_bytes, F fn) {
+static int run_build(secpe_ctx* x, char* ws, size_t ws_bytes, F fn, bool record = true) {
   Ctx& c = x->c;
   for (int attempt = 0; attempt < 3; ++attempt) {
     Builder b(c, ws, ws_bytes, c.arena, c.arena_bytes, false);
@@ -65,7 +68,7 @@ static int run_build(secpe_ctx* x, char* ws, size_t ws_bytes, F fn) {
     }
     int rc = submit(c, b, c.arena, c.arena_bytes);
     if (rc) return set_err(SECPE_EDEVICE, "kernel submission failed");
-    memcpy(c.counters, b.counters, sizeof(c.counters));
+    if (record) memcpy(c.counters, b.counters, sizeof(c.counters));
     return 0;
   }
   return set_err(SECPE_ENOMEM, "descriptor arena did not converge");
@@ -80,7 +83,7 @@ static int run_client(secpe_ctx* x, F fn) {
   if (dry.err_code) return set_err(dry.err_code, dry.err);
   int rc = ensure_buffer(c, &c.client, &c.client_bytes, dry.need_bytes() + 4096);
   if (rc) return rc;
-  return run_build(x, c.client, c.client_bytes, fn);
+  return run_build(x, c.client, c.client_bytes, fn, false);
 }
 
 static int sync(Ctx& c) {
@@ -571,7 +574,7 @@ extern "C" int secpe_ct_import(secpe_ctx* x, const uint64_t* host_in, int level,
   fn(probe);
   hipError_t e = hipMemcpy(stage, tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail("hipMemcpy", e);
-  rc = run_build(x, c.client, c.client_bytes, fn);
+  rc = run_build(x, c.client, c.client_bytes, fn, false);
   if (rc) return rc;
   out->level = level;
   out->scale = scale;
@@ -804,7 +807,7 @@ extern "C" int secpe_op_ntt(secpe_ctx* x, int prime, const uint64_t* in_host, in
   fn(probe);
   hipError_t e = hipMemcpy(buf, tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail("hipMemcpy", e);
-  rc = run_build(x, c.client, c.client_bytes, fn);
+  rc = run_build(x, c.client, c.client_bytes, fn, false);
   if (rc) return rc;
   if (out_fwd) {
     rc = download_limbs(x, fw, (size_t)n * N, out_fwd);
@@ -853,7 +856,7 @@ extern "C" int secpe_op_ring_mul(secpe_ctx* x, int prime, const uint64_t* a_host
   hipError_t e = hipMemcpy(a, tmp.data(), (size_t)N * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(bb, tmp.data() + N, (size_t)N * sizeof(double), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail("hipMemcpy", e);
-  rc = run_build(x, c.client, c.client_bytes, fn2);
+  rc = run_build(x, c.client, c.client_bytes, fn2, false);
   if (rc) return rc;
   return download_limbs(x, a, N, out_host);
 }
@@ -980,5 +983,160 @@ extern "C" int secpe_rotate_batch(secpe_ctx* x, int n, const secpe_ct* in, const
   });
   if (rc) return rc;
   for (int i = 0; i < n; ++i) { out[i].level = res[i].level; out[i].scale = res[i].scale; }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// serving
+// ---------------------------------------------------------------------------
+struct secpe_server {
+  secpe_ctx* x = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int max_active = 0;
+  SlotPool pool;
+  ArgmaxProgram prog;
+  struct Req {
+    ArgmaxQuery q;
+    int slots = 0;
+  };
+  std::deque<std::unique_ptr<Req>> pending;
+  std::map<ArgmaxQuery*, std::unique_ptr<Req>> active;
+  std::map<std::pair<int, int>, std::pair<int, size_t>> need;  // (K, C) -> (peak slots, per-item scratch)
+  int reserved_slots = 0;
+  size_t item_scratch = 0;
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  uint64_t next_ticket = 1;
+  bool broken = false;
+};
+
+static std::pair<int, size_t> request_need(secpe_ctx* x, int K, int C) {
+  Ctx& c = x->c;
+  std::vector<ArgmaxQuery> q(1);
+  q[0].in.d = (double*)(uintptr_t)0x200000000000ull;
+  q[0].in.level = c.n_q - 1;
+  q[0].in.scale = ldexp(1.0, c.log_scale);
+  q[0].out.d = (double*)(uintptr_t)0x300000000000ull;
+  q[0].K = K;
+  q[0].C = C;
+  q[0].d_min = -1.0;
+  q[0].d_max = 1.0;
+  q[0].refresh_seed = 0;
+  Builder dry(c, (char*)(uintptr_t)0x100000000000ull, (size_t)1 << 44, (char*)(uintptr_t)0x400000000000ull,
+              (size_t)1 << 40, true);
+  build_argmax(dry, q);
+  if (dry.err_code) return {-1, 0};
+  return {dry.peak_slots(), dry.peak_scratch()};
+}
+
+extern "C" size_t secpe_server_request_bytes(secpe_ctx* x, int K, int C) {
+  if (!x || K < 1 || C < 1) return 0;
+  auto n = request_need(x, K, C);
+  if (n.first < 0) return 0;
+  return (size_t)n.first * x->c.ct_bytes() + n.second;
+}
+
+extern "C" int secpe_server_create(secpe_ctx* x, void* ws_dev, size_t ws_bytes, int max_active, secpe_server** out) {
+  CHECK_CTX(x);
+  if (!ws_dev || !out || max_active < 1) return set_err(SECPE_EINVAL, "bad server arguments");
+  secpe_server* s = new secpe_server();
+  s->x = x;
+  s->ws = (char*)ws_dev;
+  s->ws_bytes = ws_bytes & ~size_t(255);
+  s->max_active = max_active;
+  s->arena_bytes = (size_t)64 << 20;
+  hipError_t e = hipMalloc((void**)&s->arena, s->arena_bytes);
+  if (e != hipSuccess) { delete s; return hip_fail("hipMalloc", e); }
+  *out = s;
+  return 0;
+}
+
+extern "C" void secpe_server_destroy(secpe_server* s) {
+  if (!s) return;
+  (void)sync(s->x->c);
+  if (s->arena) (void)hipFree(s->arena);
+  delete s;
+}
+
+extern "C" int secpe_server_submit(secpe_server* s, const secpe_ct* in, int K, int C, double d_min, double d_max,
+                                   uint64_t refresh_seed, void* out_data, uint64_t* ticket) {
+  if (!s) return set_err(SECPE_EINVAL, "null server");
+  if (s->broken) return set_err(SECPE_EDEVICE, "server stopped after an error");
+  if (!out_data) return set_err(SECPE_EINVAL, "null output buffer");
+  int rc = check_queries(s->x, 1, in, &K, &C, &d_min, &d_max);
+  if (rc) return rc;
+  auto key = std::make_pair(ilog2_ceil(K), ilog2_ceil(C));
+  auto it = s->need.find(key);
+  if (it == s->need.end()) {
+    auto n = request_need(s->x, K, C);
+    if (n.first < 0) return set_err(SECPE_EINVAL, "request cannot be planned");
+    it = s->need.emplace(key, n).first;
+  }
+  const size_t alone = (size_t)it->second.first * s->x->c.ct_bytes() + it->second.second;
+  if (alone > s->ws_bytes) return set_err(SECPE_ENOMEM, "request does not fit the server workspace");
+  std::unique_ptr<secpe_server::Req> r(new secpe_server::Req());
+  r->q.in = to_ct(in);
+  r->q.K = K;
+  r->q.C = C;
+  r->q.d_min = d_min;
+  r->q.d_max = d_max;
+  r->q.refresh_seed = refresh_seed;
+  r->q.out.d = (double*)out_data;
+  r->q.ticket = s->next_ticket++;
+  r->slots = it->second.first;
+  if (ticket) *ticket = r->q.ticket;
+  s->pending.push_back(std::move(r));
+  return 0;
+}
+
+extern "C" int secpe_server_step(secpe_server* s, int cap, int* n_done, uint64_t* tickets, int* levels, double* scales,
+                                 int* n_active, int* n_pending) {
+  if (!s) return set_err(SECPE_EINVAL, "null server");
+  if (s->broken) return set_err(SECPE_EDEVICE, "server stopped after an error");
+  Ctx& c = s->x->c;
+  if (n_done) *n_done = 0;
+  // admission: the admitted set's slots plus one round's scratch must fit
+  while (!s->pending.empty() && (int)s->active.size() < s->max_active) {
+    secpe_server::Req* r = s->pending.front().get();
+    auto n = s->need[std::make_pair(ilog2_ceil(r->q.K), ilog2_ceil(r->q.C))];
+    const size_t item = std::max(s->item_scratch, n.second);
+    const size_t want = (size_t)(s->reserved_slots + r->slots) * c.ct_bytes() + (s->active.size() + 1) * item;
+    if (want > s->ws_bytes) break;
+    Builder probe(c, s->ws, s->ws_bytes, s->arena, s->arena_bytes, true, &s->pool);
+    if (!s->prog.add(probe, &r->q)) return set_err(SECPE_EINVAL, probe.err);
+    s->item_scratch = item;
+    s->reserved_slots += r->slots;
+    s->active[&r->q] = std::move(s->pending.front());
+    s->pending.pop_front();
+  }
+  if (!s->active.empty()) {
+    Builder b(c, s->ws, s->ws_bytes, s->arena, s->arena_bytes, false, &s->pool);
+    std::vector<ArgmaxQuery*> done = s->prog.round(b, true);
+    if (b.err_code) { s->broken = true; return set_err(b.err_code, b.err); }
+    if (b.arena_overflow()) { s->broken = true; return set_err(SECPE_ENOMEM, "server descriptor arena overflow"); }
+    int rc = submit(c, b, s->arena, s->arena_bytes);
+    if (rc) { s->broken = true; return set_err(SECPE_EDEVICE, "kernel submission failed"); }
+    memcpy(c.counters, b.counters, sizeof(c.counters));
+    rc = sync(c);
+    if (rc) { s->broken = true; return rc; }
+    int k = 0;
+    for (ArgmaxQuery* q : done) {
+      if (k < cap) {
+        if (tickets) tickets[k] = q->ticket;
+        if (levels) levels[k] = q->out.level;
+        if (scales) scales[k] = q->out.scale;
+      }
+      ++k;
+      auto it = s->active.find(q);
+      if (it != s->active.end()) {
+        s->reserved_slots -= it->second->slots;
+        s->active.erase(it);
+      }
+    }
+    if (n_done) *n_done = std::min(k, cap);
+  }
+  if (n_active) *n_active = (int)s->active.size();
+  if (n_pending) *n_pending = (int)s->pending.size();
   return 0;
 }

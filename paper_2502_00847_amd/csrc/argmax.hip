@@ -283,47 +283,90 @@ static void run_step(Builder& b, int kind, std::vector<QState*>& qs) {
   }
 }
 
-void build_argmax(Builder& b, std::vector<ArgmaxQuery>& queries) {
+ArgmaxProgram::ArgmaxProgram() {}
+ArgmaxProgram::~ArgmaxProgram() {
+  for (QState* s : st_) delete s;
+}
+
+size_t ArgmaxProgram::active() const { return st_.size(); }
+
+// the step list of one query: prompt sum, normalisation, duplication, the
+// QuickMax steps (each a Max of Eq. 6 around one Sign) and the final Sign + 1
+bool ArgmaxProgram::add(Builder& b, ArgmaxQuery* q) {
   Ctx& C = b.C;
   const int total = C.dg + C.df;
-  std::vector<QState> st(queries.size());
-  for (size_t i = 0; i < queries.size(); ++i) {
-    QState& s = st[i];
-    ArgmaxQuery& q = queries[i];
-    s.q = &q;
-    s.lk = ilog2_ceil(q.K);
-    s.lc = ilog2_ceil(q.C);
-    s.kp = 1 << s.lk;
-    s.cp = 1 << s.lc;
-    if (q.K < 1 || q.C < 1 || (int64_t)s.kp * s.cp > C.N / 2) { b.fail(-1, "K' * C' exceeds the slot count"); return; }
-    s.y = view(q.in);
-    for (int k = 0; k < s.lk; ++k) s.prog.push_back({S_ROTADD, s.cp << k, false});
-    s.prog.push_back({S_NORMALISE, 0, false});
-    s.prog.push_back({S_DUP, 0, false});
-    for (int k = 0; k < s.lc; ++k) {
-      s.prog.push_back({S_MAXPRE, k, true});
-      for (int j = 0; j < total; ++j) s.prog.push_back({S_POLY, j, true});
-      s.prog.push_back({S_MAXPOST, k, true});
-    }
-    s.prog.push_back({S_FINALPRE, 0, false});
-    for (int j = 0; j < total; ++j) s.prog.push_back({S_POLY, j, false});
-    s.prog.push_back({S_FINALPOST, 0, false});
+  QState* s = new QState();
+  s->q = q;
+  s->lk = ilog2_ceil(q->K);
+  s->lc = ilog2_ceil(q->C);
+  s->kp = 1 << s->lk;
+  s->cp = 1 << s->lc;
+  if (q->K < 1 || q->C < 1 || (int64_t)s->kp * s->cp > C.N / 2) {
+    delete s;
+    b.fail(-1, "K' * C' exceeds the slot count");
+    return false;
   }
-  for (;;) {
-    int count[S_NKINDS] = {0};
-    int active = 0;
-    for (QState& s : st)
-      if (s.pc < s.prog.size()) { count[s.prog[s.pc].kind]++; active++; }
-    if (!active) break;
+  s->y = view(q->in);
+  for (int k = 0; k < s->lk; ++k) s->prog.push_back({S_ROTADD, s->cp << k, false});
+  s->prog.push_back({S_NORMALISE, 0, false});
+  s->prog.push_back({S_DUP, 0, false});
+  for (int k = 0; k < s->lc; ++k) {
+    s->prog.push_back({S_MAXPRE, k, true});
+    for (int j = 0; j < total; ++j) s->prog.push_back({S_POLY, j, true});
+    s->prog.push_back({S_MAXPOST, k, true});
+  }
+  s->prog.push_back({S_FINALPRE, 0, false});
+  for (int j = 0; j < total; ++j) s->prog.push_back({S_POLY, j, false});
+  s->prog.push_back({S_FINALPOST, 0, false});
+  st_.push_back(s);
+  return true;
+}
+
+std::vector<ArgmaxQuery*> ArgmaxProgram::round(Builder& b, bool all_kinds) {
+  std::vector<ArgmaxQuery*> done;
+  int count[S_NKINDS] = {0};
+  for (QState* s : st_) count[s->prog[s->pc].kind]++;
+  if (st_.empty()) return done;
+  std::vector<int> kinds;
+  if (all_kinds) {
+    for (int k = 0; k < S_NKINDS; ++k)
+      if (count[k]) kinds.push_back(k);
+  } else {
     int kind = 0;
     for (int k = 1; k < S_NKINDS; ++k)
       if (count[k] > count[kind]) kind = k;
-    std::vector<QState*> qs;
-    for (QState& s : st)
-      if (s.pc < s.prog.size() && s.prog[s.pc].kind == kind) qs.push_back(&s);
+    kinds.push_back(kind);
+  }
+  // every query advances at most one step per round
+  std::vector<std::vector<QState*>> groups(S_NKINDS);
+  for (QState* s : st_) groups[s->prog[s->pc].kind].push_back(s);
+  for (int kind : kinds) {
+    std::vector<QState*>& qs = groups[kind];
+    if (qs.empty()) continue;
     run_step(b, kind, qs);
-    if (b.err_code) return;
+    if (b.err_code) return done;
     for (QState* s : qs) s->pc++;
+  }
+  std::vector<QState*> keep;
+  for (QState* s : st_) {
+    if (s->pc >= s->prog.size()) {
+      done.push_back(s->q);
+      delete s;
+    } else {
+      keep.push_back(s);
+    }
+  }
+  st_.swap(keep);
+  return done;
+}
+
+void build_argmax(Builder& b, std::vector<ArgmaxQuery>& queries) {
+  ArgmaxProgram prog;
+  for (ArgmaxQuery& q : queries)
+    if (!prog.add(b, &q)) return;
+  while (prog.active()) {
+    prog.round(b, false);
+    if (b.err_code) return;
   }
 }
 

@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void k_ntt(const NttJob* __restrict__ jobs, De
   const int log_n = T.log_n;
   const int N = 1 << log_n;
   constexpr int S = 1 << LOGS;
-  const Mod m{T.mod[pr], T.minv[pr]};
+  const Mod m{KPTR(T.mod)[pr], KPTR(T.minv)[pr]};
   const double* tw = (INV ? T.ipsi : T.psi) + (size_t)pr * N;
   const double* twq = (INV ? T.ipsiq : T.psiq) + (size_t)pr * N;
   const double* src = (second ? J.dst : J.src) + (size_t)l * N;
@@ -189,6 +189,174 @@ __global__ __launch_bounds__(256) void k_ntt(const NttJob* __restrict__ jobs, De
   }
 }
 
+// ---------------------------------------------------------------------------
+// two-pass transform for N = 2^13 .. 2^16.  A workgroup owns G vectors of
+// S = 2^LOGS elements (G*S = 4096).  Round A runs the four stages on the top
+// four bits of the vector index, round B the remaining LOGS-4 stages; each
+// thread keeps its elements in registers for a round, and LDS is only used to
+// move between the two rounds' layouts.  Thread maps are chosen so that every
+// global access of a wavefront is made of 128-byte runs:
+//   column pass (elements v*C + c of columns c0..c0+G-1): lanes run over c;
+//   row pass (contiguous rows of S): lanes run over consecutive elements,
+//   with an LDS transpose for the round whose thread owns a contiguous run.
+// ---------------------------------------------------------------------------
+// One round of R radix-2 stages on x[0 .. 2^R): element e sits at vector
+// position v = (vhigh << (b_lo + R)) | (e << b_lo) | low.  The twiddle of a
+// stage depends only on the bits of v above the butterfly's bit, so a stage
+// needs 2^(R - 1 - eb) distinct twiddles (eb = butterfly bit within e); they
+// are fetched once per stage (wave-uniform in the column pass's first round).
+template <int LOGS, int R, int MODE, bool INV>
+__device__ __forceinline__ void ntt_round(double* x, int vhigh, int b_lo, int row, int k1, kdbl* __restrict__ tw,
+                                          kdbl* __restrict__ twq, const Mod& m) {
+#pragma unroll
+  for (int w = 0; w < R; ++w) {
+    // forward: highest bit first; inverse: lowest bit first
+    const int eb = INV ? w : (R - 1 - w);
+    const int half = 1 << eb;
+    const int u = LOGS - 1 - (b_lo + eb);
+    const int nt = 1 << (R - 1 - eb);
+    // v >> (LOGS - u) = (vhigh << (R - 1 - eb)) | (e0 >> (eb + 1))
+    int base = (MODE == NTT_ROW) ? (1 << (k1 + u)) + (row << u) : (1 << u);
+    base += vhigh << (R - 1 - eb);
+    double wv[1 << (R - 1)], wq[1 << (R - 1)];
+#pragma unroll
+    for (int j = 0; j < (1 << (R - 1)); ++j) {
+      if (j < nt) {
+        wv[j] = tw[base + j];
+        wq[j] = twq[base + j];
+      }
+    }
+#pragma unroll
+    for (int e0 = 0; e0 < (1 << R); ++e0) {
+      if (e0 & half) continue;
+      const int e1 = e0 + half;
+      const int j = e0 >> (eb + 1);
+      if (!INV) {
+        const double U = red(x[e0], m);
+        const double T = mul_w(x[e1], wv[j], wq[j], m.p);
+        x[e0] = U + T;
+        x[e1] = U - T;
+      } else {
+        const double U = red(x[e0], m);
+        const double V = red(x[e1], m);
+        x[e0] = U + V;
+        x[e1] = mul_w(U - V, wv[j], wq[j], m.p);
+      }
+    }
+  }
+}
+
+template <int LOGS, int G, int MODE, bool INV>
+__global__ __launch_bounds__(256) void k_ntt2(const NttJob* __restrict__ jobs, DevTables T, int second) {
+  extern __shared__ double lds[];
+  constexpr int S = 1 << LOGS;
+  constexpr int RB = LOGS - 4;         // bits of round B
+  constexpr int NB = 1 << RB;          // elements per round-B group
+  constexpr int GB = 16 / NB;          // round-B groups per thread
+  const NttJob J = jobs[blockIdx.z];
+  const int l = blockIdx.y;
+  if (l >= J.n_limbs || (l >= J.skip_lo && l < J.skip_hi)) return;
+  const int pr = l < J.n_chain ? l : T.n_q + (l - J.n_chain);
+  const int log_n = T.log_n;
+  const int N = 1 << log_n;
+  const Mod m{KPTR(T.mod)[pr], KPTR(T.minv)[pr]};
+  kdbl* tw = KPTR(INV ? T.ipsi : T.psi) + (size_t)pr * N;
+  kdbl* twq = KPTR(INV ? T.ipsiq : T.psiq) + (size_t)pr * N;
+  cgdbl* src = CGPTR(second ? J.dst : J.src) + (size_t)l * N;
+  gdbl* dst = GPTR(J.dst) + (size_t)l * N;
+  const int t = threadIdx.x;
+  const int k1 = log_n - LOGS;
+  const int C = N >> LOGS;
+  const bool scale = INV && MODE == NTT_COL;
+  const double ni = KPTR(T.ninv)[pr], niq = KPTR(T.ninvq)[pr];
+  // round-A ownership: vector va, low part la; elements v = e*NB + la, e < 16
+  const int va = MODE == NTT_COL ? (t % G) : (t / NB);
+  const int la = MODE == NTT_COL ? (t / G) : (t % NB);
+  const int c0 = MODE == NTT_COL ? blockIdx.x * G : 0;
+  const int row0 = MODE == NTT_ROW ? blockIdx.x * G : 0;
+  double x[16];
+  auto gaddr = [&](int vec, int v) -> size_t {
+    return MODE == NTT_COL ? (size_t)v * C + c0 + vec : (size_t)(row0 + vec) * S + v;
+  };
+  // LDS index: the column pass pads one element per vector (lanes run over
+  // vectors), the row pass one per 16 elements (lanes run within a vector)
+  auto lidx = [&](int vec, int v) -> int { return MODE == NTT_COL ? vec * (S + 1) + v : lpad(vec * S + v); };
+  if (!INV) {
+    // ---- round A straight from global memory
+#pragma unroll
+    for (int e = 0; e < 16; ++e) x[e] = src[gaddr(va, e * NB + la)];
+    ntt_round<LOGS, 4, MODE, false>(x, 0, RB, row0 + va, k1, tw, twq, m);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) lds[lidx(va, e * NB + la)] = x[e];
+    __syncthreads();
+    // ---- round B
+#pragma unroll
+    for (int gi = 0; gi < GB; ++gi) {
+      const int grp = t + gi * 256;
+      const int vb = MODE == NTT_COL ? (grp % G) : (grp / 16);
+      const int hb = MODE == NTT_COL ? (grp / G) : (grp % 16);
+      double y[NB];
+#pragma unroll
+      for (int e = 0; e < NB; ++e) y[e] = lds[lidx(vb, hb * NB + e)];
+      ntt_round<LOGS, RB, MODE, false>(y, hb, 0, row0 + vb, k1, tw, twq, m);
+      if (MODE == NTT_COL) {
+#pragma unroll
+        for (int e = 0; e < NB; ++e) dst[gaddr(vb, hb * NB + e)] = canon(y[e], m);
+      } else {
+#pragma unroll
+        for (int e = 0; e < NB; ++e) lds[lidx(vb, hb * NB + e)] = y[e];
+      }
+    }
+    if (MODE == NTT_ROW) {
+      __syncthreads();
+      gdbl2* d2 = (gdbl2*)(dst + (size_t)row0 * S);
+      for (int i = t; i < G * S / 2; i += 256)
+      {
+        dv2 v;
+        v.x = canon(lds[lpad(2 * i)], m);
+        v.y = canon(lds[lpad(2 * i + 1)], m);
+        d2[i] = v;
+      }
+    }
+  } else {
+    // ---- round B first (low bits), loaded straight (column) or via LDS (row)
+    if (MODE == NTT_ROW) {
+      cgdbl2* s2 = (cgdbl2*)(src + (size_t)row0 * S);
+      for (int i = t; i < G * S / 2; i += 256) {
+        const dv2 v = s2[i];
+        lds[lpad(2 * i)] = v.x;
+        lds[lpad(2 * i + 1)] = v.y;
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int gi = 0; gi < GB; ++gi) {
+      const int grp = t + gi * 256;
+      const int vb = MODE == NTT_COL ? (grp % G) : (grp / 16);
+      const int hb = MODE == NTT_COL ? (grp / G) : (grp % 16);
+      double y[NB];
+#pragma unroll
+      for (int e = 0; e < NB; ++e)
+        y[e] = MODE == NTT_COL ? src[gaddr(vb, hb * NB + e)] : lds[lidx(vb, hb * NB + e)];
+      ntt_round<LOGS, RB, MODE, true>(y, hb, 0, row0 + vb, k1, tw, twq, m);
+      // each group is read and written back by its own thread: no barrier needed here
+#pragma unroll
+      for (int e = 0; e < NB; ++e) lds[lidx(vb, hb * NB + e)] = y[e];
+    }
+    __syncthreads();
+    // ---- round A, stored straight to global memory
+#pragma unroll
+    for (int e = 0; e < 16; ++e) x[e] = lds[lidx(va, e * NB + la)];
+    ntt_round<LOGS, 4, MODE, true>(x, 0, RB, row0 + va, k1, tw, twq, m);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      double v = x[e];
+      if (scale) v = mul_w(red(v, m), ni, niq, m.p);
+      dst[gaddr(va, e * NB + la)] = canon(v, m);
+    }
+  }
+}
+
 size_t ntt_lds_bytes(int logs, int g) {
   const int n = g << logs;
   return (size_t)(n + (n >> 4)) * sizeof(double);
@@ -202,11 +370,14 @@ size_t ntt_lds_bytes(int logs, int g) {
 NTT_INST(10, 1, NTT_SINGLE)
 NTT_INST(11, 1, NTT_SINGLE)
 NTT_INST(12, 1, NTT_SINGLE)
-NTT_INST(6, 64, NTT_COL)
-NTT_INST(7, 32, NTT_COL)
-NTT_INST(8, 16, NTT_COL)
-NTT_INST(7, 32, NTT_ROW)
-NTT_INST(8, 16, NTT_ROW)
+#define NTT2_INST(LOGS, G, MODE)                                                                  \
+  template __global__ void k_ntt2<LOGS, G, MODE, false>(const NttJob* __restrict__, DevTables, int); \
+  template __global__ void k_ntt2<LOGS, G, MODE, true>(const NttJob* __restrict__, DevTables, int);
+NTT2_INST(6, 64, NTT_COL)
+NTT2_INST(7, 32, NTT_COL)
+NTT2_INST(8, 16, NTT_COL)
+NTT2_INST(7, 32, NTT_ROW)
+NTT2_INST(8, 16, NTT_ROW)
 
 void* ntt_kernel(int logs, int mode, bool inv, int* g_out) {
 #define PICK(LOGS, G, MODE)                                                                       \
@@ -217,95 +388,137 @@ void* ntt_kernel(int logs, int mode, bool inv, int* g_out) {
   PICK(10, 1, NTT_SINGLE)
   PICK(11, 1, NTT_SINGLE)
   PICK(12, 1, NTT_SINGLE)
-  PICK(6, 64, NTT_COL)
-  PICK(7, 32, NTT_COL)
-  PICK(8, 16, NTT_COL)
-  PICK(7, 32, NTT_ROW)
-  PICK(8, 16, NTT_ROW)
 #undef PICK
+#define PICK2(LOGS, G, MODE)                                                                      \
+  if (logs == LOGS && mode == MODE) {                                                             \
+    *g_out = G;                                                                                   \
+    return inv ? (void*)&k_ntt2<LOGS, G, MODE, true> : (void*)&k_ntt2<LOGS, G, MODE, false>;      \
+  }
+  PICK2(6, 64, NTT_COL)
+  PICK2(7, 32, NTT_COL)
+  PICK2(8, 16, NTT_COL)
+  PICK2(7, 32, NTT_ROW)
+  PICK2(8, 16, NTT_ROW)
+#undef PICK2
   return nullptr;
 }
 
 // ---------------------------------------------------------------------------
 // elementwise operations on limbs (NTT domain unless stated)
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 ld2(const double* p, size_t o) {
+  const dv2 v = *(cgdbl2*)(CGPTR(p) + o);
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void st2(double* p, size_t o, double a, double b) {
+  dv2 v;
+  v.x = a;
+  v.y = b;
+  *(gdbl2*)(GPTR(p) + o) = v;
+}
+
 __global__ __launch_bounds__(256) void k_ew(const EwJob* __restrict__ jobs, DevTables T) {
   const EwJob J = jobs[blockIdx.z];
   const int l = blockIdx.y;
   if (l >= J.n_limbs) return;
   const int pr = l < J.n_chain ? l : T.n_q + (l - J.n_chain);
-  const Mod m{T.mod[pr], T.minv[pr]};
+  const Mod m{KPTR(T.mod)[pr], KPTR(T.minv)[pr]};
   const int N = 1 << T.log_n;
   const size_t off = (size_t)l * N;
-  const double kk = J.k ? J.k[l] : 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+  const double kk = J.k ? KPTR(J.k)[l] : 0.0;
+  for (int i = 2 * (blockIdx.x * blockDim.x + threadIdx.x); i < N; i += 2 * gridDim.x * blockDim.x) {
     const size_t o = off + i;
     switch (J.op) {
-      case EW_ADD:
-        J.o0[o] = add_mod(J.a0[o], J.b0[o], m);
-        J.o1[o] = add_mod(J.a1[o], J.b1[o], m);
-        break;
-      case EW_SUB:
-        J.o0[o] = sub_mod(J.a0[o], J.b0[o], m);
-        J.o1[o] = sub_mod(J.a1[o], J.b1[o], m);
-        break;
-      case EW_TENSOR: {
-        const double a0 = J.a0[o], a1 = J.a1[o], b0 = J.b0[o], b1 = J.b1[o];
-        const double t0 = mul_mod(a0, b0, m);
-        const double t1 = mul_mod(a0, b1, m) + mul_mod(a1, b0, m);
-        const double t2 = mul_mod(a1, b1, m);
-        J.o0[o] = canon(t0, m);
-        J.o1[o] = canon(t1, m);
-        J.o2[o] = canon(t2, m);
+      case EW_ADD: {
+        const double2 a0 = ld2(J.a0, o), b0 = ld2(J.b0, o), a1 = ld2(J.a1, o), b1 = ld2(J.b1, o);
+        st2(J.o0, o, add_mod(a0.x, b0.x, m), add_mod(a0.y, b0.y, m));
+        st2(J.o1, o, add_mod(a1.x, b1.x, m), add_mod(a1.y, b1.y, m));
         break;
       }
-      case EW_CMUL:
-        J.o0[o] = canon(mul_mod(J.a0[o], kk, m), m);
-        J.o1[o] = canon(mul_mod(J.a1[o], kk, m), m);
+      case EW_SUB: {
+        const double2 a0 = ld2(J.a0, o), b0 = ld2(J.b0, o), a1 = ld2(J.a1, o), b1 = ld2(J.b1, o);
+        st2(J.o0, o, sub_mod(a0.x, b0.x, m), sub_mod(a0.y, b0.y, m));
+        st2(J.o1, o, sub_mod(a1.x, b1.x, m), sub_mod(a1.y, b1.y, m));
         break;
-      case EW_ADD_CONST:
-        J.o0[o] = add_mod(J.a0[o], kk, m);
-        if (J.o1 != J.a1) J.o1[o] = J.a1[o];
+      }
+      case EW_TENSOR: {
+        const double2 a0 = ld2(J.a0, o), a1 = ld2(J.a1, o), b0 = ld2(J.b0, o), b1 = ld2(J.b1, o);
+        st2(J.o0, o, canon(mul_mod(a0.x, b0.x, m), m), canon(mul_mod(a0.y, b0.y, m), m));
+        st2(J.o1, o, canon(mul_mod(a0.x, b1.x, m) + mul_mod(a1.x, b0.x, m), m),
+            canon(mul_mod(a0.y, b1.y, m) + mul_mod(a1.y, b0.y, m), m));
+        st2(J.o2, o, canon(mul_mod(a1.x, b1.x, m), m), canon(mul_mod(a1.y, b1.y, m), m));
         break;
+      }
+      case EW_CMUL: {
+        const double2 a0 = ld2(J.a0, o), a1 = ld2(J.a1, o);
+        st2(J.o0, o, canon(mul_mod(a0.x, kk, m), m), canon(mul_mod(a0.y, kk, m), m));
+        st2(J.o1, o, canon(mul_mod(a1.x, kk, m), m), canon(mul_mod(a1.y, kk, m), m));
+        break;
+      }
+      case EW_ADD_CONST: {
+        const double2 a0 = ld2(J.a0, o);
+        st2(J.o0, o, add_mod(a0.x, kk, m), add_mod(a0.y, kk, m));
+        if (J.o1 != J.a1) {
+          const double2 a1 = ld2(J.a1, o);
+          st2(J.o1, o, a1.x, a1.y);
+        }
+        break;
+      }
       case EW_PMUL: {
-        const double p = J.b0[o];
-        J.o0[o] = canon(mul_mod(J.a0[o], p, m), m);
-        J.o1[o] = canon(mul_mod(J.a1[o], p, m), m);
+        const double2 p = ld2(J.b0, o), a0 = ld2(J.a0, o), a1 = ld2(J.a1, o);
+        st2(J.o0, o, canon(mul_mod(a0.x, p.x, m), m), canon(mul_mod(a0.y, p.y, m), m));
+        st2(J.o1, o, canon(mul_mod(a1.x, p.x, m), m), canon(mul_mod(a1.y, p.y, m), m));
         break;
       }
       case EW_MODDOWN: {
-        const double d0 = mul_mod(J.b0[o] - J.c0[o], kk, m);
-        const double d1 = mul_mod(J.b1[o] - J.c1[o], kk, m);
-        J.o0[o] = canon((J.a0 ? J.a0[o] : 0.0) + d0, m);
-        J.o1[o] = canon((J.a1 ? J.a1[o] : 0.0) + d1, m);
+        const double2 b0 = ld2(J.b0, o), c0 = ld2(J.c0, o), b1 = ld2(J.b1, o), c1 = ld2(J.c1, o);
+        const double2 a0 = J.a0 ? ld2(J.a0, o) : make_double2(0.0, 0.0);
+        const double2 a1 = J.a1 ? ld2(J.a1, o) : make_double2(0.0, 0.0);
+        st2(J.o0, o, canon(a0.x + mul_mod(b0.x - c0.x, kk, m), m), canon(a0.y + mul_mod(b0.y - c0.y, kk, m), m));
+        st2(J.o1, o, canon(a1.x + mul_mod(b1.x - c1.x, kk, m), m), canon(a1.y + mul_mod(b1.y - c1.y, kk, m), m));
         break;
       }
-      case EW_RESCALE:
-        J.o0[o] = canon(mul_mod(J.a0[o] - J.b0[o], kk, m), m);
-        J.o1[o] = canon(mul_mod(J.a1[o] - J.b1[o], kk, m), m);
+      case EW_RESCALE: {
+        const double2 a0 = ld2(J.a0, o), b0 = ld2(J.b0, o), a1 = ld2(J.a1, o), b1 = ld2(J.b1, o);
+        st2(J.o0, o, canon(mul_mod(a0.x - b0.x, kk, m), m), canon(mul_mod(a0.y - b0.y, kk, m), m));
+        st2(J.o1, o, canon(mul_mod(a1.x - b1.x, kk, m), m), canon(mul_mod(a1.y - b1.y, kk, m), m));
         break;
-      case EW_DEC2:
-        J.o0[o] = canon(J.a0[o] + mul_mod(J.a1[o], J.b0[o], m), m);
+      }
+      case EW_DEC2: {
+        const double2 a0 = ld2(J.a0, o), a1 = ld2(J.a1, o), b0 = ld2(J.b0, o);
+        st2(J.o0, o, canon(a0.x + mul_mod(a1.x, b0.x, m), m), canon(a0.y + mul_mod(a1.y, b0.y, m), m));
         break;
+      }
       case EW_ENC: {
-        const double as = mul_mod(J.b0[o], J.b1[o], m);
-        J.o0[o] = canon(J.a0[o] + J.a1[o] - as, m);
+        const double2 a0 = ld2(J.a0, o), a1 = ld2(J.a1, o), b0 = ld2(J.b0, o), b1 = ld2(J.b1, o);
+        st2(J.o0, o, canon(a0.x + a1.x - mul_mod(b0.x, b1.x, m), m), canon(a0.y + a1.y - mul_mod(b0.y, b1.y, m), m));
         break;
       }
       case EW_KEYB: {
-        const double as = mul_mod(J.b0[o], J.b1[o], m);
-        double v = J.a1[o] - as;
-        if (kk != 0.0) v += mul_mod(kk, J.c0[o], m);
-        J.o0[o] = canon(v, m);
+        const double2 a1 = ld2(J.a1, o), b0 = ld2(J.b0, o), b1 = ld2(J.b1, o);
+        double vx = a1.x - mul_mod(b0.x, b1.x, m), vy = a1.y - mul_mod(b0.y, b1.y, m);
+        if (kk != 0.0) {
+          const double2 c0 = ld2(J.c0, o);
+          vx += mul_mod(kk, c0.x, m);
+          vy += mul_mod(kk, c0.y, m);
+        }
+        st2(J.o0, o, canon(vx, m), canon(vy, m));
         break;
       }
-      case EW_MUL:
-        J.o0[o] = canon(mul_mod(J.a0[o], J.b0[o], m), m);
+      case EW_MUL: {
+        const double2 a0 = ld2(J.a0, o), b0 = ld2(J.b0, o);
+        st2(J.o0, o, canon(mul_mod(a0.x, b0.x, m), m), canon(mul_mod(a0.y, b0.y, m), m));
         break;
-      case EW_COPY:
-        J.o0[o] = J.a0[o];
-        if (J.o1) J.o1[o] = J.a1[o];
+      }
+      case EW_COPY: {
+        const double2 a0 = ld2(J.a0, o);
+        st2(J.o0, o, a0.x, a0.y);
+        if (J.o1) {
+          const double2 a1 = ld2(J.a1, o);
+          st2(J.o1, o, a1.x, a1.y);
+        }
         break;
+      }
       default:
         break;
     }
@@ -330,15 +543,15 @@ __global__ __launch_bounds__(256) void k_modup(const ModUpJob* __restrict__ jobs
   for (int i = 0; i < MAX_DIGIT; ++i) {
     if (i < dsz) {
       const int pr = J.digit_lo + i;
-      const Mod mi{T.mod[pr], T.minv[pr]};
-      y[i] = canon(mul_mod(J.src[(size_t)pr * N + k], J.cinv[i], mi), mi);
+      const Mod mi{KPTR(T.mod)[pr], KPTR(T.minv)[pr]};
+      y[i] = canon(mul_mod(CGPTR(J.src)[(size_t)pr * N + k], KPTR(J.cinv)[i], mi), mi);
     }
   }
   for (int t = 0; t < J.n_ext; ++t) {
     if (t >= J.digit_lo && t < J.digit_hi) continue;
     const int pr = t < J.n_chain ? t : T.n_q + (t - J.n_chain);
-    const Mod mt{T.mod[pr], T.minv[pr]};
-    const double* ch = J.chat + (size_t)pr * dsz;
+    const Mod mt{KPTR(T.mod)[pr], KPTR(T.minv)[pr]};
+    kdbl* ch = KPTR(J.chat) + (size_t)pr * dsz;
     double acc = 0.0;
 #pragma unroll
     for (int i = 0; i < MAX_DIGIT; ++i) {
@@ -347,7 +560,7 @@ __global__ __launch_bounds__(256) void k_modup(const ModUpJob* __restrict__ jobs
         if (i & 1) acc = red(acc, mt);
       }
     }
-    J.dst[(size_t)t * N + k] = canon(acc, mt);
+    GPTR(J.dst)[(size_t)t * N + k] = canon(acc, mt);
   }
 }
 
@@ -363,13 +576,13 @@ __global__ __launch_bounds__(256) void k_moddown_conv(const ModDownJob* __restri
   for (int i = 0; i < MAX_DIGIT; ++i) {
     if (i < alpha) {
       const int pr = T.n_q + i;
-      const Mod mi{T.mod[pr], T.minv[pr]};
-      y[i] = canon(mul_mod(J.src[(size_t)i * N + k], J.cinv[i], mi), mi);
+      const Mod mi{KPTR(T.mod)[pr], KPTR(T.minv)[pr]};
+      y[i] = canon(mul_mod(CGPTR(J.src)[(size_t)i * N + k], KPTR(J.cinv)[i], mi), mi);
     }
   }
   for (int t = 0; t < J.n_chain; ++t) {
-    const Mod mt{T.mod[t], T.minv[t]};
-    const double* ch = J.chat + (size_t)t * alpha;
+    const Mod mt{KPTR(T.mod)[t], KPTR(T.minv)[t]};
+    kdbl* ch = KPTR(J.chat) + (size_t)t * alpha;
     double acc = 0.0;
 #pragma unroll
     for (int i = 0; i < MAX_DIGIT; ++i) {
@@ -378,32 +591,38 @@ __global__ __launch_bounds__(256) void k_moddown_conv(const ModDownJob* __restri
         if (i & 1) acc = red(acc, mt);
       }
     }
-    J.dst[(size_t)t * N + k] = canon(acc, mt);
+    GPTR(J.dst)[(size_t)t * N + k] = canon(acc, mt);
   }
 }
 
-// acc_w[t] = sum_j x_j[t] key_j[w][t]; x_j[t] = d[t] inside digit j, else ModUp output
+// acc_w[t] = sum_j x_j[t] key_j[w][t]; x_j[t] = d[t] inside digit j, else ModUp output.
+// blockIdx.x runs over jobs so that jobs streaming the same key limb run
+// back to back (relinearisation shares one key across a whole batch).
 __global__ __launch_bounds__(256) void k_inner(const InnerJob* __restrict__ jobs, DevTables T) {
-  const InnerJob J = jobs[blockIdx.z];
+  const InnerJob J = jobs[blockIdx.x];
   const int t = blockIdx.y;
   if (t >= J.n_ext) return;
   const int N = 1 << T.log_n;
   const int n_mod = T.n_q + T.n_p;
   const int pr = t < J.n_chain ? t : T.n_q + (t - J.n_chain);
-  const Mod m{T.mod[pr], T.minv[pr]};
+  const Mod m{KPTR(T.mod)[pr], KPTR(T.minv)[pr]};
   const int own = t < J.n_chain ? t / J.alpha : -1;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < N; k += gridDim.x * blockDim.x) {
-    double acc0 = 0.0, acc1 = 0.0;
+  for (int k = 2 * (blockIdx.z * blockDim.x + threadIdx.x); k < N; k += 2 * gridDim.z * blockDim.x) {
+    double a0x = 0.0, a0y = 0.0, a1x = 0.0, a1y = 0.0;
     for (int j = 0; j < J.n_digits; ++j) {
-      const double x = (j == own) ? J.d[(size_t)t * N + k] : J.ext[((size_t)j * J.n_ext + t) * N + k];
-      const double kb = J.key[(((size_t)j * 2 + 0) * n_mod + pr) * N + k];
-      const double ka = J.key[(((size_t)j * 2 + 1) * n_mod + pr) * N + k];
-      acc0 += mul_mod(x, kb, m);
-      acc1 += mul_mod(x, ka, m);
-      if (j & 1) { acc0 = red(acc0, m); acc1 = red(acc1, m); }
+      const double2 x = (j == own) ? ld2(J.d, (size_t)t * N + k) : ld2(J.ext, ((size_t)j * J.n_ext + t) * N + k);
+      const double2 kb = ld2(J.key, (((size_t)j * 2 + 0) * n_mod + pr) * N + k);
+      const double2 ka = ld2(J.key, (((size_t)j * 2 + 1) * n_mod + pr) * N + k);
+      a0x += mul_mod(x.x, kb.x, m);
+      a0y += mul_mod(x.y, kb.y, m);
+      a1x += mul_mod(x.x, ka.x, m);
+      a1y += mul_mod(x.y, ka.y, m);
+      if (j & 1) {
+        a0x = red(a0x, m); a0y = red(a0y, m); a1x = red(a1x, m); a1y = red(a1y, m);
+      }
     }
-    J.acc[(size_t)t * N + k] = canon(acc0, m);
-    J.acc[((size_t)J.n_ext + t) * N + k] = canon(acc1, m);
+    st2(J.acc, (size_t)t * N + k, canon(a0x, m), canon(a0y, m));
+    st2(J.acc, ((size_t)J.n_ext + t) * N + k, canon(a1x, m), canon(a1y, m));
   }
 }
 
@@ -414,7 +633,7 @@ __global__ __launch_bounds__(256) void k_spread_centred(const SpreadJob* __restr
   const int i = blockIdx.y;
   if (i >= J.n_chain) return;
   const double qt = T.mod[J.src_prime];
-  const Mod m{T.mod[i], T.minv[i]};
+  const Mod m{KPTR(T.mod)[i], KPTR(T.minv)[i]};
   const double half = (qt - 1.0) * 0.5;
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < N; k += gridDim.x * blockDim.x) {
     double v = J.src[k];
@@ -451,15 +670,15 @@ __global__ __launch_bounds__(256) void k_lift(const LiftJob* __restrict__ jobs, 
   const int N = 1 << T.log_n;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N) return;
-  const Mod m0{T.mod[0], T.minv[0]};
-  const Mod m1{T.mod[1], T.minv[1]};
+  const Mod m0{KPTR(T.mod)[0], KPTR(T.minv)[0]};
+  const Mod m1{KPTR(T.mod)[1], KPTR(T.minv)[1]};
   const double r0 = J.r0[k], r1 = J.r1[k];
   const double diff = r1 - red(r0, m1);
   const double d = canon(mul_mod(diff, q0inv_q1, m1), m1);
   const double h = (m1.p - 1.0) * 0.5;
   const bool neg = d > h || (d == h && r0 > (m0.p - 1.0) * 0.5);
   for (int t = 0; t < J.n_out; ++t) {
-    const Mod mt{T.mod[t], T.minv[t]};
+    const Mod mt{KPTR(T.mod)[t], KPTR(T.minv)[t]};
     double v = red(r0, mt) + mul_mod(d, ctab[2 * t], mt);
     if (neg) v -= ctab[2 * t + 1];
     J.dst[(size_t)t * N + k] = canon(v, mt);
@@ -501,7 +720,7 @@ __global__ __launch_bounds__(256) void k_sample(const SampleJob* __restrict__ jo
   if (l >= J.n_limbs) return;
   const int pr = l < J.n_chain ? l : T.n_q + (l - J.n_chain);
   const int N = 1 << T.log_n;
-  const Mod m{T.mod[pr], T.minv[pr]};
+  const Mod m{KPTR(T.mod)[pr], KPTR(T.minv)[pr]};
   const uint64_t tag = J.kind == SAMPLE_UNIFORM ? (J.tag_base | (uint64_t)pr) : (J.tag_base | 0xFFFull);
   const uint64_t key = sm_mix(J.seed ^ sm_mix(tag));
   const uint64_t q = (uint64_t)m.p;
@@ -677,7 +896,7 @@ void launch_moddown_conv(const DevTables& T, const ModDownJob* jobs, int n_jobs,
 }
 void launch_inner(const DevTables& T, const InnerJob* jobs, int n_jobs, int max_ext, hipStream_t s) {
   if (n_jobs <= 0 || max_ext <= 0) return;
-  dim3 grid(ew_blocks(1 << T.log_n), max_ext, n_jobs);
+  dim3 grid(n_jobs, max_ext, ew_blocks(1 << T.log_n));
   hipLaunchKernelGGL(k_inner, grid, dim3(256), 0, s, jobs, T);
 }
 void launch_spread_centred(const DevTables& T, const SpreadJob* jobs, int n_jobs, int max_chain, hipStream_t s) {

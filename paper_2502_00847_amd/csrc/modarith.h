@@ -72,6 +72,20 @@ __device__ __forceinline__ double sub_mod(double a, double b, const Mod& m) {  /
   return s < 0.0 ? s + m.p : s;
 }
 
+// Pointers read from job descriptors are generic; casting them to the global
+// address space lets the compiler emit global_load / global_store.
+typedef __attribute__((address_space(1))) double gdbl;
+typedef const __attribute__((address_space(1))) double cgdbl;
+#define GPTR(p) ((gdbl*)(p))
+#define CGPTR(p) ((cgdbl*)(p))
+// read-only tables: the constant address space lets uniform indices become
+// scalar loads
+typedef const __attribute__((address_space(4))) double kdbl;
+#define KPTR(p) ((kdbl*)(p))
+typedef double dv2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) dv2 gdbl2;
+typedef const __attribute__((address_space(1))) dv2 cgdbl2;
+
 // uint64 <-> double for values below 2^53
 __device__ __forceinline__ double u64_to_d(uint64_t v) { return (double)v; }
 __device__ __forceinline__ uint64_t d_to_u64(double v) { return (uint64_t)v; }

@@ -137,9 +137,16 @@ struct CT {
   int slot = -1;   // -1: not owned by the pool
 };
 
+// ciphertext slots of a workspace; a server keeps one across rounds
+struct SlotPool {
+  std::vector<int> free_slots;
+  int n_slots = 0;   // high-water mark
+  int live = 0;
+};
+
 class Builder {
  public:
-  Builder(Ctx& c, char* ws, size_t ws_bytes, char* arena, size_t arena_bytes, bool dry);
+  Builder(Ctx& c, char* ws, size_t ws_bytes, char* arena, size_t arena_bytes, bool dry, SlotPool* pool = nullptr);
 
   Ctx& C;
   bool dry;
@@ -153,6 +160,8 @@ class Builder {
   size_t scratch_mark() const { return scratch_cur_; }
   void scratch_release(size_t mark) { scratch_cur_ = mark; }
   size_t need_bytes() const { return need_max_; }
+  int peak_slots() const { return peak_live_; }
+  size_t peak_scratch() const { return peak_scratch_; }
   size_t blob_bytes() const { return blob_.size(); }
   bool arena_overflow() const { return blob_.size() > arena_bytes_; }
 
@@ -222,9 +231,11 @@ class Builder {
   char* arena_;
   size_t arena_bytes_;
   size_t slot_bytes_;
-  std::vector<int> free_slots_;
-  int n_slots_ = 0;
+  SlotPool own_pool_;
+  SlotPool* pool_;
+  int peak_live_ = 0;
   size_t scratch_cur_ = 0;
+  size_t peak_scratch_ = 0;
   size_t need_max_ = 0;
   void note_need();
   void push(int kind, int n, int max_y, size_t off, bool inv = false, int64_t units = 0);
@@ -243,8 +254,25 @@ struct ArgmaxQuery {
   double d_min, d_max;
   uint64_t refresh_seed;
   CT out;  // caller buffer (d set), level/scale written
+  uint64_t ticket = 0;
 };
 void build_argmax(Builder& b, std::vector<ArgmaxQuery>& q);
+
+// Per-query state machines that survive across command lists: a round
+// advances queries by one step (all step kinds present, or only the most
+// common one) and returns the queries that finished in it.
+struct QState;
+class ArgmaxProgram {
+ public:
+  ArgmaxProgram();
+  ~ArgmaxProgram();
+  bool add(Builder& b, ArgmaxQuery* q);
+  std::vector<ArgmaxQuery*> round(Builder& b, bool all_kinds);
+  size_t active() const;
+
+ private:
+  std::vector<QState*> st_;
+};
 
 int ilog2_ceil(int v);
 

@@ -255,26 +255,30 @@ void destroy_context(Ctx& c) {
 // ---------------------------------------------------------------------------
 // builder: memory
 // ---------------------------------------------------------------------------
-Builder::Builder(Ctx& c, char* ws, size_t ws_bytes, char* arena, size_t arena_bytes, bool dry_)
+Builder::Builder(Ctx& c, char* ws, size_t ws_bytes, char* arena, size_t arena_bytes, bool dry_, SlotPool* pool)
     : C(c), dry(dry_), ws_(ws), ws_bytes_(ws_bytes & ~size_t(255)), arena_(arena), arena_bytes_(arena_bytes) {
   slot_bytes_ = c.ct_bytes();
+  pool_ = pool ? pool : &own_pool_;
 }
 
 void Builder::note_need() {
-  const size_t need = (size_t)n_slots_ * slot_bytes_ + scratch_cur_;
+  const size_t need = (size_t)pool_->n_slots * slot_bytes_ + scratch_cur_;
   need_max_ = std::max(need_max_, need);
+  peak_scratch_ = std::max(peak_scratch_, scratch_cur_);
   if (!dry && need > ws_bytes_) fail(-2, "workspace too small");
 }
 
 CT Builder::new_ct(int level, double scale) {
   CT x;
-  if (!free_slots_.empty()) {
-    x.slot = free_slots_.back();
-    free_slots_.pop_back();
+  if (!pool_->free_slots.empty()) {
+    x.slot = pool_->free_slots.back();
+    pool_->free_slots.pop_back();
   } else {
-    x.slot = n_slots_++;
+    x.slot = pool_->n_slots++;
     note_need();
   }
+  pool_->live++;
+  peak_live_ = std::max(peak_live_, pool_->live);
   x.d = (double*)(ws_ + (size_t)x.slot * slot_bytes_);
   x.level = level;
   x.scale = scale;
@@ -282,7 +286,10 @@ CT Builder::new_ct(int level, double scale) {
 }
 
 void Builder::free_ct(CT& x) {
-  if (x.slot >= 0) free_slots_.push_back(x.slot);
+  if (x.slot >= 0) {
+    pool_->free_slots.push_back(x.slot);
+    pool_->live--;
+  }
   x.slot = -1;
   x.d = nullptr;
 }

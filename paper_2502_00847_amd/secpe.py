@@ -90,6 +90,11 @@ def load():
         "secpe_ntt_cts": (i32, [vp, ct, i32, i32]),
         "secpe_rotate_workspace_bytes": (sz, [vp, i32]),
         "secpe_rotate_batch": (i32, [vp, i32, ct, P(i64), vp, sz, ct]),
+        "secpe_server_create": (i32, [vp, vp, sz, i32, P(vp)]),
+        "secpe_server_destroy": (None, [vp]),
+        "secpe_server_request_bytes": (sz, [vp, i32, i32]),
+        "secpe_server_submit": (i32, [vp, ct, i32, i32, dbl, dbl, u64, vp, P(u64)]),
+        "secpe_server_step": (i32, [vp, i32, P(i32), P(u64), P(i32), P(dbl), P(i32), P(i32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -111,7 +116,9 @@ def exported_symbols():
          "secpe_op_mul_const", "secpe_op_mul_plain", "secpe_op_rescale", "secpe_op_mul_relin",
          "secpe_op_mul_relin_rescale", "secpe_op_rotate", "secpe_op_refresh", "secpe_op_eval_odd9",
          "secpe_op_key_switch", "secpe_op_ntt", "secpe_op_ring_mul", "secpe_op_encode", "secpe_profile_begin",
-         "secpe_profile_end", "secpe_ntt_cts", "secpe_rotate_workspace_bytes", "secpe_rotate_batch"])
+         "secpe_profile_end", "secpe_ntt_cts", "secpe_rotate_workspace_bytes", "secpe_rotate_batch",
+         "secpe_server_create", "secpe_server_destroy", "secpe_server_request_bytes", "secpe_server_submit",
+         "secpe_server_step"])
 
 
 def _p(arr, ctype):
@@ -428,3 +435,53 @@ class Context:
         out = np.zeros(self.N, dtype=np.int64)
         self._check(self.lib.secpe_op_encode(self.h, _p(z, C.c_double), len(z), float(scale), _p(out, C.c_int64)))
         return out
+
+
+class Server:
+    """Continuous-batching request loop over one workspace (secpe_server_*)."""
+
+    def __init__(self, ctx, ws_bytes, max_active=256):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.ws = ctx._empty(ws_bytes)
+        h = C.c_void_p()
+        ctx._check(self.lib.secpe_server_create(ctx.h, C.c_void_p(self.ws.data_ptr()), self.ws.numel() * 8,
+                                                int(max_active), C.byref(h)))
+        self.h = h
+        self.results = {}
+        self._inputs = {}
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.secpe_server_destroy(self.h)
+            self.h = None
+
+    def request_bytes(self, K, Cc):
+        return self.lib.secpe_server_request_bytes(self.ctx.h, int(K), int(Cc))
+
+    def submit(self, ct, K, Cc, d_min, d_max, refresh_seed, out=None):
+        out = out if out is not None else self.ctx.new_ct()
+        t = C.c_uint64(0)
+        c = ct._c()
+        self.ctx._check(self.lib.secpe_server_submit(self.h, C.byref(c), int(K), int(Cc), float(d_min), float(d_max),
+                                                     int(refresh_seed), C.c_void_p(out.buf.data_ptr()), C.byref(t)))
+        self._inputs[t.value] = (ct, out)
+        return t.value
+
+    def step(self, cap=1024):
+        n = C.c_int(0)
+        na = C.c_int(0)
+        npd = C.c_int(0)
+        tk = np.zeros(cap, dtype=np.uint64)
+        lv = np.zeros(cap, dtype=np.int32)
+        sc = np.zeros(cap)
+        self.ctx._check(self.lib.secpe_server_step(self.h, cap, C.byref(n), _p(tk, C.c_uint64), _p(lv, C.c_int),
+                                                   _p(sc, C.c_double), C.byref(na), C.byref(npd)))
+        done = []
+        for i in range(n.value):
+            t = int(tk[i])
+            ct, out = self._inputs.pop(t)
+            out.level, out.scale = int(lv[i]), float(sc[i])
+            self.results[t] = out
+            done.append(t)
+        return done, na.value, npd.value

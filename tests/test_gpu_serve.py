@@ -1,0 +1,89 @@
+"""Continuous batching (secpe_server_*): requests submitted while others are
+in flight join at the next round, memory-based admission queues the excess,
+and every result is bit-identical to evaluating the request alone."""
+import numpy as np
+import pytest
+
+import workload as W
+from oracle import sim
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tiny_ctx():
+    from paper_2502_00847_amd.secpe import Context
+    g = Context(W.PARAMS["tiny"])
+    g.keygen(W.KEYGEN_SEED, g.argmax_steps(32, 20))
+    return g
+
+
+def _request(g, i):
+    K, C = W.query_shape(5, i)
+    K, C = min(K, 16), min(C, 16)   # 'tiny' has 512 slots
+    y = W.logits(5, i, K, C)
+    enc, ref = W.query_seeds(5, i)
+    lo, hi = W.d_bounds(K)
+    return dict(ct=g.encrypt(y, enc), K=K, C=C, d_min=lo, d_max=hi, seed=ref, y=y)
+
+
+def test_staggered_arrivals_match_alone(tiny_ctx):
+    from paper_2502_00847_amd.secpe import Server
+    g = tiny_ctx
+    reqs = [_request(g, i) for i in range(12)]
+    srv = Server(g, 4 * g.workspace_bytes([r["K"] for r in reqs], [r["C"] for r in reqs]), max_active=64)
+    tickets = {}
+    arrivals = {0: [0, 1, 2], 2: [3, 4], 5: [5, 6, 7], 9: [8], 14: [9, 10, 11]}
+    step = 0
+    max_active = 0
+    while len(srv.results) < len(reqs):
+        for i in arrivals.get(step, []):
+            r = reqs[i]
+            tickets[i] = srv.submit(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"])
+        done, n_active, n_pending = srv.step()
+        max_active = max(max_active, n_active + len(done))
+        step += 1
+        assert step < 500
+    assert max_active > 3   # requests overlapped on the device
+    for i, r in enumerate(reqs):
+        got = srv.results[tickets[i]]
+        alone = g.eval_argmax(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"])
+        assert (got.level, got.scale) == (alone.level, alone.scale)
+        assert np.array_equal(g.export(got), g.export(alone))
+        z, idx = g.decrypt(got, r["C"])
+        i0, _, margin = sim.t0_argmax(r["y"])
+        if margin / (r["d_max"] - r["d_min"]) >= 2.0**-10:
+            assert idx == i0
+
+
+def test_admission_by_memory_queues_requests(tiny_ctx):
+    """A workspace sized for about two requests never runs more than two at once,
+    and still completes every request with the same bits."""
+    from paper_2502_00847_amd.secpe import Server
+    g = tiny_ctx
+    reqs = [_request(g, 20 + i) for i in range(6)]
+    one = max(g.lib.secpe_server_request_bytes(g.h, r["K"], r["C"]) for r in reqs)
+    srv = Server(g, int(2.2 * one), max_active=64)
+    tickets = [srv.submit(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"]) for r in reqs]
+    peak = 0
+    saw_pending = False
+    for _ in range(2000):
+        done, n_active, n_pending = srv.step()
+        peak = max(peak, n_active + len(done))
+        saw_pending |= n_pending > 0
+        if len(srv.results) == len(reqs):
+            break
+    assert len(srv.results) == len(reqs)
+    assert saw_pending and peak <= 2
+    for t, r in zip(tickets, reqs):
+        alone = g.eval_argmax(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"])
+        assert np.array_equal(g.export(srv.results[t]), g.export(alone))
+
+
+def test_server_rejects_oversized_request(tiny_ctx):
+    from paper_2502_00847_amd.secpe import SecpeError, Server
+    g = tiny_ctx
+    r = _request(g, 40)
+    srv = Server(g, g.ct_bytes() * 2, max_active=4)
+    with pytest.raises(SecpeError):
+        srv.submit(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"])
