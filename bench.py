@@ -27,6 +27,10 @@ import numpy as np  # noqa: E402
 import workload as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes the roofline kernel moves per limb it transforms, from rocprofv3
+# FETCH_SIZE (x2, the factor a 1 GiB device copy shows) + WRITE_SIZE; see
+# profiles/ntt_fwd_row_config3_traffic.md.  None when the kernel has changed since.
+TRAFFIC_PER_LIMB_PASS = 1.5 * 2**20
 
 
 def _log(msg):
@@ -133,6 +137,39 @@ def serve(g, n, warm, qps=None, frac=0.7, max_active=96):
 
 
 # ---------------------------------------------------------------------------
+# key-switch rate: 64 rotations with random steps (64 distinct keys), 24 limbs
+# ---------------------------------------------------------------------------
+def keyswitch_rate(g, params):
+    n = 64
+    N = 1 << params["log_n"]
+    nq, npp = params["n_q"], params["n_p"]
+    dnum = (nq + npp - 1) // npp
+    steps = W.random_rotation_steps(n, N // 2)
+    saved = g.steps
+    g.keygen(W.KEYGEN_SEED + 4, steps)
+    cts = [g.encrypt(W.logits(4, i, 8, 8), i + 1) for i in range(n)]
+    ws = g._empty(g.lib.secpe_rotate_workspace_bytes(g.h, n))
+    outs = [g.new_ct() for _ in range(n)]
+    g.rotate_batch(cts, steps, ws=ws, outs=outs)
+    g.sync()
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        g.rotate_batch(cts, steps, ws=ws, outs=outs)
+    g.sync()
+    dt = (time.perf_counter() - t0) / reps
+    # algorithmic bytes of one key switch at 24 limbs: the input polynomial, the two output
+    # polynomials and the switching key (2 x dnum x (n_q + n_p) limbs)
+    limbs = nq + 2 * nq + 2 * dnum * (nq + npp)
+    byts = limbs * N * 8
+    g.keygen(W.KEYGEN_SEED, saved)
+    return {"workload": "64 rotations, random steps in [1, 2^15), 64 keys, 24 limbs, dnum 3",
+            "ms": round(dt * 1e3, 3), "us_per_keyswitch": round(dt * 1e6 / n, 1),
+            "algorithmic_bytes_per_keyswitch": byts,
+            "achieved_gbs": round(n * byts / dt / 1e9, 1), "frac_of_8tbs": round(n * byts / dt / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+# ---------------------------------------------------------------------------
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +181,8 @@ def main():
     ap.add_argument("--cpu", type=int, default=1, help="run the CPU-oracle baseline")
     ap.add_argument("--cpu-procs", type=int, default=0)
     ap.add_argument("--serve", type=int, default=160, help="requests in the serving run (0 = skip)")
+    ap.add_argument("--keyswitch", type=int, default=1, help="time 64 random-step rotations at 24 limbs")
+    ap.add_argument("--calib", type=int, default=0, help="copy 1 GiB first (counter calibration kernel)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -156,6 +195,12 @@ def main():
     from paper_2502_00847_amd.secpe import Context
 
     params = W.PARAMS["full"]
+    if args.calib:
+        a = torch.ones(2**27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     g = Context(params)
     steps_rot = g.argmax_steps(32, 20)
     g.keygen(W.KEYGEN_SEED, steps_rot)
@@ -190,8 +235,11 @@ def main():
         g.sync()
     _log("warmup done")
 
-    # timed region: K steps; the forward NTT launches are bracketed by HIP events
-    g.profile_begin("ntt_fwd")
+    # timed region: K steps; the forward NTT's row-pass kernel is bracketed by HIP events.
+    # Two fill kernels of distinctive sizes mark the region in a profiler's kernel trace.
+    marker = torch.empty(4096 * 5, dtype=torch.float64, device="cuda")
+    marker[:4096 * 3].fill_(3.0)
+    g.profile_begin("ntt_fwd_row")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -199,14 +247,19 @@ def main():
     g.sync()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    marker.fill_(5.0)
+    torch.cuda.synchronize()
     prof = g.profile_end()
     elapsed = t1 - t0
     value = B * args.steps / elapsed
     _log(f"timed {args.steps} steps: {elapsed:.3f} s -> {value:.1f} Argmax/s")
 
-    # per-query completion latency within a step (queries finish with their chunk)
+    # per-query completion latency within a step (queries finish with their chunk);
+    # the whole forward transform (both passes) is timed in the same pass
     ends = []
+    g.profile_begin("ntt_fwd")
     run_step(False, ends)
+    prof_all = g.profile_end()
     lat = np.array(ends) * 1e3
 
     # correctness of the timed outputs: decrypted index vs the plaintext argmax
@@ -234,20 +287,25 @@ def main():
     zz, idx2 = g.decrypt(z2, d2["C"])
 
     N = 1 << params["log_n"]
+    # the row pass reads and writes every limb it transforms once: 2*N*8 bytes per limb
     ntt_bytes = prof["units"] * 2 * N * 8
     achieved = ntt_bytes / (prof["ms"] * 1e-3) / 1e9 if prof["ms"] > 0 else 0.0
+    whole = prof_all["units"] * 2 * N * 8 / (prof_all["ms"] * 1e-3) / 1e9 if prof_all["ms"] > 0 else 0.0
     roofline = {
         "bound": "hbm",
-        "kernel": "forward negacyclic NTT (k_ntt column pass + row pass)",
+        "kernel": "k_ntt2<8,16,ROW,fwd>: row pass (last 8 of 16 stages) of the forward negacyclic NTT",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": (round(TRAFFIC_PER_LIMB_PASS * prof["units"] / max(1, prof["launches"]))
+                    if TRAFFIC_PER_LIMB_PASS else None),
         "launches": prof["launches"],
         "avg_launch_us": round(prof["ms"] * 1e3 / max(1, prof["launches"]), 2),
-        "limb_transforms_per_launch": round(prof["units"] / max(1, prof["launches"]), 1),
-        "algorithmic_bytes_per_limb_transform": 2 * N * 8,
+        "limb_passes_per_launch": round(prof["units"] / max(1, prof["launches"]), 1),
+        "algorithmic_bytes_per_limb_pass": 2 * N * 8,
+        "whole_forward_ntt_gbs": round(whole, 1),
+        "whole_forward_ntt_note": "1 MiB per limb transform over both passes (column + row kernels)",
     }
     result = {
         "metric": "encrypted Argmax/s (batched)",
@@ -276,6 +334,8 @@ def main():
         "index_ok_at_margin_2^-10": f"{ok_margin}/{n_margin}",
         "roofline": roofline,
     }
+    if args.keyswitch:
+        result["keyswitch"] = keyswitch_rate(g, params)
     if args.serve:
         _log(f"serving run: {args.serve} requests, Poisson arrivals at 0.7x the saturated rate")
         result["serving"] = serve(g, args.serve, max(8, args.serve // 8))

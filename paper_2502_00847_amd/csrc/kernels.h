@@ -9,7 +9,9 @@ namespace secpe {
 
 // Launchers: 'jobs' points to device memory holding n_jobs descriptors.
 // max_limbs bounds the limb count of any job in the launch (grid y).
-void launch_ntt(const DevTables& T, bool inverse, const NttJob* jobs, int n_jobs, int max_limbs, hipStream_t s);
+// prof_pass >= 0 brackets that pass (0 = first, 1 = second) with events e0/e1
+void launch_ntt(const DevTables& T, bool inverse, const NttJob* jobs, int n_jobs, int max_limbs, hipStream_t s,
+                int prof_pass = -1, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_ew(const DevTables& T, const EwJob* jobs, int n_jobs, int max_limbs, hipStream_t s);
 void launch_modup(const DevTables& T, const ModUpJob* jobs, int n_jobs, hipStream_t s);
 void launch_moddown_conv(const DevTables& T, const ModDownJob* jobs, int n_jobs, hipStream_t s);

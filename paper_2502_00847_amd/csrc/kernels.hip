@@ -849,7 +849,8 @@ namespace secpe {
 
 static inline int ew_blocks(int n) { return (n + 256 * 2 - 1) / (256 * 2); }
 
-void launch_ntt(const DevTables& T, bool inverse, const NttJob* jobs, int n_jobs, int max_limbs, hipStream_t s) {
+void launch_ntt(const DevTables& T, bool inverse, const NttJob* jobs, int n_jobs, int max_limbs, hipStream_t s,
+                int prof_pass, hipEvent_t e0, hipEvent_t e1) {
   if (n_jobs <= 0 || max_limbs <= 0) return;
   const int log_n = T.log_n;
   const int N = 1 << log_n;
@@ -862,7 +863,9 @@ void launch_ntt(const DevTables& T, bool inverse, const NttJob* jobs, int n_jobs
     DevTables t = T;
     int sec = second;
     void* args[] = {(void*)&jp, (void*)&t, (void*)&sec};
+    if (prof_pass == second && e0) (void)hipEventRecord(e0, s);
     (void)hipLaunchKernel(fn, grid, dim3(256), args, ntt_lds_bytes(logs, g), s);
+    if (prof_pass == second && e1) (void)hipEventRecord(e1, s);
   };
   if (log_n <= 12) {
     run(log_n, NTT_SINGLE, 0);

@@ -127,7 +127,7 @@ struct Cmd {
 
 // kinds the event profiler can bracket (secpe_profile_begin)
 enum ProfKind { PROF_NTT_FWD = 0, PROF_NTT_INV = 1, PROF_EW = 2, PROF_MODUP = 3, PROF_MODDOWN = 4, PROF_INNER = 5,
-                PROF_AUTO = 6, PROF_SPREAD = 7, PROF_NKINDS = 8 };
+                PROF_AUTO = 6, PROF_SPREAD = 7, PROF_NTT_FWD_COL = 8, PROF_NTT_FWD_ROW = 9, PROF_NKINDS = 10 };
 
 // ciphertext handle inside a build: device data [2][n_q][N], level, scale, pool slot
 struct CT {

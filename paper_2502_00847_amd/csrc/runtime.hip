@@ -431,6 +431,15 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
   hipStream_t s = c.stream;
   for (const Cmd& k : cmds) {
     const void* j = arena + k.off;
+    // one pass of the forward NTT (N > 2^12: pass 0 = columns, pass 1 = rows)
+    if ((c.prof_kind == PROF_NTT_FWD_COL || c.prof_kind == PROF_NTT_FWD_ROW) && k.kind == C_NTT && !k.inv &&
+        c.log_n > 12) {
+      hipEvent_t e0 = prof_event(c), e1 = prof_event(c);
+      c.prof_launches++;
+      c.prof_units += k.units;
+      launch_ntt(T, false, (const NttJob*)j, k.n, k.max_y, s, c.prof_kind == PROF_NTT_FWD_ROW ? 1 : 0, e0, e1);
+      continue;
+    }
     const bool prof = c.prof_kind >= 0 && prof_kind_of(k) == c.prof_kind;
     if (prof) {
       hipEvent_t e = prof_event(c);

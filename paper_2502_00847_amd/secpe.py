@@ -294,7 +294,8 @@ class Context:
         self._check(self.lib.secpe_sync(self.h))
 
     # -- measurement -------------------------------------------------------------
-    PROF = dict(ntt_fwd=0, ntt_inv=1, ew=2, modup=3, moddown=4, inner=5, auto=6, spread=7)
+    PROF = dict(ntt_fwd=0, ntt_inv=1, ew=2, modup=3, moddown=4, inner=5, auto=6, spread=7, ntt_fwd_col=8,
+                ntt_fwd_row=9)
 
     def profile_begin(self, kind):
         self._check(self.lib.secpe_profile_begin(self.h, self.PROF[kind] if isinstance(kind, str) else int(kind)))
