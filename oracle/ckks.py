@@ -59,6 +59,9 @@ def _load():
         "orc_rotate": (vp, [vp, vp, i64]),
         "orc_refresh": (vp, [vp, vp, u64, u64]),
         "orc_key_switch": (None, [vp, u64, P(u64), ci, P(u64), P(u64)]),
+        "orc_key_switch_raw": (None, [vp, u64, P(u64), ci, P(u64), P(u64)]),
+        "orc_relin_rescale3": (vp, [vp, P(u64), ci, dbl]),
+        "orc_lincomb": (vp, [vp, vp, dbl, vp, dbl, dbl, ci]),
         "orc_automorph": (None, [vp, ci, P(u64), u64, P(u64)]),
         "orc_galois_elt": (u64, [vp, i64]),
         "orc_sign_coeffs": (None, [P(dbl), P(dbl)]),
@@ -288,6 +291,25 @@ class Oracle:
         u1 = np.zeros_like(d)
         self.lib.orc_key_switch(self.h, int(g), _p(d, C.c_uint64), level, _p(u0, C.c_uint64), _p(u1, C.c_uint64))
         return u0, u1
+
+    def key_switch_raw(self, g, d):
+        """ModUp + inner product only: (acc0, acc1) over Q_level then the special primes."""
+        d = np.ascontiguousarray(d, dtype=np.uint64)
+        level = d.shape[0] - 1
+        shape = (level + 1 + self.n_p, self.n)
+        a0 = np.zeros(shape, np.uint64)
+        a1 = np.zeros(shape, np.uint64)
+        self.lib.orc_key_switch_raw(self.h, int(g), _p(d, C.c_uint64), level, _p(a0, C.c_uint64), _p(a1, C.c_uint64))
+        return a0, a1
+
+    def relin_rescale3(self, d, scale):
+        """Relinearise-and-rescale of a degree-2 ciphertext d[3, level+1, N]."""
+        d = np.ascontiguousarray(d, dtype=np.uint64)
+        return self._wrap(self.lib.orc_relin_rescale3(self.h, _p(d, C.c_uint64), d.shape[1] - 1, float(scale)))
+
+    def lincomb(self, a, va, b, vb, target, rescale=True):
+        return self._wrap(self.lib.orc_lincomb(self.h, a.h, float(va), b.h if b is not None else None, float(vb),
+                                               float(target), int(bool(rescale))))
 
     def eval_odd9(self, x, coef, gain, target):
         coef = np.ascontiguousarray(coef, dtype=np.float64)

@@ -739,25 +739,12 @@ static void rescale_inplace(orc_ctx* c, orc_ct* x) {
   x->scale = x->scale / (double)ql;
 }
 
-/* constant multiply with exact target scale: K = llround(v * T * q_l / s), then rescale;
-   the result is defined to carry scale T */
+/* constant multiply with exact target scale: K = llround(v * T * q_l / s), then
+   rescale; the result is defined to carry scale T */
+static orc_ct* op_lincomb(orc_ctx* c, const orc_ct* a, double va, const orc_ct* b, double vb, double target,
+                          int rescale);
 static orc_ct* op_mul_const(orc_ctx* c, const orc_ct* a, double v, double target) {
-  orc_ct* x = ct_copy(c, a, a->level);
-  double ql = (double)c->mod[a->level];
-  double kf = v * target;
-  kf = kf * ql;
-  kf = kf / a->scale;
-  int64_t K = llround(kf);
-  int n = c->n;
-  for (int p = 0; p < 2; ++p)
-    for (int t = 0; t <= x->level; ++t) {
-      uint64_t q = c->mod[t], k = from_i128(K, q);
-      uint64_t* w = LIMB(x, p, t, n);
-      for (int i = 0; i < n; ++i) w[i] = mmul(w[i], k, q);
-    }
-  rescale_inplace(c, x);
-  x->scale = target;
-  return x;
+  return op_lincomb(c, a, v, NULL, 0.0, target, 1);
 }
 
 /* multiply by the encoded real vector v (nslots values) with exact target scale */
@@ -781,20 +768,16 @@ static orc_ct* op_mul_plain(orc_ctx* c, const orc_ct* a, const double* v, int ns
   return x;
 }
 
-/* hybrid key switch of d (coefficient domain, limbs 0..l) with key k:
-   returns (u0, u1) in R_{Q_l} with u0 + u1 s ~ d s' */
-static void key_switch(orc_ctx* c, const uint64_t* d, int l, const orc_key* k, uint64_t* u0, uint64_t* u1) {
+/* first half of the hybrid key switch of d (coefficient domain, limbs 0..l)
+   with key k: ModUp of every digit and the inner product with the key,
+   returned in the coefficient domain over Q_l u P (limbs 0..l, then the
+   special primes): acc0 + acc1 s = P d s' + small  (mod Q_l P) */
+static void key_switch_raw(orc_ctx* c, const uint64_t* d, int l, const orc_key* k, uint64_t** acc0, uint64_t** acc1) {
   int n = c->n, alpha = c->alpha, n_q = c->n_q, n_p = c->n_p;
   int n_ext = l + 1 + n_p;
   int* ext = (int*)xcalloc(n_ext, sizeof(int));
   for (int i = 0; i <= l; ++i) ext[i] = i;
   for (int i = 0; i < n_p; ++i) ext[l + 1 + i] = n_q + i;
-  uint64_t** acc0 = (uint64_t**)xcalloc(n_ext, sizeof(uint64_t*));
-  uint64_t** acc1 = (uint64_t**)xcalloc(n_ext, sizeof(uint64_t*));
-  for (int e = 0; e < n_ext; ++e) {
-    acc0[e] = (uint64_t*)xcalloc(n, 8);
-    acc1[e] = (uint64_t*)xcalloc(n, 8);
-  }
   uint64_t* limb = (uint64_t*)xcalloc(n, 8);
   int dn = (l + 1 + alpha - 1) / alpha;
   for (int j = 0; j < dn; ++j) {
@@ -839,7 +822,38 @@ static void key_switch(orc_ctx* c, const uint64_t* d, int l, const orc_key* k, u
     ntt_inv(c, ext[e], acc0[e]);
     ntt_inv(c, ext[e], acc1[e]);
   }
-  /* ModDown: (u - Conv_{P->q}([u]_P)) * P^{-1} mod q */
+  free(limb);
+  free(ext);
+  c->counters[CNT_KS]++;
+}
+
+/* z in [0, b) read as its centred representative in (-b/2, b/2), reduced mod q */
+static uint64_t centred_mod(uint64_t z, uint64_t b, uint64_t q) {
+  if (z <= b / 2) return z % q;
+  uint64_t m = (b - z) % q;
+  return m ? q - m : 0;
+}
+
+static uint64_t** alloc_limbs(int count, int n) {
+  uint64_t** a = (uint64_t**)xcalloc(count, sizeof(uint64_t*));
+  for (int e = 0; e < count; ++e) a[e] = (uint64_t*)xcalloc(n, 8);
+  return a;
+}
+static void free_limbs(uint64_t** a, int count) {
+  for (int e = 0; e < count; ++e) free(a[e]);
+  free(a);
+}
+
+/* hybrid key switch of d (coefficient domain, limbs 0..l) with key k:
+   returns (u0, u1) in R_{Q_l} with u0 + u1 s ~ d s' */
+static void key_switch(orc_ctx* c, const uint64_t* d, int l, const orc_key* k, uint64_t* u0, uint64_t* u1) {
+  int n = c->n, n_q = c->n_q, n_p = c->n_p;
+  int n_ext = l + 1 + n_p;
+  uint64_t** acc0 = alloc_limbs(n_ext, n);
+  uint64_t** acc1 = alloc_limbs(n_ext, n);
+  key_switch_raw(c, d, l, k, acc0, acc1);
+  /* ModDown: (u - Conv_{P->q}([u]_P)) * P^{-1} mod q, the conversion taking
+     each [u (P/p)^{-1}]_p centred so the division rounds without bias */
   for (int which = 0; which < 2; ++which) {
     uint64_t** acc = which ? acc1 : acc0;
     uint64_t* out = which ? u1 : u0;
@@ -862,16 +876,15 @@ static void key_switch(orc_ctx* c, const uint64_t* d, int l, const orc_key* k, u
         uint64_t phat = 1;
         for (int k2 = 0; k2 < n_p; ++k2)
           if (k2 != kp) phat = mmul(phat, c->mod[n_q + k2] % q, q);
-        for (int x = 0; x < n; ++x) o[x] = madd(o[x], mmul(y[kp][x] % q, phat, q), q);
+        for (int x = 0; x < n; ++x) o[x] = madd(o[x], mmul(centred_mod(y[kp][x], c->mod[n_q + kp], q), phat, q), q);
       }
       for (int x = 0; x < n; ++x) o[x] = mmul(msub(acc[t][x], o[x], q), pinv, q);
     }
     for (int kp = 0; kp < n_p; ++kp) free(y[kp]);
     free(y);
   }
-  for (int e = 0; e < n_ext; ++e) { free(acc0[e]); free(acc1[e]); }
-  free(acc0); free(acc1); free(limb); free(ext);
-  c->counters[CNT_KS]++;
+  free_limbs(acc0, n_ext);
+  free_limbs(acc1, n_ext);
 }
 
 /* ct x ct: tensor, relinearise (key switch of the s^2 part); caller rescales */
@@ -918,9 +931,176 @@ static orc_ct* op_mul_relin(orc_ctx* c, const orc_ct* a_in, const orc_ct* b_in) 
   return x;
 }
 
+/* a degree-2 ciphertext (d0, d1, d2), coefficient domain, decrypting as d0 + d1 s + d2 s^2 */
+typedef struct {
+  int level;
+  double scale;
+  uint64_t* c[3];
+} orc_ct3;
+
+static orc_ct3* ct3_new(orc_ctx* c, int level, double scale) {
+  orc_ct3* x = (orc_ct3*)xcalloc(1, sizeof(orc_ct3));
+  x->level = level;
+  x->scale = scale;
+  for (int p = 0; p < 3; ++p) x->c[p] = (uint64_t*)xcalloc((size_t)(level + 1) * c->n, 8);
+  return x;
+}
+static void ct3_free(orc_ct3* x) {
+  if (!x) return;
+  for (int p = 0; p < 3; ++p) free(x->c[p]);
+  free(x);
+}
+
+/* tensor product: (a0 + a1 s)(b0 + b1 s) = a0 b0 + (a0 b1 + a1 b0) s + a1 b1 s^2 */
+static orc_ct3* op_tensor(orc_ctx* c, const orc_ct* a, const orc_ct* b) {
+  int l = a->level < b->level ? a->level : b->level;
+  int n = c->n;
+  orc_ct3* x = ct3_new(c, l, a->scale * b->scale);
+  uint64_t* t = (uint64_t*)xcalloc(n, 8);
+  for (int i = 0; i <= l; ++i) {
+    uint64_t q = c->mod[i];
+    ring_mul(c, i, LIMB(a, 0, i, n), LIMB(b, 0, i, n), x->c[0] + (size_t)i * n);
+    ring_mul(c, i, LIMB(a, 0, i, n), LIMB(b, 1, i, n), x->c[1] + (size_t)i * n);
+    ring_mul(c, i, LIMB(a, 1, i, n), LIMB(b, 0, i, n), t);
+    uint64_t* d1 = x->c[1] + (size_t)i * n;
+    for (int k = 0; k < n; ++k) d1[k] = madd(d1[k], t[k], q);
+    ring_mul(c, i, LIMB(a, 1, i, n), LIMB(b, 1, i, n), x->c[2] + (size_t)i * n);
+  }
+  free(t);
+  return x;
+}
+
+/* x += y (degree-2 + degree-2); levels must match */
+static void op_add3_inplace(orc_ctx* c, orc_ct3* x, const orc_ct3* y) {
+  check_scales(x->scale, y->scale);
+  if (x->level != y->level) die("op_add3: level mismatch");
+  for (int p = 0; p < 3; ++p)
+    for (int i = 0; i <= x->level; ++i) {
+      uint64_t q = c->mod[i];
+      uint64_t* u = x->c[p] + (size_t)i * c->n;
+      const uint64_t* v = y->c[p] + (size_t)i * c->n;
+      for (int k = 0; k < c->n; ++k) u[k] = madd(u[k], v[k], q);
+    }
+}
+
+/* x += a (a degree-1 ciphertext at x's level or above) */
+static void op_add3_ct_inplace(orc_ctx* c, orc_ct3* x, const orc_ct* a) {
+  check_scales(x->scale, a->scale);
+  if (a->level < x->level) die("op_add3_ct: level");
+  for (int p = 0; p < 2; ++p)
+    for (int i = 0; i <= x->level; ++i) {
+      uint64_t q = c->mod[i];
+      uint64_t* u = x->c[p] + (size_t)i * c->n;
+      const uint64_t* v = LIMB(a, p, i, c->n);
+      for (int k = 0; k < c->n; ++k) u[k] = madd(u[k], v[k], q);
+    }
+}
+
+/* Relinearise and rescale in one division.  With the key-switch accumulator
+   acc of d2 over Q_l u P (acc0 + acc1 s = P d2 s^2 + small), form
+   y_w = P d_w + acc_w over Q_l u P and divide exactly by P q_l:
+     out_w = (y_w - Conv_{B -> Q_{l-1}}([y_w]_B)) (P q_l)^{-1},  B = {q_l} u P,
+   Conv being the approximate base conversion with centred digits (as in
+   ModDown), so out_w = round(y_w / (P q_l)) + v with |v| <= |B| / 2.  The
+   result is (d0 + d1 s + d2 s^2) / q_l up to small unbiased rounding: one
+   level down. */
+static orc_ct* op_relin_rescale(orc_ctx* c, const orc_ct3* x) {
+  int l = x->level, n = c->n, n_q = c->n_q, n_p = c->n_p;
+  if (l < 1) die("relin_rescale at level 0");
+  orc_key* rk = find_key(c, 0);
+  if (!rk) die("no relinearisation key");
+  int n_ext = l + 1 + n_p;
+  uint64_t** acc[2] = {alloc_limbs(n_ext, n), alloc_limbs(n_ext, n)};
+  key_switch_raw(c, x->c[2], l, rk, acc[0], acc[1]);
+  /* base B: q_l then the special primes; b_idx = absolute prime index, e_idx = extended-basis index */
+  int nb = n_p + 1;
+  int* b_idx = (int*)xcalloc(nb, sizeof(int));
+  int* e_idx = (int*)xcalloc(nb, sizeof(int));
+  b_idx[0] = l;
+  e_idx[0] = l;
+  for (int k = 0; k < n_p; ++k) { b_idx[1 + k] = n_q + k; e_idx[1 + k] = l + 1 + k; }
+  orc_ct* out = ct_new(c, l - 1, x->scale / (double)c->mod[l]);
+  uint64_t* yb = (uint64_t*)xcalloc(n, 8);
+  for (int w = 0; w < 2; ++w) {
+    /* y over Q_l u P: P d_w + acc_w on the chain primes, acc_w on the special primes */
+    for (int t = 0; t <= l; ++t) {
+      uint64_t q = c->mod[t], pm = p_mod(c, t);
+      const uint64_t* d = x->c[w] + (size_t)t * n;
+      for (int k = 0; k < n; ++k) acc[w][t][k] = madd(mmul(pm, d[k], q), acc[w][t][k], q);
+    }
+    /* z_b = [y_b (B/b)^{-1}]_b */
+    uint64_t** zb = alloc_limbs(nb, n);
+    for (int i = 0; i < nb; ++i) {
+      uint64_t qb = c->mod[b_idx[i]], bhat = 1;
+      for (int i2 = 0; i2 < nb; ++i2)
+        if (i2 != i) bhat = mmul(bhat, c->mod[b_idx[i2]] % qb, qb);
+      uint64_t inv = minv(bhat, qb);
+      for (int k = 0; k < n; ++k) zb[i][k] = mmul(acc[w][e_idx[i]][k], inv, qb);
+    }
+    for (int t = 0; t < l; ++t) {
+      uint64_t q = c->mod[t];
+      uint64_t Bq = 1;
+      for (int i = 0; i < nb; ++i) Bq = mmul(Bq, c->mod[b_idx[i]] % q, q);
+      uint64_t binv = minv(Bq, q);
+      for (int k = 0; k < n; ++k) yb[k] = 0;
+      for (int i = 0; i < nb; ++i) {
+        uint64_t bhat = 1; /* (B/b_i) mod q */
+        for (int i2 = 0; i2 < nb; ++i2)
+          if (i2 != i) bhat = mmul(bhat, c->mod[b_idx[i2]] % q, q);
+        for (int k = 0; k < n; ++k) yb[k] = madd(yb[k], mmul(centred_mod(zb[i][k], c->mod[b_idx[i]], q), bhat, q), q);
+      }
+      uint64_t* o = LIMB(out, w, t, n);
+      for (int k = 0; k < n; ++k) o[k] = mmul(msub(acc[w][t][k], yb[k], q), binv, q);
+    }
+    free_limbs(zb, nb);
+  }
+  free(yb);
+  free(b_idx);
+  free(e_idx);
+  free_limbs(acc[0], n_ext);
+  free_limbs(acc[1], n_ext);
+  c->counters[CNT_RELIN]++;
+  return out;
+}
+
 static orc_ct* op_mul_relin_rescale(orc_ctx* c, const orc_ct* a, const orc_ct* b) {
-  orc_ct* x = op_mul_relin(c, a, b);
-  rescale_inplace(c, x);
+  orc_ct3* t = op_tensor(c, a, b);
+  orc_ct* x = op_relin_rescale(c, t);
+  ct3_free(t);
+  return x;
+}
+
+/* integer constant for value v taking scale s to T: llround(v T q / s) when a
+   rescale by q follows, llround(v T / s) when none does */
+static int64_t const_for(double v, double target, double q, double s, int rescale) {
+  double k = v * target;
+  if (rescale) k = k * q;
+  k = k / s;
+  if (!(fabs(k) < 9.2e18)) die("constant does not fit 64 bits");
+  return llround(k);
+}
+
+/* K_a a + K_b b with integer constants chosen so the result carries scale T:
+   rescaled once (rescale = 1) or left at the inputs' level (rescale = 0).
+   b may be NULL; a and b share the level. */
+static orc_ct* op_lincomb(orc_ctx* c, const orc_ct* a, double va, const orc_ct* b, double vb, double target,
+                          int rescale) {
+  int l = a->level, n = c->n;
+  if (b && b->level != l) die("op_lincomb: level mismatch");
+  double ql = (double)c->mod[l];
+  int64_t Ka = const_for(va, target, ql, a->scale, rescale);
+  int64_t Kb = b ? const_for(vb, target, ql, b->scale, rescale) : 0;
+  orc_ct* x = ct_new(c, l, target);
+  for (int p = 0; p < 2; ++p)
+    for (int t = 0; t <= l; ++t) {
+      uint64_t q = c->mod[t], kA = from_i128(Ka, q), kB = from_i128(Kb, q);
+      const uint64_t* u = LIMB(a, p, t, n);
+      const uint64_t* v = b ? LIMB(b, p, t, n) : NULL;
+      uint64_t* w = LIMB(x, p, t, n);
+      for (int k = 0; k < n; ++k) w[k] = b ? madd(mmul(u[k], kA, q), mmul(v[k], kB, q), q) : mmul(u[k], kA, q);
+    }
+  if (rescale) rescale_inplace(c, x);
+  x->scale = target;
   return x;
 }
 
@@ -995,6 +1175,34 @@ ORC_API void orc_key_switch(void* h, uint64_t g, const uint64_t* d, int level, u
   if (!k) die("missing key");
   key_switch(c, d, level, k, u0, u1);
 }
+/* acc0, acc1: (level + 1 + n_p) x N, chain limbs then special limbs */
+ORC_API void orc_key_switch_raw(void* h, uint64_t g, const uint64_t* d, int level, uint64_t* acc0, uint64_t* acc1) {
+  orc_ctx* c = (orc_ctx*)h;
+  orc_key* k = find_key(c, g);
+  if (!k) die("missing key");
+  int n_ext = level + 1 + c->n_p;
+  uint64_t** a0 = alloc_limbs(n_ext, c->n);
+  uint64_t** a1 = alloc_limbs(n_ext, c->n);
+  key_switch_raw(c, d, level, k, a0, a1);
+  for (int e = 0; e < n_ext; ++e) {
+    memcpy(acc0 + (size_t)e * c->n, a0[e], 8 * (size_t)c->n);
+    memcpy(acc1 + (size_t)e * c->n, a1[e], 8 * (size_t)c->n);
+  }
+  free_limbs(a0, n_ext);
+  free_limbs(a1, n_ext);
+}
+/* d: 3 x (level + 1) x N, a degree-2 ciphertext in the coefficient domain */
+ORC_API void* orc_relin_rescale3(void* h, const uint64_t* d, int level, double scale) {
+  orc_ctx* c = (orc_ctx*)h;
+  orc_ct3* x = ct3_new(c, level, scale);
+  for (int p = 0; p < 3; ++p) memcpy(x->c[p], d + (size_t)p * (level + 1) * c->n, 8 * (size_t)(level + 1) * c->n);
+  orc_ct* y = op_relin_rescale(c, x);
+  ct3_free(x);
+  return y;
+}
+ORC_API void* orc_lincomb(void* h, const void* a, double va, const void* b, double vb, double target, int rescale) {
+  return op_lincomb((orc_ctx*)h, (const orc_ct*)a, va, (const orc_ct*)b, vb, target, rescale);
+}
 ORC_API void orc_automorph(void* h, int t, const uint64_t* in, uint64_t g, uint64_t* out) {
   orc_ctx* c = (orc_ctx*)h;
   automorph_mod(c, in, g, c->mod[t], out);
@@ -1015,9 +1223,13 @@ ORC_API void orc_sign_coeffs(double* f, double* g) {
   memcpy(g, SIGN_G, sizeof(SIGN_G));
 }
 
-/* p(x) = (c1 x + c3 x^3) + x^4 (c5 x + c7 x^3) + x^8 (c9 x), depth 4, six
-   ciphertext products. Output at level l-4 with scale 'target' (up to the FP64
-   rounding of the scale bookkeeping). c[] holds c1,c3,c5,c7,c9, times 'gain'. */
+/* p(x) = (c1 x + c3 x^3) + x^4 (c5 x + c7 x^3) + x^8 (c9 x): baby steps x^2,
+   x^3, x^4, giant step x^8; B and C as constant combinations rescaled once; A
+   as a combination that is not rescaled, at the scale of the products;
+   x^4 B + x^8 C + A summed as degree-2 ciphertexts and relinearised once.
+   Depth 4, five relinearisations.  Output at level l-4 with scale 'target' (up
+   to the FP64 rounding of the scale bookkeeping).  c[] = c1, c3, c5, c7, c9,
+   times 'gain'. */
 static orc_ct* eval_odd9(orc_ctx* c, const orc_ct* x, const double* coef, double gain, double target) {
   int l = x->level;
   if (l - 4 < c->min_level) die("eval_odd9: not enough levels");
@@ -1028,30 +1240,25 @@ static orc_ct* eval_odd9(orc_ctx* c, const orc_ct* x, const double* coef, double
   orc_ct* x4 = op_mul_relin_rescale(c, x2, x2);               /* l-2 */
   orc_ct* x8 = op_mul_relin_rescale(c, x4, x4);               /* l-3 */
   orc_ct* xl2 = ct_copy(c, x, l - 2);
+  orc_ct* xl3 = ct_copy(c, x, l - 3);
+  orc_ct* x3l3 = ct_copy(c, x3, l - 3);
   double q3 = (double)c->mod[l - 3];
-  /* A = c1 x + c3 x^3 at scale target */
-  orc_ct* a3 = op_mul_const(c, x3, k3, target);
-  orc_ct* a1 = op_mul_const(c, xl2, k1, target);
-  orc_ct* A = op_add(c, a1, a3, 0);                            /* l-3 */
-  /* B = c5 x + c7 x^3 at scale target * q_{l-3} / s(x^4) */
-  double sb = target * q3;
-  sb = sb / x4->scale;
-  orc_ct* b3 = op_mul_const(c, x3, k7, sb);
-  orc_ct* b1 = op_mul_const(c, xl2, k5, sb);
-  orc_ct* B = op_add(c, b1, b3, 0);                            /* l-3 */
+  /* before the last rescale every term carries target * q_{l-3} */
+  double ta = target * q3;
+  double sb = ta / x4->scale;
+  double sc = ta / x8->scale;
+  orc_ct* A = op_lincomb(c, xl3, k1, x3l3, k3, ta, 0);        /* l-3, not rescaled */
+  orc_ct* B = op_lincomb(c, xl2, k5, x3, k7, sb, 1);          /* l-3 */
+  orc_ct* Cc = op_lincomb(c, xl2, k9, NULL, 0.0, sc, 1);      /* l-3 */
   orc_ct* x4l = ct_copy(c, x4, l - 3);
-  orc_ct* x4B = op_mul_relin_rescale(c, x4l, B);               /* l-4 */
-  /* C = c9 x at scale target * q_{l-3} / s(x^8) */
-  double sc = target * q3;
-  sc = sc / x8->scale;
-  orc_ct* Cc = op_mul_const(c, xl2, k9, sc);                   /* l-3 */
-  orc_ct* x8C = op_mul_relin_rescale(c, x8, Cc);               /* l-4 */
-  orc_ct* Al = ct_copy(c, A, l - 4);
-  orc_ct* s1 = op_add(c, Al, x4B, 0);
-  orc_ct* p = op_add(c, s1, x8C, 0);
-  ct_free(x2); ct_free(xl1); ct_free(x3); ct_free(x4); ct_free(x8); ct_free(xl2);
-  ct_free(a3); ct_free(a1); ct_free(A); ct_free(b3); ct_free(b1); ct_free(B);
-  ct_free(x4l); ct_free(x4B); ct_free(Cc); ct_free(x8C); ct_free(Al); ct_free(s1);
+  orc_ct3* t = op_tensor(c, x4l, B);
+  orc_ct3* u = op_tensor(c, x8, Cc);
+  op_add3_inplace(c, t, u);
+  op_add3_ct_inplace(c, t, A);
+  orc_ct* p = op_relin_rescale(c, t);                         /* l-4 */
+  ct_free(x2); ct_free(xl1); ct_free(x3); ct_free(x4); ct_free(x8); ct_free(xl2); ct_free(xl3); ct_free(x3l3);
+  ct_free(A); ct_free(B); ct_free(Cc); ct_free(x4l);
+  ct3_free(t); ct3_free(u);
   c->counters[CNT_POLY]++;
   return p;
 }
@@ -1124,11 +1331,14 @@ static orc_ct* op_max(orc_ctx* c, const orc_ct* a, const orc_ct* b, refresher* r
   if (ls_real != ls) die("op_max: level plan mismatch");
   orc_ct* dl = ct_copy(c, d, lp);
   orc_ct* sgl = ct_copy(c, sg, lp);
-  orc_ct* prod = op_mul_relin_rescale(c, dl, sgl);
+  /* d * Sign/2 as a degree-2 ciphertext, (a+b)/2 added at the same scale before
+     the one relinearise-and-rescale */
+  orc_ct3* prod = op_tensor(c, dl, sgl);
   orc_ct* sl = ct_copy(c, s, lp);
-  orc_ct* half = op_mul_const(c, sl, 0.5, prod->scale);
-  orc_ct* out = op_add(c, half, prod, 0);
-  ct_free(d); ct_free(s); ct_free(sg); ct_free(dl); ct_free(sgl); ct_free(prod); ct_free(sl); ct_free(half);
+  orc_ct* half = op_lincomb(c, sl, 0.5, NULL, 0.0, prod->scale, 0);
+  op_add3_ct_inplace(c, prod, half);
+  orc_ct* out = op_relin_rescale(c, prod);
+  ct_free(d); ct_free(s); ct_free(sg); ct_free(dl); ct_free(sgl); ct3_free(prod); ct_free(sl); ct_free(half);
   c->counters[CNT_MAX]++;
   return out;
 }
