@@ -215,6 +215,12 @@ int secpe_op_add(secpe_ctx* ctx, const secpe_ct* a, const secpe_ct* b, secpe_ct*
 int secpe_op_sub(secpe_ctx* ctx, const secpe_ct* a, const secpe_ct* b, secpe_ct* out);
 int secpe_op_add_const(secpe_ctx* ctx, const secpe_ct* a, double v, secpe_ct* out);
 int secpe_op_mul_const(secpe_ctx* ctx, const secpe_ct* a, double v, double target, void* ws, size_t ws_bytes, secpe_ct* out);
+/* K_a a + K_b b (b may be NULL) with integer constants K = llround(v T q_l / s)
+   when rescale != 0 (then one rescale), K = llround(v T / s) when rescale == 0
+   (level kept); the result carries scale T exactly.  Sec. 2.2 operations;
+   used for the constant terms of the Sign polynomials (Sec. 4.3). */
+int secpe_op_lincomb(secpe_ctx* ctx, const secpe_ct* a, double va, const secpe_ct* b, double vb, double target,
+                     int rescale, void* ws, size_t ws_bytes, secpe_ct* out);
 int secpe_op_mul_plain(secpe_ctx* ctx, const secpe_ct* a, const double* v, int nslots, double target, void* ws,
                        size_t ws_bytes, secpe_ct* out);
 int secpe_op_rescale(secpe_ctx* ctx, const secpe_ct* a, void* ws, size_t ws_bytes, secpe_ct* out);

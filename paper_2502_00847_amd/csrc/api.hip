@@ -696,6 +696,19 @@ extern "C" int secpe_op_mul_const(secpe_ctx* x, const secpe_ct* a, double v, dou
   CHECK_CTX(x);
   return op_to_out(x, ws, wsb, out, [&](Builder& b) { return b.mul_const({to_ct(a)}, {v}, {target}); });
 }
+extern "C" int secpe_op_lincomb(secpe_ctx* x, const secpe_ct* a, double va, const secpe_ct* b2, double vb,
+                                double target, int rescale, void* ws, size_t wsb, secpe_ct* out) {
+  CHECK_CTX(x);
+  if (!a) return SECPE_EINVAL;
+  return op_to_out(x, ws, wsb, out, [&](Builder& b) {
+    Builder::LinItem t{};
+    t.a = to_ct(a);
+    t.va = va;
+    if (b2) { t.b = to_ct(b2); t.vb = vb; t.has_b = true; }
+    t.target = target;
+    return b.lincomb({t}, rescale != 0);
+  });
+}
 extern "C" int secpe_op_mul_plain(secpe_ctx* x, const secpe_ct* a, const double* v, int nslots, double target, void* ws,
                                   size_t wsb, secpe_ct* out) {
   CHECK_CTX(x);

@@ -211,26 +211,36 @@ static void run_step(Builder& b, int kind, std::vector<QState*>& qs) {
       break;
     }
     case S_MAXPOST: {  // Max = (a+b)/2 + (a-b)/2 * Sign(a-b)   (Eq. 6)
+      // d * Sign/2 as a degree-2 ciphertext with (a+b)/2 added at the same
+      // scale, then one relinearise-and-rescale
       auto lower = [](CT x, int l) { x.level = l; x.slot = -1; return x; };
-      for (QState* s : qs) pr.push_back({lower(s->d, s->lp), lower(s->x, s->lp)});
-      std::vector<CT> prod = b.mul_relin(pr, true);
-      if (b.err_code) return;
-      std::vector<CT> in;
-      std::vector<double> v, tg;
-      for (size_t i = 0; i < n; ++i) {
-        in.push_back(lower(qs[i]->s, qs[i]->lp));
-        v.push_back(0.5);
-        tg.push_back(prod[i].scale);
+      std::vector<Builder::LinItem> li;
+      for (QState* s : qs) {
+        Builder::LinItem t{};
+        t.a = lower(s->s, s->lp);
+        t.va = 0.5;
+        t.target = s->d.scale * s->x.scale;
+        li.push_back(t);
       }
-      std::vector<CT> half = b.mul_const(in, v, tg);
+      std::vector<CT> half = b.lincomb(li, false);
       if (b.err_code) return;
-      pr.clear();
-      for (size_t i = 0; i < n; ++i) pr.push_back({half[i], prod[i]});
-      std::vector<CT> out = b.add(pr, false);
+      const size_t mark = b.scratch_mark();
+      std::vector<Builder::TensorItem> ti;
+      for (size_t i = 0; i < n; ++i) {
+        Builder::TensorItem t{};
+        t.a = lower(qs[i]->d, qs[i]->lp);
+        t.b = lower(qs[i]->x, qs[i]->lp);
+        t.f = half[i];
+        t.has_f = true;
+        ti.push_back(t);
+      }
+      std::vector<Builder::Deg2> d2 = b.tensor2(ti);
       if (b.err_code) return;
+      std::vector<CT> out = b.relin_rescale(d2);
+      if (b.err_code) return;
+      b.scratch_release(mark);
       for (size_t i = 0; i < n; ++i) {
         QState* s = qs[i];
-        b.free_ct(prod[i]);
         b.free_ct(half[i]);
         free_owned(b, s->d);
         free_owned(b, s->s);

@@ -46,6 +46,14 @@ enum EwOp : int {
   EW_KEYB = 10,      // o0 = e - a s + k[l] s'   with a1 = e, b0 = a, b1 = s, c0 = s'
   EW_MUL = 11,       // o0 = a0 * b0 (single polynomial)
   EW_COPY = 12,      // o0 = a0, o1 = a1
+  // degree-2 sum of up to two tensor products plus a degree-1 addend:
+  //   o0 = a0 b0 + c0 e0 + f0,  o1 = a0 b1 + a1 b0 + c0 e1 + c1 e0 + f1,  o2 = a1 b1 + c1 e1
+  // (c/e and f optional)
+  EW_TENSOR2 = 13,
+  // merged relinearise + rescale, chain limbs: o_i = (k2[l] a_i + b_i - c_i) k[l]
+  //   (a = d_i, b = key-switch accumulator, c = its base conversion, k2 = P mod q, k = (P q_top)^-1)
+  EW_RRCOMB = 14,
+  EW_LIN2 = 15,      // o_i = a_i k[l] + b_i k2[l]   (b optional)
 };
 
 struct EwJob {
@@ -58,7 +66,12 @@ struct EwJob {
   const double* b1;
   const double* c0;
   const double* c1;
+  const double* e0;
+  const double* e1;
+  const double* f0;
+  const double* f1;
   const double* k;   // per-limb constants (canonical residues) or null
+  const double* k2;  // second per-limb constant table or null
   int n_limbs, n_chain;
   int op, pad;
 };
@@ -73,21 +86,28 @@ struct ModUpJob {
   int digit_lo, digit_hi, n_chain, n_ext;
 };
 
-// Conv_{P->Q}: src = special limbs (coefficient domain) -> dst chain limbs 0..n_chain-1
+// Conv_{B->Q} with centred digits: src = the limbs of B (coefficient domain) ->
+// dst chain limbs 0..n_chain-1.  B is the special primes (first_prime < 0) or
+// prime first_prime followed by the special primes.
 struct ModDownJob {
-  const double* src;    // [alpha][N]
+  const double* src;    // [|B|][N]
   double* dst;          // [n_chain][N]
-  const double* cinv;   // [alpha] (P/p_k)^-1 mod p_k
-  const double* chat;   // [n_chain][alpha] (P/p_k) mod q_i
-  int n_chain, pad;
+  const double* cinv;   // [|B|] (B/b)^-1 mod b
+  const double* chat;   // [n_chain][|B|] (B/b) mod q_i
+  int n_chain, first_prime;
 };
 
 // Inner product with a switching key: acc_w[t] = sum_j x_j[t] * key_j[w][t]
+// When top0 is set, limb n_chain-1 of acc_w also gets pmq[n_chain-1] * top_w
+// (the top limb of P d_w for the merged relinearise + rescale).
 struct InnerJob {
   const double* d;      // NTT-domain input polynomial (chain limbs 0..level)
   const double* ext;    // [dnum][n_ext][N] ModUp outputs, NTT domain
   const double* key;    // [dnum_top][2][n_mod][N]
   double* acc;          // [2][n_ext][N]
+  const double* top0;   // optional [n_chain][N], NTT domain
+  const double* top1;
+  const double* pmq;    // [n_q] P mod q_t
   int n_chain, n_ext, n_digits, alpha;
 };
 

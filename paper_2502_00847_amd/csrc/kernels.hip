@@ -519,6 +519,59 @@ __global__ __launch_bounds__(256) void k_ew(const EwJob* __restrict__ jobs, DevT
         }
         break;
       }
+      case EW_TENSOR2: {
+        const double2 a0 = ld2(J.a0, o), a1 = ld2(J.a1, o), b0 = ld2(J.b0, o), b1 = ld2(J.b1, o);
+        double r0x = mul_mod(a0.x, b0.x, m), r0y = mul_mod(a0.y, b0.y, m);
+        double r1x = mul_mod(a0.x, b1.x, m) + mul_mod(a1.x, b0.x, m);
+        double r1y = mul_mod(a0.y, b1.y, m) + mul_mod(a1.y, b0.y, m);
+        double r2x = mul_mod(a1.x, b1.x, m), r2y = mul_mod(a1.y, b1.y, m);
+        if (J.c0) {
+          const double2 c0 = ld2(J.c0, o), c1 = ld2(J.c1, o), e0 = ld2(J.e0, o), e1 = ld2(J.e1, o);
+          r0x += mul_mod(c0.x, e0.x, m);
+          r0y += mul_mod(c0.y, e0.y, m);
+          r1x = red(r1x, m) + mul_mod(c0.x, e1.x, m) + mul_mod(c1.x, e0.x, m);
+          r1y = red(r1y, m) + mul_mod(c0.y, e1.y, m) + mul_mod(c1.y, e0.y, m);
+          r2x += mul_mod(c1.x, e1.x, m);
+          r2y += mul_mod(c1.y, e1.y, m);
+        }
+        if (J.f0) {
+          const double2 f0 = ld2(J.f0, o), f1 = ld2(J.f1, o);
+          r0x += f0.x;
+          r0y += f0.y;
+          r1x = red(r1x, m) + f1.x;
+          r1y = red(r1y, m) + f1.y;
+        }
+        st2(J.o0, o, canon(r0x, m), canon(r0y, m));
+        st2(J.o1, o, canon(r1x, m), canon(r1y, m));
+        st2(J.o2, o, canon(r2x, m), canon(r2y, m));
+        break;
+      }
+      case EW_RRCOMB: {
+        const double k2 = KPTR(J.k2)[l];
+        const double2 a0 = ld2(J.a0, o), b0 = ld2(J.b0, o), c0 = ld2(J.c0, o);
+        const double2 a1 = ld2(J.a1, o), b1 = ld2(J.b1, o), c1 = ld2(J.c1, o);
+        st2(J.o0, o, canon(mul_mod(red(mul_mod(a0.x, k2, m) + (b0.x - c0.x), m), kk, m), m),
+            canon(mul_mod(red(mul_mod(a0.y, k2, m) + (b0.y - c0.y), m), kk, m), m));
+        st2(J.o1, o, canon(mul_mod(red(mul_mod(a1.x, k2, m) + (b1.x - c1.x), m), kk, m), m),
+            canon(mul_mod(red(mul_mod(a1.y, k2, m) + (b1.y - c1.y), m), kk, m), m));
+        break;
+      }
+      case EW_LIN2: {
+        const double2 a0 = ld2(J.a0, o), a1 = ld2(J.a1, o);
+        double r0x = mul_mod(a0.x, kk, m), r0y = mul_mod(a0.y, kk, m);
+        double r1x = mul_mod(a1.x, kk, m), r1y = mul_mod(a1.y, kk, m);
+        if (J.b0) {
+          const double k2 = KPTR(J.k2)[l];
+          const double2 b0 = ld2(J.b0, o), b1 = ld2(J.b1, o);
+          r0x += mul_mod(b0.x, k2, m);
+          r0y += mul_mod(b0.y, k2, m);
+          r1x += mul_mod(b1.x, k2, m);
+          r1y += mul_mod(b1.y, k2, m);
+        }
+        st2(J.o0, o, canon(r0x, m), canon(r0y, m));
+        st2(J.o1, o, canon(r1x, m), canon(r1y, m));
+        break;
+      }
       default:
         break;
     }
@@ -570,23 +623,27 @@ __global__ __launch_bounds__(256) void k_moddown_conv(const ModDownJob* __restri
   const int N = 1 << T.log_n;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N) return;
-  const int alpha = T.n_p;
-  double y[MAX_DIGIT];
+  const int extra = J.first_prime >= 0 ? 1 : 0;
+  const int nb = T.n_p + extra;
+  // digits [x_b (B/b)^-1]_b taken centred, in (-b/2, b/2), so the conversion
+  // overshoots by a signed multiple of B and the division rounds without bias
+  double y[MAX_DIGIT + 1];
 #pragma unroll
-  for (int i = 0; i < MAX_DIGIT; ++i) {
-    if (i < alpha) {
-      const int pr = T.n_q + i;
+  for (int i = 0; i < MAX_DIGIT + 1; ++i) {
+    if (i < nb) {
+      const int pr = i < extra ? J.first_prime : T.n_q + i - extra;
       const Mod mi{KPTR(T.mod)[pr], KPTR(T.minv)[pr]};
-      y[i] = canon(mul_mod(CGPTR(J.src)[(size_t)i * N + k], KPTR(J.cinv)[i], mi), mi);
+      const double z = canon(mul_mod(CGPTR(J.src)[(size_t)i * N + k], KPTR(J.cinv)[i], mi), mi);
+      y[i] = 2.0 * z > mi.p ? z - mi.p : z;
     }
   }
   for (int t = 0; t < J.n_chain; ++t) {
     const Mod mt{KPTR(T.mod)[t], KPTR(T.minv)[t]};
-    kdbl* ch = KPTR(J.chat) + (size_t)t * alpha;
+    kdbl* ch = KPTR(J.chat) + (size_t)t * nb;
     double acc = 0.0;
 #pragma unroll
-    for (int i = 0; i < MAX_DIGIT; ++i) {
-      if (i < alpha) {
+    for (int i = 0; i < MAX_DIGIT + 1; ++i) {
+      if (i < nb) {
         acc += mul_mod(y[i], ch[i], mt);
         if (i & 1) acc = red(acc, mt);
       }
@@ -620,6 +677,14 @@ __global__ __launch_bounds__(256) void k_inner(const InnerJob* __restrict__ jobs
       if (j & 1) {
         a0x = red(a0x, m); a0y = red(a0y, m); a1x = red(a1x, m); a1y = red(a1y, m);
       }
+    }
+    if (J.top0 && t == J.n_chain - 1) {
+      const double pm = KPTR(J.pmq)[t];
+      const double2 u0 = ld2(J.top0, (size_t)t * N + k), u1 = ld2(J.top1, (size_t)t * N + k);
+      a0x = red(a0x, m) + mul_mod(u0.x, pm, m);
+      a0y = red(a0y, m) + mul_mod(u0.y, pm, m);
+      a1x = red(a1x, m) + mul_mod(u1.x, pm, m);
+      a1y = red(a1y, m) + mul_mod(u1.y, pm, m);
     }
     st2(J.acc, (size_t)t * N + k, canon(a0x, m), canon(a0y, m));
     st2(J.acc, ((size_t)J.n_ext + t) * N + k, canon(a1x, m), canon(a1y, m));

@@ -74,6 +74,10 @@ struct Ctx {
   const double* md_pinv = nullptr;   // [n_q] P^-1 mod q_t
   const double* p_mod_q = nullptr;   // [n_q] P mod q_t
   const double* rs_tab = nullptr;    // [n_q][n_q] q_l^-1 mod q_i at [l][i]
+  // merged relinearise + rescale at level l over B = {q_l} u P
+  const double* rr_cinv = nullptr;   // [n_q][alpha+1] (B/b)^-1 mod b
+  const double* rr_chat = nullptr;   // [n_q][n_q][alpha+1] (B/b) mod q_t
+  const double* rr_inv = nullptr;    // [n_q][n_q] (P q_l)^-1 mod q_t
   const double* crt_tab = nullptr;   // [n_q][2]
   double q0inv_q1 = 0.0;
   // keys
@@ -199,8 +203,37 @@ class Builder {
     const double* base1;
     double* out0;
     double* out1;
+    const double* top0;   // merged relinearise + rescale: d0, d1 (else null)
+    const double* top1;
   };
+  struct KsTmp {
+    double* dcoef;
+    double* ext;
+    double* acc;
+    int n_ext;
+  };
+  // degree-2 ciphertext d0 + d1 s + d2 s^2 in scratch, NTT domain
+  struct Deg2 {
+    double* d0;
+    double* d1;
+    double* d2;
+    int level;
+    double scale;
+  };
+  struct TensorItem {
+    CT a, b, c, e, f;
+    bool has_ce, has_f;
+  };
+  struct LinItem {
+    CT a, b;
+    double va, vb, target;
+    bool has_b;
+  };
+  void ks_front(const std::vector<KsItem>& items, std::vector<KsTmp>& tmp);
   void key_switch(const std::vector<KsItem>& items);
+  std::vector<Deg2> tensor2(const std::vector<TensorItem>& v);
+  std::vector<CT> relin_rescale(const std::vector<Deg2>& xs);
+  std::vector<CT> lincomb(const std::vector<LinItem>& v, bool do_rescale);
   void rescale(std::vector<CT>& in_out);                    // in place
   std::vector<CT> mul_relin(const std::vector<std::pair<CT, CT>>& ab, bool do_rescale);
   std::vector<CT> rotate(const std::vector<CT>& in, const std::vector<int64_t>& steps);

@@ -188,6 +188,32 @@ int build_context(Ctx& c, int log_n, int n_q, int q_bits, int n_p, int p_bits, i
       h[o_mdh + (size_t)t * c.alpha + k] = (double)ph;
     }
   }
+  // merged relinearise + rescale at level l: base B = {q_l} u P
+  const int nb = c.alpha + 1;
+  size_t o_rrc = alloc((size_t)n_q * nb), o_rrh = alloc((size_t)n_q * n_q * nb), o_rri = alloc((size_t)n_q * n_q);
+  for (int l = 1; l < n_q; ++l) {
+    std::vector<int> bp(1, l);
+    for (int k = 0; k < c.alpha; ++k) bp.push_back(n_q + k);
+    for (int i = 0; i < nb; ++i) {
+      const uint64_t b = c.mod[bp[i]];
+      uint64_t bh = 1;
+      for (int i2 = 0; i2 < nb; ++i2)
+        if (i2 != i) bh = hmul(bh, c.mod[bp[i2]] % b, b);
+      h[o_rrc + (size_t)l * nb + i] = (double)hinv(bh, b);
+    }
+    for (int t = 0; t < l; ++t) {
+      const uint64_t q = c.mod[t];
+      uint64_t all = 1;
+      for (int i = 0; i < nb; ++i) {
+        all = hmul(all, c.mod[bp[i]] % q, q);
+        uint64_t bh = 1;
+        for (int i2 = 0; i2 < nb; ++i2)
+          if (i2 != i) bh = hmul(bh, c.mod[bp[i2]] % q, q);
+        h[o_rrh + ((size_t)l * n_q + t) * nb + i] = (double)bh;
+      }
+      h[o_rri + (size_t)l * n_q + t] = (double)hinv(all, q);
+    }
+  }
   // rescale: q_l^-1 mod q_i
   size_t o_rs = alloc((size_t)n_q * n_q);
   for (int l = 1; l < n_q; ++l)
@@ -225,6 +251,9 @@ int build_context(Ctx& c, int log_n, int n_q, int q_bits, int n_p, int p_bits, i
   c.md_pinv = B + o_mdp;
   c.p_mod_q = B + o_pmq;
   c.rs_tab = B + o_rs;
+  c.rr_cinv = B + o_rrc;
+  c.rr_chat = B + o_rrh;
+  c.rr_inv = B + o_rri;
   c.crt_tab = B + o_crt;
   HIPCHK(hipEventCreateWithFlags(&c.staging_done, hipEventDisableTiming));
   return 0;
@@ -357,7 +386,7 @@ void Builder::modup(const std::vector<ModUpJob>& v) {
 }
 void Builder::moddown(const std::vector<ModDownJob>& v) {
   int64_t units = 0;
-  for (auto& j : v) units += j.n_chain + C.n_p;
+  for (auto& j : v) units += j.n_chain + C.n_p + (j.first_prime >= 0 ? 1 : 0);
   PUSH_JOBS(C_MODDOWN, v, 1, false, units);
 }
 void Builder::inner(const std::vector<InnerJob>& v) {
@@ -500,32 +529,23 @@ int submit(Ctx& c, Builder& b, char* arena, size_t arena_bytes) {
 // key switching (hybrid, digits of alpha chain primes)
 //   ModUp each digit -> inner product with the key over Q_l u P -> ModDown
 // ---------------------------------------------------------------------------
-void Builder::key_switch(const std::vector<KsItem>& items) {
+// first half, shared by key switching and the merged relinearise + rescale:
+// the accumulator acc_w over Q_l u P (NTT domain) with acc0 + acc1 s' = P d s + small
+void Builder::ks_front(const std::vector<KsItem>& items, std::vector<KsTmp>& tmp) {
   const int N = C.N, alpha = C.alpha, n_p = C.n_p;
-  struct Tmp {
-    double* dcoef;
-    double* ext;
-    double* acc;
-    double* conv;
-    int n_ext, nd;
-  };
-  std::vector<Tmp> tmp(items.size());
-  std::vector<NttJob> j_inv, j_fwd_ext, j_inv_acc, j_fwd_conv;
+  tmp.resize(items.size());
+  std::vector<NttJob> j_inv, j_fwd_ext;
   std::vector<ModUpJob> j_up;
   std::vector<InnerJob> j_in;
-  std::vector<ModDownJob> j_down;
-  std::vector<EwJob> j_comb;
   for (size_t i = 0; i < items.size(); ++i) {
     const KsItem& it = items[i];
     const int l = it.level, nc = l + 1, n_ext = nc + n_p;
     const int nd = (nc + alpha - 1) / alpha;
-    Tmp& t = tmp[i];
+    KsTmp& t = tmp[i];
     t.n_ext = n_ext;
-    t.nd = nd;
     t.dcoef = scratch((size_t)nc * N);
     t.ext = scratch((size_t)nd * n_ext * N);
     t.acc = scratch((size_t)2 * n_ext * N);
-    t.conv = scratch((size_t)2 * nc * N);
     j_inv.push_back(NttJob{it.d, t.dcoef, nc, nc, 0, 0});
     for (int j = 0; j < nd; ++j) {
       const int lo = j * alpha, hi = std::min((j + 1) * alpha, nc);
@@ -534,12 +554,32 @@ void Builder::key_switch(const std::vector<KsItem>& items) {
       j_up.push_back(ModUpJob{t.dcoef, e, dt.cinv, dt.chat, lo, hi, nc, n_ext});
       j_fwd_ext.push_back(NttJob{e, e, n_ext, nc, lo, hi});
     }
-    j_in.push_back(InnerJob{it.d, t.ext, it.key, t.acc, nc, n_ext, nd, alpha});
+    j_in.push_back(InnerJob{it.d, t.ext, it.key, t.acc, it.top0, it.top1, C.p_mod_q, nc, n_ext, nd, alpha});
+  }
+  ntt(j_inv, true);
+  modup(j_up);
+  ntt(j_fwd_ext, false);
+  inner(j_in);
+}
+
+// key switching (hybrid): front half, then ModDown by P
+void Builder::key_switch(const std::vector<KsItem>& items) {
+  const int N = C.N, n_p = C.n_p;
+  std::vector<KsTmp> tmp;
+  ks_front(items, tmp);
+  std::vector<NttJob> j_inv_acc, j_fwd_conv;
+  std::vector<ModDownJob> j_down;
+  std::vector<EwJob> j_comb;
+  for (size_t i = 0; i < items.size(); ++i) {
+    const KsItem& it = items[i];
+    const int nc = it.level + 1, n_ext = tmp[i].n_ext;
+    double* acc = tmp[i].acc;
+    double* conv = scratch((size_t)2 * nc * N);
     for (int w = 0; w < 2; ++w) {
-      double* sp = t.acc + ((size_t)w * n_ext + nc) * N;
+      double* sp = acc + ((size_t)w * n_ext + nc) * N;
       j_inv_acc.push_back(NttJob{sp, sp, n_p, 0, 0, 0});
-      double* cv = t.conv + (size_t)w * nc * N;
-      j_down.push_back(ModDownJob{sp, cv, C.md_cinv, C.md_chat, nc, 0});
+      double* cv = conv + (size_t)w * nc * N;
+      j_down.push_back(ModDownJob{sp, cv, C.md_cinv, C.md_chat, nc, -1});
       j_fwd_conv.push_back(NttJob{cv, cv, nc, nc, 0, 0});
     }
     EwJob e{};
@@ -547,25 +587,120 @@ void Builder::key_switch(const std::vector<KsItem>& items) {
     e.o1 = it.out1;
     e.a0 = it.base0;
     e.a1 = it.base1;
-    e.b0 = t.acc;
-    e.b1 = t.acc + (size_t)n_ext * N;
-    e.c0 = t.conv;
-    e.c1 = t.conv + (size_t)nc * N;
+    e.b0 = acc;
+    e.b1 = acc + (size_t)n_ext * N;
+    e.c0 = conv;
+    e.c1 = conv + (size_t)nc * N;
     e.k = C.md_pinv;
     e.n_limbs = nc;
     e.n_chain = nc;
     e.op = EW_MODDOWN;
     j_comb.push_back(e);
   }
-  ntt(j_inv, true);
-  modup(j_up);
-  ntt(j_fwd_ext, false);
-  inner(j_in);
   ntt(j_inv_acc, true);
   moddown(j_down);
   ntt(j_fwd_conv, false);
   ew(j_comb);
   counters[3] += (int64_t)items.size();
+}
+
+// merged relinearise + rescale of degree-2 ciphertexts (d0, d1, d2) at level l:
+// y_w = P d_w + acc_w over Q_l u P, divided by B = P q_l with a centred base
+// conversion from {q_l} u P: out_w = (y_w - Conv_B(y_w)) B^-1 on limbs 0..l-1
+std::vector<CT> Builder::relin_rescale(const std::vector<Deg2>& xs) {
+  const int N = C.N, n_p = C.n_p, n_q = C.n_q, nb = n_p + 1;
+  auto kit = C.keys.find(0);
+  const double* rk = kit != C.keys.end() ? kit->second : (dry ? C.T.mod : nullptr);
+  if (!rk) { fail(-4, "no relinearisation key"); return {}; }
+  std::vector<KsItem> items;
+  for (const Deg2& x : xs) {
+    if (x.level < 1) { fail(-3, "relinearise-and-rescale at level 0"); return {}; }
+    items.push_back(KsItem{x.d2, x.level, rk, nullptr, nullptr, nullptr, nullptr, x.d0, x.d1});
+  }
+  std::vector<KsTmp> tmp;
+  ks_front(items, tmp);
+  std::vector<CT> out;
+  std::vector<NttJob> j_inv_acc, j_fwd_conv;
+  std::vector<ModDownJob> j_conv;
+  std::vector<EwJob> j_comb;
+  for (size_t i = 0; i < xs.size(); ++i) {
+    const Deg2& x = xs[i];
+    const int l = x.level, nc = l + 1, n_ext = tmp[i].n_ext;
+    double* acc = tmp[i].acc;
+    double* conv = scratch((size_t)2 * l * N);
+    for (int w = 0; w < 2; ++w) {
+      double* aw = acc + (size_t)w * n_ext * N;
+      // limbs l .. l+n_p of the extended basis: q_l, then the special primes
+      j_inv_acc.push_back(NttJob{aw, aw, n_ext, nc, 0, l});
+      double* cv = conv + (size_t)w * l * N;
+      j_conv.push_back(ModDownJob{aw + (size_t)l * N, cv, C.rr_cinv + (size_t)l * nb,
+                                  C.rr_chat + (size_t)l * n_q * nb, l, l});
+      j_fwd_conv.push_back(NttJob{cv, cv, l, l, 0, 0});
+    }
+    CT o = new_ct(l - 1, x.scale / (double)C.mod[l]);
+    EwJob e{};
+    e.o0 = c0(o);
+    e.o1 = c1(o);
+    e.a0 = x.d0;
+    e.a1 = x.d1;
+    e.b0 = acc;
+    e.b1 = acc + (size_t)n_ext * N;
+    e.c0 = conv;
+    e.c1 = conv + (size_t)l * N;
+    e.k = C.rr_inv + (size_t)l * n_q;
+    e.k2 = C.p_mod_q;
+    e.n_limbs = l;
+    e.n_chain = l;
+    e.op = EW_RRCOMB;
+    j_comb.push_back(e);
+    out.push_back(o);
+  }
+  ntt(j_inv_acc, true);
+  moddown(j_conv);
+  ntt(j_fwd_conv, false);
+  ew(j_comb);
+  counters[2] += (int64_t)xs.size();
+  counters[3] += (int64_t)xs.size();
+  return out;
+}
+
+// degree-2 sums: for each item, x.a (x) x.b [+ x.c (x) x.e] [+ x.f] at the
+// lowest level among the operands
+std::vector<Builder::Deg2> Builder::tensor2(const std::vector<TensorItem>& v) {
+  const int N = C.N;
+  std::vector<Deg2> out;
+  std::vector<EwJob> j;
+  for (const TensorItem& it : v) {
+    int l = std::min(it.a.level, it.b.level);
+    double sc = it.a.scale * it.b.scale;
+    if (it.has_ce) {
+      l = std::min(l, std::min(it.c.level, it.e.level));
+      const double s2 = it.c.scale * it.e.scale;
+      if (fabs(sc - s2) > 1e-9 * fabs(sc)) { fail(-1, "scale mismatch in degree-2 sum"); return {}; }
+    }
+    if (it.has_f) {
+      if (it.f.level < l) { fail(-1, "addend below the product level"); return {}; }
+      if (fabs(sc - it.f.scale) > 1e-9 * fabs(sc)) { fail(-1, "scale mismatch in degree-2 sum"); return {}; }
+    }
+    Deg2 d{};
+    d.level = l;
+    d.scale = sc;
+    d.d0 = scratch((size_t)(l + 1) * N);
+    d.d1 = scratch((size_t)(l + 1) * N);
+    d.d2 = scratch((size_t)(l + 1) * N);
+    EwJob e{};
+    e.o0 = d.d0; e.o1 = d.d1; e.o2 = d.d2;
+    e.a0 = c0(it.a); e.a1 = c1(it.a);
+    e.b0 = c0(it.b); e.b1 = c1(it.b);
+    if (it.has_ce) { e.c0 = c0(it.c); e.c1 = c1(it.c); e.e0 = c0(it.e); e.e1 = c1(it.e); }
+    if (it.has_f) { e.f0 = c0(it.f); e.f1 = c1(it.f); }
+    e.n_limbs = l + 1; e.n_chain = l + 1;
+    e.op = EW_TENSOR2;
+    j.push_back(e);
+    out.push_back(d);
+  }
+  ew(j);
+  return out;
 }
 
 // rescale by the top prime q_l: c_i <- (c_i - [c_l]centred) * q_l^-1  (in place)
@@ -611,10 +746,25 @@ void Builder::rescale(std::vector<CT>& xs) {
 
 std::vector<CT> Builder::mul_relin(const std::vector<std::pair<CT, CT>>& ab, bool do_rescale) {
   const int N = C.N;
+  const size_t mark = scratch_mark();
+  if (do_rescale) {
+    std::vector<TensorItem> ti;
+    for (auto& p : ab) {
+      TensorItem t{};
+      t.a = p.first;
+      t.b = p.second;
+      ti.push_back(t);
+    }
+    std::vector<Deg2> d = tensor2(ti);
+    if (err_code) return {};
+    std::vector<CT> out = relin_rescale(d);
+    if (err_code) return {};
+    scratch_release(mark);
+    return out;
+  }
   auto it = C.keys.find(0);
   const double* rk = it != C.keys.end() ? it->second : (dry ? C.T.mod : nullptr);
   if (!rk) { fail(-4, "no relinearisation key"); return {}; }
-  const size_t mark = scratch_mark();
   std::vector<CT> out;
   std::vector<EwJob> j_t;
   std::vector<KsItem> ks;
@@ -634,13 +784,12 @@ std::vector<CT> Builder::mul_relin(const std::vector<std::pair<CT, CT>>& ab, boo
     e.n_chain = l + 1;
     e.op = EW_TENSOR;
     j_t.push_back(e);
-    ks.push_back(KsItem{d2, l, rk, c0(o), c1(o), c0(o), c1(o)});
+    ks.push_back(KsItem{d2, l, rk, c0(o), c1(o), c0(o), c1(o), nullptr, nullptr});
     out.push_back(o);
   }
   ew(j_t);
   key_switch(ks);
   counters[2] += (int64_t)ab.size();
-  if (do_rescale) rescale(out);
   if (err_code) return {};
   scratch_release(mark);
   return out;
@@ -671,7 +820,7 @@ std::vector<CT> Builder::rotate(const std::vector<CT>& in, const std::vector<int
     double* d = scratch((size_t)nl * N);
     j_a.push_back(AutoJob{c0(x), c0(o), nl, nl, (uint32_t)g, 0});
     j_a.push_back(AutoJob{c1(x), d, nl, nl, (uint32_t)g, 0});
-    ks.push_back(KsItem{d, x.level, gk, c0(o), nullptr, c0(o), c1(o)});
+    ks.push_back(KsItem{d, x.level, gk, c0(o), nullptr, c0(o), c1(o), nullptr, nullptr});
     out.push_back(o);
   }
   automorph(j_a);
@@ -722,34 +871,65 @@ std::vector<CT> Builder::add_const(const std::vector<CT>& in, const std::vector<
   return out;
 }
 
-// constant product with exact target scale: K = llround(v T q_l / s), rescale, scale := T
-std::vector<CT> Builder::mul_const(const std::vector<CT>& in, const std::vector<double>& v,
-                                   const std::vector<double>& target) {
+// integer constant taking value v at scale s to scale T: llround(v T q / s)
+// when a rescale by q follows, llround(v T / s) when none does
+static int64_t const_for(double v, double target, double q, double s, bool rescale, bool& ok) {
+  double k = v * target;
+  if (rescale) k = k * q;
+  k = k / s;
+  ok = fabs(k) < 9.2e18;
+  return ok ? llround(k) : 0;
+}
+
+// K_a a + K_b b with constants chosen so the result carries scale T: rescaled
+// once, or left at the operands' level when 'rescale' is false
+std::vector<CT> Builder::lincomb(const std::vector<LinItem>& v, bool do_rescale) {
   std::vector<CT> out;
   std::vector<EwJob> j;
-  for (size_t i = 0; i < in.size(); ++i) {
-    const CT& x = in[i];
+  for (const LinItem& it : v) {
+    const CT& x = it.a;
+    if (it.has_b && it.b.level != x.level) { fail(-1, "lincomb: level mismatch"); return {}; }
     const double ql = (double)C.mod[x.level];
-    double kf = v[i] * target[i];
-    kf = kf * ql;
-    kf = kf / x.scale;
-    const int64_t K = llround(kf);
-    CT o = new_ct(x.level, x.scale);
+    bool ok1 = true, ok2 = true;
+    const int64_t Ka = const_for(it.va, it.target, ql, x.scale, do_rescale, ok1);
+    const int64_t Kb = it.has_b ? const_for(it.vb, it.target, ql, it.b.scale, do_rescale, ok2) : 0;
+    if (!ok1 || !ok2) { fail(-1, "constant does not fit 64 bits"); return {}; }
+    CT o = new_ct(x.level, it.target);
     EwJob e{};
     e.o0 = c0(o); e.o1 = c1(o); e.a0 = c0(x); e.a1 = c1(x);
-    e.k = put_residues(K, x.level + 1);
+    e.k = put_residues(Ka, x.level + 1);
+    if (it.has_b) {
+      e.b0 = c0(it.b); e.b1 = c1(it.b);
+      e.k2 = put_residues(Kb, x.level + 1);
+    }
     e.n_limbs = x.level + 1; e.n_chain = x.level + 1;
-    e.op = EW_CMUL;
+    e.op = EW_LIN2;
     j.push_back(e);
     out.push_back(o);
   }
   ew(j);
-  const size_t mark = scratch_mark();
-  rescale(out);
-  scratch_release(mark);
-  if (err_code) return {};
-  for (size_t i = 0; i < out.size(); ++i) out[i].scale = target[i];
+  if (do_rescale) {
+    const size_t mark = scratch_mark();
+    rescale(out);
+    scratch_release(mark);
+    if (err_code) return {};
+    for (size_t i = 0; i < out.size(); ++i) out[i].scale = v[i].target;
+  }
   return out;
+}
+
+// constant product with exact target scale: K = llround(v T q_l / s), rescale, scale := T
+std::vector<CT> Builder::mul_const(const std::vector<CT>& in, const std::vector<double>& v,
+                                   const std::vector<double>& target) {
+  std::vector<LinItem> li;
+  for (size_t i = 0; i < in.size(); ++i) {
+    LinItem t{};
+    t.a = in[i];
+    t.va = v[i];
+    t.target = target[i];
+    li.push_back(t);
+  }
+  return lincomb(li, true);
 }
 
 // product with the encoded real vector z (slots 0..len-1), exact target scale
@@ -879,8 +1059,12 @@ std::vector<CT> Builder::refresh(const std::vector<CT>& in, const std::vector<ui
   return out;
 }
 
-// odd degree-9 polynomial p(x) = (c1 x + c3 x^3) + x^4 (c5 x + c7 x^3) + x^8 (c9 x)
-// (baby-step giant-step, depth 4, six ciphertext products); output scale = target
+// odd degree-9 polynomial p(x) = (c1 x + c3 x^3) + x^4 (c5 x + c7 x^3) + x^8 (c9 x):
+// baby steps x^2, x^3, x^4, giant step x^8 (three rounds of merged
+// relinearise + rescale); B and C as constant combinations rescaled once, A
+// unrescaled at the products' scale; x^4 B + x^8 C + A as one degree-2 sum,
+// relinearised and rescaled once.  Depth 4, five relinearisations; output at
+// level l-4 carrying (target q_{l-3}) / q_{l-3}.
 std::vector<CT> Builder::eval_odd9(const std::vector<CT>& xs, const std::vector<const double*>& coef,
                                    const std::vector<double>& gain, const std::vector<double>& target) {
   const size_t n = xs.size();
@@ -902,58 +1086,53 @@ std::vector<CT> Builder::eval_odd9(const std::vector<CT>& xs, const std::vector<
   std::vector<CT> x8 = mul_relin(p, true);
   if (err_code) return {};
   for (auto& v : x2) free_ct(v);
-  // constants: a3 = c3 x^3, a1 = c1 x, b3 = c7 x^3, b1 = c5 x, cc = c9 x, all rescaled to level l-3
-  std::vector<CT> cin;
-  std::vector<double> cv, ct;
-  std::vector<double> sb(n), sc(n);
+  std::vector<LinItem> bc, a;
   for (size_t i = 0; i < n; ++i) {
     const int l = xs[i].level;
-    const double q3 = (double)C.mod[l - 3];
+    const double ta = target[i] * (double)C.mod[l - 3];
     const double g = gain[i];
     const double* c = coef[i];
-    sb[i] = target[i] * q3;
-    sb[i] = sb[i] / x4[i].scale;
-    sc[i] = target[i] * q3;
-    sc[i] = sc[i] / x8[i].scale;
     const CT xl2 = lower(xs[i], l - 2);
-    cin.push_back(x3[i]); cv.push_back(c[1] * g); ct.push_back(target[i]);
-    cin.push_back(xl2); cv.push_back(c[0] * g); ct.push_back(target[i]);
-    cin.push_back(x3[i]); cv.push_back(c[3] * g); ct.push_back(sb[i]);
-    cin.push_back(xl2); cv.push_back(c[2] * g); ct.push_back(sb[i]);
-    cin.push_back(xl2); cv.push_back(c[4] * g); ct.push_back(sc[i]);
+    LinItem B{};
+    B.a = xl2; B.va = c[2] * g; B.b = x3[i]; B.vb = c[3] * g; B.has_b = true; B.target = ta / x4[i].scale;
+    LinItem Cc{};
+    Cc.a = xl2; Cc.va = c[4] * g; Cc.target = ta / x8[i].scale;
+    bc.push_back(B);
+    bc.push_back(Cc);
+    LinItem A{};
+    A.a = lower(xs[i], l - 3); A.va = c[0] * g; A.b = lower(x3[i], l - 3); A.vb = c[1] * g; A.has_b = true;
+    A.target = ta;
+    a.push_back(A);
   }
-  std::vector<CT> k = mul_const(cin, cv, ct);
+  std::vector<CT> kbc = lincomb(bc, true);
+  if (err_code) return {};
+  std::vector<CT> ka = lincomb(a, false);
   if (err_code) return {};
   for (auto& v : x3) free_ct(v);
-  p.clear();
-  for (size_t i = 0; i < n; ++i) p.push_back({k[5 * i + 1], k[5 * i + 0]});  // A = a1 + a3
-  for (size_t i = 0; i < n; ++i) p.push_back({k[5 * i + 3], k[5 * i + 2]});  // B = b1 + b3
-  std::vector<CT> AB = add(p, false);
-  if (err_code) return {};
-  p.clear();
-  for (size_t i = 0; i < n; ++i) p.push_back({lower(x4[i], xs[i].level - 3), AB[n + i]});
-  for (size_t i = 0; i < n; ++i) p.push_back({x8[i], k[5 * i + 4]});
-  std::vector<CT> prods = mul_relin(p, true);
-  if (err_code) return {};
+  const size_t mark = scratch_mark();
+  std::vector<TensorItem> ti;
   for (size_t i = 0; i < n; ++i) {
-    for (int j = 0; j < 5; ++j) free_ct(k[5 * i + j]);
+    TensorItem t{};
+    t.a = lower(x4[i], xs[i].level - 3);
+    t.b = kbc[2 * i];
+    t.c = x8[i];
+    t.e = kbc[2 * i + 1];
+    t.has_ce = true;
+    t.f = ka[i];
+    t.has_f = true;
+    ti.push_back(t);
+  }
+  std::vector<Deg2> d = tensor2(ti);
+  if (err_code) return {};
+  std::vector<CT> res = relin_rescale(d);
+  if (err_code) return {};
+  scratch_release(mark);
+  for (size_t i = 0; i < n; ++i) {
+    free_ct(kbc[2 * i]);
+    free_ct(kbc[2 * i + 1]);
+    free_ct(ka[i]);
     free_ct(x4[i]);
     free_ct(x8[i]);
-    free_ct(AB[n + i]);
-  }
-  p.clear();
-  for (size_t i = 0; i < n; ++i) p.push_back({lower(AB[i], xs[i].level - 4), prods[i]});
-  std::vector<CT> s1 = add(p, false);
-  if (err_code) return {};
-  p.clear();
-  for (size_t i = 0; i < n; ++i) p.push_back({s1[i], prods[n + i]});
-  std::vector<CT> res = add(p, false);
-  if (err_code) return {};
-  for (size_t i = 0; i < n; ++i) {
-    free_ct(AB[i]);
-    free_ct(prods[i]);
-    free_ct(prods[n + i]);
-    free_ct(s1[i]);
   }
   counters[5] += (int64_t)n;
   return res;

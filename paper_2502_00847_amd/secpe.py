@@ -74,6 +74,7 @@ def load():
         "secpe_op_sub": (i32, [vp, ct, ct, ct]),
         "secpe_op_add_const": (i32, [vp, ct, dbl, ct]),
         "secpe_op_mul_const": (i32, [vp, ct, dbl, dbl, vp, sz, ct]),
+        "secpe_op_lincomb": (i32, [vp, ct, dbl, ct, dbl, dbl, i32, vp, sz, ct]),
         "secpe_op_mul_plain": (i32, [vp, ct, P(dbl), i32, dbl, vp, sz, ct]),
         "secpe_op_rescale": (i32, [vp, ct, vp, sz, ct]),
         "secpe_op_mul_relin": (i32, [vp, ct, ct, vp, sz, ct]),
@@ -113,7 +114,7 @@ def exported_symbols():
          "secpe_decrypt_coeffs", "secpe_workspace_bytes", "secpe_eval_argmax", "secpe_eval_argmax_batch",
          "secpe_counters", "secpe_ct_export", "secpe_ct_import", "secpe_key_export", "secpe_sk_export",
          "secpe_sync", "secpe_op_workspace_bytes", "secpe_op_add", "secpe_op_sub", "secpe_op_add_const",
-         "secpe_op_mul_const", "secpe_op_mul_plain", "secpe_op_rescale", "secpe_op_mul_relin",
+         "secpe_op_mul_const", "secpe_op_lincomb", "secpe_op_mul_plain", "secpe_op_rescale", "secpe_op_mul_relin",
          "secpe_op_mul_relin_rescale", "secpe_op_rotate", "secpe_op_refresh", "secpe_op_eval_odd9",
          "secpe_op_key_switch", "secpe_op_ntt", "secpe_op_ring_mul", "secpe_op_encode", "secpe_profile_begin",
          "secpe_profile_end", "secpe_ntt_cts", "secpe_rotate_workspace_bytes", "secpe_rotate_batch",
@@ -379,6 +380,10 @@ class Context:
 
     def mul_const(self, a, v, target):
         return self._op(self.lib.secpe_op_mul_const, C.byref(a._c()), float(v), float(target))
+
+    def lincomb(self, a, va, b, vb, target, rescale=True):
+        return self._op(self.lib.secpe_op_lincomb, C.byref(a._c()), float(va),
+                        C.byref(b._c()) if b is not None else None, float(vb), float(target), int(bool(rescale)))
 
     def mul_plain(self, a, v, target):
         v = np.ascontiguousarray(v, dtype=np.float64)

@@ -184,6 +184,19 @@ def test_elementwise_ops_bit_exact(tiny):
     _same(g, g.rescale(ga), o.rescale(a))
 
 
+def test_lincomb_bit_exact(tiny):
+    """Two-term and one-term constant combinations, rescaled and unrescaled, at two levels."""
+    g, o, _ = tiny
+    a, _ = _rand_ct(o, 16)
+    b, _ = _rand_ct(o, 17, scale=2.0**40 * 0.997)
+    for lvl in (a.level, 2):
+        al, bl = o.lower(a, lvl), o.lower(b, lvl)
+        ga, gb = g.import_(al.export(), al.scale), g.import_(bl.export(), bl.scale)
+        for vb, T, rs in ((0.37, 2.0**40, True), (-2.5, 2.0**80 * 1.01, False)):
+            _same(g, g.lincomb(ga, 1.25, gb, vb, T, rs), o.lincomb(al, 1.25, bl, vb, T, rs))
+            _same(g, g.lincomb(ga, -0.75, None, 0.0, T, rs), o.lincomb(al, -0.75, None, 0.0, T, rs))
+
+
 def test_products_and_rotations_bit_exact(tiny):
     g, o, steps = tiny
     a, _ = _rand_ct(o, 9)
@@ -191,6 +204,11 @@ def test_products_and_rotations_bit_exact(tiny):
     ga, gb = g.import_(a.export(), a.scale), g.import_(b.export(), b.scale)
     _same(g, g.mul_relin(ga, gb), o.mul_relin(a, b))
     _same(g, g.mul_relin_rescale(ga, ga), o.mul_relin_rescale(a, a))
+    # merged relinearise + rescale at a ragged level and at level 1 (result at level 0)
+    _same(g, g.mul_relin_rescale(ga, gb), o.mul_relin_rescale(a, b))
+    a1 = o.lower(a, 1)
+    ga1 = g.import_(a1.export(), a1.scale)
+    _same(g, g.mul_relin_rescale(ga1, ga1), o.mul_relin_rescale(a1, a1))
     for st in [1, 3, 5, steps[-1], o.slots - 4]:
         if st not in steps:
             continue
