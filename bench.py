@@ -54,8 +54,8 @@ def _cpu_worker(args):
 
 
 def cpu_baseline(ks_per_query, procs):
-    """Argmax/s of the oracle, from one degree-9 Sign polynomial (6 ciphertext
-    products with relinearisation at the top level) timed in 'procs' parallel
+    """Argmax/s of the oracle, from one degree-9 Sign polynomial (5 key switches:
+    merged relinearise + rescale, at the top level) timed in 'procs' parallel
     processes and scaled by key switches per query."""
     import multiprocessing as mp
     from oracle.build import build_oracle
@@ -66,16 +66,16 @@ def cpu_baseline(ks_per_query, procs):
         times = pool.map(_cpu_worker, [(i + 1,) for i in range(procs)])
     wall = time.perf_counter() - t0
     t_poly = float(np.mean(times))
-    per_query_s = t_poly * ks_per_query / 6.0
+    per_query_s = t_poly * ks_per_query / 5.0
     return {
         "value": procs / per_query_s,
         "unit": "Argmax/s",
         "cores": procs,
         "kind": "oracle",
         "sample": (f"{procs} processes, each one CPU-oracle evaluation of a degree-9 Sign polynomial "
-                   f"(6 ct-ct products + relinearisation, 5 constant products) at the top level of the "
-                   f"N=2^16 chain, mean {t_poly:.2f} s; scaled by {ks_per_query:.1f} key switches per "
-                   f"query / 6; sample wall {wall:.1f} s"),
+                   f"(5 ct-ct products with merged relinearise + rescale, 3 constant combinations) at the "
+                   f"top level of the N=2^16 chain, mean {t_poly:.2f} s; scaled by {ks_per_query:.1f} key "
+                   f"switches per query / 5; sample wall {wall:.1f} s"),
     }
 
 
