@@ -189,8 +189,12 @@ int secpe_server_step(secpe_server* srv, int cap, int* n_done, uint64_t* tickets
    residues), limbs for the others.  Kinds: */
 enum {
   SECPE_PROF_NTT_FWD = 0, SECPE_PROF_NTT_INV = 1, SECPE_PROF_EW = 2, SECPE_PROF_MODUP = 3,
-  SECPE_PROF_MODDOWN = 4, SECPE_PROF_INNER = 5, SECPE_PROF_AUTO = 6, SECPE_PROF_SPREAD = 7,
-  /* one kernel of the two-pass forward NTT (N > 2^12): the column pass, the row pass */
+  SECPE_PROF_MODDOWN = 4, SECPE_PROF_INNER = 5, SECPE_PROF_AUTO = 6,
+  /* 7 is reserved (the rescale's spread of the top limb runs fused into the forward NTT) */
+  SECPE_PROF_SPREAD = 7,
+  /* one kernel of the two-pass forward NTT (N > 2^12): the column pass, the row pass;
+     the forward NTT carries the fused rescale / ModDown / relinearise-and-rescale
+     combines in its row pass */
   SECPE_PROF_NTT_FWD_COL = 8, SECPE_PROF_NTT_FWD_ROW = 9
 };
 int secpe_profile_begin(secpe_ctx* ctx, int kind);

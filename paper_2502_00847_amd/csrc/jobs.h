@@ -25,11 +25,33 @@ struct DevTables {
   int n_q, n_p, log_n, pad;
 };
 
+enum NttEpi : int {
+  EPI_NONE = 0,      // dst = v
+  EPI_RESCALE = 1,   // eout = (ea - v) ek[l]
+  EPI_RRCOMB = 2,    // eout = (ek2[l] ea + eb - v) ek[l]
+  EPI_MODDOWN = 3,   // eout = (ebase or 0) + (eb - v) ek[l]
+};
+
 // NTT over limbs [0, n_limbs) of src (skipping [skip_lo, skip_hi)), written to dst.
+// Forward transforms may fuse a prologue into their first pass and an
+// epilogue into their last:
+//  * spread_from > 0: every limb l reads the one limb at src (coefficient
+//    domain, residues mod prime spread_from - 1, taken centred) reduced mod
+//    its own prime, instead of limb l of src;
+//  * epi != EPI_NONE: the transform v of limb l is not stored; eout at the
+//    same position receives the combination above (ea, eb, ebase, eout are
+//    limb-major arrays indexed like dst; ek, ek2 per-limb constants).
 struct NttJob {
   const double* src;
   double* dst;
   int n_limbs, n_chain, skip_lo, skip_hi;
+  int spread_from, epi;
+  const double* ea;
+  const double* eb;
+  const double* ebase;
+  double* eout;
+  const double* ek;
+  const double* ek2;
 };
 
 enum EwOp : int {
@@ -109,13 +131,6 @@ struct InnerJob {
   const double* top1;
   const double* pmq;    // [n_q] P mod q_t
   int n_chain, n_ext, n_digits, alpha;
-};
-
-// rescale: spread the centred top limb (coefficient domain) to limbs 0..n_chain-1
-struct SpreadJob {
-  const double* src;    // top limb, coefficient domain, residues mod src_prime
-  double* dst;          // [n_chain][N]
-  int src_prime, n_chain;
 };
 
 // Galois automorphism in the NTT domain (bit-reversed evaluation order)

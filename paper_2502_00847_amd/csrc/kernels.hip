@@ -24,6 +24,50 @@ namespace secpe {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 
+__device__ __forceinline__ double2 ld2(const double* p, size_t o) {
+  const dv2 v = *(cgdbl2*)(CGPTR(p) + o);
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void st2(double* p, size_t o, double a, double b) {
+  dv2 v;
+  v.x = a;
+  v.y = b;
+  *(gdbl2*)(GPTR(p) + o) = v;
+}
+
+// fused prologue: residue z mod q_src taken centred, reduced mod m
+__device__ __forceinline__ double spread_in(double z, double q_src, const Mod& m) {
+  return red(2.0 * z > q_src ? z - q_src : z, m);
+}
+
+// fused epilogue of a forward transform: v0, v1 are the (lazily reduced)
+// transform values at positions o, o + 1 of limb l
+__device__ __forceinline__ void ntt_epilogue(const NttJob& J, int l, size_t o, double v0, double v1, const Mod& m) {
+  const double c0 = canon(v0, m), c1 = canon(v1, m);
+  const double k = KPTR(J.ek)[l];
+  double r0, r1;
+  if (J.epi == EPI_RESCALE) {
+    const double2 a = ld2(J.ea, o);
+    r0 = mul_mod(a.x - c0, k, m);
+    r1 = mul_mod(a.y - c1, k, m);
+  } else if (J.epi == EPI_RRCOMB) {
+    const double k2 = KPTR(J.ek2)[l];
+    const double2 a = ld2(J.ea, o), b = ld2(J.eb, o);
+    r0 = mul_mod(red(mul_mod(a.x, k2, m) + (b.x - c0), m), k, m);
+    r1 = mul_mod(red(mul_mod(a.y, k2, m) + (b.y - c1), m), k, m);
+  } else {
+    const double2 b = ld2(J.eb, o);
+    r0 = mul_mod(b.x - c0, k, m);
+    r1 = mul_mod(b.y - c1, k, m);
+    if (J.ebase) {
+      const double2 base = ld2(J.ebase, o);
+      r0 += base.x;
+      r1 += base.y;
+    }
+  }
+  st2(J.eout, o, canon(r0, m), canon(r1, m));
+}
+
 enum { NTT_SINGLE = 0, NTT_COL = 1, NTT_ROW = 2 };
 
 template <int LOGS, int MODE>
@@ -129,8 +173,8 @@ __device__ __forceinline__ void inv_all(double* lds, const double* tw, const dou
 template <int LOGS, int G, int MODE, bool INV>
 __global__ __launch_bounds__(256) void k_ntt(const NttJob* __restrict__ jobs, DevTables T, int second) {
   extern __shared__ double lds[];
-  const NttJob J = jobs[blockIdx.z];
-  const int l = blockIdx.y;
+  const NttJob J = jobs[blockIdx.y];
+  const int l = blockIdx.z;
   if (l >= J.n_limbs || (l >= J.skip_lo && l < J.skip_hi)) return;
   const int pr = l < J.n_chain ? l : T.n_q + (l - J.n_chain);
   const int log_n = T.log_n;
@@ -139,7 +183,9 @@ __global__ __launch_bounds__(256) void k_ntt(const NttJob* __restrict__ jobs, De
   const Mod m{KPTR(T.mod)[pr], KPTR(T.minv)[pr]};
   const double* tw = (INV ? T.ipsi : T.psi) + (size_t)pr * N;
   const double* twq = (INV ? T.ipsiq : T.psiq) + (size_t)pr * N;
-  const double* src = (second ? J.dst : J.src) + (size_t)l * N;
+  const bool spread = !INV && !second && J.spread_from > 0;
+  const double* src = (second ? J.dst : J.src) + (spread ? 0 : (size_t)l * N);
+  const double q_src = spread ? KPTR(T.mod)[J.spread_from - 1] : 0.0;
   double* dst = J.dst + (size_t)l * N;
   const int tid = threadIdx.x;
   const int k1 = log_n - LOGS;
@@ -159,8 +205,8 @@ __global__ __launch_bounds__(256) void k_ntt(const NttJob* __restrict__ jobs, De
     const double2* s2 = reinterpret_cast<const double2*>(src + (size_t)row0 * S);
     for (int i = tid; i < G * S / 2; i += blockDim.x) {
       const double2 val = s2[i];
-      lds[lpad(2 * i)] = val.x;
-      lds[lpad(2 * i + 1)] = val.y;
+      lds[lpad(2 * i)] = spread ? spread_in(val.x, q_src, m) : val.x;
+      lds[lpad(2 * i + 1)] = spread ? spread_in(val.y, q_src, m) : val.y;
     }
   }
   __syncthreads();
@@ -180,11 +226,13 @@ __global__ __launch_bounds__(256) void k_ntt(const NttJob* __restrict__ jobs, De
     }
   } else {
     double2* d2 = reinterpret_cast<double2*>(dst + (size_t)row0 * S);
+    const bool epi = !INV && MODE != NTT_COL && J.epi != EPI_NONE;
     for (int i = tid; i < G * S / 2; i += blockDim.x) {
       double a = lds[lpad(2 * i)];
       double b = lds[lpad(2 * i + 1)];
       if (scale) { a = mul_w(red(a, m), ni, niq, m.p); b = mul_w(red(b, m), ni, niq, m.p); }
-      d2[i] = make_double2(canon(a, m), canon(b, m));
+      if (epi) ntt_epilogue(J, l, (size_t)l * N + (size_t)row0 * S + 2 * i, a, b, m);
+      else d2[i] = make_double2(canon(a, m), canon(b, m));
     }
   }
 }
@@ -253,8 +301,8 @@ __global__ __launch_bounds__(256) void k_ntt2(const NttJob* __restrict__ jobs, D
   constexpr int RB = LOGS - 4;         // bits of round B
   constexpr int NB = 1 << RB;          // elements per round-B group
   constexpr int GB = 16 / NB;          // round-B groups per thread
-  const NttJob J = jobs[blockIdx.z];
-  const int l = blockIdx.y;
+  const NttJob J = jobs[blockIdx.y];
+  const int l = blockIdx.z;
   if (l >= J.n_limbs || (l >= J.skip_lo && l < J.skip_hi)) return;
   const int pr = l < J.n_chain ? l : T.n_q + (l - J.n_chain);
   const int log_n = T.log_n;
@@ -262,7 +310,9 @@ __global__ __launch_bounds__(256) void k_ntt2(const NttJob* __restrict__ jobs, D
   const Mod m{KPTR(T.mod)[pr], KPTR(T.minv)[pr]};
   kdbl* tw = KPTR(INV ? T.ipsi : T.psi) + (size_t)pr * N;
   kdbl* twq = KPTR(INV ? T.ipsiq : T.psiq) + (size_t)pr * N;
-  cgdbl* src = CGPTR(second ? J.dst : J.src) + (size_t)l * N;
+  const bool spread = !INV && MODE == NTT_COL && J.spread_from > 0;
+  cgdbl* src = CGPTR(second ? J.dst : J.src) + (spread ? 0 : (size_t)l * N);
+  const double q_src = spread ? KPTR(T.mod)[J.spread_from - 1] : 0.0;
   gdbl* dst = GPTR(J.dst) + (size_t)l * N;
   const int t = threadIdx.x;
   const int k1 = log_n - LOGS;
@@ -285,6 +335,10 @@ __global__ __launch_bounds__(256) void k_ntt2(const NttJob* __restrict__ jobs, D
     // ---- round A straight from global memory
 #pragma unroll
     for (int e = 0; e < 16; ++e) x[e] = src[gaddr(va, e * NB + la)];
+    if (spread) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) x[e] = spread_in(x[e], q_src, m);
+    }
     ntt_round<LOGS, 4, MODE, false>(x, 0, RB, row0 + va, k1, tw, twq, m);
 #pragma unroll
     for (int e = 0; e < 16; ++e) lds[lidx(va, e * NB + la)] = x[e];
@@ -309,13 +363,18 @@ __global__ __launch_bounds__(256) void k_ntt2(const NttJob* __restrict__ jobs, D
     }
     if (MODE == NTT_ROW) {
       __syncthreads();
-      gdbl2* d2 = (gdbl2*)(dst + (size_t)row0 * S);
-      for (int i = t; i < G * S / 2; i += 256)
-      {
-        dv2 v;
-        v.x = canon(lds[lpad(2 * i)], m);
-        v.y = canon(lds[lpad(2 * i + 1)], m);
-        d2[i] = v;
+      if (J.epi != EPI_NONE) {
+        const size_t o0 = (size_t)l * N + (size_t)row0 * S;
+        for (int i = t; i < G * S / 2; i += 256)
+          ntt_epilogue(J, l, o0 + 2 * i, lds[lpad(2 * i)], lds[lpad(2 * i + 1)], m);
+      } else {
+        gdbl2* d2 = (gdbl2*)(dst + (size_t)row0 * S);
+        for (int i = t; i < G * S / 2; i += 256) {
+          dv2 v;
+          v.x = canon(lds[lpad(2 * i)], m);
+          v.y = canon(lds[lpad(2 * i + 1)], m);
+          d2[i] = v;
+        }
       }
     }
   } else {
@@ -406,16 +465,6 @@ void* ntt_kernel(int logs, int mode, bool inv, int* g_out) {
 // ---------------------------------------------------------------------------
 // elementwise operations on limbs (NTT domain unless stated)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double2 ld2(const double* p, size_t o) {
-  const dv2 v = *(cgdbl2*)(CGPTR(p) + o);
-  return make_double2(v.x, v.y);
-}
-__device__ __forceinline__ void st2(double* p, size_t o, double a, double b) {
-  dv2 v;
-  v.x = a;
-  v.y = b;
-  *(gdbl2*)(GPTR(p) + o) = v;
-}
 
 __global__ __launch_bounds__(256) void k_ew(const EwJob* __restrict__ jobs, DevTables T) {
   const EwJob J = jobs[blockIdx.z];
@@ -653,18 +702,19 @@ __global__ __launch_bounds__(256) void k_moddown_conv(const ModDownJob* __restri
 }
 
 // acc_w[t] = sum_j x_j[t] key_j[w][t]; x_j[t] = d[t] inside digit j, else ModUp output.
-// blockIdx.x runs over jobs so that jobs streaming the same key limb run
-// back to back (relinearisation shares one key across a whole batch).
+// Grid (tile, job, limb): with a multiple of 8 tiles per limb, one tile of a
+// key limb lands on the same XCD for every job of the batch (relinearisation
+// shares one key across the batch), so its L2 serves the repeats.
 __global__ __launch_bounds__(256) void k_inner(const InnerJob* __restrict__ jobs, DevTables T) {
-  const InnerJob J = jobs[blockIdx.x];
-  const int t = blockIdx.y;
+  const InnerJob J = jobs[blockIdx.y];
+  const int t = blockIdx.z;
   if (t >= J.n_ext) return;
   const int N = 1 << T.log_n;
   const int n_mod = T.n_q + T.n_p;
   const int pr = t < J.n_chain ? t : T.n_q + (t - J.n_chain);
   const Mod m{KPTR(T.mod)[pr], KPTR(T.minv)[pr]};
   const int own = t < J.n_chain ? t / J.alpha : -1;
-  for (int k = 2 * (blockIdx.z * blockDim.x + threadIdx.x); k < N; k += 2 * gridDim.z * blockDim.x) {
+  for (int k = 2 * (blockIdx.x * blockDim.x + threadIdx.x); k < N; k += 2 * gridDim.x * blockDim.x) {
     double a0x = 0.0, a0y = 0.0, a1x = 0.0, a1y = 0.0;
     for (int j = 0; j < J.n_digits; ++j) {
       const double2 x = (j == own) ? ld2(J.d, (size_t)t * N + k) : ld2(J.ext, ((size_t)j * J.n_ext + t) * N + k);
@@ -688,22 +738,6 @@ __global__ __launch_bounds__(256) void k_inner(const InnerJob* __restrict__ jobs
     }
     st2(J.acc, (size_t)t * N + k, canon(a0x, m), canon(a0y, m));
     st2(J.acc, ((size_t)J.n_ext + t) * N + k, canon(a1x, m), canon(a1y, m));
-  }
-}
-
-// rescale: centred top limb -> residues mod q_i, i < n_chain (coefficient domain)
-__global__ __launch_bounds__(256) void k_spread_centred(const SpreadJob* __restrict__ jobs, DevTables T) {
-  const SpreadJob J = jobs[blockIdx.z];
-  const int N = 1 << T.log_n;
-  const int i = blockIdx.y;
-  if (i >= J.n_chain) return;
-  const double qt = T.mod[J.src_prime];
-  const Mod m{KPTR(T.mod)[i], KPTR(T.minv)[i]};
-  const double half = (qt - 1.0) * 0.5;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < N; k += gridDim.x * blockDim.x) {
-    double v = J.src[k];
-    if (v > half) v -= qt;
-    J.dst[(size_t)i * N + k] = canon(v, m);
   }
 }
 
@@ -914,37 +948,44 @@ namespace secpe {
 
 static inline int ew_blocks(int n) { return (n + 256 * 2 - 1) / (256 * 2); }
 
-void launch_ntt(const DevTables& T, bool inverse, const NttJob* jobs, int n_jobs, int max_limbs, hipStream_t s,
-                int prof_pass, hipEvent_t e0, hipEvent_t e1) {
+int ntt_pass_count(const DevTables& T) { return T.log_n <= 12 ? 1 : 2; }
+
+// one pass of the negacyclic NTT over every job: a single pass for N <= 2^12;
+// otherwise N = 2^k1 x 2^k2 with pass 0 = columns then rows (forward) or rows
+// then columns (inverse); the second pass works in place on what the first
+// wrote to dst
+void launch_ntt_pass(const DevTables& T, bool inverse, const NttJob* jobs, int n_jobs, int max_limbs, int pass,
+                     hipStream_t s) {
   if (n_jobs <= 0 || max_limbs <= 0) return;
   const int log_n = T.log_n;
   const int N = 1 << log_n;
-  auto run = [&](int logs, int mode, int second) {
-    int g = 0;
-    void* fn = ntt_kernel(logs, mode, inverse, &g);
-    const int tiles = (N >> logs) / g;
-    dim3 grid(tiles, max_limbs, n_jobs);
-    const NttJob* jp = jobs;
-    DevTables t = T;
-    int sec = second;
-    void* args[] = {(void*)&jp, (void*)&t, (void*)&sec};
-    if (prof_pass == second && e0) (void)hipEventRecord(e0, s);
-    (void)hipLaunchKernel(fn, grid, dim3(256), args, ntt_lds_bytes(logs, g), s);
-    if (prof_pass == second && e1) (void)hipEventRecord(e1, s);
-  };
-  if (log_n <= 12) {
-    run(log_n, NTT_SINGLE, 0);
-    return;
-  }
-  // the second pass works in place on what the first wrote to dst
   const int k1 = log_n / 2, k2 = log_n - k1;
-  if (!inverse) {
-    run(k1, NTT_COL, 0);
-    run(k2, NTT_ROW, 1);
+  int logs, mode;
+  if (log_n <= 12) {
+    logs = log_n;
+    mode = NTT_SINGLE;
+  } else if (!inverse) {
+    logs = pass == 0 ? k1 : k2;
+    mode = pass == 0 ? NTT_COL : NTT_ROW;
   } else {
-    run(k2, NTT_ROW, 0);
-    run(k1, NTT_COL, 1);
+    logs = pass == 0 ? k2 : k1;
+    mode = pass == 0 ? NTT_ROW : NTT_COL;
   }
+  int g = 0;
+  void* fn = ntt_kernel(logs, mode, inverse, &g);
+  const int tiles = (N >> logs) / g;
+  // limb-major: consecutive workgroups transform the same limb (prime) of
+  // successive jobs, so that prime's twiddles are reused from L2
+  dim3 grid(tiles, n_jobs, max_limbs);
+  const NttJob* jp = jobs;
+  DevTables t = T;
+  int sec = log_n <= 12 ? 0 : pass;
+  void* args[] = {(void*)&jp, (void*)&t, (void*)&sec};
+  (void)hipLaunchKernel(fn, grid, dim3(256), args, ntt_lds_bytes(logs, g), s);
+}
+
+void launch_ntt(const DevTables& T, bool inverse, const NttJob* jobs, int n_jobs, int max_limbs, hipStream_t s) {
+  for (int p = 0; p < ntt_pass_count(T); ++p) launch_ntt_pass(T, inverse, jobs, n_jobs, max_limbs, p, s);
 }
 
 void launch_ew(const DevTables& T, const EwJob* jobs, int n_jobs, int max_limbs, hipStream_t s) {
@@ -964,13 +1005,8 @@ void launch_moddown_conv(const DevTables& T, const ModDownJob* jobs, int n_jobs,
 }
 void launch_inner(const DevTables& T, const InnerJob* jobs, int n_jobs, int max_ext, hipStream_t s) {
   if (n_jobs <= 0 || max_ext <= 0) return;
-  dim3 grid(n_jobs, max_ext, ew_blocks(1 << T.log_n));
+  dim3 grid(ew_blocks(1 << T.log_n), n_jobs, max_ext);
   hipLaunchKernelGGL(k_inner, grid, dim3(256), 0, s, jobs, T);
-}
-void launch_spread_centred(const DevTables& T, const SpreadJob* jobs, int n_jobs, int max_chain, hipStream_t s) {
-  if (n_jobs <= 0 || max_chain <= 0) return;
-  dim3 grid(ew_blocks(1 << T.log_n), max_chain, n_jobs);
-  hipLaunchKernelGGL(k_spread_centred, grid, dim3(256), 0, s, jobs, T);
 }
 void launch_automorph(const DevTables& T, const AutoJob* jobs, int n_jobs, int max_limbs, hipStream_t s) {
   if (n_jobs <= 0 || max_limbs <= 0) return;

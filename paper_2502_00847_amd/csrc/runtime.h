@@ -60,6 +60,9 @@ struct GraphEntry {
 struct Ctx {
   // parameters
   int log_n = 0, N = 0, n_q = 0, n_p = 0, alpha = 0, dnum = 0, n_mod = 0;
+  // two-pass NTT launches are issued in job groups of at most this many bytes
+  // of limb data (0 = one group); SECPE_NTT_CHUNK_MB overrides the default
+  size_t ntt_chunk_bytes = 0;
   int q_bits = 0, p_bits = 0, log_scale = 0, dg = 2, df = 2, min_level = 1;
   std::vector<uint64_t> mod;
   int device = 0;
@@ -115,7 +118,7 @@ void destroy_context(Ctx& c);
 // ---------------------------------------------------------------------------
 // command list: descriptors in one blob, launches replayed in order
 // ---------------------------------------------------------------------------
-enum CmdKind { C_NTT, C_EW, C_MODUP, C_MODDOWN, C_INNER, C_SPREAD, C_AUTO, C_LIFT, C_SAMPLE, C_INTSPREAD, C_ENCODE, C_DECODE };
+enum CmdKind { C_NTT, C_EW, C_MODUP, C_MODDOWN, C_INNER, C_AUTO, C_LIFT, C_SAMPLE, C_INTSPREAD, C_ENCODE, C_DECODE };
 
 struct Cmd {
   int kind;
@@ -186,7 +189,6 @@ class Builder {
   void modup(const std::vector<ModUpJob>& v);
   void moddown(const std::vector<ModDownJob>& v);
   void inner(const std::vector<InnerJob>& v);
-  void spread(const std::vector<SpreadJob>& v);
   void automorph(const std::vector<AutoJob>& v);
   void lift(const std::vector<LiftJob>& v);
   void sample(const std::vector<SampleJob>& v);

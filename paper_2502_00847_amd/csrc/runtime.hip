@@ -226,6 +226,7 @@ int build_context(Ctx& c, int log_n, int n_q, int q_bits, int n_p, int p_bits, i
     h[o_crt + 2 * t + 1] = (double)hmul(c.mod[0] % q, c.mod[1] % q, q);
   }
   c.q0inv_q1 = (double)hinv(c.mod[0] % c.mod[1], c.mod[1]);
+  if (const char* e = getenv("SECPE_NTT_CHUNK_MB")) c.ntt_chunk_bytes = (size_t)std::max(0L, atol(e)) << 20;
   // ----- upload -----
   if (hipSetDevice(device) != hipSuccess) return SECPE_EDEVICE_INTERNAL;
   c.tab_bytes = h.size() * sizeof(double);
@@ -345,6 +346,8 @@ const double* Builder::put_residues(int64_t K, int n_limbs) {
 }
 
 void Builder::push(int kind, int n, int max_y, size_t off, bool inv, int64_t units) {
+  // jobs index a grid dimension, which holds at most 65535 workgroups
+  if (n > 65535) { fail(-1, "more than 65535 jobs in one launch: split the batch"); return; }
   Cmd c{};
   c.kind = kind;
   c.n = n;
@@ -395,12 +398,6 @@ void Builder::inner(const std::vector<InnerJob>& v) {
   for (auto& j : v) { my = std::max(my, j.n_ext); units += (int64_t)j.n_ext * (3 * j.n_digits + 2); }
   PUSH_JOBS(C_INNER, v, my, false, units);
 }
-void Builder::spread(const std::vector<SpreadJob>& v) {
-  int my = 0;
-  int64_t units = 0;
-  for (auto& j : v) { my = std::max(my, j.n_chain); units += j.n_chain + 1; }
-  PUSH_JOBS(C_SPREAD, v, my, false, units);
-}
 void Builder::automorph(const std::vector<AutoJob>& v) {
   int my = 0;
   int64_t units = 0;
@@ -441,7 +438,6 @@ int prof_kind_of(const Cmd& k) {
     case C_MODDOWN: return PROF_MODDOWN;
     case C_INNER: return PROF_INNER;
     case C_AUTO: return PROF_AUTO;
-    case C_SPREAD: return PROF_SPREAD;
     default: return -1;
   }
 }
@@ -460,13 +456,40 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
   hipStream_t s = c.stream;
   for (const Cmd& k : cmds) {
     const void* j = arena + k.off;
-    // one pass of the forward NTT (N > 2^12: pass 0 = columns, pass 1 = rows)
-    if ((c.prof_kind == PROF_NTT_FWD_COL || c.prof_kind == PROF_NTT_FWD_ROW) && k.kind == C_NTT && !k.inv &&
-        c.log_n > 12) {
-      hipEvent_t e0 = prof_event(c), e1 = prof_event(c);
-      c.prof_launches++;
-      c.prof_units += k.units;
-      launch_ntt(T, false, (const NttJob*)j, k.n, k.max_y, s, c.prof_kind == PROF_NTT_FWD_ROW ? 1 : 0, e0, e1);
+    if (k.kind == C_NTT && ntt_pass_count(T) == 2) {
+      // Two-pass NTT, issued in groups of jobs whose data fits ntt_chunk_bytes
+      // so the intermediate between the passes can stay in the Infinity
+      // Cache.  The pass profilers bracket each launch of their pass.
+      const int pass_prof = c.prof_kind == PROF_NTT_FWD_COL && !k.inv ? 0
+                            : c.prof_kind == PROF_NTT_FWD_ROW && !k.inv ? 1 : -1;
+      const bool whole_prof = c.prof_kind >= 0 && prof_kind_of(k) == c.prof_kind;
+      const size_t per_job = (size_t)std::max(1, k.max_y) * c.N * sizeof(double);
+      int chunk = k.n;
+      if (c.ntt_chunk_bytes > 0) chunk = (int)std::max<size_t>(1, c.ntt_chunk_bytes / per_job);
+      hipEvent_t w0 = whole_prof ? prof_event(c) : nullptr;
+      if (w0) (void)hipEventRecord(w0, s);
+      if (whole_prof) { c.prof_launches++; c.prof_units += k.units; }
+      const NttJob* jobs = (const NttJob*)j;
+      for (int j0 = 0; j0 < k.n; j0 += chunk) {
+        const int nj = std::min(chunk, k.n - j0);
+        for (int pass = 0; pass < 2; ++pass) {
+          hipEvent_t e0 = pass == pass_prof ? prof_event(c) : nullptr;
+          if (e0) {
+            (void)hipEventRecord(e0, s);
+            c.prof_launches++;
+          }
+          launch_ntt_pass(T, k.inv, jobs + j0, nj, k.max_y, pass, s);
+          if (e0) {
+            hipEvent_t e1 = prof_event(c);
+            if (e1) (void)hipEventRecord(e1, s);
+          }
+        }
+      }
+      if (pass_prof >= 0) c.prof_units += k.units;
+      if (w0) {
+        hipEvent_t w1 = prof_event(c);
+        if (w1) (void)hipEventRecord(w1, s);
+      }
       continue;
     }
     const bool prof = c.prof_kind >= 0 && prof_kind_of(k) == c.prof_kind;
@@ -482,7 +505,6 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
       case C_MODUP: launch_modup(T, (const ModUpJob*)j, k.n, s); break;
       case C_MODDOWN: launch_moddown_conv(T, (const ModDownJob*)j, k.n, s); break;
       case C_INNER: launch_inner(T, (const InnerJob*)j, k.n, k.max_y, s); break;
-      case C_SPREAD: launch_spread_centred(T, (const SpreadJob*)j, k.n, k.max_y, s); break;
       case C_AUTO: launch_automorph(T, (const AutoJob*)j, k.n, k.max_y, s); break;
       case C_LIFT: launch_lift(T, (const LiftJob*)j, k.n, c.crt_tab, c.q0inv_q1, s); break;
       case C_SAMPLE: launch_sample(T, (const SampleJob*)j, k.n, k.max_y, s); break;
@@ -569,38 +591,30 @@ void Builder::key_switch(const std::vector<KsItem>& items) {
   ks_front(items, tmp);
   std::vector<NttJob> j_inv_acc, j_fwd_conv;
   std::vector<ModDownJob> j_down;
-  std::vector<EwJob> j_comb;
   for (size_t i = 0; i < items.size(); ++i) {
     const KsItem& it = items[i];
     const int nc = it.level + 1, n_ext = tmp[i].n_ext;
     double* acc = tmp[i].acc;
     double* conv = scratch((size_t)2 * nc * N);
     for (int w = 0; w < 2; ++w) {
-      double* sp = acc + ((size_t)w * n_ext + nc) * N;
+      double* aw = acc + (size_t)w * n_ext * N;
+      double* sp = aw + (size_t)nc * N;
       j_inv_acc.push_back(NttJob{sp, sp, n_p, 0, 0, 0});
       double* cv = conv + (size_t)w * nc * N;
       j_down.push_back(ModDownJob{sp, cv, C.md_cinv, C.md_chat, nc, -1});
-      j_fwd_conv.push_back(NttJob{cv, cv, nc, nc, 0, 0});
+      // out_w = base_w + (acc_w - NTT(conv_w)) P^-1, fused into the transform
+      NttJob f{cv, cv, nc, nc, 0, 0};
+      f.epi = EPI_MODDOWN;
+      f.eb = aw;
+      f.ebase = w ? it.base1 : it.base0;
+      f.eout = w ? it.out1 : it.out0;
+      f.ek = C.md_pinv;
+      j_fwd_conv.push_back(f);
     }
-    EwJob e{};
-    e.o0 = it.out0;
-    e.o1 = it.out1;
-    e.a0 = it.base0;
-    e.a1 = it.base1;
-    e.b0 = acc;
-    e.b1 = acc + (size_t)n_ext * N;
-    e.c0 = conv;
-    e.c1 = conv + (size_t)nc * N;
-    e.k = C.md_pinv;
-    e.n_limbs = nc;
-    e.n_chain = nc;
-    e.op = EW_MODDOWN;
-    j_comb.push_back(e);
   }
   ntt(j_inv_acc, true);
   moddown(j_down);
   ntt(j_fwd_conv, false);
-  ew(j_comb);
   counters[3] += (int64_t)items.size();
 }
 
@@ -622,12 +636,12 @@ std::vector<CT> Builder::relin_rescale(const std::vector<Deg2>& xs) {
   std::vector<CT> out;
   std::vector<NttJob> j_inv_acc, j_fwd_conv;
   std::vector<ModDownJob> j_conv;
-  std::vector<EwJob> j_comb;
   for (size_t i = 0; i < xs.size(); ++i) {
     const Deg2& x = xs[i];
     const int l = x.level, nc = l + 1, n_ext = tmp[i].n_ext;
     double* acc = tmp[i].acc;
     double* conv = scratch((size_t)2 * l * N);
+    CT o = new_ct(l - 1, x.scale / (double)C.mod[l]);
     for (int w = 0; w < 2; ++w) {
       double* aw = acc + (size_t)w * n_ext * N;
       // limbs l .. l+n_p of the extended basis: q_l, then the special primes
@@ -635,30 +649,21 @@ std::vector<CT> Builder::relin_rescale(const std::vector<Deg2>& xs) {
       double* cv = conv + (size_t)w * l * N;
       j_conv.push_back(ModDownJob{aw + (size_t)l * N, cv, C.rr_cinv + (size_t)l * nb,
                                   C.rr_chat + (size_t)l * n_q * nb, l, l});
-      j_fwd_conv.push_back(NttJob{cv, cv, l, l, 0, 0});
+      // out_w = (P d_w + acc_w - NTT(conv_w)) (P q_l)^-1, fused into the transform
+      NttJob f{cv, cv, l, l, 0, 0};
+      f.epi = EPI_RRCOMB;
+      f.ea = w ? x.d1 : x.d0;
+      f.eb = aw;
+      f.eout = w ? c1(o) : c0(o);
+      f.ek = C.rr_inv + (size_t)l * n_q;
+      f.ek2 = C.p_mod_q;
+      j_fwd_conv.push_back(f);
     }
-    CT o = new_ct(l - 1, x.scale / (double)C.mod[l]);
-    EwJob e{};
-    e.o0 = c0(o);
-    e.o1 = c1(o);
-    e.a0 = x.d0;
-    e.a1 = x.d1;
-    e.b0 = acc;
-    e.b1 = acc + (size_t)n_ext * N;
-    e.c0 = conv;
-    e.c1 = conv + (size_t)l * N;
-    e.k = C.rr_inv + (size_t)l * n_q;
-    e.k2 = C.p_mod_q;
-    e.n_limbs = l;
-    e.n_chain = l;
-    e.op = EW_RRCOMB;
-    j_comb.push_back(e);
     out.push_back(o);
   }
   ntt(j_inv_acc, true);
   moddown(j_conv);
   ntt(j_fwd_conv, false);
-  ew(j_comb);
   counters[2] += (int64_t)xs.size();
   counters[3] += (int64_t)xs.size();
   return out;
@@ -707,41 +712,31 @@ std::vector<Builder::Deg2> Builder::tensor2(const std::vector<TensorItem>& v) {
 void Builder::rescale(std::vector<CT>& xs) {
   const int N = C.N;
   std::vector<NttJob> j_top, j_fwd;
-  std::vector<SpreadJob> j_sp;
-  std::vector<EwJob> j_ew;
   for (CT& x : xs) {
     const int l = x.level;
     if (l < 1) { fail(-3, "rescale below level 0"); return; }
     double* top = scratch(2 * (size_t)N);
     double* spr = scratch(2 * (size_t)l * N);
     for (int w = 0; w < 2; ++w) {
-      const double* src = w ? c1(x) : c0(x);
+      double* cw = w ? c1(x) : c0(x);
       double* tw = top + (size_t)w * N;
       // transform only limb l: limbs [0, l) skipped; dst shifted so limb l lands in tw
-      j_top.push_back(NttJob{src, tw - (size_t)l * N, l + 1, l + 1, 0, l});
-      double* sw = spr + (size_t)w * l * N;
-      j_sp.push_back(SpreadJob{tw, sw, l, l});
-      j_fwd.push_back(NttJob{sw, sw, l, l, 0, 0});
+      j_top.push_back(NttJob{cw, tw - (size_t)l * N, l + 1, l + 1, 0, l});
+      // forward NTT of the centred top limb reduced mod each q_i (fused
+      // spread), then c_i <- (c_i - that) q_l^-1 in place (fused epilogue)
+      NttJob f{tw, spr + (size_t)w * l * N, l, l, 0, 0};
+      f.spread_from = l + 1;
+      f.epi = EPI_RESCALE;
+      f.ea = cw;
+      f.eout = cw;
+      f.ek = C.rs_tab + (size_t)l * C.n_q;
+      j_fwd.push_back(f);
     }
-    EwJob e{};
-    e.o0 = c0(x);
-    e.o1 = c1(x);
-    e.a0 = c0(x);
-    e.a1 = c1(x);
-    e.b0 = spr;
-    e.b1 = spr + (size_t)l * N;
-    e.k = C.rs_tab + (size_t)l * C.n_q;
-    e.n_limbs = l;
-    e.n_chain = l;
-    e.op = EW_RESCALE;
-    j_ew.push_back(e);
     x.scale = x.scale / (double)C.mod[l];
     x.level = l - 1;
   }
   ntt(j_top, true);
-  spread(j_sp);
   ntt(j_fwd, false);
-  ew(j_ew);
 }
 
 std::vector<CT> Builder::mul_relin(const std::vector<std::pair<CT, CT>>& ab, bool do_rescale) {
