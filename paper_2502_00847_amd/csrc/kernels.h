@@ -14,6 +14,10 @@ int ntt_pass_count(const DevTables& T);
 void launch_ntt_pass(const DevTables& T, bool inverse, const NttJob* jobs, int n_jobs, int max_limbs, int pass,
                      hipStream_t s);
 void launch_ntt(const DevTables& T, bool inverse, const NttJob* jobs, int n_jobs, int max_limbs, hipStream_t s);
+// For N > 2^12 the key-switch inner product runs fused with the row pass of
+// the ModUp outputs' forward NTT (whose column pass ran as an ordinary launch).
+bool inner_row_fused(const DevTables& T);
+void launch_inner_row(const DevTables& T, const InnerJob* jobs, int n_jobs, int max_ext, hipStream_t s);
 void launch_ew(const DevTables& T, const EwJob* jobs, int n_jobs, int max_limbs, hipStream_t s);
 void launch_modup(const DevTables& T, const ModUpJob* jobs, int n_jobs, hipStream_t s);
 void launch_moddown_conv(const DevTables& T, const ModDownJob* jobs, int n_jobs, hipStream_t s);

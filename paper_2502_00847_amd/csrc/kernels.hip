@@ -416,6 +416,116 @@ __global__ __launch_bounds__(256) void k_ntt2(const NttJob* __restrict__ jobs, D
   }
 }
 
+// Row pass of the forward transform on one G x S tile (rows row0 .. row0+G-1
+// of the limb at src, already through the column pass): rounds A and B as in
+// k_ntt2; the transformed tile is left in LDS (lazily reduced, |v| < 2.2p).
+template <int LOGS, int G>
+__device__ __forceinline__ void fwd_row_tile(double* lds, cgdbl* src, int row0, int k1, kdbl* tw, kdbl* twq,
+                                             const Mod& m) {
+  constexpr int S = 1 << LOGS;
+  constexpr int RB = LOGS - 4;
+  constexpr int NB = 1 << RB;
+  constexpr int GB = 16 / NB;
+  const int t = threadIdx.x;
+  const int va = t / NB, la = t % NB;
+  double x[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) x[e] = src[(size_t)(row0 + va) * S + e * NB + la];
+  ntt_round<LOGS, 4, NTT_ROW, false>(x, 0, RB, row0 + va, k1, tw, twq, m);
+#pragma unroll
+  for (int e = 0; e < 16; ++e) lds[lpad(va * S + e * NB + la)] = x[e];
+  __syncthreads();
+#pragma unroll
+  for (int gi = 0; gi < GB; ++gi) {
+    const int grp = t + gi * 256;
+    const int vb = grp / 16, hb = grp % 16;
+    double y[NB];
+#pragma unroll
+    for (int e = 0; e < NB; ++e) y[e] = lds[lpad(vb * S + hb * NB + e)];
+    ntt_round<LOGS, RB, NTT_ROW, false>(y, hb, 0, row0 + vb, k1, tw, twq, m);
+#pragma unroll
+    for (int e = 0; e < NB; ++e) lds[lpad(vb * S + hb * NB + e)] = y[e];
+  }
+  __syncthreads();
+}
+
+// Key-switch inner product fused with the row pass of the ModUp outputs'
+// forward transform (N > 2^12): for extended-basis limb t and one row tile,
+//   acc_w[t] = sum_j x_j[t] key_j[w][t],
+// x_j[t] = d[t] (NTT domain) inside digit j, else the row pass of ext_j[t]
+// (which has been through the column pass) computed here in LDS, so the
+// transformed ModUp outputs never go to HBM.  Grid (row tile, job, limb).
+template <int LOGS, int G>
+__global__ __launch_bounds__(256) void k_inner_row(const InnerJob* __restrict__ jobs, DevTables T) {
+  extern __shared__ double lds[];
+  constexpr int S = 1 << LOGS;
+  constexpr int NP = G * S / 2 / 256;   // pairs per thread
+  const InnerJob J = jobs[blockIdx.y];
+  const int t = blockIdx.z;
+  if (t >= J.n_ext) return;
+  const int log_n = T.log_n;
+  const int N = 1 << log_n;
+  const int n_mod = T.n_q + T.n_p;
+  const int pr = t < J.n_chain ? t : T.n_q + (t - J.n_chain);
+  const Mod m{KPTR(T.mod)[pr], KPTR(T.minv)[pr]};
+  kdbl* tw = KPTR(T.psi) + (size_t)pr * N;
+  kdbl* twq = KPTR(T.psiq) + (size_t)pr * N;
+  const int own = t < J.n_chain ? t / J.alpha : -1;
+  const int row0 = blockIdx.x * G;
+  const size_t tile = (size_t)row0 * S;
+  const int k1 = log_n - LOGS;
+  double a0x[NP], a0y[NP], a1x[NP], a1y[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) a0x[q] = a0y[q] = a1x[q] = a1y[q] = 0.0;
+  for (int j = 0; j < J.n_digits; ++j) {
+    if (j != own) fwd_row_tile<LOGS, G>(lds, CGPTR(J.ext) + ((size_t)j * J.n_ext + t) * N, row0, k1, tw, twq, m);
+    cgdbl* kb = CGPTR(J.key) + (((size_t)j * 2 + 0) * n_mod + pr) * N + tile;
+    cgdbl* ka = CGPTR(J.key) + (((size_t)j * 2 + 1) * n_mod + pr) * N + tile;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const int i = threadIdx.x + 256 * q;
+      double xx, xy;
+      if (j == own) {
+        const double2 v = ld2(J.d, (size_t)t * N + tile + 2 * i);
+        xx = v.x;
+        xy = v.y;
+      } else {
+        xx = canon(lds[lpad(2 * i)], m);
+        xy = canon(lds[lpad(2 * i + 1)], m);
+      }
+      const dv2 b = *(cgdbl2*)(kb + 2 * i);
+      const dv2 a = *(cgdbl2*)(ka + 2 * i);
+      a0x[q] += mul_mod(xx, b.x, m);
+      a0y[q] += mul_mod(xy, b.y, m);
+      a1x[q] += mul_mod(xx, a.x, m);
+      a1y[q] += mul_mod(xy, a.y, m);
+      if (j & 1) {
+        a0x[q] = red(a0x[q], m); a0y[q] = red(a0y[q], m);
+        a1x[q] = red(a1x[q], m); a1y[q] = red(a1y[q], m);
+      }
+    }
+    // the next digit's row pass overwrites the tile in LDS
+    if (j != own) __syncthreads();
+  }
+  const bool top = J.top0 && t == J.n_chain - 1;
+  const double pm = top ? KPTR(J.pmq)[t] : 0.0;
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    const size_t o = (size_t)t * N + tile + 2 * (threadIdx.x + 256 * q);
+    if (top) {
+      const double2 u0 = ld2(J.top0, o), u1 = ld2(J.top1, o);
+      a0x[q] = red(a0x[q], m) + mul_mod(u0.x, pm, m);
+      a0y[q] = red(a0y[q], m) + mul_mod(u0.y, pm, m);
+      a1x[q] = red(a1x[q], m) + mul_mod(u1.x, pm, m);
+      a1y[q] = red(a1y[q], m) + mul_mod(u1.y, pm, m);
+    }
+    st2(J.acc, o, canon(a0x[q], m), canon(a0y[q], m));
+    st2(J.acc, (size_t)J.n_ext * N + o, canon(a1x[q], m), canon(a1y[q], m));
+  }
+}
+template __global__ void k_inner_row<8, 16>(const InnerJob* __restrict__, DevTables);
+template __global__ void k_inner_row<7, 32>(const InnerJob* __restrict__, DevTables);
+
 size_t ntt_lds_bytes(int logs, int g) {
   const int n = g << logs;
   return (size_t)(n + (n >> 4)) * sizeof(double);
@@ -982,6 +1092,18 @@ void launch_ntt_pass(const DevTables& T, bool inverse, const NttJob* jobs, int n
   int sec = log_n <= 12 ? 0 : pass;
   void* args[] = {(void*)&jp, (void*)&t, (void*)&sec};
   (void)hipLaunchKernel(fn, grid, dim3(256), args, ntt_lds_bytes(logs, g), s);
+}
+
+bool inner_row_fused(const DevTables& T) { return T.log_n > 12; }
+
+void launch_inner_row(const DevTables& T, const InnerJob* jobs, int n_jobs, int max_ext, hipStream_t s) {
+  if (n_jobs <= 0 || max_ext <= 0) return;
+  const int log_n = T.log_n;
+  const int k2 = log_n - log_n / 2;   // row length of the two-pass split
+  const int g = k2 == 8 ? 16 : 32;
+  dim3 grid((1 << (log_n - k2)) / g, n_jobs, max_ext);
+  if (k2 == 8) hipLaunchKernelGGL((k_inner_row<8, 16>), grid, dim3(256), ntt_lds_bytes(8, 16), s, jobs, T);
+  else hipLaunchKernelGGL((k_inner_row<7, 32>), grid, dim3(256), ntt_lds_bytes(7, 32), s, jobs, T);
 }
 
 void launch_ntt(const DevTables& T, bool inverse, const NttJob* jobs, int n_jobs, int max_limbs, hipStream_t s) {

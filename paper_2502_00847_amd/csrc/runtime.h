@@ -118,7 +118,7 @@ void destroy_context(Ctx& c);
 // ---------------------------------------------------------------------------
 // command list: descriptors in one blob, launches replayed in order
 // ---------------------------------------------------------------------------
-enum CmdKind { C_NTT, C_EW, C_MODUP, C_MODDOWN, C_INNER, C_AUTO, C_LIFT, C_SAMPLE, C_INTSPREAD, C_ENCODE, C_DECODE };
+enum CmdKind { C_NTT, C_NTT_FIRST, C_EW, C_MODUP, C_MODDOWN, C_INNER, C_INNER_ROW, C_AUTO, C_LIFT, C_SAMPLE, C_INTSPREAD, C_ENCODE, C_DECODE };
 
 struct Cmd {
   int kind;
@@ -184,7 +184,9 @@ class Builder {
   const double* put_residues(int64_t K, int n_limbs);  // K mod q_t, t < n_limbs (chain)
 
   // raw launches
-  void ntt(const std::vector<NttJob>& v, bool inverse);
+  // first_pass_only: the column pass of a two-pass forward NTT (its row pass
+  // runs inside the fused inner product)
+  void ntt(const std::vector<NttJob>& v, bool inverse, bool first_pass_only = false);
   void ew(const std::vector<EwJob>& v);
   void modup(const std::vector<ModUpJob>& v);
   void moddown(const std::vector<ModDownJob>& v);

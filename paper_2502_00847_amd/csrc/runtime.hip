@@ -366,7 +366,7 @@ void Builder::push(int kind, int n, int max_y, size_t off, bool inv, int64_t uni
     push(KIND, (int)(V).size(), MAXY, (size_t)(p - arena_), INV, UNITS);        \
   } while (0)
 
-void Builder::ntt(const std::vector<NttJob>& v, bool inverse) {
+void Builder::ntt(const std::vector<NttJob>& v, bool inverse, bool first_pass_only) {
   int my = 0;
   int64_t units = 0;
   for (auto& j : v) {
@@ -374,7 +374,7 @@ void Builder::ntt(const std::vector<NttJob>& v, bool inverse) {
     const int lo = std::max(0, std::min(j.skip_lo, j.n_limbs)), hi = std::max(lo, std::min(j.skip_hi, j.n_limbs));
     units += j.n_limbs - (hi - lo);
   }
-  PUSH_JOBS(C_NTT, v, my, inverse, units);
+  PUSH_JOBS(first_pass_only ? C_NTT_FIRST : C_NTT, v, my, inverse, units);
 }
 void Builder::ew(const std::vector<EwJob>& v) {
   int my = 0;
@@ -396,7 +396,7 @@ void Builder::inner(const std::vector<InnerJob>& v) {
   int my = 0;
   int64_t units = 0;
   for (auto& j : v) { my = std::max(my, j.n_ext); units += (int64_t)j.n_ext * (3 * j.n_digits + 2); }
-  PUSH_JOBS(C_INNER, v, my, false, units);
+  PUSH_JOBS(inner_row_fused(C.T) ? C_INNER_ROW : C_INNER, v, my, false, units);
 }
 void Builder::automorph(const std::vector<AutoJob>& v) {
   int my = 0;
@@ -432,11 +432,13 @@ void Builder::decode(const int64_t* m, double* z, int nslots, double inv_scale) 
 // ---------------------------------------------------------------------------
 int prof_kind_of(const Cmd& k) {
   switch (k.kind) {
-    case C_NTT: return k.inv ? PROF_NTT_INV : PROF_NTT_FWD;
+    case C_NTT:
+    case C_NTT_FIRST: return k.inv ? PROF_NTT_INV : PROF_NTT_FWD;
     case C_EW: return PROF_EW;
     case C_MODUP: return PROF_MODUP;
     case C_MODDOWN: return PROF_MODDOWN;
-    case C_INNER: return PROF_INNER;
+    case C_INNER:
+    case C_INNER_ROW: return PROF_INNER;
     case C_AUTO: return PROF_AUTO;
     default: return -1;
   }
@@ -456,7 +458,7 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
   hipStream_t s = c.stream;
   for (const Cmd& k : cmds) {
     const void* j = arena + k.off;
-    if (k.kind == C_NTT && ntt_pass_count(T) == 2) {
+    if ((k.kind == C_NTT || k.kind == C_NTT_FIRST) && ntt_pass_count(T) == 2) {
       // Two-pass NTT, issued in groups of jobs whose data fits ntt_chunk_bytes
       // so the intermediate between the passes can stay in the Infinity
       // Cache.  The pass profilers bracket each launch of their pass.
@@ -468,11 +470,13 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
       if (c.ntt_chunk_bytes > 0) chunk = (int)std::max<size_t>(1, c.ntt_chunk_bytes / per_job);
       hipEvent_t w0 = whole_prof ? prof_event(c) : nullptr;
       if (w0) (void)hipEventRecord(w0, s);
-      if (whole_prof) { c.prof_launches++; c.prof_units += k.units; }
+      const int passes = k.kind == C_NTT_FIRST ? 1 : 2;
+      // a first-pass-only launch counts as half of its limb transforms
+      if (whole_prof) { c.prof_launches++; c.prof_units += passes == 2 ? k.units : k.units / 2; }
       const NttJob* jobs = (const NttJob*)j;
       for (int j0 = 0; j0 < k.n; j0 += chunk) {
         const int nj = std::min(chunk, k.n - j0);
-        for (int pass = 0; pass < 2; ++pass) {
+        for (int pass = 0; pass < passes; ++pass) {
           hipEvent_t e0 = pass == pass_prof ? prof_event(c) : nullptr;
           if (e0) {
             (void)hipEventRecord(e0, s);
@@ -485,7 +489,7 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
           }
         }
       }
-      if (pass_prof >= 0) c.prof_units += k.units;
+      if (pass_prof >= 0 && pass_prof < passes) c.prof_units += k.units;
       if (w0) {
         hipEvent_t w1 = prof_event(c);
         if (w1) (void)hipEventRecord(w1, s);
@@ -501,10 +505,12 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
     }
     switch (k.kind) {
       case C_NTT: launch_ntt(T, k.inv, (const NttJob*)j, k.n, k.max_y, s); break;
+      case C_NTT_FIRST: launch_ntt_pass(T, k.inv, (const NttJob*)j, k.n, k.max_y, 0, s); break;
       case C_EW: launch_ew(T, (const EwJob*)j, k.n, k.max_y, s); break;
       case C_MODUP: launch_modup(T, (const ModUpJob*)j, k.n, s); break;
       case C_MODDOWN: launch_moddown_conv(T, (const ModDownJob*)j, k.n, s); break;
       case C_INNER: launch_inner(T, (const InnerJob*)j, k.n, k.max_y, s); break;
+      case C_INNER_ROW: launch_inner_row(T, (const InnerJob*)j, k.n, k.max_y, s); break;
       case C_AUTO: launch_automorph(T, (const AutoJob*)j, k.n, k.max_y, s); break;
       case C_LIFT: launch_lift(T, (const LiftJob*)j, k.n, c.crt_tab, c.q0inv_q1, s); break;
       case C_SAMPLE: launch_sample(T, (const SampleJob*)j, k.n, k.max_y, s); break;
@@ -580,7 +586,7 @@ void Builder::ks_front(const std::vector<KsItem>& items, std::vector<KsTmp>& tmp
   }
   ntt(j_inv, true);
   modup(j_up);
-  ntt(j_fwd_ext, false);
+  ntt(j_fwd_ext, false, inner_row_fused(C.T));
   inner(j_in);
 }
 
