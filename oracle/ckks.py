@@ -24,7 +24,7 @@ def _load():
     vp, u64, i64, dbl, ci = C.c_void_p, C.c_uint64, C.c_int64, C.c_double, C.c_int
     P = C.POINTER
     sig = {
-        "orc_create": (vp, [ci, ci, ci, ci, ci, ci, ci, ci, ci]),
+        "orc_create": (vp, [ci, ci, ci, ci, ci, ci, ci, ci, ci, ci]),
         "orc_destroy": (None, [vp]),
         "orc_num_primes": (ci, [vp]),
         "orc_primes": (None, [vp, P(u64)]),
@@ -121,9 +121,10 @@ class Ct:
 class Oracle:
     """Plain RNS-CKKS context: chain primes q_0..q_L, special primes p_0..p_{alpha-1}."""
 
-    def __init__(self, log_n, n_q, q_bits, n_p, p_bits, log_scale, dg=2, df=2, min_level=1):
+    def __init__(self, log_n, n_q, q_bits, n_p, p_bits, log_scale, dg=2, df=2, min_level=1, refresh_level=0):
         self.lib = _load()
-        self.h = self.lib.orc_create(log_n, n_q, q_bits, n_p, p_bits, log_scale, dg, df, min_level)
+        self.h = self.lib.orc_create(log_n, n_q, q_bits, n_p, p_bits, log_scale, dg, df, min_level, refresh_level)
+        self.refresh_level = refresh_level if 0 < refresh_level < n_q else n_q - 1
         self.log_n, self.n = log_n, 1 << log_n
         self.n_q, self.n_p, self.alpha = n_q, n_p, n_p
         self.dnum = (n_q + n_p - 1) // n_p
@@ -132,7 +133,7 @@ class Oracle:
 
     @classmethod
     def from_params(cls, params):
-        keys = ("log_n", "n_q", "q_bits", "n_p", "p_bits", "log_scale", "dg", "df", "min_level")
+        keys = ("log_n", "n_q", "q_bits", "n_p", "p_bits", "log_scale", "dg", "df", "min_level", "refresh_level")
         return cls(**{k: params[k] for k in keys if k in params})
 
     def __del__(self):

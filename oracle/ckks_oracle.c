@@ -151,6 +151,7 @@ typedef struct {
   int log_scale;
   int dg, df;
   int min_level;
+  int refresh_level;    /* level a refreshed ciphertext is re-encrypted at */
   uint64_t* mod;        /* n_q chain primes, then n_p special primes */
   /* per prime NTT tables */
   uint64_t** psi_pow;   /* psi^i */
@@ -218,8 +219,9 @@ static uint64_t find_psi(uint64_t q, uint64_t n) {
   }
 }
 
+/* refresh_level: level of a refreshed ciphertext (<= 0 or above the top: the top level) */
 ORC_API void* orc_create(int log_n, int n_q, int q_bits, int n_p, int p_bits, int log_scale,
-                         int dg, int df, int min_level) {
+                         int dg, int df, int min_level, int refresh_level) {
   if (log_n < 3 || log_n > 17 || n_q < 2 || n_p < 1 || q_bits > 61 || p_bits > 61) die("bad parameters");
   orc_ctx* c = (orc_ctx*)xcalloc(1, sizeof(orc_ctx));
   c->log_n = log_n;
@@ -232,6 +234,7 @@ ORC_API void* orc_create(int log_n, int n_q, int q_bits, int n_p, int p_bits, in
   c->dg = dg;
   c->df = df;
   c->min_level = min_level;
+  c->refresh_level = (refresh_level <= 0 || refresh_level > n_q - 1) ? n_q - 1 : refresh_level;
   int np = n_q + n_p, n = c->n;
   c->mod = (uint64_t*)xcalloc(np, sizeof(uint64_t));
   make_primes(c, q_bits, p_bits);
@@ -1135,7 +1138,7 @@ static orc_ct* op_rotate(orc_ctx* c, const orc_ct* a, int64_t step) {
 static orc_ct* op_refresh(orc_ctx* c, const orc_ct* a, uint64_t seed, uint64_t index) {
   i128* m = (i128*)xcalloc(c->n, sizeof(i128));
   decrypt_int(c, a, m);
-  orc_ct* x = encrypt_int(c, m, a->scale, seed, PUR_REFRESH, index, c->n_q - 1);
+  orc_ct* x = encrypt_int(c, m, a->scale, seed, PUR_REFRESH, index, c->refresh_level);
   free(m);
   c->counters[CNT_REFRESH]++;
   return x;
@@ -1274,7 +1277,7 @@ typedef struct {
 
 static orc_ct* maybe_refresh(orc_ctx* c, orc_ct* x, int need, refresher* rf) {
   if (x->level - need >= c->min_level) return x;
-  if (c->n_q - 1 - need < c->min_level) die("modulus chain too short for one unit");
+  if (c->refresh_level - need < c->min_level) die("modulus chain too short for one unit");
   orc_ct* y = op_refresh(c, x, rf->seed, rf->next++);
   ct_free(x);
   return y;
@@ -1317,7 +1320,7 @@ static orc_ct* op_max(orc_ctx* c, const orc_ct* a, const orc_ct* b, refresher* r
     for (int i = 0; i < total; ++i) {
       int last = i == total - 1;
       int need = 4 + (last ? 1 : 0);
-      if (lvl - need < c->min_level) lvl = c->n_q - 1;
+      if (lvl - need < c->min_level) lvl = c->refresh_level;
       if (lvl - need < c->min_level) die("modulus chain too short for one unit");
       lvl -= 4;
     }

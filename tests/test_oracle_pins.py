@@ -455,6 +455,39 @@ def test_refresh_preserves_message(tiny):
     assert np.abs(o.decrypt(rf) - o.decrypt(ct)).max() <= 21
 
 
+def test_refresh_below_the_top_level():
+    """With refresh_level = 6 the stand-in re-encrypts at level 6: same message (up to a
+    fresh e), and its limbs are the first seven limbs of the top-level re-encryption
+    (the randomness is per limb and per coefficient, independent of the level)."""
+    o5 = make_oracle("tiny_r6")
+    ot = make_oracle("tiny")
+    for o in (o5, ot):
+        o.keygen(123, [1])
+    z = np.random.default_rng(10).uniform(-1, 1, o5.slots)
+    ct5 = o5.lower(o5.encrypt(o5.encode(z, 2.0**40), 2.0**40, 3), 2)
+    ctt = ot.lower(ot.encrypt(ot.encode(z, 2.0**40), 2.0**40, 3), 2)
+    r5, rt = o5.refresh(ct5, 44, 1), ot.refresh(ctt, 44, 1)
+    assert r5.level == 6 and rt.level == ot.n_q - 1
+    assert np.abs(o5.decrypt(r5) - o5.decrypt(ct5)).max() <= 21
+    assert np.array_equal(r5.export(), rt.export()[:, :7])
+
+
+def test_argmax_with_low_refresh_level():
+    """Algorithm 1 end to end with refreshes at level 6 (one Sign polynomial per
+    refresh): the decrypted index equals the plaintext argmax."""
+    o = make_oracle("tiny_r6")
+    o.keygen(5, argmax_rotation_steps(8, 8, o.slots))
+    for q, (K, C) in enumerate([(3, 5), (4, 3)]):
+        y = W.logits(9, 100 + q, K, C)
+        dmin, dmax = W.d_bounds(K)
+        o.reset_counters()
+        z = o.decrypt_decode(o.eval_argmax(o.encrypt_logits(y, 7 + q), K, C, dmin, dmax, 11 + q), C)
+        i0, _, margin = sim.t0_argmax(y)
+        if margin / (dmax - dmin) >= 2.0**-10:
+            assert sim.decoded_index(z) == i0
+        assert o.counters()["refresh"] >= 1
+
+
 # ---------------------------------------------------------- Sign polynomials -
 def test_f4_is_closed_form():
     """f_4 = sum_{i<=4} C(2i,i) 4^-i x (1-x^2)^i: expand with numpy polynomial algebra."""

@@ -13,15 +13,22 @@ import numpy as np
 
 # CKKS parameter sets.  n_q chain primes of q_bits, n_p special primes below
 # 2^p_bits (alpha = n_p primes per key-switch digit), scale 2^log_scale.
+# refresh_level: level a refreshed ciphertext comes back at (the paper's
+# bootstrapping leaves K = 14 levels, Sec. 4.1); absent = the top level.
 PARAMS = {
     # N=2^13, 8 x 30-bit primes + 1 special prime, scale 2^30 (correctness only)
     "toy": dict(log_n=13, n_q=8, q_bits=30, n_p=1, p_bits=51, log_scale=30, dg=2, df=2, min_level=1),
     # N=2^16, 24 x ~50-bit primes, 8 special primes (dnum = 3 digits), scale 2^50
-    "full": dict(log_n=16, n_q=24, q_bits=50, n_p=8, p_bits=51, log_scale=50, dg=2, df=2, min_level=1),
+    "full": dict(log_n=16, n_q=24, q_bits=50, n_p=8, p_bits=51, log_scale=50, dg=2, df=2, min_level=1,
+                 refresh_level=14),
     # N=2^16 with 3 special primes (dnum = 8 digits)
-    "full_a3": dict(log_n=16, n_q=24, q_bits=50, n_p=3, p_bits=51, log_scale=50, dg=2, df=2, min_level=1),
+    "full_a3": dict(log_n=16, n_q=24, q_bits=50, n_p=3, p_bits=51, log_scale=50, dg=2, df=2, min_level=1,
+                    refresh_level=14),
     # small parameter sets for fast unit tests
     "tiny": dict(log_n=10, n_q=8, q_bits=40, n_p=2, p_bits=51, log_scale=40, dg=2, df=2, min_level=1),
+    # tiny with refreshes re-encrypting below the top level
+    "tiny_r6": dict(log_n=10, n_q=8, q_bits=40, n_p=2, p_bits=51, log_scale=40, dg=2, df=2, min_level=1,
+                    refresh_level=6),
     "mini": dict(log_n=11, n_q=10, q_bits=45, n_p=4, p_bits=51, log_scale=45, dg=2, df=2, min_level=1),
 }
 
