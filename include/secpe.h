@@ -53,9 +53,11 @@ enum {
    and the next above), n_p special primes: the largest = 1 mod 2N below 2^p_bits.
    Key switching is hybrid with digits of alpha = n_p consecutive chain primes.
    Scale 2^log_scale.  Sign = f^df(g^dg(x)).  min_level: lowest level a
-   ciphertext may reach (decryption needs two limbs, so 1). */
+   ciphertext may reach (decryption needs two limbs, so 1).  refresh_level:
+   level at which the refresh stand-in for bootstrapping re-encrypts (the
+   paper's bootstrapping leaves K = 14 levels, Sec. 4.1); 0 = the top level. */
 typedef struct secpe_params {
-  int log_n, n_q, q_bits, n_p, p_bits, log_scale, dg, df, min_level;
+  int log_n, n_q, q_bits, n_p, p_bits, log_scale, dg, df, min_level, refresh_level;
 } secpe_params;
 
 /* A ciphertext: device buffer (layout above), its level and its scale. */

@@ -102,6 +102,7 @@ extern "C" int secpe_ctx_create(const secpe_params* p, int device, void* stream,
     return set_err(SECPE_EINVAL, "prime sizes must keep every modulus below 2^51");
   if (p->dg < 0 || p->df < 0 || p->dg + p->df < 1 || p->min_level < 1 || p->log_scale < 10 || p->log_scale > 60)
     return set_err(SECPE_EINVAL, "bad Sign or scale parameters");
+  if (p->refresh_level < 0) return set_err(SECPE_EINVAL, "refresh_level must be >= 0");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
     return set_err(SECPE_EDEVICE, "no such HIP device");
@@ -116,7 +117,7 @@ extern "C" int secpe_ctx_create(const secpe_params* p, int device, void* stream,
     x->own_stream = true;
   }
   int rc = build_context(x->c, p->log_n, p->n_q, p->q_bits, p->n_p, p->p_bits, p->log_scale, p->dg, p->df,
-                         p->min_level, device, s);
+                         p->min_level, p->refresh_level, device, s);
   if (rc) {
     destroy_context(x->c);
     if (x->own_stream) (void)hipStreamDestroy(s);

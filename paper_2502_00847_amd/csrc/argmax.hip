@@ -51,7 +51,7 @@ static void maybe_refresh(Builder& b, std::vector<QState*>& qs, std::vector<CT*>
   std::vector<CT> in;
   std::vector<uint64_t> seed, index;
   std::vector<size_t> who;
-  const int top = b.C.n_q - 1;
+  const int top = b.C.refresh_level;
   for (size_t i = 0; i < qs.size(); ++i) {
     CT& x = *cts[i];
     if (x.level - need[i] >= b.C.min_level) continue;
@@ -166,7 +166,7 @@ static void run_step(Builder& b, int kind, std::vector<QState*>& qs) {
         int lvl = s->d.level;
         for (int j = 0; j < total; ++j) {
           const int need = 4 + (j == total - 1 ? 1 : 0);
-          if (lvl - need < C.min_level) lvl = C.n_q - 1;
+          if (lvl - need < C.min_level) lvl = C.refresh_level;
           if (lvl - need < C.min_level) { b.fail(-3, "modulus chain too short for one unit"); return; }
           lvl -= 4;
         }

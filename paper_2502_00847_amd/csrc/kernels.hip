@@ -10,6 +10,9 @@
 
 namespace secpe {
 
+// largest key-switch digit (alpha primes) and special-prime count
+constexpr int MAX_DIGIT = 16;
+
 // ---------------------------------------------------------------------------
 // negacyclic NTT
 //
@@ -230,7 +233,14 @@ __global__ __launch_bounds__(256) void k_ntt(const NttJob* __restrict__ jobs, De
     for (int i = tid; i < G * S / 2; i += blockDim.x) {
       double a = lds[lpad(2 * i)];
       double b = lds[lpad(2 * i + 1)];
-      if (scale) { a = mul_w(red(a, m), ni, niq, m.p); b = mul_w(red(b, m), ni, niq, m.p); }
+      if (scale && J.ek) {
+        const double ys = KPTR(J.ek)[l];
+        a = mul_mod(red(a, m), ys, m);
+        b = mul_mod(red(b, m), ys, m);
+      } else if (scale) {
+        a = mul_w(red(a, m), ni, niq, m.p);
+        b = mul_w(red(b, m), ni, niq, m.p);
+      }
       if (epi) ntt_epilogue(J, l, (size_t)l * N + (size_t)row0 * S + 2 * i, a, b, m);
       else d2[i] = make_double2(canon(a, m), canon(b, m));
     }
@@ -294,6 +304,36 @@ __device__ __forceinline__ void ntt_round(double* x, int vhigh, int b_lo, int ro
   }
 }
 
+// Forward column pass from registers: x[e] holds element v = e*NB + la of
+// column va = t % G (la = t / G) of the tile whose first column is c0; runs
+// rounds A and B and stores the column-passed tile to dst (one limb).
+template <int LOGS, int G>
+__device__ __forceinline__ void fwd_col_from_regs(double* x, double* lds, gdbl* dst, int c0, int k1, kdbl* tw,
+                                                  kdbl* twq, const Mod& m) {
+  constexpr int S = 1 << LOGS;
+  constexpr int RB = LOGS - 4;
+  constexpr int NB = 1 << RB;
+  constexpr int GB = 16 / NB;
+  const int t = threadIdx.x;
+  const int C = (1 << (k1 + LOGS)) >> LOGS;
+  const int va = t % G, la = t / G;
+  ntt_round<LOGS, 4, NTT_COL, false>(x, 0, RB, va, k1, tw, twq, m);
+#pragma unroll
+  for (int e = 0; e < 16; ++e) lds[va * (S + 1) + e * NB + la] = x[e];
+  __syncthreads();
+#pragma unroll
+  for (int gi = 0; gi < GB; ++gi) {
+    const int grp = t + gi * 256;
+    const int vb = grp % G, hb = grp / G;
+    double y[NB];
+#pragma unroll
+    for (int e = 0; e < NB; ++e) y[e] = lds[vb * (S + 1) + hb * NB + e];
+    ntt_round<LOGS, RB, NTT_COL, false>(y, hb, 0, vb, k1, tw, twq, m);
+#pragma unroll
+    for (int e = 0; e < NB; ++e) dst[(size_t)(hb * NB + e) * C + c0 + vb] = canon(y[e], m);
+  }
+}
+
 template <int LOGS, int G, int MODE, bool INV>
 __global__ __launch_bounds__(256) void k_ntt2(const NttJob* __restrict__ jobs, DevTables T, int second) {
   extern __shared__ double lds[];
@@ -331,14 +371,18 @@ __global__ __launch_bounds__(256) void k_ntt2(const NttJob* __restrict__ jobs, D
   // LDS index: the column pass pads one element per vector (lanes run over
   // vectors), the row pass one per 16 elements (lanes run within a vector)
   auto lidx = [&](int vec, int v) -> int { return MODE == NTT_COL ? vec * (S + 1) + v : lpad(vec * S + v); };
-  if (!INV) {
-    // ---- round A straight from global memory
+  if (!INV && MODE == NTT_COL) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) x[e] = src[gaddr(va, e * NB + la)];
     if (spread) {
 #pragma unroll
       for (int e = 0; e < 16; ++e) x[e] = spread_in(x[e], q_src, m);
     }
+    fwd_col_from_regs<LOGS, G>(x, lds, dst, c0, k1, tw, twq, m);
+  } else if (!INV) {
+    // ---- round A straight from global memory
+#pragma unroll
+    for (int e = 0; e < 16; ++e) x[e] = src[gaddr(va, e * NB + la)];
     ntt_round<LOGS, 4, MODE, false>(x, 0, RB, row0 + va, k1, tw, twq, m);
 #pragma unroll
     for (int e = 0; e < 16; ++e) lds[lidx(va, e * NB + la)] = x[e];
@@ -407,10 +451,12 @@ __global__ __launch_bounds__(256) void k_ntt2(const NttJob* __restrict__ jobs, D
 #pragma unroll
     for (int e = 0; e < 16; ++e) x[e] = lds[lidx(va, e * NB + la)];
     ntt_round<LOGS, 4, MODE, true>(x, 0, RB, row0 + va, k1, tw, twq, m);
+    // J.ek set: the last pass multiplies by ek[l] (which includes N^-1) instead of N^-1
+    const double ys = (scale && J.ek) ? KPTR(J.ek)[l] : 0.0;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       double v = x[e];
-      if (scale) v = mul_w(red(v, m), ni, niq, m.p);
+      if (scale) v = J.ek ? mul_mod(red(v, m), ys, m) : mul_w(red(v, m), ni, niq, m.p);
       dst[gaddr(va, e * NB + la)] = canon(v, m);
     }
   }
@@ -525,6 +571,84 @@ __global__ __launch_bounds__(256) void k_inner_row(const InnerJob* __restrict__ 
 }
 template __global__ void k_inner_row<8, 16>(const InnerJob* __restrict__, DevTables);
 template __global__ void k_inner_row<7, 32>(const InnerJob* __restrict__, DevTables);
+
+// ModUp of one digit fused with the column pass of the forward transform of
+// its outputs (N > 2^12).  src holds y_i = [x_i (D/q_i)^-1]_{q_i} for the
+// digit's limbs (coefficient domain; the inverse transform of x wrote them
+// scaled).  A workgroup owns one column tile and a group of MODUP_EG
+// extended-basis limbs e outside the digit: it streams the digit's limbs
+// through registers once, accumulating
+//   out_e = sum_i y_i (D/q_i) mod p_e
+// for the whole group, then runs the column pass on each out_e; the result
+// (ready for the row pass, which the inner product does) goes to dst limb e.
+// Grid (tile, group, job): with a multiple of 8 tiles, every group of a tile
+// runs on the same XCD and rereads the digit's tile from its L2.
+constexpr int MODUP_EG = 4;
+
+template <int LOGS, int G>
+__global__ __launch_bounds__(256) void k_modup_col(const ModUpJob* __restrict__ jobs, DevTables T) {
+  extern __shared__ double lds[];
+  constexpr int RB = LOGS - 4;
+  constexpr int NB = 1 << RB;
+  const ModUpJob J = jobs[blockIdx.z];
+  const int dsz = J.digit_hi - J.digit_lo;
+  const int n_out = J.n_ext - dsz;
+  const int g0 = blockIdx.y * MODUP_EG;
+  if (g0 >= n_out) return;
+  const int ng = min(MODUP_EG, n_out - g0);
+  const int log_n = T.log_n;
+  const int N = 1 << log_n;
+  const int k1 = log_n - LOGS;
+  const int C = N >> LOGS;
+  const int t = threadIdx.x;
+  const int va = t % G, la = t / G;
+  const int c0 = blockIdx.x * G;
+  int ee[MODUP_EG], pe[MODUP_EG];
+  Mod me[MODUP_EG];
+#pragma unroll
+  for (int g = 0; g < MODUP_EG; ++g) {
+    const int idx = min(g0 + g, n_out - 1);
+    const int e = idx < J.digit_lo ? idx : idx + dsz;   // skip the digit's own limbs
+    ee[g] = e;
+    pe[g] = e < J.n_chain ? e : T.n_q + (e - J.n_chain);
+    me[g] = Mod{KPTR(T.mod)[pe[g]], KPTR(T.minv)[pe[g]]};
+  }
+  double acc[MODUP_EG][16];
+#pragma unroll
+  for (int g = 0; g < MODUP_EG; ++g)
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[g][k] = 0.0;
+  cgdbl* ysrc = CGPTR(J.src) + (size_t)J.digit_lo * N;
+  for (int i = 0; i < dsz; ++i) {
+    double y[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) y[k] = ysrc[(size_t)i * N + (size_t)(k * NB + la) * C + c0 + va];
+#pragma unroll
+    for (int g = 0; g < MODUP_EG; ++g) {
+      const double c = KPTR(J.chat)[(size_t)pe[g] * dsz + i];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        acc[g][k] += mul_mod(y[k], c, me[g]);
+        if (i & 1) acc[g][k] = red(acc[g][k], me[g]);
+      }
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < MODUP_EG; ++g) {
+    if (g >= ng) break;
+    kdbl* tw = KPTR(T.psi) + (size_t)pe[g] * N;
+    kdbl* twq = KPTR(T.psiq) + (size_t)pe[g] * N;
+    double x[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) x[k] = red(acc[g][k], me[g]);
+    fwd_col_from_regs<LOGS, G>(x, lds, GPTR(J.dst) + (size_t)ee[g] * N, c0, k1, tw, twq, me[g]);
+    // the next limb's column pass reuses the LDS tile
+    __syncthreads();
+  }
+}
+template __global__ void k_modup_col<8, 16>(const ModUpJob* __restrict__, DevTables);
+template __global__ void k_modup_col<7, 32>(const ModUpJob* __restrict__, DevTables);
+template __global__ void k_modup_col<6, 64>(const ModUpJob* __restrict__, DevTables);
 
 size_t ntt_lds_bytes(int logs, int g) {
   const int n = g << logs;
@@ -742,7 +866,6 @@ __global__ __launch_bounds__(256) void k_ew(const EwJob* __restrict__ jobs, DevT
 // ModUp for one digit D = prod_{i in digit} q_i:
 //   y_i = [x_i (D/q_i)^-1]_{q_i},  out_t = sum_i y_i (D/q_i) mod t
 // ---------------------------------------------------------------------------
-constexpr int MAX_DIGIT = 16;
 
 __global__ __launch_bounds__(256) void k_modup(const ModUpJob* __restrict__ jobs, DevTables T) {
   const ModUpJob J = jobs[blockIdx.z];
@@ -1095,6 +1218,18 @@ void launch_ntt_pass(const DevTables& T, bool inverse, const NttJob* jobs, int n
 }
 
 bool inner_row_fused(const DevTables& T) { return T.log_n > 12; }
+
+void launch_modup_col(const DevTables& T, const ModUpJob* jobs, int n_jobs, int max_ext, hipStream_t s) {
+  if (n_jobs <= 0 || max_ext <= 0) return;
+  const int log_n = T.log_n;
+  const int k1 = log_n / 2;   // column length of the two-pass split
+  const int g = k1 == 8 ? 16 : k1 == 7 ? 32 : 64;
+  // max_ext bounds the output limbs of a job (n_ext minus its digit)
+  dim3 grid((1 << (log_n - k1)) / g, (max_ext + MODUP_EG - 1) / MODUP_EG, n_jobs);
+  if (k1 == 8) hipLaunchKernelGGL((k_modup_col<8, 16>), grid, dim3(256), ntt_lds_bytes(8, 16), s, jobs, T);
+  else if (k1 == 7) hipLaunchKernelGGL((k_modup_col<7, 32>), grid, dim3(256), ntt_lds_bytes(7, 32), s, jobs, T);
+  else hipLaunchKernelGGL((k_modup_col<6, 64>), grid, dim3(256), ntt_lds_bytes(6, 64), s, jobs, T);
+}
 
 void launch_inner_row(const DevTables& T, const InnerJob* jobs, int n_jobs, int max_ext, hipStream_t s) {
   if (n_jobs <= 0 || max_ext <= 0) return;

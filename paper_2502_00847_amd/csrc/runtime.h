@@ -64,6 +64,7 @@ struct Ctx {
   // of limb data (0 = one group); SECPE_NTT_CHUNK_MB overrides the default
   size_t ntt_chunk_bytes = 0;
   int q_bits = 0, p_bits = 0, log_scale = 0, dg = 2, df = 2, min_level = 1;
+  int refresh_level = 0;   // level a refreshed ciphertext is re-encrypted at
   std::vector<uint64_t> mod;
   int device = 0;
   hipStream_t stream = nullptr;
@@ -77,6 +78,7 @@ struct Ctx {
   const double* md_pinv = nullptr;   // [n_q] P^-1 mod q_t
   const double* p_mod_q = nullptr;   // [n_q] P mod q_t
   const double* rs_tab = nullptr;    // [n_q][n_q] q_l^-1 mod q_i at [l][i]
+  const double* ytab = nullptr;      // [n_q][n_q] N^-1 (D_j/q_t)^-1 mod q_t at [l][t]
   // merged relinearise + rescale at level l over B = {q_l} u P
   const double* rr_cinv = nullptr;   // [n_q][alpha+1] (B/b)^-1 mod b
   const double* rr_chat = nullptr;   // [n_q][n_q][alpha+1] (B/b) mod q_t
@@ -112,13 +114,13 @@ struct Ctx {
 };
 
 int build_context(Ctx& c, int log_n, int n_q, int q_bits, int n_p, int p_bits, int log_scale, int dg, int df,
-                  int min_level, int device, hipStream_t stream);
+                  int min_level, int refresh_level, int device, hipStream_t stream);
 void destroy_context(Ctx& c);
 
 // ---------------------------------------------------------------------------
 // command list: descriptors in one blob, launches replayed in order
 // ---------------------------------------------------------------------------
-enum CmdKind { C_NTT, C_NTT_FIRST, C_EW, C_MODUP, C_MODDOWN, C_INNER, C_INNER_ROW, C_AUTO, C_LIFT, C_SAMPLE, C_INTSPREAD, C_ENCODE, C_DECODE };
+enum CmdKind { C_NTT, C_NTT_FIRST, C_EW, C_MODUP, C_MODUP_COL, C_MODDOWN, C_INNER, C_INNER_ROW, C_AUTO, C_LIFT, C_SAMPLE, C_INTSPREAD, C_ENCODE, C_DECODE };
 
 struct Cmd {
   int kind;
@@ -189,6 +191,7 @@ class Builder {
   void ntt(const std::vector<NttJob>& v, bool inverse, bool first_pass_only = false);
   void ew(const std::vector<EwJob>& v);
   void modup(const std::vector<ModUpJob>& v);
+  void modup_col(const std::vector<ModUpJob>& v);
   void moddown(const std::vector<ModDownJob>& v);
   void inner(const std::vector<InnerJob>& v);
   void automorph(const std::vector<AutoJob>& v);

@@ -91,7 +91,7 @@ static const int SECPE_EDEVICE_INTERNAL = -5;
   } while (0)
 
 int build_context(Ctx& c, int log_n, int n_q, int q_bits, int n_p, int p_bits, int log_scale, int dg, int df,
-                  int min_level, int device, hipStream_t stream) {
+                  int min_level, int refresh_level, int device, hipStream_t stream) {
   c.log_n = log_n;
   c.N = 1 << log_n;
   c.n_q = n_q;
@@ -105,6 +105,7 @@ int build_context(Ctx& c, int log_n, int n_q, int q_bits, int n_p, int p_bits, i
   c.dg = dg;
   c.df = df;
   c.min_level = min_level;
+  c.refresh_level = (refresh_level <= 0 || refresh_level > n_q - 1) ? n_q - 1 : refresh_level;
   c.device = device;
   c.stream = stream;
   c.mod = choose_primes(log_n, n_q, q_bits, n_p, p_bits);
@@ -188,6 +189,18 @@ int build_context(Ctx& c, int log_n, int n_q, int q_bits, int n_p, int p_bits, i
       h[o_mdh + (size_t)t * c.alpha + k] = (double)ph;
     }
   }
+  // inverse NTT feeding the fused ModUp: at level l, limb t is scaled by
+  // N^-1 (D_j/q_t)^-1 mod q_t, D_j the product of the primes of t's digit
+  size_t o_ytab = alloc((size_t)n_q * n_q);
+  for (int l = 0; l < n_q; ++l)
+    for (int t = 0; t <= l; ++t) {
+      const uint64_t q = c.mod[t];
+      const int lo = (t / c.alpha) * c.alpha, hi = std::min(lo + c.alpha, l + 1);
+      uint64_t dh = 1;
+      for (int i = lo; i < hi; ++i)
+        if (i != t) dh = hmul(dh, c.mod[i] % q, q);
+      h[o_ytab + (size_t)l * n_q + t] = (double)hmul(hinv(dh, q), hinv((uint64_t)c.N % q, q), q);
+    }
   // merged relinearise + rescale at level l: base B = {q_l} u P
   const int nb = c.alpha + 1;
   size_t o_rrc = alloc((size_t)n_q * nb), o_rrh = alloc((size_t)n_q * n_q * nb), o_rri = alloc((size_t)n_q * n_q);
@@ -252,6 +265,7 @@ int build_context(Ctx& c, int log_n, int n_q, int q_bits, int n_p, int p_bits, i
   c.md_pinv = B + o_mdp;
   c.p_mod_q = B + o_pmq;
   c.rs_tab = B + o_rs;
+  c.ytab = B + o_ytab;
   c.rr_cinv = B + o_rrc;
   c.rr_chat = B + o_rrh;
   c.rr_inv = B + o_rri;
@@ -387,6 +401,12 @@ void Builder::modup(const std::vector<ModUpJob>& v) {
   for (auto& j : v) units += j.n_ext;
   PUSH_JOBS(C_MODUP, v, 1, false, units);
 }
+void Builder::modup_col(const std::vector<ModUpJob>& v) {
+  int my = 0;
+  int64_t units = 0;
+  for (auto& j : v) { my = std::max(my, j.n_ext); units += j.n_ext; }
+  PUSH_JOBS(C_MODUP_COL, v, my, false, units);
+}
 void Builder::moddown(const std::vector<ModDownJob>& v) {
   int64_t units = 0;
   for (auto& j : v) units += j.n_chain + C.n_p + (j.first_prime >= 0 ? 1 : 0);
@@ -435,7 +455,8 @@ int prof_kind_of(const Cmd& k) {
     case C_NTT:
     case C_NTT_FIRST: return k.inv ? PROF_NTT_INV : PROF_NTT_FWD;
     case C_EW: return PROF_EW;
-    case C_MODUP: return PROF_MODUP;
+    case C_MODUP:
+    case C_MODUP_COL: return PROF_MODUP;
     case C_MODDOWN: return PROF_MODDOWN;
     case C_INNER:
     case C_INNER_ROW: return PROF_INNER;
@@ -508,6 +529,7 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
       case C_NTT_FIRST: launch_ntt_pass(T, k.inv, (const NttJob*)j, k.n, k.max_y, 0, s); break;
       case C_EW: launch_ew(T, (const EwJob*)j, k.n, k.max_y, s); break;
       case C_MODUP: launch_modup(T, (const ModUpJob*)j, k.n, s); break;
+      case C_MODUP_COL: launch_modup_col(T, (const ModUpJob*)j, k.n, k.max_y, s); break;
       case C_MODDOWN: launch_moddown_conv(T, (const ModDownJob*)j, k.n, s); break;
       case C_INNER: launch_inner(T, (const InnerJob*)j, k.n, k.max_y, s); break;
       case C_INNER_ROW: launch_inner_row(T, (const InnerJob*)j, k.n, k.max_y, s); break;
@@ -561,6 +583,7 @@ int submit(Ctx& c, Builder& b, char* arena, size_t arena_bytes) {
 // the accumulator acc_w over Q_l u P (NTT domain) with acc0 + acc1 s' = P d s + small
 void Builder::ks_front(const std::vector<KsItem>& items, std::vector<KsTmp>& tmp) {
   const int N = C.N, alpha = C.alpha, n_p = C.n_p;
+  const bool fused = inner_row_fused(C.T);
   tmp.resize(items.size());
   std::vector<NttJob> j_inv, j_fwd_ext;
   std::vector<ModUpJob> j_up;
@@ -574,7 +597,10 @@ void Builder::ks_front(const std::vector<KsItem>& items, std::vector<KsTmp>& tmp
     t.dcoef = scratch((size_t)nc * N);
     t.ext = scratch((size_t)nd * n_ext * N);
     t.acc = scratch((size_t)2 * n_ext * N);
-    j_inv.push_back(NttJob{it.d, t.dcoef, nc, nc, 0, 0});
+    NttJob ji{it.d, t.dcoef, nc, nc, 0, 0};
+    // fused path: the inverse transform leaves the ModUp digits y_t = [x_t (D_j/q_t)^-1]
+    if (fused) ji.ek = C.ytab + (size_t)l * C.n_q;
+    j_inv.push_back(ji);
     for (int j = 0; j < nd; ++j) {
       const int lo = j * alpha, hi = std::min((j + 1) * alpha, nc);
       const DigitTable& dt = C.digits.at({lo, hi - lo});
@@ -585,8 +611,13 @@ void Builder::ks_front(const std::vector<KsItem>& items, std::vector<KsTmp>& tmp
     j_in.push_back(InnerJob{it.d, t.ext, it.key, t.acc, it.top0, it.top1, C.p_mod_q, nc, n_ext, nd, alpha});
   }
   ntt(j_inv, true);
-  modup(j_up);
-  ntt(j_fwd_ext, false, inner_row_fused(C.T));
+  if (fused) {
+    // ModUp + column pass in one kernel; the row pass runs inside the inner product
+    modup_col(j_up);
+  } else {
+    modup(j_up);
+    ntt(j_fwd_ext, false);
+  }
   inner(j_in);
 }
 
@@ -1011,10 +1042,10 @@ void Builder::encrypt_into(const std::vector<const int64_t*>& m_dev, const std::
 }
 
 // refresh stand-in: decrypt with the key owner's secret, lift m exactly from
-// limbs 0 and 1, re-encrypt at the top level; scale kept
+// limbs 0 and 1, re-encrypt at the refresh level; scale kept
 std::vector<CT> Builder::refresh(const std::vector<CT>& in, const std::vector<uint64_t>& seed,
                                  const std::vector<uint64_t>& index) {
-  const int N = C.N, L = C.n_q;
+  const int N = C.N, L = C.refresh_level + 1;
   const double* rsk = C.refresh_sk ? C.refresh_sk : (dry ? C.T.mod : nullptr);
   if (!rsk) { fail(-3, "modulus chain exhausted and no refresh key registered"); return {}; }
   const size_t mark = scratch_mark();

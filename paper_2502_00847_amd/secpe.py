@@ -21,7 +21,8 @@ class SecpeError(RuntimeError):
 
 
 class _Params(C.Structure):
-    _fields_ = [(n, C.c_int) for n in ("log_n", "n_q", "q_bits", "n_p", "p_bits", "log_scale", "dg", "df", "min_level")]
+    _fields_ = [(n, C.c_int) for n in ("log_n", "n_q", "q_bits", "n_p", "p_bits", "log_scale", "dg", "df", "min_level",
+                                       "refresh_level")]
 
 
 class _Ct(C.Structure):
@@ -150,7 +151,7 @@ class Context:
         self.device = device
         torch.cuda.set_device(device)
         self.stream = torch.cuda.Stream(device=device)
-        p = _Params(**{k: int(params[k]) for k, _ in _Params._fields_})
+        p = _Params(**{k: int(params.get(k, 0)) for k, _ in _Params._fields_})
         h = C.c_void_p()
         self._check(self.lib.secpe_ctx_create(C.byref(p), device, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.h = h

@@ -22,6 +22,8 @@ EXTRA_STEPS = [3, 5]
 def _params(name):
     if name == "p13":
         return dict(log_n=13, n_q=8, q_bits=36, n_p=2, p_bits=51, log_scale=36, dg=2, df=2, min_level=1)
+    if name == "p13_r6":
+        return dict(_params("p13"), refresh_level=6)
     if name == "p14":
         return dict(log_n=14, n_q=8, q_bits=40, n_p=3, p_bits=51, log_scale=40, dg=2, df=2, min_level=1)
     return dict(W.PARAMS[name])
@@ -265,6 +267,20 @@ def test_argmax_bit_exact_tiny(tiny, K, C):
     z, idx = g.decrypt(zg, C)
     zs = sim.t1_argmax(y, *W.d_bounds(K), o.slots)
     assert np.abs(z - zs).max() < 1e-3
+
+
+@pytest.mark.parametrize("name", ["tiny_r6", "p13_r6"])
+def test_argmax_refresh_below_top_bit_exact(name):
+    """Refreshes re-encrypting at level 6 instead of the top (single-pass and two-pass
+    NTT sizes): refresh and the whole Algorithm 1 match the oracle bit for bit."""
+    g, o, _ = _pair(name, 4, 8)
+    a, _ = _rand_ct(o, 31, level=2)
+    ga = g.import_(a.export(), a.scale)
+    r = o.refresh(a, 77, 2)
+    assert r.level == 6
+    _same(g, g.refresh(ga, 77, 2), r)
+    y, zo, zg = _argmax_pair(g, o, 3, 5, q=5)
+    _same(g, zg, zo)
 
 
 def test_argmax_toy_config(p13):
