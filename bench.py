@@ -27,10 +27,16 @@ import numpy as np  # noqa: E402
 import workload as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes the roofline kernel moves per limb it transforms, from rocprofv3
-# FETCH_SIZE (x2, the factor a 1 GiB device copy shows) + WRITE_SIZE; see
-# profiles/ntt_fwd_row_config3_traffic.md.  None when the kernel has changed since.
-TRAFFIC_PER_LIMB_PASS = 1.5 * 2**20
+# Roofline kernel: k_inner_row, the key-switch inner product fused with the
+# row pass of the ModUp outputs' forward NTT.  Its algorithmic traffic is one
+# limb (N residues x 8 B) per unit; a job at n_ext extended limbs and nd digits
+# is n_ext * (3 nd + 2) units (per digit: the digit's input limb and the two
+# key limbs read; the two accumulator limbs written).
+# HBM bytes it actually moves per unit, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (each scaled by what the counter reads for a 1 GiB device copy);
+# see profiles/k_inner_row_config3_traffic.md.  None when the kernel has
+# changed since the counters were taken.
+TRAFFIC_PER_UNIT = 288839
 
 
 def _log(msg):
@@ -235,11 +241,11 @@ def main():
         g.sync()
     _log("warmup done")
 
-    # timed region: K steps; the forward NTT's row-pass kernel is bracketed by HIP events.
+    # timed region: K steps; every launch of the roofline kernel is bracketed by HIP events.
     # Two fill kernels of distinctive sizes mark the region in a profiler's kernel trace.
     marker = torch.empty(4096 * 5, dtype=torch.float64, device="cuda")
     marker[:4096 * 3].fill_(3.0)
-    g.profile_begin("ntt_fwd_row")
+    g.profile_begin("inner")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -287,25 +293,27 @@ def main():
     zz, idx2 = g.decrypt(z2, d2["C"])
 
     N = 1 << params["log_n"]
-    # the row pass reads and writes every limb it transforms once: 2*N*8 bytes per limb
-    ntt_bytes = prof["units"] * 2 * N * 8
-    achieved = ntt_bytes / (prof["ms"] * 1e-3) / 1e9 if prof["ms"] > 0 else 0.0
+    unit_bytes = N * 8
+    launches = max(1, prof["launches"])
+    per_launch = prof["units"] * unit_bytes / launches
+    avg_s = prof["ms"] * 1e-3 / launches
+    achieved = per_launch / avg_s / 1e9 if prof["ms"] > 0 else 0.0
     whole = prof_all["units"] * 2 * N * 8 / (prof_all["ms"] * 1e-3) / 1e9 if prof_all["ms"] > 0 else 0.0
     roofline = {
         "bound": "hbm",
-        "kernel": "k_ntt2<8,16,ROW,fwd>: row pass (last 8 of 16 stages) of the forward negacyclic NTT",
+        "kernel": "k_inner_row<8,16>: key-switch inner product fused with the row pass of the ModUp outputs' NTT",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": (round(TRAFFIC_PER_LIMB_PASS * prof["units"] / max(1, prof["launches"]))
-                    if TRAFFIC_PER_LIMB_PASS else None),
+        "traffic": round(TRAFFIC_PER_UNIT * prof["units"] / launches) if TRAFFIC_PER_UNIT else None,
+        "algorithmic_bytes_per_launch": round(per_launch),
         "launches": prof["launches"],
-        "avg_launch_us": round(prof["ms"] * 1e3 / max(1, prof["launches"]), 2),
-        "limb_passes_per_launch": round(prof["units"] / max(1, prof["launches"]), 1),
-        "algorithmic_bytes_per_limb_pass": 2 * N * 8,
+        "avg_launch_us": round(avg_s * 1e6, 2),
+        "units_per_launch": round(prof["units"] / launches, 1),
+        "bytes_per_unit": unit_bytes,
         "whole_forward_ntt_gbs": round(whole, 1),
-        "whole_forward_ntt_note": "1 MiB per limb transform over both passes (column + row kernels)",
+        "whole_forward_ntt_note": "forward NTT launches (with their fused epilogues) at 1 MiB per limb transform",
     }
     result = {
         "metric": "encrypted Argmax/s (batched)",
