@@ -141,6 +141,18 @@ int secpe_eval_argmax_batch(secpe_ctx* ctx, int n, const secpe_ct* in, const int
                             const double* d_min, const double* d_max, const uint64_t* refresh_seed,
                             void* ws_dev, size_t ws_bytes, secpe_ct* out, int flags);
 
+/* Autotuner for the batched path.  Evaluates the batch given (same arguments
+   as secpe_eval_argmax_batch, no graph) under each candidate schedule and
+   keeps the fastest in the context for later calls:
+     candidate i: output limbs per workgroup of the fused ModUp = (i & 1) ? 2 : 4,
+                  NTT passes issued in job groups of (i & 2) ? 128 MiB : all jobs.
+   Writes the chosen candidate to *chosen and, for i < cap, the measured
+   milliseconds of candidate i to ms[i].  Synchronous.  Returns 0 or an error. */
+#define SECPE_AUTOTUNE_CANDIDATES 4
+int secpe_autotune(secpe_ctx* ctx, int n, const secpe_ct* in, const int* K, const int* C, const double* d_min,
+                   const double* d_max, const uint64_t* refresh_seed, void* ws_dev, size_t ws_bytes,
+                   secpe_ct* out, int* chosen, double* ms, int cap);
+
 /* Operation counts of the last evaluation: [sign, rotate, relin, key_switch,
    refresh, poly, max, kernel launches]. */
 int secpe_counters(const secpe_ctx* ctx, int64_t* out8);

@@ -932,6 +932,49 @@ extern "C" int secpe_profile_end(secpe_ctx* x, int64_t* launches, double* total_
   return 0;
 }
 
+static void set_candidate(Ctx& c, int i) {
+  c.modup_eg = (i & 1) ? 2 : 4;
+  c.ntt_chunk_bytes = (i & 2) ? ((size_t)128 << 20) : 0;
+}
+
+extern "C" int secpe_autotune(secpe_ctx* x, int n, const secpe_ct* in, const int* K, const int* C,
+                              const double* dmin, const double* dmax, const uint64_t* rs, void* ws, size_t ws_bytes,
+                              secpe_ct* out, int* chosen, double* ms, int cap) {
+  CHECK_CTX(x);
+  if (!chosen) return set_err(SECPE_EINVAL, "null argument");
+  Ctx& c = x->c;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return set_err(SECPE_EDEVICE, "hipEventCreate failed");
+  }
+  int best = -1;
+  float best_ms = 0.0f;
+  int rc = 0;
+  for (int i = 0; i < SECPE_AUTOTUNE_CANDIDATES && !rc; ++i) {
+    set_candidate(c, i);
+    float t = 0.0f;
+    for (int rep = 0; rep < 2 && !rc; ++rep) {
+      (void)hipEventRecord(e0, c.stream);
+      rc = secpe_eval_argmax_batch(x, n, in, K, C, dmin, dmax, rs, ws, ws_bytes, out, 0);
+      (void)hipEventRecord(e1, c.stream);
+      if (!rc && hipEventSynchronize(e1) == hipSuccess) (void)hipEventElapsedTime(&t, e0, e1);
+    }
+    if (rc) break;
+    if (ms && i < cap) ms[i] = t;
+    if (best < 0 || t < best_ms) {
+      best = i;
+      best_ms = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  set_candidate(c, best);
+  *chosen = best;
+  return 0;
+}
+
 extern "C" int secpe_ntt_cts(secpe_ctx* x, const secpe_ct* cts, int n, int inverse) {
   CHECK_CTX(x);
   Ctx& c = x->c;

@@ -20,7 +20,8 @@ bool inner_row_fused(const DevTables& T);
 void launch_inner_row(const DevTables& T, const InnerJob* jobs, int n_jobs, int max_ext, hipStream_t s);
 // ... and ModUp runs fused with the column pass of that forward NTT; its
 // source is the digit-scaled inverse transform (NttJob::ek on the inverse).
-void launch_modup_col(const DevTables& T, const ModUpJob* jobs, int n_jobs, int max_ext, hipStream_t s);
+// eg: output limbs per workgroup (2 or 4; a tunable)
+void launch_modup_col(const DevTables& T, const ModUpJob* jobs, int n_jobs, int max_ext, int eg, hipStream_t s);
 void launch_ew(const DevTables& T, const EwJob* jobs, int n_jobs, int max_limbs, hipStream_t s);
 void launch_modup(const DevTables& T, const ModUpJob* jobs, int n_jobs, hipStream_t s);
 void launch_moddown_conv(const DevTables& T, const ModDownJob* jobs, int n_jobs, hipStream_t s);

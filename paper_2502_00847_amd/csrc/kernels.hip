@@ -575,7 +575,7 @@ template __global__ void k_inner_row<7, 32>(const InnerJob* __restrict__, DevTab
 // ModUp of one digit fused with the column pass of the forward transform of
 // its outputs (N > 2^12).  src holds y_i = [x_i (D/q_i)^-1]_{q_i} for the
 // digit's limbs (coefficient domain; the inverse transform of x wrote them
-// scaled).  A workgroup owns one column tile and a group of MODUP_EG
+// scaled).  A workgroup owns one column tile and a group of EG
 // extended-basis limbs e outside the digit: it streams the digit's limbs
 // through registers once, accumulating
 //   out_e = sum_i y_i (D/q_i) mod p_e
@@ -583,9 +583,7 @@ template __global__ void k_inner_row<7, 32>(const InnerJob* __restrict__, DevTab
 // (ready for the row pass, which the inner product does) goes to dst limb e.
 // Grid (tile, group, job): with a multiple of 8 tiles, every group of a tile
 // runs on the same XCD and rereads the digit's tile from its L2.
-constexpr int MODUP_EG = 4;
-
-template <int LOGS, int G>
+template <int LOGS, int G, int EG>
 __global__ __launch_bounds__(256) void k_modup_col(const ModUpJob* __restrict__ jobs, DevTables T) {
   extern __shared__ double lds[];
   constexpr int RB = LOGS - 4;
@@ -593,9 +591,9 @@ __global__ __launch_bounds__(256) void k_modup_col(const ModUpJob* __restrict__ 
   const ModUpJob J = jobs[blockIdx.z];
   const int dsz = J.digit_hi - J.digit_lo;
   const int n_out = J.n_ext - dsz;
-  const int g0 = blockIdx.y * MODUP_EG;
+  const int g0 = blockIdx.y * EG;
   if (g0 >= n_out) return;
-  const int ng = min(MODUP_EG, n_out - g0);
+  const int ng = min(EG, n_out - g0);
   const int log_n = T.log_n;
   const int N = 1 << log_n;
   const int k1 = log_n - LOGS;
@@ -603,19 +601,19 @@ __global__ __launch_bounds__(256) void k_modup_col(const ModUpJob* __restrict__ 
   const int t = threadIdx.x;
   const int va = t % G, la = t / G;
   const int c0 = blockIdx.x * G;
-  int ee[MODUP_EG], pe[MODUP_EG];
-  Mod me[MODUP_EG];
+  int ee[EG], pe[EG];
+  Mod me[EG];
 #pragma unroll
-  for (int g = 0; g < MODUP_EG; ++g) {
+  for (int g = 0; g < EG; ++g) {
     const int idx = min(g0 + g, n_out - 1);
     const int e = idx < J.digit_lo ? idx : idx + dsz;   // skip the digit's own limbs
     ee[g] = e;
     pe[g] = e < J.n_chain ? e : T.n_q + (e - J.n_chain);
     me[g] = Mod{KPTR(T.mod)[pe[g]], KPTR(T.minv)[pe[g]]};
   }
-  double acc[MODUP_EG][16];
+  double acc[EG][16];
 #pragma unroll
-  for (int g = 0; g < MODUP_EG; ++g)
+  for (int g = 0; g < EG; ++g)
 #pragma unroll
     for (int k = 0; k < 16; ++k) acc[g][k] = 0.0;
   cgdbl* ysrc = CGPTR(J.src) + (size_t)J.digit_lo * N;
@@ -624,7 +622,7 @@ __global__ __launch_bounds__(256) void k_modup_col(const ModUpJob* __restrict__ 
 #pragma unroll
     for (int k = 0; k < 16; ++k) y[k] = ysrc[(size_t)i * N + (size_t)(k * NB + la) * C + c0 + va];
 #pragma unroll
-    for (int g = 0; g < MODUP_EG; ++g) {
+    for (int g = 0; g < EG; ++g) {
       const double c = KPTR(J.chat)[(size_t)pe[g] * dsz + i];
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
@@ -634,7 +632,7 @@ __global__ __launch_bounds__(256) void k_modup_col(const ModUpJob* __restrict__ 
     }
   }
 #pragma unroll
-  for (int g = 0; g < MODUP_EG; ++g) {
+  for (int g = 0; g < EG; ++g) {
     if (g >= ng) break;
     kdbl* tw = KPTR(T.psi) + (size_t)pe[g] * N;
     kdbl* twq = KPTR(T.psiq) + (size_t)pe[g] * N;
@@ -646,9 +644,12 @@ __global__ __launch_bounds__(256) void k_modup_col(const ModUpJob* __restrict__ 
     __syncthreads();
   }
 }
-template __global__ void k_modup_col<8, 16>(const ModUpJob* __restrict__, DevTables);
-template __global__ void k_modup_col<7, 32>(const ModUpJob* __restrict__, DevTables);
-template __global__ void k_modup_col<6, 64>(const ModUpJob* __restrict__, DevTables);
+#define MODUP_INST(EG)                                                              \
+  template __global__ void k_modup_col<8, 16, EG>(const ModUpJob* __restrict__, DevTables); \
+  template __global__ void k_modup_col<7, 32, EG>(const ModUpJob* __restrict__, DevTables); \
+  template __global__ void k_modup_col<6, 64, EG>(const ModUpJob* __restrict__, DevTables);
+MODUP_INST(2)
+MODUP_INST(4)
 
 size_t ntt_lds_bytes(int logs, int g) {
   const int n = g << logs;
@@ -1219,16 +1220,25 @@ void launch_ntt_pass(const DevTables& T, bool inverse, const NttJob* jobs, int n
 
 bool inner_row_fused(const DevTables& T) { return T.log_n > 12; }
 
-void launch_modup_col(const DevTables& T, const ModUpJob* jobs, int n_jobs, int max_ext, hipStream_t s) {
+void launch_modup_col(const DevTables& T, const ModUpJob* jobs, int n_jobs, int max_ext, int eg, hipStream_t s) {
   if (n_jobs <= 0 || max_ext <= 0) return;
   const int log_n = T.log_n;
   const int k1 = log_n / 2;   // column length of the two-pass split
   const int g = k1 == 8 ? 16 : k1 == 7 ? 32 : 64;
+  eg = eg == 2 ? 2 : 4;
   // max_ext bounds the output limbs of a job (n_ext minus its digit)
-  dim3 grid((1 << (log_n - k1)) / g, (max_ext + MODUP_EG - 1) / MODUP_EG, n_jobs);
-  if (k1 == 8) hipLaunchKernelGGL((k_modup_col<8, 16>), grid, dim3(256), ntt_lds_bytes(8, 16), s, jobs, T);
-  else if (k1 == 7) hipLaunchKernelGGL((k_modup_col<7, 32>), grid, dim3(256), ntt_lds_bytes(7, 32), s, jobs, T);
-  else hipLaunchKernelGGL((k_modup_col<6, 64>), grid, dim3(256), ntt_lds_bytes(6, 64), s, jobs, T);
+  dim3 grid((1 << (log_n - k1)) / g, (max_ext + eg - 1) / eg, n_jobs);
+  const size_t lds = ntt_lds_bytes(k1, g);
+#define LAUNCH_MODUP(EG)                                                                         \
+  if (k1 == 8) hipLaunchKernelGGL((k_modup_col<8, 16, EG>), grid, dim3(256), lds, s, jobs, T);     \
+  else if (k1 == 7) hipLaunchKernelGGL((k_modup_col<7, 32, EG>), grid, dim3(256), lds, s, jobs, T); \
+  else hipLaunchKernelGGL((k_modup_col<6, 64, EG>), grid, dim3(256), lds, s, jobs, T);
+  if (eg == 2) {
+    LAUNCH_MODUP(2)
+  } else {
+    LAUNCH_MODUP(4)
+  }
+#undef LAUNCH_MODUP
 }
 
 void launch_inner_row(const DevTables& T, const InnerJob* jobs, int n_jobs, int max_ext, hipStream_t s) {

@@ -63,6 +63,8 @@ struct Ctx {
   // two-pass NTT launches are issued in job groups of at most this many bytes
   // of limb data (0 = one group); SECPE_NTT_CHUNK_MB overrides the default
   size_t ntt_chunk_bytes = 0;
+  // output limbs per workgroup of the fused ModUp (2 or 4); set by the autotuner
+  int modup_eg = 4;
   int q_bits = 0, p_bits = 0, log_scale = 0, dg = 2, df = 2, min_level = 1;
   int refresh_level = 0;   // level a refreshed ciphertext is re-encrypted at
   std::vector<uint64_t> mod;

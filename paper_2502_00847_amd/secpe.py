@@ -76,6 +76,8 @@ def load():
         "secpe_op_add_const": (i32, [vp, ct, dbl, ct]),
         "secpe_op_mul_const": (i32, [vp, ct, dbl, dbl, vp, sz, ct]),
         "secpe_op_lincomb": (i32, [vp, ct, dbl, ct, dbl, dbl, i32, vp, sz, ct]),
+        "secpe_autotune": (i32, [vp, i32, ct, P(i32), P(i32), P(dbl), P(dbl), P(u64), vp, sz, ct, P(i32), P(dbl),
+                                 i32]),
         "secpe_op_mul_plain": (i32, [vp, ct, P(dbl), i32, dbl, vp, sz, ct]),
         "secpe_op_rescale": (i32, [vp, ct, vp, sz, ct]),
         "secpe_op_mul_relin": (i32, [vp, ct, ct, vp, sz, ct]),
@@ -115,7 +117,7 @@ def exported_symbols():
          "secpe_decrypt_coeffs", "secpe_workspace_bytes", "secpe_eval_argmax", "secpe_eval_argmax_batch",
          "secpe_counters", "secpe_ct_export", "secpe_ct_import", "secpe_key_export", "secpe_sk_export",
          "secpe_sync", "secpe_op_workspace_bytes", "secpe_op_add", "secpe_op_sub", "secpe_op_add_const",
-         "secpe_op_mul_const", "secpe_op_lincomb", "secpe_op_mul_plain", "secpe_op_rescale", "secpe_op_mul_relin",
+         "secpe_op_mul_const", "secpe_op_lincomb", "secpe_autotune", "secpe_op_mul_plain", "secpe_op_rescale", "secpe_op_mul_relin",
          "secpe_op_mul_relin_rescale", "secpe_op_rotate", "secpe_op_refresh", "secpe_op_eval_odd9",
          "secpe_op_key_switch", "secpe_op_ntt", "secpe_op_ring_mul", "secpe_op_encode", "secpe_profile_begin",
          "secpe_profile_end", "secpe_ntt_cts", "secpe_rotate_workspace_bytes", "secpe_rotate_batch",
@@ -282,6 +284,28 @@ class Context:
         for o, c in zip(outs, cout):
             o.level, o.scale = c.level, c.scale
         return outs
+
+    AUTOTUNE_CANDIDATES = [dict(modup_outputs_per_workgroup=2 if i & 1 else 4,
+                                ntt_job_group_mib=128 if i & 2 else None) for i in range(4)]
+
+    def autotune(self, cts, Ks, Cs, d_min, d_max, seeds, ws, outs):
+        """Time the batch under each candidate schedule; the fastest stays set."""
+        n = len(cts)
+        Ks = np.ascontiguousarray(Ks, dtype=np.int32)
+        Cs = np.ascontiguousarray(Cs, dtype=np.int32)
+        dmin = np.ascontiguousarray(d_min, dtype=np.float64)
+        dmax = np.ascontiguousarray(d_max, dtype=np.float64)
+        sd = np.ascontiguousarray([int(s) for s in seeds], dtype=np.uint64)
+        cin = (_Ct * n)(*[c._c() for c in cts])
+        cout = (_Ct * n)(*[c._c() for c in outs])
+        chosen = C.c_int(-1)
+        ms = np.zeros(len(self.AUTOTUNE_CANDIDATES), dtype=np.float64)
+        self._check(self.lib.secpe_autotune(self.h, n, cin, _p(Ks, C.c_int), _p(Cs, C.c_int), _p(dmin, C.c_double),
+                                            _p(dmax, C.c_double), _p(sd, C.c_uint64), C.c_void_p(ws.data_ptr()),
+                                            ws.numel() * 8, cout, C.byref(chosen), _p(ms, C.c_double), len(ms)))
+        for o, c in zip(outs, cout):
+            o.level, o.scale = c.level, c.scale
+        return chosen.value, [dict(c, ms=round(float(t), 3)) for c, t in zip(self.AUTOTUNE_CANDIDATES, ms)]
 
     def eval_argmax(self, ct, K, Cc, d_min, d_max, refresh_seed, ws=None):
         return self.eval_argmax_batch([ct], [K], [Cc], [d_min], [d_max], [refresh_seed], ws=ws)[0]

@@ -91,6 +91,31 @@ def test_full_key_switch_levels(full_pair, level):
     assert np.array_equal(gu[0], ou[0]) and np.array_equal(gu[1], ou[1])
 
 
+def test_full_batched_ntt_and_rotations(full_pair):
+    """The kernel microbenchmark's entry points: batched inverse NTT of whole
+    ciphertexts equals the oracle's coefficient-domain residues, forward NTT
+    restores them; batched rotations with different keys equal the oracle's."""
+    g, o = full_pair
+    cts, gcts = [], []
+    for i, lvl in enumerate((23, 23, 11)):
+        z = np.random.default_rng(40 + i).uniform(-1, 1, 128)
+        c = o.lower(o.encrypt(o.encode(z, 2.0**50), 2.0**50, 40 + i), lvl)
+        cts.append(c)
+        gcts.append(g.import_(c.export(), c.scale))
+    g.ntt_cts(gcts, inverse=True)
+    g.sync()
+    for c, gc in zip(cts, gcts):
+        raw = gc.buf.view(2, g.n_q, g.N)[:, : c.level + 1].cpu().numpy().astype(np.uint64)
+        assert np.array_equal(raw, c.export())
+    g.ntt_cts(gcts, inverse=False)
+    for c, gc in zip(cts, gcts):
+        assert np.array_equal(g.export(gc), c.export())
+    steps = [1, 4096, 1]
+    outs = g.rotate_batch(gcts, steps)
+    for c, st, out in zip(cts, steps, outs):
+        _same(g, out, o.rotate(c, st))
+
+
 def test_full_refresh_and_poly(full_pair):
     g, o = full_pair
     f, gg = sign_coeffs()

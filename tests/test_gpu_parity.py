@@ -314,6 +314,24 @@ def test_batch_equals_one_at_a_time(tiny):
         assert np.array_equal(g.export(outs[i]), g.export(alone))
 
 
+def test_autotune_keeps_bits(p13):
+    """Every autotuner candidate schedule gives the same ciphertexts (two-pass NTT size)."""
+    g, o, _ = p13
+    shapes = [(4, 4), (3, 2), (2, 3)]
+    qs = [(K, C, W.logits(9, 300 + i, K, C), W.query_seeds(9, 300 + i)) for i, (K, C) in enumerate(shapes)]
+    cts = [g.encrypt(y, enc) for K, C, y, (enc, _) in qs]
+    args = ([K for K, *_ in qs], [C for _, C, *_ in qs], [W.d_bounds(K)[0] for K, *_ in qs],
+            [W.d_bounds(K)[1] for K, *_ in qs], [ref for *_, (_, ref) in qs])
+    ws = g.workspace(args[0], args[1])
+    before = [g.export(z) for z in g.eval_argmax_batch(cts, *args, ws=ws)]
+    outs = [g.new_ct() for _ in cts]
+    chosen, cands = g.autotune(cts, *args, ws=ws, outs=outs)
+    assert 0 <= chosen < len(cands) and all(c["ms"] > 0 for c in cands)
+    assert all(np.array_equal(g.export(a), b) for a, b in zip(outs, before))
+    after = [g.export(z) for z in g.eval_argmax_batch(cts, *args, ws=ws)]
+    assert all(np.array_equal(a, b) for a, b in zip(after, before))
+
+
 def test_graph_replay_is_deterministic(tiny):
     g, o, _ = tiny
     shapes = [(3, 5), (8, 2), (2, 3)]
