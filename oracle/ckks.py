@@ -69,6 +69,10 @@ def _load():
         "orc_layout": (None, [vp, P(dbl), ci, ci, P(dbl)]),
         "orc_encrypt_logits": (vp, [vp, P(dbl), ci, ci, u64]),
         "orc_eval_argmax": (vp, [vp, vp, ci, ci, dbl, dbl, u64]),
+        "orc_packed_shape": (ci, [vp, ci, P(ci), P(ci), P(ci)]),
+        "orc_layout_packed": (None, [vp, ci, P(dbl), P(ci), P(ci), P(dbl)]),
+        "orc_encrypt_packed": (vp, [vp, ci, P(dbl), P(ci), P(ci), u64]),
+        "orc_eval_argmax_packed": (vp, [vp, vp, ci, P(ci), P(ci), P(dbl), P(dbl), u64]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -316,9 +320,44 @@ class Oracle:
         coef = np.ascontiguousarray(coef, dtype=np.float64)
         return self._wrap(self.lib.orc_eval_odd9(self.h, x.h, _p(coef, C.c_double), float(gain), float(target)))
 
+    def packed_shape(self, shapes):
+        """(blocks per ciphertext, K', C', block size) for a group of (K, C) shapes."""
+        Ks = np.ascontiguousarray([k for k, _ in shapes], dtype=np.int32)
+        Cs = np.ascontiguousarray([c for _, c in shapes], dtype=np.int32)
+        out = np.zeros(3, dtype=np.int32)
+        nb = self.lib.orc_packed_shape(self.h, len(shapes), _p(Ks, C.c_int), _p(Cs, C.c_int), _p(out, C.c_int))
+        return int(nb), int(out[0]), int(out[1]), int(out[2])
+
+    def encrypt_packed(self, blocks, seed):
+        """blocks: list of K_b x C_b logit arrays, packed one per slot block."""
+        Ks, Cs, flat = _packed_args(blocks)
+        return self._wrap(self.lib.orc_encrypt_packed(self.h, len(blocks), _p(flat, C.c_double), _p(Ks, C.c_int),
+                                                      _p(Cs, C.c_int), int(seed)))
+
+    def eval_argmax_packed(self, ct, shapes, d_min, d_max, refresh_seed):
+        Ks = np.ascontiguousarray([k for k, _ in shapes], dtype=np.int32)
+        Cs = np.ascontiguousarray([c for _, c in shapes], dtype=np.int32)
+        lo = np.ascontiguousarray(d_min, dtype=np.float64)
+        hi = np.ascontiguousarray(d_max, dtype=np.float64)
+        return self._wrap(self.lib.orc_eval_argmax_packed(self.h, ct.h, len(shapes), _p(Ks, C.c_int), _p(Cs, C.c_int),
+                                                          _p(lo, C.c_double), _p(hi, C.c_double), int(refresh_seed)))
+
+    def decrypt_packed(self, ct, shapes):
+        """Each block's decrypted z[:C_b]."""
+        nb, kp, cp, bsz = self.packed_shape(shapes)
+        z = self.decrypt_decode(ct, len(shapes) * bsz)
+        return [z[b * bsz:b * bsz + c] for b, (_, c) in enumerate(shapes)]
+
     def eval_argmax(self, ct, K, Cc, d_min, d_max, refresh_seed):
         return self._wrap(self.lib.orc_eval_argmax(self.h, ct.h, int(K), int(Cc), float(d_min), float(d_max),
                                                    int(refresh_seed)))
+
+
+def _packed_args(blocks):
+    Ks = np.ascontiguousarray([np.asarray(l).shape[0] for l in blocks], dtype=np.int32)
+    Cs = np.ascontiguousarray([np.asarray(l).shape[1] for l in blocks], dtype=np.int32)
+    flat = np.ascontiguousarray(np.concatenate([np.asarray(l, dtype=np.float64).ravel() for l in blocks]))
+    return Ks, Cs, flat
 
 
 def argmax_rotation_steps(k_max, c_max, slots):

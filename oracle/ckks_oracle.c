@@ -771,6 +771,21 @@ static orc_ct* op_mul_plain(orc_ctx* c, const orc_ct* a, const double* v, int ns
   return x;
 }
 
+/* x = a + encode(v) at a's scale (the plaintext added to c0) */
+static orc_ct* op_add_plain(orc_ctx* c, const orc_ct* a, const double* v, int nslots) {
+  int n = c->n;
+  int64_t* m = (int64_t*)xcalloc(n, 8);
+  encode_real(c, v, nslots, a->scale, m);
+  orc_ct* x = ct_copy(c, a, a->level);
+  for (int t = 0; t <= x->level; ++t) {
+    uint64_t q = c->mod[t];
+    uint64_t* w = LIMB(x, 0, t, n);
+    for (int i = 0; i < n; ++i) w[i] = madd(w[i], from_i128(m[i], q), q);
+  }
+  free(m);
+  return x;
+}
+
 /* first half of the hybrid key switch of d (coefficient domain, limbs 0..l)
    with key k: ModUp of every digit and the inner product with the key,
    returned in the coefficient domain over Q_l u P (limbs 0..l, then the
@@ -1375,6 +1390,56 @@ ORC_API void* orc_encrypt_logits(void* h, const double* logits, int K, int C, ui
   return x;
 }
 
+/* Packed layout (Sec. 3.2 packs N/(2n) Argmax inputs in one ciphertext): n_b
+   queries, query b in the block of slots [b*bsz, (b+1)*bsz) at slot
+   b*bsz + k*C' + c, with K', C' the largest padded shape of the group and
+   bsz = max(K'C', 2C'), so that the prompt sum, the duplication and QuickMax
+   of every block stay inside it. */
+static void packed_shape(int n_b, const int* K, const int* C, int* kp, int* cp, int* bsz) {
+  int lk = 0, lc = 0;
+  for (int b = 0; b < n_b; ++b) {
+    if (ilog2_ceil(K[b]) > lk) lk = ilog2_ceil(K[b]);
+    if (ilog2_ceil(C[b]) > lc) lc = ilog2_ceil(C[b]);
+  }
+  *kp = 1 << lk;
+  *cp = 1 << lc;
+  *bsz = *kp * *cp > 2 * *cp ? *kp * *cp : 2 * *cp;
+}
+
+/* out3 = {K', C', block size}; returns the number of blocks a ciphertext holds */
+ORC_API int orc_packed_shape(void* h, int n_b, const int* K, const int* C, int* out3) {
+  orc_ctx* c = (orc_ctx*)h;
+  packed_shape(n_b, K, C, &out3[0], &out3[1], &out3[2]);
+  return (c->n / 2) / out3[2];
+}
+
+/* logits: the queries' K_b x C_b blocks concatenated */
+ORC_API void orc_layout_packed(void* h, int n_b, const double* logits, const int* K, const int* C, double* slots) {
+  orc_ctx* c = (orc_ctx*)h;
+  int kp, cp, bsz;
+  packed_shape(n_b, K, C, &kp, &cp, &bsz);
+  if ((int64_t)n_b * bsz > c->n / 2) die("packed queries exceed the slot count");
+  for (int j = 0; j < c->n / 2; ++j) slots[j] = 0.0;
+  const double* y = logits;
+  for (int b = 0; b < n_b; ++b) {
+    for (int k = 0; k < K[b]; ++k)
+      for (int cc = 0; cc < C[b]; ++cc) slots[b * bsz + k * cp + cc] = y[k * C[b] + cc];
+    y += K[b] * C[b];
+  }
+}
+
+ORC_API void* orc_encrypt_packed(void* h, int n_b, const double* logits, const int* K, const int* C, uint64_t seed) {
+  orc_ctx* c = (orc_ctx*)h;
+  double* slots = (double*)xcalloc(c->n / 2, sizeof(double));
+  orc_layout_packed(h, n_b, logits, K, C, slots);
+  int64_t* m = (int64_t*)xcalloc(c->n, 8);
+  encode_real(c, slots, c->n / 2, ldexp(1.0, c->log_scale), m);
+  void* x = orc_encrypt(h, m, ldexp(1.0, c->log_scale), seed);
+  free(slots);
+  free(m);
+  return x;
+}
+
 /* The encrypted Argmax (Algorithm 1) over the prompt-summed logits.
    y[k*C'+c] holds the k-th prompt's score for class c.  Steps:
      prompt sum   y <- y + RotL(y, C' 2^i), i < log K'   (sum by doubling, Sec. 3.2)
@@ -1383,14 +1448,13 @@ ORC_API void* orc_encrypt_logits(void* h, const double* logits, int K, int C, ui
      line 3       y_max <- QuickMax(y): y <- Max(RotL(y, 2^i), y), i < log C'
      line 4       y <- y - y_max
      lines 5-6    z <- Sign(y) + 1                                   (Eq. 2) */
-ORC_API void* orc_eval_argmax(void* h, const void* ct_in, int K, int C, double d_min, double d_max, uint64_t refresh_seed) {
-  orc_ctx* c = (orc_ctx*)h;
+static orc_ct* eval_argmax_core(orc_ctx* c, const orc_ct* ct_in, int lk, int lc, int packed, int n_b, int bsz,
+                                const int* C, const double* d_min, const double* d_max, uint64_t refresh_seed) {
   double delta = ldexp(1.0, c->log_scale);
-  int lk = ilog2_ceil(K), lc = ilog2_ceil(C);
   int cp = 1 << lc;
   int slots = c->n / 2;
   refresher rf = {refresh_seed, 0};
-  orc_ct* y = ct_copy(c, (const orc_ct*)ct_in, ((const orc_ct*)ct_in)->level);
+  orc_ct* y = ct_copy(c, ct_in, ct_in->level);
   for (int i = 0; i < lk; ++i) {
     orc_ct* r = op_rotate(c, y, (int64_t)cp << i);
     orc_ct* s = op_add(c, y, r, 0);
@@ -1399,12 +1463,32 @@ ORC_API void* orc_eval_argmax(void* h, const void* ct_in, int K, int C, double d
   }
   /* normalise; y must keep one level for the mask product */
   y = maybe_refresh(c, y, 1, &rf);
-  op_add_const_inplace(c, y, -d_min);
-  double* mask = (double*)xcalloc(cp, sizeof(double));
-  double inv_range = 1.0 / (d_max - d_min);
-  for (int j = 0; j < C; ++j) mask[j] = inv_range;
-  orc_ct* yn = op_mul_plain(c, y, mask, cp, delta);
-  free(mask);
+  orc_ct* yn;
+  if (!packed) {
+    op_add_const_inplace(c, y, -d_min[0]);
+    double* mask = (double*)xcalloc(cp, sizeof(double));
+    double inv_range = 1.0 / (d_max[0] - d_min[0]);
+    for (int j = 0; j < C[0]; ++j) mask[j] = inv_range;
+    yn = op_mul_plain(c, y, mask, cp, delta);
+    free(mask);
+  } else {
+    /* per block: -D_min on its classes, then the mask 1/(D_max - D_min) there */
+    int used = n_b * bsz;
+    double* shift = (double*)xcalloc(used, sizeof(double));
+    double* mask = (double*)xcalloc(used, sizeof(double));
+    for (int b = 0; b < n_b; ++b) {
+      double inv_range = 1.0 / (d_max[b] - d_min[b]);
+      for (int j = 0; j < C[b]; ++j) {
+        shift[b * bsz + j] = -d_min[b];
+        mask[b * bsz + j] = inv_range;
+      }
+    }
+    orc_ct* y1 = op_add_plain(c, y, shift, used);
+    yn = op_mul_plain(c, y1, mask, used, delta);
+    ct_free(y1);
+    free(shift);
+    free(mask);
+  }
   ct_free(y);
   /* line 2: duplicate */
   orc_ct* r = op_rotate(c, yn, (int64_t)slots - cp);
@@ -1427,4 +1511,21 @@ ORC_API void* orc_eval_argmax(void* h, const void* ct_in, int K, int C, double d
   ct_free(d);
   op_add_const_inplace(c, z, 1.0);
   return z;
+}
+
+ORC_API void* orc_eval_argmax(void* h, const void* ct_in, int K, int C, double d_min, double d_max, uint64_t refresh_seed) {
+  return eval_argmax_core((orc_ctx*)h, (const orc_ct*)ct_in, ilog2_ceil(K), ilog2_ceil(C), 0, 1, 0, &C, &d_min,
+                          &d_max, refresh_seed);
+}
+
+/* Algorithm 1 on every block of a packed ciphertext at once (same steps, with
+   K', C' of the group; Eq. 5 with each block's own bounds and classes) */
+ORC_API void* orc_eval_argmax_packed(void* h, const void* ct_in, int n_b, const int* K, const int* C,
+                                     const double* d_min, const double* d_max, uint64_t refresh_seed) {
+  orc_ctx* c = (orc_ctx*)h;
+  int kp, cp, bsz;
+  packed_shape(n_b, K, C, &kp, &cp, &bsz);
+  if ((int64_t)n_b * bsz > c->n / 2) die("packed queries exceed the slot count");
+  return eval_argmax_core(c, (const orc_ct*)ct_in, ilog2_ceil(kp), ilog2_ceil(cp), 1, n_b, bsz, C, d_min, d_max,
+                          refresh_seed);
 }

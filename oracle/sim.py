@@ -89,5 +89,46 @@ def t1_argmax(logits, d_min, d_max, slots, dg=2, df=2, exact_sign=False, return_
     return z[:C]
 
 
+def packed_shape(shapes):
+    """(K', C', block size) of a packed group: the largest padded shape, blocks of max(K'C', 2C')."""
+    Kp = max(_pow2ceil(K) for K, _ in shapes)
+    Cp = max(_pow2ceil(C) for _, C in shapes)
+    return Kp, Cp, max(Kp * Cp, 2 * Cp)
+
+
+def t1_argmax_packed(blocks, slots, dg=2, df=2, exact_sign=False):
+    """Algorithm 1 on a packed slot vector (Sec. 3.2: several Argmax inputs in one
+    ciphertext).  blocks: list of (logits K_b x C_b, d_min_b, d_max_b); query b
+    sits at slot b*B + k*C' + c.  Returns each block's z[:C_b]."""
+    shapes = [np.asarray(l).shape for l, _, _ in blocks]
+    Kp, Cp, B = packed_shape(shapes)
+    assert len(blocks) * B <= slots
+    sgn = np.sign if exact_sign else (lambda v: sign_composite(v, dg, df))
+    y = np.zeros(slots)
+    shift = np.zeros(slots)
+    mask = np.zeros(slots)
+    for b, (lg, lo, hi) in enumerate(blocks):
+        lg = np.asarray(lg, dtype=np.float64)
+        K, C = lg.shape
+        for k in range(K):
+            y[b * B + k * Cp:b * B + k * Cp + C] = lg[k]
+        shift[b * B:b * B + C] = -lo
+        mask[b * B:b * B + C] = 1.0 / (hi - lo)
+    i = 1
+    while i < Kp:
+        y = y + np.roll(y, -Cp * i)
+        i <<= 1
+    y = mask * (y + shift)                          # Eq. 5 per block
+    y = y + np.roll(y, Cp)
+    ym = y.copy()
+    i = 1
+    while i < Cp:
+        r = np.roll(ym, -i)
+        ym = (r + ym) / 2 + (r - ym) / 2 * sgn(r - ym)
+        i <<= 1
+    z = sgn(y - ym) + 1.0
+    return [z[b * B:b * B + s[1]] for b, s in enumerate(shapes)]
+
+
 def decoded_index(z):
     return int(np.argmax(np.asarray(z)))

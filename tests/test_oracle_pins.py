@@ -596,6 +596,59 @@ def test_counts_match_paper():
         assert cnt["relin"] == 20 * (lc + 1) + lc
 
 
+def _packed_group(seed, shapes):
+    out = []
+    for i, (K, C) in enumerate(shapes):
+        y = W.logits(9, seed * 100 + i, K, C)
+        lo, hi = W.d_bounds(K)
+        out.append((y, lo, hi))
+    return out
+
+
+def test_t1_packed_blocks_do_not_interact():
+    """Packed Algorithm 1 with the exact sign: every block's z is one-hot at its own
+    plaintext argmax (no leakage between blocks), and a single block equals the
+    unpacked Algorithm 1 bit for bit."""
+    # integer logits and bounds +-64 keep every step exact in FP64 (dyadic values)
+    rng = np.random.default_rng(31)
+    for trial in range(40):
+        n = int(rng.integers(1, 9))
+        shapes = [(int(rng.integers(1, 9)), int(rng.integers(1, 9))) for _ in range(n)]
+        blocks = [(rng.integers(-6, 7, size=sh).astype(np.float64), -64.0, 64.0) for sh in shapes]
+        zs = sim.t1_argmax_packed(blocks, 512, exact_sign=True)
+        for (y, lo, hi), z in zip(blocks, zs):
+            tot = np.sum(y, 0)
+            assert np.array_equal(z, (tot == tot.max()).astype(np.float64))
+    y, lo, hi = _packed_group(99, [(3, 5)])[0]
+    Kp, Cp, B = sim.packed_shape([(3, 5)])
+    z1 = sim.t1_argmax_packed([(y, lo, hi)], 512)[0]
+    assert np.array_equal(z1, sim.t1_argmax(y, lo, hi, 512))
+
+
+def test_oracle_packed_argmax_tiny():
+    """Encrypted packed Argmax (tiny parameters, four queries of uneven shape in one
+    ciphertext): each block decrypts to the packed FP64 Algorithm 1 and to the plaintext
+    argmax; the operation counts are those of one query of the group's padded shape."""
+    o = make_oracle("tiny")
+    o.keygen(5, argmax_rotation_steps(8, 8, o.slots))
+    shapes = [(3, 5), (2, 3), (4, 2), (1, 4)]
+    blocks = _packed_group(7, shapes)
+    nb, kp, cp, bsz = o.packed_shape(shapes)
+    assert (kp, cp, bsz) == (4, 8, 32) and nb == o.slots // 32
+    ct = o.encrypt_packed([b[0] for b in blocks], 21)
+    o.reset_counters()
+    z = o.eval_argmax_packed(ct, shapes, [b[1] for b in blocks], [b[2] for b in blocks], 22)
+    cnt = o.counters()
+    assert cnt["sign"] == 3 + 1 and cnt["rotate"] == 2 + 1 + 3 and cnt["max"] == 3
+    zs = o.decrypt_packed(z, shapes)
+    ts = sim.t1_argmax_packed(blocks, o.slots)
+    for (y, lo, hi), zb, tb in zip(blocks, zs, ts):
+        assert np.abs(zb - tb).max() < 1e-3
+        i0, _, margin = sim.t0_argmax(y)
+        if margin / (hi - lo) >= 2.0**-10:
+            assert sim.decoded_index(zb) == i0
+
+
 def test_packing_count_matches_paper():
     """2n slots per Argmax of length n -> N/(2n) inputs per ciphertext: 32768 slots, n=256 -> 64 (Sec. 3.2)."""
     o_slots = (1 << W.PARAMS["full"]["log_n"]) // 2
