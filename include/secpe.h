@@ -141,6 +141,32 @@ int secpe_eval_argmax_batch(secpe_ctx* ctx, int n, const secpe_ct* in, const int
                             const double* d_min, const double* d_max, const uint64_t* refresh_seed,
                             void* ws_dev, size_t ws_bytes, secpe_ct* out, int flags);
 
+/* ---- slot-packed Argmax (Sec. 3.2: N/(2n) Argmax inputs share one
+   ciphertext).  A group of queries of shapes (K_b, C_b) is laid out in
+   blocks of B = max(K'C', 2C') slots, K' and C' the largest padded shape of
+   the group: query b at slot b*B + k*C' + c.  Every block runs Algorithm 1
+   with the group's K', C' (padded classes get the normalised minimum 0, so
+   they never win) and Eq. 5 with its own bounds; one evaluation serves the
+   whole group. ---- */
+/* Writes {K', C', B} to out3; returns the number of blocks a ciphertext holds
+   (or a negative error). */
+int secpe_packed_shape(secpe_ctx* ctx, int n, const int* K, const int* C, int* out3);
+/* Client encryption of n queries in one ciphertext; logits: the K_b x C_b
+   blocks concatenated (row k = prompt k). */
+int secpe_encrypt_packed(secpe_ctx* ctx, const void* sk_dev, int n, const double* logits, const int* K, const int* C,
+                         uint64_t seed, secpe_ct* out);
+/* Workspace bytes for one evaluation of n packed ciphertexts; n_blocks[i]
+   queries in ciphertext i, their K and C concatenated. */
+size_t secpe_packed_workspace_bytes(secpe_ctx* ctx, int n, const int* n_blocks, const int* K, const int* C);
+/* Evaluate n packed ciphertexts (batched like secpe_eval_argmax_batch); the
+   per-block K, C, d_min, d_max are concatenated over the ciphertexts; one
+   refresh seed per ciphertext.  Decrypt block b of a result with
+   secpe_decrypt over nslots = n_blocks * B and read slots [b*B, b*B + C_b).
+   Asynchronous. */
+int secpe_eval_argmax_packed(secpe_ctx* ctx, int n, const secpe_ct* in, const int* n_blocks, const int* K, const int* C,
+                             const double* d_min, const double* d_max, const uint64_t* refresh_seed, void* ws_dev,
+                             size_t ws_bytes, secpe_ct* out);
+
 /* Autotuner for the batched path.  Evaluates the batch given (same arguments
    as secpe_eval_argmax_batch, no graph) under each candidate schedule and
    keeps the fastest in the context for later calls:

@@ -384,6 +384,115 @@ static std::vector<ArgmaxQuery> make_queries(secpe_ctx* x, int n, const secpe_ct
   return q;
 }
 
+// packed queries: n_b[i] blocks for ciphertext i, their K, C, bounds concatenated
+static int make_packed(secpe_ctx* x, int n, const secpe_ct* in, const int* n_b, const int* K, const int* C,
+                       const double* dmin, const double* dmax, const uint64_t* rs, secpe_ct* out,
+                       std::vector<ArgmaxQuery>& q) {
+  q.assign(n, ArgmaxQuery{});
+  size_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!in[i].data) return set_err(SECPE_EINVAL, "null input ciphertext");
+    if (in[i].level < 0 || in[i].level >= x->c.n_q) return set_err(SECPE_EINVAL, "input level out of range");
+    if (n_b[i] < 1) return set_err(SECPE_EINVAL, "a packed ciphertext needs at least one block");
+    ArgmaxQuery& a = q[i];
+    for (int j = 0; j < n_b[i]; ++j, ++off) {
+      if (K[off] < 1 || C[off] < 1) return set_err(SECPE_EINVAL, "K and C must be positive");
+      if (!(dmax[off] > dmin[off])) return set_err(SECPE_EINVAL, "need d_max > d_min");
+      a.bK.push_back(K[off]);
+      a.bC.push_back(C[off]);
+      a.blo.push_back(dmin[off]);
+      a.bhi.push_back(dmax[off]);
+    }
+    int kp, cp, bsz;
+    packed_shape(a.bK, a.bC, &kp, &cp, &bsz);
+    if ((int64_t)n_b[i] * bsz > x->c.N / 2) return set_err(SECPE_EINVAL, "packed queries exceed the slot count");
+    a.in.d = (double*)in[i].data;
+    a.in.level = in[i].level;
+    a.in.scale = in[i].scale;
+    a.K = kp;
+    a.C = cp;
+    a.d_min = a.blo[0];
+    a.d_max = a.bhi[0];
+    a.refresh_seed = rs[i];
+    a.out.d = out ? (double*)out[i].data : nullptr;
+  }
+  return 0;
+}
+
+extern "C" int secpe_packed_shape(secpe_ctx* x, int n, const int* K, const int* C, int* out3) {
+  CHECK_CTX(x);
+  if (n < 1 || !K || !C || !out3) return set_err(SECPE_EINVAL, "bad arguments");
+  for (int i = 0; i < n; ++i)
+    if (K[i] < 1 || C[i] < 1) return set_err(SECPE_EINVAL, "K and C must be positive");
+  std::vector<int> k(K, K + n), c(C, C + n);
+  packed_shape(k, c, &out3[0], &out3[1], &out3[2]);
+  const int per = (x->c.N / 2) / out3[2];
+  if (per < 1) return set_err(SECPE_EINVAL, "one block exceeds the slot count");
+  return per;
+}
+
+extern "C" int secpe_encrypt_packed(secpe_ctx* x, const void* sk_dev, int n, const double* logits, const int* K,
+                                    const int* C, uint64_t seed, secpe_ct* out) {
+  CHECK_CTX(x);
+  int shape[3];
+  const int per = secpe_packed_shape(x, n, K, C, shape);
+  if (per < 0) return per;
+  if (n > per) return set_err(SECPE_EINVAL, "packed queries exceed the slot count");
+  if (!logits) return set_err(SECPE_EINVAL, "null logits");
+  const int cp = shape[1], bsz = shape[2];
+  std::vector<double> z((size_t)n * bsz, 0.0);
+  const double* y = logits;
+  for (int b = 0; b < n; ++b) {
+    for (int k = 0; k < K[b]; ++k)
+      for (int j = 0; j < C[b]; ++j) z[(size_t)b * bsz + (size_t)k * cp + j] = y[(size_t)k * C[b] + j];
+    y += (size_t)K[b] * C[b];
+  }
+  return encrypt_impl(x, sk_dev, z, nullptr, ldexp(1.0, x->c.log_scale), seed, out);
+}
+
+extern "C" size_t secpe_packed_workspace_bytes(secpe_ctx* x, int n, const int* n_b, const int* K, const int* C) {
+  if (!x || n < 1 || !n_b || !K || !C) return 0;
+  Ctx& c = x->c;
+  size_t tot = 0;
+  for (int i = 0; i < n; ++i) tot += (size_t)std::max(0, n_b[i]);
+  std::vector<secpe_ct> in(n), out(n);
+  std::vector<double> dmin(tot, -1.0), dmax(tot, 1.0);
+  std::vector<uint64_t> rs(n, 0);
+  for (int i = 0; i < n; ++i) {
+    in[i].data = (void*)(uintptr_t)0x200000000000ull;
+    in[i].level = c.n_q - 1;
+    in[i].scale = ldexp(1.0, c.log_scale);
+    out[i].data = (void*)(uintptr_t)0x300000000000ull;
+  }
+  std::vector<ArgmaxQuery> q;
+  if (make_packed(x, n, in.data(), n_b, K, C, dmin.data(), dmax.data(), rs.data(), out.data(), q)) return 0;
+  Builder dry(c, (char*)(uintptr_t)0x100000000000ull, (size_t)1 << 44, (char*)(uintptr_t)0x400000000000ull,
+              (size_t)1 << 40, true);
+  build_argmax(dry, q);
+  if (dry.err_code) {
+    set_err(dry.err_code, dry.err);
+    return 0;
+  }
+  return dry.need_bytes() + 4096;
+}
+
+extern "C" int secpe_eval_argmax_packed(secpe_ctx* x, int n, const secpe_ct* in, const int* n_b, const int* K,
+                                        const int* C, const double* dmin, const double* dmax, const uint64_t* rs,
+                                        void* ws, size_t ws_bytes, secpe_ct* out) {
+  CHECK_CTX(x);
+  if (n < 1 || !in || !n_b || !K || !C || !dmin || !dmax || !rs || !ws || !out)
+    return set_err(SECPE_EINVAL, "null argument");
+  for (int i = 0; i < n; ++i)
+    if (!out[i].data) return set_err(SECPE_EINVAL, "null output ciphertext");
+  std::vector<ArgmaxQuery> q;
+  int rc = make_packed(x, n, in, n_b, K, C, dmin, dmax, rs, out, q);
+  if (rc) return rc;
+  rc = run_build(x, (char*)ws, ws_bytes, [&](Builder& b) { build_argmax(b, q); });
+  if (rc) return rc;
+  for (int i = 0; i < n; ++i) { out[i].level = q[i].out.level; out[i].scale = q[i].out.scale; }
+  return 0;
+}
+
 static int check_queries(secpe_ctx* x, int n, const secpe_ct* in, const int* K, const int* C, const double* dmin,
                          const double* dmax) {
   for (int i = 0; i < n; ++i) {

@@ -27,6 +27,7 @@ struct Step {
 struct QState {
   ArgmaxQuery* q;
   int kp, cp, lk, lc;
+  int bsz = 0;   // packed input: block size (0 = one query per ciphertext)
   uint64_t rnext = 0;
   CT y, ydup, ym, d, s, x;
   int lp = 0, ls = 0;
@@ -100,26 +101,63 @@ static void run_step(Builder& b, int kind, std::vector<QState*>& qs) {
       for (QState* s : qs) cts.push_back(&s->y);
       maybe_refresh(b, qs, cts, std::vector<int>(n, 1));
       if (b.err_code) return;
-      std::vector<CT> in;
-      std::vector<double> v;
-      for (QState* s : qs) { in.push_back(s->y); v.push_back(-s->q->d_min); }
-      std::vector<CT> y1 = b.add_const(in, v);
-      if (b.err_code) return;
-      std::vector<std::vector<double>> masks;
-      std::vector<double> tg;
-      for (QState* s : qs) {
-        std::vector<double> m(s->cp, 0.0);
-        const double inv_range = 1.0 / (s->q->d_max - s->q->d_min);
-        for (int j = 0; j < s->q->C; ++j) m[j] = inv_range;
-        masks.push_back(m);
-        tg.push_back(delta);
+      std::vector<QState*> one, packed;
+      for (QState* s : qs) (s->bsz ? packed : one).push_back(s);
+      if (!one.empty()) {
+        std::vector<CT> in;
+        std::vector<double> v;
+        for (QState* s : one) { in.push_back(s->y); v.push_back(-s->q->d_min); }
+        std::vector<CT> y1 = b.add_const(in, v);
+        if (b.err_code) return;
+        std::vector<std::vector<double>> masks;
+        std::vector<double> tg;
+        for (QState* s : one) {
+          std::vector<double> m(s->cp, 0.0);
+          const double inv_range = 1.0 / (s->q->d_max - s->q->d_min);
+          for (int j = 0; j < s->q->C; ++j) m[j] = inv_range;
+          masks.push_back(m);
+          tg.push_back(delta);
+        }
+        std::vector<CT> yn = b.mul_plain(y1, masks, tg);
+        if (b.err_code) return;
+        for (size_t i = 0; i < one.size(); ++i) {
+          b.free_ct(y1[i]);
+          free_owned(b, one[i]->y);
+          one[i]->y = yn[i];
+        }
       }
-      std::vector<CT> yn = b.mul_plain(y1, masks, tg);
-      if (b.err_code) return;
-      for (size_t i = 0; i < n; ++i) {
-        b.free_ct(y1[i]);
-        free_owned(b, qs[i]->y);
-        qs[i]->y = yn[i];
+      if (!packed.empty()) {
+        // per block b: -D_min_b on its classes, then the mask 1/(D_max_b - D_min_b) there
+        std::vector<CT> in;
+        std::vector<Builder::SparseSlots> shift, mask;
+        std::vector<double> tg;
+        for (QState* s : packed) {
+          Builder::SparseSlots sh, mk;
+          const ArgmaxQuery& q = *s->q;
+          for (size_t bl = 0; bl < q.bK.size(); ++bl) {
+            const double inv_range = 1.0 / (q.bhi[bl] - q.blo[bl]);
+            for (int j = 0; j < q.bC[bl]; ++j) {
+              const int slot = (int)bl * s->bsz + j;
+              sh.slot.push_back(slot);
+              sh.val.push_back(-q.blo[bl]);
+              mk.slot.push_back(slot);
+              mk.val.push_back(inv_range);
+            }
+          }
+          in.push_back(s->y);
+          shift.push_back(sh);
+          mask.push_back(mk);
+          tg.push_back(delta);
+        }
+        std::vector<CT> y1 = b.add_plain_sparse(in, shift);
+        if (b.err_code) return;
+        std::vector<CT> yn = b.mul_plain_sparse(y1, mask, tg);
+        if (b.err_code) return;
+        for (size_t i = 0; i < packed.size(); ++i) {
+          b.free_ct(y1[i]);
+          free_owned(b, packed[i]->y);
+          packed[i]->y = yn[i];
+        }
       }
       break;
     }
@@ -293,6 +331,17 @@ static void run_step(Builder& b, int kind, std::vector<QState*>& qs) {
   }
 }
 
+void packed_shape(const std::vector<int>& K, const std::vector<int>& C, int* kp, int* cp, int* bsz) {
+  int lk = 0, lc = 0;
+  for (size_t i = 0; i < K.size(); ++i) {
+    lk = std::max(lk, ilog2_ceil(K[i]));
+    lc = std::max(lc, ilog2_ceil(C[i]));
+  }
+  *kp = 1 << lk;
+  *cp = 1 << lc;
+  *bsz = std::max(*kp * *cp, 2 * *cp);
+}
+
 ArgmaxProgram::ArgmaxProgram() {}
 ArgmaxProgram::~ArgmaxProgram() {
   for (QState* s : st_) delete s;
@@ -307,14 +356,25 @@ bool ArgmaxProgram::add(Builder& b, ArgmaxQuery* q) {
   const int total = C.dg + C.df;
   QState* s = new QState();
   s->q = q;
-  s->lk = ilog2_ceil(q->K);
-  s->lc = ilog2_ceil(q->C);
-  s->kp = 1 << s->lk;
-  s->cp = 1 << s->lc;
-  if (q->K < 1 || q->C < 1 || (int64_t)s->kp * s->cp > C.N / 2) {
-    delete s;
-    b.fail(-1, "K' * C' exceeds the slot count");
-    return false;
+  if (!q->bK.empty()) {
+    packed_shape(q->bK, q->bC, &s->kp, &s->cp, &s->bsz);
+    s->lk = ilog2_ceil(s->kp);
+    s->lc = ilog2_ceil(s->cp);
+    if ((int64_t)q->bK.size() * s->bsz > C.N / 2) {
+      delete s;
+      b.fail(-1, "packed queries exceed the slot count");
+      return false;
+    }
+  } else {
+    s->lk = ilog2_ceil(q->K);
+    s->lc = ilog2_ceil(q->C);
+    s->kp = 1 << s->lk;
+    s->cp = 1 << s->lc;
+    if (q->K < 1 || q->C < 1 || (int64_t)s->kp * s->cp > C.N / 2) {
+      delete s;
+      b.fail(-1, "K' * C' exceeds the slot count");
+      return false;
+    }
   }
   s->y = view(q->in);
   for (int k = 0; k < s->lk; ++k) s->prog.push_back({S_ROTADD, s->cp << k, false});

@@ -76,6 +76,7 @@ enum EwOp : int {
   //   (a = d_i, b = key-switch accumulator, c = its base conversion, k2 = P mod q, k = (P q_top)^-1)
   EW_RRCOMB = 14,
   EW_LIN2 = 15,      // o_i = a_i k[l] + b_i k2[l]   (b optional)
+  EW_PADD = 16,      // o0 = a0 + b0 (plaintext polynomial b0), o1 = a1
 };
 
 struct EwJob {
@@ -167,12 +168,14 @@ struct IntSpreadJob {
   int n_limbs, n_chain;
 };
 
-// encode: m_k = round(scale * 2/N * sum_{j < nnz} z_j cos(pi (5^j k mod 2N)/N))
+// encode: m_k = round(scale * 2/N * sum_{j < nnz} z_j cos(pi (5^j k mod 2N)/N));
+// sparse form (gs set): entry j is slot s_j with gs[j] = 5^{s_j} mod 2N
 struct EncodeJob {
   const double* z;      // [nnz] slot values
   int64_t* m;           // [N]
   double scale_hi, scale_lo;   // scale * 2 / N as a double-double
   int nnz, pad;
+  const uint32_t* gs;   // optional [nnz]
 };
 
 }  // namespace secpe

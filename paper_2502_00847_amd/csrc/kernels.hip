@@ -840,6 +840,15 @@ __global__ __launch_bounds__(256) void k_ew(const EwJob* __restrict__ jobs, DevT
             canon(mul_mod(red(mul_mod(a1.y, k2, m) + (b1.y - c1.y), m), kk, m), m));
         break;
       }
+      case EW_PADD: {
+        const double2 a0 = ld2(J.a0, o), p = ld2(J.b0, o);
+        st2(J.o0, o, add_mod(a0.x, p.x, m), add_mod(a0.y, p.y, m));
+        if (J.o1 != J.a1) {
+          const double2 a1 = ld2(J.a1, o);
+          st2(J.o1, o, a1.x, a1.y);
+        }
+        break;
+      }
       case EW_LIN2: {
         const double2 a0 = ld2(J.a0, o), a1 = ld2(J.a1, o);
         double r0x = mul_mod(a0.x, kk, m), r0y = mul_mod(a0.y, kk, m);
@@ -1131,8 +1140,9 @@ __global__ __launch_bounds__(256) void k_encode(const EncodeJob* __restrict__ jo
   uint32_t g = 1;
   for (int j = 0; j < J.nnz; ++j) {
     const double z = J.z[j];
+    const uint32_t gj = J.gs ? J.gs[j] : g;
     if (z != 0.0) {
-      const uint32_t t = (g * (uint32_t)k) & mask;
+      const uint32_t t = (gj * (uint32_t)k) & mask;
       double ph, pl;
       dd_mul(z, 0.0, T.cos_hi[t], T.cos_lo[t], ph, pl);
       dd_add(sh, sl, ph, pl);

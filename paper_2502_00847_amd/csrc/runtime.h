@@ -251,6 +251,17 @@ class Builder {
   std::vector<CT> mul_const(const std::vector<CT>& in, const std::vector<double>& v, const std::vector<double>& target);
   std::vector<CT> mul_plain(const std::vector<CT>& in, const std::vector<std::vector<double>>& z,
                             const std::vector<double>& target);
+  // slot values given as (slot, value) pairs
+  struct SparseSlots {
+    std::vector<int> slot;
+    std::vector<double> val;
+  };
+  std::vector<CT> mul_plain_sparse(const std::vector<CT>& in, const std::vector<SparseSlots>& z,
+                                   const std::vector<double>& target);
+  // x + encode(z) at x's scale
+  std::vector<CT> add_plain_sparse(const std::vector<CT>& in, const std::vector<SparseSlots>& z);
+  std::vector<CT> plain_op(const std::vector<CT>& in, const std::vector<std::vector<double>>* dense,
+                           const std::vector<SparseSlots>* sparse, const std::vector<double>* target, bool product);
   std::vector<CT> refresh(const std::vector<CT>& in, const std::vector<uint64_t>& seed,
                           const std::vector<uint64_t>& index);
   std::vector<CT> eval_odd9(const std::vector<CT>& x, const std::vector<const double*>& coef,
@@ -297,7 +308,14 @@ struct ArgmaxQuery {
   uint64_t refresh_seed;
   CT out;  // caller buffer (d set), level/scale written
   uint64_t ticket = 0;
+  // slot-packed input (several Argmax inputs in one ciphertext): per block
+  // K, C and the bounds of Eq. 5; empty for one query per ciphertext
+  std::vector<int> bK, bC;
+  std::vector<double> blo, bhi;
 };
+// K', C' and block size of a packed group (the largest padded shape; blocks
+// of max(K'C', 2C') slots)
+void packed_shape(const std::vector<int>& K, const std::vector<int>& C, int* kp, int* cp, int* bsz);
 void build_argmax(Builder& b, std::vector<ArgmaxQuery>& q);
 
 // Per-query state machines that survive across command lists: a round

@@ -964,30 +964,53 @@ std::vector<CT> Builder::mul_const(const std::vector<CT>& in, const std::vector<
   return lincomb(li, true);
 }
 
-// product with the encoded real vector z (slots 0..len-1), exact target scale
-std::vector<CT> Builder::mul_plain(const std::vector<CT>& in, const std::vector<std::vector<double>>& z,
-                                   const std::vector<double>& target) {
+// Plaintext operand of each item: its slot values (a dense prefix, or sparse
+// (slot, value) pairs) encoded at 'scale', spread to the item's limbs and
+// transformed.  product: x * pt, rescaled, scale := target (K of the encoding
+// = target q_l / s, exact target scale); otherwise x + pt at x's scale.
+std::vector<CT> Builder::plain_op(const std::vector<CT>& in, const std::vector<std::vector<double>>* dense,
+                                  const std::vector<SparseSlots>* sparse, const std::vector<double>* target,
+                                  bool product) {
   const int N = C.N;
+  const uint32_t m2n = 2u * (uint32_t)N;
   const size_t mark = scratch_mark();
   std::vector<CT> out;
   std::vector<EncodeJob> j_enc;
   std::vector<IntSpreadJob> j_sp;
   std::vector<NttJob> j_ntt;
-  std::vector<EwJob> j_mul;
+  std::vector<EwJob> j_op;
   for (size_t i = 0; i < in.size(); ++i) {
     const CT& x = in[i];
     const int nl = x.level + 1;
-    const double ql = (double)C.mod[x.level];
-    double ps = target[i] * ql;
-    ps = ps / x.scale;
+    double ps = x.scale;
+    if (product) {
+      const double ql = (double)C.mod[x.level];
+      ps = (*target)[i] * ql;
+      ps = ps / x.scale;
+    }
     int64_t* m = (int64_t*)scratch(N);
     double* pt = scratch((size_t)nl * N);
     EncodeJob ej{};
-    ej.z = put(z[i]);
+    if (sparse) {
+      const SparseSlots& sp = (*sparse)[i];
+      std::vector<uint32_t> g(sp.slot.size());
+      for (size_t j = 0; j < sp.slot.size(); ++j) {
+        // 5^slot mod 2N
+        uint64_t r = 1, b = 5;
+        for (uint32_t e = (uint32_t)sp.slot[j]; e; e >>= 1, b = b * b % m2n)
+          if (e & 1) r = r * b % m2n;
+        g[j] = (uint32_t)r;
+      }
+      ej.z = put(sp.val);
+      ej.gs = put(g);
+      ej.nnz = (int)sp.val.size();
+    } else {
+      ej.z = put((*dense)[i]);
+      ej.nnz = (int)(*dense)[i].size();
+    }
     ej.m = m;
     ej.scale_hi = ps * 2.0 / (double)N;
     ej.scale_lo = 0.0;
-    ej.nnz = (int)z[i].size();
     j_enc.push_back(ej);
     j_sp.push_back(IntSpreadJob{m, pt, nl, nl});
     j_ntt.push_back(NttJob{pt, pt, nl, nl, 0, 0});
@@ -995,19 +1018,34 @@ std::vector<CT> Builder::mul_plain(const std::vector<CT>& in, const std::vector<
     EwJob e{};
     e.o0 = c0(o); e.o1 = c1(o); e.a0 = c0(x); e.a1 = c1(x); e.b0 = pt;
     e.n_limbs = nl; e.n_chain = nl;
-    e.op = EW_PMUL;
-    j_mul.push_back(e);
+    e.op = product ? EW_PMUL : EW_PADD;
+    j_op.push_back(e);
     out.push_back(o);
   }
   encode(j_enc);
   intspread(j_sp);
   ntt(j_ntt, false);
-  ew(j_mul);
-  rescale(out);
-  if (err_code) return {};
-  for (size_t i = 0; i < out.size(); ++i) out[i].scale = target[i];
+  ew(j_op);
+  if (product) {
+    rescale(out);
+    if (err_code) return {};
+    for (size_t i = 0; i < out.size(); ++i) out[i].scale = (*target)[i];
+  }
   scratch_release(mark);
   return out;
+}
+
+// product with the encoded real vector z (slots 0..len-1), exact target scale
+std::vector<CT> Builder::mul_plain(const std::vector<CT>& in, const std::vector<std::vector<double>>& z,
+                                   const std::vector<double>& target) {
+  return plain_op(in, &z, nullptr, &target, true);
+}
+std::vector<CT> Builder::mul_plain_sparse(const std::vector<CT>& in, const std::vector<SparseSlots>& z,
+                                          const std::vector<double>& target) {
+  return plain_op(in, nullptr, &z, &target, true);
+}
+std::vector<CT> Builder::add_plain_sparse(const std::vector<CT>& in, const std::vector<SparseSlots>& z) {
+  return plain_op(in, nullptr, &z, nullptr, false);
 }
 
 // encryption of integer plaintexts (device int64 coefficient arrays) at the top level

@@ -76,6 +76,10 @@ def load():
         "secpe_op_add_const": (i32, [vp, ct, dbl, ct]),
         "secpe_op_mul_const": (i32, [vp, ct, dbl, dbl, vp, sz, ct]),
         "secpe_op_lincomb": (i32, [vp, ct, dbl, ct, dbl, dbl, i32, vp, sz, ct]),
+        "secpe_packed_shape": (i32, [vp, i32, P(i32), P(i32), P(i32)]),
+        "secpe_encrypt_packed": (i32, [vp, vp, i32, P(dbl), P(i32), P(i32), u64, ct]),
+        "secpe_packed_workspace_bytes": (sz, [vp, i32, P(i32), P(i32), P(i32)]),
+        "secpe_eval_argmax_packed": (i32, [vp, i32, ct, P(i32), P(i32), P(i32), P(dbl), P(dbl), P(u64), vp, sz, ct]),
         "secpe_autotune": (i32, [vp, i32, ct, P(i32), P(i32), P(dbl), P(dbl), P(u64), vp, sz, ct, P(i32), P(dbl),
                                  i32]),
         "secpe_op_mul_plain": (i32, [vp, ct, P(dbl), i32, dbl, vp, sz, ct]),
@@ -117,7 +121,8 @@ def exported_symbols():
          "secpe_decrypt_coeffs", "secpe_workspace_bytes", "secpe_eval_argmax", "secpe_eval_argmax_batch",
          "secpe_counters", "secpe_ct_export", "secpe_ct_import", "secpe_key_export", "secpe_sk_export",
          "secpe_sync", "secpe_op_workspace_bytes", "secpe_op_add", "secpe_op_sub", "secpe_op_add_const",
-         "secpe_op_mul_const", "secpe_op_lincomb", "secpe_autotune", "secpe_op_mul_plain", "secpe_op_rescale", "secpe_op_mul_relin",
+         "secpe_op_mul_const", "secpe_op_lincomb", "secpe_autotune", "secpe_packed_shape", "secpe_encrypt_packed",
+         "secpe_packed_workspace_bytes", "secpe_eval_argmax_packed", "secpe_op_mul_plain", "secpe_op_rescale", "secpe_op_mul_relin",
          "secpe_op_mul_relin_rescale", "secpe_op_rotate", "secpe_op_refresh", "secpe_op_eval_odd9",
          "secpe_op_key_switch", "secpe_op_ntt", "secpe_op_ring_mul", "secpe_op_encode", "secpe_profile_begin",
          "secpe_profile_end", "secpe_ntt_cts", "secpe_rotate_workspace_bytes", "secpe_rotate_batch",
@@ -244,6 +249,75 @@ class Context:
         self._check(self.lib.secpe_decrypt(self.h, C.c_void_p(sk.data_ptr()), C.byref(c), nslots,
                                            _p(z, C.c_double), C.byref(idx)))
         return z, int(idx.value)
+
+    # -- slot-packed Argmax ------------------------------------------------------
+    def packed_shape(self, shapes):
+        """(blocks per ciphertext, K', C', block size) for a group of (K, C) shapes."""
+        Ks = np.ascontiguousarray([k for k, _ in shapes], dtype=np.int32)
+        Cs = np.ascontiguousarray([c for _, c in shapes], dtype=np.int32)
+        out = np.zeros(3, dtype=np.int32)
+        per = self.lib.secpe_packed_shape(self.h, len(shapes), _p(Ks, C.c_int), _p(Cs, C.c_int), _p(out, C.c_int))
+        if per < 0:
+            self._check(per)
+        return int(per), int(out[0]), int(out[1]), int(out[2])
+
+    def encrypt_packed(self, blocks, seed, sk=None):
+        """blocks: list of K_b x C_b logit arrays, one query per slot block."""
+        sk = self.sk if sk is None else sk
+        Ks = np.ascontiguousarray([np.asarray(b).shape[0] for b in blocks], dtype=np.int32)
+        Cs = np.ascontiguousarray([np.asarray(b).shape[1] for b in blocks], dtype=np.int32)
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(b, dtype=np.float64).ravel() for b in blocks]))
+        ct = self.new_ct()
+        c = ct._c()
+        self._check(self.lib.secpe_encrypt_packed(self.h, C.c_void_p(sk.data_ptr()), len(blocks), _p(flat, C.c_double),
+                                                  _p(Ks, C.c_int), _p(Cs, C.c_int), int(seed), C.byref(c)))
+        ct.level, ct.scale = c.level, c.scale
+        return ct
+
+    def _packed_arrays(self, groups):
+        nb = np.ascontiguousarray([len(g) for g in groups], dtype=np.int32)
+        Ks = np.ascontiguousarray([k for g in groups for k, _ in g], dtype=np.int32)
+        Cs = np.ascontiguousarray([c for g in groups for _, c in g], dtype=np.int32)
+        return nb, Ks, Cs
+
+    def packed_workspace(self, groups):
+        nb, Ks, Cs = self._packed_arrays(groups)
+        n = self.lib.secpe_packed_workspace_bytes(self.h, len(groups), _p(nb, C.c_int), _p(Ks, C.c_int),
+                                                  _p(Cs, C.c_int))
+        if n == 0:
+            raise SecpeError(self.lib.secpe_last_error().decode())
+        return self._empty(n)
+
+    def eval_argmax_packed(self, cts, groups, d_min, d_max, seeds, ws=None, outs=None):
+        """groups[i]: the (K, C) shapes packed in cts[i]; d_min, d_max: per block, concatenated."""
+        n = len(cts)
+        nb, Ks, Cs = self._packed_arrays(groups)
+        lo = np.ascontiguousarray(d_min, dtype=np.float64)
+        hi = np.ascontiguousarray(d_max, dtype=np.float64)
+        sd = np.ascontiguousarray([int(s) for s in seeds], dtype=np.uint64)
+        if ws is None:
+            ws = self.packed_workspace(groups)
+        if outs is None:
+            outs = [self.new_ct() for _ in range(n)]
+        cin = (_Ct * n)(*[c._c() for c in cts])
+        cout = (_Ct * n)(*[c._c() for c in outs])
+        self._check(self.lib.secpe_eval_argmax_packed(self.h, n, cin, _p(nb, C.c_int), _p(Ks, C.c_int),
+                                                      _p(Cs, C.c_int), _p(lo, C.c_double), _p(hi, C.c_double),
+                                                      _p(sd, C.c_uint64), C.c_void_p(ws.data_ptr()), ws.numel() * 8,
+                                                      cout))
+        for o, c in zip(outs, cout):
+            o.level, o.scale = c.level, c.scale
+        return outs
+
+    def decrypt_packed(self, ct, shapes, sk=None):
+        """Each block's decrypted z[:C_b] and its index."""
+        per, kp, cp, bsz = self.packed_shape(shapes)
+        z, _ = self.decrypt(ct, len(shapes) * bsz, sk)
+        out = []
+        for b, (_, c) in enumerate(shapes):
+            zb = z[b * bsz:b * bsz + c]
+            out.append((zb, int(np.argmax(zb))))
+        return out
 
     def decrypt_coeffs(self, ct, sk=None):
         sk = self.sk if sk is None else sk

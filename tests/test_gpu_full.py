@@ -183,3 +183,24 @@ def test_config3_batch_indices_and_bit_identity(full_gpu):
     for i in (0, 37, 130, 255):
         alone = g.eval_argmax(cts[i], qs[i]["K"], qs[i]["C"], qs[i]["d_min"], qs[i]["d_max"], qs[i]["refresh_seed"])
         assert np.array_equal(g.export(alone), g.export(outs[i]))
+
+
+def test_config3_packed_indices(full_gpu):
+    """The 256 config-3 queries packed 128 per ciphertext (blocks of 256 slots, K' = C' = 16):
+    every block's decrypted index equals the plaintext argmax at normalised margin >= 2^-10."""
+    g = full_gpu
+    qs = [W.query(3, i) for i in range(256)]
+    shapes = [(q["K"], q["C"]) for q in qs]
+    per, kp, cp, bsz = g.packed_shape(shapes)
+    assert per == 128 and (kp, cp, bsz) == (16, 16, 256)
+    groups = [shapes[i:i + per] for i in range(0, 256, per)]
+    cts = [g.encrypt_packed([q["logits"] for q in qs[i:i + per]], 7000 + i) for i in range(0, 256, per)]
+    outs = g.eval_argmax_packed(cts, groups, [q["d_min"] for q in qs], [q["d_max"] for q in qs], [8000, 8001])
+    bad = []
+    for j, (ct, grp) in enumerate(zip(outs, groups)):
+        for b, (zb, idx) in enumerate(g.decrypt_packed(ct, grp)):
+            q = qs[j * per + b]
+            i0, _, margin = sim.t0_argmax(q["logits"])
+            if margin / (q["d_max"] - q["d_min"]) >= 2.0**-10 and idx != i0:
+                bad.append(j * per + b)
+    assert not bad, bad

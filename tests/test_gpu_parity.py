@@ -283,6 +283,42 @@ def test_argmax_refresh_below_top_bit_exact(name):
     _same(g, zg, zo)
 
 
+def _packed_case(seed, shapes):
+    blocks = [W.logits(9, seed * 100 + i, K, C) for i, (K, C) in enumerate(shapes)]
+    lo = [W.d_bounds(K)[0] for K, _ in shapes]
+    hi = [W.d_bounds(K)[1] for K, _ in shapes]
+    return blocks, lo, hi
+
+
+@pytest.mark.parametrize("name", ["tiny", "p13"])
+def test_packed_argmax_bit_exact(name, tiny, p13):
+    """Slot-packed Argmax (several queries in one ciphertext, Sec. 3.2): encryption and
+    the whole evaluation match the oracle bit for bit; two packed ciphertexts in one
+    batch give the same bits as each alone; every block decodes to its plaintext argmax."""
+    g, o, _ = tiny if name == "tiny" else p13
+    groups = [[(3, 5), (2, 3), (4, 2), (1, 4)], [(2, 2), (3, 3)]]
+    if name == "p13":
+        groups = [[(3, 4), (2, 3), (4, 2)], [(1, 2), (2, 4)]]
+    cases = [_packed_case(20 + i, sh) for i, sh in enumerate(groups)]
+    gcts, octs = [], []
+    for i, (blocks, lo, hi) in enumerate(cases):
+        octs.append(o.encrypt_packed(blocks, 50 + i))
+        gcts.append(g.encrypt_packed(blocks, 50 + i))
+        _same(g, gcts[-1], octs[-1])
+    lo_all = [v for _, lo, _ in cases for v in lo]
+    hi_all = [v for _, _, hi in cases for v in hi]
+    outs = g.eval_argmax_packed(gcts, groups, lo_all, hi_all, [60, 61])
+    for i, (blocks, lo, hi) in enumerate(cases):
+        zo = o.eval_argmax_packed(octs[i], groups[i], lo, hi, 60 + i)
+        _same(g, outs[i], zo)
+        alone = g.eval_argmax_packed([gcts[i]], [groups[i]], lo, hi, [60 + i])[0]
+        assert np.array_equal(g.export(alone), g.export(outs[i]))
+        for (zb, idx), y, l, h in zip(g.decrypt_packed(outs[i], groups[i]), blocks, lo, hi):
+            i0, _, margin = sim.t0_argmax(y)
+            if margin / (h - l) >= 2.0**-10:
+                assert idx == i0
+
+
 def test_argmax_toy_config(p13):
     """Toy-shaped parameters with the two-pass NTT: K=4, C=2 (config 1 shape)."""
     g, o, _ = p13
