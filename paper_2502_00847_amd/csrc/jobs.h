@@ -123,6 +123,8 @@ struct ModDownJob {
 // Inner product with a switching key: acc_w[t] = sum_j x_j[t] * key_j[w][t]
 // When top0 is set, limb n_chain-1 of acc_w also gets pmq[n_chain-1] * top_w
 // (the top limb of P d_w for the merged relinearise + rescale).
+// The fused kernel (N > 2^12) writes limbs t >= inv_from of acc after the
+// first pass of their inverse transform (the column pass follows).
 struct InnerJob {
   const double* d;      // NTT-domain input polynomial (chain limbs 0..level)
   const double* ext;    // [dnum][n_ext][N] ModUp outputs, NTT domain
@@ -132,6 +134,7 @@ struct InnerJob {
   const double* top1;
   const double* pmq;    // [n_q] P mod q_t
   int n_chain, n_ext, n_digits, alpha;
+  int inv_from, pad;
 };
 
 // Galois automorphism in the NTT domain (bit-reversed evaluation order)

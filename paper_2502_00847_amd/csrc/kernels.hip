@@ -334,6 +334,40 @@ __device__ __forceinline__ void fwd_col_from_regs(double* x, double* lds, gdbl* 
   }
 }
 
+// Inverse row pass (the first pass of the inverse transform) on one G x S
+// tile already in LDS in row layout (element e of row v at lpad(v*S + e)):
+// rounds B and A, then the tile is stored canonically to rows row0 .. of dst
+// (one limb; no N^-1, which the column pass applies).
+template <int LOGS, int G>
+__device__ __forceinline__ void inv_row_from_lds(double* lds, gdbl* dst, int row0, int k1, kdbl* tw, kdbl* twq,
+                                                 const Mod& m) {
+  constexpr int S = 1 << LOGS;
+  constexpr int RB = LOGS - 4;
+  constexpr int NB = 1 << RB;
+  constexpr int GB = 16 / NB;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int gi = 0; gi < GB; ++gi) {
+    const int grp = t + gi * 256;
+    const int vb = grp / 16, hb = grp % 16;
+    double y[NB];
+#pragma unroll
+    for (int e = 0; e < NB; ++e) y[e] = lds[lpad(vb * S + hb * NB + e)];
+    ntt_round<LOGS, RB, NTT_ROW, true>(y, hb, 0, row0 + vb, k1, tw, twq, m);
+    // each group is read and written back by its own thread: no barrier needed here
+#pragma unroll
+    for (int e = 0; e < NB; ++e) lds[lpad(vb * S + hb * NB + e)] = y[e];
+  }
+  __syncthreads();
+  const int va = t / NB, la = t % NB;
+  double x[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) x[e] = lds[lpad(va * S + e * NB + la)];
+  ntt_round<LOGS, 4, NTT_ROW, true>(x, 0, RB, row0 + va, k1, tw, twq, m);
+#pragma unroll
+  for (int e = 0; e < 16; ++e) dst[(size_t)(row0 + va) * S + e * NB + la] = canon(x[e], m);
+}
+
 template <int LOGS, int G, int MODE, bool INV>
 __global__ __launch_bounds__(256) void k_ntt2(const NttJob* __restrict__ jobs, DevTables T, int second) {
   extern __shared__ double lds[];
@@ -431,6 +465,8 @@ __global__ __launch_bounds__(256) void k_ntt2(const NttJob* __restrict__ jobs, D
         lds[lpad(2 * i + 1)] = v.y;
       }
       __syncthreads();
+      inv_row_from_lds<LOGS, G>(lds, dst, row0, k1, tw, twq, m);
+      return;
     }
 #pragma unroll
     for (int gi = 0; gi < GB; ++gi) {
@@ -557,14 +593,36 @@ __global__ __launch_bounds__(256) void k_inner_row(const InnerJob* __restrict__ 
   const double pm = top ? KPTR(J.pmq)[t] : 0.0;
 #pragma unroll
   for (int q = 0; q < NP; ++q) {
-    const size_t o = (size_t)t * N + tile + 2 * (threadIdx.x + 256 * q);
     if (top) {
+      const size_t o = (size_t)t * N + tile + 2 * (threadIdx.x + 256 * q);
       const double2 u0 = ld2(J.top0, o), u1 = ld2(J.top1, o);
       a0x[q] = red(a0x[q], m) + mul_mod(u0.x, pm, m);
       a0y[q] = red(a0y[q], m) + mul_mod(u0.y, pm, m);
       a1x[q] = red(a1x[q], m) + mul_mod(u1.x, pm, m);
       a1y[q] = red(a1y[q], m) + mul_mod(u1.y, pm, m);
     }
+  }
+  if (t >= J.inv_from) {
+    // limbs the base conversion reads: the first pass of their inverse
+    // transform runs here, on the tile in LDS
+    kdbl* itw = KPTR(T.ipsi) + (size_t)pr * N;
+    kdbl* itwq = KPTR(T.ipsiq) + (size_t)pr * N;
+    for (int w = 0; w < 2; ++w) {
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        lds[lpad(2 * i)] = canon(w ? a1x[q] : a0x[q], m);
+        lds[lpad(2 * i + 1)] = canon(w ? a1y[q] : a0y[q], m);
+      }
+      __syncthreads();
+      inv_row_from_lds<LOGS, G>(lds, GPTR(J.acc) + ((size_t)w * J.n_ext + t) * N, row0, k1, itw, itwq, m);
+      __syncthreads();
+    }
+    return;
+  }
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    const size_t o = (size_t)t * N + tile + 2 * (threadIdx.x + 256 * q);
     st2(J.acc, o, canon(a0x[q], m), canon(a0y[q], m));
     st2(J.acc, (size_t)J.n_ext * N + o, canon(a1x[q], m), canon(a1y[q], m));
   }

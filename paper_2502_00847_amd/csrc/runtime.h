@@ -122,7 +122,7 @@ void destroy_context(Ctx& c);
 // ---------------------------------------------------------------------------
 // command list: descriptors in one blob, launches replayed in order
 // ---------------------------------------------------------------------------
-enum CmdKind { C_NTT, C_NTT_FIRST, C_EW, C_MODUP, C_MODUP_COL, C_MODDOWN, C_INNER, C_INNER_ROW, C_AUTO, C_LIFT, C_SAMPLE, C_INTSPREAD, C_ENCODE, C_DECODE };
+enum CmdKind { C_NTT, C_NTT_FIRST, C_NTT_SECOND, C_EW, C_MODUP, C_MODUP_COL, C_MODDOWN, C_INNER, C_INNER_ROW, C_AUTO, C_LIFT, C_SAMPLE, C_INTSPREAD, C_ENCODE, C_DECODE };
 
 struct Cmd {
   int kind;
@@ -190,7 +190,9 @@ class Builder {
   // raw launches
   // first_pass_only: the column pass of a two-pass forward NTT (its row pass
   // runs inside the fused inner product)
-  void ntt(const std::vector<NttJob>& v, bool inverse, bool first_pass_only = false);
+  // pass: -1 = the whole transform; 0 or 1 = only that pass of a two-pass
+  // NTT (the other pass runs fused into a neighbouring kernel)
+  void ntt(const std::vector<NttJob>& v, bool inverse, int pass = -1);
   void ew(const std::vector<EwJob>& v);
   void modup(const std::vector<ModUpJob>& v);
   void modup_col(const std::vector<ModUpJob>& v);
@@ -238,7 +240,10 @@ class Builder {
     double va, vb, target;
     bool has_b;
   };
-  void ks_front(const std::vector<KsItem>& items, std::vector<KsTmp>& tmp);
+  // merged: the conversion that follows reads limbs level .. level+n_p of the
+  // accumulator (merged relinearise + rescale), else the special limbs only;
+  // the fused inner product runs the first inverse NTT pass on those limbs
+  void ks_front(const std::vector<KsItem>& items, std::vector<KsTmp>& tmp, bool merged);
   void key_switch(const std::vector<KsItem>& items);
   std::vector<Deg2> tensor2(const std::vector<TensorItem>& v);
   std::vector<CT> relin_rescale(const std::vector<Deg2>& xs);

@@ -380,7 +380,7 @@ void Builder::push(int kind, int n, int max_y, size_t off, bool inv, int64_t uni
     push(KIND, (int)(V).size(), MAXY, (size_t)(p - arena_), INV, UNITS);        \
   } while (0)
 
-void Builder::ntt(const std::vector<NttJob>& v, bool inverse, bool first_pass_only) {
+void Builder::ntt(const std::vector<NttJob>& v, bool inverse, int pass) {
   int my = 0;
   int64_t units = 0;
   for (auto& j : v) {
@@ -388,7 +388,7 @@ void Builder::ntt(const std::vector<NttJob>& v, bool inverse, bool first_pass_on
     const int lo = std::max(0, std::min(j.skip_lo, j.n_limbs)), hi = std::max(lo, std::min(j.skip_hi, j.n_limbs));
     units += j.n_limbs - (hi - lo);
   }
-  PUSH_JOBS(first_pass_only ? C_NTT_FIRST : C_NTT, v, my, inverse, units);
+  PUSH_JOBS(pass == 0 ? C_NTT_FIRST : pass == 1 ? C_NTT_SECOND : C_NTT, v, my, inverse, units);
 }
 void Builder::ew(const std::vector<EwJob>& v) {
   int my = 0;
@@ -453,7 +453,8 @@ void Builder::decode(const int64_t* m, double* z, int nslots, double inv_scale) 
 int prof_kind_of(const Cmd& k) {
   switch (k.kind) {
     case C_NTT:
-    case C_NTT_FIRST: return k.inv ? PROF_NTT_INV : PROF_NTT_FWD;
+    case C_NTT_FIRST:
+    case C_NTT_SECOND: return k.inv ? PROF_NTT_INV : PROF_NTT_FWD;
     case C_EW: return PROF_EW;
     case C_MODUP:
     case C_MODUP_COL: return PROF_MODUP;
@@ -479,7 +480,7 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
   hipStream_t s = c.stream;
   for (const Cmd& k : cmds) {
     const void* j = arena + k.off;
-    if ((k.kind == C_NTT || k.kind == C_NTT_FIRST) && ntt_pass_count(T) == 2) {
+    if ((k.kind == C_NTT || k.kind == C_NTT_FIRST || k.kind == C_NTT_SECOND) && ntt_pass_count(T) == 2) {
       // Two-pass NTT, issued in groups of jobs whose data fits ntt_chunk_bytes
       // so the intermediate between the passes can stay in the Infinity
       // Cache.  The pass profilers bracket each launch of their pass.
@@ -491,13 +492,13 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
       if (c.ntt_chunk_bytes > 0) chunk = (int)std::max<size_t>(1, c.ntt_chunk_bytes / per_job);
       hipEvent_t w0 = whole_prof ? prof_event(c) : nullptr;
       if (w0) (void)hipEventRecord(w0, s);
-      const int passes = k.kind == C_NTT_FIRST ? 1 : 2;
-      // a first-pass-only launch counts as half of its limb transforms
-      if (whole_prof) { c.prof_launches++; c.prof_units += passes == 2 ? k.units : k.units / 2; }
+      const int p_lo = k.kind == C_NTT_SECOND ? 1 : 0, p_hi = k.kind == C_NTT_FIRST ? 1 : 2;
+      // a single-pass launch counts as half of its limb transforms
+      if (whole_prof) { c.prof_launches++; c.prof_units += p_hi - p_lo == 2 ? k.units : k.units / 2; }
       const NttJob* jobs = (const NttJob*)j;
       for (int j0 = 0; j0 < k.n; j0 += chunk) {
         const int nj = std::min(chunk, k.n - j0);
-        for (int pass = 0; pass < passes; ++pass) {
+        for (int pass = p_lo; pass < p_hi; ++pass) {
           hipEvent_t e0 = pass == pass_prof ? prof_event(c) : nullptr;
           if (e0) {
             (void)hipEventRecord(e0, s);
@@ -510,7 +511,7 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
           }
         }
       }
-      if (pass_prof >= 0 && pass_prof < passes) c.prof_units += k.units;
+      if (pass_prof >= p_lo && pass_prof < p_hi) c.prof_units += k.units;
       if (w0) {
         hipEvent_t w1 = prof_event(c);
         if (w1) (void)hipEventRecord(w1, s);
@@ -527,6 +528,7 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
     switch (k.kind) {
       case C_NTT: launch_ntt(T, k.inv, (const NttJob*)j, k.n, k.max_y, s); break;
       case C_NTT_FIRST: launch_ntt_pass(T, k.inv, (const NttJob*)j, k.n, k.max_y, 0, s); break;
+      case C_NTT_SECOND: launch_ntt_pass(T, k.inv, (const NttJob*)j, k.n, k.max_y, 1, s); break;
       case C_EW: launch_ew(T, (const EwJob*)j, k.n, k.max_y, s); break;
       case C_MODUP: launch_modup(T, (const ModUpJob*)j, k.n, s); break;
       case C_MODUP_COL: launch_modup_col(T, (const ModUpJob*)j, k.n, k.max_y, c.modup_eg, s); break;
@@ -581,7 +583,7 @@ int submit(Ctx& c, Builder& b, char* arena, size_t arena_bytes) {
 // ---------------------------------------------------------------------------
 // first half, shared by key switching and the merged relinearise + rescale:
 // the accumulator acc_w over Q_l u P (NTT domain) with acc0 + acc1 s' = P d s + small
-void Builder::ks_front(const std::vector<KsItem>& items, std::vector<KsTmp>& tmp) {
+void Builder::ks_front(const std::vector<KsItem>& items, std::vector<KsTmp>& tmp, bool merged) {
   const int N = C.N, alpha = C.alpha, n_p = C.n_p;
   const bool fused = inner_row_fused(C.T);
   tmp.resize(items.size());
@@ -608,7 +610,9 @@ void Builder::ks_front(const std::vector<KsItem>& items, std::vector<KsTmp>& tmp
       j_up.push_back(ModUpJob{t.dcoef, e, dt.cinv, dt.chat, lo, hi, nc, n_ext});
       j_fwd_ext.push_back(NttJob{e, e, n_ext, nc, lo, hi});
     }
-    j_in.push_back(InnerJob{it.d, t.ext, it.key, t.acc, it.top0, it.top1, C.p_mod_q, nc, n_ext, nd, alpha});
+    InnerJob in{it.d, t.ext, it.key, t.acc, it.top0, it.top1, C.p_mod_q, nc, n_ext, nd, alpha};
+    in.inv_from = fused ? (merged ? l : l + 1) : n_ext;
+    j_in.push_back(in);
   }
   ntt(j_inv, true);
   if (fused) {
@@ -625,7 +629,7 @@ void Builder::ks_front(const std::vector<KsItem>& items, std::vector<KsTmp>& tmp
 void Builder::key_switch(const std::vector<KsItem>& items) {
   const int N = C.N, n_p = C.n_p;
   std::vector<KsTmp> tmp;
-  ks_front(items, tmp);
+  ks_front(items, tmp, false);
   std::vector<NttJob> j_inv_acc, j_fwd_conv;
   std::vector<ModDownJob> j_down;
   for (size_t i = 0; i < items.size(); ++i) {
@@ -636,6 +640,7 @@ void Builder::key_switch(const std::vector<KsItem>& items) {
     for (int w = 0; w < 2; ++w) {
       double* aw = acc + (size_t)w * n_ext * N;
       double* sp = aw + (size_t)nc * N;
+      // (fused: the first pass already ran inside the inner product)
       j_inv_acc.push_back(NttJob{sp, sp, n_p, 0, 0, 0});
       double* cv = conv + (size_t)w * nc * N;
       j_down.push_back(ModDownJob{sp, cv, C.md_cinv, C.md_chat, nc, -1});
@@ -649,7 +654,7 @@ void Builder::key_switch(const std::vector<KsItem>& items) {
       j_fwd_conv.push_back(f);
     }
   }
-  ntt(j_inv_acc, true);
+  ntt(j_inv_acc, true, inner_row_fused(C.T) ? 1 : -1);
   moddown(j_down);
   ntt(j_fwd_conv, false);
   counters[3] += (int64_t)items.size();
@@ -669,7 +674,7 @@ std::vector<CT> Builder::relin_rescale(const std::vector<Deg2>& xs) {
     items.push_back(KsItem{x.d2, x.level, rk, nullptr, nullptr, nullptr, nullptr, x.d0, x.d1});
   }
   std::vector<KsTmp> tmp;
-  ks_front(items, tmp);
+  ks_front(items, tmp, true);
   std::vector<CT> out;
   std::vector<NttJob> j_inv_acc, j_fwd_conv;
   std::vector<ModDownJob> j_conv;
@@ -698,7 +703,8 @@ std::vector<CT> Builder::relin_rescale(const std::vector<Deg2>& xs) {
     }
     out.push_back(o);
   }
-  ntt(j_inv_acc, true);
+  // (fused: the first inverse pass already ran inside the inner product)
+  ntt(j_inv_acc, true, inner_row_fused(C.T) ? 1 : -1);
   moddown(j_conv);
   ntt(j_fwd_conv, false);
   counters[2] += (int64_t)xs.size();
