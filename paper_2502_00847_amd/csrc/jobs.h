@@ -41,11 +41,15 @@ enum NttEpi : int {
 //  * epi != EPI_NONE: the transform v of limb l is not stored; eout at the
 //    same position receives the combination above (ea, eb, ebase, eout are
 //    limb-major arrays indexed like dst; ek, ek2 per-limb constants).
+//  * sq (squares of degree-1 ciphertexts, two-pass sizes): an inverse
+//    transform squares src on load; the EPI_RRCOMB epilogue takes its d as
+//    ea^2 (sq = 1) or 2 ea ebase (sq = 2) instead of reading it.
 struct NttJob {
   const double* src;
   double* dst;
   int n_limbs, n_chain, skip_lo, skip_hi;
   int spread_from, epi;
+  int sq, pad;
   const double* ea;
   const double* eb;
   const double* ebase;
@@ -124,7 +128,9 @@ struct ModDownJob {
 // When top0 is set, limb n_chain-1 of acc_w also gets pmq[n_chain-1] * top_w
 // (the top limb of P d_w for the merged relinearise + rescale).
 // The fused kernel (N > 2^12) writes limbs t >= inv_from of acc after the
-// first pass of their inverse transform (the column pass follows).
+// first pass of their inverse transform (the column pass follows).  With
+// d_square set, d (and top) hold a1 (and a0, a1) of a square: the digit
+// limbs are d^2 and the top term is a0^2 (w = 0) or 2 a0 a1 (w = 1).
 struct InnerJob {
   const double* d;      // NTT-domain input polynomial (chain limbs 0..level)
   const double* ext;    // [dnum][n_ext][N] ModUp outputs, NTT domain
@@ -134,7 +140,7 @@ struct InnerJob {
   const double* top1;
   const double* pmq;    // [n_q] P mod q_t
   int n_chain, n_ext, n_digits, alpha;
-  int inv_from, pad;
+  int inv_from, d_square;
 };
 
 // Galois automorphism in the NTT domain (bit-reversed evaluation order)

@@ -55,7 +55,16 @@ __device__ __forceinline__ void ntt_epilogue(const NttJob& J, int l, size_t o, d
     r1 = mul_mod(a.y - c1, k, m);
   } else if (J.epi == EPI_RRCOMB) {
     const double k2 = KPTR(J.ek2)[l];
-    const double2 a = ld2(J.ea, o), b = ld2(J.eb, o);
+    double2 a = ld2(J.ea, o);
+    const double2 b = ld2(J.eb, o);
+    if (J.sq == 1) {
+      a.x = mul_mod(a.x, a.x, m);
+      a.y = mul_mod(a.y, a.y, m);
+    } else if (J.sq == 2) {
+      const double2 a1 = ld2(J.ebase, o);
+      a.x = mul_mod(2.0 * a.x, a1.x, m);
+      a.y = mul_mod(2.0 * a.y, a1.y, m);
+    }
     r0 = mul_mod(red(mul_mod(a.x, k2, m) + (b.x - c0), m), k, m);
     r1 = mul_mod(red(mul_mod(a.y, k2, m) + (b.y - c1), m), k, m);
   } else {
@@ -459,10 +468,11 @@ __global__ __launch_bounds__(256) void k_ntt2(const NttJob* __restrict__ jobs, D
     // ---- round B first (low bits), loaded straight (column) or via LDS (row)
     if (MODE == NTT_ROW) {
       cgdbl2* s2 = (cgdbl2*)(src + (size_t)row0 * S);
+      const bool sq = J.sq && !second;
       for (int i = t; i < G * S / 2; i += 256) {
         const dv2 v = s2[i];
-        lds[lpad(2 * i)] = v.x;
-        lds[lpad(2 * i + 1)] = v.y;
+        lds[lpad(2 * i)] = sq ? canon(mul_mod(v.x, v.x, m), m) : v.x;
+        lds[lpad(2 * i + 1)] = sq ? canon(mul_mod(v.y, v.y, m), m) : v.y;
       }
       __syncthreads();
       inv_row_from_lds<LOGS, G>(lds, dst, row0, k1, tw, twq, m);
@@ -569,8 +579,8 @@ __global__ __launch_bounds__(256) void k_inner_row(const InnerJob* __restrict__ 
       double xx, xy;
       if (j == own) {
         const double2 v = ld2(J.d, (size_t)t * N + tile + 2 * i);
-        xx = v.x;
-        xy = v.y;
+        xx = J.d_square ? canon(mul_mod(v.x, v.x, m), m) : v.x;
+        xy = J.d_square ? canon(mul_mod(v.y, v.y, m), m) : v.y;
       } else {
         xx = canon(lds[lpad(2 * i)], m);
         xy = canon(lds[lpad(2 * i + 1)], m);
@@ -595,7 +605,15 @@ __global__ __launch_bounds__(256) void k_inner_row(const InnerJob* __restrict__ 
   for (int q = 0; q < NP; ++q) {
     if (top) {
       const size_t o = (size_t)t * N + tile + 2 * (threadIdx.x + 256 * q);
-      const double2 u0 = ld2(J.top0, o), u1 = ld2(J.top1, o);
+      double2 u0 = ld2(J.top0, o), u1 = ld2(J.top1, o);
+      if (J.d_square) {
+        // top0, top1 = a0, a1 of the square: d0 = a0^2, d1 = 2 a0 a1
+        const double2 a0 = u0;
+        u0.x = canon(mul_mod(a0.x, a0.x, m), m);
+        u0.y = canon(mul_mod(a0.y, a0.y, m), m);
+        u1.x = canon(mul_mod(2.0 * a0.x, u1.x, m), m);
+        u1.y = canon(mul_mod(2.0 * a0.y, u1.y, m), m);
+      }
       a0x[q] = red(a0x[q], m) + mul_mod(u0.x, pm, m);
       a0y[q] = red(a0y[q], m) + mul_mod(u0.y, pm, m);
       a1x[q] = red(a1x[q], m) + mul_mod(u1.x, pm, m);

@@ -216,6 +216,7 @@ class Builder {
     double* out1;
     const double* top0;   // merged relinearise + rescale: d0, d1 (else null)
     const double* top1;
+    bool square;          // d, top0, top1 are a1, a0, a1 of a square (fused path)
   };
   struct KsTmp {
     double* dcoef;
@@ -223,13 +224,17 @@ class Builder {
     double* acc;
     int n_ext;
   };
-  // degree-2 ciphertext d0 + d1 s + d2 s^2 in scratch, NTT domain
+  // degree-2 ciphertext d0 + d1 s + d2 s^2 in scratch, NTT domain; or, when
+  // sq0 is set (two-pass sizes), the square of (sq0, sq1) formed on the fly
+  // by the kernels that read it
   struct Deg2 {
     double* d0;
     double* d1;
     double* d2;
     int level;
     double scale;
+    const double* sq0 = nullptr;
+    const double* sq1 = nullptr;
   };
   struct TensorItem {
     CT a, b, c, e, f;

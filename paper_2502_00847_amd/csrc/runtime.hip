@@ -600,6 +600,7 @@ void Builder::ks_front(const std::vector<KsItem>& items, std::vector<KsTmp>& tmp
     t.ext = scratch((size_t)nd * n_ext * N);
     t.acc = scratch((size_t)2 * n_ext * N);
     NttJob ji{it.d, t.dcoef, nc, nc, 0, 0};
+    ji.sq = it.square ? 1 : 0;
     // fused path: the inverse transform leaves the ModUp digits y_t = [x_t (D_j/q_t)^-1]
     if (fused) ji.ek = C.ytab + (size_t)l * C.n_q;
     j_inv.push_back(ji);
@@ -612,6 +613,7 @@ void Builder::ks_front(const std::vector<KsItem>& items, std::vector<KsTmp>& tmp
     }
     InnerJob in{it.d, t.ext, it.key, t.acc, it.top0, it.top1, C.p_mod_q, nc, n_ext, nd, alpha};
     in.inv_from = fused ? (merged ? l : l + 1) : n_ext;
+    in.d_square = it.square ? 1 : 0;
     j_in.push_back(in);
   }
   ntt(j_inv, true);
@@ -671,7 +673,12 @@ std::vector<CT> Builder::relin_rescale(const std::vector<Deg2>& xs) {
   std::vector<KsItem> items;
   for (const Deg2& x : xs) {
     if (x.level < 1) { fail(-3, "relinearise-and-rescale at level 0"); return {}; }
-    items.push_back(KsItem{x.d2, x.level, rk, nullptr, nullptr, nullptr, nullptr, x.d0, x.d1});
+    if (x.sq0) {
+      if (!inner_row_fused(C.T)) { fail(-1, "fused squares need the two-pass NTT"); return {}; }
+      items.push_back(KsItem{x.sq1, x.level, rk, nullptr, nullptr, nullptr, nullptr, x.sq0, x.sq1, true});
+    } else {
+      items.push_back(KsItem{x.d2, x.level, rk, nullptr, nullptr, nullptr, nullptr, x.d0, x.d1, false});
+    }
   }
   std::vector<KsTmp> tmp;
   ks_front(items, tmp, true);
@@ -694,7 +701,14 @@ std::vector<CT> Builder::relin_rescale(const std::vector<Deg2>& xs) {
       // out_w = (P d_w + acc_w - NTT(conv_w)) (P q_l)^-1, fused into the transform
       NttJob f{cv, cv, l, l, 0, 0};
       f.epi = EPI_RRCOMB;
-      f.ea = w ? x.d1 : x.d0;
+      if (x.sq0) {
+        // d0 = a0^2, d1 = 2 a0 a1 of the square, formed in the epilogue
+        f.ea = x.sq0;
+        f.ebase = x.sq1;
+        f.sq = w ? 2 : 1;
+      } else {
+        f.ea = w ? x.d1 : x.d0;
+      }
       f.eb = aw;
       f.eout = w ? c1(o) : c0(o);
       f.ek = C.rr_inv + (size_t)l * n_q;
@@ -786,15 +800,35 @@ std::vector<CT> Builder::mul_relin(const std::vector<std::pair<CT, CT>>& ab, boo
   const int N = C.N;
   const size_t mark = scratch_mark();
   if (do_rescale) {
+    // squares at two-pass sizes skip the tensor product: the kernels that
+    // read d0, d1, d2 form them from the operand
+    const bool fuse_sq = inner_row_fused(C.T);
     std::vector<TensorItem> ti;
-    for (auto& p : ab) {
+    std::vector<int> where(ab.size(), -1);
+    for (size_t i = 0; i < ab.size(); ++i) {
+      const auto& p = ab[i];
+      if (fuse_sq && p.first.d == p.second.d && p.first.level == p.second.level) continue;
       TensorItem t{};
       t.a = p.first;
       t.b = p.second;
+      where[i] = (int)ti.size();
       ti.push_back(t);
     }
-    std::vector<Deg2> d = tensor2(ti);
+    std::vector<Deg2> dt = tensor2(ti);
     if (err_code) return {};
+    std::vector<Deg2> d;
+    for (size_t i = 0; i < ab.size(); ++i) {
+      if (where[i] >= 0) {
+        d.push_back(dt[where[i]]);
+        continue;
+      }
+      Deg2 q{};
+      q.level = ab[i].first.level;
+      q.scale = ab[i].first.scale * ab[i].second.scale;
+      q.sq0 = c0(ab[i].first);
+      q.sq1 = c1(ab[i].first);
+      d.push_back(q);
+    }
     std::vector<CT> out = relin_rescale(d);
     if (err_code) return {};
     scratch_release(mark);
@@ -822,7 +856,7 @@ std::vector<CT> Builder::mul_relin(const std::vector<std::pair<CT, CT>>& ab, boo
     e.n_chain = l + 1;
     e.op = EW_TENSOR;
     j_t.push_back(e);
-    ks.push_back(KsItem{d2, l, rk, c0(o), c1(o), c0(o), c1(o), nullptr, nullptr});
+    ks.push_back(KsItem{d2, l, rk, c0(o), c1(o), c0(o), c1(o), nullptr, nullptr, false});
     out.push_back(o);
   }
   ew(j_t);
@@ -858,7 +892,7 @@ std::vector<CT> Builder::rotate(const std::vector<CT>& in, const std::vector<int
     double* d = scratch((size_t)nl * N);
     j_a.push_back(AutoJob{c0(x), c0(o), nl, nl, (uint32_t)g, 0});
     j_a.push_back(AutoJob{c1(x), d, nl, nl, (uint32_t)g, 0});
-    ks.push_back(KsItem{d, x.level, gk, c0(o), nullptr, c0(o), c1(o), nullptr, nullptr});
+    ks.push_back(KsItem{d, x.level, gk, c0(o), nullptr, c0(o), c1(o), nullptr, nullptr, false});
     out.push_back(o);
   }
   automorph(j_a);
