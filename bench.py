@@ -227,6 +227,53 @@ def sim_t0(logits):
     return sim.t0_argmax(logits)
 
 
+def variants(params):
+    """Higher-precision Sign ((d_g, d_f) = (4, 3), seven polynomials per Sign) on the
+    config-2 query, and a large-n Argmax (K = 4 prompts, C = 256 classes), alone."""
+    from paper_2502_00847_amd.secpe import Context
+    out = {}
+    p43 = dict(params, dg=4, df=3)
+    g = Context(p43)
+    g.keygen(W.KEYGEN_SEED, g.argmax_steps(8, 4))
+    d2 = W.query(2, 0)
+    ct = g.encrypt(d2["logits"], d2["encrypt_seed"])
+    ws = g.workspace([d2["K"]], [d2["C"]])
+    lat = []
+    for _ in range(4):
+        g.sync()
+        t0 = time.perf_counter()
+        z = g.eval_argmax(ct, d2["K"], d2["C"], d2["d_min"], d2["d_max"], d2["refresh_seed"], ws=ws)
+        g.sync()
+        lat.append((time.perf_counter() - t0) * 1e3)
+    zz, idx = g.decrypt(z, d2["C"])
+    i0 = sim_t0(d2["logits"])[0]
+    onehot = np.zeros(d2["C"])
+    onehot[i0] = 1.0
+    out["precise_sign"] = {"dg_df": [4, 3], "config": "K=8, C=4", "ms": round(float(np.median(lat[1:])), 3),
+                           "index_ok": bool(idx == i0), "max_abs_z_minus_onehot": float(np.abs(zz - onehot).max())}
+    del g, ws, ct, z
+    g = Context(params)
+    K, C = 4, 256
+    g.keygen(W.KEYGEN_SEED, g.argmax_steps(K, C))
+    y = W.logits(6, 0, K, C)
+    lo, hi = W.d_bounds(K)
+    ct = g.encrypt(y, 6001)
+    ws = g.workspace([K], [C])
+    lat = []
+    for _ in range(3):
+        g.sync()
+        t0 = time.perf_counter()
+        z = g.eval_argmax(ct, K, C, lo, hi, 6002, ws=ws)
+        g.sync()
+        lat.append((time.perf_counter() - t0) * 1e3)
+    zz, idx = g.decrypt(z, C)
+    i0, _, margin = sim_t0(y)
+    out["large_n"] = {"K": K, "C": C, "ms": round(float(np.median(lat[1:])), 3), "index_ok": bool(idx == i0),
+                      "normalised_margin_log2": round(float(np.log2(margin / (hi - lo))), 2),
+                      "signs": g.counters()["sign"], "key_switches": g.counters()["key_switch"]}
+    return out
+
+
 def keyswitch_rate(g, params):
     n = 64
     N = 1 << params["log_n"]
@@ -271,6 +318,7 @@ def main():
     ap.add_argument("--serve", type=int, default=160, help="requests in the serving run (0 = skip)")
     ap.add_argument("--keyswitch", type=int, default=1, help="time 64 random-step rotations at 24 limbs")
     ap.add_argument("--calib", type=int, default=0, help="copy 1 GiB first (counter calibration kernel)")
+    ap.add_argument("--variants", type=int, default=1, help="precise-Sign and large-n single-query runs")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -443,6 +491,8 @@ def main():
         g.sync()
         result["graph_replay_argmax_per_s"] = round(B / (time.perf_counter() - tg), 2)
     result["packed"] = packed_rate(g, qs)
+    if args.variants:
+        result.update(variants(params))
     if args.keyswitch:
         result["ntt"] = ntt_rate(g, params)
         result["keyswitch"] = keyswitch_rate(g, params)

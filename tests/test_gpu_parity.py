@@ -22,6 +22,8 @@ EXTRA_STEPS = [3, 5]
 def _params(name):
     if name == "p13":
         return dict(log_n=13, n_q=8, q_bits=36, n_p=2, p_bits=51, log_scale=36, dg=2, df=2, min_level=1)
+    if name == "tiny43":
+        return dict(W.PARAMS["tiny"], dg=4, df=3)
     if name == "p13_r6":
         return dict(_params("p13"), refresh_level=6)
     if name == "p14":
@@ -317,6 +319,32 @@ def test_packed_argmax_bit_exact(name, tiny, p13):
             i0, _, margin = sim.t0_argmax(y)
             if margin / (h - l) >= 2.0**-10:
                 assert idx == i0
+
+
+def test_argmax_precise_sign_bit_exact():
+    """Higher-precision Sign, (d_g, d_f) = (4, 3) (seven polynomials per Sign): the
+    whole Algorithm 1 matches the oracle bit for bit."""
+    g, o, _ = _pair("tiny43", 4, 8)
+    for i, (K, C) in enumerate([(3, 5), (2, 2)]):
+        y, zo, zg = _argmax_pair(g, o, K, C, q=400 + i)
+        _same(g, zg, zo)
+
+
+def test_argmax_large_n_bit_exact(tiny):
+    """Large n: C = 200 classes (C' = 256, eight QuickMax steps, nine Signs) in the 512
+    slots of N = 2^10: bit-exact with the oracle and the right index."""
+    from paper_2502_00847_amd.secpe import Context
+    p = _params("tiny")
+    g, o = Context(p), Oracle.from_params(p)
+    steps = g.argmax_steps(2, 256)
+    g.keygen(SEED, steps)
+    o.keygen(SEED, steps)
+    y, zo, zg = _argmax_pair(g, o, 2, 200, q=500)
+    _same(g, zg, zo)
+    z, idx = g.decrypt(zg, 200)
+    i0, _, margin = sim.t0_argmax(y)
+    if margin / (W.d_bounds(2)[1] - W.d_bounds(2)[0]) >= 2.0**-10:
+        assert idx == i0
 
 
 def test_argmax_toy_config(p13):

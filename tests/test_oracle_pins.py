@@ -649,6 +649,27 @@ def test_oracle_packed_argmax_tiny():
             assert sim.decoded_index(zb) == i0
 
 
+def test_oracle_argmax_precise_sign_small_margins():
+    """(d_g, d_f) = (4, 3): the encrypted Argmax (tiny parameters) decrypts to the
+    plaintext argmax at normalised margins down to 2^-12, where (2, 2) is not
+    guaranteed (its index threshold is 2^-10)."""
+    o = make_oracle("tiny", dg=4, df=3)
+    o.keygen(5, argmax_rotation_steps(4, 4, o.slots))
+    rng = np.random.default_rng(41)
+    K, C = 2, 4
+    lo, hi = W.d_bounds(K)
+    for trial in range(3):
+        y = rng.uniform(-3, 3, (K, C))
+        tot = y.sum(0)
+        top = int(np.argmax(tot))
+        # place the runner-up at normalised margin 2^-11.5 below the top
+        second = (top + 1) % C
+        y[0, second] += (tot[top] - 2.0**-11.5 * (hi - lo)) - tot[second]
+        assert sim.t0_argmax(y)[0] == top
+        z = o.decrypt_decode(o.eval_argmax(o.encrypt_logits(y, 3 + trial), K, C, lo, hi, 9 + trial), C)
+        assert sim.decoded_index(z) == top
+
+
 def test_packing_count_matches_paper():
     """2n slots per Argmax of length n -> N/(2n) inputs per ciphertext: 32768 slots, n=256 -> 64 (Sec. 3.2)."""
     o_slots = (1 << W.PARAMS["full"]["log_n"]) // 2
