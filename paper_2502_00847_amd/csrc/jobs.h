@@ -62,11 +62,8 @@ enum EwOp : int {
   EW_ADD = 0,        // o0 = a0 + b0, o1 = a1 + b1
   EW_SUB = 1,        // o0 = a0 - b0, o1 = a1 - b1
   EW_TENSOR = 2,     // o0 = a0 b0, o1 = a0 b1 + a1 b0, o2 = a1 b1
-  EW_CMUL = 3,       // o_i = a_i * k[l]
   EW_ADD_CONST = 4,  // o0 = a0 + k[l], o1 = a1
   EW_PMUL = 5,       // o_i = a_i * b0 (plaintext polynomial b0)
-  EW_MODDOWN = 6,    // o_i = (a_i ? a_i : 0) + (b_i - c_i) * k[l]   (c_i = Conv_P of b_i)
-  EW_RESCALE = 7,    // o_i = (a_i - b_i) * k[l]
   EW_DEC2 = 8,       // o0 = a0 + a1 * b0   (b0 = secret key limb)
   EW_ENC = 9,        // o0 = m + e - a s   with a0 = m, a1 = e, b0 = a, b1 = s
   EW_KEYB = 10,      // o0 = e - a s + k[l] s'   with a1 = e, b0 = a, b1 = s, c0 = s'
@@ -76,9 +73,6 @@ enum EwOp : int {
   //   o0 = a0 b0 + c0 e0 + f0,  o1 = a0 b1 + a1 b0 + c0 e1 + c1 e0 + f1,  o2 = a1 b1 + c1 e1
   // (c/e and f optional)
   EW_TENSOR2 = 13,
-  // merged relinearise + rescale, chain limbs: o_i = (k2[l] a_i + b_i - c_i) k[l]
-  //   (a = d_i, b = key-switch accumulator, c = its base conversion, k2 = P mod q, k = (P q_top)^-1)
-  EW_RRCOMB = 14,
   EW_LIN2 = 15,      // o_i = a_i k[l] + b_i k2[l]   (b optional)
   EW_PADD = 16,      // o0 = a0 + b0 (plaintext polynomial b0), o1 = a1
 };

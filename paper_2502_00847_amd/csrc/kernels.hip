@@ -809,12 +809,6 @@ __global__ __launch_bounds__(256) void k_ew(const EwJob* __restrict__ jobs, DevT
         st2(J.o2, o, canon(mul_mod(a1.x, b1.x, m), m), canon(mul_mod(a1.y, b1.y, m), m));
         break;
       }
-      case EW_CMUL: {
-        const double2 a0 = ld2(J.a0, o), a1 = ld2(J.a1, o);
-        st2(J.o0, o, canon(mul_mod(a0.x, kk, m), m), canon(mul_mod(a0.y, kk, m), m));
-        st2(J.o1, o, canon(mul_mod(a1.x, kk, m), m), canon(mul_mod(a1.y, kk, m), m));
-        break;
-      }
       case EW_ADD_CONST: {
         const double2 a0 = ld2(J.a0, o);
         st2(J.o0, o, add_mod(a0.x, kk, m), add_mod(a0.y, kk, m));
@@ -828,20 +822,6 @@ __global__ __launch_bounds__(256) void k_ew(const EwJob* __restrict__ jobs, DevT
         const double2 p = ld2(J.b0, o), a0 = ld2(J.a0, o), a1 = ld2(J.a1, o);
         st2(J.o0, o, canon(mul_mod(a0.x, p.x, m), m), canon(mul_mod(a0.y, p.y, m), m));
         st2(J.o1, o, canon(mul_mod(a1.x, p.x, m), m), canon(mul_mod(a1.y, p.y, m), m));
-        break;
-      }
-      case EW_MODDOWN: {
-        const double2 b0 = ld2(J.b0, o), c0 = ld2(J.c0, o), b1 = ld2(J.b1, o), c1 = ld2(J.c1, o);
-        const double2 a0 = J.a0 ? ld2(J.a0, o) : make_double2(0.0, 0.0);
-        const double2 a1 = J.a1 ? ld2(J.a1, o) : make_double2(0.0, 0.0);
-        st2(J.o0, o, canon(a0.x + mul_mod(b0.x - c0.x, kk, m), m), canon(a0.y + mul_mod(b0.y - c0.y, kk, m), m));
-        st2(J.o1, o, canon(a1.x + mul_mod(b1.x - c1.x, kk, m), m), canon(a1.y + mul_mod(b1.y - c1.y, kk, m), m));
-        break;
-      }
-      case EW_RESCALE: {
-        const double2 a0 = ld2(J.a0, o), b0 = ld2(J.b0, o), a1 = ld2(J.a1, o), b1 = ld2(J.b1, o);
-        st2(J.o0, o, canon(mul_mod(a0.x - b0.x, kk, m), m), canon(mul_mod(a0.y - b0.y, kk, m), m));
-        st2(J.o1, o, canon(mul_mod(a1.x - b1.x, kk, m), m), canon(mul_mod(a1.y - b1.y, kk, m), m));
         break;
       }
       case EW_DEC2: {
@@ -904,16 +884,6 @@ __global__ __launch_bounds__(256) void k_ew(const EwJob* __restrict__ jobs, DevT
         st2(J.o0, o, canon(r0x, m), canon(r0y, m));
         st2(J.o1, o, canon(r1x, m), canon(r1y, m));
         st2(J.o2, o, canon(r2x, m), canon(r2y, m));
-        break;
-      }
-      case EW_RRCOMB: {
-        const double k2 = KPTR(J.k2)[l];
-        const double2 a0 = ld2(J.a0, o), b0 = ld2(J.b0, o), c0 = ld2(J.c0, o);
-        const double2 a1 = ld2(J.a1, o), b1 = ld2(J.b1, o), c1 = ld2(J.c1, o);
-        st2(J.o0, o, canon(mul_mod(red(mul_mod(a0.x, k2, m) + (b0.x - c0.x), m), kk, m), m),
-            canon(mul_mod(red(mul_mod(a0.y, k2, m) + (b0.y - c0.y), m), kk, m), m));
-        st2(J.o1, o, canon(mul_mod(red(mul_mod(a1.x, k2, m) + (b1.x - c1.x), m), kk, m), m),
-            canon(mul_mod(red(mul_mod(a1.y, k2, m) + (b1.y - c1.y), m), kk, m), m));
         break;
       }
       case EW_PADD: {
