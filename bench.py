@@ -311,7 +311,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--queries", type=int, default=256)
-    ap.add_argument("--chunk", type=int, default=64, help="queries per batched launch sequence")
+    ap.add_argument("--chunk", type=int, default=256, help="queries per batched launch sequence")
     ap.add_argument("--graph", type=int, default=0, help="replay captured hipGraphs in the timed steps")
     ap.add_argument("--cpu", type=int, default=1, help="run the CPU-oracle baseline")
     ap.add_argument("--cpu-procs", type=int, default=0)
