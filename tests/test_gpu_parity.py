@@ -432,3 +432,13 @@ def test_errors_are_reported(tiny):
         g.eval_argmax(ct, 64, 64, -1, 1, 0)   # K' C' exceeds the slots
     with pytest.raises(SecpeError):
         g.eval_argmax(ct, 2, 2, 1.0, 1.0, 0)  # empty normalisation range
+    # slot-packed mode: too many blocks for the slots, bad shapes, bad bounds
+    with pytest.raises(SecpeError):
+        g.encrypt_packed([np.zeros((4, 8))] * 17, 1)          # 17 blocks of 32 > 512 slots
+    with pytest.raises(SecpeError):
+        g.packed_shape([(0, 2)])
+    packed = g.encrypt_packed([np.zeros((2, 2))] * 2, 1)
+    with pytest.raises(SecpeError):
+        g.eval_argmax_packed([packed], [[(2, 2)] * 200], [-1.0] * 200, [1.0] * 200, [0])
+    with pytest.raises(SecpeError):
+        g.eval_argmax_packed([packed], [[(2, 2), (2, 2)]], [-1.0, 1.0], [1.0, 1.0], [0])
