@@ -69,6 +69,7 @@ def _load():
         "orc_layout": (None, [vp, P(dbl), ci, ci, P(dbl)]),
         "orc_encrypt_logits": (vp, [vp, P(dbl), ci, ci, u64]),
         "orc_eval_argmax": (vp, [vp, vp, ci, ci, dbl, dbl, u64]),
+        "orc_eval_argmax_phoenix": (vp, [vp, vp, ci, ci, dbl, dbl, u64]),
         "orc_packed_shape": (ci, [vp, ci, P(ci), P(ci), P(ci)]),
         "orc_layout_packed": (None, [vp, ci, P(dbl), P(ci), P(ci), P(dbl)]),
         "orc_encrypt_packed": (vp, [vp, ci, P(dbl), P(ci), P(ci), u64]),
@@ -319,6 +320,11 @@ class Oracle:
     def eval_odd9(self, x, coef, gain, target):
         coef = np.ascontiguousarray(coef, dtype=np.float64)
         return self._wrap(self.lib.orc_eval_odd9(self.h, x.h, _p(coef, C.c_double), float(gain), float(target)))
+
+    def eval_argmax_phoenix(self, ct, K, Cc, d_min, d_max, refresh_seed):
+        """The comparison path (Phoenix): C Signs and C rotations."""
+        return self._wrap(self.lib.orc_eval_argmax_phoenix(self.h, ct.h, int(K), int(Cc), float(d_min), float(d_max),
+                                                           int(refresh_seed)))
 
     def packed_shape(self, shapes):
         """(blocks per ciphertext, K', C', block size) for a group of (K, C) shapes."""

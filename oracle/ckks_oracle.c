@@ -1285,15 +1285,18 @@ ORC_API void* orc_eval_odd9(void* h, const void* x, const double* coef, double g
   return eval_odd9((orc_ctx*)h, (const orc_ct*)x, coef, gain, target);
 }
 
+/* refresh randomness: the k-th refresh of a chain uses index base + stride * k */
 typedef struct {
   uint64_t seed;
   uint64_t next;
+  uint64_t stride;
+  uint64_t base;
 } refresher;
 
 static orc_ct* maybe_refresh(orc_ctx* c, orc_ct* x, int need, refresher* rf) {
   if (x->level - need >= c->min_level) return x;
   if (c->refresh_level - need < c->min_level) die("modulus chain too short for one unit");
-  orc_ct* y = op_refresh(c, x, rf->seed, rf->next++);
+  orc_ct* y = op_refresh(c, x, rf->seed, rf->base + rf->stride * rf->next++);
   ct_free(x);
   return y;
 }
@@ -1453,7 +1456,7 @@ static orc_ct* eval_argmax_core(orc_ctx* c, const orc_ct* ct_in, int lk, int lc,
   double delta = ldexp(1.0, c->log_scale);
   int cp = 1 << lc;
   int slots = c->n / 2;
-  refresher rf = {refresh_seed, 0};
+  refresher rf = {refresh_seed, 0, 1, 0};
   orc_ct* y = ct_copy(c, ct_in, ct_in->level);
   for (int i = 0; i < lk; ++i) {
     orc_ct* r = op_rotate(c, y, (int64_t)cp << i);
@@ -1516,6 +1519,71 @@ static orc_ct* eval_argmax_core(orc_ctx* c, const orc_ct* ct_in, int lk, int lc,
 ORC_API void* orc_eval_argmax(void* h, const void* ct_in, int K, int C, double d_min, double d_max, uint64_t refresh_seed) {
   return eval_argmax_core((orc_ctx*)h, (const orc_ct*)ct_in, ilog2_ceil(K), ilog2_ceil(C), 0, 1, 0, &C, &d_min,
                           &d_max, refresh_seed);
+}
+
+/* The comparison path the paper measures against (Phoenix, Sec. 3.2): after
+   the same prompt sum and Eq. 5, every class is compared with each of the
+   other C-1 classes,
+     s = sum_{i=1}^{C-1} Sign(y - RotL(y, i))     (y duplicated at offset C),
+   so the largest class reaches s = C-1 and every other s <= C-3; then
+     z = (Sign((s - (C-2)) / (2C-3)) + 1) / 2
+   turns s into the one-hot vector (the paper leaves this last linear map to
+   the Phoenix paper; this is the reading).  C Signs and C rotations.  The
+   k-th refresh of comparison i (i = 0 for the prefix and the final Sign)
+   uses refresh index k * 512 + i. */
+#define PHOENIX_STRIDE 512
+ORC_API void* orc_eval_argmax_phoenix(void* h, const void* ct_in, int K, int C, double d_min, double d_max,
+                                      uint64_t refresh_seed) {
+  orc_ctx* c = (orc_ctx*)h;
+  if (C < 2 || C >= PHOENIX_STRIDE) die("phoenix path: need 2 <= C < 512");
+  double delta = ldexp(1.0, c->log_scale);
+  int lk = ilog2_ceil(K), cp = 1 << ilog2_ceil(C);
+  int slots = c->n / 2;
+  if ((int64_t)(1 << lk) * cp > slots || 2 * C > slots) die("phoenix path: shape exceeds the slot count");
+  refresher rf0 = {refresh_seed, 0, PHOENIX_STRIDE, 0};
+  orc_ct* y = ct_copy(c, (const orc_ct*)ct_in, ((const orc_ct*)ct_in)->level);
+  for (int i = 0; i < lk; ++i) {
+    orc_ct* r = op_rotate(c, y, (int64_t)cp << i);
+    orc_ct* t = op_add(c, y, r, 0);
+    ct_free(r); ct_free(y);
+    y = t;
+  }
+  y = maybe_refresh(c, y, 1, &rf0);
+  op_add_const_inplace(c, y, -d_min);
+  double* mask = (double*)xcalloc(cp, sizeof(double));
+  double inv_range = 1.0 / (d_max - d_min);
+  for (int j = 0; j < C; ++j) mask[j] = inv_range;
+  orc_ct* yn = op_mul_plain(c, y, mask, cp, delta);
+  free(mask);
+  ct_free(y);
+  orc_ct* r = op_rotate(c, yn, (int64_t)slots - C);
+  orc_ct* yd = op_add(c, yn, r, 0);
+  ct_free(r); ct_free(yn);
+  orc_ct* s = NULL;
+  for (int i = 1; i < C; ++i) {
+    refresher rfi = {refresh_seed, 0, PHOENIX_STRIDE, (uint64_t)i};
+    orc_ct* ri = op_rotate(c, yd, i);
+    orc_ct* di = op_add(c, yd, ri, 1);
+    orc_ct* si = eval_sign(c, di, 1.0, delta, 0, &rfi, NULL);
+    ct_free(ri); ct_free(di);
+    if (!s) {
+      s = si;
+    } else {
+      orc_ct* t = op_add(c, s, si, 0);
+      ct_free(s); ct_free(si);
+      s = t;
+    }
+  }
+  ct_free(yd);
+  /* x = (s - (C - 2)) / (2C - 3), one level for the constant product */
+  s = maybe_refresh(c, s, 1, &rf0);
+  op_add_const_inplace(c, s, -(double)(C - 2));
+  orc_ct* x = op_mul_const(c, s, 1.0 / (double)(2 * C - 3), delta);
+  ct_free(s);
+  orc_ct* z = eval_sign(c, x, 0.5, delta, 0, &rf0, NULL);
+  ct_free(x);
+  op_add_const_inplace(c, z, 0.5);
+  return z;
 }
 
 /* Algorithm 1 on every block of a packed ciphertext at once (same steps, with

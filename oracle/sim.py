@@ -130,5 +130,32 @@ def t1_argmax_packed(blocks, slots, dg=2, df=2, exact_sign=False):
     return [z[b * B:b * B + s[1]] for b, s in enumerate(shapes)]
 
 
+def t1_argmax_phoenix(logits, d_min, d_max, slots, dg=2, df=2, exact_sign=False):
+    """The comparison path (Phoenix, Sec. 3.2) on the real slot vector: prompt sum
+    and Eq. 5 as in Algorithm 1, then s = sum_{i<C} Sign(y - RotL(y, i)) with y
+    duplicated at offset C, and z = (Sign((s - (C-2)) / (2C-3)) + 1) / 2."""
+    logits = np.asarray(logits, dtype=np.float64)
+    K, C = logits.shape
+    Kp, Cp = _pow2ceil(K), _pow2ceil(C)
+    sgn = np.sign if exact_sign else (lambda v: sign_composite(v, dg, df))
+    y = np.zeros(slots)
+    for k in range(K):
+        y[k * Cp:k * Cp + C] = logits[k]
+    i = 1
+    while i < Kp:
+        y = y + np.roll(y, -Cp * i)
+        i <<= 1
+    mask = np.zeros(slots)
+    mask[:C] = 1.0
+    y = mask * (y - d_min) / (d_max - d_min)
+    y = y + np.roll(y, C)
+    s = np.zeros(slots)
+    for i in range(1, C):
+        s = s + sgn(y - np.roll(y, -i))
+    x = (s - (C - 2)) / (2 * C - 3)
+    z = 0.5 * sgn(x) + 0.5
+    return z[:C]
+
+
 def decoded_index(z):
     return int(np.argmax(np.asarray(z)))

@@ -670,6 +670,42 @@ def test_oracle_argmax_precise_sign_small_margins():
         assert sim.decoded_index(z) == top
 
 
+def test_t1_phoenix_exact_sign_is_one_hot():
+    """The comparison path with the exact sign: the largest class wins all C-1
+    comparisons, so z is e_idx (distinct dyadic inputs keep FP64 exact)."""
+    rng = np.random.default_rng(51)
+    for trial in range(30):
+        K, C = int(rng.integers(1, 5)), int(rng.integers(2, 10))
+        y = rng.permutation(np.arange(C) - C // 2)[None, :].repeat(K, 0).astype(np.float64) / 4
+        z = sim.t1_argmax_phoenix(y, -64.0, 64.0, 256, exact_sign=True)
+        want = np.zeros(C)
+        want[int(np.argmax(y.sum(0)))] = 1.0
+        assert np.array_equal(z, want)
+
+
+def test_oracle_phoenix_argmax_tiny():
+    """Encrypted comparison path (tiny parameters): decrypts to its FP64 simulation and
+    the plaintext argmax, with the paper's counts: C Signs, C rotations after the
+    prompt sum (Sec. 4.5)."""
+    o = make_oracle("tiny")
+    K, C = 2, 5
+    lk = (K - 1).bit_length()
+    steps = sorted(set(argmax_rotation_steps(K, C, o.slots) + list(range(1, C)) + [o.slots - C]))
+    o.keygen(5, steps)
+    y = W.logits(9, 700, K, C)
+    lo, hi = W.d_bounds(K)
+    ct = o.encrypt_logits(y, 31)
+    o.reset_counters()
+    z = o.decrypt_decode(o.eval_argmax_phoenix(ct, K, C, lo, hi, 32), C)
+    cnt = o.counters()
+    assert cnt["sign"] == C and cnt["rotate"] == lk + C
+    t = sim.t1_argmax_phoenix(y, lo, hi, o.slots)
+    assert np.abs(z - t).max() < 1e-3
+    i0, _, margin = sim.t0_argmax(y)
+    if margin / (hi - lo) >= 2.0**-8:
+        assert sim.decoded_index(z) == i0
+
+
 def test_packing_count_matches_paper():
     """2n slots per Argmax of length n -> N/(2n) inputs per ciphertext: 32768 slots, n=256 -> 64 (Sec. 3.2)."""
     o_slots = (1 << W.PARAMS["full"]["log_n"]) // 2
