@@ -274,6 +274,45 @@ def variants(params):
     return out
 
 
+def phoenix_compare(params, ns=(4, 16, 64, 256), K=4):
+    """Algorithm 1 against the comparison path the paper measures against (Phoenix:
+    C Signs and C rotations), one query of K prompts and n classes each, alone."""
+    from paper_2502_00847_amd.secpe import Context
+    g = Context(params)
+    steps = sorted(set(g.phoenix_steps(K, max(ns)) + g.argmax_steps(K, max(ns))))
+    g.keygen(W.KEYGEN_SEED, steps)
+    lo, hi = W.d_bounds(K)
+    out = []
+    for n in ns:
+        y = W.logits(7, n, K, n)
+        ct = g.encrypt(y, 7100 + n)
+        i0 = sim_t0(y)[0]
+        row = {"n": n}
+        for name in ("secpe", "phoenix"):
+            if name == "secpe":
+                ws = g.workspace([K], [n])
+                run = lambda: g.eval_argmax(ct, K, n, lo, hi, 7200 + n, ws=ws)
+            else:
+                ws = g._empty(g.lib.secpe_phoenix_workspace_bytes(g.h, K, n))
+                run = lambda: g.eval_argmax_phoenix(ct, K, n, lo, hi, 7200 + n, ws=ws)
+            run()
+            g.sync()
+            t0 = time.perf_counter()
+            z = run()
+            g.sync()
+            ms = (time.perf_counter() - t0) * 1e3
+            cnt = g.counters()
+            idx = g.decrypt(z, n)[1]
+            row[name] = {"ms": round(ms, 2), "signs": cnt["sign"], "rotations": cnt["rotate"],
+                         "key_switches": cnt["key_switch"], "index_ok": bool(idx == i0)}
+            del ws, run, z
+        row["speedup"] = round(row["phoenix"]["ms"] / row["secpe"]["ms"], 2)
+        out.append(row)
+        _log(f"phoenix vs secpe n={n}: {row}")
+    return {"K": K, "rows": out,
+            "what": "one query alone, wall time; the comparison path runs its C-1 comparisons batched"}
+
+
 def keyswitch_rate(g, params):
     n = 64
     N = 1 << params["log_n"]
@@ -493,6 +532,7 @@ def main():
     result["packed"] = packed_rate(g, qs)
     if args.variants:
         result.update(variants(params))
+        result["phoenix_vs_secpe"] = phoenix_compare(params)
     if args.keyswitch:
         result["ntt"] = ntt_rate(g, params)
         result["keyswitch"] = keyswitch_rate(g, params)

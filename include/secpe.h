@@ -167,6 +167,17 @@ int secpe_eval_argmax_packed(secpe_ctx* ctx, int n, const secpe_ct* in, const in
                              const double* d_min, const double* d_max, const uint64_t* refresh_seed, void* ws_dev,
                              size_t ws_bytes, secpe_ct* out);
 
+/* ---- the comparison path the paper measures against (Phoenix, Sec. 3.2):
+   after the prompt sum and Eq. 5, every class is compared with each of the
+   other C-1 (s = sum_i Sign(y - RotL(y, i)), y duplicated at offset C), and
+   z = (Sign((s - (C-2)) / (2C-3)) + 1) / 2.  C Signs and C rotations against
+   Algorithm 1's log C' + 1.  The comparisons run in the same launches.
+   Needs the rotation keys of secpe_phoenix_steps; 2 <= C < 512. ---- */
+int secpe_phoenix_steps(const secpe_ctx* ctx, int k_max, int C, int64_t* out, int cap);
+size_t secpe_phoenix_workspace_bytes(secpe_ctx* ctx, int K, int C);
+int secpe_eval_argmax_phoenix(secpe_ctx* ctx, const secpe_ct* in, int K, int C, double d_min, double d_max,
+                              uint64_t refresh_seed, void* ws_dev, size_t ws_bytes, secpe_ct* out);
+
 /* Autotuner for the batched path.  Evaluates the batch given (same arguments
    as secpe_eval_argmax_batch, no graph) under each candidate schedule and
    keeps the fastest in the context for later calls:

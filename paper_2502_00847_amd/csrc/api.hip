@@ -170,6 +170,23 @@ extern "C" int secpe_argmax_steps(const secpe_ctx* x, int k_max, int c_max, int6
   return (int)st.size();
 }
 
+extern "C" int secpe_phoenix_steps(const secpe_ctx* x, int k_max, int c, int64_t* out, int cap) {
+  CHECK_CTX(x);
+  if (c < 2) return set_err(SECPE_EINVAL, "need C >= 2");
+  const int slots = x->c.N / 2;
+  std::vector<int64_t> st(256);
+  int n = secpe_argmax_steps(x, k_max, c, st.data(), (int)st.size());
+  if (n < 0) return n;
+  st.resize(n);
+  for (int i = 1; i < c; ++i) st.push_back(i);
+  st.push_back(slots - c);
+  std::sort(st.begin(), st.end());
+  st.erase(std::unique(st.begin(), st.end()), st.end());
+  st.erase(std::remove_if(st.begin(), st.end(), [&](int64_t v) { return v % slots == 0; }), st.end());
+  for (size_t i = 0; i < st.size() && (int)i < cap; ++i) out[i] = st[i];
+  return (int)st.size();
+}
+
 // ---------------------------------------------------------------------------
 // keys
 // ---------------------------------------------------------------------------
@@ -490,6 +507,53 @@ extern "C" int secpe_eval_argmax_packed(secpe_ctx* x, int n, const secpe_ct* in,
   rc = run_build(x, (char*)ws, ws_bytes, [&](Builder& b) { build_argmax(b, q); });
   if (rc) return rc;
   for (int i = 0; i < n; ++i) { out[i].level = q[i].out.level; out[i].scale = q[i].out.scale; }
+  return 0;
+}
+
+static void phoenix_query(secpe_ctx* x, const secpe_ct* in, int K, int C, double dmin, double dmax, uint64_t rs,
+                          secpe_ct* out, ArgmaxQuery& q) {
+  (void)x;
+  q.in.d = (double*)in->data;
+  q.in.level = in->level;
+  q.in.scale = in->scale;
+  q.K = K;
+  q.C = C;
+  q.d_min = dmin;
+  q.d_max = dmax;
+  q.refresh_seed = rs;
+  q.out.d = (double*)out->data;
+}
+
+extern "C" size_t secpe_phoenix_workspace_bytes(secpe_ctx* x, int K, int C) {
+  if (!x || K < 1 || C < 2) return 0;
+  Ctx& c = x->c;
+  secpe_ct in{(void*)(uintptr_t)0x200000000000ull, c.n_q - 1, ldexp(1.0, c.log_scale)};
+  secpe_ct out{(void*)(uintptr_t)0x300000000000ull, 0, 0.0};
+  ArgmaxQuery q;
+  phoenix_query(x, &in, K, C, -1.0, 1.0, 0, &out, q);
+  Builder dry(c, (char*)(uintptr_t)0x100000000000ull, (size_t)1 << 44, (char*)(uintptr_t)0x400000000000ull,
+              (size_t)1 << 40, true);
+  build_phoenix(dry, q);
+  if (dry.err_code) {
+    set_err(dry.err_code, dry.err);
+    return 0;
+  }
+  return dry.need_bytes() + 4096;
+}
+
+extern "C" int secpe_eval_argmax_phoenix(secpe_ctx* x, const secpe_ct* in, int K, int C, double dmin, double dmax,
+                                         uint64_t rs, void* ws, size_t ws_bytes, secpe_ct* out) {
+  CHECK_CTX(x);
+  if (!in || !in->data || !out || !out->data || !ws) return set_err(SECPE_EINVAL, "null argument");
+  if (in->level < 0 || in->level >= x->c.n_q) return set_err(SECPE_EINVAL, "input level out of range");
+  if (K < 1 || C < 2) return set_err(SECPE_EINVAL, "need K >= 1 and C >= 2");
+  if (!(dmax > dmin)) return set_err(SECPE_EINVAL, "need d_max > d_min");
+  ArgmaxQuery q;
+  phoenix_query(x, in, K, C, dmin, dmax, rs, out, q);
+  int rc = run_build(x, (char*)ws, ws_bytes, [&](Builder& b) { build_phoenix(b, q); });
+  if (rc) return rc;
+  out->level = q.out.level;
+  out->scale = q.out.scale;
   return 0;
 }
 

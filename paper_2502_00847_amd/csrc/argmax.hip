@@ -331,6 +331,150 @@ static void run_step(Builder& b, int kind, std::vector<QState*>& qs) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// The comparison path the paper measures against (Phoenix, Sec. 3.2): after
+// the prompt sum and Eq. 5, s = sum_{i<C} Sign(y - RotL(y, i)) with y
+// duplicated at offset C, then z = (Sign((s - (C-2)) / (2C-3)) + 1) / 2.  The
+// C-1 comparisons are independent and run in the same launches.  The k-th
+// refresh of comparison i (i = 0: the prefix and the final Sign) uses refresh
+// index k * 512 + i.
+// ---------------------------------------------------------------------------
+static const int kPhoenixStride = 512;
+
+// refresh every chain whose level cannot afford 'need'; chain i's k-th refresh
+// takes index k * 512 + chain[i]
+static void refresh_chains(Builder& b, std::vector<CT>& x, const std::vector<int>& chain, std::vector<int>& k,
+                           int need, uint64_t seed) {
+  std::vector<CT> in;
+  std::vector<uint64_t> sd, idx;
+  std::vector<size_t> who;
+  for (size_t i = 0; i < x.size(); ++i) {
+    if (x[i].level - need >= b.C.min_level) continue;
+    if (b.C.refresh_level - need < b.C.min_level) { b.fail(-3, "modulus chain too short for one unit"); return; }
+    in.push_back(x[i]);
+    sd.push_back(seed);
+    idx.push_back((uint64_t)k[i]++ * kPhoenixStride + (uint64_t)chain[i]);
+    who.push_back(i);
+  }
+  if (in.empty()) return;
+  std::vector<CT> out = b.refresh(in, sd, idx);
+  if (b.err_code) return;
+  for (size_t j = 0; j < who.size(); ++j) {
+    free_owned(b, x[who[j]]);
+    x[who[j]] = out[j];
+  }
+}
+
+// Sign = f^df(g^dg(x)) on every item, each with its refresh chain
+static std::vector<CT> sign_chains(Builder& b, std::vector<CT> x, const std::vector<int>& chain, std::vector<int>& k,
+                                   double last_gain, uint64_t seed) {
+  Ctx& C = b.C;
+  const int total = C.dg + C.df;
+  const double delta = ldexp(1.0, C.log_scale);
+  for (int j = 0; j < total; ++j) {
+    refresh_chains(b, x, chain, k, 4, seed);
+    if (b.err_code) return {};
+    const bool last = j == total - 1;
+    std::vector<const double*> coef(x.size(), j < C.dg ? kSignG : kSignF);
+    std::vector<double> gain(x.size(), last ? last_gain : 1.0), tg(x.size(), delta);
+    std::vector<CT> y = b.eval_odd9(x, coef, gain, tg);
+    if (b.err_code) return {};
+    for (size_t i = 0; i < x.size(); ++i) free_owned(b, x[i]);
+    x = y;
+  }
+  b.counters[0] += (int64_t)x.size();
+  return x;
+}
+
+void build_phoenix(Builder& b, ArgmaxQuery& q) {
+  Ctx& C = b.C;
+  const double delta = ldexp(1.0, C.log_scale);
+  const int slots = C.N / 2;
+  const int n = q.C;
+  const int lk = ilog2_ceil(q.K), cp = 1 << ilog2_ceil(n);
+  if (n < 2 || n >= kPhoenixStride || (int64_t)(1 << lk) * cp > slots || 2 * n > slots) {
+    b.fail(-1, "phoenix path: need 2 <= C < 512 and the shape inside the slots");
+    return;
+  }
+  const uint64_t seed = q.refresh_seed;
+  std::vector<int> chain0{0}, k0{0};
+  std::vector<CT> y{view(q.in)};
+  for (int i = 0; i < lk; ++i) {
+    std::vector<CT> r = b.rotate(y, {(int64_t)cp << i});
+    if (b.err_code) return;
+    std::vector<CT> s = b.add({{y[0], r[0]}}, false);
+    if (b.err_code) return;
+    b.free_ct(r[0]);
+    free_owned(b, y[0]);
+    y = s;
+  }
+  refresh_chains(b, y, chain0, k0, 1, seed);
+  if (b.err_code) return;
+  std::vector<CT> y1 = b.add_const(y, {-q.d_min});
+  if (b.err_code) return;
+  std::vector<double> mask(cp, 0.0);
+  for (int j = 0; j < n; ++j) mask[j] = 1.0 / (q.d_max - q.d_min);
+  std::vector<CT> yn = b.mul_plain(y1, {mask}, {delta});
+  if (b.err_code) return;
+  b.free_ct(y1[0]);
+  free_owned(b, y[0]);
+  std::vector<CT> r = b.rotate(yn, {(int64_t)slots - n});
+  if (b.err_code) return;
+  std::vector<CT> yd = b.add({{yn[0], r[0]}}, false);
+  if (b.err_code) return;
+  b.free_ct(r[0]);
+  b.free_ct(yn[0]);
+  // the C-1 comparisons, batched
+  std::vector<CT> src(n - 1, yd[0]);
+  std::vector<int64_t> st;
+  std::vector<int> chain, kc(n - 1, 0);
+  for (int i = 1; i < n; ++i) { st.push_back(i); chain.push_back(i); }
+  std::vector<CT> ri = b.rotate(src, st);
+  if (b.err_code) return;
+  std::vector<std::pair<CT, CT>> pr;
+  for (int i = 0; i < n - 1; ++i) pr.push_back({yd[0], ri[i]});
+  std::vector<CT> di = b.add(pr, true);
+  if (b.err_code) return;
+  for (CT& v : ri) b.free_ct(v);
+  b.free_ct(yd[0]);
+  std::vector<CT> si = sign_chains(b, di, chain, kc, 1.0, seed);
+  if (b.err_code) return;
+  CT s = si[0];
+  for (int i = 1; i < n - 1; ++i) {
+    std::vector<CT> t = b.add({{s, si[i]}}, false);
+    if (b.err_code) return;
+    free_owned(b, s);
+    b.free_ct(si[i]);
+    s = t[0];
+  }
+  std::vector<CT> sv{s};
+  refresh_chains(b, sv, chain0, k0, 1, seed);
+  if (b.err_code) return;
+  std::vector<CT> s1 = b.add_const(sv, {-(double)(n - 2)});
+  if (b.err_code) return;
+  std::vector<CT> x = b.mul_const(s1, {1.0 / (double)(2 * n - 3)}, {delta});
+  if (b.err_code) return;
+  b.free_ct(s1[0]);
+  free_owned(b, sv[0]);
+  std::vector<CT> z = sign_chains(b, x, chain0, k0, 0.5, seed);
+  if (b.err_code) return;
+  // z + 1/2 into the caller's buffer
+  const int64_t half = llround(0.5 * z[0].scale);
+  EwJob e{};
+  e.o0 = q.out.d;
+  e.o1 = q.out.d + (size_t)C.n_q * C.N;
+  e.a0 = b.c0(z[0]);
+  e.a1 = b.c1(z[0]);
+  e.k = b.put_residues(half, z[0].level + 1);
+  e.n_limbs = z[0].level + 1;
+  e.n_chain = z[0].level + 1;
+  e.op = EW_ADD_CONST;
+  b.ew({e});
+  q.out.level = z[0].level;
+  q.out.scale = z[0].scale;
+  free_owned(b, z[0]);
+}
+
 void packed_shape(const std::vector<int>& K, const std::vector<int>& C, int* kp, int* cp, int* bsz) {
   int lk = 0, lc = 0;
   for (size_t i = 0; i < K.size(); ++i) {

@@ -327,6 +327,8 @@ struct ArgmaxQuery {
 // of max(K'C', 2C') slots)
 void packed_shape(const std::vector<int>& K, const std::vector<int>& C, int* kp, int* cp, int* bsz);
 void build_argmax(Builder& b, std::vector<ArgmaxQuery>& q);
+// the comparison path (Phoenix) for one query
+void build_phoenix(Builder& b, ArgmaxQuery& q);
 
 // Per-query state machines that survive across command lists: a round
 // advances queries by one step (all step kinds present, or only the most

@@ -77,6 +77,9 @@ def load():
         "secpe_op_mul_const": (i32, [vp, ct, dbl, dbl, vp, sz, ct]),
         "secpe_op_lincomb": (i32, [vp, ct, dbl, ct, dbl, dbl, i32, vp, sz, ct]),
         "secpe_packed_shape": (i32, [vp, i32, P(i32), P(i32), P(i32)]),
+        "secpe_phoenix_steps": (i32, [vp, i32, i32, P(i64), i32]),
+        "secpe_phoenix_workspace_bytes": (sz, [vp, i32, i32]),
+        "secpe_eval_argmax_phoenix": (i32, [vp, ct, i32, i32, dbl, dbl, u64, vp, sz, ct]),
         "secpe_encrypt_packed": (i32, [vp, vp, i32, P(dbl), P(i32), P(i32), u64, ct]),
         "secpe_packed_workspace_bytes": (sz, [vp, i32, P(i32), P(i32), P(i32)]),
         "secpe_eval_argmax_packed": (i32, [vp, i32, ct, P(i32), P(i32), P(i32), P(dbl), P(dbl), P(u64), vp, sz, ct]),
@@ -122,7 +125,8 @@ def exported_symbols():
          "secpe_counters", "secpe_ct_export", "secpe_ct_import", "secpe_key_export", "secpe_sk_export",
          "secpe_sync", "secpe_op_workspace_bytes", "secpe_op_add", "secpe_op_sub", "secpe_op_add_const",
          "secpe_op_mul_const", "secpe_op_lincomb", "secpe_autotune", "secpe_packed_shape", "secpe_encrypt_packed",
-         "secpe_packed_workspace_bytes", "secpe_eval_argmax_packed", "secpe_op_mul_plain", "secpe_op_rescale", "secpe_op_mul_relin",
+         "secpe_packed_workspace_bytes", "secpe_eval_argmax_packed", "secpe_phoenix_steps",
+         "secpe_phoenix_workspace_bytes", "secpe_eval_argmax_phoenix", "secpe_op_mul_plain", "secpe_op_rescale", "secpe_op_mul_relin",
          "secpe_op_mul_relin_rescale", "secpe_op_rotate", "secpe_op_refresh", "secpe_op_eval_odd9",
          "secpe_op_key_switch", "secpe_op_ntt", "secpe_op_ring_mul", "secpe_op_encode", "secpe_profile_begin",
          "secpe_profile_end", "secpe_ntt_cts", "secpe_rotate_workspace_bytes", "secpe_rotate_batch",
@@ -249,6 +253,28 @@ class Context:
         self._check(self.lib.secpe_decrypt(self.h, C.c_void_p(sk.data_ptr()), C.byref(c), nslots,
                                            _p(z, C.c_double), C.byref(idx)))
         return z, int(idx.value)
+
+    # -- the comparison path (Phoenix) -------------------------------------------
+    def phoenix_steps(self, k_max, c):
+        out = np.zeros(1024, dtype=np.int64)
+        n = self.lib.secpe_phoenix_steps(self.h, int(k_max), int(c), _p(out, C.c_int64), len(out))
+        if n < 0:
+            self._check(n)
+        return [int(v) for v in out[:n]]
+
+    def eval_argmax_phoenix(self, ct, K, Cc, d_min, d_max, refresh_seed, ws=None, out=None):
+        if ws is None:
+            nb = self.lib.secpe_phoenix_workspace_bytes(self.h, int(K), int(Cc))
+            if nb == 0:
+                raise SecpeError(self.lib.secpe_last_error().decode())
+            ws = self._empty(nb)
+        out = self.new_ct() if out is None else out
+        c = out._c()
+        self._check(self.lib.secpe_eval_argmax_phoenix(self.h, C.byref(ct._c()), int(K), int(Cc), float(d_min),
+                                                       float(d_max), int(refresh_seed), C.c_void_p(ws.data_ptr()),
+                                                       ws.numel() * 8, C.byref(c)))
+        out.level, out.scale = c.level, c.scale
+        return out
 
     # -- slot-packed Argmax ------------------------------------------------------
     def packed_shape(self, shapes):

@@ -347,6 +347,30 @@ def test_argmax_large_n_bit_exact(tiny):
         assert idx == i0
 
 
+@pytest.mark.parametrize("name,K,C", [("tiny", 2, 5), ("p13", 3, 4)])
+def test_phoenix_bit_exact(name, K, C):
+    """The comparison path (Phoenix: C Signs, C rotations) matches the oracle bit for
+    bit at single-pass and two-pass NTT sizes, and decodes to the plaintext argmax."""
+    from paper_2502_00847_amd.secpe import Context
+    p = _params(name)
+    g, o = Context(p), Oracle.from_params(p)
+    steps = g.phoenix_steps(K, C)
+    g.keygen(SEED, steps)
+    o.keygen(SEED, steps)
+    y = W.logits(9, 800 + C, K, C)
+    lo, hi = W.d_bounds(K)
+    enc, ref = W.query_seeds(9, 800 + C)
+    zg = g.eval_argmax_phoenix(g.encrypt(y, enc), K, C, lo, hi, ref)
+    zo = o.eval_argmax_phoenix(o.encrypt_logits(y, enc), K, C, lo, hi, ref)
+    _same(g, zg, zo)
+    cnt = g.counters()
+    assert cnt["sign"] == C and cnt["rotate"] == (K - 1).bit_length() + C
+    z, idx = g.decrypt(zg, C)
+    i0, _, margin = sim.t0_argmax(y)
+    if margin / (hi - lo) >= 2.0**-8:
+        assert idx == i0
+
+
 def test_argmax_toy_config(p13):
     """Toy-shaped parameters with the two-pass NTT: K=4, C=2 (config 1 shape)."""
     g, o, _ = p13
