@@ -74,6 +74,17 @@ def _load():
         "orc_layout_packed": (None, [vp, ci, P(dbl), P(ci), P(ci), P(dbl)]),
         "orc_encrypt_packed": (vp, [vp, ci, P(dbl), P(ci), P(ci), u64]),
         "orc_eval_argmax_packed": (vp, [vp, vp, ci, P(ci), P(ci), P(dbl), P(dbl), u64]),
+        "orc_encode_complex": (None, [vp, P(dbl), P(dbl), ci, dbl, P(i64)]),
+        "orc_set_boot": (ci, [vp, ci, ci, ci, ci, ci, ci, ci]),
+        "orc_boot_steps": (ci, [vp, P(i64), ci]),
+        "orc_boot_cheb": (None, [vp, P(dbl)]),
+        "orc_boot_out_level": (ci, [vp]),
+        "orc_boot_group_apply": (None, [vp, ci, ci, P(dbl), P(dbl), P(dbl), P(dbl)]),
+        "orc_mod_raise": (vp, [vp, vp]),
+        "orc_mul_monomial_half": (vp, [vp, vp, ci]),
+        "orc_eval_mod": (vp, [vp, vp]),
+        "orc_bootstrap": (vp, [vp, vp]),
+        "orc_boot_transform": (vp, [vp, vp, ci]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -139,7 +150,70 @@ class Oracle:
     @classmethod
     def from_params(cls, params):
         keys = ("log_n", "n_q", "q_bits", "n_p", "p_bits", "log_scale", "dg", "df", "min_level", "refresh_level")
-        return cls(**{k: params[k] for k in keys if k in params})
+        o = cls(**{k: params[k] for k in keys if k in params})
+        if params.get("h", 0) or params.get("boot_K", 0):
+            o.set_boot(params.get("h", 0), params.get("boot_K", 0), params.get("boot_r", 0),
+                       params.get("boot_deg", 1), params.get("boot_ratio", 1), params.get("boot_groups", 1),
+                       params.get("boot_refresh", 0))
+        return o
+
+    # -- bootstrapping -------------------------------------------------------
+    def set_boot(self, h, K, r, deg, ratio, groups, mode):
+        """Sparse secret weight h and bootstrapping parameters (before keygen).
+        Returns the level of a bootstrapped ciphertext (-1: chain too short)."""
+        self.boot = dict(h=h, K=K, r=r, deg=deg, ratio=ratio, groups=groups, mode=mode)
+        out = self.lib.orc_set_boot(self.h, int(h), int(K), int(r), int(deg), int(ratio), int(groups), int(mode))
+        if mode and out >= 0:
+            self.refresh_level = out
+        return out
+
+    def boot_out_level(self):
+        return self.lib.orc_boot_out_level(self.h)
+
+    def boot_steps(self):
+        out = np.zeros(4096, dtype=np.int64)
+        k = self.lib.orc_boot_steps(self.h, _p(out, C.c_int64), len(out))
+        return [int(v) for v in out[:k]]
+
+    def boot_cheb(self):
+        out = np.zeros(self.boot["deg"] + 1)
+        self.lib.orc_boot_cheb(self.h, _p(out, C.c_double))
+        return out
+
+    def boot_group_apply(self, inverse, g, v):
+        v = np.asarray(v, dtype=np.complex128)
+        vr = np.ascontiguousarray(v.real)
+        vi = np.ascontiguousarray(v.imag)
+        ore = np.zeros(self.slots)
+        oim = np.zeros(self.slots)
+        self.lib.orc_boot_group_apply(self.h, int(inverse), int(g), _p(vr, C.c_double), _p(vi, C.c_double),
+                                      _p(ore, C.c_double), _p(oim, C.c_double))
+        return ore + 1j * oim
+
+    def mod_raise(self, ct):
+        return self._wrap(self.lib.orc_mod_raise(self.h, ct.h))
+
+    def mul_monomial_half(self, ct, neg):
+        return self._wrap(self.lib.orc_mul_monomial_half(self.h, ct.h, int(neg)))
+
+    def eval_mod(self, ct):
+        return self._wrap(self.lib.orc_eval_mod(self.h, ct.h))
+
+    def boot_transform(self, ct, inverse):
+        """CoeffToSlot (inverse = 1) or SlotToCoeff (inverse = 0): every group, one level each."""
+        return self._wrap(self.lib.orc_boot_transform(self.h, ct.h, int(inverse)))
+
+    def bootstrap(self, ct):
+        return self._wrap(self.lib.orc_bootstrap(self.h, ct.h))
+
+    def encode_complex(self, z, scale):
+        z = np.asarray(z, dtype=np.complex128)
+        zr = np.ascontiguousarray(z.real)
+        zi = np.ascontiguousarray(z.imag)
+        out = np.zeros(self.n, dtype=np.int64)
+        self.lib.orc_encode_complex(self.h, _p(zr, C.c_double), _p(zi, C.c_double), len(z), float(scale),
+                                    _p(out, C.c_int64))
+        return out
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

@@ -125,6 +125,13 @@ static int64_t sample_ternary(uint64_t key, uint64_t i) {
   uint64_t r = sm_draw(key, i);
   return (int64_t)(uint64_t)(((u128)r * 3) >> 64) - 1;
 }
+/* sparse ternary: nonzero iff the top log2 N bits of the draw are below h
+   (probability h/N), sign from the lowest bit */
+static int64_t sample_sparse(uint64_t key, uint64_t i, int log_n, int h) {
+  uint64_t r = sm_draw(key, i);
+  if ((r >> (64 - log_n)) >= (uint64_t)h) return 0;
+  return (r & 1) ? -1 : 1;
+}
 static int64_t sample_cbd21(uint64_t key, uint64_t i) {
   uint64_t r = sm_draw(key, i);
   const uint64_t m = (1ull << 21) - 1;
@@ -139,6 +146,14 @@ static uint64_t sample_uniform(uint64_t key, uint64_t i, uint64_t q) {
 /* ------------------------------------------------------------------------- */
 /* context                                                                    */
 /* ------------------------------------------------------------------------- */
+/* the encoded plaintexts of one linear-transform group at one plaintext scale */
+struct boot_pt {
+  int inverse, g;
+  double pscale;
+  int64_t** m;          /* [slot offset] encoded (pre-rotated) diagonal, or NULL */
+  struct boot_pt* next;
+};
+
 typedef struct {
   uint64_t g;           /* Galois element; 0 marks the relinearisation key */
   uint64_t*** b;        /* [digit][limb] NTT-domain vectors, limb over all primes */
@@ -152,6 +167,12 @@ typedef struct {
   int dg, df;
   int min_level;
   int refresh_level;    /* level a refreshed ciphertext is re-encrypted at */
+  int secret_h;         /* > 0: sparse secret, each coefficient nonzero w.p. h/N */
+  int boot_mode;        /* 1: refreshes are bootstraps */
+  int boot_K, boot_r, boot_deg, boot_ratio, boot_groups;
+  int boot_out_level;   /* level of a bootstrapped ciphertext (-1: not set up) */
+  double* boot_cheb;    /* Chebyshev coefficients c_0..c_deg of the scaled cosine */
+  struct boot_pt* boot_cache; /* encoded diagonals, by (direction, group, scale) */
   uint64_t* mod;        /* n_q chain primes, then n_p special primes */
   /* per prime NTT tables */
   uint64_t** psi_pow;   /* psi^i */
@@ -235,6 +256,7 @@ ORC_API void* orc_create(int log_n, int n_q, int q_bits, int n_p, int p_bits, in
   c->df = df;
   c->min_level = min_level;
   c->refresh_level = (refresh_level <= 0 || refresh_level > n_q - 1) ? n_q - 1 : refresh_level;
+  c->boot_out_level = -1;
   int np = n_q + n_p, n = c->n;
   c->mod = (uint64_t*)xcalloc(np, sizeof(uint64_t));
   make_primes(c, q_bits, p_bits);
@@ -282,7 +304,14 @@ ORC_API void orc_destroy(void* h) {
   int np = c->n_q + c->n_p;
   for (int t = 0; t < np; ++t) { free(c->psi_pow[t]); free(c->psi_ipow[t]); free(c->om_pow[t]); free(c->om_ipow[t]); }
   free(c->psi_pow); free(c->psi_ipow); free(c->om_pow); free(c->om_ipow); free(c->n_inv);
-  free(c->cos_tab); free(c->rot_group); free(c->s);
+  free(c->cos_tab); free(c->rot_group); free(c->s); free(c->boot_cheb);
+  for (struct boot_pt* e = c->boot_cache; e;) {
+    struct boot_pt* nx = e->next;
+    for (int d = 0; d < c->n / 2; ++d) free(e->m[d]);
+    free(e->m);
+    free(e);
+    e = nx;
+  }
   for (int i = 0; i < c->n_keys; ++i) free_key(c, &c->keys[i]);
   free(c->keys); free(c->mod); free(c);
 }
@@ -467,7 +496,8 @@ ORC_API void orc_gen_secret(void* h, uint64_t seed) {
   free(c->s);
   c->s = (int64_t*)xcalloc(c->n, sizeof(int64_t));
   uint64_t key = sm_key(seed, make_tag(PUR_SECRET, 0, 0, LIMB_NONE));
-  for (int i = 0; i < c->n; ++i) c->s[i] = sample_ternary(key, (uint64_t)i);
+  for (int i = 0; i < c->n; ++i)
+    c->s[i] = c->secret_h > 0 ? sample_sparse(key, (uint64_t)i, c->log_n, c->secret_h) : sample_ternary(key, (uint64_t)i);
 }
 ORC_API void orc_get_secret(void* h, int64_t* out) { orc_ctx* c = (orc_ctx*)h; memcpy(out, c->s, 8 * (size_t)c->n); }
 
@@ -552,7 +582,10 @@ static orc_key* add_key(orc_ctx* c, uint64_t g) {
   return k;
 }
 
+/* the step value that asks for the conjugation X -> X^(2N-1) */
+#define CONJ_STEP INT64_MIN
 static uint64_t galois_elt(orc_ctx* c, int64_t step) {
+  if (step == CONJ_STEP) return 2ull * (uint64_t)c->n - 1;
   int64_t slots = c->n / 2;
   int64_t r = ((step % slots) + slots) % slots;
   return c->rot_group[r];
@@ -1122,9 +1155,8 @@ static orc_ct* op_lincomb(orc_ctx* c, const orc_ct* a, double va, const orc_ct* 
   return x;
 }
 
-/* RotL(x, step): slot j <- slot j+step; automorphism X -> X^(5^step) then key switch */
-static orc_ct* op_rotate(orc_ctx* c, const orc_ct* a, int64_t step) {
-  uint64_t g = galois_elt(c, step);
+/* automorphism X -> X^g, then key switch back to s */
+static orc_ct* op_automorph_ks(orc_ctx* c, const orc_ct* a, uint64_t g) {
   if (g == 1) return ct_copy(c, a, a->level);
   orc_key* k = find_key(c, g);
   if (!k) die("missing Galois key");
@@ -1147,6 +1179,8 @@ static orc_ct* op_rotate(orc_ctx* c, const orc_ct* a, int64_t step) {
   c->counters[CNT_ROT]++;
   return x;
 }
+/* RotL(x, step): slot j <- slot j+step (g = 5^step); the conjugation for CONJ_STEP */
+static orc_ct* op_rotate(orc_ctx* c, const orc_ct* a, int64_t step) { return op_automorph_ks(c, a, galois_elt(c, step)); }
 
 /* key-owner refresh, the stand-in for bootstrapping: decrypt, lift the message
    exactly and re-encrypt at the top level with fresh randomness; scale kept */
@@ -1293,9 +1327,15 @@ typedef struct {
   uint64_t base;
 } refresher;
 
+static orc_ct* bootstrap(orc_ctx* c, const orc_ct* x);
 static orc_ct* maybe_refresh(orc_ctx* c, orc_ct* x, int need, refresher* rf) {
   if (x->level - need >= c->min_level) return x;
   if (c->refresh_level - need < c->min_level) die("modulus chain too short for one unit");
+  if (c->boot_mode) {
+    orc_ct* b = bootstrap(c, x);
+    ct_free(x);
+    return b;
+  }
   orc_ct* y = op_refresh(c, x, rf->seed, rf->base + rf->stride * rf->next++);
   ct_free(x);
   return y;
@@ -1597,3 +1637,540 @@ ORC_API void* orc_eval_argmax_packed(void* h, const void* ct_in, int n_b, const 
   return eval_argmax_core(c, (const orc_ct*)ct_in, ilog2_ceil(kp), ilog2_ceil(cp), 1, n_b, bsz, C, d_min, d_max,
                           refresh_seed);
 }
+
+/* ========================================================================= */
+/* bootstrapping                                                              */
+/* ========================================================================= */
+/* The paper refreshes by bootstrapping (Sec. 2.2; Sec. 4.1: K = 14 levels of
+   L = 35) and cites full-RNS CKKS bootstrapping without giving its steps.
+   This is the standard pipeline, step by step:
+     scale-down   the level-1 input times one constant lands on level 0 with
+                  scale T_b = q_0 2^-ratio, so |m| <= q_0 2^-ratio for |z| <= 1;
+     ModRaise     centred lift of the level-0 residues to every chain prime:
+                  the result decrypts to t = m + q_0 I with I small (sparse
+                  secret) and is declared at scale q_0, so its slots hold
+                  U (t_lo + i t_hi) / q_0 with U_jk = zeta^(5^j k), j, k < N/2;
+     CoeffToSlot  U^-1 = P F_1^-1 ... F_L^-1, P the bit reversal, F_m the
+                  radix-2 butterfly stages of the special FFT (Cheon, Han,
+                  Kim, Kim, Song, SAC 2018), merged into groups of one level,
+                  each evaluated with baby-step giant-step diagonals; the
+                  conjugation then splits real and imaginary parts;
+     EvalMod      x = t / q_0 mod 1 through cos(2 pi (x - 1/4) / 2^r) as a
+                  Chebyshev interpolant on [-(K+1), K+1] and r double angles
+                  cos 2a = 2 cos^2 a - 1 (Han, Ki, CT-RSA 2020), which leaves
+                  sin(2 pi x) ~ 2 pi m / q_0;
+     SlotToCoeff  F_L ... F_1 with 2^ratio / (2 pi) folded in, back to z at
+                  scale Delta.
+   Slot vectors of the linear transforms are computed in binary128 and
+   rounded to binary64 before encoding. */
+
+typedef struct { __float128 re, im; } cq;
+static inline cq cq_mul(cq a, cq b) { cq r = {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; return r; }
+
+/* zeta^t = exp(i pi t / N) from the binary128 cosine table */
+static cq zeta_pow(orc_ctx* c, uint64_t t) {
+  uint64_t m2n = 2ull * (uint64_t)c->n;
+  t %= m2n;
+  cq r = {c->cos_tab[t], c->cos_tab[(t + 3ull * (uint64_t)c->n / 2) % m2n]};
+  return r;
+}
+
+/* m_k = round(scale * 2/N * Re sum_j z_j zeta^(-5^j k)) for complex slot values */
+static void encode_complex(orc_ctx* c, const double* re, const double* im, int nslots, double scale, int64_t* m) {
+  int n = c->n;
+  uint64_t m2n = 2ull * (uint64_t)n;
+  __float128 f = (__float128)scale * 2 / (__float128)n;
+  for (int k = 0; k < n; ++k) {
+    __float128 acc = 0;
+    for (int j = 0; j < nslots; ++j) {
+      if (re[j] == 0.0 && im[j] == 0.0) continue;
+      uint64_t t = (c->rot_group[j] * (uint64_t)k) % m2n;
+      acc += (__float128)re[j] * c->cos_tab[t] + (__float128)im[j] * c->cos_tab[(t + 3ull * (uint64_t)n / 2) % m2n];
+    }
+    m[k] = round_half_away_q(f * acc);
+  }
+}
+ORC_API void orc_encode_complex(void* h, const double* re, const double* im, int nslots, double scale, int64_t* m) {
+  encode_complex((orc_ctx*)h, re, im, nslots, scale, m);
+}
+
+/* a matrix on the S slots as generalised diagonals: out[p] = sum_d D[d][p] in[(p+d) mod S] */
+typedef struct { int S; cq** d; } diagmat;
+static diagmat dm_new(int S) { diagmat m = {S, (cq**)xcalloc(S, sizeof(cq*))}; return m; }
+static void dm_free(diagmat* m) {
+  for (int i = 0; i < m->S; ++i) free(m->d[i]);
+  free(m->d);
+}
+static cq* dm_at(diagmat* m, int off) {
+  if (!m->d[off]) m->d[off] = (cq*)xcalloc(m->S, sizeof(cq));
+  return m->d[off];
+}
+/* one radix-2 stage on blocks of m slots, D_m[j] = zeta^((S/m) 5^j):
+   forward  out[r] = in[r] + D[r] in[r+h],  out[r+h] = in[r] - D[r] in[r+h]   (h = m/2)
+   inverse  out[r] = (in[r] + in[r+h]) / 2, out[r+h] = conj(D[r]) (in[r] - in[r+h]) / 2 */
+static diagmat dm_stage(orc_ctx* c, int m, int inverse) {
+  int S = c->n / 2, h = m / 2;
+  diagmat A = dm_new(S);
+  for (int p = 0; p < S; ++p) {
+    int r = p % m;
+    int j = r < h ? r : r - h;
+    cq D = zeta_pow(c, (uint64_t)(S / m) * c->rot_group[j]);
+    if (!inverse) {
+      if (r < h) {
+        dm_at(&A, 0)[p] = (cq){1, 0};
+        dm_at(&A, h % S)[p] = D;
+      } else {
+        dm_at(&A, 0)[p] = (cq){-D.re, -D.im};
+        dm_at(&A, (S - h) % S)[p] = (cq){1, 0};
+      }
+    } else {
+      if (r < h) {
+        dm_at(&A, 0)[p] = (cq){0.5Q, 0};
+        dm_at(&A, h % S)[p] = (cq){0.5Q, 0};
+      } else {
+        cq Dc = {D.re / 2, -D.im / 2};
+        dm_at(&A, (S - h) % S)[p] = Dc;
+        dm_at(&A, 0)[p] = (cq){-Dc.re, -Dc.im};
+      }
+    }
+  }
+  return A;
+}
+/* A B (B applied first): (AB)[d1+d2][p] += A[d1][p] B[d2][p+d1] */
+static diagmat dm_mul(const diagmat* A, const diagmat* B) {
+  int S = A->S;
+  diagmat R = dm_new(S);
+  for (int d1 = 0; d1 < S; ++d1) {
+    if (!A->d[d1]) continue;
+    for (int d2 = 0; d2 < S; ++d2) {
+      if (!B->d[d2]) continue;
+      cq* out = dm_at(&R, (d1 + d2) % S);
+      for (int p = 0; p < S; ++p) {
+        cq t = cq_mul(A->d[d1][p], B->d[d2][(p + d1) % S]);
+        out[p].re += t.re;
+        out[p].im += t.im;
+      }
+    }
+  }
+  return R;
+}
+
+/* the groups of stages: L = log2 S stages split into 'groups' runs, the
+   larger runs first; CoeffToSlot applies m = S, S/2, ..., 2, SlotToCoeff
+   m = 2, 4, ..., S.  Group g covers stages [first, first + len) of that order. */
+static int boot_group_len(int L, int groups, int g) { return L / groups + (g < L % groups ? 1 : 0); }
+static int boot_stage_m(int L, int inverse, int idx) { return inverse ? 1 << (L - idx) : 1 << (idx + 1); }
+
+/* baby-step size for a group of g stages: 2^ceil((g+1)/2), at most E */
+static int boot_n1(int g, int E) {
+  int n1 = 1 << ((g + 2) / 2);
+  return n1 > E ? E : n1;
+}
+static int64_t floor_div(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+typedef struct {
+  int inverse, level;           /* level of the input ciphertext */
+  int delta, n1, E;             /* offsets are multiples of delta; E = S / delta */
+  diagmat M;
+} boot_group;
+
+static boot_group boot_make_group(orc_ctx* c, int inverse, int g, int level) {
+  int S = c->n / 2, L = 0;
+  while ((1 << L) < S) ++L;
+  int first = 0;
+  for (int i = 0; i < g; ++i) first += boot_group_len(L, c->boot_groups, i);
+  int len = boot_group_len(L, c->boot_groups, g);
+  boot_group G;
+  G.inverse = inverse;
+  G.level = level;
+  int mmin = S;
+  diagmat M = dm_stage(c, boot_stage_m(L, inverse, first), inverse);
+  if (boot_stage_m(L, inverse, first) < mmin) mmin = boot_stage_m(L, inverse, first);
+  for (int i = 1; i < len; ++i) {
+    int m = boot_stage_m(L, inverse, first + i);
+    if (m < mmin) mmin = m;
+    diagmat St = dm_stage(c, m, inverse);
+    diagmat R = dm_mul(&St, &M);
+    dm_free(&St);
+    dm_free(&M);
+    M = R;
+  }
+  /* constants folded into the first group applied */
+  if (g == 0) {
+    __float128 k = inverse ? 1.0Q / (2.0Q * (__float128)(c->boot_K + 1))
+                           : ldexpq(1.0Q, c->boot_ratio) / (2.0Q * M_PIq);
+    for (int d = 0; d < S; ++d)
+      if (M.d[d])
+        for (int p = 0; p < S; ++p) { M.d[d][p].re *= k; M.d[d][p].im *= k; }
+  }
+  G.M = M;
+  G.delta = mmin / 2;
+  G.E = S / G.delta;
+  G.n1 = boot_n1(len, G.E);
+  return G;
+}
+
+/* centred multiple e of delta for slot offset d: e in [-E/2, E/2) */
+static int64_t boot_e(const boot_group* G, int d) {
+  int64_t e = d / G->delta;
+  if (e >= G->E / 2) e -= G->E;
+  return e;
+}
+
+/* one group = one level: out = sum_G Rot( sum_b pt_{G,b} * Rot(x, delta b), delta n1 G ),
+   pt_{G,b} = the diagonal of e = n1 G + b rotated right by delta n1 G, encoded at
+   p = T q_l / s; the sum is rescaled once and carries scale T */
+static orc_ct* boot_apply_group(orc_ctx* c, const boot_group* G, int g, const orc_ct* x, double target) {
+  int S = c->n / 2, n = c->n, l = x->level;
+  if (l != G->level) die("boot group: level mismatch");
+  double ql = (double)c->mod[l];
+  double pscale = target * ql;
+  pscale = pscale / x->scale;
+  int64_t gmin = floor_div(-(int64_t)G->E / 2, G->n1), gmax = floor_div((int64_t)G->E / 2 - 1, G->n1);
+  int n_g = (int)(gmax - gmin + 1);
+  /* which baby steps are used */
+  int* used = (int*)xcalloc(G->n1, sizeof(int));
+  for (int d = 0; d < S; ++d) {
+    if (!G->M.d[d]) continue;
+    int64_t e = boot_e(G, d);
+    used[e - G->n1 * floor_div(e, G->n1)] = 1;
+  }
+  orc_ct** xb = (orc_ct**)xcalloc(G->n1, sizeof(orc_ct*));
+  for (int b = 0; b < G->n1; ++b)
+    if (used[b]) xb[b] = b == 0 ? ct_copy(c, x, l) : op_rotate(c, x, (int64_t)G->delta * b);
+  orc_ct* out = NULL;
+  /* the encoded diagonals are kept per (direction, group, plaintext scale) */
+  struct boot_pt* cache = c->boot_cache;
+  while (cache && !(cache->inverse == G->inverse && cache->g == g && cache->pscale == pscale)) cache = cache->next;
+  if (!cache) {
+    cache = (struct boot_pt*)xcalloc(1, sizeof(struct boot_pt));
+    cache->inverse = G->inverse;
+    cache->g = g;
+    cache->pscale = pscale;
+    cache->m = (int64_t**)xcalloc(S, sizeof(int64_t*));
+    cache->next = c->boot_cache;
+    c->boot_cache = cache;
+  }
+  double* re = (double*)xcalloc(S, sizeof(double));
+  double* im = (double*)xcalloc(S, sizeof(double));
+  int64_t* m = (int64_t*)xcalloc(n, 8);
+  uint64_t* mp = (uint64_t*)xcalloc(n, 8);
+  uint64_t* tmp = (uint64_t*)xcalloc(n, 8);
+  for (int gi = 0; gi < n_g; ++gi) {
+    int64_t gg = gmin + gi;
+    orc_ct* inner = NULL;
+    for (int d = 0; d < S; ++d) {
+      if (!G->M.d[d]) continue;
+      int64_t e = boot_e(G, d);
+      if (floor_div(e, G->n1) != gg) continue;
+      int b = (int)(e - G->n1 * gg);
+      if (!cache->m[d]) {
+        int64_t shift = ((G->delta * G->n1 * gg) % S + S) % S;
+        for (int p = 0; p < S; ++p) {
+          cq v = G->M.d[d][(p - shift + S) % S];
+          re[p] = (double)v.re;
+          im[p] = (double)v.im;
+        }
+        cache->m[d] = (int64_t*)xcalloc(n, 8);
+        encode_complex(c, re, im, S, pscale, cache->m[d]);
+      }
+      memcpy(m, cache->m[d], 8 * (size_t)n);
+      if (!inner) inner = ct_new(c, l, x->scale * pscale);
+      for (int t = 0; t <= l; ++t) {
+        uint64_t q = c->mod[t];
+        poly_from_small(c, m, t, mp);
+        for (int pp = 0; pp < 2; ++pp) {
+          ring_mul(c, t, LIMB(xb[b], pp, t, n), mp, tmp);
+          uint64_t* w = LIMB(inner, pp, t, n);
+          for (int i = 0; i < n; ++i) w[i] = madd(w[i], tmp[i], q);
+        }
+      }
+    }
+    if (!inner) continue;
+    orc_ct* r = gg == 0 ? inner : op_rotate(c, inner, (int64_t)G->delta * G->n1 * gg);
+    if (r != inner) ct_free(inner);
+    if (!out) {
+      out = r;
+    } else {
+      orc_ct* t = op_add(c, out, r, 0);
+      ct_free(out);
+      ct_free(r);
+      out = t;
+    }
+  }
+  for (int b = 0; b < G->n1; ++b) ct_free(xb[b]);
+  free(xb); free(used); free(re); free(im); free(m); free(mp); free(tmp);
+  rescale_inplace(c, out);
+  out->scale = target;
+  return out;
+}
+
+/* rotation steps one bootstrap uses (CONJ_STEP for the conjugation) */
+static int boot_steps(orc_ctx* c, int64_t* out, int cap) {
+  int S = c->n / 2, L = 0, k = 0;
+  while ((1 << L) < S) ++L;
+  int64_t* st = (int64_t*)xcalloc(4096, sizeof(int64_t));
+  for (int inv = 0; inv < 2; ++inv)
+    for (int g = 0; g < c->boot_groups; ++g) {
+      int first = 0;
+      for (int i = 0; i < g; ++i) first += boot_group_len(L, c->boot_groups, i);
+      int len = boot_group_len(L, c->boot_groups, g);
+      int mmin = S;
+      for (int i = 0; i < len; ++i) {
+        int mm = boot_stage_m(L, inv, first + i);
+        if (mm < mmin) mmin = mm;
+      }
+      int delta = mmin / 2, E = S / delta, n1 = boot_n1(len, E);
+      for (int b = 1; b < n1; ++b) st[k++] = (int64_t)delta * b % S;
+      /* the group's offsets are delta e, |e| <= 2^len - 1, centred in [-E/2, E/2) */
+      int64_t span = ((int64_t)1 << len) - 1;
+      int64_t elo = span < E / 2 ? -span : -(int64_t)E / 2, ehi = span < E / 2 - 1 ? span : (int64_t)E / 2 - 1;
+      int64_t gmin = floor_div(elo, n1), gmax = floor_div(ehi, n1);
+      for (int64_t gg = gmin; gg <= gmax; ++gg)
+        if (gg) st[k++] = (((int64_t)delta * n1 * gg) % S + S) % S;
+    }
+  /* sort, unique, drop multiples of S */
+  for (int i = 1; i < k; ++i)
+    for (int j = i; j > 0 && st[j - 1] > st[j]; --j) { int64_t t = st[j]; st[j] = st[j - 1]; st[j - 1] = t; }
+  int u = 0;
+  for (int i = 0; i < k; ++i)
+    if (st[i] % S != 0 && (u == 0 || st[u - 1] != st[i])) st[u++] = st[i];
+  st[u++] = CONJ_STEP;
+  for (int i = 0; i < u && i < cap; ++i) out[i] = st[i];
+  free(st);
+  return u;
+}
+ORC_API int orc_boot_steps(void* h, int64_t* out, int cap) { return boot_steps((orc_ctx*)h, out, cap); }
+
+/* Chebyshev interpolant of f(u) = cos(2 pi ((K+1) u - 1/4) / 2^r) on [-1, 1] at
+   the deg+1 Chebyshev nodes, in binary128:
+   c_j = (2 - [j = 0]) / n sum_k f(cos th_k) cos(j th_k), th_k = pi (k + 1/2) / n */
+static void boot_cheb_coeffs(int K, int r, int deg, double* out) {
+  int n = deg + 1;
+  for (int j = 0; j <= deg; ++j) {
+    __float128 acc = 0;
+    for (int k = 0; k < n; ++k) {
+      __float128 th = M_PIq * ((__float128)k + 0.5Q) / (__float128)n;
+      __float128 u = cosq(th);
+      __float128 f = cosq(2.0Q * M_PIq * ((__float128)(K + 1) * u - 0.25Q) / ldexpq(1.0Q, r));
+      acc += f * cosq((__float128)j * th);
+    }
+    acc = acc * 2.0Q / (__float128)n;
+    if (j == 0) acc /= 2;
+    out[j] = (double)acc;
+  }
+}
+ORC_API void orc_boot_cheb(void* h, double* out) {
+  orc_ctx* c = (orc_ctx*)h;
+  memcpy(out, c->boot_cheb, sizeof(double) * (size_t)(c->boot_deg + 1));
+}
+
+/* multiply by +-X^(N/2): every slot times +-i (5^j = 1 mod 4) */
+static orc_ct* op_mul_monomial_half(orc_ctx* c, const orc_ct* a, int neg) {
+  int n = c->n, h = n / 2;
+  orc_ct* x = ct_new(c, a->level, a->scale);
+  for (int p = 0; p < 2; ++p)
+    for (int t = 0; t <= a->level; ++t) {
+      uint64_t q = c->mod[t];
+      const uint64_t* u = LIMB(a, p, t, n);
+      uint64_t* w = LIMB(x, p, t, n);
+      for (int i = 0; i < n; ++i) {
+        int j = i + h;
+        uint64_t v = j < n ? u[i] : mneg(u[i], q);
+        if (neg) v = mneg(v, q);
+        w[j < n ? j : j - n] = v;
+      }
+    }
+  return x;
+}
+
+/* level-0 residues, centred, lifted to every chain prime; declared at scale q_0 */
+static orc_ct* mod_raise(orc_ctx* c, const orc_ct* a) {
+  if (a->level != 0) die("mod_raise: input must be at level 0");
+  int n = c->n, top = c->n_q - 1;
+  uint64_t q0 = c->mod[0];
+  orc_ct* x = ct_new(c, top, (double)q0);
+  for (int p = 0; p < 2; ++p)
+    for (int i = 0; i < n; ++i) {
+      uint64_t v = a->c[p][i];
+      i128 w = v > q0 / 2 ? (i128)v - (i128)q0 : (i128)v;
+      for (int t = 0; t <= top; ++t) LIMB(x, p, t, n)[i] = from_i128(w, c->mod[t]);
+    }
+  return x;
+}
+
+/* x * 2 (an exact integer product: the constant is 2 at the same scale) */
+static orc_ct* op_double(orc_ctx* c, const orc_ct* a) { return op_lincomb(c, a, 2.0, NULL, 0.0, a->scale, 0); }
+
+/* EvalMod on u = x / (K+1): Chebyshev basis T_1 = u,
+     T_2a    = 2 T_a^2 - 1          (square, doubled, constant subtracted)
+     T_(a+b) = 2 T_a T_b - T_(a-b)  (b < a, a the largest power of two below a+b;
+                                     (2 T_a) (x) T_b with -T_(a-b) added before
+                                     the one relinearise-and-rescale)
+   then p = sum_j c_j T_j at level l - k - 1 (every term a combination at scale
+   Delta q, one rescale), then r double angles y <- 2 y^2 - 1. */
+static orc_ct* eval_mod(orc_ctx* c, const orc_ct* u) {
+  double delta = ldexp(1.0, c->log_scale);
+  int deg = c->boot_deg;
+  orc_ct** T = (orc_ct**)xcalloc(deg + 1, sizeof(orc_ct*));
+  orc_ct** T2 = (orc_ct**)xcalloc(deg + 1, sizeof(orc_ct*));
+  T[1] = ct_copy(c, u, u->level);
+  for (int j = 2; j <= deg; ++j) {
+    int a = 1;
+    while (2 * a < j) a *= 2;
+    int b = j - a;
+    if (b == a) {
+      orc_ct* P = op_mul_relin_rescale(c, T[a], T[a]);
+      T[j] = op_double(c, P);
+      ct_free(P);
+      op_add_const_inplace(c, T[j], -1.0);
+    } else {
+      if (!T2[a]) T2[a] = op_double(c, T[a]);
+      orc_ct3* t3 = op_tensor(c, T2[a], T[b]);
+      orc_ct* lo = ct_copy(c, T[a - b], t3->level);
+      orc_ct* A = op_lincomb(c, lo, -1.0, NULL, 0.0, t3->scale, 0);
+      op_add3_ct_inplace(c, t3, A);
+      T[j] = op_relin_rescale(c, t3);
+      ct3_free(t3); ct_free(lo); ct_free(A);
+    }
+  }
+  int ld = T[deg]->level;
+  double sig = delta * (double)c->mod[ld];
+  orc_ct* acc = NULL;
+  for (int j = 1; j <= deg; j += 2) {
+    orc_ct* a1 = ct_copy(c, T[j], ld);
+    orc_ct* b1 = j + 1 <= deg ? ct_copy(c, T[j + 1], ld) : NULL;
+    orc_ct* t = op_lincomb(c, a1, c->boot_cheb[j], b1, b1 ? c->boot_cheb[j + 1] : 0.0, sig, 0);
+    ct_free(a1); ct_free(b1);
+    if (!acc) {
+      acc = t;
+    } else {
+      orc_ct* s = op_add(c, acc, t, 0);
+      ct_free(acc); ct_free(t);
+      acc = s;
+    }
+  }
+  rescale_inplace(c, acc);
+  acc->scale = delta;
+  op_add_const_inplace(c, acc, c->boot_cheb[0]);
+  for (int j = 0; j <= deg; ++j) { ct_free(T[j]); ct_free(T2[j]); }
+  free(T); free(T2);
+  for (int i = 0; i < c->boot_r; ++i) {
+    orc_ct* P = op_mul_relin_rescale(c, acc, acc);
+    orc_ct* y = op_double(c, P);
+    ct_free(P);
+    op_add_const_inplace(c, y, -1.0);
+    ct_free(acc);
+    acc = y;
+  }
+  return acc;
+}
+ORC_API void* orc_eval_mod(void* h, const void* u) { return eval_mod((orc_ctx*)h, (const orc_ct*)u); }
+
+static int boot_levels(orc_ctx* c) {
+  int k = 0;
+  while ((1 << k) < c->boot_deg + 1) ++k;
+  return 2 * c->boot_groups + k + 1 + c->boot_r;
+}
+
+/* the linear transforms: all groups of one direction, each at the level below
+   the previous (targets Delta) */
+static orc_ct* boot_transform(orc_ctx* c, const orc_ct* x, int inverse) {
+  double delta = ldexp(1.0, c->log_scale);
+  orc_ct* y = ct_copy(c, x, x->level);
+  int l0 = x->level;
+  for (int g = 0; g < c->boot_groups; ++g) {
+    boot_group G = boot_make_group(c, inverse, g, l0 - g);
+    orc_ct* t = boot_apply_group(c, &G, g, y, delta);
+    dm_free(&G.M);
+    ct_free(y);
+    y = t;
+  }
+  return y;
+}
+static orc_ct* coeff_to_slot(orc_ctx* c, const orc_ct* x) { return boot_transform(c, x, 1); }
+static orc_ct* slot_to_coeff(orc_ctx* c, const orc_ct* x) { return boot_transform(c, x, 0); }
+ORC_API void* orc_boot_transform(void* h, const void* x, int inverse) {
+  return boot_transform((orc_ctx*)h, (const orc_ct*)x, inverse);
+}
+
+/* the whole bootstrap of a ciphertext at level >= 1 with slot values |z| <= 1;
+   the result is at boot_out_level with scale Delta */
+static orc_ct* bootstrap(orc_ctx* c, const orc_ct* x) {
+  if (c->boot_out_level < 0) die("bootstrap: not set up");
+  if (x->level < 1) die("bootstrap: input needs level >= 1");
+  double tb = ldexp((double)c->mod[0], -c->boot_ratio);
+  orc_ct* x1 = ct_copy(c, x, 1);
+  orc_ct* x0 = op_lincomb(c, x1, 1.0, NULL, 0.0, tb, 1);
+  ct_free(x1);
+  orc_ct* y0 = mod_raise(c, x0);
+  ct_free(x0);
+  orc_ct* y = coeff_to_slot(c, y0);
+  ct_free(y0);
+  /* real and imaginary parts: w + conj(w), -i (w - conj(w)) */
+  orc_ct* yc = op_rotate(c, y, CONJ_STEP);
+  orc_ct* re = op_add(c, y, yc, 0);
+  orc_ct* df = op_add(c, y, yc, 1);
+  orc_ct* im = op_mul_monomial_half(c, df, 1);
+  ct_free(yc); ct_free(df); ct_free(y);
+  orc_ct* re2 = eval_mod(c, re);
+  orc_ct* im2 = eval_mod(c, im);
+  ct_free(re); ct_free(im);
+  orc_ct* imi = op_mul_monomial_half(c, im2, 0);
+  orc_ct* w = op_add(c, re2, imi, 0);
+  ct_free(re2); ct_free(im2); ct_free(imi);
+  orc_ct* w2 = slot_to_coeff(c, w);
+  ct_free(w);
+  w = w2;
+  if (w->level != c->boot_out_level) die("bootstrap: level plan mismatch");
+  c->counters[CNT_REFRESH]++;
+  return w;
+}
+ORC_API void* orc_bootstrap(void* h, const void* x) { return bootstrap((orc_ctx*)h, (const orc_ct*)x); }
+
+/* bootstrapping parameters; call before keygen (the secret weight h is used
+   there).  mode 1 makes every refresh a bootstrap.  Returns the level of a
+   bootstrapped ciphertext, or -1 when the chain is too short. */
+ORC_API int orc_set_boot(void* h, int secret_h, int K, int r, int deg, int ratio, int groups, int mode) {
+  orc_ctx* c = (orc_ctx*)h;
+  c->secret_h = secret_h;
+  if (K <= 0) { c->boot_out_level = -1; c->boot_mode = 0; return -1; }
+  if (deg < 1 || ((deg + 1) & deg) || r < 0 || groups < 1 || ratio < 1) die("bad bootstrapping parameters");
+  c->boot_K = K; c->boot_r = r; c->boot_deg = deg; c->boot_ratio = ratio; c->boot_groups = groups;
+  free(c->boot_cheb);
+  c->boot_cheb = (double*)xcalloc(deg + 1, sizeof(double));
+  boot_cheb_coeffs(K, r, deg, c->boot_cheb);
+  int out = c->n_q - 1 - boot_levels(c);
+  if (out < c->min_level) { c->boot_out_level = -1; c->boot_mode = 0; return -1; }
+  c->boot_out_level = out;
+  c->boot_mode = mode;
+  if (mode) c->refresh_level = out;
+  return out;
+}
+
+/* the CoeffToSlot (inverse = 1) or SlotToCoeff group g as its slot map applied
+   to v (complex, S values), for checks against the matrix definition */
+ORC_API void orc_boot_group_apply(void* h, int inverse, int g, const double* vre, const double* vim, double* ore,
+                                  double* oim) {
+  orc_ctx* c = (orc_ctx*)h;
+  int S = c->n / 2;
+  boot_group G = boot_make_group(c, inverse, g, 0);
+  for (int p = 0; p < S; ++p) {
+    __float128 ar = 0, ai = 0;
+    for (int d = 0; d < S; ++d) {
+      if (!G.M.d[d]) continue;
+      cq v = {vre[(p + d) % S], vim[(p + d) % S]};
+      cq t = cq_mul(G.M.d[d][p], v);
+      ar += t.re;
+      ai += t.im;
+    }
+    ore[p] = (double)ar;
+    oim[p] = (double)ai;
+  }
+  dm_free(&G.M);
+}
+ORC_API void* orc_mod_raise(void* h, const void* x) { return mod_raise((orc_ctx*)h, (const orc_ct*)x); }
+ORC_API void* orc_mul_monomial_half(void* h, const void* x, int neg) {
+  return op_mul_monomial_half((orc_ctx*)h, (const orc_ct*)x, neg);
+}
+ORC_API int orc_boot_out_level(void* h) { return ((orc_ctx*)h)->boot_out_level; }

@@ -1,0 +1,224 @@
+"""Pins of the oracle's bootstrapping against the mathematics it approximates.
+
+The paper refreshes ciphertexts by bootstrapping (arXiv 2502.00847, Sec. 2.2;
+Sec. 4.1) without giving its steps; the oracle follows the standard pipeline
+(scale-down, ModRaise, CoeffToSlot, EvalMod, SlotToCoeff).  Each test checks one
+step against its definition written here with numpy: the canonical embedding
+as a dense matrix, Chebyshev interpolation through numpy's own routines, the
+sine it approximates, and the identity the whole bootstrap must realise.
+"""
+import numpy as np
+import pytest
+
+import workload as W
+from conftest import make_oracle
+from oracle import sim
+from oracle.ckks import argmax_rotation_steps
+
+P = W.PARAMS["tiny_boot"]
+
+
+def _embedding(o):
+    """U_jk = zeta^(5^j k), j < N/2, k < N (slot j <-> root zeta^(5^j), zeta = e^(i pi / N))."""
+    n, m2 = o.n, 2 * o.n
+    g5 = np.array([pow(5, j, m2) for j in range(o.slots)], dtype=np.int64)
+    k = np.arange(n, dtype=np.int64)
+    return np.exp(1j * np.pi * ((g5[:, None] * k[None, :]) % m2) / n)
+
+
+def _bitrev(S):
+    L = S.bit_length() - 1
+    return np.array([int(format(i, f"0{L}b")[::-1], 2) for i in range(S)])
+
+
+def _cdecode(o, ct, E=None):
+    """complex slot values of a ciphertext: decrypt to integers, evaluate at the roots"""
+    E = _embedding(o) if E is None else E
+    return E @ o.decrypt(ct).astype(np.float64) / ct.scale
+
+
+@pytest.fixture(scope="module")
+def boot():
+    o = make_oracle("tiny_boot")
+    steps = sorted(set(o.boot_steps()) | set(argmax_rotation_steps(4, 4, o.slots)))
+    o.keygen(77, steps)
+    return o, _embedding(o)
+
+
+def test_bootstrap_level_budget():
+    """2 * groups linear-transform levels, log2(deg+1) + 1 for the Chebyshev sum, r double angles."""
+    o = make_oracle("tiny_boot")
+    k = int(np.log2(P["boot_deg"] + 1))
+    assert o.boot_out_level() == P["n_q"] - 1 - (2 * P["boot_groups"] + k + 1 + P["boot_r"])
+    assert o.refresh_level == o.boot_out_level()
+    # a chain too short for the pipeline is refused
+    short = make_oracle("tiny_boot", n_q=12)
+    assert short.boot_out_level() == -1
+
+
+def test_sparse_secret_weight():
+    """Each coefficient nonzero with probability h/N, values +-1."""
+    o = make_oracle("tiny_boot")
+    o.gen_secret(5)
+    s = o.secret()
+    assert set(np.unique(s)) <= {-1, 0, 1}
+    w = int(np.count_nonzero(s))
+    h = P["h"]
+    assert abs(w - h) < 5 * np.sqrt(h)
+
+
+def test_coeff_to_slot_is_inverse_embedding():
+    """The CoeffToSlot groups, applied in order, equal P U^-1 / (2 (K+1)) where
+    U_jk = zeta^(5^j k) on the N/2 complex coefficients t_k + i t_(k+N/2) and P
+    the bit reversal (Cheon et al. 2018: the special FFT factorised)."""
+    o = make_oracle("tiny_boot")
+    S = o.slots
+    E = _embedding(o)
+    U = E[:, :S]
+    rng = np.random.default_rng(1)
+    z = rng.normal(size=S) + 1j * rng.normal(size=S)
+    v = z
+    for g in range(P["boot_groups"]):
+        v = o.boot_group_apply(1, g, v)
+    ref = np.linalg.solve(U, z)[_bitrev(S)] / (2 * (P["boot_K"] + 1))
+    assert np.abs(v - ref).max() < 1e-12 * np.abs(ref).max() * S
+
+
+def test_slot_to_coeff_is_embedding():
+    """The SlotToCoeff groups equal U P^-1 times 2^ratio / (2 pi)."""
+    o = make_oracle("tiny_boot")
+    S = o.slots
+    U = _embedding(o)[:, :S]
+    rng = np.random.default_rng(2)
+    w = rng.normal(size=S) + 1j * rng.normal(size=S)
+    v = w
+    for g in range(P["boot_groups"]):
+        v = o.boot_group_apply(0, g, v)
+    wn = np.empty_like(w)
+    wn[_bitrev(S)] = w
+    ref = U @ wn * 2.0 ** P["boot_ratio"] / (2 * np.pi)
+    assert np.abs(v - ref).max() < 1e-12 * np.abs(ref).max() * S
+
+
+def test_chebyshev_interpolant():
+    """c_j interpolate f(u) = cos(2 pi ((K+1) u - 1/4) / 2^r) at the deg+1 Chebyshev
+    nodes (numpy's chebval), and approximate it on the whole interval."""
+    o = make_oracle("tiny_boot")
+    K, r, deg = P["boot_K"], P["boot_r"], P["boot_deg"]
+    c = o.boot_cheb()
+    f = lambda u: np.cos(2 * np.pi * ((K + 1) * u - 0.25) / 2**r)
+    n = deg + 1
+    nodes = np.cos(np.pi * (np.arange(n) + 0.5) / n)
+    assert np.abs(np.polynomial.chebyshev.chebval(nodes, c) - f(nodes)).max() < 1e-13
+    u = np.linspace(-1, 1, 4001)
+    assert np.abs(np.polynomial.chebyshev.chebval(u, c) - f(u)).max() < 1e-9
+    # composed with r double angles this is sin(2 pi x) on |x| <= K + 1
+    y = np.polynomial.chebyshev.chebval(u, c)
+    for _ in range(r):
+        y = 2 * y * y - 1
+    assert np.abs(y - np.sin(2 * np.pi * (K + 1) * u)).max() < 1e-8
+
+
+def test_encode_complex_is_inverse_embedding():
+    o = make_oracle("tiny_boot")
+    rng = np.random.default_rng(3)
+    z = rng.uniform(-1, 1, o.slots) + 1j * rng.uniform(-1, 1, o.slots)
+    scale = 2.0**40
+    m = o.encode_complex(z, scale)
+    got = _embedding(o) @ m.astype(np.float64) / scale
+    assert np.abs(got - z).max() < o.n / scale
+    # real values encode as the real encoder does
+    assert np.array_equal(o.encode_complex(z.real, scale), o.encode(z.real, scale))
+
+
+def test_mod_raise_keeps_residue_mod_q0(boot):
+    """After the scale-down to level 0 at T_b = q_0 2^-ratio and the lift, the
+    message t satisfies t = m (mod q_0) with m encoding z at T_b, t - m = q_0 I,
+    |I| <= K; limb 0 is unchanged."""
+    o, E = boot
+    q0 = int(o.primes[0])
+    rng = np.random.default_rng(4)
+    z = rng.uniform(-1, 1, o.slots)
+    sc = 2.0**50
+    ct = o.lower(o.encrypt(o.encode(z, sc), sc, 5), 1)
+    tb = float(q0) * 2.0 ** -P["boot_ratio"]
+    x0 = o.lincomb(ct, 1.0, None, 0.0, tb, 1)
+    assert x0.level == 0 and x0.scale == tb
+    r = o.mod_raise(x0)
+    assert r.level == o.n_q - 1 and r.scale == float(q0)
+    assert np.array_equal(r.export()[:, 0, :], x0.export()[:, 0, :])
+    t = [int(v) for v in o.decrypt(r)]
+    m = [((v + q0 // 2) % q0) - q0 // 2 for v in t]
+    I = [(a - b) // q0 for a, b in zip(t, m)]
+    assert all((a - b) % q0 == 0 for a, b in zip(t, m))
+    assert max(abs(v) for v in I) <= P["boot_K"]
+    zz = (E @ np.array(m, dtype=np.float64)).real / tb
+    assert np.abs(zz - z).max() < 1e-6
+
+
+def test_monomial_half_multiplies_slots_by_i(boot):
+    """X^(N/2) evaluates to i at every root zeta^(5^j) (5^j = 1 mod 4)."""
+    o, E = boot
+    rng = np.random.default_rng(6)
+    z = rng.uniform(-1, 1, o.slots)
+    sc = 2.0**40
+    ct = o.lower(o.encrypt(o.encode(z, sc), sc, 7), 3)
+    a = _cdecode(o, o.mul_monomial_half(ct, 0), E)
+    b = _cdecode(o, o.mul_monomial_half(ct, 1), E)
+    assert np.abs(a - 1j * z).max() < 1e-6
+    assert np.abs(b + 1j * z).max() < 1e-6
+
+
+def test_eval_mod_is_sine(boot):
+    """EvalMod on u = x / (K+1), x = I + eps near integers, returns sin(2 pi x)
+    (Han-Ki 2020: the scaled cosine, then double angles), r + log2(deg+1) + 1 levels down."""
+    o, _ = boot
+    K = P["boot_K"]
+    rng = np.random.default_rng(8)
+    x = rng.integers(-K, K + 1, o.slots) + rng.uniform(-2.0**-8, 2.0**-8, o.slots)
+    sc = 2.0**50
+    lvl = o.n_q - 1 - P["boot_groups"]
+    ct = o.lower(o.encrypt(o.encode(x / (K + 1), sc), sc, 9), lvl)
+    y = o.eval_mod(ct)
+    k = int(np.log2(P["boot_deg"] + 1))
+    assert y.level == lvl - (k + 1 + P["boot_r"])
+    assert abs(y.scale / sc - 1) < 1e-6  # the double angles leave Delta^2 / q per step
+    got = o.decrypt_decode(y, o.slots)
+    assert np.abs(got - np.sin(2 * np.pi * x)).max() < 1e-7
+
+
+@pytest.mark.parametrize("kind,level", [("uniform", 1), ("sparse", 1), ("uniform", 7)])
+def test_bootstrap_is_identity(boot, kind, level):
+    """A bootstrapped ciphertext decrypts to its input (|z| <= 1) at the output
+    level with scale Delta, within 2^-16 on N = 2^10."""
+    o, _ = boot
+    rng = np.random.default_rng(10 + level)
+    if kind == "uniform":
+        z = rng.uniform(-1, 1, o.slots)
+    else:
+        z = np.zeros(o.slots)
+        z[:8] = rng.uniform(0, 1, 8)
+    sc = 2.0**49
+    ct = o.lower(o.encrypt(o.encode(z, sc), sc, 11), level)
+    o.reset_counters()
+    b = o.bootstrap(ct)
+    assert b.level == o.boot_out_level()
+    assert b.scale == 2.0 ** P["log_scale"]
+    assert np.abs(o.decrypt_decode(b, o.slots) - z).max() < 2.0**-16
+    assert o.counters()["refresh"] == 1
+
+
+def test_argmax_with_bootstrapping(boot):
+    """Algorithm 1 with every refresh a bootstrap: the index is the plaintext
+    argmax and z follows the FP64 simulation of the same polynomials."""
+    o, _ = boot
+    K, C = 2, 4
+    y = W.logits(9, 5, K, C)
+    lo, hi = W.d_bounds(K)
+    o.reset_counters()
+    z = o.decrypt_decode(o.eval_argmax(o.encrypt_logits(y, 3), K, C, lo, hi, 4), C)
+    cnt = o.counters()
+    assert cnt["refresh"] >= 1 and cnt["sign"] == 3
+    zs = sim.t1_argmax(y, lo, hi, o.slots)[:C]
+    assert np.abs(z - zs).max() < 1e-3
+    assert int(np.argmax(z)) == sim.t0_argmax(y)[0]
