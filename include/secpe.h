@@ -178,6 +178,52 @@ size_t secpe_phoenix_workspace_bytes(secpe_ctx* ctx, int K, int C);
 int secpe_eval_argmax_phoenix(secpe_ctx* ctx, const secpe_ct* in, int K, int C, double d_min, double d_max,
                               uint64_t refresh_seed, void* ws_dev, size_t ws_bytes, secpe_ct* out);
 
+/* ---- Bootstrapping (Sec. 2.2; Sec. 4.1: the paper refreshes by
+   bootstrapping, K = 14 of L = 35 levels, and gives no further steps).  The
+   pipeline: one constant product takes the level-1 input to level 0 at scale
+   T_b = q_0 2^-ratio; ModRaise lifts the centred level-0 residues to every
+   chain prime (declared scale q_0); CoeffToSlot (groups of merged radix-2
+   stages of the special FFT, each one level, baby-step giant-step diagonals);
+   a conjugation splits real and imaginary parts; EvalMod on both (Chebyshev
+   interpolant of cos(2 pi (x - 1/4) / 2^r) on |x| <= K + 1, then r double
+   angles); recombination; SlotToCoeff with 2^ratio / (2 pi) folded in.  The
+   output carries scale 2^log_scale at level
+     n_q - 1 - (2 groups + log2(deg + 1) + 1 + r).
+   Inputs need |slot value| <= 1 (the sine is read as its argument). ---- */
+typedef struct secpe_boot_params {
+  int secret_h;   /* > 0: sparse secret, coefficient nonzero w.p. h / N (0: uniform ternary) */
+  int K;          /* EvalMod range |t / q_0| <= K + 1 (bound on the ModRaise overflow) */
+  int r;          /* double angles */
+  int deg;        /* Chebyshev degree, 2^k - 1 */
+  int ratio;      /* log2(q_0 / T_b) */
+  int groups;     /* levels (merged stage groups) of each linear transform */
+  int refresh;    /* 1: every refresh of an evaluation is a bootstrap */
+} secpe_boot_params;
+/* the step value secpe_keygen takes as the conjugation key (X -> X^(2N-1)) */
+#define SECPE_STEP_CONJUGATE INT64_MIN
+/* Set the parameters; call before secpe_keygen (the secret uses secret_h).
+   K <= 0 leaves bootstrapping off (secret_h still applies).  Writes the
+   output level; returns SECPE_EINVAL when the chain is too short. */
+int secpe_set_boot(secpe_ctx* ctx, const secpe_boot_params* bp, int* out_level);
+/* Rotation steps one bootstrap uses (SECPE_STEP_CONJUGATE included); count
+   returned, at most cap written. */
+int secpe_boot_steps(const secpe_ctx* ctx, int64_t* out, int cap);
+/* Device bytes of the precomputed linear-transform plaintexts. */
+size_t secpe_boot_key_bytes(secpe_ctx* ctx);
+/* Encode every group's diagonals (pre-rotated for the giant steps, at the
+   plaintext scale each group's input needs) into buf_dev, which must stay
+   alive while the context bootstraps.  After secpe_keygen.  Synchronous. */
+int secpe_boot_setup(secpe_ctx* ctx, void* buf_dev, size_t bytes);
+/* Bootstrap n ciphertexts (level >= 1) into the caller's buffers; the
+   workspace size needs secpe_boot_setup first (0 and an error otherwise), as
+   do the workspace sizes of evaluations that refresh by bootstrapping. */
+size_t secpe_bootstrap_workspace_bytes(secpe_ctx* ctx, int n);
+int secpe_bootstrap(secpe_ctx* ctx, int n, const secpe_ct* in, void* ws_dev, size_t ws_bytes, secpe_ct* out);
+/* Single steps, for parity checks: step 0 ModRaise (level-0 input), 1
+   CoeffToSlot, 2 SlotToCoeff, 3 EvalMod, 4 slots times i, 5 slots times -i.
+   ws sized by secpe_bootstrap_workspace_bytes(ctx, 1). */
+int secpe_op_boot_step(secpe_ctx* ctx, int step, const secpe_ct* a, void* ws_dev, size_t ws_bytes, secpe_ct* out);
+
 /* Autotuner for the batched path.  Evaluates the batch given (same arguments
    as secpe_eval_argmax_batch, no graph) under each candidate schedule and
    keeps the fastest in the context for later calls:

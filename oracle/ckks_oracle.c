@@ -1999,6 +1999,36 @@ static orc_ct* mod_raise(orc_ctx* c, const orc_ct* a) {
   return x;
 }
 
+/* relinearise a degree-2 ciphertext without rescaling: (d0, d1) + KS(d2) */
+static orc_ct* op_relin3(orc_ctx* c, const orc_ct3* x) {
+  int l = x->level, n = c->n;
+  orc_key* rk = find_key(c, 0);
+  if (!rk) die("no relinearisation key");
+  orc_ct* out = ct_new(c, l, x->scale);
+  uint64_t* u0 = (uint64_t*)xcalloc((size_t)(l + 1) * n, 8);
+  uint64_t* u1 = (uint64_t*)xcalloc((size_t)(l + 1) * n, 8);
+  key_switch(c, x->c[2], l, rk, u0, u1);
+  for (int t = 0; t <= l; ++t) {
+    uint64_t q = c->mod[t];
+    for (int i = 0; i < n; ++i) {
+      size_t o = (size_t)t * n + i;
+      out->c[0][o] = madd(x->c[0][o], u0[o], q);
+      out->c[1][o] = madd(x->c[1][o], u1[o], q);
+    }
+  }
+  free(u0);
+  free(u1);
+  c->counters[CNT_RELIN]++;
+  return out;
+}
+
+/* x^2 relinearised, then rescaled by exact rounding (one level) */
+static orc_ct* op_square_exact(orc_ctx* c, const orc_ct* a) {
+  orc_ct* p = op_mul_relin(c, a, a);
+  rescale_inplace(c, p);
+  return p;
+}
+
 /* x * 2 (an exact integer product: the constant is 2 at the same scale) */
 static orc_ct* op_double(orc_ctx* c, const orc_ct* a) { return op_lincomb(c, a, 2.0, NULL, 0.0, a->scale, 0); }
 
@@ -2006,9 +2036,12 @@ static orc_ct* op_double(orc_ctx* c, const orc_ct* a) { return op_lincomb(c, a, 
      T_2a    = 2 T_a^2 - 1          (square, doubled, constant subtracted)
      T_(a+b) = 2 T_a T_b - T_(a-b)  (b < a, a the largest power of two below a+b;
                                      (2 T_a) (x) T_b with -T_(a-b) added before
-                                     the one relinearise-and-rescale)
+                                     relinearising)
    then p = sum_j c_j T_j at level l - k - 1 (every term a combination at scale
-   Delta q, one rescale), then r double angles y <- 2 y^2 - 1. */
+   Delta q, one rescale), then r double angles y <- 2 y^2 - 1.  Every product
+   here is relinearised and then rescaled by exact rounding: the merged
+   relinearise-and-rescale rounds through an approximate conversion whose error
+   (up to (alpha + 1) / 2 per coefficient) the double angles would amplify. */
 static orc_ct* eval_mod(orc_ctx* c, const orc_ct* u) {
   double delta = ldexp(1.0, c->log_scale);
   int deg = c->boot_deg;
@@ -2020,7 +2053,7 @@ static orc_ct* eval_mod(orc_ctx* c, const orc_ct* u) {
     while (2 * a < j) a *= 2;
     int b = j - a;
     if (b == a) {
-      orc_ct* P = op_mul_relin_rescale(c, T[a], T[a]);
+      orc_ct* P = op_square_exact(c, T[a]);
       T[j] = op_double(c, P);
       ct_free(P);
       op_add_const_inplace(c, T[j], -1.0);
@@ -2030,7 +2063,8 @@ static orc_ct* eval_mod(orc_ctx* c, const orc_ct* u) {
       orc_ct* lo = ct_copy(c, T[a - b], t3->level);
       orc_ct* A = op_lincomb(c, lo, -1.0, NULL, 0.0, t3->scale, 0);
       op_add3_ct_inplace(c, t3, A);
-      T[j] = op_relin_rescale(c, t3);
+      T[j] = op_relin3(c, t3);
+      rescale_inplace(c, T[j]);
       ct3_free(t3); ct_free(lo); ct_free(A);
     }
   }
@@ -2056,7 +2090,7 @@ static orc_ct* eval_mod(orc_ctx* c, const orc_ct* u) {
   for (int j = 0; j <= deg; ++j) { ct_free(T[j]); ct_free(T2[j]); }
   free(T); free(T2);
   for (int i = 0; i < c->boot_r; ++i) {
-    orc_ct* P = op_mul_relin_rescale(c, acc, acc);
+    orc_ct* P = op_square_exact(c, acc);
     orc_ct* y = op_double(c, P);
     ct_free(P);
     op_add_const_inplace(c, y, -1.0);

@@ -1,5 +1,5 @@
 """Build the gfx950 HIP library libsecpe.so in-tree (hipcc, plus g++ for the
-binary128 cosine table)."""
+binary128 host tables: the cosine table and the bootstrapping tables)."""
 import os
 import subprocess
 import sys
@@ -37,15 +37,18 @@ def build(verbose: bool = False) -> str:
     for src in HIP_SOURCES:
         obj = os.path.join(OBJ, src + ".o")
         jobs.append([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
-    cos_obj = os.path.join(OBJ, "cos_table.o")
-    jobs.append(["g++", "-O2", "-fPIC", "-c", os.path.join(CSRC, "cos_table.cpp"), "-o", cos_obj])
+    host_objs = []
+    for src in ("cos_table.cpp", "boot_tables.cpp"):
+        obj = os.path.join(OBJ, src.replace(".cpp", ".o"))
+        jobs.append(["g++", "-O2", "-std=gnu++17", "-fPIC", "-c", os.path.join(CSRC, src), "-o", obj])
+        host_objs.append(obj)
     with ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
         outs = list(ex.map(_run, jobs))
     if verbose:
         for o in outs:
             if o:
                 print(o)
-    objs = [os.path.join(OBJ, s + ".o") for s in HIP_SOURCES] + [cos_obj]
+    objs = [os.path.join(OBJ, s + ".o") for s in HIP_SOURCES] + host_objs
     tmp = LIB + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-lquadmath"])
     os.replace(tmp, LIB)

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/secpe.h"
+#include "boot_tables.h"
 #include "runtime.h"
 
 struct secpe_ctx {
@@ -202,7 +203,8 @@ extern "C" int secpe_keygen(secpe_ctx* x, uint64_t seed, const int64_t* steps, i
   std::vector<uint64_t> gal(1 + n_steps, 0);
   for (int i = 0; i < n_steps; ++i) gal[1 + i] = c.galois(steps[i]);
   auto fn = [&](Builder& b) {
-    std::vector<SampleJob> js{SampleJob{sk, seed, (1ull << 56), nm, nq, SAMPLE_TERNARY, 0}};
+    std::vector<SampleJob> js{c.secret_h > 0 ? SampleJob{sk, seed, (1ull << 56), nm, nq, SAMPLE_SPARSE, c.secret_h}
+                                             : SampleJob{sk, seed, (1ull << 56), nm, nq, SAMPLE_TERNARY, 0}};
     b.sample(js);
     b.ntt({NttJob{sk, sk, nm, nq, 0, 0}}, false);
     double* s2 = b.scratch((size_t)nm * N);
@@ -1369,4 +1371,293 @@ extern "C" int secpe_server_step(secpe_server* s, int cap, int* n_done, uint64_t
   if (n_active) *n_active = (int)s->active.size();
   if (n_pending) *n_pending = (int)s->pending.size();
   return 0;
+}
+
+// ---------------------------------------------------------------------------
+// bootstrapping
+// ---------------------------------------------------------------------------
+static int64_t floor_div64(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// levels, input scales and plaintext scales of every group (no slot vectors)
+static void boot_plan(Ctx& c) {
+  const double delta = ldexp(1.0, c.log_scale);
+  const int top = c.n_q - 1;
+  int k = 0;
+  while ((1 << k) < c.boot_deg + 1) ++k;
+  c.boot_cts.clear();
+  c.boot_stc.clear();
+  for (int inv = 1; inv >= 0; --inv) {
+    int lvl0 = top;
+    double s0 = (double)c.mod[0];
+    if (!inv) {
+      // EvalMod: the Chebyshev sum lands on Delta one level below T_deg, then
+      // each double angle takes s to s^2 / q_l
+      lvl0 = top - c.boot_groups - k - 1;
+      s0 = delta;
+      for (int i = 0; i < c.boot_r; ++i) {
+        s0 = s0 * s0 / (double)c.mod[lvl0];
+        --lvl0;
+      }
+    }
+    for (int g = 0; g < c.boot_groups; ++g) {
+      BootGroupTable t = boot_group_geometry(c.log_n, c.boot_groups, inv, g);
+      BootGroup G;
+      G.inverse = inv;
+      G.g = g;
+      G.level = lvl0 - g;
+      G.delta = t.delta;
+      G.n1 = t.n1;
+      G.E = t.E;
+      G.in_scale = g == 0 ? s0 : delta;
+      double ps = delta * (double)c.mod[G.level];
+      ps = ps / G.in_scale;
+      G.pscale = ps;
+      (inv ? c.boot_cts : c.boot_stc).push_back(G);
+    }
+  }
+}
+
+extern "C" int secpe_set_boot(secpe_ctx* x, const secpe_boot_params* bp, int* out_level) {
+  CHECK_CTX(x);
+  if (!bp) return set_err(SECPE_EINVAL, "null parameters");
+  Ctx& c = x->c;
+  if (bp->secret_h < 0 || bp->secret_h > c.N) return set_err(SECPE_EINVAL, "secret_h must be in [0, N]");
+  c.secret_h = bp->secret_h;
+  c.boot_cts.clear();
+  c.boot_stc.clear();
+  c.boot_ready = false;
+  c.boot_mono = nullptr;
+  c.boot_mode = 0;
+  c.boot_out_level = -1;
+  if (out_level) *out_level = -1;
+  if (bp->K <= 0) return 0;
+  if (bp->deg < 1 || ((bp->deg + 1) & bp->deg) || bp->r < 0 || bp->groups < 1 || bp->groups > c.log_n - 1 ||
+      bp->ratio < 1 || bp->ratio > 40)
+    return set_err(SECPE_EINVAL, "bad bootstrapping parameters");
+  int k = 0;
+  while ((1 << k) < bp->deg + 1) ++k;
+  const int out = c.n_q - 1 - (2 * bp->groups + k + 1 + bp->r);
+  if (out < c.min_level) return set_err(SECPE_EINVAL, "modulus chain too short for bootstrapping");
+  c.boot_K = bp->K;
+  c.boot_r = bp->r;
+  c.boot_deg = bp->deg;
+  c.boot_ratio = bp->ratio;
+  c.boot_groups = bp->groups;
+  c.boot_cheb.assign(bp->deg + 1, 0.0);
+  boot_cheb_coeffs(bp->K, bp->r, bp->deg, c.boot_cheb.data());
+  c.boot_out_level = out;
+  c.boot_mode = bp->refresh ? 1 : 0;
+  if (c.boot_mode) c.refresh_level = out;
+  boot_plan(c);
+  if (out_level) *out_level = out;
+  return 0;
+}
+
+extern "C" int secpe_boot_steps(const secpe_ctx* x, int64_t* out, int cap) {
+  CHECK_CTX(x);
+  const Ctx& c = x->c;
+  if (c.boot_out_level < 0) return set_err(SECPE_EINVAL, "bootstrapping is not configured");
+  const int64_t S = c.N / 2;
+  std::vector<int64_t> st;
+  for (int inv = 0; inv < 2; ++inv)
+    for (int g = 0; g < c.boot_groups; ++g) {
+      BootGroupTable t = boot_group_geometry(c.log_n, c.boot_groups, inv, g);
+      for (int b = 1; b < t.n1; ++b) st.push_back((int64_t)t.delta * b % S);
+      // offsets are delta e with |e| <= 2^len - 1, centred in [-E/2, E/2)
+      const int64_t span = ((int64_t)1 << t.len) - 1;
+      const int64_t elo = std::max(-span, -(int64_t)t.E / 2), ehi = std::min(span, (int64_t)t.E / 2 - 1);
+      for (int64_t G = floor_div64(elo, t.n1); G <= floor_div64(ehi, t.n1); ++G)
+        if (G) st.push_back((((int64_t)t.delta * t.n1 * G) % S + S) % S);
+    }
+  std::sort(st.begin(), st.end());
+  st.erase(std::unique(st.begin(), st.end()), st.end());
+  st.erase(std::remove_if(st.begin(), st.end(), [&](int64_t v) { return v % S == 0; }), st.end());
+  st.push_back(kConjStep);
+  for (size_t i = 0; i < st.size() && (int)i < cap; ++i) out[i] = st[i];
+  return (int)st.size();
+}
+
+// offsets present in a group: every delta e, e centred in [-E/2, E/2) with
+// |e| <= 2^len - 1 (sums of the stages' 0, +-m/2), as slot offsets mod S
+static std::vector<int64_t> boot_group_es(const BootGroup& G, int len) {
+  const int64_t span = ((int64_t)1 << len) - 1;
+  const int64_t elo = std::max(-span, -(int64_t)G.E / 2), ehi = std::min(span, (int64_t)G.E / 2 - 1);
+  std::vector<int64_t> es;
+  for (int64_t e = elo; e <= ehi; ++e) es.push_back(e);
+  return es;
+}
+
+extern "C" size_t secpe_boot_key_bytes(secpe_ctx* x) {
+  if (!x || x->c.boot_out_level < 0) return 0;
+  Ctx& c = x->c;
+  size_t total = 2 * (size_t)c.n_q * c.limb_bytes();
+  for (int inv = 0; inv < 2; ++inv)
+    for (const BootGroup& G : inv ? c.boot_cts : c.boot_stc) {
+      const int len = boot_group_geometry(c.log_n, c.boot_groups, inv, G.g).len;
+      total += boot_group_es(G, len).size() * (size_t)(G.level + 1) * c.limb_bytes();
+    }
+  return total;
+}
+
+extern "C" int secpe_boot_setup(secpe_ctx* x, void* buf_dev, size_t bytes) {
+  CHECK_CTX(x);
+  Ctx& c = x->c;
+  if (c.boot_out_level < 0) return set_err(SECPE_EINVAL, "bootstrapping is not configured");
+  if (!buf_dev || bytes < secpe_boot_key_bytes(x)) return set_err(SECPE_EINVAL, "boot key buffer too small");
+  const int N = c.N, S = N / 2;
+  double* cur = (double*)buf_dev;
+  c.boot_ready = false;
+  // X^(N/2) and -X^(N/2) in the NTT domain, every chain limb
+  {
+    double* mono = cur;
+    cur += 2 * (size_t)c.n_q * N;
+    std::vector<int64_t> mp(N, 0), mn(N, 0);
+    mp[N / 2] = 1;
+    mn[N / 2] = -1;
+    auto fn = [&](Builder& b) {
+      const int64_t* sp = (const int64_t*)b.put_bytes(mp.data(), sizeof(int64_t) * N);
+      const int64_t* sn = (const int64_t*)b.put_bytes(mn.data(), sizeof(int64_t) * N);
+      double* d1 = mono + (size_t)c.n_q * N;
+      b.intspread({IntSpreadJob{sp, mono, c.n_q, c.n_q}, IntSpreadJob{sn, d1, c.n_q, c.n_q}});
+      b.ntt({NttJob{mono, mono, c.n_q, c.n_q, 0, 0}, NttJob{d1, d1, c.n_q, c.n_q, 0, 0}}, false);
+    };
+    int rc = run_client(x, fn);
+    if (rc) return rc;
+    c.boot_mono = mono;
+  }
+  for (int inv = 1; inv >= 0; --inv)
+    for (BootGroup& G : inv ? c.boot_cts : c.boot_stc) {
+      BootGroupTable t = boot_group_table(c.log_n, c.boot_groups, c.boot_K, c.boot_ratio, inv, G.g);
+      G.e.clear();
+      G.pt.clear();
+      std::vector<std::vector<double>> re, im;
+      for (const BootDiag& d : t.diags) {
+        int64_t e = d.off / G.delta;
+        if (e >= G.E / 2) e -= G.E;
+        const int64_t gg = floor_div64(e, G.n1);
+        const int64_t shift = (((int64_t)G.delta * G.n1 * gg) % S + S) % S;
+        std::vector<double> r(S), i2(S);
+        for (int p = 0; p < S; ++p) {
+          const int src = (int)(((int64_t)p - shift + S) % S);
+          r[p] = d.re[src];
+          i2[p] = d.im[src];
+        }
+        G.e.push_back(e);
+        G.pt.push_back(cur);
+        cur += (size_t)(G.level + 1) * N;
+        re.push_back(std::move(r));
+        im.push_back(std::move(i2));
+      }
+      const int nl = G.level + 1;
+      auto fn = [&](Builder& b) {
+        std::vector<EncodeJob> j_enc;
+        std::vector<IntSpreadJob> j_sp;
+        std::vector<NttJob> j_ntt;
+        for (size_t i = 0; i < G.pt.size(); ++i) {
+          int64_t* m = (int64_t*)b.scratch(N);
+          EncodeJob ej{};
+          ej.z = b.put(re[i]);
+          ej.zi = b.put(im[i]);
+          ej.nnz = S;
+          ej.m = m;
+          ej.scale_hi = G.pscale * 2.0 / (double)N;
+          ej.scale_lo = 0.0;
+          j_enc.push_back(ej);
+          double* pt = (double*)G.pt[i];
+          j_sp.push_back(IntSpreadJob{m, pt, nl, nl});
+          j_ntt.push_back(NttJob{pt, pt, nl, nl, 0, 0});
+        }
+        b.encode(j_enc);
+        b.intspread(j_sp);
+        b.ntt(j_ntt, false);
+      };
+      int rc = run_client(x, fn);
+      if (rc) return rc;
+      rc = sync(c);
+      if (rc) return rc;
+    }
+  c.boot_ready = true;
+  return sync(c);
+}
+
+static std::vector<CT> boot_inputs(int n, const secpe_ct* in) {
+  std::vector<CT> v;
+  for (int i = 0; i < n; ++i) v.push_back(to_ct(&in[i]));
+  return v;
+}
+
+extern "C" size_t secpe_bootstrap_workspace_bytes(secpe_ctx* x, int n) {
+  if (!x || n < 1) return 0;
+  if (!x->c.boot_ready) {
+    set_err(SECPE_EINVAL, "bootstrapping is not set up (secpe_boot_setup)");
+    return 0;
+  }
+  Ctx& c = x->c;
+  std::vector<secpe_ct> in(n, secpe_ct{(void*)(uintptr_t)0x200000000000ull, 1, ldexp(1.0, c.log_scale)});
+  Builder dry(c, (char*)(uintptr_t)0x100000000000ull, (size_t)1 << 44, (char*)(uintptr_t)0x400000000000ull,
+              (size_t)1 << 40, true);
+  std::vector<CT> v = boot_inputs(n, in.data());
+  // the dry build takes the set-up scales for granted
+  dry.bootstrap(v);
+  if (dry.err_code) {
+    set_err(dry.err_code, dry.err);
+    return 0;
+  }
+  return dry.need_bytes() + 4096;
+}
+
+extern "C" int secpe_bootstrap(secpe_ctx* x, int n, const secpe_ct* in, void* ws, size_t ws_bytes, secpe_ct* out) {
+  CHECK_CTX(x);
+  Ctx& c = x->c;
+  if (n < 1 || !in || !out || !ws) return set_err(SECPE_EINVAL, "bad bootstrap arguments");
+  if (!c.boot_ready) return set_err(SECPE_EINVAL, "bootstrapping is not set up (secpe_boot_setup)");
+  for (int i = 0; i < n; ++i) {
+    if (!in[i].data || !out[i].data) return set_err(SECPE_EINVAL, "null ciphertext");
+    if (in[i].level < 1 || in[i].level >= c.n_q) return set_err(SECPE_EINVAL, "bootstrap input needs level in [1, n_q)");
+  }
+  std::vector<CT> res;
+  int rc = run_build(x, (char*)ws, ws_bytes, [&](Builder& b) {
+    std::vector<CT> r = b.bootstrap(boot_inputs(n, in));
+    if (b.err_code) return;
+    std::vector<EwJob> j;
+    for (int i = 0; i < n; ++i) {
+      EwJob e{};
+      e.o0 = (double*)out[i].data;
+      e.o1 = (double*)out[i].data + (size_t)c.n_q * c.N;
+      e.a0 = b.c0(r[i]);
+      e.a1 = b.c1(r[i]);
+      e.n_limbs = r[i].level + 1;
+      e.n_chain = r[i].level + 1;
+      e.op = EW_COPY;
+      j.push_back(e);
+    }
+    b.ew(j);
+    res = r;
+  });
+  if (rc) return rc;
+  for (int i = 0; i < n; ++i) {
+    out[i].level = res[i].level;
+    out[i].scale = res[i].scale;
+  }
+  return 0;
+}
+
+extern "C" int secpe_op_boot_step(secpe_ctx* x, int step, const secpe_ct* a, void* ws, size_t ws_bytes, secpe_ct* out) {
+  CHECK_CTX(x);
+  if (!a || !a->data) return set_err(SECPE_EINVAL, "null input");
+  if (step < 0 || step > 5) return set_err(SECPE_EINVAL, "unknown bootstrapping step");
+  if ((step >= 1 && step <= 4 && step != 4) && !x->c.boot_ready)
+    return set_err(SECPE_EINVAL, "bootstrapping is not set up (secpe_boot_setup)");
+  if ((step == 4 || step == 5) && !x->c.boot_mono) return set_err(SECPE_EINVAL, "bootstrapping is not set up");
+  return op_to_out(x, ws, ws_bytes, out, [&](Builder& b) -> std::vector<CT> {
+    const std::vector<CT> v{to_ct(a)};
+    switch (step) {
+      case 0: return b.mod_raise(v);
+      case 1: return b.boot_transform(v, true);
+      case 2: return b.boot_transform(v, false);
+      case 3: return b.eval_mod(v);
+      case 4: return b.mul_monomial_half(v, false);
+      default: return b.mul_monomial_half(v, true);
+    }
+  });
 }

@@ -75,6 +75,7 @@ enum EwOp : int {
   EW_TENSOR2 = 13,
   EW_LIN2 = 15,      // o_i = a_i k[l] + b_i k2[l]   (b optional)
   EW_PADD = 16,      // o0 = a0 + b0 (plaintext polynomial b0), o1 = a1
+  EW_PMAC = 17,      // o_i = a_i * b0 + c_i (plaintext product accumulated; c may alias o)
 };
 
 struct EwJob {
@@ -155,13 +156,15 @@ struct LiftJob {
   int n_out, pad;
 };
 
-enum SampleKind : int { SAMPLE_UNIFORM = 0, SAMPLE_CBD = 1, SAMPLE_TERNARY = 2 };
+// SAMPLE_SPARSE: nonzero (+-1 by the lowest bit) iff the top log2 N bits of
+// the draw are below 'param' (the expected Hamming weight h)
+enum SampleKind : int { SAMPLE_UNIFORM = 0, SAMPLE_CBD = 1, SAMPLE_TERNARY = 2, SAMPLE_SPARSE = 3 };
 
 struct SampleJob {
   double* dst;          // [n_limbs][N]
   uint64_t seed;
   uint64_t tag_base;    // tag with limb field 0; uniform adds the prime index
-  int n_limbs, n_chain, kind, pad;
+  int n_limbs, n_chain, kind, param;
 };
 
 // spread an int64 polynomial (host- or device-encoded) to limbs mod q_t
@@ -171,14 +174,23 @@ struct IntSpreadJob {
   int n_limbs, n_chain;
 };
 
-// encode: m_k = round(scale * 2/N * sum_{j < nnz} z_j cos(pi (5^j k mod 2N)/N));
+// encode: m_k = round(scale * 2/N * sum_{j < nnz} (z_j cos + zi_j sin)(pi (5^j k mod 2N)/N));
 // sparse form (gs set): entry j is slot s_j with gs[j] = 5^{s_j} mod 2N
 struct EncodeJob {
-  const double* z;      // [nnz] slot values
+  const double* z;      // [nnz] slot values (real parts)
   int64_t* m;           // [N]
   double scale_hi, scale_lo;   // scale * 2 / N as a double-double
   int nnz, pad;
   const uint32_t* gs;   // optional [nnz]
+  const double* zi;     // optional [nnz] imaginary parts
+};
+
+// ModRaise: the centred value of a coefficient-domain residue mod q_0
+// (src, [N]) reduced mod q_t for t < n_out (dst, [n_out][N])
+struct RaiseJob {
+  const double* src;
+  double* dst;
+  int n_out, pad;
 };
 
 }  // namespace secpe

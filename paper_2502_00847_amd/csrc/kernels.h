@@ -28,6 +28,7 @@ void launch_moddown_conv(const DevTables& T, const ModDownJob* jobs, int n_jobs,
 void launch_inner(const DevTables& T, const InnerJob* jobs, int n_jobs, int max_ext, hipStream_t s);
 void launch_automorph(const DevTables& T, const AutoJob* jobs, int n_jobs, int max_limbs, hipStream_t s);
 void launch_lift(const DevTables& T, const LiftJob* jobs, int n_jobs, const double* ctab, double q0inv_q1, hipStream_t s);
+void launch_raise(const DevTables& T, const RaiseJob* jobs, int n_jobs, hipStream_t s);
 void launch_sample(const DevTables& T, const SampleJob* jobs, int n_jobs, int max_limbs, hipStream_t s);
 void launch_int_spread(const DevTables& T, const IntSpreadJob* jobs, int n_jobs, int max_limbs, hipStream_t s);
 void launch_encode(const DevTables& T, const EncodeJob* jobs, int n_jobs, hipStream_t s);

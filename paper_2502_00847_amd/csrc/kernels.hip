@@ -895,6 +895,12 @@ __global__ __launch_bounds__(256) void k_ew(const EwJob* __restrict__ jobs, DevT
         }
         break;
       }
+      case EW_PMAC: {
+        const double2 p = ld2(J.b0, o), a0 = ld2(J.a0, o), a1 = ld2(J.a1, o), c0 = ld2(J.c0, o), c1 = ld2(J.c1, o);
+        st2(J.o0, o, canon(mul_mod(a0.x, p.x, m) + c0.x, m), canon(mul_mod(a0.y, p.y, m) + c0.y, m));
+        st2(J.o1, o, canon(mul_mod(a1.x, p.x, m) + c1.x, m), canon(mul_mod(a1.y, p.y, m) + c1.y, m));
+        break;
+      }
       case EW_LIN2: {
         const double2 a0 = ld2(J.a0, o), a1 = ld2(J.a1, o);
         double r0x = mul_mod(a0.x, kk, m), r0y = mul_mod(a0.y, kk, m);
@@ -1092,6 +1098,21 @@ __global__ __launch_bounds__(256) void k_lift(const LiftJob* __restrict__ jobs, 
   }
 }
 
+// ModRaise: residue r mod q_0 -> centred value v in (-q_0/2, q_0/2] -> v mod q_t
+__global__ __launch_bounds__(256) void k_raise(const RaiseJob* __restrict__ jobs, DevTables T) {
+  const RaiseJob J = jobs[blockIdx.z];
+  const int N = 1 << T.log_n;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const double q0 = KPTR(T.mod)[0];
+  const double r = J.src[k];
+  const double v = r > (q0 - 1.0) * 0.5 ? r - q0 : r;
+  for (int t = 0; t < J.n_out; ++t) {
+    const Mod mt{KPTR(T.mod)[t], KPTR(T.minv)[t]};
+    J.dst[(size_t)t * N + k] = canon(v, mt);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // counter-based SplitMix64 (Steele, Lea, Flood 2014) and samplers
 // ---------------------------------------------------------------------------
@@ -1126,6 +1147,9 @@ __global__ __launch_bounds__(256) void k_sample(const SampleJob* __restrict__ jo
       const uint64_t mk = (1ull << 21) - 1;
       v = (double)((int)__popcll(r & mk) - (int)__popcll((r >> 21) & mk));
       v = v < 0.0 ? v + m.p : v;
+    } else if (J.kind == SAMPLE_SPARSE) {
+      const uint64_t r = sm_draw(key, (uint64_t)i);
+      v = (r >> (64 - T.log_n)) < (uint64_t)J.param ? ((r & 1ull) ? m.p - 1.0 : 1.0) : 0.0;
     } else {
       const uint64_t r = sm_draw(key, (uint64_t)i);
       v = (double)(int64_t)__umul64hi(r, 3ull) - 1.0;
@@ -1184,13 +1208,22 @@ __global__ __launch_bounds__(256) void k_encode(const EncodeJob* __restrict__ jo
   if (k >= N) return;
   double sh = 0.0, sl = 0.0;
   uint32_t g = 1;
+  // sin(pi t / N) = cos(pi (t + 3N/2) / N)
+  const uint32_t quarter = 3u * (uint32_t)N / 2u;
   for (int j = 0; j < J.nnz; ++j) {
     const double z = J.z[j];
+    const double zi = J.zi ? J.zi[j] : 0.0;
     const uint32_t gj = J.gs ? J.gs[j] : g;
+    const uint32_t t = (gj * (uint32_t)k) & mask;
     if (z != 0.0) {
-      const uint32_t t = (gj * (uint32_t)k) & mask;
       double ph, pl;
       dd_mul(z, 0.0, T.cos_hi[t], T.cos_lo[t], ph, pl);
+      dd_add(sh, sl, ph, pl);
+    }
+    if (zi != 0.0) {
+      const uint32_t ts = (t + quarter) & mask;
+      double ph, pl;
+      dd_mul(zi, 0.0, T.cos_hi[ts], T.cos_lo[ts], ph, pl);
       dd_add(sh, sl, ph, pl);
     }
     g = (g * 5u) & mask;
@@ -1340,6 +1373,11 @@ void launch_lift(const DevTables& T, const LiftJob* jobs, int n_jobs, const doub
   if (n_jobs <= 0) return;
   dim3 grid((1 << T.log_n) / 256, 1, n_jobs);
   hipLaunchKernelGGL(k_lift, grid, dim3(256), 0, s, jobs, T, ctab, q0inv_q1);
+}
+void launch_raise(const DevTables& T, const RaiseJob* jobs, int n_jobs, hipStream_t s) {
+  if (n_jobs <= 0) return;
+  dim3 grid((1 << T.log_n) / 256, 1, n_jobs);
+  hipLaunchKernelGGL(k_raise, grid, dim3(256), 0, s, jobs, T);
 }
 void launch_sample(const DevTables& T, const SampleJob* jobs, int n_jobs, int max_limbs, hipStream_t s) {
   if (n_jobs <= 0 || max_limbs <= 0) return;

@@ -46,6 +46,19 @@ struct KeyRef {
 
 struct Ctx;
 
+// one group of a bootstrapping linear transform, its plaintexts precomputed:
+// diagonal i (slot offset off[i] = delta e, e centred) is stored pre-rotated by
+// -delta n1 floor(e / n1) and encoded for an input of scale in_scale at 'level'
+struct BootGroup {
+  int inverse = 0, g = 0, level = 0, delta = 0, n1 = 0, E = 0;
+  double in_scale = 0.0, pscale = 0.0;
+  std::vector<int64_t> e;          // centred offset multiple of each diagonal
+  std::vector<const double*> pt;   // NTT domain, limbs 0..level
+};
+
+// the step value that asks for the conjugation X -> X^(2N-1)
+constexpr int64_t kConjStep = INT64_MIN;
+
 struct GraphEntry {
   uint64_t hash = 0;
   hipGraph_t graph = nullptr;
@@ -67,6 +80,16 @@ struct Ctx {
   int modup_eg = 4;
   int q_bits = 0, p_bits = 0, log_scale = 0, dg = 2, df = 2, min_level = 1;
   int refresh_level = 0;   // level a refreshed ciphertext is re-encrypted at
+  // bootstrapping (secpe_set_boot, secpe_boot_setup)
+  int secret_h = 0;        // > 0: sparse secret of expected Hamming weight h
+  int boot_mode = 0;       // 1: refreshes are bootstraps
+  int boot_K = 0, boot_r = 0, boot_deg = 0, boot_ratio = 0, boot_groups = 0;
+  int boot_out_level = -1;
+  std::vector<double> boot_cheb;
+  std::vector<BootGroup> boot_cts, boot_stc;   // CoeffToSlot, SlotToCoeff groups
+  const double* boot_mono = nullptr;            // X^(N/2), then -X^(N/2): [2][n_q][N], NTT domain
+  bool boot_ready = false;
+  int boot_chunk = 8;      // ciphertexts bootstrapped together in one pass
   std::vector<uint64_t> mod;
   int device = 0;
   hipStream_t stream = nullptr;
@@ -122,7 +145,7 @@ void destroy_context(Ctx& c);
 // ---------------------------------------------------------------------------
 // command list: descriptors in one blob, launches replayed in order
 // ---------------------------------------------------------------------------
-enum CmdKind { C_NTT, C_NTT_FIRST, C_NTT_SECOND, C_EW, C_MODUP, C_MODUP_COL, C_MODDOWN, C_INNER, C_INNER_ROW, C_AUTO, C_LIFT, C_SAMPLE, C_INTSPREAD, C_ENCODE, C_DECODE };
+enum CmdKind { C_NTT, C_NTT_FIRST, C_NTT_SECOND, C_EW, C_MODUP, C_MODUP_COL, C_MODDOWN, C_INNER, C_INNER_ROW, C_AUTO, C_LIFT, C_SAMPLE, C_INTSPREAD, C_ENCODE, C_DECODE, C_RAISE };
 
 struct Cmd {
   int kind;
@@ -200,6 +223,7 @@ class Builder {
   void inner(const std::vector<InnerJob>& v);
   void automorph(const std::vector<AutoJob>& v);
   void lift(const std::vector<LiftJob>& v);
+  void raise(const std::vector<RaiseJob>& v);
   void sample(const std::vector<SampleJob>& v);
   void intspread(const std::vector<IntSpreadJob>& v);
   void encode(const std::vector<EncodeJob>& v);
@@ -276,6 +300,15 @@ class Builder {
                           const std::vector<uint64_t>& index);
   std::vector<CT> eval_odd9(const std::vector<CT>& x, const std::vector<const double*>& coef,
                             const std::vector<double>& gain, const std::vector<double>& target);
+  // bootstrapping steps (the groups' plaintexts come from secpe_boot_setup)
+  std::vector<CT> mod_raise(const std::vector<CT>& in);                 // level 0 -> top, scale q_0
+  std::vector<CT> mul_monomial_half(const std::vector<CT>& in, bool neg);  // slots times +-i
+  std::vector<CT> boot_transform(const std::vector<CT>& in, bool inverse);
+  std::vector<CT> eval_mod(const std::vector<CT>& u);
+  std::vector<CT> relin(const std::vector<Deg2>& xs);        // relinearise, no rescale
+  std::vector<CT> square_exact(const std::vector<CT>& xs);   // relinearise, then rescale
+  std::vector<CT> bootstrap(const std::vector<CT>& in);
+  std::vector<CT> bootstrap_chunk(const std::vector<CT>& in);
   // client-side helpers
   void encrypt_into(const std::vector<const int64_t*>& m_dev, const std::vector<uint64_t>& seed, int purpose,
                     const std::vector<uint64_t>& sub, const double* sk, const std::vector<CT>& out);

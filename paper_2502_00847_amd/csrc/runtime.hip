@@ -73,6 +73,7 @@ static uint32_t bitrev(uint32_t x, int bits) {
 }
 
 uint64_t Ctx::galois(int64_t step) const {
+  if (step == kConjStep) return 2 * (uint64_t)N - 1;
   const int64_t slots = N / 2;
   const int64_t r = ((step % slots) + slots) % slots;
   return hpow(5, (uint64_t)r, 2 * (uint64_t)N);
@@ -425,6 +426,7 @@ void Builder::automorph(const std::vector<AutoJob>& v) {
   PUSH_JOBS(C_AUTO, v, my, false, units);
 }
 void Builder::lift(const std::vector<LiftJob>& v) { PUSH_JOBS(C_LIFT, v, 1, false, 0); }
+void Builder::raise(const std::vector<RaiseJob>& v) { PUSH_JOBS(C_RAISE, v, 1, false, 0); }
 void Builder::sample(const std::vector<SampleJob>& v) {
   int my = 0;
   for (auto& j : v) my = std::max(my, j.n_limbs);
@@ -537,6 +539,7 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
       case C_INNER_ROW: launch_inner_row(T, (const InnerJob*)j, k.n, k.max_y, s); break;
       case C_AUTO: launch_automorph(T, (const AutoJob*)j, k.n, k.max_y, s); break;
       case C_LIFT: launch_lift(T, (const LiftJob*)j, k.n, c.crt_tab, c.q0inv_q1, s); break;
+      case C_RAISE: launch_raise(T, (const RaiseJob*)j, k.n, s); break;
       case C_SAMPLE: launch_sample(T, (const SampleJob*)j, k.n, k.max_y, s); break;
       case C_INTSPREAD: launch_int_spread(T, (const IntSpreadJob*)j, k.n, k.max_y, s); break;
       case C_ENCODE: launch_encode(T, (const EncodeJob*)j, k.n, s); break;
@@ -1123,6 +1126,7 @@ void Builder::encrypt_into(const std::vector<const int64_t*>& m_dev, const std::
 // limbs 0 and 1, re-encrypt at the refresh level; scale kept
 std::vector<CT> Builder::refresh(const std::vector<CT>& in, const std::vector<uint64_t>& seed,
                                  const std::vector<uint64_t>& index) {
+  if (C.boot_mode) return bootstrap(in);
   const int N = C.N, L = C.refresh_level + 1;
   const double* rsk = C.refresh_sk ? C.refresh_sk : (dry ? C.T.mod : nullptr);
   if (!rsk) { fail(-3, "modulus chain exhausted and no refresh key registered"); return {}; }
@@ -1246,6 +1250,446 @@ std::vector<CT> Builder::eval_odd9(const std::vector<CT>& xs, const std::vector<
   }
   counters[5] += (int64_t)n;
   return res;
+}
+
+}  // namespace secpe
+
+namespace secpe {
+
+// ---------------------------------------------------------------------------
+// bootstrapping (the paper refreshes by bootstrapping, Sec. 2.2 and Sec. 4.1):
+// scale-down to level 0 at T_b = q_0 2^-ratio, ModRaise, CoeffToSlot,
+// real/imaginary split by conjugation, EvalMod on both parts, recombination,
+// SlotToCoeff.  The groups' plaintexts are built by secpe_boot_setup.
+// ---------------------------------------------------------------------------
+
+// level-0 ciphertexts: centred residues mod q_0 lifted to every chain prime;
+// the result decrypts to t = m + q_0 I and is declared at scale q_0
+std::vector<CT> Builder::mod_raise(const std::vector<CT>& in) {
+  const int N = C.N, L = C.n_q;
+  const size_t mark = scratch_mark();
+  std::vector<CT> out;
+  std::vector<NttJob> j_inv, j_fwd;
+  std::vector<RaiseJob> j_r;
+  for (const CT& x : in) {
+    if (x.level != 0) { fail(-1, "mod_raise: input must be at level 0"); return {}; }
+    CT o = new_ct(L - 1, (double)C.mod[0]);
+    for (int w = 0; w < 2; ++w) {
+      double* r = scratch(N);
+      double* dst = w ? c1(o) : c0(o);
+      j_inv.push_back(NttJob{w ? c1(x) : c0(x), r, 1, 1, 0, 0});
+      j_r.push_back(RaiseJob{r, dst, L, 0});
+      j_fwd.push_back(NttJob{dst, dst, L, L, 0, 0});
+    }
+    out.push_back(o);
+  }
+  ntt(j_inv, true);
+  raise(j_r);
+  ntt(j_fwd, false);
+  scratch_release(mark);
+  return out;
+}
+
+// slots times i (X^(N/2): 5^j = 1 mod 4) or -i (-X^(N/2)); exact, scale kept
+std::vector<CT> Builder::mul_monomial_half(const std::vector<CT>& in, bool neg) {
+  const double* mono = C.boot_mono ? C.boot_mono : (dry ? C.T.mod : nullptr);
+  if (!mono) { fail(-1, "bootstrapping is not set up"); return {}; }
+  std::vector<CT> out;
+  std::vector<EwJob> j;
+  for (const CT& x : in) {
+    CT o = new_ct(x.level, x.scale);
+    EwJob e{};
+    e.o0 = c0(o); e.o1 = c1(o); e.a0 = c0(x); e.a1 = c1(x);
+    e.b0 = mono + (neg ? (size_t)C.n_q * C.N : 0);
+    e.n_limbs = x.level + 1; e.n_chain = x.level + 1;
+    e.op = EW_PMUL;
+    j.push_back(e);
+    out.push_back(o);
+  }
+  ew(j);
+  return out;
+}
+
+static int64_t fdiv(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// all groups of one direction; group g: out = sum_G RotL(sum_b pt_{G,b} * RotL(x, delta b), delta n1 G),
+// rescaled once, scale := Delta.  Inner sums are accumulated baby step by baby
+// step, so one rotated copy of each input is alive at a time.
+std::vector<CT> Builder::boot_transform(const std::vector<CT>& in, bool inverse) {
+  const std::vector<BootGroup>& groups = inverse ? C.boot_cts : C.boot_stc;
+  if (groups.empty() || (!C.boot_ready && !dry)) { fail(-1, "bootstrapping is not set up"); return {}; }
+  const double delta = ldexp(1.0, C.log_scale);
+  std::vector<CT> cur = in;
+  bool own = false;
+  for (const BootGroup& G : groups) {
+    const size_t n = cur.size();
+    if (G.e.empty() || G.e.size() != G.pt.size()) { fail(-1, "bootstrapping plaintexts are not set up"); return {}; }
+    for (const CT& x : cur) {
+      if (x.level != G.level) { fail(-1, "boot transform: input level does not match the set-up"); return {}; }
+      if (x.scale != G.in_scale) { fail(-1, "boot transform: input scale does not match the set-up"); return {}; }
+    }
+    // giant steps present, in ascending order
+    std::vector<int64_t> giants;
+    for (int64_t e : G.e) giants.push_back(fdiv(e, G.n1));
+    std::sort(giants.begin(), giants.end());
+    giants.erase(std::unique(giants.begin(), giants.end()), giants.end());
+    const size_t ng = giants.size();
+    std::vector<CT> acc(n * ng);
+    std::vector<char> have(n * ng, 0);
+    for (int b = 0; b < G.n1; ++b) {
+      std::vector<size_t> di;
+      for (size_t i = 0; i < G.e.size(); ++i)
+        if (G.e[i] - G.n1 * fdiv(G.e[i], G.n1) == b) di.push_back(i);
+      if (di.empty()) continue;
+      std::vector<CT> xb = cur;
+      if (b > 0) {
+        xb = rotate(cur, std::vector<int64_t>(n, (int64_t)G.delta * b));
+        if (err_code) return {};
+      }
+      // every accumulator gets at most one term per baby step: the first
+      // term of an accumulator is a product, later ones accumulate
+      std::vector<EwJob> j;
+      for (size_t it = 0; it < n; ++it)
+        for (size_t i : di) {
+          const size_t gi = std::lower_bound(giants.begin(), giants.end(), fdiv(G.e[i], G.n1)) - giants.begin();
+          const size_t a = it * ng + gi;
+          EwJob e{};
+          if (!have[a]) {
+            acc[a] = new_ct(G.level, cur[it].scale * G.pscale);
+            have[a] = 1;
+            e.op = EW_PMUL;
+          } else {
+            e.c0 = c0(acc[a]); e.c1 = c1(acc[a]);
+            e.op = EW_PMAC;
+          }
+          e.o0 = c0(acc[a]); e.o1 = c1(acc[a]);
+          e.a0 = c0(xb[it]); e.a1 = c1(xb[it]);
+          e.b0 = G.pt[i];
+          e.n_limbs = G.level + 1; e.n_chain = G.level + 1;
+          j.push_back(e);
+        }
+      ew(j);
+      if (b > 0)
+        for (CT& v : xb) free_ct(v);
+    }
+    // giant rotations, then the sum over giant steps
+    std::vector<CT> rin;
+    std::vector<int64_t> rst;
+    std::vector<size_t> rpos;
+    for (size_t it = 0; it < n; ++it)
+      for (size_t gi = 0; gi < ng; ++gi)
+        if (giants[gi] != 0) {
+          rin.push_back(acc[it * ng + gi]);
+          rst.push_back((int64_t)G.delta * G.n1 * giants[gi]);
+          rpos.push_back(it * ng + gi);
+        }
+    if (!rin.empty()) {
+      std::vector<CT> rout = rotate(rin, rst);
+      if (err_code) return {};
+      for (size_t k = 0; k < rpos.size(); ++k) {
+        free_ct(acc[rpos[k]]);
+        acc[rpos[k]] = rout[k];
+      }
+    }
+    std::vector<CT> nxt;
+    for (size_t it = 0; it < n; ++it) {
+      if (ng == 1) {
+        nxt.push_back(acc[it]);
+        continue;
+      }
+      std::vector<CT> sum = add({{acc[it * ng], acc[it * ng + 1]}}, false);
+      if (err_code) return {};
+      for (size_t gi = 2; gi < ng; ++gi) {
+        std::vector<CT> t = add({{sum[0], acc[it * ng + gi]}}, false);
+        if (err_code) return {};
+        free_ct(sum[0]);
+        sum = t;
+      }
+      for (size_t gi = 0; gi < ng; ++gi) free_ct(acc[it * ng + gi]);
+      nxt.push_back(sum[0]);
+    }
+    const size_t mark = scratch_mark();
+    rescale(nxt);
+    scratch_release(mark);
+    if (err_code) return {};
+    for (CT& v : nxt) v.scale = delta;
+    if (own)
+      for (CT& v : cur) free_ct(v);
+    cur = nxt;
+    own = true;
+  }
+  return cur;
+}
+
+// relinearise degree-2 ciphertexts without rescaling: (d0, d1) + KS(d2)
+std::vector<CT> Builder::relin(const std::vector<Deg2>& xs) {
+  auto kit = C.keys.find(0);
+  const double* rk = kit != C.keys.end() ? kit->second : (dry ? C.T.mod : nullptr);
+  if (!rk) { fail(-4, "no relinearisation key"); return {}; }
+  std::vector<CT> out;
+  std::vector<KsItem> ks;
+  for (const Deg2& x : xs) {
+    if (x.sq0) { fail(-1, "relin: fused squares are not supported here"); return {}; }
+    CT o = new_ct(x.level, x.scale);
+    ks.push_back(KsItem{x.d2, x.level, rk, x.d0, x.d1, c0(o), c1(o), nullptr, nullptr, false});
+    out.push_back(o);
+  }
+  key_switch(ks);
+  counters[2] += (int64_t)xs.size();
+  return out;
+}
+
+// x^2 relinearised, then rescaled by exact rounding (one level)
+std::vector<CT> Builder::square_exact(const std::vector<CT>& xs) {
+  std::vector<std::pair<CT, CT>> sq;
+  for (const CT& x : xs) sq.push_back({x, x});
+  std::vector<CT> p = mul_relin(sq, false);
+  if (err_code) return {};
+  const size_t mark = scratch_mark();
+  rescale(p);
+  scratch_release(mark);
+  return p;
+}
+
+// EvalMod on u = x / (K+1) (Han-Ki 2020): Chebyshev basis T_1 = u,
+//   T_2a    = 2 T_a^2 - 1           (square, doubled, constant subtracted),
+//   T_(a+b) = 2 T_a T_b - T_(a-b)   (b < a, a the largest power of two below
+//             a+b: (2 T_a) (x) T_b plus -T_(a-b) at the product's scale, one
+//             relinearise-and-rescale),
+// p = sum_j c_j T_j accumulated at the level of T_deg with scale Delta q (one
+// rescale to Delta), then r double angles y <- 2 y^2 - 1.  Every product is
+// relinearised and then rescaled by exact rounding: the merged
+// relinearise-and-rescale rounds through an approximate conversion whose error
+// (up to (alpha + 1) / 2 per coefficient) the double angles would amplify.
+std::vector<CT> Builder::eval_mod(const std::vector<CT>& us) {
+  const size_t n = us.size();
+  const int deg = C.boot_deg;
+  if (deg < 1 || (int)C.boot_cheb.size() != deg + 1) { fail(-1, "bootstrapping is not set up"); return {}; }
+  const double delta = ldexp(1.0, C.log_scale);
+  int k = 0;
+  while ((1 << k) < deg + 1) ++k;
+  for (const CT& u : us) {
+    if (u.level != us[0].level) { fail(-1, "eval_mod: inputs must share the level"); return {}; }
+    if (u.level - k - 1 - C.boot_r < 0) { fail(-3, "eval_mod: not enough levels"); return {}; }
+  }
+  std::vector<std::vector<CT>> T(deg + 1, std::vector<CT>(n)), T2(deg + 1, std::vector<CT>(n));
+  std::vector<char> owned(deg + 1, 0), have2(deg + 1, 0);
+  T[1] = us;
+  std::vector<CT> acc;
+  // T_j sits at level l - ceil(log2 j); the sum is formed at the level of T_deg
+  const int ld = us[0].level - k;
+  const double sig = delta * (double)C.mod[ld];
+  const int half = 1 << (k - 1);
+  // c_j T_j (lowered to the level of T_deg) added into the accumulator; T_j of
+  // the top octave are needed by nothing else and are freed right away
+  auto accumulate = [&](int j) {
+    std::vector<LinItem> li;
+    for (size_t i = 0; i < n; ++i) {
+      LinItem t{};
+      t.a = T[j][i];
+      t.a.level = ld;
+      t.a.slot = -1;
+      t.va = C.boot_cheb[j];
+      t.target = sig;
+      if (!acc.empty()) { t.b = acc[i]; t.vb = 1.0; t.has_b = true; }
+      li.push_back(t);
+    }
+    std::vector<CT> nx = lincomb(li, false);
+    if (err_code) return;
+    for (CT& v : acc) free_ct(v);
+    acc = nx;
+  };
+  for (int j = 2; j <= deg; ++j) {
+    int a = 1;
+    while (2 * a < j) a *= 2;
+    const int b = j - a;
+    const size_t mark = scratch_mark();
+    if (b == a) {
+      std::vector<CT> P = square_exact(T[a]);
+      if (err_code) return {};
+      std::vector<LinItem> li;
+      for (size_t i = 0; i < n; ++i) {
+        LinItem t{};
+        t.a = P[i];
+        t.va = 2.0;
+        t.target = P[i].scale;
+        li.push_back(t);
+      }
+      std::vector<CT> P2 = lincomb(li, false);
+      if (err_code) return {};
+      for (CT& v : P) free_ct(v);
+      T[j] = add_const(P2, std::vector<double>(n, -1.0));
+      if (err_code) return {};
+      for (CT& v : P2) free_ct(v);
+    } else {
+      if (!have2[a]) {
+        std::vector<LinItem> li;
+        for (size_t i = 0; i < n; ++i) {
+          LinItem t{};
+          t.a = T[a][i];
+          t.va = 2.0;
+          t.target = T[a][i].scale;
+          li.push_back(t);
+        }
+        T2[a] = lincomb(li, false);
+        if (err_code) return {};
+        have2[a] = 1;
+      }
+      std::vector<LinItem> la;
+      for (size_t i = 0; i < n; ++i) {
+        LinItem t{};
+        t.a = T[a - b][i];
+        t.a.level = T2[a][i].level;
+        t.a.slot = -1;
+        t.va = -1.0;
+        t.target = T2[a][i].scale * T[b][i].scale;
+        la.push_back(t);
+      }
+      std::vector<CT> A = lincomb(la, false);
+      if (err_code) return {};
+      std::vector<TensorItem> ti;
+      for (size_t i = 0; i < n; ++i) {
+        TensorItem t{};
+        t.a = T2[a][i];
+        t.b = T[b][i];
+        t.f = A[i];
+        t.has_f = true;
+        ti.push_back(t);
+      }
+      std::vector<Deg2> d = tensor2(ti);
+      if (err_code) return {};
+      T[j] = relin(d);
+      if (err_code) return {};
+      rescale(T[j]);
+      if (err_code) return {};
+      for (CT& v : A) free_ct(v);
+    }
+    scratch_release(mark);
+    owned[j] = 1;
+    if (j > half) {
+      // the top octave is needed by nothing but the sum
+      accumulate(j);
+      if (err_code) return {};
+      for (CT& v : T[j]) free_ct(v);
+      owned[j] = 0;
+    }
+  }
+  for (int j = 1; j <= half && j <= deg; ++j) {
+    accumulate(j);
+    if (err_code) return {};
+  }
+  for (int j = 2; j <= deg; ++j)
+    if (owned[j])
+      for (CT& v : T[j]) free_ct(v);
+  for (int j = 1; j <= deg; ++j)
+    if (have2[j])
+      for (CT& v : T2[j]) free_ct(v);
+  {
+    const size_t mark = scratch_mark();
+    rescale(acc);
+    scratch_release(mark);
+    if (err_code) return {};
+  }
+  for (CT& v : acc) v.scale = delta;
+  std::vector<CT> y = add_const(acc, std::vector<double>(n, C.boot_cheb[0]));
+  if (err_code) return {};
+  for (CT& v : acc) free_ct(v);
+  for (int i = 0; i < C.boot_r; ++i) {
+    const size_t mark = scratch_mark();
+    std::vector<CT> P = square_exact(y);
+    if (err_code) return {};
+    std::vector<LinItem> li;
+    for (size_t t = 0; t < n; ++t) {
+      LinItem it{};
+      it.a = P[t];
+      it.va = 2.0;
+      it.target = P[t].scale;
+      li.push_back(it);
+    }
+    std::vector<CT> P2 = lincomb(li, false);
+    if (err_code) return {};
+    for (CT& v : P) free_ct(v);
+    std::vector<CT> y2 = add_const(P2, std::vector<double>(n, -1.0));
+    if (err_code) return {};
+    for (CT& v : P2) free_ct(v);
+    for (CT& v : y) free_ct(v);
+    y = y2;
+    scratch_release(mark);
+  }
+  return y;
+}
+
+// the whole bootstrap of ciphertexts at level >= 1 with slot values |z| <= 1;
+// results at boot_out_level with scale Delta.  Items run in chunks of
+// boot_chunk so the temporaries of one chunk bound the workspace.
+std::vector<CT> Builder::bootstrap(const std::vector<CT>& all) {
+  if (C.boot_out_level < 0 || (!C.boot_ready && !dry)) { fail(-1, "bootstrapping is not set up"); return {}; }
+  std::vector<CT> res;
+  const size_t chunk = (size_t)std::max(1, C.boot_chunk);
+  for (size_t c0 = 0; c0 < all.size(); c0 += chunk) {
+    std::vector<CT> part(all.begin() + c0, all.begin() + std::min(all.size(), c0 + chunk));
+    std::vector<CT> o = bootstrap_chunk(part);
+    if (err_code) return {};
+    res.insert(res.end(), o.begin(), o.end());
+  }
+  return res;
+}
+
+std::vector<CT> Builder::bootstrap_chunk(const std::vector<CT>& in) {
+  const size_t n = in.size();
+  const double tb = ldexp((double)C.mod[0], -C.boot_ratio);
+  std::vector<LinItem> li;
+  for (const CT& x : in) {
+    if (x.level < 1) { fail(-3, "bootstrap: input needs level >= 1"); return {}; }
+    LinItem t{};
+    t.a = x;
+    t.a.level = 1;
+    t.a.slot = -1;
+    t.va = 1.0;
+    t.target = tb;
+    li.push_back(t);
+  }
+  std::vector<CT> x0 = lincomb(li, true);
+  if (err_code) return {};
+  std::vector<CT> r = mod_raise(x0);
+  if (err_code) return {};
+  for (CT& v : x0) free_ct(v);
+  std::vector<CT> y = boot_transform(r, true);
+  if (err_code) return {};
+  for (CT& v : r) free_ct(v);
+  std::vector<CT> yc = rotate(y, std::vector<int64_t>(n, kConjStep));
+  if (err_code) return {};
+  std::vector<std::pair<CT, CT>> pr;
+  for (size_t i = 0; i < n; ++i) pr.push_back({y[i], yc[i]});
+  std::vector<CT> re = add(pr, false);
+  std::vector<CT> df = add(pr, true);
+  if (err_code) return {};
+  for (CT& v : y) free_ct(v);
+  for (CT& v : yc) free_ct(v);
+  std::vector<CT> im = mul_monomial_half(df, true);
+  if (err_code) return {};
+  for (CT& v : df) free_ct(v);
+  std::vector<CT> both = re;
+  both.insert(both.end(), im.begin(), im.end());
+  std::vector<CT> e = eval_mod(both);
+  if (err_code) return {};
+  for (CT& v : both) free_ct(v);
+  std::vector<CT> ei(e.begin() + n, e.end());
+  std::vector<CT> imi = mul_monomial_half(ei, false);
+  if (err_code) return {};
+  pr.clear();
+  for (size_t i = 0; i < n; ++i) pr.push_back({e[i], imi[i]});
+  std::vector<CT> w = add(pr, false);
+  if (err_code) return {};
+  for (CT& v : e) free_ct(v);
+  for (CT& v : imi) free_ct(v);
+  std::vector<CT> out = boot_transform(w, false);
+  if (err_code) return {};
+  for (CT& v : w) free_ct(v);
+  for (const CT& v : out)
+    if (v.level != C.boot_out_level) { fail(-1, "bootstrap: level plan mismatch"); return {}; }
+  counters[4] += (int64_t)n;
+  return out;
 }
 
 }  // namespace secpe

@@ -25,6 +25,14 @@ class _Params(C.Structure):
                                        "refresh_level")]
 
 
+class _BootParams(C.Structure):
+    _fields_ = [(n, C.c_int) for n in ("secret_h", "K", "r", "deg", "ratio", "groups", "refresh")]
+
+
+# the step value keygen takes for the conjugation key
+STEP_CONJUGATE = -(1 << 63)
+
+
 class _Ct(C.Structure):
     _fields_ = [("data", C.c_void_p), ("level", C.c_int), ("scale", C.c_double)]
 
@@ -106,6 +114,13 @@ def load():
         "secpe_server_request_bytes": (sz, [vp, i32, i32]),
         "secpe_server_submit": (i32, [vp, ct, i32, i32, dbl, dbl, u64, vp, P(u64)]),
         "secpe_server_step": (i32, [vp, i32, P(i32), P(u64), P(i32), P(dbl), P(i32), P(i32)]),
+        "secpe_set_boot": (i32, [vp, P(_BootParams), P(i32)]),
+        "secpe_boot_steps": (i32, [vp, P(i64), i32]),
+        "secpe_boot_key_bytes": (sz, [vp]),
+        "secpe_boot_setup": (i32, [vp, vp, sz]),
+        "secpe_bootstrap_workspace_bytes": (sz, [vp, i32]),
+        "secpe_bootstrap": (i32, [vp, i32, ct, vp, sz, ct]),
+        "secpe_op_boot_step": (i32, [vp, i32, ct, vp, sz, ct]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -131,7 +146,8 @@ def exported_symbols():
          "secpe_op_key_switch", "secpe_op_ntt", "secpe_op_ring_mul", "secpe_op_encode", "secpe_profile_begin",
          "secpe_profile_end", "secpe_ntt_cts", "secpe_rotate_workspace_bytes", "secpe_rotate_batch",
          "secpe_server_create", "secpe_server_destroy", "secpe_server_request_bytes", "secpe_server_submit",
-         "secpe_server_step"])
+         "secpe_server_step", "secpe_set_boot", "secpe_boot_steps", "secpe_boot_key_bytes", "secpe_boot_setup",
+         "secpe_bootstrap_workspace_bytes", "secpe_bootstrap", "secpe_op_boot_step"])
 
 
 def _p(arr, ctype):
@@ -172,6 +188,11 @@ class Context:
         self.slots = self.N // 2
         self.sk = None
         self.evk = None
+        self.boot_out_level = -1
+        if params.get("h", 0) or params.get("boot_K", 0):
+            self.set_boot(params.get("h", 0), params.get("boot_K", 0), params.get("boot_r", 0),
+                          params.get("boot_deg", 1), params.get("boot_ratio", 1), params.get("boot_groups", 1),
+                          params.get("boot_refresh", 0))
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -222,6 +243,56 @@ class Context:
 
     def set_refresh_key(self, sk):
         self._check(self.lib.secpe_set_refresh_key(self.h, C.c_void_p(sk.data_ptr()) if sk is not None else None))
+
+    # -- bootstrapping -----------------------------------------------------------
+    def set_boot(self, h, K, r, deg, ratio, groups, refresh):
+        """Sparse secret weight and bootstrapping parameters (before keygen)."""
+        bp = _BootParams(int(h), int(K), int(r), int(deg), int(ratio), int(groups), int(refresh))
+        lvl = C.c_int(-1)
+        self._check(self.lib.secpe_set_boot(self.h, C.byref(bp), C.byref(lvl)))
+        self.boot_out_level = lvl.value
+        return lvl.value
+
+    def boot_steps(self):
+        out = np.zeros(4096, dtype=np.int64)
+        n = self.lib.secpe_boot_steps(self.h, _p(out, C.c_int64), len(out))
+        if n < 0:
+            self._check(n)
+        return [int(v) for v in out[:n]]
+
+    def boot_setup(self):
+        """Encode the linear-transform plaintexts (after keygen)."""
+        nb = self.lib.secpe_boot_key_bytes(self.h)
+        self.boot_keys = self._empty(nb)
+        self._check(self.lib.secpe_boot_setup(self.h, C.c_void_p(self.boot_keys.data_ptr()), nb))
+
+    def bootstrap_workspace(self, n):
+        nb = self.lib.secpe_bootstrap_workspace_bytes(self.h, int(n))
+        if nb == 0:
+            raise SecpeError(self.lib.secpe_last_error().decode())
+        return self._empty(nb)
+
+    def bootstrap(self, cts, ws=None, outs=None):
+        n = len(cts)
+        ws = self.bootstrap_workspace(n) if ws is None else ws
+        outs = [self.new_ct() for _ in range(n)] if outs is None else outs
+        ins = (_Ct * n)(*[c._c() for c in cts])
+        os_ = (_Ct * n)(*[o._c() for o in outs])
+        self._check(self.lib.secpe_bootstrap(self.h, n, ins, C.c_void_p(ws.data_ptr()), ws.numel() * 8, os_))
+        for o, c in zip(outs, os_):
+            o.level, o.scale = c.level, c.scale
+        return outs
+
+    def boot_step(self, step, a):
+        """0 ModRaise, 1 CoeffToSlot, 2 SlotToCoeff, 3 EvalMod, 4 times i, 5 times -i."""
+        if getattr(self, "_bws", None) is None:
+            self._bws = self.bootstrap_workspace(1)
+        out = self.new_ct()
+        c = out._c()
+        self._check(self.lib.secpe_op_boot_step(self.h, int(step), C.byref(a._c()), C.c_void_p(self._bws.data_ptr()),
+                                                self._bws.numel() * 8, C.byref(c)))
+        out.level, out.scale = c.level, c.scale
+        return out
 
     # -- client ------------------------------------------------------------------
     def encrypt(self, logits, seed, sk=None):

@@ -1,0 +1,187 @@
+"""Bootstrapping on the GPU against the oracle, bit for bit (N = 2^10), and by
+its defining property at N = 2^16.  The paper refreshes by bootstrapping
+(arXiv 2502.00847, Sec. 2.2; Sec. 4.1)."""
+import numpy as np
+import pytest
+
+import workload as W
+from oracle import sim
+from oracle.ckks import Oracle, argmax_rotation_steps
+
+pytestmark = pytest.mark.gpu
+
+SEED = 0xB007
+P = W.PARAMS["tiny_boot"]
+
+
+def _same(g, gct, oct_):
+    assert gct.level == oct_.level, (gct.level, oct_.level)
+    assert gct.scale == oct_.scale, (gct.scale, oct_.scale)
+    a = g.export(gct)
+    b = oct_.export()
+    if not np.array_equal(a, b):
+        bad = np.argwhere(a != b)
+        raise AssertionError(f"{len(bad)} residues differ, first at {bad[:5].tolist()}")
+
+
+@pytest.fixture(scope="module")
+def pair():
+    from paper_2502_00847_amd.secpe import Context
+    g = Context(P)
+    o = Oracle.from_params(P)
+    assert g.boot_out_level == o.boot_out_level() > 0
+    steps = sorted(set(g.boot_steps()) | set(argmax_rotation_steps(4, 4, g.slots)), key=lambda v: (v < 0, v))
+    print(f"[boot] keygen {len(steps)} keys", flush=True)
+    g.keygen(SEED, steps)
+    o.keygen(SEED, steps)
+    g.boot_setup()
+    return g, o
+
+
+def _enc(o, z, scale, seed, level):
+    return o.lower(o.encrypt(o.encode(z, scale), scale, seed), level)
+
+
+def test_boot_steps_and_secret_match(pair):
+    g, o = pair
+    assert g.boot_steps() == o.boot_steps()
+    assert np.array_equal(g.secret(), o.secret())
+    assert 0 < np.count_nonzero(o.secret()) < g.N // 4
+
+
+def test_mod_raise_bit_exact(pair):
+    g, o = pair
+    z = np.random.default_rng(1).uniform(-1, 1, g.slots)
+    ct = _enc(o, z, 2.0**50, 3, 1)
+    tb = float(o.primes[0]) * 2.0 ** -P["boot_ratio"]
+    x0o = o.lincomb(ct, 1.0, None, 0.0, tb, 1)
+    x0g = g.lincomb(g.import_(ct.export(), ct.scale), 1.0, None, 0.0, tb, True)
+    _same(g, x0g, x0o)
+    _same(g, g.boot_step(0, x0g), o.mod_raise(x0o))
+
+
+def test_monomials_bit_exact(pair):
+    g, o = pair
+    ct = _enc(o, np.random.default_rng(2).uniform(-1, 1, g.slots), 2.0**45, 4, 5)
+    gc = g.import_(ct.export(), ct.scale)
+    _same(g, g.boot_step(4, gc), o.mul_monomial_half(ct, 0))
+    _same(g, g.boot_step(5, gc), o.mul_monomial_half(ct, 1))
+
+
+def test_coeff_to_slot_bit_exact(pair):
+    g, o = pair
+    z = np.random.default_rng(3).uniform(-1, 1, g.slots)
+    ct = _enc(o, z, 2.0**50, 5, 1)
+    tb = float(o.primes[0]) * 2.0 ** -P["boot_ratio"]
+    r = o.mod_raise(o.lincomb(ct, 1.0, None, 0.0, tb, 1))
+    _same(g, g.boot_step(1, g.import_(r.export(), r.scale)), o.boot_transform(r, 1))
+
+
+def test_eval_mod_bit_exact(pair):
+    g, o = pair
+    K = P["boot_K"]
+    rng = np.random.default_rng(4)
+    x = rng.integers(-K, K + 1, g.slots) + rng.uniform(-2.0**-8, 2.0**-8, g.slots)
+    ct = _enc(o, x / (K + 1), 2.0 ** P["log_scale"], 6, g.n_q - 1 - P["boot_groups"])
+    yo = o.eval_mod(ct)
+    _same(g, g.boot_step(3, g.import_(ct.export(), ct.scale)), yo)
+
+
+def test_bootstrap_bit_exact(pair):
+    g, o = pair
+    z = np.random.default_rng(5).uniform(-1, 1, g.slots)
+    ct = _enc(o, z, 2.0**49, 7, 3)
+    bo = o.bootstrap(ct)
+    o.reset_counters()
+    [bg] = g.bootstrap([g.import_(ct.export(), ct.scale)])
+    _same(g, bg, bo)
+    assert bg.level == g.boot_out_level
+    assert np.abs(o.decrypt_decode(bo, g.slots) - z).max() < 2.0**-16
+
+
+def test_bootstrap_batch_equals_single(pair):
+    """Three ciphertexts in one call (one chunk) give the single-call results."""
+    g, o = pair
+    cts = [_enc(o, np.random.default_rng(10 + i).uniform(-1, 1, g.slots), 2.0**50, 20 + i, 1 + 2 * i)
+           for i in range(3)]
+    outs = g.bootstrap([g.import_(c.export(), c.scale) for c in cts])
+    for c, b in zip(cts, outs):
+        _same(g, b, o.bootstrap(c))
+
+
+def test_argmax_with_bootstrapping_bit_exact(pair):
+    """Algorithm 1 refreshing by bootstrapping, on the GPU and in the oracle."""
+    g, o = pair
+    K, C = 2, 4
+    y = W.logits(9, 5, K, C)
+    lo, hi = W.d_bounds(K)
+    o.reset_counters()
+    zo = o.eval_argmax(o.encrypt_logits(y, 3), K, C, lo, hi, 4)
+    zg = g.eval_argmax(g.encrypt(y, 3), K, C, lo, hi, 4)
+    _same(g, zg, zo)
+    cg, co = g.counters(), o.counters()
+    for k in ("sign", "rotate", "relin", "key_switch", "refresh", "max"):
+        assert cg[k] == co[k], (k, cg[k], co[k])
+    assert co["refresh"] >= 1
+    z, idx = g.decrypt(zg, C)
+    assert idx == sim.t0_argmax(y)[0]
+    assert np.abs(z - sim.t1_argmax(y, lo, hi, g.slots)[:C]).max() < 1e-3
+
+
+def test_bootstrap_errors_are_reported(pair):
+    from paper_2502_00847_amd.secpe import SecpeError
+    g, o = pair
+    ct = _enc(o, np.zeros(4), 2.0**50, 8, 0)
+    with pytest.raises(SecpeError):
+        g.bootstrap([g.import_(ct.export(), ct.scale)])   # level 0 has no level for the scale-down
+    with pytest.raises(SecpeError):
+        g.boot_step(9, g.import_(ct.export(), ct.scale))
+
+
+@pytest.fixture(scope="module")
+def full():
+    from paper_2502_00847_amd.secpe import Context
+    p = W.PARAMS["full_boot"]
+    g = Context(p)
+    steps = sorted(set(g.boot_steps()) | set(g.argmax_steps(16, 16)), key=lambda v: (v < 0, v))
+    print(f"[boot] full keygen {len(steps)} keys", flush=True)
+    g.keygen(SEED, steps)
+    g.boot_setup()
+    print("[boot] full set-up done", flush=True)
+    return g
+
+
+def test_full_bootstrap_precision(full):
+    """N = 2^16, L = 35: a bootstrapped ciphertext decrypts to its input within
+    2^-12 (|z| <= 1), at level n_q - 1 - 16 with scale 2^50."""
+    g = full
+    rng = np.random.default_rng(6)
+    for kind in ("uniform", "sparse"):
+        if kind == "uniform":
+            z = rng.uniform(-1, 1, g.slots)
+        else:
+            z = np.zeros(g.slots)
+            z[:16] = rng.uniform(0, 1, 16)
+        # the full slot vector through the logits layout (K = 1, C = slots)
+        ct = g.encrypt(z.reshape(1, -1), 40 + len(kind))
+        [b] = g.bootstrap([ct])
+        assert b.level == g.n_q - 1 - 16 and b.scale == 2.0**50
+        got, _ = g.decrypt(b, g.slots)
+        err = np.abs(got - z).max()
+        print(f"[boot] full {kind}: max error 2^{np.log2(err):.1f}", flush=True)
+        assert err < 2.0**-12
+
+
+def test_full_argmax_with_bootstrapping(full):
+    """Config 2 (K = 8, C = 4) with every refresh a bootstrap: the index is the
+    plaintext argmax and z follows the FP64 simulation."""
+    g = full
+    q = W.query(2, 0)
+    z = g.eval_argmax(g.encrypt(q["logits"], q["encrypt_seed"]), q["K"], q["C"], q["d_min"], q["d_max"],
+                      q["refresh_seed"])
+    cnt = g.counters()
+    assert cnt["refresh"] >= 1
+    zz, idx = g.decrypt(z, q["C"])
+    assert idx == sim.t0_argmax(q["logits"])[0]
+    zs = sim.t1_argmax(q["logits"], q["d_min"], q["d_max"], g.slots)[:q["C"]]
+    assert np.abs(zz - zs).max() < 1e-2

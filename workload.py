@@ -36,11 +36,11 @@ PARAMS = {
     # linear transform; boot_refresh = 1 makes every refresh a bootstrap.
     # 2 * 3 + 6 + 3 = 15 levels on N = 2^10 (a bootstrapped ciphertext has 10 left)
     "tiny_boot": dict(log_n=10, n_q=26, q_bits=50, n_p=8, p_bits=51, log_scale=50, dg=2, df=2, min_level=1,
-                      h=64, boot_K=12, boot_r=3, boot_deg=31, boot_ratio=10, boot_groups=3, boot_refresh=1),
+                      h=64, boot_K=12, boot_r=3, boot_deg=31, boot_ratio=8, boot_groups=3, boot_refresh=1),
     # L = 35 chain primes as in the paper (Sec. 4.1); 2 * 3 + 6 + 4 = 16 levels,
     # a bootstrapped ciphertext has 18 left
     "full_boot": dict(log_n=16, n_q=35, q_bits=50, n_p=12, p_bits=51, log_scale=50, dg=2, df=2, min_level=1,
-                      h=192, boot_K=24, boot_r=4, boot_deg=31, boot_ratio=10, boot_groups=3, boot_refresh=1),
+                      h=192, boot_K=24, boot_r=4, boot_deg=31, boot_ratio=8, boot_groups=3, boot_refresh=1),
 }
 
 CLIP = 6.0
