@@ -313,6 +313,83 @@ def phoenix_compare(params, ns=(4, 16, 64, 256), K=4):
             "what": "one query alone, wall time; the comparison path runs its C-1 comparisons batched"}
 
 
+def bootstrap_rate(n_batch=8, n_queries=32):
+    """Bootstrapping on the paper's chain (L = 35 primes, N = 2^16, Sec. 4.1):
+    throughput and precision of one chunk of ciphertexts, and the Argmax with
+    every refresh a bootstrap (config 2 alone; config-3 queries batched)."""
+    from paper_2502_00847_amd.secpe import Context
+    p = W.PARAMS["full_boot"]
+    t0 = time.perf_counter()
+    g = Context(p)
+    steps = sorted(set(g.boot_steps()) | set(g.argmax_steps(16, 16)), key=lambda v: (v < 0, v))
+    g.keygen(W.KEYGEN_SEED, steps)
+    t1 = time.perf_counter()
+    g.boot_setup()
+    g.sync()
+    t2 = time.perf_counter()
+    rng = np.random.default_rng(77)
+    zs = [rng.uniform(-1, 1, g.slots) for _ in range(n_batch)]
+    cts = [g.encrypt(z.reshape(1, -1), 7700 + i) for i, z in enumerate(zs)]
+    ws = g.bootstrap_workspace(n_batch)
+    outs = [g.new_ct() for _ in range(n_batch)]
+    g.bootstrap(cts, ws=ws, outs=outs)
+    g.sync()
+    reps = 3
+    ta = time.perf_counter()
+    for _ in range(reps):
+        g.bootstrap(cts, ws=ws, outs=outs)
+    g.sync()
+    batch_s = (time.perf_counter() - ta) / reps
+    err = max(float(np.abs(g.decrypt(o, g.slots)[0] - z).max()) for o, z in zip(outs, zs))
+    ws1 = g.bootstrap_workspace(1)
+    g.bootstrap(cts[:1], ws=ws1, outs=outs[:1])
+    g.sync()
+    ta = time.perf_counter()
+    g.bootstrap(cts[:1], ws=ws1, outs=outs[:1])
+    g.sync()
+    one_ms = (time.perf_counter() - ta) * 1e3
+    cnt_boot = g.counters()
+    del ws, ws1
+    out = {"params": "N=2^16, 35 chain + 12 special primes, h=192, K=24, r=4, deg=31, q0/T_b=2^8, 3+3 groups",
+           "out_level": g.boot_out_level, "keygen_s": round(t1 - t0, 2), "setup_s": round(t2 - t1, 2),
+           "bootstraps_per_s": round(n_batch / batch_s, 2), "batch": n_batch, "one_ms": round(one_ms, 2),
+           "max_error": err, "log2_max_error": round(float(np.log2(err)), 2),
+           "rotations": cnt_boot["rotate"], "key_switches": cnt_boot["key_switch"]}
+    _log(f"bootstrap: {out}")
+    # Argmax refreshing by bootstrapping
+    d2 = W.query(2, 0)
+    ct = g.encrypt(d2["logits"], d2["encrypt_seed"])
+    ws = g.workspace([d2["K"]], [d2["C"]])
+    g.eval_argmax(ct, d2["K"], d2["C"], d2["d_min"], d2["d_max"], d2["refresh_seed"], ws=ws)
+    g.sync()
+    ta = time.perf_counter()
+    z = g.eval_argmax(ct, d2["K"], d2["C"], d2["d_min"], d2["d_max"], d2["refresh_seed"], ws=ws)
+    g.sync()
+    ms2 = (time.perf_counter() - ta) * 1e3
+    cnt = g.counters()
+    idx2 = g.decrypt(z, d2["C"])[1]
+    del ws
+    qs = [W.query(3, i) for i in range(n_queries)]
+    qcts = [g.encrypt(q["logits"], q["encrypt_seed"]) for q in qs]
+    Ks, Cs = [q["K"] for q in qs], [q["C"] for q in qs]
+    ws = g.workspace(Ks, Cs)
+    args = ([q["d_min"] for q in qs], [q["d_max"] for q in qs], [q["refresh_seed"] for q in qs])
+    zo = g.eval_argmax_batch(qcts, Ks, Cs, *args, ws=ws)
+    g.sync()
+    ta = time.perf_counter()
+    zo = g.eval_argmax_batch(qcts, Ks, Cs, *args, ws=ws)
+    g.sync()
+    tb = time.perf_counter() - ta
+    cntb = g.counters()
+    ok = sum(int(g.decrypt(z, q["C"])[1] == sim_t0(q["logits"])[0]) for z, q in zip(zo, qs))
+    out["argmax_config2"] = {"ms": round(ms2, 2), "bootstraps": cnt["refresh"],
+                             "index_ok": bool(idx2 == sim_t0(d2["logits"])[0])}
+    out["argmax_config3_batch"] = {"queries": n_queries, "argmax_per_s": round(n_queries / tb, 2),
+                                   "bootstraps": cntb["refresh"], "correct": ok}
+    _log(f"argmax with bootstrapping: {out['argmax_config2']} {out['argmax_config3_batch']}")
+    return out
+
+
 def keyswitch_rate(g, params):
     n = 64
     N = 1 << params["log_n"]
@@ -533,6 +610,7 @@ def main():
     if args.variants:
         result.update(variants(params))
         result["phoenix_vs_secpe"] = phoenix_compare(params)
+        result["bootstrapping"] = bootstrap_rate()
     if args.keyswitch:
         result["ntt"] = ntt_rate(g, params)
         result["keyswitch"] = keyswitch_rate(g, params)

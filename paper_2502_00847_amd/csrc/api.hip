@@ -1530,23 +1530,36 @@ extern "C" int secpe_boot_setup(secpe_ctx* x, void* buf_dev, size_t bytes) {
       BootGroupTable t = boot_group_table(c.log_n, c.boot_groups, c.boot_K, c.boot_ratio, inv, G.g);
       G.e.clear();
       G.pt.clear();
+      // the nonzero entries of each pre-rotated diagonal as (5^slot mod 2N, re, im)
       std::vector<std::vector<double>> re, im;
+      std::vector<std::vector<uint32_t>> gs;
+      std::vector<uint32_t> g5(S);
+      for (int p = 0, v = 1; p < S; ++p, v = (int)((uint64_t)v * 5 % (2ull * N))) g5[p] = (uint32_t)v;
       for (const BootDiag& d : t.diags) {
         int64_t e = d.off / G.delta;
         if (e >= G.E / 2) e -= G.E;
         const int64_t gg = floor_div64(e, G.n1);
         const int64_t shift = (((int64_t)G.delta * G.n1 * gg) % S + S) % S;
-        std::vector<double> r(S), i2(S);
+        std::vector<double> r, i2;
+        std::vector<uint32_t> gv;
         for (int p = 0; p < S; ++p) {
           const int src = (int)(((int64_t)p - shift + S) % S);
-          r[p] = d.re[src];
-          i2[p] = d.im[src];
+          if (d.re[src] == 0.0 && d.im[src] == 0.0) continue;
+          r.push_back(d.re[src]);
+          i2.push_back(d.im[src]);
+          gv.push_back(g5[p]);
+        }
+        if (r.empty()) {  // an all-zero diagonal still takes part (as zero)
+          r.push_back(0.0);
+          i2.push_back(0.0);
+          gv.push_back(1u);
         }
         G.e.push_back(e);
         G.pt.push_back(cur);
         cur += (size_t)(G.level + 1) * N;
         re.push_back(std::move(r));
         im.push_back(std::move(i2));
+        gs.push_back(std::move(gv));
       }
       const int nl = G.level + 1;
       auto fn = [&](Builder& b) {
@@ -1558,7 +1571,8 @@ extern "C" int secpe_boot_setup(secpe_ctx* x, void* buf_dev, size_t bytes) {
           EncodeJob ej{};
           ej.z = b.put(re[i]);
           ej.zi = b.put(im[i]);
-          ej.nnz = S;
+          ej.gs = b.put(gs[i]);
+          ej.nnz = (int)re[i].size();
           ej.m = m;
           ej.scale_hi = G.pscale * 2.0 / (double)N;
           ej.scale_lo = 0.0;

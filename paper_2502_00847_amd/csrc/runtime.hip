@@ -241,6 +241,7 @@ int build_context(Ctx& c, int log_n, int n_q, int q_bits, int n_p, int p_bits, i
   }
   c.q0inv_q1 = (double)hinv(c.mod[0] % c.mod[1], c.mod[1]);
   if (const char* e = getenv("SECPE_NTT_CHUNK_MB")) c.ntt_chunk_bytes = (size_t)std::max(0L, atol(e)) << 20;
+  if (const char* e = getenv("SECPE_BOOT_CHUNK")) c.boot_chunk = (int)std::max(1L, std::min(256L, atol(e)));
   // ----- upload -----
   if (hipSetDevice(device) != hipSuccess) return SECPE_EDEVICE_INTERNAL;
   c.tab_bytes = h.size() * sizeof(double);
