@@ -185,6 +185,18 @@ struct EncodeJob {
   const double* zi;     // optional [nnz] imaginary parts
 };
 
+// one baby-step giant-step group of a linear transform on one ciphertext:
+// out_G = sum_b pt[G * 8 + b] * x_b (both polynomials), for giant index
+// G < n_giants and baby step b < n1 (a null pt skips the term); NTT domain
+struct BsgsJob {
+  const double* x0[8];
+  const double* x1[8];
+  double* o0[8];
+  double* o1[8];
+  const double* pt[64];
+  int n_limbs, n_giants, n1, pad;
+};
+
 // ModRaise: the centred value of a coefficient-domain residue mod q_0
 // (src, [N]) reduced mod q_t for t < n_out (dst, [n_out][N])
 struct RaiseJob {

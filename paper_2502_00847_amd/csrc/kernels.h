@@ -29,6 +29,7 @@ void launch_inner(const DevTables& T, const InnerJob* jobs, int n_jobs, int max_
 void launch_automorph(const DevTables& T, const AutoJob* jobs, int n_jobs, int max_limbs, hipStream_t s);
 void launch_lift(const DevTables& T, const LiftJob* jobs, int n_jobs, const double* ctab, double q0inv_q1, hipStream_t s);
 void launch_raise(const DevTables& T, const RaiseJob* jobs, int n_jobs, hipStream_t s);
+void launch_bsgs(const DevTables& T, const BsgsJob* jobs, int n_jobs, int max_limbs, hipStream_t s);
 void launch_sample(const DevTables& T, const SampleJob* jobs, int n_jobs, int max_limbs, hipStream_t s);
 void launch_int_spread(const DevTables& T, const IntSpreadJob* jobs, int n_jobs, int max_limbs, hipStream_t s);
 void launch_encode(const DevTables& T, const EncodeJob* jobs, int n_jobs, hipStream_t s);

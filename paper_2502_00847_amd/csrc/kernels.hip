@@ -1098,6 +1098,51 @@ __global__ __launch_bounds__(256) void k_lift(const LiftJob* __restrict__ jobs, 
   }
 }
 
+// Baby-step giant-step inner sums of one linear-transform group: every input
+// x_b is read once, every plaintext once, every output written once (the
+// per-baby-step multiply-accumulate reads and writes each output n1 times).
+// Two residues per thread; partial sums are reduced after every term.
+__global__ __launch_bounds__(256) void k_bsgs(const BsgsJob* __restrict__ jobs, DevTables T) {
+  const BsgsJob& J = jobs[blockIdx.z];
+  const int l = blockIdx.y;
+  if (l >= J.n_limbs) return;
+  const Mod m{KPTR(T.mod)[l], KPTR(T.minv)[l]};
+  const int N = 1 << T.log_n;
+  const size_t off = (size_t)l * N;
+  const int n1 = J.n1, ng = J.n_giants;
+  for (int i = 2 * (blockIdx.x * blockDim.x + threadIdx.x); i < N; i += 2 * gridDim.x * blockDim.x) {
+    const size_t o = off + i;
+    double2 xa[8], xb[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      if (b < n1) {
+        xa[b] = ld2(J.x0[b], o);
+        xb[b] = ld2(J.x1[b], o);
+      } else {
+        xa[b] = make_double2(0.0, 0.0);
+        xb[b] = make_double2(0.0, 0.0);
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      if (g >= ng) break;
+      double a0x = 0.0, a0y = 0.0, a1x = 0.0, a1y = 0.0;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const double* pp = J.pt[g * 8 + b];
+        if (b >= n1 || !pp) continue;
+        const double2 p = ld2(pp, o);
+        a0x = red(a0x + mul_mod(xa[b].x, p.x, m), m);
+        a0y = red(a0y + mul_mod(xa[b].y, p.y, m), m);
+        a1x = red(a1x + mul_mod(xb[b].x, p.x, m), m);
+        a1y = red(a1y + mul_mod(xb[b].y, p.y, m), m);
+      }
+      st2(J.o0[g], o, canon(a0x, m), canon(a0y, m));
+      st2(J.o1[g], o, canon(a1x, m), canon(a1y, m));
+    }
+  }
+}
+
 // ModRaise: residue r mod q_0 -> centred value v in (-q_0/2, q_0/2] -> v mod q_t
 __global__ __launch_bounds__(256) void k_raise(const RaiseJob* __restrict__ jobs, DevTables T) {
   const RaiseJob J = jobs[blockIdx.z];
@@ -1373,6 +1418,11 @@ void launch_lift(const DevTables& T, const LiftJob* jobs, int n_jobs, const doub
   if (n_jobs <= 0) return;
   dim3 grid((1 << T.log_n) / 256, 1, n_jobs);
   hipLaunchKernelGGL(k_lift, grid, dim3(256), 0, s, jobs, T, ctab, q0inv_q1);
+}
+void launch_bsgs(const DevTables& T, const BsgsJob* jobs, int n_jobs, int max_limbs, hipStream_t s) {
+  if (n_jobs <= 0 || max_limbs <= 0) return;
+  dim3 grid(ew_blocks(1 << T.log_n), max_limbs, n_jobs);
+  hipLaunchKernelGGL(k_bsgs, grid, dim3(256), 0, s, jobs, T);
 }
 void launch_raise(const DevTables& T, const RaiseJob* jobs, int n_jobs, hipStream_t s) {
   if (n_jobs <= 0) return;

@@ -145,7 +145,7 @@ void destroy_context(Ctx& c);
 // ---------------------------------------------------------------------------
 // command list: descriptors in one blob, launches replayed in order
 // ---------------------------------------------------------------------------
-enum CmdKind { C_NTT, C_NTT_FIRST, C_NTT_SECOND, C_EW, C_MODUP, C_MODUP_COL, C_MODDOWN, C_INNER, C_INNER_ROW, C_AUTO, C_LIFT, C_SAMPLE, C_INTSPREAD, C_ENCODE, C_DECODE, C_RAISE };
+enum CmdKind { C_NTT, C_NTT_FIRST, C_NTT_SECOND, C_EW, C_MODUP, C_MODUP_COL, C_MODDOWN, C_INNER, C_INNER_ROW, C_AUTO, C_LIFT, C_SAMPLE, C_INTSPREAD, C_ENCODE, C_DECODE, C_RAISE, C_BSGS };
 
 struct Cmd {
   int kind;
@@ -224,6 +224,7 @@ class Builder {
   void automorph(const std::vector<AutoJob>& v);
   void lift(const std::vector<LiftJob>& v);
   void raise(const std::vector<RaiseJob>& v);
+  void bsgs(const std::vector<BsgsJob>& v);
   void sample(const std::vector<SampleJob>& v);
   void intspread(const std::vector<IntSpreadJob>& v);
   void encode(const std::vector<EncodeJob>& v);

@@ -428,6 +428,11 @@ void Builder::automorph(const std::vector<AutoJob>& v) {
 }
 void Builder::lift(const std::vector<LiftJob>& v) { PUSH_JOBS(C_LIFT, v, 1, false, 0); }
 void Builder::raise(const std::vector<RaiseJob>& v) { PUSH_JOBS(C_RAISE, v, 1, false, 0); }
+void Builder::bsgs(const std::vector<BsgsJob>& v) {
+  int my = 0;
+  for (auto& j : v) my = std::max(my, j.n_limbs);
+  PUSH_JOBS(C_BSGS, v, my, false, 0);
+}
 void Builder::sample(const std::vector<SampleJob>& v) {
   int my = 0;
   for (auto& j : v) my = std::max(my, j.n_limbs);
@@ -541,6 +546,7 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
       case C_AUTO: launch_automorph(T, (const AutoJob*)j, k.n, k.max_y, s); break;
       case C_LIFT: launch_lift(T, (const LiftJob*)j, k.n, c.crt_tab, c.q0inv_q1, s); break;
       case C_RAISE: launch_raise(T, (const RaiseJob*)j, k.n, s); break;
+      case C_BSGS: launch_bsgs(T, (const BsgsJob*)j, k.n, k.max_y, s); break;
       case C_SAMPLE: launch_sample(T, (const SampleJob*)j, k.n, k.max_y, s); break;
       case C_INTSPREAD: launch_int_spread(T, (const IntSpreadJob*)j, k.n, k.max_y, s); break;
       case C_ENCODE: launch_encode(T, (const EncodeJob*)j, k.n, s); break;
@@ -1336,42 +1342,90 @@ std::vector<CT> Builder::boot_transform(const std::vector<CT>& in, bool inverse)
     giants.erase(std::unique(giants.begin(), giants.end()), giants.end());
     const size_t ng = giants.size();
     std::vector<CT> acc(n * ng);
-    std::vector<char> have(n * ng, 0);
-    for (int b = 0; b < G.n1; ++b) {
-      std::vector<size_t> di;
-      for (size_t i = 0; i < G.e.size(); ++i)
-        if (G.e[i] - G.n1 * fdiv(G.e[i], G.n1) == b) di.push_back(i);
-      if (di.empty()) continue;
-      std::vector<CT> xb = cur;
-      if (b > 0) {
-        xb = rotate(cur, std::vector<int64_t>(n, (int64_t)G.delta * b));
+    if (G.n1 <= 8 && ng <= 8) {
+      // every baby step in use at once, then one fused launch for all inner sums
+      std::vector<int> slot_of(G.n1, -1);
+      std::vector<char> used(G.n1, 0);
+      for (int64_t e : G.e) used[e - G.n1 * fdiv(e, G.n1)] = 1;
+      std::vector<CT> rin;
+      std::vector<int64_t> rst;
+      for (int b = 1; b < G.n1; ++b) {
+        if (!used[b]) continue;
+        slot_of[b] = (int)(rin.size() / n);
+        for (size_t it = 0; it < n; ++it) {
+          rin.push_back(cur[it]);
+          rst.push_back((int64_t)G.delta * b);
+        }
+      }
+      std::vector<CT> rb;
+      if (!rin.empty()) {
+        rb = rotate(rin, rst);
         if (err_code) return {};
       }
-      // every accumulator gets at most one term per baby step: the first
-      // term of an accumulator is a product, later ones accumulate
-      std::vector<EwJob> j;
-      for (size_t it = 0; it < n; ++it)
-        for (size_t i : di) {
-          const size_t gi = std::lower_bound(giants.begin(), giants.end(), fdiv(G.e[i], G.n1)) - giants.begin();
-          const size_t a = it * ng + gi;
-          EwJob e{};
-          if (!have[a]) {
-            acc[a] = new_ct(G.level, cur[it].scale * G.pscale);
-            have[a] = 1;
-            e.op = EW_PMUL;
-          } else {
-            e.c0 = c0(acc[a]); e.c1 = c1(acc[a]);
-            e.op = EW_PMAC;
-          }
-          e.o0 = c0(acc[a]); e.o1 = c1(acc[a]);
-          e.a0 = c0(xb[it]); e.a1 = c1(xb[it]);
-          e.b0 = G.pt[i];
-          e.n_limbs = G.level + 1; e.n_chain = G.level + 1;
-          j.push_back(e);
+      std::vector<BsgsJob> jb;
+      for (size_t it = 0; it < n; ++it) {
+        BsgsJob J{};
+        J.n_limbs = G.level + 1;
+        J.n_giants = (int)ng;
+        J.n1 = G.n1;
+        for (int b = 0; b < G.n1; ++b) {
+          // an unused baby step has no plaintext; its input is only read
+          const CT& xb = slot_of[b] < 0 ? cur[it] : rb[(size_t)slot_of[b] * n + it];
+          J.x0[b] = c0(xb);
+          J.x1[b] = c1(xb);
         }
-      ew(j);
-      if (b > 0)
-        for (CT& v : xb) free_ct(v);
+        for (size_t gi = 0; gi < ng; ++gi) {
+          acc[it * ng + gi] = new_ct(G.level, cur[it].scale * G.pscale);
+          J.o0[gi] = c0(acc[it * ng + gi]);
+          J.o1[gi] = c1(acc[it * ng + gi]);
+        }
+        for (size_t i = 0; i < G.e.size(); ++i) {
+          const int64_t gg = fdiv(G.e[i], G.n1);
+          const size_t gi = std::lower_bound(giants.begin(), giants.end(), gg) - giants.begin();
+          J.pt[gi * 8 + (size_t)(G.e[i] - G.n1 * gg)] = G.pt[i];
+        }
+        jb.push_back(J);
+      }
+      bsgs(jb);
+      for (CT& v : rb) free_ct(v);
+    } else {
+      std::vector<char> have(n * ng, 0);
+      for (int b = 0; b < G.n1; ++b) {
+        std::vector<size_t> di;
+        for (size_t i = 0; i < G.e.size(); ++i)
+          if (G.e[i] - G.n1 * fdiv(G.e[i], G.n1) == b) di.push_back(i);
+        if (di.empty()) continue;
+        std::vector<CT> xb = cur;
+        if (b > 0) {
+          xb = rotate(cur, std::vector<int64_t>(n, (int64_t)G.delta * b));
+          if (err_code) return {};
+        }
+        // every accumulator gets at most one term per baby step: the first
+        // term of an accumulator is a product, later ones accumulate
+        std::vector<EwJob> j;
+        for (size_t it = 0; it < n; ++it)
+          for (size_t i : di) {
+            const size_t gi = std::lower_bound(giants.begin(), giants.end(), fdiv(G.e[i], G.n1)) - giants.begin();
+            const size_t a = it * ng + gi;
+            EwJob e{};
+            if (!have[a]) {
+              acc[a] = new_ct(G.level, cur[it].scale * G.pscale);
+              have[a] = 1;
+              e.op = EW_PMUL;
+            } else {
+              e.c0 = c0(acc[a]); e.c1 = c1(acc[a]);
+              e.op = EW_PMAC;
+            }
+            e.o0 = c0(acc[a]); e.o1 = c1(acc[a]);
+            e.a0 = c0(xb[it]); e.a1 = c1(xb[it]);
+            e.b0 = G.pt[i];
+            e.n_limbs = G.level + 1; e.n_chain = G.level + 1;
+            j.push_back(e);
+          }
+        ew(j);
+        if (b > 0)
+          for (CT& v : xb) free_ct(v);
+      }
     }
     // giant rotations, then the sum over giant steps
     std::vector<CT> rin;
