@@ -2032,62 +2032,136 @@ static orc_ct* op_square_exact(orc_ctx* c, const orc_ct* a) {
 /* x * 2 (an exact integer product: the constant is 2 at the same scale) */
 static orc_ct* op_double(orc_ctx* c, const orc_ct* a) { return op_lincomb(c, a, 2.0, NULL, 0.0, a->scale, 0); }
 
-/* EvalMod on u = x / (K+1): Chebyshev basis T_1 = u,
+/* EvalMod on u = x / (K+1) (Han, Ki 2020): p(u) = sum_j c_j T_j(u), the
+   Chebyshev interpolant of cos(2 pi ((K+1) u - 1/4) / 2^r), then r double
+   angles y <- 2 y^2 - 1.
+
+   p is evaluated baby-step giant-step in the Chebyshev basis: baby steps
+   T_1 .. T_(B-1) (B = 2^ceil(k/2) for degree 2^k - 1), giant steps T_B, T_2B,
+   .., T_(2^(k-1)); a polynomial of degree < 2h (h a giant) splits by Chebyshev
+   division, T_(h+j) = 2 T_h T_j - T_(h-j), into p = r + T_h q with
+     q_0 = c_h, q_j = 2 c_(h+j),   r_0 = c_0, r_j = c_j - c_(2h-j)   (0 < j < h),
+   recursively, down to combinations of the baby steps.  Each split costs one
+   product: (2^m1 - 2) + (k - m1) + (2^(k-m1) - 1) products in all (11 for
+   degree 31, against 30 for the whole basis), depth k + 1.  Scales: every node
+   lands exactly on the scale its parent needs (its q child's target is
+   T q_l / s_h); an r child that is a combination of baby steps is added,
+   unrescaled, at the product's scale before relinearising, its constant
+   after.  The basis products:
      T_2a    = 2 T_a^2 - 1          (square, doubled, constant subtracted)
-     T_(a+b) = 2 T_a T_b - T_(a-b)  (b < a, a the largest power of two below a+b;
-                                     (2 T_a) (x) T_b with -T_(a-b) added before
-                                     relinearising)
-   then p = sum_j c_j T_j at level l - k - 1 (every term a combination at scale
-   Delta q, one rescale), then r double angles y <- 2 y^2 - 1.  Every product
-   here is relinearised and then rescaled by exact rounding: the merged
-   relinearise-and-rescale rounds through an approximate conversion whose error
-   (up to (alpha + 1) / 2 per coefficient) the double angles would amplify. */
-static orc_ct* eval_mod(orc_ctx* c, const orc_ct* u) {
-  double delta = ldexp(1.0, c->log_scale);
-  int deg = c->boot_deg;
-  orc_ct** T = (orc_ct**)xcalloc(deg + 1, sizeof(orc_ct*));
-  orc_ct** T2 = (orc_ct**)xcalloc(deg + 1, sizeof(orc_ct*));
-  T[1] = ct_copy(c, u, u->level);
-  for (int j = 2; j <= deg; ++j) {
-    int a = 1;
-    while (2 * a < j) a *= 2;
-    int b = j - a;
-    if (b == a) {
-      orc_ct* P = op_square_exact(c, T[a]);
-      T[j] = op_double(c, P);
-      ct_free(P);
-      op_add_const_inplace(c, T[j], -1.0);
-    } else {
-      if (!T2[a]) T2[a] = op_double(c, T[a]);
-      orc_ct3* t3 = op_tensor(c, T2[a], T[b]);
-      orc_ct* lo = ct_copy(c, T[a - b], t3->level);
-      orc_ct* A = op_lincomb(c, lo, -1.0, NULL, 0.0, t3->scale, 0);
-      op_add3_ct_inplace(c, t3, A);
-      T[j] = op_relin3(c, t3);
-      rescale_inplace(c, T[j]);
-      ct3_free(t3); ct_free(lo); ct_free(A);
-    }
-  }
-  int ld = T[deg]->level;
-  double sig = delta * (double)c->mod[ld];
+     T_(a+b) = 2 T_a T_b - T_(a-b)  (b < a, a the largest power of two below
+                                     a+b; (2 T_a) (x) T_b with -T_(a-b) added
+                                     before relinearising).
+   Every product here is relinearised and then rescaled by exact rounding: the
+   merged relinearise-and-rescale rounds through an approximate conversion
+   whose error (up to (alpha + 1) / 2 per coefficient) the double angles would
+   amplify. */
+
+/* sum_{0 < j < n} cf[j] T_j, every T_j lowered to level lv, at scale 'scale'
+   (not rescaled) */
+static orc_ct* cheb_combination(orc_ctx* c, orc_ct** T, const double* cf, int n, int lv, double scale) {
   orc_ct* acc = NULL;
-  for (int j = 1; j <= deg; j += 2) {
-    orc_ct* a1 = ct_copy(c, T[j], ld);
-    orc_ct* b1 = j + 1 <= deg ? ct_copy(c, T[j + 1], ld) : NULL;
-    orc_ct* t = op_lincomb(c, a1, c->boot_cheb[j], b1, b1 ? c->boot_cheb[j + 1] : 0.0, sig, 0);
-    ct_free(a1); ct_free(b1);
+  for (int j = 1; j < n; ++j) {
+    orc_ct* a1 = ct_copy(c, T[j], lv);
+    orc_ct* t = op_lincomb(c, a1, cf[j], NULL, 0.0, scale, 0);
+    ct_free(a1);
     if (!acc) {
       acc = t;
     } else {
-      orc_ct* s = op_add(c, acc, t, 0);
-      ct_free(acc); ct_free(t);
-      acc = s;
+      orc_ct* s2 = op_add(c, acc, t, 0);
+      ct_free(acc);
+      ct_free(t);
+      acc = s2;
     }
   }
-  rescale_inplace(c, acc);
-  acc->scale = delta;
-  op_add_const_inplace(c, acc, c->boot_cheb[0]);
-  for (int j = 0; j <= deg; ++j) { ct_free(T[j]); ct_free(T2[j]); }
+  return acc;
+}
+
+/* sum_{j < 2^m} cf[j] T_j with scale exactly 'target'; baby steps below B,
+   their deepest level lb; a node of 2^m terms ends at level lb - 1 - (m - log2 B) */
+static orc_ct* cheb_node(orc_ctx* c, orc_ct** T, int B, int lb, const double* cf, int m, double target) {
+  int n = 1 << m;
+  if (n <= B) {
+    double pre = target * (double)c->mod[lb];
+    orc_ct* acc = cheb_combination(c, T, cf, n, lb, pre);
+    rescale_inplace(c, acc);
+    acc->scale = target;
+    op_add_const_inplace(c, acc, cf[0]);
+    return acc;
+  }
+  int h = n / 2;
+  double* q = (double*)xcalloc(h, sizeof(double));
+  double* r = (double*)xcalloc(h, sizeof(double));
+  q[0] = cf[h];
+  r[0] = cf[0];
+  for (int j = 1; j < h; ++j) {
+    q[j] = 2.0 * cf[h + j];
+    r[j] = cf[j] - cf[2 * h - j];
+  }
+  int mb = 0;
+  while ((1 << mb) < B) ++mb;
+  int lq = lb - 1 - (m - 1 - mb);           /* level of the children */
+  double tq = target * (double)c->mod[lq];
+  tq = tq / T[h]->scale;
+  orc_ct* qc = cheb_node(c, T, B, lb, q, m - 1, tq);
+  orc_ct* g = ct_copy(c, T[h], lq);
+  orc_ct3* t3 = op_tensor(c, qc, g);
+  orc_ct* A;
+  if (h <= B) {
+    A = cheb_combination(c, T, r, h, lq, t3->scale);
+  } else {
+    orc_ct* rc = cheb_node(c, T, B, lb, r, m - 1, ldexp(1.0, c->log_scale));
+    A = op_lincomb(c, rc, 1.0, NULL, 0.0, t3->scale, 0);
+    ct_free(rc);
+  }
+  op_add3_ct_inplace(c, t3, A);
+  orc_ct* out = op_relin3(c, t3);
+  rescale_inplace(c, out);
+  out->scale = target;
+  if (h <= B) op_add_const_inplace(c, out, r[0]);
+  ct_free(qc); ct_free(g); ct_free(A); ct3_free(t3);
+  free(q); free(r);
+  return out;
+}
+
+/* T_j by the product rules above */
+static void cheb_basis_step(orc_ctx* c, orc_ct** T, orc_ct** T2, int j) {
+  int a = 1;
+  while (2 * a < j) a *= 2;
+  int b = j - a;
+  if (b == a) {
+    orc_ct* P = op_square_exact(c, T[a]);
+    T[j] = op_double(c, P);
+    ct_free(P);
+    op_add_const_inplace(c, T[j], -1.0);
+  } else {
+    if (!T2[a]) T2[a] = op_double(c, T[a]);
+    orc_ct3* t3 = op_tensor(c, T2[a], T[b]);
+    orc_ct* lo = ct_copy(c, T[a - b], t3->level);
+    orc_ct* A = op_lincomb(c, lo, -1.0, NULL, 0.0, t3->scale, 0);
+    op_add3_ct_inplace(c, t3, A);
+    T[j] = op_relin3(c, t3);
+    rescale_inplace(c, T[j]);
+    ct3_free(t3); ct_free(lo); ct_free(A);
+  }
+}
+
+static orc_ct* eval_mod(orc_ctx* c, const orc_ct* u) {
+  double delta = ldexp(1.0, c->log_scale);
+  int deg = c->boot_deg;
+  int k = 0;
+  while ((1 << k) < deg + 1) ++k;
+  int mb = (k + 1) / 2;
+  if (mb < 1) mb = 1;
+  int B = 1 << mb;
+  orc_ct** T = (orc_ct**)xcalloc(deg + 2, sizeof(orc_ct*));
+  orc_ct** T2 = (orc_ct**)xcalloc(deg + 2, sizeof(orc_ct*));
+  T[1] = ct_copy(c, u, u->level);
+  for (int j = 2; j < B; ++j) cheb_basis_step(c, T, T2, j);
+  for (int h = B; h < (1 << k); h *= 2) cheb_basis_step(c, T, T2, h);
+  int lb = B > 2 ? T[B - 1]->level : T[1]->level;
+  orc_ct* acc = cheb_node(c, T, B, lb, c->boot_cheb, k, delta);
+  for (int j = 0; j <= deg + 1; ++j) { ct_free(T[j]); ct_free(T2[j]); }
   free(T); free(T2);
   for (int i = 0; i < c->boot_r; ++i) {
     orc_ct* P = op_square_exact(c, acc);

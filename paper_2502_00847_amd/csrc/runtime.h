@@ -307,6 +307,11 @@ class Builder {
   std::vector<CT> boot_transform(const std::vector<CT>& in, bool inverse);
   std::vector<CT> eval_mod(const std::vector<CT>& u);
   std::vector<CT> relin(const std::vector<Deg2>& xs);        // relinearise, no rescale
+  void cheb_basis_step(std::vector<std::vector<CT>>& T, std::vector<std::vector<CT>>& T2, int j);
+  std::vector<CT> cheb_combination(const std::vector<std::vector<CT>>& T, const double* cf, int nt, int lv,
+                                   const std::vector<double>& scale);
+  std::vector<CT> cheb_node(const std::vector<std::vector<CT>>& T, int B, int lb, const double* cf, int m,
+                            const std::vector<double>& target);
   std::vector<CT> square_exact(const std::vector<CT>& xs);   // relinearise, then rescale
   std::vector<CT> bootstrap(const std::vector<CT>& in);
   std::vector<CT> bootstrap_chunk(const std::vector<CT>& in);

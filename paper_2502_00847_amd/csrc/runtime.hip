@@ -1506,16 +1506,207 @@ std::vector<CT> Builder::square_exact(const std::vector<CT>& xs) {
   return p;
 }
 
-// EvalMod on u = x / (K+1) (Han-Ki 2020): Chebyshev basis T_1 = u,
-//   T_2a    = 2 T_a^2 - 1           (square, doubled, constant subtracted),
-//   T_(a+b) = 2 T_a T_b - T_(a-b)   (b < a, a the largest power of two below
-//             a+b: (2 T_a) (x) T_b plus -T_(a-b) at the product's scale, one
-//             relinearise-and-rescale),
-// p = sum_j c_j T_j accumulated at the level of T_deg with scale Delta q (one
-// rescale to Delta), then r double angles y <- 2 y^2 - 1.  Every product is
-// relinearised and then rescaled by exact rounding: the merged
-// relinearise-and-rescale rounds through an approximate conversion whose error
-// (up to (alpha + 1) / 2 per coefficient) the double angles would amplify.
+// EvalMod on u = x / (K+1) (Han-Ki 2020): p(u) = sum_j c_j T_j(u), the
+// Chebyshev interpolant of cos(2 pi ((K+1) u - 1/4) / 2^r), then r double
+// angles y <- 2 y^2 - 1.  p runs baby-step giant-step in the Chebyshev basis:
+// baby steps T_1 .. T_(B-1) (B = 2^ceil(k/2), degree 2^k - 1), giant steps
+// T_B .. T_(2^(k-1)); a node of degree < 2h splits by Chebyshev division into
+// r + T_h q (q_0 = c_h, q_j = 2 c_(h+j), r_0 = c_0, r_j = c_j - c_(2h-j)),
+// recursively down to combinations of the baby steps: one product per split,
+// 11 products for degree 31, depth k + 1.  Every node lands exactly on the
+// scale its parent needs; an r child made of baby steps is added, unrescaled,
+// at the product's scale before relinearising and its constant after.  Basis
+// products: T_2a = 2 T_a^2 - 1 (square, doubled, constant subtracted) and
+// T_(a+b) = 2 T_a T_b - T_(a-b) ((2 T_a) (x) T_b plus -T_(a-b) at the
+// product's scale).  Every product is relinearised and then rescaled by exact
+// rounding: the merged relinearise-and-rescale rounds through an approximate
+// conversion whose error (up to (alpha + 1) / 2 per coefficient) the double
+// angles would amplify.
+
+// T_j for every item by the product rules
+void Builder::cheb_basis_step(std::vector<std::vector<CT>>& T, std::vector<std::vector<CT>>& T2, int j) {
+  const size_t n = T[1].size();
+  int a = 1;
+  while (2 * a < j) a *= 2;
+  const int b = j - a;
+  const size_t mark = scratch_mark();
+  if (b == a) {
+    std::vector<CT> P = square_exact(T[a]);
+    if (err_code) return;
+    std::vector<LinItem> li;
+    for (size_t i = 0; i < n; ++i) {
+      LinItem t{};
+      t.a = P[i];
+      t.va = 2.0;
+      t.target = P[i].scale;
+      li.push_back(t);
+    }
+    std::vector<CT> P2 = lincomb(li, false);
+    if (err_code) return;
+    for (CT& v : P) free_ct(v);
+    T[j] = add_const(P2, std::vector<double>(n, -1.0));
+    if (err_code) return;
+    for (CT& v : P2) free_ct(v);
+  } else {
+    if (T2[a].empty()) {
+      std::vector<LinItem> li;
+      for (size_t i = 0; i < n; ++i) {
+        LinItem t{};
+        t.a = T[a][i];
+        t.va = 2.0;
+        t.target = T[a][i].scale;
+        li.push_back(t);
+      }
+      T2[a] = lincomb(li, false);
+      if (err_code) return;
+    }
+    std::vector<LinItem> la;
+    for (size_t i = 0; i < n; ++i) {
+      LinItem t{};
+      t.a = T[a - b][i];
+      t.a.level = T2[a][i].level;
+      t.a.slot = -1;
+      t.va = -1.0;
+      t.target = T2[a][i].scale * T[b][i].scale;
+      la.push_back(t);
+    }
+    std::vector<CT> A = lincomb(la, false);
+    if (err_code) return;
+    std::vector<TensorItem> ti;
+    for (size_t i = 0; i < n; ++i) {
+      TensorItem t{};
+      t.a = T2[a][i];
+      t.b = T[b][i];
+      t.f = A[i];
+      t.has_f = true;
+      ti.push_back(t);
+    }
+    std::vector<Deg2> d = tensor2(ti);
+    if (err_code) return;
+    T[j] = relin(d);
+    if (err_code) return;
+    rescale(T[j]);
+    if (err_code) return;
+    for (CT& v : A) free_ct(v);
+  }
+  scratch_release(mark);
+}
+
+// sum_{0 < j < nt} cf[j] T_j, every T_j lowered to level lv, at scale 'scale' (not rescaled)
+std::vector<CT> Builder::cheb_combination(const std::vector<std::vector<CT>>& T, const double* cf, int nt, int lv,
+                                          const std::vector<double>& scale) {
+  const size_t n = T[1].size();
+  std::vector<CT> acc;
+  for (int j = 1; j < nt; ++j) {
+    std::vector<LinItem> li;
+    for (size_t i = 0; i < n; ++i) {
+      LinItem t{};
+      t.a = T[j][i];
+      t.a.level = lv;
+      t.a.slot = -1;
+      t.va = cf[j];
+      t.target = scale[i];
+      if (!acc.empty()) { t.b = acc[i]; t.vb = 1.0; t.has_b = true; }
+      li.push_back(t);
+    }
+    std::vector<CT> nx = lincomb(li, false);
+    if (err_code) return {};
+    for (CT& v : acc) free_ct(v);
+    acc = nx;
+  }
+  return acc;
+}
+
+// sum_{j < 2^m} cf[j] T_j with scale exactly target[i]; baby steps below B at
+// deepest level lb; a node of 2^m terms ends at level lb - 1 - (m - log2 B)
+std::vector<CT> Builder::cheb_node(const std::vector<std::vector<CT>>& T, int B, int lb, const double* cf, int m,
+                                   const std::vector<double>& target) {
+  const size_t n = T[1].size();
+  const int nt = 1 << m;
+  if (nt <= B) {
+    std::vector<double> pre(n);
+    for (size_t i = 0; i < n; ++i) pre[i] = target[i] * (double)C.mod[lb];
+    std::vector<CT> acc = cheb_combination(T, cf, nt, lb, pre);
+    if (err_code) return {};
+    const size_t mark = scratch_mark();
+    rescale(acc);
+    scratch_release(mark);
+    if (err_code) return {};
+    for (size_t i = 0; i < n; ++i) acc[i].scale = target[i];
+    std::vector<CT> out = add_const(acc, std::vector<double>(n, cf[0]));
+    if (err_code) return {};
+    for (CT& v : acc) free_ct(v);
+    return out;
+  }
+  const int h = nt / 2;
+  std::vector<double> q(h), r(h);
+  q[0] = cf[h];
+  r[0] = cf[0];
+  for (int j = 1; j < h; ++j) {
+    q[j] = 2.0 * cf[h + j];
+    r[j] = cf[j] - cf[2 * h - j];
+  }
+  int mb = 0;
+  while ((1 << mb) < B) ++mb;
+  const int lq = lb - 1 - (m - 1 - mb);
+  std::vector<double> tq(n);
+  for (size_t i = 0; i < n; ++i) {
+    tq[i] = target[i] * (double)C.mod[lq];
+    tq[i] = tq[i] / T[h][i].scale;
+  }
+  std::vector<CT> qc = cheb_node(T, B, lb, q.data(), m - 1, tq);
+  if (err_code) return {};
+  std::vector<double> sig(n);
+  for (size_t i = 0; i < n; ++i) sig[i] = qc[i].scale * T[h][i].scale;
+  std::vector<CT> A;
+  if (h <= B) {
+    A = cheb_combination(T, r.data(), h, lq, sig);
+  } else {
+    std::vector<CT> rc = cheb_node(T, B, lb, r.data(), m - 1, std::vector<double>(n, ldexp(1.0, C.log_scale)));
+    if (err_code) return {};
+    std::vector<LinItem> li;
+    for (size_t i = 0; i < n; ++i) {
+      LinItem t{};
+      t.a = rc[i];
+      t.va = 1.0;
+      t.target = sig[i];
+      li.push_back(t);
+    }
+    A = lincomb(li, false);
+    for (CT& v : rc) free_ct(v);
+  }
+  if (err_code) return {};
+  const size_t mark = scratch_mark();
+  std::vector<TensorItem> ti;
+  for (size_t i = 0; i < n; ++i) {
+    TensorItem t{};
+    t.a = qc[i];
+    t.b = T[h][i];
+    t.b.level = lq;
+    t.b.slot = -1;
+    t.f = A[i];
+    t.has_f = true;
+    ti.push_back(t);
+  }
+  std::vector<Deg2> d = tensor2(ti);
+  if (err_code) return {};
+  std::vector<CT> out = relin(d);
+  if (err_code) return {};
+  rescale(out);
+  if (err_code) return {};
+  scratch_release(mark);
+  for (size_t i = 0; i < n; ++i) out[i].scale = target[i];
+  for (CT& v : qc) free_ct(v);
+  for (CT& v : A) free_ct(v);
+  if (h <= B) {
+    std::vector<CT> o2 = add_const(out, std::vector<double>(n, r[0]));
+    if (err_code) return {};
+    for (CT& v : out) free_ct(v);
+    out = o2;
+  }
+  return out;
+}
+
 std::vector<CT> Builder::eval_mod(const std::vector<CT>& us) {
   const size_t n = us.size();
   const int deg = C.boot_deg;
@@ -1527,128 +1718,26 @@ std::vector<CT> Builder::eval_mod(const std::vector<CT>& us) {
     if (u.level != us[0].level) { fail(-1, "eval_mod: inputs must share the level"); return {}; }
     if (u.level - k - 1 - C.boot_r < 0) { fail(-3, "eval_mod: not enough levels"); return {}; }
   }
-  std::vector<std::vector<CT>> T(deg + 1, std::vector<CT>(n)), T2(deg + 1, std::vector<CT>(n));
-  std::vector<char> owned(deg + 1, 0), have2(deg + 1, 0);
+  int mb = (k + 1) / 2;
+  if (mb < 1) mb = 1;
+  const int B = 1 << mb;
+  std::vector<std::vector<CT>> T(deg + 2), T2(deg + 2);
   T[1] = us;
-  std::vector<CT> acc;
-  // T_j sits at level l - ceil(log2 j); the sum is formed at the level of T_deg
-  const int ld = us[0].level - k;
-  const double sig = delta * (double)C.mod[ld];
-  const int half = 1 << (k - 1);
-  // c_j T_j (lowered to the level of T_deg) added into the accumulator; T_j of
-  // the top octave are needed by nothing else and are freed right away
-  auto accumulate = [&](int j) {
-    std::vector<LinItem> li;
-    for (size_t i = 0; i < n; ++i) {
-      LinItem t{};
-      t.a = T[j][i];
-      t.a.level = ld;
-      t.a.slot = -1;
-      t.va = C.boot_cheb[j];
-      t.target = sig;
-      if (!acc.empty()) { t.b = acc[i]; t.vb = 1.0; t.has_b = true; }
-      li.push_back(t);
-    }
-    std::vector<CT> nx = lincomb(li, false);
-    if (err_code) return;
-    for (CT& v : acc) free_ct(v);
-    acc = nx;
-  };
-  for (int j = 2; j <= deg; ++j) {
-    int a = 1;
-    while (2 * a < j) a *= 2;
-    const int b = j - a;
-    const size_t mark = scratch_mark();
-    if (b == a) {
-      std::vector<CT> P = square_exact(T[a]);
-      if (err_code) return {};
-      std::vector<LinItem> li;
-      for (size_t i = 0; i < n; ++i) {
-        LinItem t{};
-        t.a = P[i];
-        t.va = 2.0;
-        t.target = P[i].scale;
-        li.push_back(t);
-      }
-      std::vector<CT> P2 = lincomb(li, false);
-      if (err_code) return {};
-      for (CT& v : P) free_ct(v);
-      T[j] = add_const(P2, std::vector<double>(n, -1.0));
-      if (err_code) return {};
-      for (CT& v : P2) free_ct(v);
-    } else {
-      if (!have2[a]) {
-        std::vector<LinItem> li;
-        for (size_t i = 0; i < n; ++i) {
-          LinItem t{};
-          t.a = T[a][i];
-          t.va = 2.0;
-          t.target = T[a][i].scale;
-          li.push_back(t);
-        }
-        T2[a] = lincomb(li, false);
-        if (err_code) return {};
-        have2[a] = 1;
-      }
-      std::vector<LinItem> la;
-      for (size_t i = 0; i < n; ++i) {
-        LinItem t{};
-        t.a = T[a - b][i];
-        t.a.level = T2[a][i].level;
-        t.a.slot = -1;
-        t.va = -1.0;
-        t.target = T2[a][i].scale * T[b][i].scale;
-        la.push_back(t);
-      }
-      std::vector<CT> A = lincomb(la, false);
-      if (err_code) return {};
-      std::vector<TensorItem> ti;
-      for (size_t i = 0; i < n; ++i) {
-        TensorItem t{};
-        t.a = T2[a][i];
-        t.b = T[b][i];
-        t.f = A[i];
-        t.has_f = true;
-        ti.push_back(t);
-      }
-      std::vector<Deg2> d = tensor2(ti);
-      if (err_code) return {};
-      T[j] = relin(d);
-      if (err_code) return {};
-      rescale(T[j]);
-      if (err_code) return {};
-      for (CT& v : A) free_ct(v);
-    }
-    scratch_release(mark);
-    owned[j] = 1;
-    if (j > half) {
-      // the top octave is needed by nothing but the sum
-      accumulate(j);
-      if (err_code) return {};
-      for (CT& v : T[j]) free_ct(v);
-      owned[j] = 0;
-    }
-  }
-  for (int j = 1; j <= half && j <= deg; ++j) {
-    accumulate(j);
+  for (int j = 2; j < B; ++j) {
+    cheb_basis_step(T, T2, j);
     if (err_code) return {};
   }
-  for (int j = 2; j <= deg; ++j)
-    if (owned[j])
-      for (CT& v : T[j]) free_ct(v);
-  for (int j = 1; j <= deg; ++j)
-    if (have2[j])
-      for (CT& v : T2[j]) free_ct(v);
-  {
-    const size_t mark = scratch_mark();
-    rescale(acc);
-    scratch_release(mark);
+  for (int h = B; h < (1 << k); h *= 2) {
+    cheb_basis_step(T, T2, h);
     if (err_code) return {};
   }
-  for (CT& v : acc) v.scale = delta;
-  std::vector<CT> y = add_const(acc, std::vector<double>(n, C.boot_cheb[0]));
+  const int lb = B > 2 ? T[B - 1][0].level : T[1][0].level;
+  std::vector<CT> y = cheb_node(T, B, lb, C.boot_cheb.data(), k, std::vector<double>(n, delta));
   if (err_code) return {};
-  for (CT& v : acc) free_ct(v);
+  for (int j = 2; j <= deg + 1; ++j)
+    for (CT& v : T[j]) free_ct(v);
+  for (int j = 1; j <= deg + 1; ++j)
+    for (CT& v : T2[j]) free_ct(v);
   for (int i = 0; i < C.boot_r; ++i) {
     const size_t mark = scratch_mark();
     std::vector<CT> P = square_exact(y);
