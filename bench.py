@@ -442,6 +442,7 @@ def main():
     ap.add_argument("--keyswitch", type=int, default=1, help="time 64 random-step rotations at 24 limbs")
     ap.add_argument("--calib", type=int, default=0, help="copy 1 GiB first (counter calibration kernel)")
     ap.add_argument("--variants", type=int, default=1, help="precise-Sign and large-n single-query runs")
+    ap.add_argument("--ntt-only", type=int, default=0, help="only the NTT microbenchmark (64 x 2 x 24 limbs)")
     ap.add_argument("--boot-only", type=int, default=0,
                     help="only the bootstrapping run (its timed batch between marker fills of 28672 and 36864 doubles)")
     args = ap.parse_args()
@@ -457,6 +458,11 @@ def main():
 
     if args.boot_only:
         print(json.dumps({"bootstrapping": bootstrap_rate()}), flush=True)
+        return
+    if args.ntt_only:
+        g = Context(W.PARAMS["full"])
+        g.keygen(W.KEYGEN_SEED, [])
+        print(json.dumps({"ntt": ntt_rate(g, W.PARAMS["full"])}), flush=True)
         return
     params = W.PARAMS["full"]
     if args.calib:
@@ -625,6 +631,14 @@ def main():
     if args.serve:
         _log(f"serving run: {args.serve} requests, Poisson arrivals at 0.7x the saturated rate")
         result["serving"] = serve(g, args.serve, max(8, args.serve // 8))
+        sat = result["serving"]["saturated_argmax_per_s"]
+        sweep = []
+        for frac in (0.25, 0.5, 0.9):
+            r = serve(g, max(40, args.serve // 2), max(8, args.serve // 16), qps=frac * sat)
+            r["load"] = frac
+            sweep.append(r)
+        result["serving_sweep"] = {"what": "the same mix at fractions of the saturated rate", "runs": sweep}
+        _log(f"serving sweep: {[(r['load'], r['p50_ms'], r['p99_ms']) for r in sweep]}")
     if args.cpu:
         # key switches per query from the counters of one chunk
         ks_total = 0
