@@ -167,6 +167,7 @@ typedef struct {
   int dg, df;
   int min_level;
   int refresh_level;    /* level a refreshed ciphertext is re-encrypted at */
+  int refresh_level_set; /* the level the parameters asked for */
   int secret_h;         /* > 0: sparse secret, each coefficient nonzero w.p. h/N */
   int boot_mode;        /* 1: refreshes are bootstraps */
   int boot_K, boot_r, boot_deg, boot_ratio, boot_groups;
@@ -257,6 +258,7 @@ ORC_API void* orc_create(int log_n, int n_q, int q_bits, int n_p, int p_bits, in
   c->min_level = min_level;
   c->refresh_level = (refresh_level <= 0 || refresh_level > n_q - 1) ? n_q - 1 : refresh_level;
   c->boot_out_level = -1;
+  c->refresh_level_set = c->refresh_level;
   int np = n_q + n_p, n = c->n;
   c->mod = (uint64_t*)xcalloc(np, sizeof(uint64_t));
   make_primes(c, q_bits, p_bits);
@@ -2242,6 +2244,7 @@ ORC_API void* orc_bootstrap(void* h, const void* x) { return bootstrap((orc_ctx*
 ORC_API int orc_set_boot(void* h, int secret_h, int K, int r, int deg, int ratio, int groups, int mode) {
   orc_ctx* c = (orc_ctx*)h;
   c->secret_h = secret_h;
+  if (c->boot_mode) c->refresh_level = c->refresh_level_set;
   if (K <= 0) { c->boot_out_level = -1; c->boot_mode = 0; return -1; }
   if (deg < 1 || ((deg + 1) & deg) || r < 0 || groups < 1 || ratio < 1) die("bad bootstrapping parameters");
   c->boot_K = K; c->boot_r = r; c->boot_deg = deg; c->boot_ratio = ratio; c->boot_groups = groups;
@@ -2249,7 +2252,7 @@ ORC_API int orc_set_boot(void* h, int secret_h, int K, int r, int deg, int ratio
   c->boot_cheb = (double*)xcalloc(deg + 1, sizeof(double));
   boot_cheb_coeffs(K, r, deg, c->boot_cheb);
   int out = c->n_q - 1 - boot_levels(c);
-  if (out < c->min_level) { c->boot_out_level = -1; c->boot_mode = 0; return -1; }
+  if (out < c->min_level) { c->boot_out_level = -1; c->boot_mode = 0; c->refresh_level = c->refresh_level_set; return -1; }
   c->boot_out_level = out;
   c->boot_mode = mode;
   if (mode) c->refresh_level = out;

@@ -1429,6 +1429,7 @@ extern "C" int secpe_set_boot(secpe_ctx* x, const secpe_boot_params* bp, int* ou
   c.boot_mono = nullptr;
   c.boot_mode = 0;
   c.boot_out_level = -1;
+  c.refresh_level = c.refresh_level_set;
   if (out_level) *out_level = -1;
   if (bp->K <= 0) return 0;
   if (bp->deg < 1 || ((bp->deg + 1) & bp->deg) || bp->r < 0 || bp->groups < 1 || bp->groups > c.log_n - 1 ||
@@ -1660,9 +1661,10 @@ extern "C" int secpe_op_boot_step(secpe_ctx* x, int step, const secpe_ct* a, voi
   CHECK_CTX(x);
   if (!a || !a->data) return set_err(SECPE_EINVAL, "null input");
   if (step < 0 || step > 5) return set_err(SECPE_EINVAL, "unknown bootstrapping step");
-  if ((step >= 1 && step <= 4 && step != 4) && !x->c.boot_ready)
+  // the linear transforms and the monomials need secpe_boot_setup; EvalMod the parameters
+  if ((step == 1 || step == 2 || step == 4 || step == 5) && !x->c.boot_ready)
     return set_err(SECPE_EINVAL, "bootstrapping is not set up (secpe_boot_setup)");
-  if ((step == 4 || step == 5) && !x->c.boot_mono) return set_err(SECPE_EINVAL, "bootstrapping is not set up");
+  if (step == 3 && x->c.boot_out_level < 0) return set_err(SECPE_EINVAL, "bootstrapping is not configured");
   return op_to_out(x, ws, ws_bytes, out, [&](Builder& b) -> std::vector<CT> {
     const std::vector<CT> v{to_ct(a)};
     switch (step) {

@@ -80,6 +80,7 @@ struct Ctx {
   int modup_eg = 4;
   int q_bits = 0, p_bits = 0, log_scale = 0, dg = 2, df = 2, min_level = 1;
   int refresh_level = 0;   // level a refreshed ciphertext is re-encrypted at
+  int refresh_level_set = 0;  // the level the parameters asked for (bootstrapping may override it)
   // bootstrapping (secpe_set_boot, secpe_boot_setup)
   int secret_h = 0;        // > 0: sparse secret of expected Hamming weight h
   int boot_mode = 0;       // 1: refreshes are bootstraps

@@ -107,6 +107,7 @@ int build_context(Ctx& c, int log_n, int n_q, int q_bits, int n_p, int p_bits, i
   c.df = df;
   c.min_level = min_level;
   c.refresh_level = (refresh_level <= 0 || refresh_level > n_q - 1) ? n_q - 1 : refresh_level;
+  c.refresh_level_set = c.refresh_level;
   c.device = device;
   c.stream = stream;
   c.mod = choose_primes(log_n, n_q, q_bits, n_p, p_bits);
