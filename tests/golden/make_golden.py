@@ -6,7 +6,8 @@ coefficient domain (canonical residues, uint64 little-endian, [2][level+1][N]),
 its level and scale, the decrypted z and the operation counts.  The GPU parity
 test recomputes the same digest from the HIP path.
 
-Cases: config 1 (toy N=2^13, 8 x 30-bit primes, K=4, C=2) and config 2
+Cases: config 1 (toy N=2^13, 8 x 30-bit primes, K=4, C=2; and on 36 primes,
+alpha = 4, with no refresh at all) and config 2
 (N=2^16, 24 x 50-bit primes, dnum 3, K=8, C=4, margin >= 0.05), plus one
 config-3 query.  Run from the repository root: python tests/golden/make_golden.py
 """
@@ -27,6 +28,8 @@ OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "argmax_digests.j
 CASES = [
     # name, parameter set, workload config id, query index, rotation keys for (k_max, c_max)
     ("config1_toy", "toy", 1, 0, (4, 2)),
+    # config 1 on a 36-prime chain: the whole of Algorithm 1 without a refresh
+    ("config1_toy_deep", "toy_deep", 1, 0, (4, 2)),
     ("config2_full", "full", 2, 0, (16, 14)),
     ("config3_full_q0", "full", 3, 0, (16, 14)),
 ]

@@ -159,6 +159,27 @@ def test_toy_argmax_matches_oracle_digest(golden):
     assert idx == sim.t0_argmax(d["logits"])[0]
 
 
+def test_toy_deep_argmax_without_refresh(golden):
+    """Config 1 on a 36-prime chain (alpha = 4, dnum = 9): the whole of Algorithm 1
+    non-interactively, no refresh, bit-identical to the oracle."""
+    from paper_2502_00847_amd.secpe import Context
+    rec = golden["config1_toy_deep"]
+    g = Context(W.PARAMS["toy_deep"])
+    g.keygen(W.KEYGEN_SEED, g.argmax_steps(4, 2))
+    g.set_refresh_key(None)
+    d = W.query(1, 0)
+    ct = g.encrypt(d["logits"], d["encrypt_seed"])
+    z = g.eval_argmax(ct, d["K"], d["C"], d["d_min"], d["d_max"], d["refresh_seed"])
+    assert z.level == rec["level"] and z.scale == rec["scale"]
+    assert _digest(g.export(z)) == rec["output_sha256"]
+    cnt = g.counters()
+    assert cnt["refresh"] == 0 == rec["counters"]["refresh"]
+    for k in ("sign", "rotate", "relin", "key_switch", "max"):
+        assert cnt[k] == rec["counters"][k], k
+    zz, idx = g.decrypt(z, 2)
+    assert idx == sim.t0_argmax(d["logits"])[0]
+
+
 def test_config3_batch_indices_and_bit_identity(full_gpu):
     """256 queries with uneven (K, C) in batched launches: every decrypted index
     equals the plaintext argmax when the normalised top-2 margin is at least

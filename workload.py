@@ -24,6 +24,9 @@ PARAMS = {
     # N=2^16 with 3 special primes (dnum = 8 digits)
     "full_a3": dict(log_n=16, n_q=24, q_bits=50, n_p=3, p_bits=51, log_scale=50, dg=2, df=2, min_level=1,
                     refresh_level=14),
+    # config 1 without any refresh: the whole of Algorithm 1 for C' = 2 on a
+    # 36-prime chain (alpha = 4, dnum = 9), non-interactively
+    "toy_deep": dict(log_n=13, n_q=36, q_bits=30, n_p=4, p_bits=51, log_scale=30, dg=2, df=2, min_level=1),
     # small parameter sets for fast unit tests
     "tiny": dict(log_n=10, n_q=8, q_bits=40, n_p=2, p_bits=51, log_scale=40, dg=2, df=2, min_level=1),
     # tiny with refreshes re-encrypting below the top level
