@@ -389,6 +389,12 @@ def bootstrap_rate(n_batch=8, n_queries=32):
     tb = time.perf_counter() - ta
     cntb = g.counters()
     ok = sum(int(g.decrypt(z, q["C"])[1] == sim_t0(q["logits"])[0]) for z, q in zip(zo, qs))
+    # the same 256 config-3 queries slot-packed: one bootstrap refreshes 128 queries
+    del ws
+    qs256 = [W.query(3, i) for i in range(256)]
+    out["argmax_config3_packed"] = packed_rate(g, qs256)
+    out["argmax_config3_packed"]["bootstraps"] = g.counters()["refresh"]
+    _log(f"packed argmax with bootstrapping: {out['argmax_config3_packed']}")
     out["argmax_config2"] = {"ms": round(ms2, 2), "bootstraps": cnt["refresh"],
                              "index_ok": bool(idx2 == sim_t0(d2["logits"])[0])}
     out["argmax_config3_batch"] = {"queries": n_queries, "argmax_per_s": round(n_queries / tb, 2),

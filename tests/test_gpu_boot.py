@@ -128,6 +128,28 @@ def test_argmax_with_bootstrapping_bit_exact(pair):
     assert np.abs(z - sim.t1_argmax(y, lo, hi, g.slots)[:C]).max() < 1e-3
 
 
+def test_packed_argmax_with_bootstrapping_bit_exact(pair):
+    """Slot-packed Argmax (Sec. 3.2) refreshing by bootstrapping: every block of
+    the ciphertext is bootstrapped at once; bits equal the oracle's."""
+    g, o = pair
+    shapes = [(2, 3), (3, 4), (1, 2)]
+    blocks = [W.logits(9, 900 + i, K, C) for i, (K, C) in enumerate(shapes)]
+    lo = [W.d_bounds(K)[0] for K, _ in shapes]
+    hi = [W.d_bounds(K)[1] for K, _ in shapes]
+    oc = o.encrypt_packed(blocks, 91)
+    gc = g.encrypt_packed(blocks, 91)
+    _same(g, gc, oc)
+    o.reset_counters()
+    zo = o.eval_argmax_packed(oc, shapes, lo, hi, 92)
+    [zg] = g.eval_argmax_packed([gc], [shapes], lo, hi, [92])
+    _same(g, zg, zo)
+    assert o.counters()["refresh"] >= 1
+    for (zb, idx), y, l, h in zip(g.decrypt_packed(zg, shapes), blocks, lo, hi):
+        i0, _, margin = sim.t0_argmax(y)
+        if margin / (h - l) >= 2.0**-10:
+            assert idx == i0
+
+
 def test_bootstrap_errors_are_reported(pair):
     from paper_2502_00847_amd.secpe import SecpeError
     g, o = pair
