@@ -2185,13 +2185,19 @@ static int boot_levels(orc_ctx* c) {
 
 /* the linear transforms: all groups of one direction, each at the level below
    the previous (targets Delta) */
+/* output scale of group g: CoeffToSlot keeps 2^5 Delta until its last group
+   (its first groups carry the large ModRaise overflow, so their plaintexts
+   get the larger scale), everything else Delta */
+static double boot_group_target(orc_ctx* c, int inverse, int g) {
+  if (inverse && g < c->boot_groups - 1) return ldexp(1.0, c->log_scale + 5);
+  return ldexp(1.0, c->log_scale);
+}
 static orc_ct* boot_transform(orc_ctx* c, const orc_ct* x, int inverse) {
-  double delta = ldexp(1.0, c->log_scale);
   orc_ct* y = ct_copy(c, x, x->level);
   int l0 = x->level;
   for (int g = 0; g < c->boot_groups; ++g) {
     boot_group G = boot_make_group(c, inverse, g, l0 - g);
-    orc_ct* t = boot_apply_group(c, &G, g, y, delta);
+    orc_ct* t = boot_apply_group(c, &G, g, y, boot_group_target(c, inverse, g));
     dm_free(&G.M);
     ct_free(y);
     y = t;

@@ -1408,8 +1408,11 @@ static void boot_plan(Ctx& c) {
       G.delta = t.delta;
       G.n1 = t.n1;
       G.E = t.E;
-      G.in_scale = g == 0 ? s0 : delta;
-      double ps = delta * (double)c.mod[G.level];
+      // CoeffToSlot keeps 2^5 Delta until its last group: its first groups
+      // carry the large ModRaise overflow, so their plaintexts get the larger scale
+      G.out_scale = (inv && g < c.boot_groups - 1) ? ldexp(1.0, c.log_scale + 5) : delta;
+      G.in_scale = g == 0 ? s0 : (inv ? c.boot_cts : c.boot_stc).back().out_scale;
+      double ps = G.out_scale * (double)c.mod[G.level];
       ps = ps / G.in_scale;
       G.pscale = ps;
       (inv ? c.boot_cts : c.boot_stc).push_back(G);

@@ -51,7 +51,7 @@ struct Ctx;
 // -delta n1 floor(e / n1) and encoded for an input of scale in_scale at 'level'
 struct BootGroup {
   int inverse = 0, g = 0, level = 0, delta = 0, n1 = 0, E = 0;
-  double in_scale = 0.0, pscale = 0.0;
+  double in_scale = 0.0, pscale = 0.0, out_scale = 0.0;
   std::vector<int64_t> e;          // centred offset multiple of each diagonal
   std::vector<const double*> pt;   // NTT domain, limbs 0..level
 };

@@ -1321,12 +1321,11 @@ std::vector<CT> Builder::mul_monomial_half(const std::vector<CT>& in, bool neg) 
 static int64_t fdiv(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
 // all groups of one direction; group g: out = sum_G RotL(sum_b pt_{G,b} * RotL(x, delta b), delta n1 G),
-// rescaled once, scale := Delta.  Inner sums are accumulated baby step by baby
+// rescaled once, scale := the group's output scale.  Inner sums are accumulated baby step by baby
 // step, so one rotated copy of each input is alive at a time.
 std::vector<CT> Builder::boot_transform(const std::vector<CT>& in, bool inverse) {
   const std::vector<BootGroup>& groups = inverse ? C.boot_cts : C.boot_stc;
   if (groups.empty() || (!C.boot_ready && !dry)) { fail(-1, "bootstrapping is not set up"); return {}; }
-  const double delta = ldexp(1.0, C.log_scale);
   std::vector<CT> cur = in;
   bool own = false;
   for (const BootGroup& G : groups) {
@@ -1468,7 +1467,7 @@ std::vector<CT> Builder::boot_transform(const std::vector<CT>& in, bool inverse)
     rescale(nxt);
     scratch_release(mark);
     if (err_code) return {};
-    for (CT& v : nxt) v.scale = delta;
+    for (CT& v : nxt) v.scale = G.out_scale;
     if (own)
       for (CT& v : cur) free_ct(v);
     cur = nxt;
