@@ -150,6 +150,53 @@ def test_packed_argmax_with_bootstrapping_bit_exact(pair):
             assert idx == i0
 
 
+def _boot_queries(g, n):
+    qs = []
+    for i in range(n):
+        K, C = [(2, 3), (3, 4), (2, 2), (4, 3)][i % 4]
+        y = W.logits(13, i, K, C)
+        enc, ref = W.query_seeds(13, i)
+        lo, hi = W.d_bounds(K)
+        qs.append(dict(ct=g.encrypt(y, enc), K=K, C=C, d_min=lo, d_max=hi, seed=ref, y=y))
+    return qs
+
+
+def test_bootstrapping_batch_graph_and_server_match_alone(pair):
+    """With every refresh a bootstrap, a batch (eager and hipGraph replays), and
+    the continuous-batching server with staggered arrivals, all give the bits of
+    each query evaluated alone."""
+    from paper_2502_00847_amd.secpe import Server
+    g, _ = pair
+    qs = _boot_queries(g, 4)
+    alone = [g.export(g.eval_argmax(q["ct"], q["K"], q["C"], q["d_min"], q["d_max"], q["seed"])) for q in qs]
+    args = ([q["ct"] for q in qs], [q["K"] for q in qs], [q["C"] for q in qs], [q["d_min"] for q in qs],
+            [q["d_max"] for q in qs], [q["seed"] for q in qs])
+    ws = g.workspace(args[1], args[2])
+    outs = [g.new_ct() for _ in qs]
+    for a, c in zip(alone, g.eval_argmax_batch(*args, ws=ws, outs=outs)):
+        assert np.array_equal(g.export(c), a)
+    assert g.counters()["refresh"] >= len(qs)
+    for rep in range(2):
+        got = g.eval_argmax_batch(*args, ws=ws, outs=outs, graph=True)
+        g.sync()
+        for a, c in zip(alone, got):
+            assert np.array_equal(g.export(c), a)
+        g.eval_argmax(qs[0]["ct"], qs[0]["K"], qs[0]["C"], qs[0]["d_min"], qs[0]["d_max"], qs[0]["seed"])
+    srv = Server(g, 3 * g.workspace_bytes(args[1], args[2]), max_active=8)
+    tickets = {}
+    arrivals = {0: [0, 1], 2: [2], 4: [3]}
+    step = 0
+    while len(srv.results) < len(qs):
+        for i in arrivals.get(step, []):
+            q = qs[i]
+            tickets[i] = srv.submit(q["ct"], q["K"], q["C"], q["d_min"], q["d_max"], q["seed"])
+        srv.step()
+        step += 1
+        assert step < 500
+    for i, a in enumerate(alone):
+        assert np.array_equal(g.export(srv.results[tickets[i]]), a)
+
+
 def test_bootstrap_errors_are_reported(pair):
     from paper_2502_00847_amd.secpe import SecpeError
     g, o = pair
