@@ -645,6 +645,29 @@ def main():
             sweep.append(r)
         result["serving_sweep"] = {"what": "the same mix at fractions of the saturated rate", "runs": sweep}
         _log(f"serving sweep: {[(r['load'], r['p50_ms'], r['p99_ms']) for r in sweep]}")
+    # the refresh stand-in, timed on its own: refreshes in one step (counters of
+    # every chunk) and the time of one refresh of a level-1 ciphertext
+    n_ref = 0
+    for grp in groups:
+        g.eval_argmax_batch([cts[i] for i in grp], [Ks[i] for i in grp], [Cs[i] for i in grp],
+                            [qs[i]["d_min"] for i in grp], [qs[i]["d_max"] for i in grp],
+                            [qs[i]["refresh_seed"] for i in grp], ws=ws, outs=[outs[i] for i in grp])
+        g.sync()
+        n_ref += g.counters()["refresh"]
+    low = g.import_(g.export(cts[0])[:, :2, :], cts[0].scale)
+    g.refresh(low, 1, 0)
+    g.sync()
+    tr = time.perf_counter()
+    for r in range(16):
+        g.refresh(low, 1, r)
+    g.sync()
+    per_ref = (time.perf_counter() - tr) / 16
+    result["refresh"] = {"per_step": n_ref, "ms_each": round(per_ref * 1e3, 3),
+                         "share_of_step": round(n_ref * per_ref / (elapsed / args.steps), 4),
+                         "what": "the key-owner refresh (stand-in for bootstrapping): refreshes in one step, "
+                                 "one level-1 ciphertext refreshed alone, and their product over the step time "
+                                 "(an upper bound: in the step they run batched)"}
+    _log(f"refresh: {result['refresh']}")
     if args.cpu:
         # key switches per query from the counters of one chunk
         ks_total = 0
