@@ -569,31 +569,56 @@ __global__ __launch_bounds__(256) void k_inner_row(const InnerJob* __restrict__ 
   double a0x[NP], a0y[NP], a1x[NP], a1y[NP];
 #pragma unroll
   for (int q = 0; q < NP; ++q) a0x[q] = a0y[q] = a1x[q] = a1y[q] = 0.0;
+  // the key tile of a digit is requested in two halves of NP/2 pairs, each
+  // half at once (two round trips per digit, not one per pair), after the
+  // row pass so that the loads hold no registers through the transform
+  constexpr int NH = NP / 2;
   for (int j = 0; j < J.n_digits; ++j) {
-    if (j != own) fwd_row_tile<LOGS, G>(lds, CGPTR(J.ext) + ((size_t)j * J.n_ext + t) * N, row0, k1, tw, twq, m);
     cgdbl* kb = CGPTR(J.key) + (((size_t)j * 2 + 0) * n_mod + pr) * N + tile;
     cgdbl* ka = CGPTR(J.key) + (((size_t)j * 2 + 1) * n_mod + pr) * N + tile;
+    if (j != own) fwd_row_tile<LOGS, G>(lds, CGPTR(J.ext) + ((size_t)j * J.n_ext + t) * N, row0, k1, tw, twq, m);
 #pragma unroll
-    for (int q = 0; q < NP; ++q) {
-      const int i = threadIdx.x + 256 * q;
-      double xx, xy;
-      if (j == own) {
-        const double2 v = ld2(J.d, (size_t)t * N + tile + 2 * i);
-        xx = J.d_square ? canon(mul_mod(v.x, v.x, m), m) : v.x;
-        xy = J.d_square ? canon(mul_mod(v.y, v.y, m), m) : v.y;
-      } else {
-        xx = canon(lds[lpad(2 * i)], m);
-        xy = canon(lds[lpad(2 * i + 1)], m);
+    for (int h = 0; h < 2; ++h) {
+      dv2 kbv[NH], kav[NH], xv[NH];
+#pragma unroll
+      for (int r = 0; r < NH; ++r) {
+        const int i = threadIdx.x + 256 * (h * NH + r);
+        kbv[r] = *(cgdbl2*)(kb + 2 * i);
+        kav[r] = *(cgdbl2*)(ka + 2 * i);
       }
-      const dv2 b = *(cgdbl2*)(kb + 2 * i);
-      const dv2 a = *(cgdbl2*)(ka + 2 * i);
-      a0x[q] += mul_mod(xx, b.x, m);
-      a0y[q] += mul_mod(xy, b.y, m);
-      a1x[q] += mul_mod(xx, a.x, m);
-      a1y[q] += mul_mod(xy, a.y, m);
-      if (j & 1) {
-        a0x[q] = red(a0x[q], m); a0y[q] = red(a0y[q], m);
-        a1x[q] = red(a1x[q], m); a1y[q] = red(a1y[q], m);
+      if (j != own) {
+#pragma unroll
+        for (int r = 0; r < NH; ++r) {
+          const int i = threadIdx.x + 256 * (h * NH + r);
+          xv[r].x = canon(lds[lpad(2 * i)], m);
+          xv[r].y = canon(lds[lpad(2 * i + 1)], m);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < NH; ++r) {
+          const double2 v = ld2(J.d, (size_t)t * N + tile + 2 * (threadIdx.x + 256 * (h * NH + r)));
+          xv[r].x = v.x;
+          xv[r].y = v.y;
+        }
+        if (J.d_square) {
+#pragma unroll
+          for (int r = 0; r < NH; ++r) {
+            xv[r].x = canon(mul_mod(xv[r].x, xv[r].x, m), m);
+            xv[r].y = canon(mul_mod(xv[r].y, xv[r].y, m), m);
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < NH; ++r) {
+        const int q = h * NH + r;
+        a0x[q] += mul_mod(xv[r].x, kbv[r].x, m);
+        a0y[q] += mul_mod(xv[r].y, kbv[r].y, m);
+        a1x[q] += mul_mod(xv[r].x, kav[r].x, m);
+        a1y[q] += mul_mod(xv[r].y, kav[r].y, m);
+        if (j & 1) {
+          a0x[q] = red(a0x[q], m); a0y[q] = red(a0y[q], m);
+          a1x[q] = red(a1x[q], m); a1y[q] = red(a1y[q], m);
+        }
       }
     }
     // the next digit's row pass overwrites the tile in LDS
