@@ -80,6 +80,79 @@ __device__ __forceinline__ void ntt_epilogue(const NttJob& J, int l, size_t o, d
   st2(J.eout, o, canon(r0, m), canon(r1, m));
 }
 
+// The same epilogue over a row tile held in LDS (lazily reduced values at
+// lpad(2i), lpad(2i+1) for pair i = t + 256 q, q < NPP, pair i at offset
+// o0 + 2i of limb l).  Pairs go in batches of NB: every operand of a batch is
+// requested at once, so a batch costs one load round trip, not one per pair.
+template <int NPP>
+__device__ __forceinline__ void row_epilogue(const NttJob& J, int l, size_t o0, const double* lds, const Mod& m) {
+  constexpr int NB = NPP / 2;
+  const int t = threadIdx.x;
+  const double k = KPTR(J.ek)[l];
+  const double k2 = J.epi == EPI_RRCOMB ? KPTR(J.ek2)[l] : 0.0;
+#pragma unroll
+  for (int h = 0; h < NPP / NB; ++h) {
+    auto off = [&](int r) -> size_t { return o0 + 2 * (size_t)(t + 256 * (h * NB + r)); };
+    auto val = [&](int r, int c) -> double { return canon(lds[lpad(2 * (t + 256 * (h * NB + r)) + c)], m); };
+    dv2 a[NB], b[NB];
+    if (J.epi == EPI_RESCALE) {
+#pragma unroll
+      for (int r = 0; r < NB; ++r) a[r] = *(cgdbl2*)(CGPTR(J.ea) + off(r));
+#pragma unroll
+      for (int r = 0; r < NB; ++r) {
+        const double r0 = mul_mod(a[r].x - val(r, 0), k, m);
+        const double r1 = mul_mod(a[r].y - val(r, 1), k, m);
+        st2(J.eout, off(r), canon(r0, m), canon(r1, m));
+      }
+    } else if (J.epi == EPI_RRCOMB) {
+#pragma unroll
+      for (int r = 0; r < NB; ++r) {
+        a[r] = *(cgdbl2*)(CGPTR(J.ea) + off(r));
+        b[r] = *(cgdbl2*)(CGPTR(J.eb) + off(r));
+      }
+      if (J.sq == 1) {
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+          a[r].x = mul_mod(a[r].x, a[r].x, m);
+          a[r].y = mul_mod(a[r].y, a[r].y, m);
+        }
+      } else if (J.sq == 2) {
+        dv2 a1[NB];
+#pragma unroll
+        for (int r = 0; r < NB; ++r) a1[r] = *(cgdbl2*)(CGPTR(J.ebase) + off(r));
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+          a[r].x = mul_mod(2.0 * a[r].x, a1[r].x, m);
+          a[r].y = mul_mod(2.0 * a[r].y, a1[r].y, m);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < NB; ++r) {
+        const double r0 = mul_mod(red(mul_mod(a[r].x, k2, m) + (b[r].x - val(r, 0)), m), k, m);
+        const double r1 = mul_mod(red(mul_mod(a[r].y, k2, m) + (b[r].y - val(r, 1)), m), k, m);
+        st2(J.eout, off(r), canon(r0, m), canon(r1, m));
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < NB; ++r) b[r] = *(cgdbl2*)(CGPTR(J.eb) + off(r));
+      if (J.ebase) {
+#pragma unroll
+        for (int r = 0; r < NB; ++r) a[r] = *(cgdbl2*)(CGPTR(J.ebase) + off(r));
+      }
+#pragma unroll
+      for (int r = 0; r < NB; ++r) {
+        double r0 = mul_mod(b[r].x - val(r, 0), k, m);
+        double r1 = mul_mod(b[r].y - val(r, 1), k, m);
+        if (J.ebase) {
+          r0 += a[r].x;
+          r1 += a[r].y;
+        }
+        st2(J.eout, off(r), canon(r0, m), canon(r1, m));
+      }
+    }
+  }
+}
+
 enum { NTT_SINGLE = 0, NTT_COL = 1, NTT_ROW = 2 };
 
 template <int LOGS, int MODE>
@@ -378,7 +451,7 @@ __device__ __forceinline__ void inv_row_from_lds(double* lds, gdbl* dst, int row
 }
 
 template <int LOGS, int G, int MODE, bool INV>
-__global__ __launch_bounds__(256) void k_ntt2(const NttJob* __restrict__ jobs, DevTables T, int second) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_ntt2(const NttJob* __restrict__ jobs, DevTables T, int second) {
   extern __shared__ double lds[];
   constexpr int S = 1 << LOGS;
   constexpr int RB = LOGS - 4;         // bits of round B
@@ -451,9 +524,7 @@ __global__ __launch_bounds__(256) void k_ntt2(const NttJob* __restrict__ jobs, D
     if (MODE == NTT_ROW) {
       __syncthreads();
       if (J.epi != EPI_NONE) {
-        const size_t o0 = (size_t)l * N + (size_t)row0 * S;
-        for (int i = t; i < G * S / 2; i += 256)
-          ntt_epilogue(J, l, o0 + 2 * i, lds[lpad(2 * i)], lds[lpad(2 * i + 1)], m);
+        row_epilogue<G * S / 2 / 256>(J, l, (size_t)l * N + (size_t)row0 * S, lds, m);
       } else {
         gdbl2* d2 = (gdbl2*)(dst + (size_t)row0 * S);
         for (int i = t; i < G * S / 2; i += 256) {
