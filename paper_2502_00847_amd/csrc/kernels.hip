@@ -540,10 +540,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     if (MODE == NTT_ROW) {
       cgdbl2* s2 = (cgdbl2*)(src + (size_t)row0 * S);
       const bool sq = J.sq && !second;
-      for (int i = t; i < G * S / 2; i += 256) {
-        const dv2 v = s2[i];
-        lds[lpad(2 * i)] = sq ? canon(mul_mod(v.x, v.x, m), m) : v.x;
-        lds[lpad(2 * i + 1)] = sq ? canon(mul_mod(v.y, v.y, m), m) : v.y;
+      // every pair of the thread is requested at once (one load round trip)
+      constexpr int NPP = G * S / 2 / 256;
+      dv2 v[NPP];
+#pragma unroll
+      for (int q = 0; q < NPP; ++q) v[q] = s2[t + 256 * q];
+      if (sq) {
+#pragma unroll
+        for (int q = 0; q < NPP; ++q) {
+          v[q].x = canon(mul_mod(v[q].x, v[q].x, m), m);
+          v[q].y = canon(mul_mod(v[q].y, v[q].y, m), m);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < NPP; ++q) {
+        lds[lpad(2 * (t + 256 * q))] = v[q].x;
+        lds[lpad(2 * (t + 256 * q) + 1)] = v[q].y;
       }
       __syncthreads();
       inv_row_from_lds<LOGS, G>(lds, dst, row0, k1, tw, twq, m);
@@ -906,12 +918,12 @@ __global__ __launch_bounds__(256) void k_ew(const EwJob* __restrict__ jobs, DevT
         break;
       }
       case EW_ADD_CONST: {
+        // optional operands are requested with the others (one load round trip)
+        const bool cp = J.o1 != J.a1;
         const double2 a0 = ld2(J.a0, o);
+        const double2 a1 = cp ? ld2(J.a1, o) : make_double2(0.0, 0.0);
         st2(J.o0, o, add_mod(a0.x, kk, m), add_mod(a0.y, kk, m));
-        if (J.o1 != J.a1) {
-          const double2 a1 = ld2(J.a1, o);
-          st2(J.o1, o, a1.x, a1.y);
-        }
+        if (cp) st2(J.o1, o, a1.x, a1.y);
         break;
       }
       case EW_PMUL: {
@@ -932,9 +944,9 @@ __global__ __launch_bounds__(256) void k_ew(const EwJob* __restrict__ jobs, DevT
       }
       case EW_KEYB: {
         const double2 a1 = ld2(J.a1, o), b0 = ld2(J.b0, o), b1 = ld2(J.b1, o);
+        const double2 c0 = kk != 0.0 ? ld2(J.c0, o) : make_double2(0.0, 0.0);
         double vx = a1.x - mul_mod(b0.x, b1.x, m), vy = a1.y - mul_mod(b0.y, b1.y, m);
         if (kk != 0.0) {
-          const double2 c0 = ld2(J.c0, o);
           vx += mul_mod(kk, c0.x, m);
           vy += mul_mod(kk, c0.y, m);
         }
@@ -948,21 +960,22 @@ __global__ __launch_bounds__(256) void k_ew(const EwJob* __restrict__ jobs, DevT
       }
       case EW_COPY: {
         const double2 a0 = ld2(J.a0, o);
+        const double2 a1 = J.o1 ? ld2(J.a1, o) : make_double2(0.0, 0.0);
         st2(J.o0, o, a0.x, a0.y);
-        if (J.o1) {
-          const double2 a1 = ld2(J.a1, o);
-          st2(J.o1, o, a1.x, a1.y);
-        }
+        if (J.o1) st2(J.o1, o, a1.x, a1.y);
         break;
       }
       case EW_TENSOR2: {
         const double2 a0 = ld2(J.a0, o), a1 = ld2(J.a1, o), b0 = ld2(J.b0, o), b1 = ld2(J.b1, o);
+        const double2 z2 = make_double2(0.0, 0.0);
+        const double2 c0 = J.c0 ? ld2(J.c0, o) : z2, c1 = J.c0 ? ld2(J.c1, o) : z2;
+        const double2 e0 = J.c0 ? ld2(J.e0, o) : z2, e1 = J.c0 ? ld2(J.e1, o) : z2;
+        const double2 f0 = J.f0 ? ld2(J.f0, o) : z2, f1 = J.f0 ? ld2(J.f1, o) : z2;
         double r0x = mul_mod(a0.x, b0.x, m), r0y = mul_mod(a0.y, b0.y, m);
         double r1x = mul_mod(a0.x, b1.x, m) + mul_mod(a1.x, b0.x, m);
         double r1y = mul_mod(a0.y, b1.y, m) + mul_mod(a1.y, b0.y, m);
         double r2x = mul_mod(a1.x, b1.x, m), r2y = mul_mod(a1.y, b1.y, m);
         if (J.c0) {
-          const double2 c0 = ld2(J.c0, o), c1 = ld2(J.c1, o), e0 = ld2(J.e0, o), e1 = ld2(J.e1, o);
           r0x += mul_mod(c0.x, e0.x, m);
           r0y += mul_mod(c0.y, e0.y, m);
           r1x = red(r1x, m) + mul_mod(c0.x, e1.x, m) + mul_mod(c1.x, e0.x, m);
@@ -971,7 +984,6 @@ __global__ __launch_bounds__(256) void k_ew(const EwJob* __restrict__ jobs, DevT
           r2y += mul_mod(c1.y, e1.y, m);
         }
         if (J.f0) {
-          const double2 f0 = ld2(J.f0, o), f1 = ld2(J.f1, o);
           r0x += f0.x;
           r0y += f0.y;
           r1x = red(r1x, m) + f1.x;
@@ -983,12 +995,11 @@ __global__ __launch_bounds__(256) void k_ew(const EwJob* __restrict__ jobs, DevT
         break;
       }
       case EW_PADD: {
+        const bool cp = J.o1 != J.a1;
         const double2 a0 = ld2(J.a0, o), p = ld2(J.b0, o);
+        const double2 a1 = cp ? ld2(J.a1, o) : make_double2(0.0, 0.0);
         st2(J.o0, o, add_mod(a0.x, p.x, m), add_mod(a0.y, p.y, m));
-        if (J.o1 != J.a1) {
-          const double2 a1 = ld2(J.a1, o);
-          st2(J.o1, o, a1.x, a1.y);
-        }
+        if (cp) st2(J.o1, o, a1.x, a1.y);
         break;
       }
       case EW_PMAC: {
@@ -999,11 +1010,12 @@ __global__ __launch_bounds__(256) void k_ew(const EwJob* __restrict__ jobs, DevT
       }
       case EW_LIN2: {
         const double2 a0 = ld2(J.a0, o), a1 = ld2(J.a1, o);
+        const double2 b0 = J.b0 ? ld2(J.b0, o) : make_double2(0.0, 0.0);
+        const double2 b1 = J.b0 ? ld2(J.b1, o) : make_double2(0.0, 0.0);
         double r0x = mul_mod(a0.x, kk, m), r0y = mul_mod(a0.y, kk, m);
         double r1x = mul_mod(a1.x, kk, m), r1y = mul_mod(a1.y, kk, m);
         if (J.b0) {
           const double k2 = KPTR(J.k2)[l];
-          const double2 b0 = ld2(J.b0, o), b1 = ld2(J.b1, o);
           r0x += mul_mod(b0.x, k2, m);
           r0y += mul_mod(b0.y, k2, m);
           r1x += mul_mod(b1.x, k2, m);
@@ -1067,13 +1079,17 @@ __global__ __launch_bounds__(256) void k_moddown_conv(const ModDownJob* __restri
   const int nb = T.n_p + extra;
   // digits [x_b (B/b)^-1]_b taken centred, in (-b/2, b/2), so the conversion
   // overshoots by a signed multiple of B and the division rounds without bias
+  // all source limbs are requested before any is used (one load round trip)
   double y[MAX_DIGIT + 1];
+#pragma unroll
+  for (int i = 0; i < MAX_DIGIT + 1; ++i)
+    if (i < nb) y[i] = CGPTR(J.src)[(size_t)i * N + k];
 #pragma unroll
   for (int i = 0; i < MAX_DIGIT + 1; ++i) {
     if (i < nb) {
       const int pr = i < extra ? J.first_prime : T.n_q + i - extra;
       const Mod mi{KPTR(T.mod)[pr], KPTR(T.minv)[pr]};
-      const double z = canon(mul_mod(CGPTR(J.src)[(size_t)i * N + k], KPTR(J.cinv)[i], mi), mi);
+      const double z = canon(mul_mod(y[i], KPTR(J.cinv)[i], mi), mi);
       y[i] = 2.0 * z > mi.p ? z - mi.p : z;
     }
   }
