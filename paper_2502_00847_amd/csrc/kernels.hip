@@ -450,8 +450,13 @@ __device__ __forceinline__ void inv_row_from_lds(double* lds, gdbl* dst, int row
   for (int e = 0; e < 16; ++e) dst[(size_t)(row0 + va) * S + e * NB + la] = canon(x[e], m);
 }
 
+// The row passes are compiled for the 4 waves per SIMD that their 34 KiB LDS
+// tile allows (the compiler cannot see the dynamic LDS size and would
+// otherwise keep registers low for 8 and not hoist the twiddle loads); the
+// column passes measure best at the compiler's default.
 template <int LOGS, int G, int MODE, bool INV>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_ntt2(const NttJob* __restrict__ jobs, DevTables T, int second) {
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(MODE == NTT_ROW ? 4 : 1, MODE == NTT_ROW ? 4 : 8))) void k_ntt2(const NttJob* __restrict__ jobs, DevTables T, int second) {
   extern __shared__ double lds[];
   constexpr int S = 1 << LOGS;
   constexpr int RB = LOGS - 4;         // bits of round B
