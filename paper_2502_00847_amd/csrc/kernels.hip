@@ -27,6 +27,27 @@ constexpr int MAX_DIGIT = 16;
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 
+// Pair p (elements 2p, 2p+1) of a G x S tile taken by the calling thread in its
+// slot q < G*S/512.  With rows of S = 256, the row-pass thread maps give each
+// wave four whole rows (16 lanes per row), and this map keeps a wave's pairs
+// inside those rows too: the tile's LDS traffic then never crosses waves, and
+// tile_sync orders it within the wave instead of across the workgroup.
+template <int S>
+__device__ __forceinline__ int tile_pair(int q) {
+  const int t = threadIdx.x;
+  return S == 256 ? (t >> 6) * 512 + q * 64 + (t & 63) : t + 256 * q;
+}
+template <int S>
+__device__ __forceinline__ void tile_sync() {
+  if (S == 256) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 __device__ __forceinline__ double2 ld2(const double* p, size_t o) {
   const dv2 v = *(cgdbl2*)(CGPTR(p) + o);
   return make_double2(v.x, v.y);
@@ -81,19 +102,18 @@ __device__ __forceinline__ void ntt_epilogue(const NttJob& J, int l, size_t o, d
 }
 
 // The same epilogue over a row tile held in LDS (lazily reduced values at
-// lpad(2i), lpad(2i+1) for pair i = t + 256 q, q < NPP, pair i at offset
+// lpad(2i), lpad(2i+1) for pair i = tile_pair(q), q < NPP, pair i at offset
 // o0 + 2i of limb l).  Pairs go in batches of NB: every operand of a batch is
 // requested at once, so a batch costs one load round trip, not one per pair.
-template <int NPP>
+template <int NPP, int S>
 __device__ __forceinline__ void row_epilogue(const NttJob& J, int l, size_t o0, const double* lds, const Mod& m) {
   constexpr int NB = NPP / 2;
-  const int t = threadIdx.x;
   const double k = KPTR(J.ek)[l];
   const double k2 = J.epi == EPI_RRCOMB ? KPTR(J.ek2)[l] : 0.0;
 #pragma unroll
   for (int h = 0; h < NPP / NB; ++h) {
-    auto off = [&](int r) -> size_t { return o0 + 2 * (size_t)(t + 256 * (h * NB + r)); };
-    auto val = [&](int r, int c) -> double { return canon(lds[lpad(2 * (t + 256 * (h * NB + r)) + c)], m); };
+    auto off = [&](int r) -> size_t { return o0 + 2 * (size_t)tile_pair<S>(h * NB + r); };
+    auto val = [&](int r, int c) -> double { return canon(lds[lpad(2 * tile_pair<S>(h * NB + r) + c)], m); };
     dv2 a[NB], b[NB];
     if (J.epi == EPI_RESCALE) {
 #pragma unroll
@@ -440,7 +460,7 @@ __device__ __forceinline__ void inv_row_from_lds(double* lds, gdbl* dst, int row
 #pragma unroll
     for (int e = 0; e < NB; ++e) lds[lpad(vb * S + hb * NB + e)] = y[e];
   }
-  __syncthreads();
+  tile_sync<S>();
   const int va = t / NB, la = t % NB;
   double x[16];
 #pragma unroll
@@ -507,7 +527,8 @@ __attribute__((amdgpu_waves_per_eu(MODE == NTT_ROW ? 4 : 1, MODE == NTT_ROW ? 4 
     ntt_round<LOGS, 4, MODE, false>(x, 0, RB, row0 + va, k1, tw, twq, m);
 #pragma unroll
     for (int e = 0; e < 16; ++e) lds[lidx(va, e * NB + la)] = x[e];
-    __syncthreads();
+    // (this branch is the row pass: the exchange stays inside each wave at S = 256)
+    tile_sync<S>();
     // ---- round B
 #pragma unroll
     for (int gi = 0; gi < GB; ++gi) {
@@ -527,12 +548,14 @@ __attribute__((amdgpu_waves_per_eu(MODE == NTT_ROW ? 4 : 1, MODE == NTT_ROW ? 4 
       }
     }
     if (MODE == NTT_ROW) {
-      __syncthreads();
+      tile_sync<S>();
       if (J.epi != EPI_NONE) {
-        row_epilogue<G * S / 2 / 256>(J, l, (size_t)l * N + (size_t)row0 * S, lds, m);
+        row_epilogue<G * S / 2 / 256, S>(J, l, (size_t)l * N + (size_t)row0 * S, lds, m);
       } else {
         gdbl2* d2 = (gdbl2*)(dst + (size_t)row0 * S);
-        for (int i = t; i < G * S / 2; i += 256) {
+#pragma unroll
+        for (int q = 0; q < G * S / 2 / 256; ++q) {
+          const int i = tile_pair<S>(q);
           dv2 v;
           v.x = canon(lds[lpad(2 * i)], m);
           v.y = canon(lds[lpad(2 * i + 1)], m);
@@ -549,7 +572,7 @@ __attribute__((amdgpu_waves_per_eu(MODE == NTT_ROW ? 4 : 1, MODE == NTT_ROW ? 4 
       constexpr int NPP = G * S / 2 / 256;
       dv2 v[NPP];
 #pragma unroll
-      for (int q = 0; q < NPP; ++q) v[q] = s2[t + 256 * q];
+      for (int q = 0; q < NPP; ++q) v[q] = s2[tile_pair<S>(q)];
       if (sq) {
 #pragma unroll
         for (int q = 0; q < NPP; ++q) {
@@ -559,10 +582,10 @@ __attribute__((amdgpu_waves_per_eu(MODE == NTT_ROW ? 4 : 1, MODE == NTT_ROW ? 4 
       }
 #pragma unroll
       for (int q = 0; q < NPP; ++q) {
-        lds[lpad(2 * (t + 256 * q))] = v[q].x;
-        lds[lpad(2 * (t + 256 * q) + 1)] = v[q].y;
+        lds[lpad(2 * tile_pair<S>(q))] = v[q].x;
+        lds[lpad(2 * tile_pair<S>(q) + 1)] = v[q].y;
       }
-      __syncthreads();
+      tile_sync<S>();
       inv_row_from_lds<LOGS, G>(lds, dst, row0, k1, tw, twq, m);
       return;
     }
@@ -614,7 +637,7 @@ __device__ __forceinline__ void fwd_row_tile(double* lds, cgdbl* src, int row0, 
   ntt_round<LOGS, 4, NTT_ROW, false>(x, 0, RB, row0 + va, k1, tw, twq, m);
 #pragma unroll
   for (int e = 0; e < 16; ++e) lds[lpad(va * S + e * NB + la)] = x[e];
-  __syncthreads();
+  tile_sync<S>();
 #pragma unroll
   for (int gi = 0; gi < GB; ++gi) {
     const int grp = t + gi * 256;
@@ -626,7 +649,7 @@ __device__ __forceinline__ void fwd_row_tile(double* lds, cgdbl* src, int row0, 
 #pragma unroll
     for (int e = 0; e < NB; ++e) lds[lpad(vb * S + hb * NB + e)] = y[e];
   }
-  __syncthreads();
+  tile_sync<S>();
 }
 
 // Key-switch inner product fused with the row pass of the ModUp outputs'
@@ -670,21 +693,21 @@ __global__ __launch_bounds__(256) void k_inner_row(const InnerJob* __restrict__ 
       dv2 kbv[NH], kav[NH], xv[NH];
 #pragma unroll
       for (int r = 0; r < NH; ++r) {
-        const int i = threadIdx.x + 256 * (h * NH + r);
+        const int i = tile_pair<S>(h * NH + r);
         kbv[r] = *(cgdbl2*)(kb + 2 * i);
         kav[r] = *(cgdbl2*)(ka + 2 * i);
       }
       if (j != own) {
 #pragma unroll
         for (int r = 0; r < NH; ++r) {
-          const int i = threadIdx.x + 256 * (h * NH + r);
+          const int i = tile_pair<S>(h * NH + r);
           xv[r].x = canon(lds[lpad(2 * i)], m);
           xv[r].y = canon(lds[lpad(2 * i + 1)], m);
         }
       } else {
 #pragma unroll
         for (int r = 0; r < NH; ++r) {
-          const double2 v = ld2(J.d, (size_t)t * N + tile + 2 * (threadIdx.x + 256 * (h * NH + r)));
+          const double2 v = ld2(J.d, (size_t)t * N + tile + 2 * (tile_pair<S>(h * NH + r)));
           xv[r].x = v.x;
           xv[r].y = v.y;
         }
@@ -710,14 +733,14 @@ __global__ __launch_bounds__(256) void k_inner_row(const InnerJob* __restrict__ 
       }
     }
     // the next digit's row pass overwrites the tile in LDS
-    if (j != own) __syncthreads();
+    if (j != own) tile_sync<S>();
   }
   const bool top = J.top0 && t == J.n_chain - 1;
   const double pm = top ? KPTR(J.pmq)[t] : 0.0;
 #pragma unroll
   for (int q = 0; q < NP; ++q) {
     if (top) {
-      const size_t o = (size_t)t * N + tile + 2 * (threadIdx.x + 256 * q);
+      const size_t o = (size_t)t * N + tile + 2 * (tile_pair<S>(q));
       double2 u0 = ld2(J.top0, o), u1 = ld2(J.top1, o);
       if (J.d_square) {
         // top0, top1 = a0, a1 of the square: d0 = a0^2, d1 = 2 a0 a1
@@ -741,19 +764,19 @@ __global__ __launch_bounds__(256) void k_inner_row(const InnerJob* __restrict__ 
     for (int w = 0; w < 2; ++w) {
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
-        const int i = threadIdx.x + 256 * q;
+        const int i = tile_pair<S>(q);
         lds[lpad(2 * i)] = canon(w ? a1x[q] : a0x[q], m);
         lds[lpad(2 * i + 1)] = canon(w ? a1y[q] : a0y[q], m);
       }
-      __syncthreads();
+      tile_sync<S>();
       inv_row_from_lds<LOGS, G>(lds, GPTR(J.acc) + ((size_t)w * J.n_ext + t) * N, row0, k1, itw, itwq, m);
-      __syncthreads();
+      tile_sync<S>();
     }
     return;
   }
 #pragma unroll
   for (int q = 0; q < NP; ++q) {
-    const size_t o = (size_t)t * N + tile + 2 * (threadIdx.x + 256 * q);
+    const size_t o = (size_t)t * N + tile + 2 * (tile_pair<S>(q));
     st2(J.acc, o, canon(a0x[q], m), canon(a0y[q], m));
     st2(J.acc, (size_t)J.n_ext * N + o, canon(a1x[q], m), canon(a1y[q], m));
   }
