@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE (each scaled by what the counter reads for a 1 GiB device copy);
 # see profiles/k_inner_row_config3_traffic.md.  None when the kernel has
 # changed since the counters were taken.
-TRAFFIC_PER_UNIT = 290090
+TRAFFIC_PER_UNIT = 287125
 
 
 def _log(msg):
