@@ -30,6 +30,7 @@ enum NttEpi : int {
   EPI_RESCALE = 1,   // eout = (ea - v) ek[l]
   EPI_RRCOMB = 2,    // eout = (ek2[l] ea + eb - v) ek[l]
   EPI_MODDOWN = 3,   // eout = (ebase or 0) + (eb - v) ek[l]
+  EPI_LINRS = 4,     // eout = ([ek2[l] ea + ek3[l] eb] - v) ek[l]   (eb optional; [.] canonical)
 };
 
 // NTT over limbs [0, n_limbs) of src (skipping [skip_lo, skip_hi)), written to dst.
@@ -40,7 +41,9 @@ enum NttEpi : int {
 //    its own prime, instead of limb l of src;
 //  * epi != EPI_NONE: the transform v of limb l is not stored; eout at the
 //    same position receives the combination above (ea, eb, ebase, eout are
-//    limb-major arrays indexed like dst; ek, ek2 per-limb constants).
+//    limb-major arrays indexed like dst; ek, ek2, ek3 per-limb constants).
+//    EPI_LINRS is a constant combination and its rescale in one: the
+//    combination is formed here rather than read back from HBM.
 //  * sq (squares of degree-1 ciphertexts, two-pass sizes): an inverse
 //    transform squares src on load; the EPI_RRCOMB epilogue takes its d as
 //    ea^2 (sq = 1) or 2 ea ebase (sq = 2) instead of reading it.
@@ -56,6 +59,7 @@ struct NttJob {
   double* eout;
   const double* ek;
   const double* ek2;
+  const double* ek3;
 };
 
 enum EwOp : int {
@@ -95,7 +99,7 @@ struct EwJob {
   const double* k;   // per-limb constants (canonical residues) or null
   const double* k2;  // second per-limb constant table or null
   int n_limbs, n_chain;
-  int op, pad;
+  int op, l_first;   // limbs below l_first are left untouched
 };
 
 // ModUp of one digit: src (coefficient domain, limbs 0..level) -> dst limbs of

@@ -74,6 +74,18 @@ __device__ __forceinline__ void ntt_epilogue(const NttJob& J, int l, size_t o, d
     const double2 a = ld2(J.ea, o);
     r0 = mul_mod(a.x - c0, k, m);
     r1 = mul_mod(a.y - c1, k, m);
+  } else if (J.epi == EPI_LINRS) {
+    const double2 a = ld2(J.ea, o);
+    const double2 b = J.eb ? ld2(J.eb, o) : make_double2(0.0, 0.0);
+    const double ka = KPTR(J.ek2)[l];
+    double sx = mul_mod(a.x, ka, m), sy = mul_mod(a.y, ka, m);
+    if (J.eb) {
+      const double kb = KPTR(J.ek3)[l];
+      sx += mul_mod(b.x, kb, m);
+      sy += mul_mod(b.y, kb, m);
+    }
+    r0 = mul_mod(canon(sx, m) - c0, k, m);
+    r1 = mul_mod(canon(sy, m) - c1, k, m);
   } else if (J.epi == EPI_RRCOMB) {
     const double k2 = KPTR(J.ek2)[l];
     double2 a = ld2(J.ea, o);
@@ -122,6 +134,26 @@ __device__ __forceinline__ void row_epilogue(const NttJob& J, int l, size_t o0, 
       for (int r = 0; r < NB; ++r) {
         const double r0 = mul_mod(a[r].x - val(r, 0), k, m);
         const double r1 = mul_mod(a[r].y - val(r, 1), k, m);
+        st2(J.eout, off(r), canon(r0, m), canon(r1, m));
+      }
+    } else if (J.epi == EPI_LINRS) {
+      const double ka = KPTR(J.ek2)[l];
+      const double kb = J.eb ? KPTR(J.ek3)[l] : 0.0;
+#pragma unroll
+      for (int r = 0; r < NB; ++r) a[r] = *(cgdbl2*)(CGPTR(J.ea) + off(r));
+      if (J.eb) {
+#pragma unroll
+        for (int r = 0; r < NB; ++r) b[r] = *(cgdbl2*)(CGPTR(J.eb) + off(r));
+      }
+#pragma unroll
+      for (int r = 0; r < NB; ++r) {
+        double sx = mul_mod(a[r].x, ka, m), sy = mul_mod(a[r].y, ka, m);
+        if (J.eb) {
+          sx += mul_mod(b[r].x, kb, m);
+          sy += mul_mod(b[r].y, kb, m);
+        }
+        const double r0 = mul_mod(canon(sx, m) - val(r, 0), k, m);
+        const double r1 = mul_mod(canon(sy, m) - val(r, 1), k, m);
         st2(J.eout, off(r), canon(r0, m), canon(r1, m));
       }
     } else if (J.epi == EPI_RRCOMB) {
@@ -916,7 +948,7 @@ void* ntt_kernel(int logs, int mode, bool inv, int* g_out) {
 __global__ __launch_bounds__(256) void k_ew(const EwJob* __restrict__ jobs, DevTables T) {
   const EwJob J = jobs[blockIdx.z];
   const int l = blockIdx.y;
-  if (l >= J.n_limbs) return;
+  if (l >= J.n_limbs || l < J.l_first) return;
   const int pr = l < J.n_chain ? l : T.n_q + (l - J.n_chain);
   const Mod m{KPTR(T.mod)[pr], KPTR(T.minv)[pr]};
   const int N = 1 << T.log_n;

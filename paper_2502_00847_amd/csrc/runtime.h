@@ -280,6 +280,17 @@ class Builder {
   std::vector<CT> relin_rescale(const std::vector<Deg2>& xs);
   std::vector<CT> lincomb(const std::vector<LinItem>& v, bool do_rescale);
   void rescale(std::vector<CT>& in_out);                    // in place
+  // the sources of a constant combination whose rescale forms it in its
+  // epilogue (only the top limb of the combination is in HBM beforehand)
+  struct LinSrc {
+    const double* a0;
+    const double* a1;
+    const double* b0;   // null without a second term
+    const double* b1;
+    const double* ka;   // per-limb residues of the constants
+    const double* kb;
+  };
+  void rescale(std::vector<CT>& in_out, const std::vector<LinSrc>* lin);
   std::vector<CT> mul_relin(const std::vector<std::pair<CT, CT>>& ab, bool do_rescale);
   std::vector<CT> rotate(const std::vector<CT>& in, const std::vector<int64_t>& steps);
   std::vector<CT> add(const std::vector<std::pair<CT, CT>>& ab, bool sub);

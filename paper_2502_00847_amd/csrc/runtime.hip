@@ -396,7 +396,7 @@ void Builder::ntt(const std::vector<NttJob>& v, bool inverse, int pass) {
 void Builder::ew(const std::vector<EwJob>& v) {
   int my = 0;
   int64_t units = 0;
-  for (auto& j : v) { my = std::max(my, j.n_limbs); units += j.n_limbs; }
+  for (auto& j : v) { my = std::max(my, j.n_limbs); units += j.n_limbs - std::min(j.l_first, j.n_limbs); }
   PUSH_JOBS(C_EW, v, my, false, units);
 }
 void Builder::modup(const std::vector<ModUpJob>& v) {
@@ -777,10 +777,13 @@ std::vector<Builder::Deg2> Builder::tensor2(const std::vector<TensorItem>& v) {
 }
 
 // rescale by the top prime q_l: c_i <- (c_i - [c_l]centred) * q_l^-1  (in place)
-void Builder::rescale(std::vector<CT>& xs) {
+void Builder::rescale(std::vector<CT>& xs) { rescale(xs, nullptr); }
+
+void Builder::rescale(std::vector<CT>& xs, const std::vector<LinSrc>* lin) {
   const int N = C.N;
   std::vector<NttJob> j_top, j_fwd;
-  for (CT& x : xs) {
+  for (size_t xi = 0; xi < xs.size(); ++xi) {
+    CT& x = xs[xi];
     const int l = x.level;
     if (l < 1) { fail(-3, "rescale below level 0"); return; }
     double* top = scratch(2 * (size_t)N);
@@ -798,6 +801,15 @@ void Builder::rescale(std::vector<CT>& xs) {
       f.ea = cw;
       f.eout = cw;
       f.ek = C.rs_tab + (size_t)l * C.n_q;
+      if (lin) {
+        // limbs below l of the combination are formed from its sources here
+        const LinSrc& ls = (*lin)[xi];
+        f.epi = EPI_LINRS;
+        f.ea = w ? ls.a1 : ls.a0;
+        f.eb = w ? ls.b1 : ls.b0;
+        f.ek2 = ls.ka;
+        f.ek3 = ls.kb;
+      }
       j_fwd.push_back(f);
     }
     x.scale = x.scale / (double)C.mod[l];
@@ -969,6 +981,7 @@ static int64_t const_for(double v, double target, double q, double s, bool resca
 std::vector<CT> Builder::lincomb(const std::vector<LinItem>& v, bool do_rescale) {
   std::vector<CT> out;
   std::vector<EwJob> j;
+  std::vector<LinSrc> lin;
   for (const LinItem& it : v) {
     const CT& x = it.a;
     if (it.has_b && it.b.level != x.level) { fail(-1, "lincomb: level mismatch"); return {}; }
@@ -987,13 +1000,19 @@ std::vector<CT> Builder::lincomb(const std::vector<LinItem>& v, bool do_rescale)
     }
     e.n_limbs = x.level + 1; e.n_chain = x.level + 1;
     e.op = EW_LIN2;
+    if (do_rescale) {
+      // only the top limb is formed here: the rescale's forward transform
+      // forms the others in its epilogue, from the same sources
+      e.l_first = x.level;
+      lin.push_back(LinSrc{e.a0, e.a1, e.b0, e.b1, e.k, e.k2});
+    }
     j.push_back(e);
     out.push_back(o);
   }
   ew(j);
   if (do_rescale) {
     const size_t mark = scratch_mark();
-    rescale(out);
+    rescale(out, &lin);
     scratch_release(mark);
     if (err_code) return {};
     for (size_t i = 0; i < out.size(); ++i) out[i].scale = v[i].target;
