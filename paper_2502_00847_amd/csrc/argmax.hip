@@ -260,16 +260,14 @@ static void run_step(Builder& b, int kind, std::vector<QState*>& qs) {
         t.target = s->d.scale * s->x.scale;
         li.push_back(t);
       }
-      std::vector<CT> half = b.lincomb(li, false);
-      if (b.err_code) return;
       const size_t mark = b.scratch_mark();
       std::vector<Builder::TensorItem> ti;
       for (size_t i = 0; i < n; ++i) {
         Builder::TensorItem t{};
         t.a = lower(qs[i]->d, qs[i]->lp);
         t.b = lower(qs[i]->x, qs[i]->lp);
-        t.f = half[i];
-        t.has_f = true;
+        t.fl = li[i];   // (a+b)/2 formed inside the degree-2 sum
+        t.has_fl = true;
         ti.push_back(t);
       }
       std::vector<Builder::Deg2> d2 = b.tensor2(ti);
@@ -279,7 +277,6 @@ static void run_step(Builder& b, int kind, std::vector<QState*>& qs) {
       b.scratch_release(mark);
       for (size_t i = 0; i < n; ++i) {
         QState* s = qs[i];
-        b.free_ct(half[i]);
         free_owned(b, s->d);
         free_owned(b, s->s);
         free_owned(b, s->x);

@@ -75,7 +75,7 @@ enum EwOp : int {
   EW_COPY = 12,      // o0 = a0, o1 = a1
   // degree-2 sum of up to two tensor products plus a degree-1 addend:
   //   o0 = a0 b0 + c0 e0 + f0,  o1 = a0 b1 + a1 b0 + c0 e1 + c1 e0 + f1,  o2 = a1 b1 + c1 e1
-  // (c/e and f optional)
+  // (c/e and f optional; with k set, f stands for the combination f k + g k2)
   EW_TENSOR2 = 13,
   EW_LIN2 = 15,      // o_i = a_i k[l] + b_i k2[l]   (b optional)
   EW_PADD = 16,      // o0 = a0 + b0 (plaintext polynomial b0), o1 = a1
@@ -98,6 +98,8 @@ struct EwJob {
   const double* f1;
   const double* k;   // per-limb constants (canonical residues) or null
   const double* k2;  // second per-limb constant table or null
+  const double* g0;  // EW_TENSOR2 with k set: the addend is f k[l] + g k2[l] (g optional)
+  const double* g1;
   int n_limbs, n_chain;
   int op, l_first;   // limbs below l_first are left untouched
 };

@@ -1031,6 +1031,7 @@ __global__ __launch_bounds__(256) void k_ew(const EwJob* __restrict__ jobs, DevT
         const double2 c0 = J.c0 ? ld2(J.c0, o) : z2, c1 = J.c0 ? ld2(J.c1, o) : z2;
         const double2 e0 = J.c0 ? ld2(J.e0, o) : z2, e1 = J.c0 ? ld2(J.e1, o) : z2;
         const double2 f0 = J.f0 ? ld2(J.f0, o) : z2, f1 = J.f0 ? ld2(J.f1, o) : z2;
+        const double2 g0 = J.g0 ? ld2(J.g0, o) : z2, g1 = J.g0 ? ld2(J.g1, o) : z2;
         double r0x = mul_mod(a0.x, b0.x, m), r0y = mul_mod(a0.y, b0.y, m);
         double r1x = mul_mod(a0.x, b1.x, m) + mul_mod(a1.x, b0.x, m);
         double r1y = mul_mod(a0.y, b1.y, m) + mul_mod(a1.y, b0.y, m);
@@ -1044,10 +1045,23 @@ __global__ __launch_bounds__(256) void k_ew(const EwJob* __restrict__ jobs, DevT
           r2y += mul_mod(c1.y, e1.y, m);
         }
         if (J.f0) {
-          r0x += f0.x;
-          r0y += f0.y;
-          r1x = red(r1x, m) + f1.x;
-          r1y = red(r1y, m) + f1.y;
+          double fx0 = f0.x, fy0 = f0.y, fx1 = f1.x, fy1 = f1.y;
+          if (J.k) {
+            // the addend is a constant combination, formed as EW_LIN2 forms it
+            fx0 = mul_mod(f0.x, kk, m); fy0 = mul_mod(f0.y, kk, m);
+            fx1 = mul_mod(f1.x, kk, m); fy1 = mul_mod(f1.y, kk, m);
+            if (J.g0) {
+              const double k2 = KPTR(J.k2)[l];
+              fx0 += mul_mod(g0.x, k2, m); fy0 += mul_mod(g0.y, k2, m);
+              fx1 += mul_mod(g1.x, k2, m); fy1 += mul_mod(g1.y, k2, m);
+            }
+            fx0 = canon(fx0, m); fy0 = canon(fy0, m);
+            fx1 = canon(fx1, m); fy1 = canon(fy1, m);
+          }
+          r0x += fx0;
+          r0y += fy0;
+          r1x = red(r1x, m) + fx1;
+          r1y = red(r1y, m) + fy1;
         }
         st2(J.o0, o, canon(r0x, m), canon(r0y, m));
         st2(J.o1, o, canon(r1x, m), canon(r1y, m));

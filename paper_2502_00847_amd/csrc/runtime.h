@@ -262,14 +262,18 @@ class Builder {
     const double* sq0 = nullptr;
     const double* sq1 = nullptr;
   };
-  struct TensorItem {
-    CT a, b, c, e, f;
-    bool has_ce, has_f;
-  };
   struct LinItem {
     CT a, b;
     double va, vb, target;
     bool has_b;
+  };
+  // has_fl: the degree-1 addend is the (unrescaled) constant combination fl,
+  // formed inside the degree-2 sum instead of being written out first
+  struct TensorItem {
+    CT a, b, c, e, f;
+    bool has_ce, has_f;
+    LinItem fl{};
+    bool has_fl = false;
   };
   // merged: the conversion that follows reads limbs level .. level+n_p of the
   // accumulator (merged relinearise + rescale), else the special limbs only;

@@ -739,6 +739,8 @@ std::vector<CT> Builder::relin_rescale(const std::vector<Deg2>& xs) {
 
 // degree-2 sums: for each item, x.a (x) x.b [+ x.c (x) x.e] [+ x.f] at the
 // lowest level among the operands
+static int64_t const_for(double v, double target, double q, double s, bool rescale, bool& ok);
+
 std::vector<Builder::Deg2> Builder::tensor2(const std::vector<TensorItem>& v) {
   const int N = C.N;
   std::vector<Deg2> out;
@@ -755,6 +757,12 @@ std::vector<Builder::Deg2> Builder::tensor2(const std::vector<TensorItem>& v) {
       if (it.f.level < l) { fail(-1, "addend below the product level"); return {}; }
       if (fabs(sc - it.f.scale) > 1e-9 * fabs(sc)) { fail(-1, "scale mismatch in degree-2 sum"); return {}; }
     }
+    if (it.has_fl) {
+      const LinItem& L = it.fl;
+      if (L.has_b && L.b.level != L.a.level) { fail(-1, "lincomb: level mismatch"); return {}; }
+      if (L.a.level < l) { fail(-1, "addend below the product level"); return {}; }
+      if (fabs(sc - L.target) > 1e-9 * fabs(sc)) { fail(-1, "scale mismatch in degree-2 sum"); return {}; }
+    }
     Deg2 d{};
     d.level = l;
     d.scale = sc;
@@ -767,6 +775,20 @@ std::vector<Builder::Deg2> Builder::tensor2(const std::vector<TensorItem>& v) {
     e.b0 = c0(it.b); e.b1 = c1(it.b);
     if (it.has_ce) { e.c0 = c0(it.c); e.c1 = c1(it.c); e.e0 = c0(it.e); e.e1 = c1(it.e); }
     if (it.has_f) { e.f0 = c0(it.f); e.f1 = c1(it.f); }
+    if (it.has_fl) {
+      // the constants EW_LIN2 would use for the same combination (unrescaled)
+      const LinItem& L = it.fl;
+      bool ok1 = true, ok2 = true;
+      const int64_t Ka = const_for(L.va, L.target, 0.0, L.a.scale, false, ok1);
+      const int64_t Kb = L.has_b ? const_for(L.vb, L.target, 0.0, L.b.scale, false, ok2) : 0;
+      if (!ok1 || !ok2) { fail(-1, "constant does not fit 64 bits"); return {}; }
+      e.f0 = c0(L.a); e.f1 = c1(L.a);
+      e.k = put_residues(Ka, l + 1);
+      if (L.has_b) {
+        e.g0 = c0(L.b); e.g1 = c1(L.b);
+        e.k2 = put_residues(Kb, l + 1);
+      }
+    }
     e.n_limbs = l + 1; e.n_chain = l + 1;
     e.op = EW_TENSOR2;
     j.push_back(e);
@@ -1203,7 +1225,7 @@ std::vector<CT> Builder::refresh(const std::vector<CT>& in, const std::vector<ui
 // odd degree-9 polynomial p(x) = (c1 x + c3 x^3) + x^4 (c5 x + c7 x^3) + x^8 (c9 x):
 // baby steps x^2, x^3, x^4, giant step x^8 (three rounds of merged
 // relinearise + rescale); B and C as constant combinations rescaled once, A
-// unrescaled at the products' scale; x^4 B + x^8 C + A as one degree-2 sum,
+// unrescaled at the products' scale (formed inside the sum); x^4 B + x^8 C + A as one degree-2 sum,
 // relinearised and rescaled once.  Depth 4, five relinearisations; output at
 // level l-4 carrying (target q_{l-3}) / q_{l-3}.
 std::vector<CT> Builder::eval_odd9(const std::vector<CT>& xs, const std::vector<const double*>& coef,
@@ -1247,9 +1269,6 @@ std::vector<CT> Builder::eval_odd9(const std::vector<CT>& xs, const std::vector<
   }
   std::vector<CT> kbc = lincomb(bc, true);
   if (err_code) return {};
-  std::vector<CT> ka = lincomb(a, false);
-  if (err_code) return {};
-  for (auto& v : x3) free_ct(v);
   const size_t mark = scratch_mark();
   std::vector<TensorItem> ti;
   for (size_t i = 0; i < n; ++i) {
@@ -1259,19 +1278,19 @@ std::vector<CT> Builder::eval_odd9(const std::vector<CT>& xs, const std::vector<
     t.c = x8[i];
     t.e = kbc[2 * i + 1];
     t.has_ce = true;
-    t.f = ka[i];
-    t.has_f = true;
+    t.fl = a[i];   // A is formed inside the degree-2 sum
+    t.has_fl = true;
     ti.push_back(t);
   }
   std::vector<Deg2> d = tensor2(ti);
   if (err_code) return {};
+  for (auto& v : x3) free_ct(v);
   std::vector<CT> res = relin_rescale(d);
   if (err_code) return {};
   scratch_release(mark);
   for (size_t i = 0; i < n; ++i) {
     free_ct(kbc[2 * i]);
     free_ct(kbc[2 * i + 1]);
-    free_ct(ka[i]);
     free_ct(x4[i]);
     free_ct(x8[i]);
   }
