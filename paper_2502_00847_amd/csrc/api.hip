@@ -1568,24 +1568,50 @@ extern "C" int secpe_boot_setup(secpe_ctx* x, void* buf_dev, size_t bytes) {
       const int nl = G.level + 1;
       auto fn = [&](Builder& b) {
         std::vector<EncodeJob> j_enc;
+        std::vector<FftEncJob> j_fft;
         std::vector<IntSpreadJob> j_sp;
         std::vector<NttJob> j_ntt;
+        // diagonals with many nonzero slots go through one length-2N FFT each
+        // (O(N log N) instead of O(N nnz)), in groups that share one buffer
+        constexpr int kFftMinSlots = 256, kFftGroup = 32;
+        double* fft_buf = nullptr;
         for (size_t i = 0; i < G.pt.size(); ++i) {
           int64_t* m = (int64_t*)b.scratch(N);
-          EncodeJob ej{};
-          ej.z = b.put(re[i]);
-          ej.zi = b.put(im[i]);
-          ej.gs = b.put(gs[i]);
-          ej.nnz = (int)re[i].size();
-          ej.m = m;
-          ej.scale_hi = G.pscale * 2.0 / (double)N;
-          ej.scale_lo = 0.0;
-          j_enc.push_back(ej);
+          const int nnz = (int)re[i].size();
+          const double sc = G.pscale * 2.0 / (double)N;   // exact: N is a power of two
+          if (nnz > kFftMinSlots) {
+            if (!fft_buf) fft_buf = b.scratch((size_t)kFftGroup * 16 * N);
+            FftEncJob fj{};
+            fj.z = b.put(re[i]);
+            fj.zi = b.put(im[i]);
+            fj.gs = b.put(gs[i]);
+            fj.nnz = nnz;
+            fj.m = m;
+            fj.buf = fft_buf + (size_t)(j_fft.size() % kFftGroup) * 16 * N;
+            fj.scale_hi = sc;
+            fj.scale_lo = 0.0;
+            j_fft.push_back(fj);
+          } else {
+            EncodeJob ej{};
+            ej.z = b.put(re[i]);
+            ej.zi = b.put(im[i]);
+            ej.gs = b.put(gs[i]);
+            ej.nnz = nnz;
+            ej.m = m;
+            ej.scale_hi = sc;
+            ej.scale_lo = 0.0;
+            j_enc.push_back(ej);
+          }
           double* pt = (double*)G.pt[i];
           j_sp.push_back(IntSpreadJob{m, pt, nl, nl});
           j_ntt.push_back(NttJob{pt, pt, nl, nl, 0, 0});
         }
         b.encode(j_enc);
+        // groups run one after another on the stream, so they can share the buffer
+        for (size_t g0 = 0; g0 < j_fft.size(); g0 += kFftGroup) {
+          const size_t g1 = std::min(j_fft.size(), g0 + (size_t)kFftGroup);
+          b.fft_encode(std::vector<FftEncJob>(j_fft.begin() + g0, j_fft.begin() + g1));
+        }
         b.intspread(j_sp);
         b.ntt(j_ntt, false);
       };

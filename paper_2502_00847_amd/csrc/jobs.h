@@ -191,6 +191,22 @@ struct EncodeJob {
   const double* zi;     // optional [nnz] imaginary parts
 };
 
+// Dense complex encoding through one length-2N FFT in double-double (the
+// bootstrapping set-up's diagonals, every slot nonzero): the sum that
+// EncodeJob forms term by term, sum_j z_j cos(pi g_j k / N) + zi_j sin(pi g_j k / N),
+// is Re X[k] of X[k] = sum_t A[t] e^(i pi t k / N) with A[g_j] = z_j - i zi_j
+// (the g_j = 5^j mod 2N are distinct) and A zero elsewhere.  buf holds two
+// sets of four planes (re hi, re lo, im hi, im lo) of 2N doubles each.
+struct FftEncJob {
+  const double* z;       // [nnz]
+  const double* zi;      // [nnz]
+  const uint32_t* gs;    // [nnz]
+  double* buf;           // [2][4][2N]
+  int64_t* m;            // [N]
+  double scale_hi, scale_lo;   // scale * 2 / N as a double-double
+  int nnz, pad;
+};
+
 // one baby-step giant-step group of a linear transform on one ciphertext:
 // out_G = sum_b pt[G * 8 + b] * x_b (both polynomials), for giant index
 // G < n_giants and baby step b < n1 (a null pt skips the term); NTT domain

@@ -33,6 +33,8 @@ void launch_bsgs(const DevTables& T, const BsgsJob* jobs, int n_jobs, int max_li
 void launch_sample(const DevTables& T, const SampleJob* jobs, int n_jobs, int max_limbs, hipStream_t s);
 void launch_int_spread(const DevTables& T, const IntSpreadJob* jobs, int n_jobs, int max_limbs, hipStream_t s);
 void launch_encode(const DevTables& T, const EncodeJob* jobs, int n_jobs, hipStream_t s);
+// phase: -2 zero, -1 scatter, 0 .. log2(2N)-1 FFT stages, 1000 round (FftEncJob)
+void launch_fft_enc(const DevTables& T, const FftEncJob* jobs, int n_jobs, int phase, hipStream_t s);
 void launch_decode(const DevTables& T, const int64_t* m, double* z, int nslots, double inv_scale, hipStream_t s);
 
 }  // namespace secpe

@@ -1429,6 +1429,17 @@ __device__ __forceinline__ void dd_mul(double ah, double al, double bh, double b
   ph = p + e;
   pl = e - (ph - p);
 }
+// (sh + sl)(kh + kl) rounded half away from zero, as an integer
+__device__ __forceinline__ int64_t dd_scale_round(double sh, double sl, double kh, double kl) {
+  double yh, yl;
+  dd_mul(sh, sl, kh, kl, yh, yl);
+  const bool negv = yh < 0.0 || (yh == 0.0 && yl < 0.0);
+  if (negv) { yh = -yh; yl = -yl; }
+  const double f = floor(yh);
+  const double frac = (yh - f) + yl + 0.5;
+  const int64_t v = (int64_t)f + (int64_t)floor(frac);
+  return negv ? -v : v;
+}
 
 __global__ __launch_bounds__(256) void k_encode(const EncodeJob* __restrict__ jobs, DevTables T) {
   const EncodeJob J = jobs[blockIdx.z];
@@ -1459,14 +1470,73 @@ __global__ __launch_bounds__(256) void k_encode(const EncodeJob* __restrict__ jo
     }
     g = (g * 5u) & mask;
   }
-  double yh, yl;
-  dd_mul(sh, sl, J.scale_hi, J.scale_lo, yh, yl);
-  const bool negv = yh < 0.0 || (yh == 0.0 && yl < 0.0);
-  if (negv) { yh = -yh; yl = -yl; }
-  const double f = floor(yh);
-  const double frac = (yh - f) + yl + 0.5;
-  const int64_t v = (int64_t)f + (int64_t)floor(frac);
-  J.m[k] = negv ? -v : v;
+  J.m[k] = dd_scale_round(sh, sl, J.scale_hi, J.scale_lo);
+}
+
+// ---- dense encoding through a length-2N Stockham FFT (FftEncJob) ----
+// phase -2: zero the first plane set; -1: scatter A; s >= 0: radix-2 stage s
+// (butterfly j: p = j >> s, q = j mod 2^s, length-2N data, m = N >> s):
+//   y[q + 2^s 2p] = a + b,  y[q + 2^s (2p+1)] = (a - b) w^(p 2^s),  w = e^(i pi / N),
+//   a = x[q + 2^s p], b = x[q + 2^s (p + m)]   (ping-pong between the plane sets);
+// phase 1000: Re X[k] for k < N, scaled and rounded half away from zero.
+__global__ __launch_bounds__(256) void k_fft_enc(const FftEncJob* __restrict__ jobs, DevTables T, int phase) {
+  const FftEncJob J = jobs[blockIdx.y];
+  const int log_n = T.log_n;
+  const int N = 1 << log_n;
+  const int L = 2 * N;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double* P0 = J.buf;
+  double* P1 = J.buf + 4 * (size_t)L;
+  if (phase == -2) {
+    if (i < L) P0[i] = P0[L + i] = P0[2 * L + i] = P0[3 * L + i] = 0.0;
+    return;
+  }
+  if (phase == -1) {
+    if (i < J.nnz) {
+      const uint32_t t = J.gs[i];
+      P0[t] = J.z[i];
+      P0[2 * L + t] = -J.zi[i];
+    }
+    return;
+  }
+  if (phase == 1000) {
+    if (i >= N) return;
+    const double* X = ((log_n + 1) & 1) ? P1 : P0;   // log2(2N) stages
+    J.m[i] = dd_scale_round(X[i], X[L + i], J.scale_hi, J.scale_lo);
+    return;
+  }
+  const int st = phase;
+  if (i >= N) return;
+  const double* x = (st & 1) ? P1 : P0;
+  double* y = (st & 1) ? P0 : P1;
+  const int sp = 1 << st;
+  const int p = i >> st, q = i & (sp - 1);
+  const int m = N >> st;
+  const int ia = q + sp * p, ib = q + sp * (p + m);
+  const int o0 = q + sp * 2 * p, o1 = o0 + sp;
+  double arh = x[ia], arl = x[L + ia], aih = x[2 * L + ia], ail = x[3 * L + ia];
+  const double brh = x[ib], brl = x[L + ib], bih = x[2 * L + ib], bil = x[3 * L + ib];
+  // difference first (a is overwritten by the sum)
+  double drh = arh, drl = arl, dih = aih, dil = ail;
+  dd_add(drh, drl, -brh, -brl);
+  dd_add(dih, dil, -bih, -bil);
+  dd_add(arh, arl, brh, brl);
+  dd_add(aih, ail, bih, bil);
+  y[o0] = arh; y[L + o0] = arl; y[2 * L + o0] = aih; y[3 * L + o0] = ail;
+  const uint32_t mask = (uint32_t)L - 1u;
+  const uint32_t t = ((uint32_t)p << st) & mask;
+  const uint32_t ts = (t + 3u * (uint32_t)N / 2u) & mask;
+  const double wrh = T.cos_hi[t], wrl = T.cos_lo[t], wih = T.cos_hi[ts], wil = T.cos_lo[ts];
+  // (dr + i di)(wr + i wi) = (dr wr - di wi) + i (dr wi + di wr)
+  double rh, rl, uh, ul;
+  dd_mul(drh, drl, wrh, wrl, rh, rl);
+  dd_mul(dih, dil, wih, wil, uh, ul);
+  dd_add(rh, rl, -uh, -ul);
+  double ih, il, vh, vl;
+  dd_mul(drh, drl, wih, wil, ih, il);
+  dd_mul(dih, dil, wrh, wrl, vh, vl);
+  dd_add(ih, il, vh, vl);
+  y[o1] = rh; y[L + o1] = rl; y[2 * L + o1] = ih; y[3 * L + o1] = il;
 }
 
 // decode of slots [0, nslots): z_j = (1/scale) sum_k m_k cos(pi (5^j k mod 2N) / N)
@@ -1629,6 +1699,14 @@ void launch_encode(const DevTables& T, const EncodeJob* jobs, int n_jobs, hipStr
   if (n_jobs <= 0) return;
   dim3 grid((1 << T.log_n) / 256, 1, n_jobs);
   hipLaunchKernelGGL(k_encode, grid, dim3(256), 0, s, jobs, T);
+}
+void launch_fft_enc(const DevTables& T, const FftEncJob* jobs, int n_jobs, int phase, hipStream_t s) {
+  if (n_jobs <= 0) return;
+  const int N = 1 << T.log_n;
+  // zeroing covers 2N elements; scatter covers N/2 slots; stages and rounding N
+  const int work = phase == -2 ? 2 * N : phase == -1 ? N / 2 : N;
+  dim3 grid((work + 255) / 256, n_jobs, 1);
+  hipLaunchKernelGGL(k_fft_enc, grid, dim3(256), 0, s, jobs, T, phase);
 }
 void launch_decode(const DevTables& T, const int64_t* m, double* z, int nslots, double inv_scale, hipStream_t s) {
   if (nslots <= 0) return;

@@ -146,7 +146,7 @@ void destroy_context(Ctx& c);
 // ---------------------------------------------------------------------------
 // command list: descriptors in one blob, launches replayed in order
 // ---------------------------------------------------------------------------
-enum CmdKind { C_NTT, C_NTT_FIRST, C_NTT_SECOND, C_EW, C_MODUP, C_MODUP_COL, C_MODDOWN, C_INNER, C_INNER_ROW, C_AUTO, C_LIFT, C_SAMPLE, C_INTSPREAD, C_ENCODE, C_DECODE, C_RAISE, C_BSGS };
+enum CmdKind { C_NTT, C_NTT_FIRST, C_NTT_SECOND, C_EW, C_MODUP, C_MODUP_COL, C_MODDOWN, C_INNER, C_INNER_ROW, C_AUTO, C_LIFT, C_SAMPLE, C_INTSPREAD, C_ENCODE, C_DECODE, C_RAISE, C_BSGS, C_FFTENC };
 
 struct Cmd {
   int kind;
@@ -229,6 +229,8 @@ class Builder {
   void sample(const std::vector<SampleJob>& v);
   void intspread(const std::vector<IntSpreadJob>& v);
   void encode(const std::vector<EncodeJob>& v);
+  // dense encodings through a length-2N FFT (max_y of each command = its phase)
+  void fft_encode(const std::vector<FftEncJob>& v);
   void decode(const int64_t* m, double* z, int nslots, double inv_scale);
 
   // CKKS operations over batches of items

@@ -445,6 +445,15 @@ void Builder::intspread(const std::vector<IntSpreadJob>& v) {
   PUSH_JOBS(C_INTSPREAD, v, my, false, 0);
 }
 void Builder::encode(const std::vector<EncodeJob>& v) { PUSH_JOBS(C_ENCODE, v, 1, false, 0); }
+void Builder::fft_encode(const std::vector<FftEncJob>& v) {
+  if (v.empty()) return;
+  const size_t off = (size_t)((const char*)put(v) - arena_);
+  const int n = (int)v.size();
+  push(C_FFTENC, n, -2, off);
+  push(C_FFTENC, n, -1, off);
+  for (int st = 0; st <= C.T.log_n; ++st) push(C_FFTENC, n, st, off);
+  push(C_FFTENC, n, 1000, off);
+}
 void Builder::decode(const int64_t* m, double* z, int nslots, double inv_scale) {
   Cmd c{};
   c.kind = C_DECODE;
@@ -551,6 +560,7 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
       case C_SAMPLE: launch_sample(T, (const SampleJob*)j, k.n, k.max_y, s); break;
       case C_INTSPREAD: launch_int_spread(T, (const IntSpreadJob*)j, k.n, k.max_y, s); break;
       case C_ENCODE: launch_encode(T, (const EncodeJob*)j, k.n, s); break;
+      case C_FFTENC: launch_fft_enc(T, (const FftEncJob*)j, k.n, k.max_y, s); break;
       case C_DECODE: launch_decode(T, k.m, k.z, k.n, k.inv_scale, s); break;
       default: break;
     }
