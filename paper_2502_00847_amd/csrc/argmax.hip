@@ -189,9 +189,8 @@ static void run_step(Builder& b, int kind, std::vector<QState*>& qs) {
       std::vector<CT> r = b.rotate(in, st);
       if (b.err_code) return;
       for (size_t i = 0; i < n; ++i) pr.push_back({r[i], qs[i]->ym});
-      std::vector<CT> d = b.add(pr, true);
-      if (b.err_code) return;
-      std::vector<CT> sm = b.add(pr, false);
+      std::vector<CT> d, sm;
+      b.add_sub(pr, d, sm);
       if (b.err_code) return;
       for (size_t i = 0; i < n; ++i) {
         QState* s = qs[i];

@@ -80,6 +80,7 @@ enum EwOp : int {
   EW_LIN2 = 15,      // o_i = a_i k[l] + b_i k2[l]   (b optional)
   EW_PADD = 16,      // o0 = a0 + b0 (plaintext polynomial b0), o1 = a1
   EW_PMAC = 17,      // o_i = a_i * b0 + c_i (plaintext product accumulated; c may alias o)
+  EW_ADDSUB = 18,    // o0 = a0 - b0, o1 = a0 + b0 (one polynomial: difference and sum from one read)
 };
 
 struct EwJob {

@@ -963,6 +963,12 @@ __global__ __launch_bounds__(256) void k_ew(const EwJob* __restrict__ jobs, DevT
         st2(J.o1, o, add_mod(a1.x, b1.x, m), add_mod(a1.y, b1.y, m));
         break;
       }
+      case EW_ADDSUB: {
+        const double2 a0 = ld2(J.a0, o), b0 = ld2(J.b0, o);
+        st2(J.o0, o, sub_mod(a0.x, b0.x, m), sub_mod(a0.y, b0.y, m));
+        st2(J.o1, o, add_mod(a0.x, b0.x, m), add_mod(a0.y, b0.y, m));
+        break;
+      }
       case EW_SUB: {
         const double2 a0 = ld2(J.a0, o), b0 = ld2(J.b0, o), a1 = ld2(J.a1, o), b1 = ld2(J.b1, o);
         st2(J.o0, o, sub_mod(a0.x, b0.x, m), sub_mod(a0.y, b0.y, m));

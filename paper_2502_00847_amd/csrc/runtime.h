@@ -300,6 +300,8 @@ class Builder {
   std::vector<CT> mul_relin(const std::vector<std::pair<CT, CT>>& ab, bool do_rescale);
   std::vector<CT> rotate(const std::vector<CT>& in, const std::vector<int64_t>& steps);
   std::vector<CT> add(const std::vector<std::pair<CT, CT>>& ab, bool sub);
+  // a - b and a + b of each pair from one read of a and b
+  void add_sub(const std::vector<std::pair<CT, CT>>& ab, std::vector<CT>& diff, std::vector<CT>& sum);
   std::vector<CT> add_const(const std::vector<CT>& in, const std::vector<double>& v);
   std::vector<CT> mul_const(const std::vector<CT>& in, const std::vector<double>& v, const std::vector<double>& target);
   std::vector<CT> mul_plain(const std::vector<CT>& in, const std::vector<std::vector<double>>& z,

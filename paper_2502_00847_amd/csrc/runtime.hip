@@ -978,6 +978,32 @@ std::vector<CT> Builder::add(const std::vector<std::pair<CT, CT>>& ab, bool sub)
   return out;
 }
 
+void Builder::add_sub(const std::vector<std::pair<CT, CT>>& ab, std::vector<CT>& diff, std::vector<CT>& sum) {
+  diff.clear();
+  sum.clear();
+  std::vector<EwJob> j;
+  for (auto& p : ab) {
+    const double sa = p.first.scale, sb = p.second.scale;
+    if (fabs(sa - sb) > 1e-9 * fabs(sa)) { fail(-1, "scale mismatch in addition"); return; }
+    const int l = std::min(p.first.level, p.second.level);
+    CT d = new_ct(l, sa);
+    CT s = new_ct(l, sa);
+    for (int w = 0; w < 2; ++w) {
+      EwJob e{};
+      e.o0 = w ? c1(d) : c0(d);
+      e.o1 = w ? c1(s) : c0(s);
+      e.a0 = w ? c1(p.first) : c0(p.first);
+      e.b0 = w ? c1(p.second) : c0(p.second);
+      e.n_limbs = l + 1; e.n_chain = l + 1;
+      e.op = EW_ADDSUB;
+      j.push_back(e);
+    }
+    diff.push_back(d);
+    sum.push_back(s);
+  }
+  ew(j);
+}
+
 std::vector<CT> Builder::add_const(const std::vector<CT>& in, const std::vector<double>& v) {
   std::vector<CT> out;
   std::vector<EwJob> j;
@@ -1195,7 +1221,7 @@ std::vector<CT> Builder::refresh(const std::vector<CT>& in, const std::vector<ui
   std::vector<NttJob> j_inv, j_fwd, j_fwd2;
   std::vector<LiftJob> j_lift;
   std::vector<SampleJob> j_s;
-  std::vector<EwJob> j_enc;
+  std::vector<EwJob> j_me, j_enc;
   for (size_t i = 0; i < in.size(); ++i) {
     const CT& x = in[i];
     if (x.level < 1) { fail(-3, "refresh needs two limbs"); return {}; }
@@ -1212,12 +1238,16 @@ std::vector<CT> Builder::refresh(const std::vector<CT>& in, const std::vector<ui
     const uint64_t tag = (5ull << 56) | ((index[i] & 0xFFFull) << 12);
     j_s.push_back(SampleJob{c1(o), seed[i], tag, L, L, SAMPLE_UNIFORM, 0});
     j_s.push_back(SampleJob{e, seed[i], tag, L, L, SAMPLE_CBD, 0});
+    // m + e is formed in the coefficient domain, so one transform serves both
+    EwJob me{};
+    me.o0 = mm; me.a0 = mm; me.b0 = e;
+    me.n_limbs = L; me.n_chain = L; me.op = EW_PADD;
+    j_me.push_back(me);
     j_fwd.push_back(NttJob{mm, mm, L, L, 0, 0});
-    j_fwd.push_back(NttJob{e, e, L, L, 0, 0});
     j_fwd.push_back(NttJob{c1(o), c1(o), L, L, 0, 0});
     EwJob w{};
-    w.o0 = c0(o); w.a0 = mm; w.a1 = e; w.b0 = c1(o); w.b1 = rsk;
-    w.n_limbs = L; w.n_chain = L; w.op = EW_ENC;
+    w.o0 = c0(o); w.a1 = mm; w.b0 = c1(o); w.b1 = rsk;   // (m + e) - a s
+    w.n_limbs = L; w.n_chain = L; w.op = EW_KEYB;
     j_enc.push_back(w);
     out.push_back(o);
   }
@@ -1225,6 +1255,7 @@ std::vector<CT> Builder::refresh(const std::vector<CT>& in, const std::vector<ui
   ntt(j_inv, true);
   lift(j_lift);
   sample(j_s);
+  ew(j_me);
   ntt(j_fwd, false);
   ew(j_enc);
   counters[4] += (int64_t)in.size();
