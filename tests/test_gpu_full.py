@@ -126,6 +126,35 @@ def test_full_refresh_and_poly(full_pair):
     _same(g, g.refresh(gl, 99, 1), o.refresh(low, 99, 1))
 
 
+@pytest.mark.parametrize("level", [23, 12, 1])
+def test_full_lincomb_levels(full_pair, level):
+    """Constant combinations on the two-pass transform sizes: a rescaled one is
+    formed in the rescale's row-pass epilogue, an unrescaled one elementwise;
+    one and two terms, at the top, a middle and the lowest rescalable level."""
+    g, o = full_pair
+    rng = np.random.default_rng(60 + level)
+    sb = 2.0**50 * 0.997
+    a = o.lower(o.encrypt(o.encode(rng.uniform(-1, 1, 64), 2.0**50), 2.0**50, 61), level)
+    b = o.lower(o.encrypt(o.encode(rng.uniform(-1, 1, 64), sb), sb, 62), level)
+    ga, gb = g.import_(a.export(), a.scale), g.import_(b.export(), b.scale)
+    for T, rs in ((2.0**50, True), (2.0**100 * 1.01, False)):
+        _same(g, g.lincomb(ga, 1.25, gb, 0.37, T, rs), o.lincomb(a, 1.25, b, 0.37, T, rs))
+        _same(g, g.lincomb(ga, -0.75, None, 0.0, T, rs), o.lincomb(a, -0.75, None, 0.0, T, rs))
+
+
+def test_full_eval_odd9(full_pair):
+    """One Sign polynomial on the two-pass sizes (fused squares, the degree-2
+    sum that forms its addend combination, combinations rescaled in the
+    epilogue, merged relinearise + rescale), for g and for f with the Max gain."""
+    g, o = full_pair
+    f, gg = sign_coeffs()
+    z = np.random.default_rng(63).uniform(-1, 1, 64)
+    a = o.lower(o.encrypt(o.encode(z, 2.0**50), 2.0**50, 64), 8)
+    ga = g.import_(a.export(), a.scale)
+    _same(g, g.eval_odd9(ga, gg, 1.0, 2.0**50), o.eval_odd9(a, gg, 1.0, 2.0**50))
+    _same(g, g.eval_odd9(ga, f, 0.5, 2.0**50 * 0.999), o.eval_odd9(a, f, 0.5, 2.0**50 * 0.999))
+
+
 @pytest.mark.parametrize("case", ["config2_full", "config3_full_q0"])
 def test_full_argmax_matches_oracle_digest(full_gpu, golden, case):
     """Config 2 (K=8, C=4, N=2^16, dnum 3): the whole encrypted Argmax is bit-exact with the oracle."""
