@@ -228,49 +228,52 @@ def sim_t0(logits):
 
 
 def variants(params):
-    """Higher-precision Sign ((d_g, d_f) = (4, 3), seven polynomials per Sign) on the
-    config-2 query, and a large-n Argmax (K = 4 prompts, C = 256 classes), alone."""
+    """Higher-precision Signs ((d_g, d_f) = (4, 3) and (5, 2), seven polynomials per
+    Sign) on the config-2 query, and large-n Argmax (K = 4 prompts, C = 256 and
+    1024 classes), each alone."""
     from paper_2502_00847_amd.secpe import Context
     out = {}
-    p43 = dict(params, dg=4, df=3)
-    g = Context(p43)
-    g.keygen(W.KEYGEN_SEED, g.argmax_steps(8, 4))
     d2 = W.query(2, 0)
-    ct = g.encrypt(d2["logits"], d2["encrypt_seed"])
-    ws = g.workspace([d2["K"]], [d2["C"]])
-    lat = []
-    for _ in range(4):
-        g.sync()
-        t0 = time.perf_counter()
-        z = g.eval_argmax(ct, d2["K"], d2["C"], d2["d_min"], d2["d_max"], d2["refresh_seed"], ws=ws)
-        g.sync()
-        lat.append((time.perf_counter() - t0) * 1e3)
-    zz, idx = g.decrypt(z, d2["C"])
     i0 = sim_t0(d2["logits"])[0]
     onehot = np.zeros(d2["C"])
     onehot[i0] = 1.0
-    out["precise_sign"] = {"dg_df": [4, 3], "config": "K=8, C=4", "ms": round(float(np.median(lat[1:])), 3),
-                           "index_ok": bool(idx == i0), "max_abs_z_minus_onehot": float(np.abs(zz - onehot).max())}
-    del g, ws, ct, z
+    for dg, df, key in ((4, 3, "precise_sign"), (5, 2, "precise_sign_5_2")):
+        g = Context(dict(params, dg=dg, df=df))
+        g.keygen(W.KEYGEN_SEED, g.argmax_steps(8, 4))
+        ct = g.encrypt(d2["logits"], d2["encrypt_seed"])
+        ws = g.workspace([d2["K"]], [d2["C"]])
+        lat = []
+        for _ in range(4):
+            g.sync()
+            t0 = time.perf_counter()
+            z = g.eval_argmax(ct, d2["K"], d2["C"], d2["d_min"], d2["d_max"], d2["refresh_seed"], ws=ws)
+            g.sync()
+            lat.append((time.perf_counter() - t0) * 1e3)
+        zz, idx = g.decrypt(z, d2["C"])
+        out[key] = {"dg_df": [dg, df], "config": "K=8, C=4", "ms": round(float(np.median(lat[1:])), 3),
+                    "index_ok": bool(idx == i0), "max_abs_z_minus_onehot": float(np.abs(zz - onehot).max())}
+        del g, ws, ct, z
+    K = 4
     g = Context(params)
-    K, C = 4, 256
-    g.keygen(W.KEYGEN_SEED, g.argmax_steps(K, C))
-    y = W.logits(6, 0, K, C)
+    g.keygen(W.KEYGEN_SEED, g.argmax_steps(K, 1024))
     lo, hi = W.d_bounds(K)
-    ct = g.encrypt(y, 6001)
-    ws = g.workspace([K], [C])
-    lat = []
-    for _ in range(3):
-        g.sync()
-        t0 = time.perf_counter()
-        z = g.eval_argmax(ct, K, C, lo, hi, 6002, ws=ws)
-        g.sync()
-        lat.append((time.perf_counter() - t0) * 1e3)
-    zz, idx = g.decrypt(z, C)
-    i0, _, margin = sim_t0(y)
-    out["large_n"] = {"K": K, "C": C, "ms": round(float(np.median(lat[1:])), 3), "index_ok": bool(idx == i0),
-                      "normalised_margin_log2": round(float(np.log2(margin / (hi - lo))), 2),
-                      "signs": g.counters()["sign"], "key_switches": g.counters()["key_switch"]}
+    for C, key in ((256, "large_n"), (1024, "large_n_1024")):
+        y = W.logits(6, 0 if C == 256 else 1, K, C)
+        ct = g.encrypt(y, 6001)
+        ws = g.workspace([K], [C])
+        lat = []
+        for _ in range(3):
+            g.sync()
+            t0 = time.perf_counter()
+            z = g.eval_argmax(ct, K, C, lo, hi, 6002, ws=ws)
+            g.sync()
+            lat.append((time.perf_counter() - t0) * 1e3)
+        zz, idx = g.decrypt(z, C)
+        j0, _, margin = sim_t0(y)
+        out[key] = {"K": K, "C": C, "ms": round(float(np.median(lat[1:])), 3), "index_ok": bool(idx == j0),
+                    "normalised_margin_log2": round(float(np.log2(margin / (hi - lo))), 2),
+                    "signs": g.counters()["sign"], "key_switches": g.counters()["key_switch"]}
+        del ws, ct, z
     return out
 
 
