@@ -24,6 +24,8 @@ def _params(name):
         return dict(log_n=13, n_q=8, q_bits=36, n_p=2, p_bits=51, log_scale=36, dg=2, df=2, min_level=1)
     if name == "tiny43":
         return dict(W.PARAMS["tiny"], dg=4, df=3)
+    if name == "tiny52":
+        return dict(W.PARAMS["tiny"], dg=5, df=2)
     if name == "p13_r6":
         return dict(_params("p13"), refresh_level=6)
     if name == "p14":
@@ -321,10 +323,11 @@ def test_packed_argmax_bit_exact(name, tiny, p13):
                 assert idx == i0
 
 
-def test_argmax_precise_sign_bit_exact():
-    """Higher-precision Sign, (d_g, d_f) = (4, 3) (seven polynomials per Sign): the
-    whole Algorithm 1 matches the oracle bit for bit."""
-    g, o, _ = _pair("tiny43", 4, 8)
+@pytest.mark.parametrize("name", ["tiny43", "tiny52"])
+def test_argmax_precise_sign_bit_exact(name):
+    """Higher-precision Signs, (d_g, d_f) = (4, 3) and (5, 2) (seven polynomials per
+    Sign): the whole Algorithm 1 matches the oracle bit for bit."""
+    g, o, _ = _pair(name, 4, 8)
     for i, (K, C) in enumerate([(3, 5), (2, 2)]):
         y, zo, zg = _argmax_pair(g, o, K, C, q=400 + i)
         _same(g, zg, zo)
