@@ -692,7 +692,12 @@ def main():
         torch.cuda.empty_cache()
         for name, fn in (("variants", lambda: variants(params)), ("phoenix_vs_secpe", lambda: phoenix_compare(params)),
                          ("bootstrapping", bootstrap_rate)):
-            r = fn()
+            # a side measurement that fails is reported as such; the headline line still prints
+            try:
+                r = fn()
+            except Exception as e:  # noqa: BLE001
+                _log(f"{name} failed: {type(e).__name__}: {e}")
+                r = {name: {"error": f"{type(e).__name__}: {e}"}} if name == "variants" else {"error": f"{type(e).__name__}: {e}"}
             if name == "variants":
                 result.update(r)
             else:
