@@ -17,7 +17,8 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    path = oracle_lib_path()
+    # ORACLE_LIB selects another build of the same source (the sanitizer test)
+    path = os.environ.get("ORACLE_LIB") or oracle_lib_path()
     if not os.path.exists(path):
         build_oracle()
     lib = C.CDLL(path)
