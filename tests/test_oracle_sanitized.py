@@ -1,9 +1,13 @@
-"""The C oracle under AddressSanitizer and UndefinedBehaviorSanitizer (host
-code only): a separate process loads a sanitized build of the same source
-(built here with gcc) with the runtimes preloaded and runs
-a tiny Argmax, a key switch at every level, the Phoenix path, slot packing and a
-bootstrap; any sanitizer report fails the test.  Leak checking is off: the
-Python interpreter itself holds memory to exit."""
+"""Host code under AddressSanitizer and UndefinedBehaviorSanitizer.
+
+* The C oracle: a separate process loads a build of the same source made here
+  with gcc and the sanitizers (their runtimes preloaded) and runs a tiny
+  Argmax, a key switch at every level, the Phoenix path, slot packing and a
+  bootstrap.  Leak checking is off: the Python interpreter itself holds memory
+  to exit.
+* The host C++ that builds the bootstrapping tables (binary128), in a small
+  driver over every group of both transforms.
+Any sanitizer report fails the test."""
 import os
 import subprocess
 import sys
@@ -79,3 +83,41 @@ def test_oracle_under_asan_and_ubsan(tmp_path):
     assert "runtime error" not in r.stderr, report
     assert r.returncode == 0, report
     assert "sanitized oracle run complete" in r.stdout
+
+
+DRIVER = r"""
+#include <cstdio>
+#include "boot_tables.h"
+int main() {
+  // every group of both transforms at N = 2^10 and N = 2^12, 2 and 3 groups
+  double cheb[64];
+  for (int log_n : {10, 12})
+    for (int groups : {2, 3})
+      for (int inverse : {0, 1})
+        for (int g = 0; g < groups; ++g) {
+          secpe::BootGroupTable t = secpe::boot_group_table(log_n, groups, 12, 8, inverse, g);
+          if (t.diags.empty()) return 2;
+        }
+  secpe::boot_cheb_coeffs(24, 4, 31, cheb);
+  std::printf("tables ok %.3f\n", cheb[1]);
+  return 0;
+}
+"""
+
+
+@pytest.mark.timeout(600)
+def test_boot_tables_under_asan_and_ubsan(tmp_path):
+    """The host C++ that builds the bootstrapping tables (binary128), under
+    AddressSanitizer and UndefinedBehaviorSanitizer."""
+    csrc = os.path.join(ROOT, "paper_2502_00847_amd", "csrc")
+    drv = tmp_path / "drv.cpp"
+    drv.write_text(DRIVER)
+    exe = str(tmp_path / "drv")
+    subprocess.run(["g++", "-O1", "-g", "-fno-omit-frame-pointer", "-std=gnu++17", "-fsanitize=address,undefined",
+                    "-fno-sanitize-recover=undefined", "-I", csrc, str(drv), os.path.join(csrc, "boot_tables.cpp"),
+                    "-o", exe, "-lquadmath"], check=True)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=580,
+                       env=dict(os.environ, ASAN_OPTIONS="halt_on_error=1", UBSAN_OPTIONS="halt_on_error=1"))
+    assert "AddressSanitizer" not in r.stderr and "runtime error" not in r.stderr, r.stderr[-4000:]
+    assert r.returncode == 0 and "tables ok" in r.stdout, (r.returncode, r.stderr[-2000:])
+
