@@ -1525,22 +1525,25 @@ std::vector<CT> Builder::boot_transform(const std::vector<CT>& in, bool inverse)
         acc[rpos[k]] = rout[k];
       }
     }
+    // the sum over giant steps, one launch per giant for every item at once
     std::vector<CT> nxt;
-    for (size_t it = 0; it < n; ++it) {
-      if (ng == 1) {
-        nxt.push_back(acc[it]);
-        continue;
-      }
-      std::vector<CT> sum = add({{acc[it * ng], acc[it * ng + 1]}}, false);
+    if (ng == 1) {
+      for (size_t it = 0; it < n; ++it) nxt.push_back(acc[it]);
+    } else {
+      std::vector<std::pair<CT, CT>> pr;
+      for (size_t it = 0; it < n; ++it) pr.push_back({acc[it * ng], acc[it * ng + 1]});
+      std::vector<CT> sum = add(pr, false);
       if (err_code) return {};
       for (size_t gi = 2; gi < ng; ++gi) {
-        std::vector<CT> t = add({{sum[0], acc[it * ng + gi]}}, false);
+        pr.clear();
+        for (size_t it = 0; it < n; ++it) pr.push_back({sum[it], acc[it * ng + gi]});
+        std::vector<CT> t = add(pr, false);
         if (err_code) return {};
-        free_ct(sum[0]);
+        for (CT& v : sum) free_ct(v);
         sum = t;
       }
-      for (size_t gi = 0; gi < ng; ++gi) free_ct(acc[it * ng + gi]);
-      nxt.push_back(sum[0]);
+      for (size_t a = 0; a < n * ng; ++a) free_ct(acc[a]);
+      nxt = sum;
     }
     const size_t mark = scratch_mark();
     rescale(nxt);
