@@ -262,7 +262,9 @@ int secpe_sync(secpe_ctx* ctx);
    workspace of the admitted set fits (and at most max_active run), then
    advances every admitted request by one step of Algorithm 1 (the steps of
    different requests run in the same kernel launches), waits for the GPU and
-   returns the requests that completed.  A request's result is bit-identical
+   returns the requests that completed.  When that round holds little work
+   (few requests active), further rounds join the same submission until a
+   request completes or about 32 key-switches are queued.  A request's result is bit-identical
    to evaluating it alone.  The input ciphertext must stay valid until its
    request completes; out_data receives z (secpe_ct_bytes). */
 typedef struct secpe_server secpe_server;
@@ -272,8 +274,9 @@ void secpe_server_destroy(secpe_server* srv);
 size_t secpe_server_request_bytes(secpe_ctx* ctx, int K, int C);
 int secpe_server_submit(secpe_server* srv, const secpe_ct* in, int K, int C, double d_min, double d_max,
                         uint64_t refresh_seed, void* out_data, uint64_t* ticket);
-/* One round.  Writes up to 'cap' completed tickets with the level and scale of
-   their results; n_active / n_pending report the queue after the round. */
+/* One submission of one or more rounds.  Writes up to 'cap' completed
+   tickets with the level and scale of their results; n_active / n_pending
+   report the queue after the submission. */
 int secpe_server_step(secpe_server* srv, int cap, int* n_done, uint64_t* tickets, int* levels, double* scales,
                       int* n_active, int* n_pending);
 

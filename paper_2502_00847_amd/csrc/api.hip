@@ -1345,6 +1345,16 @@ extern "C" int secpe_server_step(secpe_server* s, int cap, int* n_done, uint64_t
   if (!s->active.empty()) {
     Builder b(c, s->ws, s->ws_bytes, s->arena, s->arena_bytes, false, &s->pool);
     std::vector<ArgmaxQuery*> done = s->prog.round(b, true);
+    // At light load a round is a few small launches, shorter than the host
+    // round trip that follows it: further rounds join the same submission
+    // until a request completes or the batch holds about 32 key-switches
+    // (a few ms of GPU time, the longest a new arrival then waits for
+    // admission).  Each request still advances through its own steps in
+    // order, so results are unchanged.
+    for (int r = 1; r < 64 && done.empty() && !b.err_code && s->prog.active() && b.counters[3] < 32 &&
+                    b.counters[7] < 1024 && b.blob_bytes() < s->arena_bytes / 4;
+         ++r)
+      done = s->prog.round(b, true);
     if (b.err_code) { s->broken = true; return set_err(b.err_code, b.err); }
     if (b.arena_overflow()) { s->broken = true; return set_err(SECPE_ENOMEM, "server descriptor arena overflow"); }
     int rc = submit(c, b, s->arena, s->arena_bytes);

@@ -83,7 +83,28 @@ def test_admission_by_memory_queues_requests(tiny_ctx):
 def test_server_rejects_oversized_request(tiny_ctx):
     from paper_2502_00847_amd.secpe import SecpeError, Server
     g = tiny_ctx
-    r = _request(g, 40)
+    r = _request(g, 44)
     srv = Server(g, g.ct_bytes() * 2, max_active=4)
     with pytest.raises(SecpeError):
         srv.submit(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"])
+
+
+def test_lone_request_runs_many_rounds_per_step(tiny_ctx):
+    """With one request active a step carries several rounds of its program
+    (a 16 x 16 query has 36 with two Sign compositions of each kind), with
+    the same bits as alone."""
+    from paper_2502_00847_amd.secpe import Server
+    g = tiny_ctx
+    r = _request(g, 44)
+    srv = Server(g, 2 * g.lib.secpe_server_request_bytes(g.h, r["K"], r["C"]), max_active=8)
+    t = srv.submit(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"])
+    steps = 0
+    while t not in srv.results:
+        srv.step()
+        steps += 1
+        assert steps < 200
+    assert (r["K"], r["C"]) == (16, 16) and steps <= 18
+    alone = g.eval_argmax(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"])
+    got = srv.results[t]
+    assert (got.level, got.scale) == (alone.level, alone.scale)
+    assert np.array_equal(g.export(got), g.export(alone))
