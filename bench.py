@@ -88,41 +88,75 @@ def cpu_baseline(ks_per_query, procs):
 # ---------------------------------------------------------------------------
 # serving: Poisson arrivals into the continuous-batching server
 # ---------------------------------------------------------------------------
-def serve(g, n, warm, qps=None, frac=0.7, max_active=96):
-    """Config 5 mix (K ~ U{4..32}, C ~ U{2..20}).  With qps=None the rate is
-    'frac' x the saturated throughput of the same mix, measured first by
-    submitting every request at once."""
-    from paper_2502_00847_amd.secpe import Server
-    total = n + warm
-    qs = [W.query(5, i) for i in range(total)]
-    cts = [g.encrypt(q["logits"], q["encrypt_seed"]) for q in qs]
-    g.sync()
-    per = max(g.lib.secpe_server_request_bytes(g.h, q["K"], q["C"]) for q in qs)
-    srv = Server(g, int(per * max_active * 1.05), max_active=max_active)
-    outs = [g.new_ct() for _ in range(total)]
+def tenant_contexts(g, params, n_tenants):
+    """The serving tenants: g plus n_tenants - 1 further contexts on the same
+    device, each with its own stream and its own resident keys (seeded per
+    tenant), all for the config-5 shapes."""
+    from paper_2502_00847_amd.secpe import Context
+    gs = [g]
+    for t in range(1, n_tenants):
+        h = Context(params)
+        h.keygen(W.KEYGEN_SEED + t, h.argmax_steps(32, 20))
+        gs.append(h)
+    return gs
 
-    def run(arrivals):
+
+def serve(gs, n, warm, qps=None, frac=0.7, max_active=96, distinct=256):
+    """Config 5 mix (K ~ U{4..32}, C ~ U{2..20}) over len(gs) tenants.  Query
+    i is config-5 query i mod 'distinct', encrypted under the keys of tenant
+    (i mod distinct) mod len(gs) and served by that tenant's server.  The
+    servers run on their own streams at the same time: each is collected as
+    soon as its submission ends (secpe_server_ready) and relaunched.  With qps=None the
+    rate is 'frac' x the saturated throughput of the same mix, measured first
+    with up to 2 x max_active requests outstanding (a closed loop)."""
+    from paper_2502_00847_amd.secpe import Server
+    T = len(gs)
+    total = n + warm
+    nd = min(distinct, total)
+    qs = [W.query(5, i) for i in range(nd)]
+    cts = [gs[i % T].encrypt(q["logits"], q["encrypt_seed"]) for i, q in enumerate(qs)]
+    for h in gs:
+        h.sync()
+    per = max(gs[0].lib.secpe_server_request_bytes(gs[0].h, q["K"], q["C"]) for q in qs)
+    cap = max(1, max_active // T)
+    srvs = [Server(h, int(per * cap * 1.05), max_active=cap) for h in gs]
+    free = [[] for _ in gs]   # output buffers of completed requests, per tenant
+
+    def run(arrivals, window=None):
         t0 = time.perf_counter()
-        arrive, finish = {}, {}
+        arrive, finish, owner = {}, {}, {}
+        launched = [False] * T
         nxt = 0
         while len(finish) < total:
             now = time.perf_counter() - t0
-            while nxt < total and arrivals[nxt] <= now:
-                q = qs[nxt]
-                t = srv.submit(cts[nxt], q["K"], q["C"], q["d_min"], q["d_max"], q["refresh_seed"], out=outs[nxt])
-                arrive[t] = arrivals[nxt]
+            while nxt < total and arrivals[nxt] <= now and (window is None or len(arrive) - len(finish) < window):
+                qi = nxt % nd
+                q, k = qs[qi], qi % T
+                out = free[k].pop() if free[k] else gs[k].new_ct()
+                t = srvs[k].submit(cts[qi], q["K"], q["C"], q["d_min"], q["d_max"], q["refresh_seed"], out=out)
+                arrive[(k, t)] = arrivals[nxt]
+                owner[(k, t)] = out
                 nxt += 1
-            if len(arrive) > len(finish):
-                done, _, _ = srv.step()
-                now = time.perf_counter() - t0
-                for t in done:
-                    finish[t] = now
-            elif nxt < total:
-                time.sleep(max(0.0, arrivals[nxt] - now))
+            # each server is collected as soon as its own submission ends and
+            # relaunched at once (no lockstep between tenants)
+            for k in range(T):
+                if launched[k] and srvs[k].ready():
+                    done, _, _ = srvs[k].collect()
+                    launched[k] = False
+                    now = time.perf_counter() - t0
+                    for t in done:
+                        finish[(k, t)] = now
+                        free[k].append(owner.pop((k, t)))
+                        srvs[k].results.pop(t, None)
+                if not launched[k] and srvs[k]._inputs:
+                    srvs[k].launch()
+                    launched[k] = True
+            if not any(launched) and nxt < total:
+                time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
         return arrive, finish
 
     if qps is None:
-        arrive, finish = run(np.zeros(total))
+        arrive, finish = run(np.zeros(total), window=2 * max_active)
         span = max(finish.values())
         qps = frac * total / span
         sat = total / span
@@ -134,11 +168,12 @@ def serve(g, n, warm, qps=None, frac=0.7, max_active=96):
     lat = np.array([(finish[t] - arrive[t]) * 1e3 for t in order])
     span = max(finish[t] for t in order) - min(arrive[t] for t in order)
     return {
-        "workload": "config5_poisson", "requests": n, "warmup_requests": warm, "qps": round(qps, 2),
+        "workload": "config5_poisson", "tenants": T, "requests": n, "warmup_requests": warm,
+        "distinct_queries": nd, "qps": round(qps, 2),
         "saturated_argmax_per_s": round(sat, 2) if sat else None,
         "throughput_argmax_per_s": round(len(order) / span, 2),
         "p50_ms": round(float(np.percentile(lat, 50)), 1), "p99_ms": round(float(np.percentile(lat, 99)), 1),
-        "max_active": max_active,
+        "max_active": cap * T,
     }
 
 
@@ -492,7 +527,8 @@ def main():
     ap.add_argument("--graph", type=int, default=0, help="replay captured hipGraphs in the timed steps")
     ap.add_argument("--cpu", type=int, default=1, help="run the CPU-oracle baseline")
     ap.add_argument("--cpu-procs", type=int, default=0)
-    ap.add_argument("--serve", type=int, default=160, help="requests in the serving run (0 = skip)")
+    ap.add_argument("--serve", type=int, default=2000, help="measured requests in the serving run (0 = skip)")
+    ap.add_argument("--tenants", type=int, default=4, help="serving tenants, each with its own keys and stream")
     ap.add_argument("--keyswitch", type=int, default=1, help="time 64 random-step rotations at 24 limbs")
     ap.add_argument("--calib", type=int, default=0, help="copy 1 GiB first (counter calibration kernel)")
     ap.add_argument("--variants", type=int, default=1, help="precise-Sign and large-n single-query runs")
@@ -683,16 +719,19 @@ def main():
         result["ntt"] = ntt_rate(g, params)
         result["keyswitch"] = keyswitch_rate(g, params)
     if args.serve:
-        _log(f"serving run: {args.serve} requests, Poisson arrivals at 0.7x the saturated rate")
-        result["serving"] = serve(g, args.serve, max(8, args.serve // 8))
+        gs = tenant_contexts(g, params, args.tenants)
+        _log(f"serving run: {args.tenants} tenants, {args.serve} + {args.serve // 10} warm-up requests, "
+             f"Poisson arrivals at 0.7x the saturated rate")
+        result["serving"] = serve(gs, args.serve, args.serve // 10)
         sat = result["serving"]["saturated_argmax_per_s"]
         sweep = []
         for frac in (0.25, 0.5, 0.9):
-            r = serve(g, max(40, args.serve // 2), max(8, args.serve // 16), qps=frac * sat)
+            r = serve(gs, 160, 20, qps=frac * sat)
             r["load"] = frac
             sweep.append(r)
         result["serving_sweep"] = {"what": "the same mix at fractions of the saturated rate", "runs": sweep}
         _log(f"serving sweep: {[(r['load'], r['p50_ms'], r['p99_ms']) for r in sweep]}")
+        del gs
     # the refresh stand-in, timed on its own: refreshes in one step (counters of
     # every chunk) and the time of one refresh of a level-1 ciphertext
     n_ref = 0

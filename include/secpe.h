@@ -279,6 +279,20 @@ int secpe_server_submit(secpe_server* srv, const secpe_ct* in, int K, int C, dou
    report the queue after the submission. */
 int secpe_server_step(secpe_server* srv, int cap, int* n_done, uint64_t* tickets, int* levels, double* scales,
                       int* n_active, int* n_pending);
+/* secpe_server_step in two halves, so that the host can keep several servers
+   busy at once (one per tenant, each on its own context and stream: launch
+   every server, then collect every server).  secpe_server_launch admits and
+   queues the submission without waiting (nothing to run is not an error);
+   calling it again before secpe_server_collect fails with SECPE_EINVAL.
+   secpe_server_collect waits for the server's stream and reports as
+   secpe_server_step does (n_done = 0 when nothing was launched). */
+int secpe_server_launch(secpe_server* srv);
+/* 1 when secpe_server_collect would not wait (the launched submission has
+   finished, or nothing is launched), 0 while it runs, negative on a device
+   error.  Lets the host relaunch each server as soon as its own work ends. */
+int secpe_server_ready(secpe_server* srv);
+int secpe_server_collect(secpe_server* srv, int cap, int* n_done, uint64_t* tickets, int* levels, double* scales,
+                         int* n_active, int* n_pending);
 
 /* ---- measurement ---- */
 /* Event profiler: while enabled, every launch of the given kind is bracketed

@@ -1241,6 +1241,8 @@ struct secpe_server {
   size_t arena_bytes = 0;
   uint64_t next_ticket = 1;
   bool broken = false;
+  bool launched = false;                // a submission awaits secpe_server_collect
+  std::vector<ArgmaxQuery*> finishing;  // requests that complete in it
 };
 
 static std::pair<int, size_t> request_need(secpe_ctx* x, int K, int C) {
@@ -1322,12 +1324,11 @@ extern "C" int secpe_server_submit(secpe_server* s, const secpe_ct* in, int K, i
   return 0;
 }
 
-extern "C" int secpe_server_step(secpe_server* s, int cap, int* n_done, uint64_t* tickets, int* levels, double* scales,
-                                 int* n_active, int* n_pending) {
+extern "C" int secpe_server_launch(secpe_server* s) {
   if (!s) return set_err(SECPE_EINVAL, "null server");
   if (s->broken) return set_err(SECPE_EDEVICE, "server stopped after an error");
+  if (s->launched) return set_err(SECPE_EINVAL, "collect the previous launch first");
   Ctx& c = s->x->c;
-  if (n_done) *n_done = 0;
   // admission: the admitted set's slots plus one round's scratch must fit
   while (!s->pending.empty() && (int)s->active.size() < s->max_active) {
     secpe_server::Req* r = s->pending.front().get();
@@ -1342,28 +1343,39 @@ extern "C" int secpe_server_step(secpe_server* s, int cap, int* n_done, uint64_t
     s->active[&r->q] = std::move(s->pending.front());
     s->pending.pop_front();
   }
-  if (!s->active.empty()) {
-    Builder b(c, s->ws, s->ws_bytes, s->arena, s->arena_bytes, false, &s->pool);
-    std::vector<ArgmaxQuery*> done = s->prog.round(b, true);
-    // At light load a round is a few small launches, shorter than the host
-    // round trip that follows it: further rounds join the same submission
-    // until a request completes or the batch holds about 32 key-switches
-    // (a few ms of GPU time, the longest a new arrival then waits for
-    // admission).  Each request still advances through its own steps in
-    // order, so results are unchanged.
-    for (int r = 1; r < 64 && done.empty() && !b.err_code && s->prog.active() && b.counters[3] < 32 &&
-                    b.counters[7] < 1024 && b.blob_bytes() < s->arena_bytes / 4;
-         ++r)
-      done = s->prog.round(b, true);
-    if (b.err_code) { s->broken = true; return set_err(b.err_code, b.err); }
-    if (b.arena_overflow()) { s->broken = true; return set_err(SECPE_ENOMEM, "server descriptor arena overflow"); }
-    int rc = submit(c, b, s->arena, s->arena_bytes);
-    if (rc) { s->broken = true; return set_err(SECPE_EDEVICE, "kernel submission failed"); }
-    memcpy(c.counters, b.counters, sizeof(c.counters));
-    rc = sync(c);
+  if (s->active.empty()) return 0;
+  Builder b(c, s->ws, s->ws_bytes, s->arena, s->arena_bytes, false, &s->pool);
+  std::vector<ArgmaxQuery*> done = s->prog.round(b, true);
+  // At light load a round is a few small launches, shorter than the host
+  // round trip that follows it: further rounds join the same submission
+  // until a request completes or the batch holds about 32 key-switches
+  // (a few ms of GPU time, the longest a new arrival then waits for
+  // admission).  Each request still advances through its own steps in
+  // order, so results are unchanged.
+  for (int r = 1; r < 64 && done.empty() && !b.err_code && s->prog.active() && b.counters[3] < 32 &&
+                  b.counters[7] < 1024 && b.blob_bytes() < s->arena_bytes / 4;
+       ++r)
+    done = s->prog.round(b, true);
+  if (b.err_code) { s->broken = true; return set_err(b.err_code, b.err); }
+  if (b.arena_overflow()) { s->broken = true; return set_err(SECPE_ENOMEM, "server descriptor arena overflow"); }
+  int rc = submit(c, b, s->arena, s->arena_bytes);
+  if (rc) { s->broken = true; return set_err(SECPE_EDEVICE, "kernel submission failed"); }
+  memcpy(c.counters, b.counters, sizeof(c.counters));
+  s->finishing = std::move(done);
+  s->launched = true;
+  return 0;
+}
+
+extern "C" int secpe_server_collect(secpe_server* s, int cap, int* n_done, uint64_t* tickets, int* levels,
+                                    double* scales, int* n_active, int* n_pending) {
+  if (!s) return set_err(SECPE_EINVAL, "null server");
+  if (n_done) *n_done = 0;
+  if (s->launched) {
+    s->launched = false;
+    int rc = sync(s->x->c);
     if (rc) { s->broken = true; return rc; }
     int k = 0;
-    for (ArgmaxQuery* q : done) {
+    for (ArgmaxQuery* q : s->finishing) {
       if (k < cap) {
         if (tickets) tickets[k] = q->ticket;
         if (levels) levels[k] = q->out.level;
@@ -1376,11 +1388,31 @@ extern "C" int secpe_server_step(secpe_server* s, int cap, int* n_done, uint64_t
         s->active.erase(it);
       }
     }
+    s->finishing.clear();
     if (n_done) *n_done = std::min(k, cap);
   }
   if (n_active) *n_active = (int)s->active.size();
   if (n_pending) *n_pending = (int)s->pending.size();
   return 0;
+}
+
+extern "C" int secpe_server_ready(secpe_server* s) {
+  if (!s) return set_err(SECPE_EINVAL, "null server");
+  if (!s->launched) return 1;
+  Ctx& c = s->x->c;
+  hipError_t e = hipStreamQuery(c.stream);
+  if (e == hipSuccess) return 1;
+  if (e == hipErrorNotReady) return 0;
+  s->broken = true;
+  return hip_fail("stream query", e);
+}
+
+extern "C" int secpe_server_step(secpe_server* s, int cap, int* n_done, uint64_t* tickets, int* levels, double* scales,
+                                 int* n_active, int* n_pending) {
+  if (n_done) *n_done = 0;
+  int rc = secpe_server_launch(s);
+  if (rc) return rc;
+  return secpe_server_collect(s, cap, n_done, tickets, levels, scales, n_active, n_pending);
 }
 
 // ---------------------------------------------------------------------------

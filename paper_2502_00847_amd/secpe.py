@@ -114,6 +114,9 @@ def load():
         "secpe_server_request_bytes": (sz, [vp, i32, i32]),
         "secpe_server_submit": (i32, [vp, ct, i32, i32, dbl, dbl, u64, vp, P(u64)]),
         "secpe_server_step": (i32, [vp, i32, P(i32), P(u64), P(i32), P(dbl), P(i32), P(i32)]),
+        "secpe_server_launch": (i32, [vp]),
+        "secpe_server_ready": (i32, [vp]),
+        "secpe_server_collect": (i32, [vp, i32, P(i32), P(u64), P(i32), P(dbl), P(i32), P(i32)]),
         "secpe_set_boot": (i32, [vp, P(_BootParams), P(i32)]),
         "secpe_boot_steps": (i32, [vp, P(i64), i32]),
         "secpe_boot_key_bytes": (sz, [vp]),
@@ -146,7 +149,8 @@ def exported_symbols():
          "secpe_op_key_switch", "secpe_op_ntt", "secpe_op_ring_mul", "secpe_op_encode", "secpe_profile_begin",
          "secpe_profile_end", "secpe_ntt_cts", "secpe_rotate_workspace_bytes", "secpe_rotate_batch",
          "secpe_server_create", "secpe_server_destroy", "secpe_server_request_bytes", "secpe_server_submit",
-         "secpe_server_step", "secpe_set_boot", "secpe_boot_steps", "secpe_boot_key_bytes", "secpe_boot_setup",
+         "secpe_server_step", "secpe_server_launch", "secpe_server_ready",
+         "secpe_server_collect", "secpe_set_boot", "secpe_boot_steps", "secpe_boot_key_bytes", "secpe_boot_setup",
          "secpe_bootstrap_workspace_bytes", "secpe_bootstrap", "secpe_op_boot_step"])
 
 
@@ -671,14 +675,32 @@ class Server:
         return t.value
 
     def step(self, cap=1024):
+        """Launch and collect: (completed tickets, active, pending)."""
+        return self._report(self.lib.secpe_server_step, cap)
+
+    def launch(self):
+        """Queue the next submission without waiting (pair with collect)."""
+        self.ctx._check(self.lib.secpe_server_launch(self.h))
+
+    def ready(self):
+        """True when collect would not wait."""
+        r = self.lib.secpe_server_ready(self.h)
+        self.ctx._check(min(r, 0))
+        return r == 1
+
+    def collect(self, cap=1024):
+        """Wait for the launched submission: (completed tickets, active, pending)."""
+        return self._report(self.lib.secpe_server_collect, cap)
+
+    def _report(self, fn, cap):
         n = C.c_int(0)
         na = C.c_int(0)
         npd = C.c_int(0)
         tk = np.zeros(cap, dtype=np.uint64)
         lv = np.zeros(cap, dtype=np.int32)
         sc = np.zeros(cap)
-        self.ctx._check(self.lib.secpe_server_step(self.h, cap, C.byref(n), _p(tk, C.c_uint64), _p(lv, C.c_int),
-                                                   _p(sc, C.c_double), C.byref(na), C.byref(npd)))
+        self.ctx._check(fn(self.h, cap, C.byref(n), _p(tk, C.c_uint64), _p(lv, C.c_int), _p(sc, C.c_double),
+                           C.byref(na), C.byref(npd)))
         done = []
         for i in range(n.value):
             t = int(tk[i])

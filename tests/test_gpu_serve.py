@@ -108,3 +108,47 @@ def test_lone_request_runs_many_rounds_per_step(tiny_ctx):
     got = srv.results[t]
     assert (got.level, got.scale) == (alone.level, alone.scale)
     assert np.array_equal(g.export(got), g.export(alone))
+
+
+def test_tenants_launch_then_collect(tiny_ctx):
+    """Two tenants (own keys, own stream), each with its own server: every
+    step launches both servers before polling and collecting either; each
+    result is bit-identical to evaluating the request alone under its
+    tenant's keys."""
+    from paper_2502_00847_amd.secpe import Context, Server, SecpeError
+    g0 = tiny_ctx
+    g1 = Context(W.PARAMS["tiny"])
+    g1.keygen(W.KEYGEN_SEED + 1, g1.argmax_steps(32, 20))
+    gs = [g0, g1]
+    reqs = [(i % 2, _request(gs[i % 2], 60 + i)) for i in range(8)]
+    srvs = [Server(h, 4 * h.workspace_bytes([r["K"] for _, r in reqs], [r["C"] for _, r in reqs]), max_active=8)
+            for h in gs]
+    tickets = {}
+    for i, (k, r) in enumerate(reqs[:4]):
+        tickets[i] = srvs[k].submit(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"])
+    srvs[0].launch()
+    with pytest.raises(SecpeError):
+        srvs[0].launch()   # the previous launch is not collected yet
+    srvs[0].collect()
+    step = 0
+    while sum(len(s.results) for s in srvs) < len(reqs):
+        if step == 2:
+            for i, (k, r) in enumerate(reqs[4:], start=4):
+                tickets[i] = srvs[k].submit(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"])
+        for s in srvs:
+            s.launch()
+        for s in srvs:
+            spins = 0
+            while not s.ready():
+                spins += 1
+                assert spins < 10_000_000
+            assert s.ready()
+            s.collect()
+            assert s.ready()   # nothing launched
+        step += 1
+        assert step < 500
+    for i, (k, r) in enumerate(reqs):
+        got = srvs[k].results[tickets[i]]
+        alone = gs[k].eval_argmax(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"])
+        assert (got.level, got.scale) == (alone.level, alone.scale)
+        assert np.array_equal(gs[k].export(got), gs[k].export(alone))
