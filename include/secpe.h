@@ -275,7 +275,8 @@ size_t secpe_server_request_bytes(secpe_ctx* ctx, int K, int C);
 int secpe_server_submit(secpe_server* srv, const secpe_ct* in, int K, int C, double d_min, double d_max,
                         uint64_t refresh_seed, void* out_data, uint64_t* ticket);
 /* One submission of one or more rounds.  Writes up to 'cap' completed
-   tickets with the level and scale of their results; n_active / n_pending
+   tickets with the level and scale of their results (completions beyond
+   'cap' are kept and reported first by the next call); n_active / n_pending
    report the queue after the submission. */
 int secpe_server_step(secpe_server* srv, int cap, int* n_done, uint64_t* tickets, int* levels, double* scales,
                       int* n_active, int* n_pending);

@@ -1243,6 +1243,12 @@ struct secpe_server {
   bool broken = false;
   bool launched = false;                // a submission awaits secpe_server_collect
   std::vector<ArgmaxQuery*> finishing;  // requests that complete in it
+  struct Done {
+    uint64_t ticket;
+    int level;
+    double scale;
+  };
+  std::deque<Done> unreported;          // completed beyond a caller's 'cap', reported next
 };
 
 static std::pair<int, size_t> request_need(secpe_ctx* x, int K, int C) {
@@ -1374,14 +1380,8 @@ extern "C" int secpe_server_collect(secpe_server* s, int cap, int* n_done, uint6
     s->launched = false;
     int rc = sync(s->x->c);
     if (rc) { s->broken = true; return rc; }
-    int k = 0;
     for (ArgmaxQuery* q : s->finishing) {
-      if (k < cap) {
-        if (tickets) tickets[k] = q->ticket;
-        if (levels) levels[k] = q->out.level;
-        if (scales) scales[k] = q->out.scale;
-      }
-      ++k;
+      s->unreported.push_back({q->ticket, q->out.level, q->out.scale});
       auto it = s->active.find(q);
       if (it != s->active.end()) {
         s->reserved_slots -= it->second->slots;
@@ -1389,8 +1389,16 @@ extern "C" int secpe_server_collect(secpe_server* s, int cap, int* n_done, uint6
       }
     }
     s->finishing.clear();
-    if (n_done) *n_done = std::min(k, cap);
   }
+  int k = 0;
+  for (; k < cap && !s->unreported.empty(); ++k) {
+    const secpe_server::Done& d = s->unreported.front();
+    if (tickets) tickets[k] = d.ticket;
+    if (levels) levels[k] = d.level;
+    if (scales) scales[k] = d.scale;
+    s->unreported.pop_front();
+  }
+  if (n_done) *n_done = k;
   if (n_active) *n_active = (int)s->active.size();
   if (n_pending) *n_pending = (int)s->pending.size();
   return 0;

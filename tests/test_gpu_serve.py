@@ -152,3 +152,24 @@ def test_tenants_launch_then_collect(tiny_ctx):
         alone = gs[k].eval_argmax(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"])
         assert (got.level, got.scale) == (alone.level, alone.scale)
         assert np.array_equal(gs[k].export(got), gs[k].export(alone))
+
+
+def test_completions_beyond_cap_are_reported_later(tiny_ctx):
+    """Four requests of one shape finish in the same round; with cap = 1 each
+    call reports one ticket, and every ticket is reported exactly once."""
+    from paper_2502_00847_amd.secpe import Server
+    g = tiny_ctx
+    r = _request(g, 44)
+    srv = Server(g, 6 * g.lib.secpe_server_request_bytes(g.h, r["K"], r["C"]), max_active=8)
+    tickets = [srv.submit(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"]) for _ in range(4)]
+    seen = []
+    for _ in range(400):
+        done, _, _ = srv.step(cap=1)
+        assert len(done) <= 1
+        seen += done
+        if len(seen) == 4:
+            break
+    assert sorted(seen) == sorted(tickets)
+    ref = g.export(srv.results[tickets[0]])
+    for t in tickets[1:]:
+        assert np.array_equal(g.export(srv.results[t]), ref)
