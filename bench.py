@@ -168,7 +168,7 @@ def serve(gs, n, warm, qps=None, frac=0.7, max_active=96, distinct=256):
     lat = np.array([(finish[t] - arrive[t]) * 1e3 for t in order])
     span = max(finish[t] for t in order) - min(arrive[t] for t in order)
     return {
-        "workload": "config5_poisson", "tenants": T, "requests": n, "warmup_requests": warm,
+        "workload": "config5_poisson", "tenants": T, "servers": T, "requests": n, "warmup_requests": warm,
         "distinct_queries": nd, "qps": round(qps, 2),
         "saturated_argmax_per_s": round(sat, 2) if sat else None,
         "throughput_argmax_per_s": round(len(order) / span, 2),
@@ -732,6 +732,20 @@ def main():
         result["serving_sweep"] = {"what": "the same mix at fractions of the saturated rate", "runs": sweep}
         _log(f"serving sweep: {[(r['load'], r['p50_ms'], r['p99_ms']) for r in sweep]}")
         del gs
+        # one key owner's requests over 4 contexts that share its keys (4 streams)
+        from paper_2502_00847_amd.secpe import Context
+        shared = [g]
+        for _ in range(3):
+            h = Context(params)
+            h.share_keys(g)
+            shared.append(h)
+        r = serve(shared, 500, 50)
+        r["tenants"] = 1
+        r["what"] = "one key owner, 4 servers on 4 streams sharing its keys (secpe_keys_share), load 0.7"
+        result["serving_one_owner_4_streams"] = r
+        _log(f"one key owner on 4 streams: p50 {r['p50_ms']} ms, p99 {r['p99_ms']} ms, "
+             f"saturated {r['saturated_argmax_per_s']}/s")
+        del shared
     # the refresh stand-in, timed on its own: refreshes in one step (counters of
     # every chunk) and the time of one refresh of a level-1 ciphertext
     n_ref = 0

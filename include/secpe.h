@@ -103,6 +103,13 @@ int secpe_keygen(secpe_ctx* ctx, uint64_t seed, const int64_t* steps, int n_step
    bootstrapping (Sec. 2.2; Sec. 4.1): when a ciphertext runs out of levels the
    evaluation decrypts and re-encrypts it at the top level.  NULL disables it. */
 int secpe_set_refresh_key(secpe_ctx* ctx, const void* sk_dev);
+/* Let dst evaluate with the switching keys and refresh key that src holds
+   (no copy: the device buffers given to src's secpe_keygen must outlive
+   both).  Both contexts need the same parameters on the same device; each
+   keeps its own stream, so one key owner's requests can run on several
+   streams at once (one server per context).  Bootstrapping keys are not
+   shared. */
+int secpe_keys_share(secpe_ctx* dst, const secpe_ctx* src);
 
 /* Client encryption of a K x C block of logits (row k = prompt k) at the top
    level with scale 2^log_scale.  Slot k*C' + c holds logits[k*C + c],

@@ -259,6 +259,21 @@ extern "C" int secpe_keygen(secpe_ctx* x, uint64_t seed, const int64_t* steps, i
   return 0;
 }
 
+extern "C" int secpe_keys_share(secpe_ctx* dst, const secpe_ctx* src) {
+  CHECK_CTX(dst);
+  if (!src || src == dst) return set_err(SECPE_EINVAL, "bad key source");
+  const Ctx& a = src->c;
+  Ctx& b = dst->c;
+  if (a.mod != b.mod || a.N != b.N || a.n_q != b.n_q || a.dnum != b.dnum || a.device != b.device)
+    return set_err(SECPE_EINVAL, "key source has other parameters or another device");
+  if (a.keys.empty()) return set_err(SECPE_EINVAL, "key source has no keys");
+  b.keys = a.keys;
+  b.refresh_sk = a.refresh_sk;
+  dst->evk = src->evk;
+  dst->key_list = src->key_list;
+  return 0;
+}
+
 extern "C" int secpe_set_refresh_key(secpe_ctx* x, const void* sk_dev) {
   CHECK_CTX(x);
   x->c.refresh_sk = (const double*)sk_dev;

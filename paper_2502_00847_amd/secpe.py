@@ -115,6 +115,7 @@ def load():
         "secpe_server_submit": (i32, [vp, ct, i32, i32, dbl, dbl, u64, vp, P(u64)]),
         "secpe_server_step": (i32, [vp, i32, P(i32), P(u64), P(i32), P(dbl), P(i32), P(i32)]),
         "secpe_server_launch": (i32, [vp]),
+        "secpe_keys_share": (i32, [vp, vp]),
         "secpe_server_ready": (i32, [vp]),
         "secpe_server_collect": (i32, [vp, i32, P(i32), P(u64), P(i32), P(dbl), P(i32), P(i32)]),
         "secpe_set_boot": (i32, [vp, P(_BootParams), P(i32)]),
@@ -149,7 +150,7 @@ def exported_symbols():
          "secpe_op_key_switch", "secpe_op_ntt", "secpe_op_ring_mul", "secpe_op_encode", "secpe_profile_begin",
          "secpe_profile_end", "secpe_ntt_cts", "secpe_rotate_workspace_bytes", "secpe_rotate_batch",
          "secpe_server_create", "secpe_server_destroy", "secpe_server_request_bytes", "secpe_server_submit",
-         "secpe_server_step", "secpe_server_launch", "secpe_server_ready",
+         "secpe_server_step", "secpe_server_launch", "secpe_server_ready", "secpe_keys_share",
          "secpe_server_collect", "secpe_set_boot", "secpe_boot_steps", "secpe_boot_key_bytes", "secpe_boot_setup",
          "secpe_bootstrap_workspace_bytes", "secpe_bootstrap", "secpe_op_boot_step"])
 
@@ -244,6 +245,12 @@ class Context:
         if refresh:
             self.set_refresh_key(self.sk)
         return self.sk, self.evk
+
+    def share_keys(self, other):
+        """Evaluate with other's switching and refresh keys (same parameters and
+        device); this context keeps its own stream."""
+        self._check(self.lib.secpe_keys_share(self.h, other.h))
+        self.sk, self.evk, self.steps = other.sk, other.evk, other.steps
 
     def set_refresh_key(self, sk):
         self._check(self.lib.secpe_set_refresh_key(self.h, C.c_void_p(sk.data_ptr()) if sk is not None else None))

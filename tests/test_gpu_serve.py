@@ -173,3 +173,34 @@ def test_completions_beyond_cap_are_reported_later(tiny_ctx):
     ref = g.export(srv.results[tickets[0]])
     for t in tickets[1:]:
         assert np.array_equal(g.export(srv.results[t]), ref)
+
+
+def test_shared_keys_servers_on_two_streams(tiny_ctx):
+    """A second context evaluating with the first one's keys (its own stream):
+    requests of one key owner split over two servers give the bits of the
+    request alone; sharing across other parameters is refused."""
+    from paper_2502_00847_amd.secpe import Context, Server, SecpeError
+    g0 = tiny_ctx
+    g1 = Context(W.PARAMS["tiny"])
+    g1.share_keys(g0)
+    other = Context(W.PARAMS["mini"])
+    with pytest.raises(SecpeError):
+        other.share_keys(g0)
+    gs = [g0, g1]
+    reqs = [_request(g0, 80 + i) for i in range(6)]
+    srvs = [Server(h, 4 * h.workspace_bytes([r["K"] for r in reqs], [r["C"] for r in reqs]), max_active=8)
+            for h in gs]
+    tickets = [(i % 2, srvs[i % 2].submit(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"]))
+               for i, r in enumerate(reqs)]
+    for _ in range(500):
+        for s in srvs:
+            s.launch()
+        for s in srvs:
+            s.collect()
+        if sum(len(s.results) for s in srvs) == len(reqs):
+            break
+    for (k, t), r in zip(tickets, reqs):
+        got = srvs[k].results[t]
+        alone = g0.eval_argmax(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"])
+        assert (got.level, got.scale) == (alone.level, alone.scale)
+        assert np.array_equal(g0.export(got), g0.export(alone))
