@@ -70,3 +70,21 @@ def test_product_does_not_import_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in re.findall(r"(?:import|from|include)\s+[\"<]?(oracle)", text)
+
+
+def test_server_and_key_sharing_refuse_null_handles(lib_path):
+    """Argument checks come before any device call, so they run here."""
+    lib = ctypes.CDLL(lib_path)
+    for name in ("secpe_server_launch", "secpe_server_ready"):
+        fn = getattr(lib, name)
+        fn.restype = ctypes.c_int
+        fn.argtypes = [ctypes.c_void_p]
+        assert fn(None) < 0
+    fn = lib.secpe_server_collect
+    fn.restype = ctypes.c_int
+    n = ctypes.c_int(7)
+    assert fn(None, 0, ctypes.byref(n), None, None, None, None, None) < 0
+    fn = lib.secpe_keys_share
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    assert fn(None, None) < 0
