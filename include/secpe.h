@@ -271,7 +271,7 @@ int secpe_sync(secpe_ctx* ctx);
    different requests run in the same kernel launches), waits for the GPU and
    returns the requests that completed.  When that round holds little work
    (few requests active), further rounds join the same submission until a
-   request completes or about 32 key-switches are queued.  A request's result is bit-identical
+   request completes or about 96 key-switches are queued.  A request's result is bit-identical
    to evaluating it alone.  The input ciphertext must stay valid until its
    request completes; out_data receives z (secpe_ct_bytes). */
 typedef struct secpe_server secpe_server;

@@ -1369,11 +1369,11 @@ extern "C" int secpe_server_launch(secpe_server* s) {
   std::vector<ArgmaxQuery*> done = s->prog.round(b, true);
   // At light load a round is a few small launches, shorter than the host
   // round trip that follows it: further rounds join the same submission
-  // until a request completes or the batch holds about 32 key-switches
+  // until a request completes or the batch holds about 96 key-switches
   // (a few ms of GPU time, the longest a new arrival then waits for
   // admission).  Each request still advances through its own steps in
   // order, so results are unchanged.
-  for (int r = 1; r < 64 && done.empty() && !b.err_code && s->prog.active() && b.counters[3] < 32 &&
+  for (int r = 1; r < 64 && done.empty() && !b.err_code && s->prog.active() && b.counters[3] < 96 &&
                   b.counters[7] < 1024 && b.blob_bytes() < s->arena_bytes / 4;
        ++r)
     done = s->prog.round(b, true);
