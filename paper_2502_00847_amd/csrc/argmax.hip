@@ -539,19 +539,22 @@ std::vector<ArgmaxQuery*> ArgmaxProgram::round(Builder& b, bool all_kinds) {
   if (st_.empty()) return done;
   std::vector<int> kinds;
   if (all_kinds) {
-    for (int k = 0; k < S_NKINDS; ++k)
-      if (count[k]) kinds.push_back(k);
+    for (int k = 0; k < S_NKINDS; ++k) kinds.push_back(k);
   } else {
     int kind = 0;
     for (int k = 1; k < S_NKINDS; ++k)
       if (count[k] > count[kind]) kind = k;
     kinds.push_back(kind);
   }
-  // every query advances at most one step per round
-  std::vector<std::vector<QState*>> groups(S_NKINDS);
-  for (QState* s : st_) groups[s->prog[s->pc].kind].push_back(s);
+  // With all_kinds the kinds run in ascending order and a query whose next
+  // step is of a later kind takes it in the same round (at most one step of
+  // each kind per query per round); otherwise one kind runs, one step each.
+  // Either way each query's steps keep their order, so its bits do not
+  // depend on the grouping.
   for (int kind : kinds) {
-    std::vector<QState*>& qs = groups[kind];
+    std::vector<QState*> qs;
+    for (QState* s : st_)
+      if (s->pc < s->prog.size() && s->prog[s->pc].kind == kind) qs.push_back(s);
     if (qs.empty()) continue;
     run_step(b, kind, qs);
     if (b.err_code) return done;
