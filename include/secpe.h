@@ -267,13 +267,17 @@ int secpe_sync(secpe_ctx* ctx);
    workspace (caller-owned device memory).  Requests are submitted at any time;
    each call to secpe_server_step admits pending requests while the estimated
    workspace of the admitted set fits (and at most max_active run), then
-   advances every admitted request by one step of Algorithm 1 (the steps of
-   different requests run in the same kernel launches), waits for the GPU and
-   returns the requests that completed.  When that round holds little work
-   (few requests active), further rounds join the same submission until a
-   request completes or about 96 key-switches are queued.  A request's result is bit-identical
-   to evaluating it alone.  The input ciphertext must stay valid until its
-   request completes; out_data receives z (secpe_ct_bytes). */
+   runs one round of Algorithm 1 over every admitted request, waits for the
+   GPU and returns the requests that completed.  In a round the step kinds
+   (prompt sum, normalisation, duplication, Max pre-step, Sign polynomial,
+   Max post-step, final pre-step, final post-step) run in that order, the
+   steps of one kind for all requests in the same kernel launches, and a
+   request takes at most one step of each kind.  When that round holds
+   little work (few requests active), further rounds join the same
+   submission until a request completes or about 96 key-switches are
+   queued.  A request's result is bit-identical to evaluating it alone.
+   The input ciphertext must stay valid until its request completes;
+   out_data receives z (secpe_ct_bytes). */
 typedef struct secpe_server secpe_server;
 int secpe_server_create(secpe_ctx* ctx, void* ws_dev, size_t ws_bytes, int max_active, secpe_server** out);
 void secpe_server_destroy(secpe_server* srv);
