@@ -148,7 +148,7 @@ def serve(gs, n, warm, qps=None, frac=0.7, max_active=96, distinct=256):
                         finish[(k, t)] = now
                         free[k].append(owner.pop((k, t)))
                         srvs[k].results.pop(t, None)
-                if not launched[k] and srvs[k]._inputs:
+                if not launched[k] and srvs[k].in_flight:
                     srvs[k].launch()
                     launched[k] = True
             if not any(launched) and nxt < total:

@@ -669,6 +669,11 @@ class Server:
             _lib.secpe_server_destroy(self.h)
             self.h = None
 
+    @property
+    def in_flight(self):
+        """Requests submitted and not yet reported complete."""
+        return len(self._inputs)
+
     def request_bytes(self, K, Cc):
         return self.lib.secpe_server_request_bytes(self.ctx.h, int(K), int(Cc))
 
