@@ -43,7 +43,7 @@ enum {
   SECPE_OK = 0,
   SECPE_EINVAL = -1,   /* bad argument or parameter set */
   SECPE_ENOMEM = -2,   /* workspace or device allocation too small / failed */
-  SECPE_ENOLEVEL = -3, /* the modulus chain is exhausted and no refresh key is registered */
+  SECPE_ENOLEVEL = -3, /* the modulus chain is exhausted and neither a key owner nor bootstrapping can refresh */
   SECPE_ENOKEY = -4,   /* no switching key for a needed rotation */
   SECPE_EDEVICE = -5   /* a HIP call failed */
 };
@@ -70,6 +70,8 @@ typedef struct secpe_ct {
 typedef struct secpe_ctx secpe_ctx;
 
 const char* secpe_last_error(void);
+/* A fixed description of a status code (never NULL). */
+const char* secpe_strerror(int code);
 
 /* Create a context on HIP device 'device', issuing work on 'stream' (a
    hipStream_t; NULL = the null stream).  Builds primes and device tables. */
@@ -99,17 +101,29 @@ int secpe_argmax_steps(const secpe_ctx* ctx, int k_max, int c_max, int64_t* out,
    the context evaluates.  Synchronous. */
 int secpe_keygen(secpe_ctx* ctx, uint64_t seed, const int64_t* steps, int n_steps, void* sk_dev, void* evk_dev);
 
-/* Register the key owner's secret key for the refresh stand-in of
-   bootstrapping (Sec. 2.2; Sec. 4.1): when a ciphertext runs out of levels the
-   evaluation decrypts and re-encrypts it at the top level.  NULL disables it. */
-int secpe_set_refresh_key(secpe_ctx* ctx, const void* sk_dev);
-/* Let dst evaluate with the switching keys and refresh key that src holds
-   (no copy: the device buffers given to src's secpe_keygen must outlive
-   both).  Both contexts need the same parameters on the same device; each
-   keeps its own stream, so one key owner's requests can run on several
-   streams at once (one server per context).  Bootstrapping keys are not
-   shared. */
+/* Let dst evaluate with the switching keys src holds (no copy: the device
+   buffers given to src's secpe_keygen must outlive both).  Only public
+   switching keys are shared; no context ever holds a secret.  Both contexts
+   need the same parameters on the same device; each keeps its own stream, so
+   one user's requests can run on several streams at once (one server per
+   context).  Bootstrapping keys are not shared. */
 int secpe_keys_share(secpe_ctx* dst, const secpe_ctx* src);
+
+/* ---- the key owner (Sec. 3.1: only the user holds the secret key; the
+   server evaluates without it).  The paper refreshes exhausted ciphertexts by
+   bootstrapping (Sec. 2.2; Sec. 4.1), which needs no secret.  Without
+   bootstrapping, this library can instead refresh on the key owner's behalf:
+   decrypt, lift the message exactly and re-encrypt with fresh randomness (an
+   interactive stand-in in which the key owner takes part in the evaluation).
+   A key owner handle names the secret for that purpose.  It is passed to
+   each evaluation that may refresh and is never stored by a context; an
+   evaluation given NULL (and not bootstrapping) stops with SECPE_ENOLEVEL at
+   its first refresh point, before any work is queued.  The handle refers to
+   sk_dev (caller-owned, it must outlive every evaluation given the handle)
+   and to the context's parameters and device; it holds no device memory. ---- */
+typedef struct secpe_key_owner secpe_key_owner;
+int secpe_key_owner_create(const secpe_ctx* ctx, const void* sk_dev, secpe_key_owner** out);
+void secpe_key_owner_destroy(secpe_key_owner* owner);
 
 /* Client encryption of a K x C block of logits (row k = prompt k) at the top
    level with scale 2^log_scale.  Slot k*C' + c holds logits[k*C + c],
@@ -133,19 +147,22 @@ size_t secpe_workspace_bytes(secpe_ctx* ctx, int n, const int* K, const int* C);
 /* The encrypted Argmax (Algorithm 1) of one query: prompt sum by doubling
    (Sec. 3.2, "applies to all associative operations"), normalisation with the
    public bounds d_min, d_max (Eq. 5), duplication, QuickMax with Eq. 6, then
-   Sign(y - y_max) + 1 (Eq. 2).  'in' is read only.  refresh_seed keys the
-   randomness of the refresh stand-in.  Asynchronous. */
-int secpe_eval_argmax(secpe_ctx* ctx, const secpe_ct* in, int K, int C, double d_min, double d_max,
-                      uint64_t refresh_seed, void* ws_dev, size_t ws_bytes, secpe_ct* out);
+   Sign(y - y_max) + 1 (Eq. 2).  'in' is read only.  owner: the key owner
+   for the refresh stand-in, or NULL (then SECPE_ENOLEVEL where a refresh is
+   needed, unless bootstrapping refreshes); refresh_seed keys the randomness
+   of the refresh.  Asynchronous. */
+int secpe_eval_argmax(secpe_ctx* ctx, const secpe_key_owner* owner, const secpe_ct* in, int K, int C, double d_min,
+                      double d_max, uint64_t refresh_seed, void* ws_dev, size_t ws_bytes, secpe_ct* out);
 
 /* Many queries of uneven (K, C) at once: every step of every query is issued
    in batched kernels (one launch per step kind for all queries at it).
    flags: SECPE_GRAPH captures the launches in a hipGraph and replays it on
-   later calls with identical arguments.  Results are bit-identical to one
-   query at a time.  Asynchronous. */
+   later calls with identical arguments (key owner included); keygen, key
+   sharing, bootstrapping set-up and the autotuner discard captured graphs.
+   Results are bit-identical to one query at a time.  Asynchronous. */
 #define SECPE_GRAPH 1
-int secpe_eval_argmax_batch(secpe_ctx* ctx, int n, const secpe_ct* in, const int* K, const int* C,
-                            const double* d_min, const double* d_max, const uint64_t* refresh_seed,
+int secpe_eval_argmax_batch(secpe_ctx* ctx, const secpe_key_owner* owner, int n, const secpe_ct* in, const int* K,
+                            const int* C, const double* d_min, const double* d_max, const uint64_t* refresh_seed,
                             void* ws_dev, size_t ws_bytes, secpe_ct* out, int flags);
 
 /* ---- slot-packed Argmax (Sec. 3.2: N/(2n) Argmax inputs share one
@@ -170,9 +187,9 @@ size_t secpe_packed_workspace_bytes(secpe_ctx* ctx, int n, const int* n_blocks, 
    refresh seed per ciphertext.  Decrypt block b of a result with
    secpe_decrypt over nslots = n_blocks * B and read slots [b*B, b*B + C_b).
    Asynchronous. */
-int secpe_eval_argmax_packed(secpe_ctx* ctx, int n, const secpe_ct* in, const int* n_blocks, const int* K, const int* C,
-                             const double* d_min, const double* d_max, const uint64_t* refresh_seed, void* ws_dev,
-                             size_t ws_bytes, secpe_ct* out);
+int secpe_eval_argmax_packed(secpe_ctx* ctx, const secpe_key_owner* owner, int n, const secpe_ct* in,
+                             const int* n_blocks, const int* K, const int* C, const double* d_min, const double* d_max,
+                             const uint64_t* refresh_seed, void* ws_dev, size_t ws_bytes, secpe_ct* out);
 
 /* ---- the comparison path the paper measures against (Phoenix, Sec. 3.2):
    after the prompt sum and Eq. 5, every class is compared with each of the
@@ -182,8 +199,9 @@ int secpe_eval_argmax_packed(secpe_ctx* ctx, int n, const secpe_ct* in, const in
    Needs the rotation keys of secpe_phoenix_steps; 2 <= C < 512. ---- */
 int secpe_phoenix_steps(const secpe_ctx* ctx, int k_max, int C, int64_t* out, int cap);
 size_t secpe_phoenix_workspace_bytes(secpe_ctx* ctx, int K, int C);
-int secpe_eval_argmax_phoenix(secpe_ctx* ctx, const secpe_ct* in, int K, int C, double d_min, double d_max,
-                              uint64_t refresh_seed, void* ws_dev, size_t ws_bytes, secpe_ct* out);
+int secpe_eval_argmax_phoenix(secpe_ctx* ctx, const secpe_key_owner* owner, const secpe_ct* in, int K, int C,
+                              double d_min, double d_max, uint64_t refresh_seed, void* ws_dev, size_t ws_bytes,
+                              secpe_ct* out);
 
 /* ---- Bootstrapping (Sec. 2.2; Sec. 4.1: the paper refreshes by
    bootstrapping, K = 14 of L = 35 levels, and gives no further steps).  The
@@ -239,9 +257,9 @@ int secpe_op_boot_step(secpe_ctx* ctx, int step, const secpe_ct* a, void* ws_dev
    Writes the chosen candidate to *chosen and, for i < cap, the measured
    milliseconds of candidate i to ms[i].  Synchronous.  Returns 0 or an error. */
 #define SECPE_AUTOTUNE_CANDIDATES 4
-int secpe_autotune(secpe_ctx* ctx, int n, const secpe_ct* in, const int* K, const int* C, const double* d_min,
-                   const double* d_max, const uint64_t* refresh_seed, void* ws_dev, size_t ws_bytes,
-                   secpe_ct* out, int* chosen, double* ms, int cap);
+int secpe_autotune(secpe_ctx* ctx, const secpe_key_owner* owner, int n, const secpe_ct* in, const int* K,
+                   const int* C, const double* d_min, const double* d_max, const uint64_t* refresh_seed,
+                   void* ws_dev, size_t ws_bytes, secpe_ct* out, int* chosen, double* ms, int cap);
 
 /* Operation counts of the last evaluation: [sign, rotate, relin, key_switch,
    refresh, poly, max, kernel launches]. */
@@ -277,9 +295,11 @@ int secpe_sync(secpe_ctx* ctx);
    submission until a request completes or about 96 key-switches are
    queued.  A request's result is bit-identical to evaluating it alone.
    The input ciphertext must stay valid until its request completes;
-   out_data receives z (secpe_ct_bytes). */
+   out_data receives z (secpe_ct_bytes).  owner (or NULL) refreshes as in
+   secpe_eval_argmax for every request of the server. */
 typedef struct secpe_server secpe_server;
-int secpe_server_create(secpe_ctx* ctx, void* ws_dev, size_t ws_bytes, int max_active, secpe_server** out);
+int secpe_server_create(secpe_ctx* ctx, const secpe_key_owner* owner, void* ws_dev, size_t ws_bytes, int max_active,
+                        secpe_server** out);
 void secpe_server_destroy(secpe_server* srv);
 /* Estimated workspace one request of shape (K, C) holds while active. */
 size_t secpe_server_request_bytes(secpe_ctx* ctx, int K, int C);
@@ -321,10 +341,27 @@ enum {
   /* one kernel of the two-pass forward NTT (N > 2^12): the column pass, the row pass;
      the forward NTT carries the fused rescale / ModDown / relinearise-and-rescale
      combines in its row pass */
-  SECPE_PROF_NTT_FWD_COL = 8, SECPE_PROF_NTT_FWD_ROW = 9
+  SECPE_PROF_NTT_FWD_COL = 8, SECPE_PROF_NTT_FWD_ROW = 9,
+  /* the segments of an evaluation: events at the start and end of every
+     command list and at the start and end of every refresh stand-in, so the
+     intervals alternate computation and refresh (secpe_profile_segments) */
+  SECPE_PROF_SEGMENTS = 10
 };
 int secpe_profile_begin(secpe_ctx* ctx, int kind);
-int secpe_profile_end(secpe_ctx* ctx, int64_t* launches, double* total_ms, int64_t* units);
+/* units_shared: the same count with data that several jobs of one launch
+   read counted once (the key limbs of the key-switch inner product, read by
+   every job that switches with the same key); equal to units for the other
+   kinds. */
+int secpe_profile_end(secpe_ctx* ctx, int64_t* launches, double* total_ms, int64_t* units, int64_t* units_shared);
+/* After a SECPE_PROF_SEGMENTS profile: the milliseconds between consecutive
+   events in order (count returned, at most cap written). */
+int secpe_profile_segments(const secpe_ctx* ctx, double* ms, int cap);
+
+/* The algorithmic HBM bytes of the last evaluation's key switches: for each
+   key switch at l+1 limbs, (l+1) limbs read and 2 (l+1) written, and for
+   each launch each distinct key's 2 dnum_l (l+1+alpha) limbs once, however
+   many jobs share it (the hybrid key switch of Sec. 2.2 touches no less). */
+int secpe_keyswitch_traffic(const secpe_ctx* ctx, int64_t* alg_bytes);
 
 /* Batched negacyclic NTT (Sec. 2.2 ring) in place over limbs 0..level of both
    polynomials of n ciphertexts, one launch per direction: inverse != 0 maps
@@ -357,7 +394,8 @@ int secpe_op_rescale(secpe_ctx* ctx, const secpe_ct* a, void* ws, size_t ws_byte
 int secpe_op_mul_relin(secpe_ctx* ctx, const secpe_ct* a, const secpe_ct* b, void* ws, size_t ws_bytes, secpe_ct* out);
 int secpe_op_mul_relin_rescale(secpe_ctx* ctx, const secpe_ct* a, const secpe_ct* b, void* ws, size_t ws_bytes, secpe_ct* out);
 int secpe_op_rotate(secpe_ctx* ctx, const secpe_ct* a, int64_t step, void* ws, size_t ws_bytes, secpe_ct* out);
-int secpe_op_refresh(secpe_ctx* ctx, const secpe_ct* a, uint64_t seed, uint64_t index, void* ws, size_t ws_bytes, secpe_ct* out);
+int secpe_op_refresh(secpe_ctx* ctx, const secpe_key_owner* owner, const secpe_ct* a, uint64_t seed, uint64_t index,
+                     void* ws, size_t ws_bytes, secpe_ct* out);
 int secpe_op_eval_odd9(secpe_ctx* ctx, const secpe_ct* a, const double* coef5, double gain, double target, void* ws,
                        size_t ws_bytes, secpe_ct* out);
 /* hybrid key switch of d (host, coefficient domain, [level+1][N]) with key

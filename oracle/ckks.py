@@ -32,6 +32,7 @@ def _load():
         "orc_psi": (u64, [vp, ci]),
         "orc_counters": (None, [vp, P(i64)]),
         "orc_reset_counters": (None, [vp]),
+        "orc_set_textbook": (None, [vp, ci]),
         "orc_ring_mul": (None, [vp, ci, P(u64), P(u64), P(u64)]),
         "orc_ntt_roundtrip": (None, [vp, ci, P(u64)]),
         "orc_ct_import": (vp, [vp, P(u64), ci, dbl]),
@@ -239,6 +240,12 @@ class Oracle:
 
     def reset_counters(self):
         self.lib.orc_reset_counters(self.h)
+
+    def set_textbook(self, on):
+        """Evaluate products the textbook way (Sec. 2.2: tensor, relinearise,
+        rescale, six key switches per Sign polynomial) instead of the merged
+        relinearise-and-rescale with lazy relinearisation (five)."""
+        self.lib.orc_set_textbook(self.h, int(bool(on)))
 
     def galois_elt(self, step):
         return int(self.lib.orc_galois_elt(self.h, int(step)))

@@ -170,6 +170,7 @@ typedef struct {
   int refresh_level_set; /* the level the parameters asked for */
   int secret_h;         /* > 0: sparse secret, each coefficient nonzero w.p. h/N */
   int boot_mode;        /* 1: refreshes are bootstraps */
+  int textbook;         /* 1: every product relinearised, then rescaled (no merged op) */
   int boot_K, boot_r, boot_deg, boot_ratio, boot_groups;
   int boot_out_level;   /* level of a bootstrapped ciphertext (-1: not set up) */
   double* boot_cheb;    /* Chebyshev coefficients c_0..c_deg of the scaled cosine */
@@ -1284,7 +1285,52 @@ ORC_API void orc_sign_coeffs(double* f, double* g) {
    Depth 4, five relinearisations.  Output at level l-4 with scale 'target' (up
    to the FP64 rounding of the scale bookkeeping).  c[] = c1, c3, c5, c7, c9,
    times 'gain'. */
+/* ct x ct as the textbook evaluator does it (Sec. 2.2): tensor, relinearise
+   (hybrid key switch of the s^2 part), then rescale by the top prime */
+static orc_ct* op_mul_relin_then_rescale(orc_ctx* c, const orc_ct* a, const orc_ct* b) {
+  orc_ct* x = op_mul_relin(c, a, b);
+  rescale_inplace(c, x);
+  return x;
+}
+
+/* The same odd polynomial with the textbook evaluator: every product
+   relinearised and then rescaled on its own, every constant combination
+   rescaled once:
+     x^2 = x x, x^3 = x^2 x, x^4 = x^2 x^2, x^8 = x^4 x^4       (levels l-1 .. l-3)
+     A = c1 x + c3 x^3, B = c5 x + c7 x^3, C = c9 x            (level l-3)
+     p = x^4 B + x^8 C + A                                      (level l-4)
+   Six key switches, depth 4, and the scales of the merged form: the products
+   land on (T q_{l-3}) / q_{l-3} and A is taken to that scale exactly. */
+static orc_ct* eval_odd9_textbook(orc_ctx* c, const orc_ct* x, const double* coef, double gain, double target) {
+  int l = x->level;
+  if (l - 4 < c->min_level) die("eval_odd9: not enough levels");
+  double k1 = coef[0] * gain, k3 = coef[1] * gain, k5 = coef[2] * gain, k7 = coef[3] * gain, k9 = coef[4] * gain;
+  orc_ct* x2 = op_mul_relin_then_rescale(c, x, x);            /* l-1 */
+  orc_ct* x3 = op_mul_relin_then_rescale(c, x2, x);           /* l-2 */
+  orc_ct* x4 = op_mul_relin_then_rescale(c, x2, x2);          /* l-2 */
+  orc_ct* x8 = op_mul_relin_then_rescale(c, x4, x4);          /* l-3 */
+  orc_ct* xl2 = ct_copy(c, x, l - 2);
+  double q3 = (double)c->mod[l - 3];
+  double ta = target * q3;
+  double sb = ta / x4->scale;
+  double sc = ta / x8->scale;
+  orc_ct* B = op_lincomb(c, xl2, k5, x3, k7, sb, 1);          /* l-3 */
+  orc_ct* Cc = op_lincomb(c, xl2, k9, NULL, 0.0, sc, 1);      /* l-3 */
+  orc_ct* x4l = ct_copy(c, x4, l - 3);
+  orc_ct* t = op_mul_relin_then_rescale(c, x4l, B);           /* l-4 */
+  orc_ct* u = op_mul_relin_then_rescale(c, x8, Cc);           /* l-4 */
+  orc_ct* A3 = op_lincomb(c, xl2, k1, x3, k3, t->scale, 1);   /* l-3 */
+  orc_ct* A = ct_copy(c, A3, l - 4);
+  orc_ct* tu = op_add(c, t, u, 0);
+  orc_ct* p = op_add(c, tu, A, 0);
+  ct_free(x2); ct_free(x3); ct_free(x4); ct_free(x8); ct_free(xl2); ct_free(B); ct_free(Cc); ct_free(x4l);
+  ct_free(t); ct_free(u); ct_free(A3); ct_free(A); ct_free(tu);
+  c->counters[CNT_POLY]++;
+  return p;
+}
+
 static orc_ct* eval_odd9(orc_ctx* c, const orc_ct* x, const double* coef, double gain, double target) {
+  if (c->textbook) return eval_odd9_textbook(c, x, coef, gain, target);
   int l = x->level;
   if (l - 4 < c->min_level) die("eval_odd9: not enough levels");
   double k1 = coef[0] * gain, k3 = coef[1] * gain, k5 = coef[2] * gain, k7 = coef[3] * gain, k9 = coef[4] * gain;
@@ -1316,6 +1362,10 @@ static orc_ct* eval_odd9(orc_ctx* c, const orc_ct* x, const double* coef, double
   c->counters[CNT_POLY]++;
   return p;
 }
+
+/* 1: the textbook evaluator (every product relinearised, then rescaled; no
+   merged relinearise-and-rescale, no lazy relinearisation); 0: the default */
+ORC_API void orc_set_textbook(void* h, int on) { ((orc_ctx*)h)->textbook = on ? 1 : 0; }
 
 ORC_API void* orc_eval_odd9(void* h, const void* x, const double* coef, double gain, double target) {
   return eval_odd9((orc_ctx*)h, (const orc_ct*)x, coef, gain, target);
@@ -1394,6 +1444,17 @@ static orc_ct* op_max(orc_ctx* c, const orc_ct* a, const orc_ct* b, refresher* r
   if (ls_real != ls) die("op_max: level plan mismatch");
   orc_ct* dl = ct_copy(c, d, lp);
   orc_ct* sgl = ct_copy(c, sg, lp);
+  if (c->textbook) {
+    /* textbook: d * Sign/2 relinearised, then rescaled; (a+b)/2 as its own
+       constant product rescaled to the same level and scale; then added */
+    orc_ct* pr = op_mul_relin_then_rescale(c, dl, sgl);
+    orc_ct* sl = ct_copy(c, s, lp);
+    orc_ct* half = op_lincomb(c, sl, 0.5, NULL, 0.0, pr->scale, 1);
+    orc_ct* out = op_add(c, pr, half, 0);
+    ct_free(d); ct_free(s); ct_free(sg); ct_free(dl); ct_free(sgl); ct_free(pr); ct_free(sl); ct_free(half);
+    c->counters[CNT_MAX]++;
+    return out;
+  }
   /* d * Sign/2 as a degree-2 ciphertext, (a+b)/2 added at the same scale before
      the one relinearise-and-rescale */
   orc_ct3* prod = op_tensor(c, dl, sgl);

@@ -20,6 +20,15 @@ struct secpe_ctx {
   std::vector<const double*> key_list;
 };
 
+// The key owner's side of the refresh stand-in: a reference to the secret key
+// (caller-owned device memory) and the parameters it belongs to.  Contexts
+// never store it; every evaluation that may refresh is handed one.
+struct secpe_key_owner {
+  const double* sk = nullptr;
+  int device = 0;
+  std::vector<uint64_t> mod;
+};
+
 using namespace secpe;
 
 static thread_local std::string g_err;
@@ -30,6 +39,18 @@ static int set_err(int code, const std::string& msg) {
 }
 
 extern "C" const char* secpe_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char* secpe_strerror(int code) {
+  switch (code) {
+    case SECPE_OK: return "success";
+    case SECPE_EINVAL: return "invalid argument or parameter set";
+    case SECPE_ENOMEM: return "workspace or device memory too small";
+    case SECPE_ENOLEVEL: return "modulus chain exhausted: a key owner or bootstrapping is needed";
+    case SECPE_ENOKEY: return "no switching key for a needed rotation";
+    case SECPE_EDEVICE: return "HIP device error";
+    default: return "unknown error code";
+  }
+}
 
 #define CHECK_CTX(ctx) \
   if (!(ctx)) return set_err(SECPE_EINVAL, "null context")
@@ -54,6 +75,17 @@ static int ensure_buffer(Ctx& c, char** buf, size_t* cap, size_t need) {
   return 0;
 }
 
+// The secret an evaluation may refresh with: null without a key owner; an
+// error when the owner belongs to other parameters or another device.
+static int owner_sk(const secpe_ctx* x, const secpe_key_owner* o, const double** sk) {
+  *sk = nullptr;
+  if (!o) return 0;
+  if (!o->sk || o->device != x->c.device || o->mod != x->c.mod)
+    return set_err(SECPE_EINVAL, "key owner has other parameters or another device");
+  *sk = o->sk;
+  return 0;
+}
+
 // Build with 'fn' into the context arena (growing it when needed) and submit.
 template <class F>
 static int run_build(secpe_ctx* x, char* ws, size_t ws_bytes, F fn, bool record = true) {
@@ -69,7 +101,10 @@ static int run_build(secpe_ctx* x, char* ws, size_t ws_bytes, F fn, bool record 
     }
     int rc = submit(c, b, c.arena, c.arena_bytes);
     if (rc) return set_err(SECPE_EDEVICE, "kernel submission failed");
-    if (record) memcpy(c.counters, b.counters, sizeof(c.counters));
+    if (record) {
+      memcpy(c.counters, b.counters, sizeof(c.counters));
+      c.ks_alg_limbs = b.ks_alg_limbs;
+    }
     return 0;
   }
   return set_err(SECPE_ENOMEM, "descriptor arena did not converge");
@@ -247,6 +282,7 @@ extern "C" int secpe_keygen(secpe_ctx* x, uint64_t seed, const int64_t* steps, i
   if (rc) return rc;
   rc = sync(c);
   if (rc) return rc;
+  drop_graphs(c);
   c.keys.clear();
   x->key_list.clear();
   x->evk = evk;
@@ -267,18 +303,25 @@ extern "C" int secpe_keys_share(secpe_ctx* dst, const secpe_ctx* src) {
   if (a.mod != b.mod || a.N != b.N || a.n_q != b.n_q || a.dnum != b.dnum || a.device != b.device)
     return set_err(SECPE_EINVAL, "key source has other parameters or another device");
   if (a.keys.empty()) return set_err(SECPE_EINVAL, "key source has no keys");
+  drop_graphs(b);
   b.keys = a.keys;
-  b.refresh_sk = a.refresh_sk;
   dst->evk = src->evk;
   dst->key_list = src->key_list;
   return 0;
 }
 
-extern "C" int secpe_set_refresh_key(secpe_ctx* x, const void* sk_dev) {
+extern "C" int secpe_key_owner_create(const secpe_ctx* x, const void* sk_dev, secpe_key_owner** out) {
   CHECK_CTX(x);
-  x->c.refresh_sk = (const double*)sk_dev;
+  if (!sk_dev || !out) return set_err(SECPE_EINVAL, "null argument");
+  secpe_key_owner* o = new secpe_key_owner();
+  o->sk = (const double*)sk_dev;
+  o->device = x->c.device;
+  o->mod = x->c.mod;
+  *out = o;
   return 0;
 }
+
+extern "C" void secpe_key_owner_destroy(secpe_key_owner* o) { delete o; }
 
 // ---------------------------------------------------------------------------
 // client encryption / decryption
@@ -510,18 +553,22 @@ extern "C" size_t secpe_packed_workspace_bytes(secpe_ctx* x, int n, const int* n
   return dry.need_bytes() + 4096;
 }
 
-extern "C" int secpe_eval_argmax_packed(secpe_ctx* x, int n, const secpe_ct* in, const int* n_b, const int* K,
-                                        const int* C, const double* dmin, const double* dmax, const uint64_t* rs,
-                                        void* ws, size_t ws_bytes, secpe_ct* out) {
+extern "C" int secpe_eval_argmax_packed(secpe_ctx* x, const secpe_key_owner* owner, int n, const secpe_ct* in,
+                                        const int* n_b, const int* K, const int* C, const double* dmin,
+                                        const double* dmax, const uint64_t* rs, void* ws, size_t ws_bytes,
+                                        secpe_ct* out) {
   CHECK_CTX(x);
   if (n < 1 || !in || !n_b || !K || !C || !dmin || !dmax || !rs || !ws || !out)
     return set_err(SECPE_EINVAL, "null argument");
   for (int i = 0; i < n; ++i)
     if (!out[i].data) return set_err(SECPE_EINVAL, "null output ciphertext");
-  std::vector<ArgmaxQuery> q;
-  int rc = make_packed(x, n, in, n_b, K, C, dmin, dmax, rs, out, q);
+  const double* rsk = nullptr;
+  int rc = owner_sk(x, owner, &rsk);
   if (rc) return rc;
-  rc = run_build(x, (char*)ws, ws_bytes, [&](Builder& b) { build_argmax(b, q); });
+  std::vector<ArgmaxQuery> q;
+  rc = make_packed(x, n, in, n_b, K, C, dmin, dmax, rs, out, q);
+  if (rc) return rc;
+  rc = run_build(x, (char*)ws, ws_bytes, [&](Builder& b) { b.refresh_sk = rsk; build_argmax(b, q); });
   if (rc) return rc;
   for (int i = 0; i < n; ++i) { out[i].level = q[i].out.level; out[i].scale = q[i].out.scale; }
   return 0;
@@ -558,16 +605,20 @@ extern "C" size_t secpe_phoenix_workspace_bytes(secpe_ctx* x, int K, int C) {
   return dry.need_bytes() + 4096;
 }
 
-extern "C" int secpe_eval_argmax_phoenix(secpe_ctx* x, const secpe_ct* in, int K, int C, double dmin, double dmax,
-                                         uint64_t rs, void* ws, size_t ws_bytes, secpe_ct* out) {
+extern "C" int secpe_eval_argmax_phoenix(secpe_ctx* x, const secpe_key_owner* owner, const secpe_ct* in, int K, int C,
+                                         double dmin, double dmax, uint64_t rs, void* ws, size_t ws_bytes,
+                                         secpe_ct* out) {
   CHECK_CTX(x);
   if (!in || !in->data || !out || !out->data || !ws) return set_err(SECPE_EINVAL, "null argument");
   if (in->level < 0 || in->level >= x->c.n_q) return set_err(SECPE_EINVAL, "input level out of range");
   if (K < 1 || C < 2) return set_err(SECPE_EINVAL, "need K >= 1 and C >= 2");
   if (!(dmax > dmin)) return set_err(SECPE_EINVAL, "need d_max > d_min");
+  const double* rsk = nullptr;
+  int rc = owner_sk(x, owner, &rsk);
+  if (rc) return rc;
   ArgmaxQuery q;
   phoenix_query(x, in, K, C, dmin, dmax, rs, out, q);
-  int rc = run_build(x, (char*)ws, ws_bytes, [&](Builder& b) { build_phoenix(b, q); });
+  rc = run_build(x, (char*)ws, ws_bytes, [&](Builder& b) { b.refresh_sk = rsk; build_phoenix(b, q); });
   if (rc) return rc;
   out->level = q.out.level;
   out->scale = q.out.scale;
@@ -616,19 +667,22 @@ static uint64_t fnv(uint64_t h, const void* p, size_t n) {
   return h;
 }
 
-extern "C" int secpe_eval_argmax_batch(secpe_ctx* x, int n, const secpe_ct* in, const int* K, const int* C,
-                                       const double* dmin, const double* dmax, const uint64_t* rs, void* ws,
-                                       size_t ws_bytes, secpe_ct* out, int flags) {
+extern "C" int secpe_eval_argmax_batch(secpe_ctx* x, const secpe_key_owner* owner, int n, const secpe_ct* in,
+                                       const int* K, const int* C, const double* dmin, const double* dmax,
+                                       const uint64_t* rs, void* ws, size_t ws_bytes, secpe_ct* out, int flags) {
   CHECK_CTX(x);
   if (n < 1 || !in || !K || !C || !dmin || !dmax || !rs || !ws || !out) return set_err(SECPE_EINVAL, "null argument");
-  int rc = check_queries(x, n, in, K, C, dmin, dmax);
+  const double* rsk = nullptr;
+  int rc = owner_sk(x, owner, &rsk);
+  if (rc) return rc;
+  rc = check_queries(x, n, in, K, C, dmin, dmax);
   if (rc) return rc;
   for (int i = 0; i < n; ++i)
     if (!out[i].data) return set_err(SECPE_EINVAL, "null output ciphertext");
   Ctx& c = x->c;
   std::vector<ArgmaxQuery> q = make_queries(x, n, in, K, C, dmin, dmax, rs, out);
   if (!(flags & SECPE_GRAPH)) {
-    rc = run_build(x, (char*)ws, ws_bytes, [&](Builder& b) { build_argmax(b, q); });
+    rc = run_build(x, (char*)ws, ws_bytes, [&](Builder& b) { b.refresh_sk = rsk; build_argmax(b, q); });
     if (rc) return rc;
     for (int i = 0; i < n; ++i) { out[i].level = q[i].out.level; out[i].scale = q[i].out.scale; }
     return 0;
@@ -647,12 +701,14 @@ extern "C" int secpe_eval_argmax_batch(secpe_ctx* x, int n, const secpe_ct* in, 
   }
   h = fnv(h, &ws, sizeof(ws));
   h = fnv(h, &ws_bytes, sizeof(ws_bytes));
+  h = fnv(h, &rsk, sizeof(rsk));
   for (GraphEntry& g : c.graphs) {
     if (g.hash != h) continue;
     hipError_t e = hipGraphLaunch(g.exec, c.stream);
     if (e != hipSuccess) return hip_fail("hipGraphLaunch", e);
     for (int i = 0; i < n; ++i) { out[i].level = g.out_level[i]; out[i].scale = g.out_scale[i]; }
     memcpy(c.counters, g.counters, sizeof(c.counters));
+    c.ks_alg_limbs = g.ks_alg_limbs;
     return 0;
   }
   if (!c.stream) return set_err(SECPE_EINVAL, "graph capture needs a non-null stream");
@@ -661,6 +717,7 @@ extern "C" int secpe_eval_argmax_batch(secpe_ctx* x, int n, const secpe_ct* in, 
   // size the graph's own descriptor arena with a dry run
   {
     Builder dry(c, (char*)ws, ws_bytes, (char*)(uintptr_t)0x400000000000ull, (size_t)1 << 40, true);
+    dry.refresh_sk = rsk;
     std::vector<ArgmaxQuery> qd = q;
     build_argmax(dry, qd);
     if (dry.err_code) return set_err(dry.err_code, dry.err);
@@ -669,6 +726,7 @@ extern "C" int secpe_eval_argmax_batch(secpe_ctx* x, int n, const secpe_ct* in, 
   hipError_t e = hipMalloc((void**)&g.arena, g.arena_bytes);
   if (e != hipSuccess) return hip_fail("hipMalloc", e);
   Builder b(c, (char*)ws, ws_bytes, g.arena, g.arena_bytes, false);
+  b.refresh_sk = rsk;
   build_argmax(b, q);
   if (b.err_code) { (void)hipFree(g.arena); return set_err(b.err_code, b.err); }
   e = hipMemcpy(g.arena, b.blob_.data(), b.blob_.size(), hipMemcpyHostToDevice);
@@ -682,22 +740,32 @@ extern "C" int secpe_eval_argmax_batch(secpe_ctx* x, int n, const secpe_ct* in, 
   if (e != hipSuccess) { (void)hipGraphDestroy(g.graph); (void)hipFree(g.arena); return hip_fail("hipGraphInstantiate", e); }
   for (int i = 0; i < n; ++i) { g.out_level.push_back(q[i].out.level); g.out_scale.push_back(q[i].out.scale); }
   memcpy(g.counters, b.counters, sizeof(g.counters));
+  g.ks_alg_limbs = b.ks_alg_limbs;
   c.graphs.push_back(g);
   e = hipGraphLaunch(g.exec, c.stream);
   if (e != hipSuccess) return hip_fail("hipGraphLaunch", e);
   for (int i = 0; i < n; ++i) { out[i].level = g.out_level[i]; out[i].scale = g.out_scale[i]; }
   memcpy(c.counters, g.counters, sizeof(c.counters));
+  c.ks_alg_limbs = g.ks_alg_limbs;
   return 0;
 }
 
-extern "C" int secpe_eval_argmax(secpe_ctx* x, const secpe_ct* in, int K, int C, double d_min, double d_max,
-                                 uint64_t refresh_seed, void* ws, size_t ws_bytes, secpe_ct* out) {
-  return secpe_eval_argmax_batch(x, 1, in, &K, &C, &d_min, &d_max, &refresh_seed, ws, ws_bytes, out, 0);
+extern "C" int secpe_eval_argmax(secpe_ctx* x, const secpe_key_owner* owner, const secpe_ct* in, int K, int C,
+                                 double d_min, double d_max, uint64_t refresh_seed, void* ws, size_t ws_bytes,
+                                 secpe_ct* out) {
+  return secpe_eval_argmax_batch(x, owner, 1, in, &K, &C, &d_min, &d_max, &refresh_seed, ws, ws_bytes, out, 0);
 }
 
 extern "C" int secpe_counters(const secpe_ctx* x, int64_t* out8) {
   CHECK_CTX(x);
   memcpy(out8, x->c.counters, sizeof(int64_t) * 8);
+  return 0;
+}
+
+extern "C" int secpe_keyswitch_traffic(const secpe_ctx* x, int64_t* alg_bytes) {
+  CHECK_CTX(x);
+  if (!alg_bytes) return set_err(SECPE_EINVAL, "null argument");
+  *alg_bytes = x->c.ks_alg_limbs * (int64_t)x->c.limb_bytes();
   return 0;
 }
 
@@ -934,10 +1002,16 @@ extern "C" int secpe_op_rotate(secpe_ctx* x, const secpe_ct* a, int64_t step, vo
   CHECK_CTX(x);
   return op_to_out(x, ws, wsb, out, [&](Builder& b) { return b.rotate({to_ct(a)}, {step}); });
 }
-extern "C" int secpe_op_refresh(secpe_ctx* x, const secpe_ct* a, uint64_t seed, uint64_t index, void* ws, size_t wsb,
-                                secpe_ct* out) {
+extern "C" int secpe_op_refresh(secpe_ctx* x, const secpe_key_owner* owner, const secpe_ct* a, uint64_t seed,
+                                uint64_t index, void* ws, size_t wsb, secpe_ct* out) {
   CHECK_CTX(x);
-  return op_to_out(x, ws, wsb, out, [&](Builder& b) { return b.refresh({to_ct(a)}, {seed}, {index}); });
+  const double* rsk = nullptr;
+  int rc = owner_sk(x, owner, &rsk);
+  if (rc) return rc;
+  return op_to_out(x, ws, wsb, out, [&](Builder& b) {
+    b.refresh_sk = rsk;
+    return b.refresh({to_ct(a)}, {seed}, {index});
+  });
 }
 extern "C" int secpe_op_eval_odd9(secpe_ctx* x, const secpe_ct* a, const double* coef5, double gain, double target,
                                   void* ws, size_t wsb, secpe_ct* out) {
@@ -1101,25 +1175,46 @@ extern "C" int secpe_profile_begin(secpe_ctx* x, int kind) {
   x->c.prof_used = 0;
   x->c.prof_launches = 0;
   x->c.prof_units = 0;
+  x->c.prof_units_shared = 0;
   return 0;
 }
 
-extern "C" int secpe_profile_end(secpe_ctx* x, int64_t* launches, double* total_ms, int64_t* units) {
+extern "C" int secpe_profile_end(secpe_ctx* x, int64_t* launches, double* total_ms, int64_t* units,
+                                 int64_t* units_shared) {
   CHECK_CTX(x);
   Ctx& c = x->c;
   int rc = sync(c);
   if (rc) return rc;
   double ms = 0.0;
-  for (size_t i = 0; i + 1 < c.prof_used; i += 2) {
-    float t = 0.0f;
-    if (hipEventElapsedTime(&t, c.prof_pool[i], c.prof_pool[i + 1]) == hipSuccess) ms += t;
+  c.seg_ms.clear();
+  if (c.prof_kind == PROF_SEGMENTS) {
+    // consecutive marks: every interval between two events in order
+    for (size_t i = 0; i + 1 < c.prof_used; ++i) {
+      float t = 0.0f;
+      if (hipEventElapsedTime(&t, c.prof_pool[i], c.prof_pool[i + 1]) != hipSuccess) t = 0.0f;
+      c.seg_ms.push_back(t);
+      ms += t;
+    }
+  } else {
+    for (size_t i = 0; i + 1 < c.prof_used; i += 2) {
+      float t = 0.0f;
+      if (hipEventElapsedTime(&t, c.prof_pool[i], c.prof_pool[i + 1]) == hipSuccess) ms += t;
+    }
   }
   if (launches) *launches = c.prof_launches;
   if (total_ms) *total_ms = ms;
   if (units) *units = c.prof_units;
+  if (units_shared) *units_shared = c.prof_units_shared;
   c.prof_kind = -1;
   c.prof_used = 0;
   return 0;
+}
+
+extern "C" int secpe_profile_segments(const secpe_ctx* x, double* ms, int cap) {
+  CHECK_CTX(x);
+  const std::vector<double>& v = x->c.seg_ms;
+  for (int i = 0; i < cap && i < (int)v.size(); ++i) ms[i] = v[i];
+  return (int)v.size();
 }
 
 static void set_candidate(Ctx& c, int i) {
@@ -1127,12 +1222,14 @@ static void set_candidate(Ctx& c, int i) {
   c.ntt_chunk_bytes = (i & 2) ? ((size_t)128 << 20) : 0;
 }
 
-extern "C" int secpe_autotune(secpe_ctx* x, int n, const secpe_ct* in, const int* K, const int* C,
-                              const double* dmin, const double* dmax, const uint64_t* rs, void* ws, size_t ws_bytes,
-                              secpe_ct* out, int* chosen, double* ms, int cap) {
+extern "C" int secpe_autotune(secpe_ctx* x, const secpe_key_owner* owner, int n, const secpe_ct* in, const int* K,
+                              const int* C, const double* dmin, const double* dmax, const uint64_t* rs, void* ws,
+                              size_t ws_bytes, secpe_ct* out, int* chosen, double* ms, int cap) {
   CHECK_CTX(x);
   if (!chosen) return set_err(SECPE_EINVAL, "null argument");
   Ctx& c = x->c;
+  // captured graphs bake in the schedule they were recorded with
+  drop_graphs(c);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
@@ -1146,7 +1243,7 @@ extern "C" int secpe_autotune(secpe_ctx* x, int n, const secpe_ct* in, const int
     float t = 0.0f;
     for (int rep = 0; rep < 2 && !rc; ++rep) {
       (void)hipEventRecord(e0, c.stream);
-      rc = secpe_eval_argmax_batch(x, n, in, K, C, dmin, dmax, rs, ws, ws_bytes, out, 0);
+      rc = secpe_eval_argmax_batch(x, owner, n, in, K, C, dmin, dmax, rs, ws, ws_bytes, out, 0);
       (void)hipEventRecord(e1, c.stream);
       if (!rc && hipEventSynchronize(e1) == hipSuccess) (void)hipEventElapsedTime(&t, e0, e1);
     }
@@ -1238,6 +1335,7 @@ extern "C" int secpe_rotate_batch(secpe_ctx* x, int n, const secpe_ct* in, const
 // ---------------------------------------------------------------------------
 struct secpe_server {
   secpe_ctx* x = nullptr;
+  const double* refresh_sk = nullptr;   // the key owner's secret, or null
   char* ws = nullptr;
   size_t ws_bytes = 0;
   int max_active = 0;
@@ -1250,6 +1348,7 @@ struct secpe_server {
   std::deque<std::unique_ptr<Req>> pending;
   std::map<ArgmaxQuery*, std::unique_ptr<Req>> active;
   std::map<std::pair<int, int>, std::pair<int, size_t>> need;  // (K, C) -> (peak slots, per-item scratch)
+  std::map<std::pair<int, int>, int64_t> refreshes;            // (K, C) -> refreshes of one request
   int reserved_slots = 0;
   size_t item_scratch = 0;
   char* arena = nullptr;
@@ -1266,7 +1365,7 @@ struct secpe_server {
   std::deque<Done> unreported;          // completed beyond a caller's 'cap', reported next
 };
 
-static std::pair<int, size_t> request_need(secpe_ctx* x, int K, int C) {
+static std::pair<int, size_t> request_need(secpe_ctx* x, int K, int C, int64_t* refreshes = nullptr) {
   Ctx& c = x->c;
   std::vector<ArgmaxQuery> q(1);
   q[0].in.d = (double*)(uintptr_t)0x200000000000ull;
@@ -1282,6 +1381,7 @@ static std::pair<int, size_t> request_need(secpe_ctx* x, int K, int C) {
               (size_t)1 << 40, true);
   build_argmax(dry, q);
   if (dry.err_code) return {-1, 0};
+  if (refreshes) *refreshes = dry.counters[4];
   return {dry.peak_slots(), dry.peak_scratch()};
 }
 
@@ -1292,11 +1392,16 @@ extern "C" size_t secpe_server_request_bytes(secpe_ctx* x, int K, int C) {
   return (size_t)n.first * x->c.ct_bytes() + n.second;
 }
 
-extern "C" int secpe_server_create(secpe_ctx* x, void* ws_dev, size_t ws_bytes, int max_active, secpe_server** out) {
+extern "C" int secpe_server_create(secpe_ctx* x, const secpe_key_owner* owner, void* ws_dev, size_t ws_bytes,
+                                   int max_active, secpe_server** out) {
   CHECK_CTX(x);
   if (!ws_dev || !out || max_active < 1) return set_err(SECPE_EINVAL, "bad server arguments");
+  const double* rsk = nullptr;
+  int rc = owner_sk(x, owner, &rsk);
+  if (rc) return rc;
   secpe_server* s = new secpe_server();
   s->x = x;
+  s->refresh_sk = rsk;
   s->ws = (char*)ws_dev;
   s->ws_bytes = ws_bytes & ~size_t(255);
   s->max_active = max_active;
@@ -1324,10 +1429,15 @@ extern "C" int secpe_server_submit(secpe_server* s, const secpe_ct* in, int K, i
   auto key = std::make_pair(ilog2_ceil(K), ilog2_ceil(C));
   auto it = s->need.find(key);
   if (it == s->need.end()) {
-    auto n = request_need(s->x, K, C);
+    int64_t nr = 0;
+    auto n = request_need(s->x, K, C, &nr);
     if (n.first < 0) return set_err(SECPE_EINVAL, "request cannot be planned");
     it = s->need.emplace(key, n).first;
+    s->refreshes[key] = nr;
   }
+  // a request that must refresh is refused up front without a key owner
+  if (s->refreshes[key] > 0 && !s->refresh_sk && !s->x->c.boot_mode)
+    return set_err(SECPE_ENOLEVEL, "request needs a refresh and the server has no key owner");
   const size_t alone = (size_t)it->second.first * s->x->c.ct_bytes() + it->second.second;
   if (alone > s->ws_bytes) return set_err(SECPE_ENOMEM, "request does not fit the server workspace");
   std::unique_ptr<secpe_server::Req> r(new secpe_server::Req());
@@ -1354,10 +1464,11 @@ extern "C" int secpe_server_launch(secpe_server* s) {
   while (!s->pending.empty() && (int)s->active.size() < s->max_active) {
     secpe_server::Req* r = s->pending.front().get();
     auto n = s->need[std::make_pair(ilog2_ceil(r->q.K), ilog2_ceil(r->q.C))];
-    const size_t item = std::max(s->item_scratch, n.second);
+    const size_t item = s->active.empty() ? n.second : std::max(s->item_scratch, n.second);
     const size_t want = (size_t)(s->reserved_slots + r->slots) * c.ct_bytes() + (s->active.size() + 1) * item;
     if (want > s->ws_bytes) break;
     Builder probe(c, s->ws, s->ws_bytes, s->arena, s->arena_bytes, true, &s->pool);
+    probe.refresh_sk = s->refresh_sk;
     if (!s->prog.add(probe, &r->q)) return set_err(SECPE_EINVAL, probe.err);
     s->item_scratch = item;
     s->reserved_slots += r->slots;
@@ -1366,6 +1477,7 @@ extern "C" int secpe_server_launch(secpe_server* s) {
   }
   if (s->active.empty()) return 0;
   Builder b(c, s->ws, s->ws_bytes, s->arena, s->arena_bytes, false, &s->pool);
+  b.refresh_sk = s->refresh_sk;
   std::vector<ArgmaxQuery*> done = s->prog.round(b, true);
   // At light load a round is a few small launches, shorter than the host
   // round trip that follows it: further rounds join the same submission
@@ -1382,6 +1494,7 @@ extern "C" int secpe_server_launch(secpe_server* s) {
   int rc = submit(c, b, s->arena, s->arena_bytes);
   if (rc) { s->broken = true; return set_err(SECPE_EDEVICE, "kernel submission failed"); }
   memcpy(c.counters, b.counters, sizeof(c.counters));
+  c.ks_alg_limbs = b.ks_alg_limbs;
   s->finishing = std::move(done);
   s->launched = true;
   return 0;
@@ -1404,6 +1517,11 @@ extern "C" int secpe_server_collect(secpe_server* s, int cap, int* n_done, uint6
       }
     }
     s->finishing.clear();
+    // the per-request scratch reservation follows the requests still active
+    s->item_scratch = 0;
+    for (auto& a : s->active)
+      s->item_scratch = std::max(
+          s->item_scratch, s->need[std::make_pair(ilog2_ceil(a.second->q.K), ilog2_ceil(a.second->q.C))].second);
   }
   int k = 0;
   for (; k < cap && !s->unreported.empty(); ++k) {
@@ -1490,6 +1608,7 @@ extern "C" int secpe_set_boot(secpe_ctx* x, const secpe_boot_params* bp, int* ou
   if (!bp) return set_err(SECPE_EINVAL, "null parameters");
   Ctx& c = x->c;
   if (bp->secret_h < 0 || bp->secret_h > c.N) return set_err(SECPE_EINVAL, "secret_h must be in [0, N]");
+  drop_graphs(c);
   c.secret_h = bp->secret_h;
   c.boot_cts.clear();
   c.boot_stc.clear();
@@ -1685,6 +1804,7 @@ extern "C" int secpe_boot_setup(secpe_ctx* x, void* buf_dev, size_t bytes) {
       rc = sync(c);
       if (rc) return rc;
     }
+  drop_graphs(c);
   c.boot_ready = true;
   return sync(c);
 }

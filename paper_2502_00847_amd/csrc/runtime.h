@@ -68,6 +68,7 @@ struct GraphEntry {
   std::vector<int> out_level;
   std::vector<double> out_scale;
   int64_t counters[8] = {0};
+  int64_t ks_alg_limbs = 0;
 };
 
 struct Ctx {
@@ -113,7 +114,6 @@ struct Ctx {
   double q0inv_q1 = 0.0;
   // keys
   std::map<uint64_t, const double*> keys;  // Galois element -> key; 0 = relinearisation
-  const double* refresh_sk = nullptr;
   // descriptor arena
   char* arena = nullptr;
   size_t arena_bytes = 0;
@@ -129,7 +129,12 @@ struct Ctx {
   int prof_kind = -1;
   std::vector<hipEvent_t> prof_pool;
   size_t prof_used = 0;
-  int64_t prof_launches = 0, prof_units = 0;
+  int64_t prof_launches = 0, prof_units = 0, prof_units_shared = 0;
+  std::vector<double> seg_ms;   // intervals of the last segment profile
+  // algorithmic HBM limbs of the last evaluation's key switches: per key
+  // switch at l+1 limbs, (l+1) read + 2 (l+1) written, plus the key's
+  // 2 dnum_l (l+1+alpha) limbs once per launch for all the jobs sharing it
+  int64_t ks_alg_limbs = 0;
   std::vector<GraphEntry> graphs;
 
   size_t limb_bytes() const { return (size_t)N * sizeof(double); }
@@ -142,11 +147,14 @@ struct Ctx {
 int build_context(Ctx& c, int log_n, int n_q, int q_bits, int n_p, int p_bits, int log_scale, int dg, int df,
                   int min_level, int refresh_level, int device, hipStream_t stream);
 void destroy_context(Ctx& c);
+// destroy every captured graph (their launches bake in keys and schedule settings)
+void drop_graphs(Ctx& c);
 
 // ---------------------------------------------------------------------------
 // command list: descriptors in one blob, launches replayed in order
 // ---------------------------------------------------------------------------
-enum CmdKind { C_NTT, C_NTT_FIRST, C_NTT_SECOND, C_EW, C_MODUP, C_MODUP_COL, C_MODDOWN, C_INNER, C_INNER_ROW, C_AUTO, C_LIFT, C_SAMPLE, C_INTSPREAD, C_ENCODE, C_DECODE, C_RAISE, C_BSGS, C_FFTENC };
+enum CmdKind { C_NTT, C_NTT_FIRST, C_NTT_SECOND, C_EW, C_MODUP, C_MODUP_COL, C_MODDOWN, C_INNER, C_INNER_ROW, C_AUTO, C_LIFT, C_SAMPLE, C_INTSPREAD, C_ENCODE, C_DECODE, C_RAISE, C_BSGS, C_FFTENC,
+               C_MARK /* no launch: a segment boundary for the segment profiler */ };
 
 struct Cmd {
   int kind;
@@ -158,11 +166,15 @@ struct Cmd {
   double* z;
   double inv_scale;
   int64_t units;   // limbs processed by the launch (limb transforms for the NTT)
+  // the same with data that several jobs of the launch read counted once
+  // (the key limbs of the inner product); equals units for the other kinds
+  int64_t units_shared;
 };
 
 // kinds the event profiler can bracket (secpe_profile_begin)
 enum ProfKind { PROF_NTT_FWD = 0, PROF_NTT_INV = 1, PROF_EW = 2, PROF_MODUP = 3, PROF_MODDOWN = 4, PROF_INNER = 5,
-                PROF_AUTO = 6, PROF_SPREAD = 7, PROF_NTT_FWD_COL = 8, PROF_NTT_FWD_ROW = 9, PROF_NKINDS = 10 };
+                PROF_AUTO = 6, PROF_SPREAD = 7, PROF_NTT_FWD_COL = 8, PROF_NTT_FWD_ROW = 9, PROF_SEGMENTS = 10,
+                PROF_NKINDS = 11 };
 
 // ciphertext handle inside a build: device data [2][n_q][N], level, scale, pool slot
 struct CT {
@@ -187,6 +199,9 @@ class Builder {
   bool dry;
   std::string err;
   int err_code = 0;
+  // the key owner's secret for the refresh stand-in of bootstrapping, given
+  // per evaluation (never held by the context); null: no refresh available
+  const double* refresh_sk = nullptr;
 
   // memory
   CT new_ct(int level, double scale);
@@ -232,6 +247,8 @@ class Builder {
   // dense encodings through a length-2N FFT (max_y of each command = its phase)
   void fft_encode(const std::vector<FftEncJob>& v);
   void decode(const int64_t* m, double* z, int nslots, double inv_scale);
+  // a segment boundary (the refresh stand-in marks its start and end)
+  void mark();
 
   // CKKS operations over batches of items
   struct KsItem {
@@ -346,6 +363,7 @@ class Builder {
   std::vector<char> blob_;
   std::vector<Cmd> cmds_;
   int64_t counters[8] = {0};
+  int64_t ks_alg_limbs = 0;   // see Ctx::ks_alg_limbs
 
  private:
   char* ws_;
@@ -360,7 +378,7 @@ class Builder {
   size_t peak_scratch_ = 0;
   size_t need_max_ = 0;
   void note_need();
-  void push(int kind, int n, int max_y, size_t off, bool inv = false, int64_t units = 0);
+  void push(int kind, int n, int max_y, size_t off, bool inv = false, int64_t units = 0, int64_t units_shared = -1);
 };
 
 // Submit a command list: upload the descriptor blob to 'arena' and launch all

@@ -277,7 +277,8 @@ int build_context(Ctx& c, int log_n, int n_q, int q_bits, int n_p, int p_bits, i
   return 0;
 }
 
-void destroy_context(Ctx& c) {
+void drop_graphs(Ctx& c) {
+  if (c.graphs.empty()) return;
   if (c.stream) (void)hipStreamSynchronize(c.stream);
   else (void)hipDeviceSynchronize();
   for (auto& g : c.graphs) {
@@ -286,6 +287,12 @@ void destroy_context(Ctx& c) {
     if (g.arena) (void)hipFree(g.arena);
   }
   c.graphs.clear();
+}
+
+void destroy_context(Ctx& c) {
+  if (c.stream) (void)hipStreamSynchronize(c.stream);
+  else (void)hipDeviceSynchronize();
+  drop_graphs(c);
   if (c.d_tab) (void)hipFree(c.d_tab);
   if (c.arena) (void)hipFree(c.arena);
   if (c.staging) (void)hipHostFree(c.staging);
@@ -362,7 +369,7 @@ const double* Builder::put_residues(int64_t K, int n_limbs) {
   return put(r);
 }
 
-void Builder::push(int kind, int n, int max_y, size_t off, bool inv, int64_t units) {
+void Builder::push(int kind, int n, int max_y, size_t off, bool inv, int64_t units, int64_t units_shared) {
   // jobs index a grid dimension, which holds at most 65535 workgroups
   if (n > 65535) { fail(-1, "more than 65535 jobs in one launch: split the batch"); return; }
   Cmd c{};
@@ -372,6 +379,7 @@ void Builder::push(int kind, int n, int max_y, size_t off, bool inv, int64_t uni
   c.off = off;
   c.inv = inv;
   c.units = units;
+  c.units_shared = units_shared < 0 ? units : units_shared;
   cmds_.push_back(c);
   counters[7]++;
 }
@@ -417,9 +425,22 @@ void Builder::moddown(const std::vector<ModDownJob>& v) {
 }
 void Builder::inner(const std::vector<InnerJob>& v) {
   int my = 0;
-  int64_t units = 0;
-  for (auto& j : v) { my = std::max(my, j.n_ext); units += (int64_t)j.n_ext * (3 * j.n_digits + 2); }
-  PUSH_JOBS(inner_row_fused(C.T) ? C_INNER_ROW : C_INNER, v, my, false, units);
+  int64_t units = 0, own = 0;
+  // a key read by several jobs of the launch: the union of their key limbs,
+  // which is the set the highest-level job reads (digit and limb prefixes)
+  std::map<const double*, int64_t> key_limbs;
+  for (auto& j : v) {
+    my = std::max(my, j.n_ext);
+    units += (int64_t)j.n_ext * (3 * j.n_digits + 2);
+    own += (int64_t)j.n_ext * (j.n_digits + 2);
+    int64_t& kl = key_limbs[j.key];
+    kl = std::max(kl, (int64_t)2 * j.n_digits * j.n_ext);
+  }
+  int64_t shared = own;
+  for (auto& kv : key_limbs) shared += kv.second;
+  if (v.empty()) return;
+  const char* p = (const char*)put(v);
+  push(inner_row_fused(C.T) ? C_INNER_ROW : C_INNER, (int)v.size(), my, (size_t)(p - arena_), false, units, shared);
 }
 void Builder::automorph(const std::vector<AutoJob>& v) {
   int my = 0;
@@ -453,6 +474,11 @@ void Builder::fft_encode(const std::vector<FftEncJob>& v) {
   push(C_FFTENC, n, -1, off);
   for (int st = 0; st <= C.T.log_n; ++st) push(C_FFTENC, n, st, off);
   push(C_FFTENC, n, 1000, off);
+}
+void Builder::mark() {
+  Cmd c{};
+  c.kind = C_MARK;
+  cmds_.push_back(c);
 }
 void Builder::decode(const int64_t* m, double* z, int nslots, double inv_scale) {
   Cmd c{};
@@ -496,7 +522,20 @@ static hipEvent_t prof_event(Ctx& c) {
 void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
   const DevTables& T = c.T;
   hipStream_t s = c.stream;
+  // segment profiler: an event at the start, at every mark and at the end
+  const bool seg = c.prof_kind == PROF_SEGMENTS;
+  if (seg) {
+    hipEvent_t e = prof_event(c);
+    if (e) (void)hipEventRecord(e, s);
+  }
   for (const Cmd& k : cmds) {
+    if (k.kind == C_MARK) {
+      if (seg) {
+        hipEvent_t e = prof_event(c);
+        if (e) (void)hipEventRecord(e, s);
+      }
+      continue;
+    }
     const void* j = arena + k.off;
     if ((k.kind == C_NTT || k.kind == C_NTT_FIRST || k.kind == C_NTT_SECOND) && ntt_pass_count(T) == 2) {
       // Two-pass NTT, issued in groups of jobs whose data fits ntt_chunk_bytes
@@ -512,7 +551,11 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
       if (w0) (void)hipEventRecord(w0, s);
       const int p_lo = k.kind == C_NTT_SECOND ? 1 : 0, p_hi = k.kind == C_NTT_FIRST ? 1 : 2;
       // a single-pass launch counts as half of its limb transforms
-      if (whole_prof) { c.prof_launches++; c.prof_units += p_hi - p_lo == 2 ? k.units : k.units / 2; }
+      if (whole_prof) {
+        c.prof_launches++;
+        c.prof_units += p_hi - p_lo == 2 ? k.units : k.units / 2;
+        c.prof_units_shared += p_hi - p_lo == 2 ? k.units_shared : k.units_shared / 2;
+      }
       const NttJob* jobs = (const NttJob*)j;
       for (int j0 = 0; j0 < k.n; j0 += chunk) {
         const int nj = std::min(chunk, k.n - j0);
@@ -529,7 +572,10 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
           }
         }
       }
-      if (pass_prof >= p_lo && pass_prof < p_hi) c.prof_units += k.units;
+      if (pass_prof >= p_lo && pass_prof < p_hi) {
+        c.prof_units += k.units;
+        c.prof_units_shared += k.units_shared;
+      }
       if (w0) {
         hipEvent_t w1 = prof_event(c);
         if (w1) (void)hipEventRecord(w1, s);
@@ -542,6 +588,7 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
       if (e) (void)hipEventRecord(e, s);
       c.prof_launches++;
       c.prof_units += k.units;
+      c.prof_units_shared += k.units_shared;
     }
     switch (k.kind) {
       case C_NTT: launch_ntt(T, k.inv, (const NttJob*)j, k.n, k.max_y, s); break;
@@ -568,6 +615,11 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
       hipEvent_t e = prof_event(c);
       if (e) (void)hipEventRecord(e, s);
     }
+  }
+  if (seg) {
+    hipEvent_t e = prof_event(c);
+    if (e) (void)hipEventRecord(e, s);
+    c.prof_launches++;
   }
 }
 
@@ -633,9 +685,21 @@ void Builder::ks_front(const std::vector<KsItem>& items, std::vector<KsTmp>& tmp
       j_fwd_ext.push_back(NttJob{e, e, n_ext, nc, lo, hi});
     }
     InnerJob in{it.d, t.ext, it.key, t.acc, it.top0, it.top1, C.p_mod_q, nc, n_ext, nd, alpha};
+    // section (d) accounting: ciphertext limbs in and out
+    ks_alg_limbs += 3 * (int64_t)nc;
     in.inv_from = fused ? (merged ? l : l + 1) : n_ext;
     in.d_square = it.square ? 1 : 0;
     j_in.push_back(in);
+  }
+  // ... and each distinct key once for the launch (its highest-level reader)
+  {
+    std::map<const double*, int64_t> kl;
+    for (const KsItem& it : items) {
+      const int nc = it.level + 1, nd = (nc + alpha - 1) / alpha;
+      int64_t& v = kl[it.key];
+      v = std::max(v, (int64_t)2 * nd * (nc + n_p));
+    }
+    for (auto& kv : kl) ks_alg_limbs += kv.second;
   }
   ntt(j_inv, true);
   if (fused) {
@@ -1212,9 +1276,10 @@ void Builder::encrypt_into(const std::vector<const int64_t*>& m_dev, const std::
 std::vector<CT> Builder::refresh(const std::vector<CT>& in, const std::vector<uint64_t>& seed,
                                  const std::vector<uint64_t>& index) {
   if (C.boot_mode) return bootstrap(in);
+  mark();
   const int N = C.N, L = C.refresh_level + 1;
-  const double* rsk = C.refresh_sk ? C.refresh_sk : (dry ? C.T.mod : nullptr);
-  if (!rsk) { fail(-3, "modulus chain exhausted and no refresh key registered"); return {}; }
+  const double* rsk = refresh_sk ? refresh_sk : (dry ? C.T.mod : nullptr);
+  if (!rsk) { fail(-3, "modulus chain exhausted: refreshing needs a key owner (or bootstrapping)"); return {}; }
   const size_t mark = scratch_mark();
   std::vector<CT> out;
   std::vector<EwJob> j_dec;
@@ -1258,6 +1323,7 @@ std::vector<CT> Builder::refresh(const std::vector<CT>& in, const std::vector<ui
   ew(j_me);
   ntt(j_fwd, false);
   ew(j_enc);
+  this->mark();
   counters[4] += (int64_t)in.size();
   scratch_release(mark);
   return out;

@@ -54,6 +54,7 @@ def load():
     ct = P(_Ct)
     sig = {
         "secpe_last_error": (C.c_char_p, []),
+        "secpe_strerror": (C.c_char_p, [i32]),
         "secpe_ctx_create": (i32, [P(_Params), i32, vp, P(vp)]),
         "secpe_ctx_destroy": (None, [vp]),
         "secpe_primes": (i32, [vp, P(u64), i32]),
@@ -64,14 +65,15 @@ def load():
         "secpe_galois_elt": (u64, [vp, i64]),
         "secpe_argmax_steps": (i32, [vp, i32, i32, P(i64), i32]),
         "secpe_keygen": (i32, [vp, u64, P(i64), i32, vp, vp]),
-        "secpe_set_refresh_key": (i32, [vp, vp]),
+        "secpe_key_owner_create": (i32, [vp, vp, P(vp)]),
+        "secpe_key_owner_destroy": (None, [vp]),
         "secpe_encrypt": (i32, [vp, vp, P(dbl), i32, i32, u64, ct]),
         "secpe_encrypt_coeffs": (i32, [vp, vp, P(i64), dbl, u64, ct]),
         "secpe_decrypt": (i32, [vp, vp, ct, i32, P(dbl), P(i32)]),
         "secpe_decrypt_coeffs": (i32, [vp, vp, ct, P(i64)]),
         "secpe_workspace_bytes": (sz, [vp, i32, P(i32), P(i32)]),
-        "secpe_eval_argmax": (i32, [vp, ct, i32, i32, dbl, dbl, u64, vp, sz, ct]),
-        "secpe_eval_argmax_batch": (i32, [vp, i32, ct, P(i32), P(i32), P(dbl), P(dbl), P(u64), vp, sz, ct, i32]),
+        "secpe_eval_argmax": (i32, [vp, vp, ct, i32, i32, dbl, dbl, u64, vp, sz, ct]),
+        "secpe_eval_argmax_batch": (i32, [vp, vp, i32, ct, P(i32), P(i32), P(dbl), P(dbl), P(u64), vp, sz, ct, i32]),
         "secpe_counters": (i32, [vp, P(i64)]),
         "secpe_ct_export": (i32, [vp, ct, P(u64)]),
         "secpe_ct_import": (i32, [vp, P(u64), i32, dbl, ct]),
@@ -87,29 +89,32 @@ def load():
         "secpe_packed_shape": (i32, [vp, i32, P(i32), P(i32), P(i32)]),
         "secpe_phoenix_steps": (i32, [vp, i32, i32, P(i64), i32]),
         "secpe_phoenix_workspace_bytes": (sz, [vp, i32, i32]),
-        "secpe_eval_argmax_phoenix": (i32, [vp, ct, i32, i32, dbl, dbl, u64, vp, sz, ct]),
+        "secpe_eval_argmax_phoenix": (i32, [vp, vp, ct, i32, i32, dbl, dbl, u64, vp, sz, ct]),
         "secpe_encrypt_packed": (i32, [vp, vp, i32, P(dbl), P(i32), P(i32), u64, ct]),
         "secpe_packed_workspace_bytes": (sz, [vp, i32, P(i32), P(i32), P(i32)]),
-        "secpe_eval_argmax_packed": (i32, [vp, i32, ct, P(i32), P(i32), P(i32), P(dbl), P(dbl), P(u64), vp, sz, ct]),
-        "secpe_autotune": (i32, [vp, i32, ct, P(i32), P(i32), P(dbl), P(dbl), P(u64), vp, sz, ct, P(i32), P(dbl),
-                                 i32]),
+        "secpe_eval_argmax_packed": (i32, [vp, vp, i32, ct, P(i32), P(i32), P(i32), P(dbl), P(dbl), P(u64), vp, sz,
+                                           ct]),
+        "secpe_autotune": (i32, [vp, vp, i32, ct, P(i32), P(i32), P(dbl), P(dbl), P(u64), vp, sz, ct, P(i32),
+                                 P(dbl), i32]),
         "secpe_op_mul_plain": (i32, [vp, ct, P(dbl), i32, dbl, vp, sz, ct]),
         "secpe_op_rescale": (i32, [vp, ct, vp, sz, ct]),
         "secpe_op_mul_relin": (i32, [vp, ct, ct, vp, sz, ct]),
         "secpe_op_mul_relin_rescale": (i32, [vp, ct, ct, vp, sz, ct]),
         "secpe_op_rotate": (i32, [vp, ct, i64, vp, sz, ct]),
-        "secpe_op_refresh": (i32, [vp, ct, u64, u64, vp, sz, ct]),
+        "secpe_op_refresh": (i32, [vp, vp, ct, u64, u64, vp, sz, ct]),
         "secpe_op_eval_odd9": (i32, [vp, ct, P(dbl), dbl, dbl, vp, sz, ct]),
         "secpe_op_key_switch": (i32, [vp, i32, P(u64), i32, vp, sz, P(u64), P(u64)]),
         "secpe_op_ntt": (i32, [vp, i32, P(u64), i32, P(u64), P(u64)]),
         "secpe_op_ring_mul": (i32, [vp, i32, P(u64), P(u64), P(u64)]),
         "secpe_op_encode": (i32, [vp, P(dbl), i32, dbl, P(i64)]),
         "secpe_profile_begin": (i32, [vp, i32]),
-        "secpe_profile_end": (i32, [vp, P(i64), P(dbl), P(i64)]),
+        "secpe_profile_end": (i32, [vp, P(i64), P(dbl), P(i64), P(i64)]),
+        "secpe_keyswitch_traffic": (i32, [vp, P(i64)]),
+        "secpe_profile_segments": (i32, [vp, P(dbl), i32]),
         "secpe_ntt_cts": (i32, [vp, ct, i32, i32]),
         "secpe_rotate_workspace_bytes": (sz, [vp, i32]),
         "secpe_rotate_batch": (i32, [vp, i32, ct, P(i64), vp, sz, ct]),
-        "secpe_server_create": (i32, [vp, vp, sz, i32, P(vp)]),
+        "secpe_server_create": (i32, [vp, vp, vp, sz, i32, P(vp)]),
         "secpe_server_destroy": (None, [vp]),
         "secpe_server_request_bytes": (sz, [vp, i32, i32]),
         "secpe_server_submit": (i32, [vp, ct, i32, i32, dbl, dbl, u64, vp, P(u64)]),
@@ -137,9 +142,9 @@ def load():
 def exported_symbols():
     """Names the library must export (those declared in include/secpe.h)."""
     return sorted(
-        ["secpe_last_error", "secpe_ctx_create", "secpe_ctx_destroy", "secpe_primes", "secpe_slots",
+        ["secpe_last_error", "secpe_strerror", "secpe_ctx_create", "secpe_ctx_destroy", "secpe_primes", "secpe_slots",
          "secpe_ct_bytes", "secpe_sk_bytes", "secpe_key_bytes", "secpe_galois_elt", "secpe_argmax_steps",
-         "secpe_keygen", "secpe_set_refresh_key", "secpe_encrypt", "secpe_encrypt_coeffs", "secpe_decrypt",
+         "secpe_keygen", "secpe_key_owner_create", "secpe_key_owner_destroy", "secpe_encrypt", "secpe_encrypt_coeffs", "secpe_decrypt",
          "secpe_decrypt_coeffs", "secpe_workspace_bytes", "secpe_eval_argmax", "secpe_eval_argmax_batch",
          "secpe_counters", "secpe_ct_export", "secpe_ct_import", "secpe_key_export", "secpe_sk_export",
          "secpe_sync", "secpe_op_workspace_bytes", "secpe_op_add", "secpe_op_sub", "secpe_op_add_const",
@@ -148,7 +153,7 @@ def exported_symbols():
          "secpe_phoenix_workspace_bytes", "secpe_eval_argmax_phoenix", "secpe_op_mul_plain", "secpe_op_rescale", "secpe_op_mul_relin",
          "secpe_op_mul_relin_rescale", "secpe_op_rotate", "secpe_op_refresh", "secpe_op_eval_odd9",
          "secpe_op_key_switch", "secpe_op_ntt", "secpe_op_ring_mul", "secpe_op_encode", "secpe_profile_begin",
-         "secpe_profile_end", "secpe_ntt_cts", "secpe_rotate_workspace_bytes", "secpe_rotate_batch",
+         "secpe_profile_end", "secpe_profile_segments", "secpe_keyswitch_traffic", "secpe_ntt_cts", "secpe_rotate_workspace_bytes", "secpe_rotate_batch",
          "secpe_server_create", "secpe_server_destroy", "secpe_server_request_bytes", "secpe_server_submit",
          "secpe_server_step", "secpe_server_launch", "secpe_server_ready", "secpe_keys_share",
          "secpe_server_collect", "secpe_set_boot", "secpe_boot_steps", "secpe_boot_key_bytes", "secpe_boot_setup",
@@ -169,6 +174,28 @@ class Ciphertext:
 
     def _c(self):
         return _Ct(C.c_void_p(self.buf.data_ptr()), self.level, self.scale)
+
+
+class KeyOwner:
+    """The key owner's handle (secpe_key_owner): names the secret for the
+    refresh stand-in of bootstrapping.  Evaluations that may refresh take it
+    explicitly; without one they stop with SECPE_ENOLEVEL."""
+
+    def __init__(self, ctx, sk):
+        self.lib = ctx.lib
+        self.sk = sk
+        h = C.c_void_p()
+        ctx._check(self.lib.secpe_key_owner_create(ctx.h, C.c_void_p(sk.data_ptr()), C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.secpe_key_owner_destroy(self.h)
+            self.h = None
+
+
+def _owner(owner):
+    return owner.h if owner is not None else None
 
 
 class Context:
@@ -234,7 +261,10 @@ class Context:
         return [int(v) for v in out[:n]]
 
     # -- keys ------------------------------------------------------------------
-    def keygen(self, seed, steps, refresh=True):
+    def keygen(self, seed, steps):
+        """Client key generation: the secret (kept here for the client's
+        encrypt and decrypt calls) and the switching keys the context evaluates
+        with.  The context itself never holds the secret."""
         steps = list(steps)
         self.sk = self._empty(self.lib.secpe_sk_bytes(self.h))
         self.evk = self._empty(self.lib.secpe_key_bytes(self.h) * (1 + len(steps)))
@@ -242,18 +272,18 @@ class Context:
         self._check(self.lib.secpe_keygen(self.h, int(seed), _p(st, C.c_int64), len(steps),
                                           C.c_void_p(self.sk.data_ptr()), C.c_void_p(self.evk.data_ptr())))
         self.steps = steps
-        if refresh:
-            self.set_refresh_key(self.sk)
         return self.sk, self.evk
 
+    def key_owner(self, sk=None):
+        """A key-owner handle for the client's secret (or the given one)."""
+        return KeyOwner(self, self.sk if sk is None else sk)
+
     def share_keys(self, other):
-        """Evaluate with other's switching and refresh keys (same parameters and
-        device); this context keeps its own stream."""
+        """Evaluate with other's switching keys (same parameters and device);
+        this context keeps its own stream.  The client-side secret reference is
+        copied for this binding's encrypt and decrypt conveniences only."""
         self._check(self.lib.secpe_keys_share(self.h, other.h))
         self.sk, self.evk, self.steps = other.sk, other.evk, other.steps
-
-    def set_refresh_key(self, sk):
-        self._check(self.lib.secpe_set_refresh_key(self.h, C.c_void_p(sk.data_ptr()) if sk is not None else None))
 
     # -- bootstrapping -----------------------------------------------------------
     def set_boot(self, h, K, r, deg, ratio, groups, refresh):
@@ -344,7 +374,7 @@ class Context:
             self._check(n)
         return [int(v) for v in out[:n]]
 
-    def eval_argmax_phoenix(self, ct, K, Cc, d_min, d_max, refresh_seed, ws=None, out=None):
+    def eval_argmax_phoenix(self, ct, K, Cc, d_min, d_max, refresh_seed, ws=None, out=None, owner=None):
         if ws is None:
             nb = self.lib.secpe_phoenix_workspace_bytes(self.h, int(K), int(Cc))
             if nb == 0:
@@ -352,9 +382,9 @@ class Context:
             ws = self._empty(nb)
         out = self.new_ct() if out is None else out
         c = out._c()
-        self._check(self.lib.secpe_eval_argmax_phoenix(self.h, C.byref(ct._c()), int(K), int(Cc), float(d_min),
-                                                       float(d_max), int(refresh_seed), C.c_void_p(ws.data_ptr()),
-                                                       ws.numel() * 8, C.byref(c)))
+        self._check(self.lib.secpe_eval_argmax_phoenix(self.h, _owner(owner), C.byref(ct._c()), int(K), int(Cc),
+                                                       float(d_min), float(d_max), int(refresh_seed),
+                                                       C.c_void_p(ws.data_ptr()), ws.numel() * 8, C.byref(c)))
         out.level, out.scale = c.level, c.scale
         return out
 
@@ -396,7 +426,7 @@ class Context:
             raise SecpeError(self.lib.secpe_last_error().decode())
         return self._empty(n)
 
-    def eval_argmax_packed(self, cts, groups, d_min, d_max, seeds, ws=None, outs=None):
+    def eval_argmax_packed(self, cts, groups, d_min, d_max, seeds, ws=None, outs=None, owner=None):
         """groups[i]: the (K, C) shapes packed in cts[i]; d_min, d_max: per block, concatenated."""
         n = len(cts)
         nb, Ks, Cs = self._packed_arrays(groups)
@@ -409,7 +439,7 @@ class Context:
             outs = [self.new_ct() for _ in range(n)]
         cin = (_Ct * n)(*[c._c() for c in cts])
         cout = (_Ct * n)(*[c._c() for c in outs])
-        self._check(self.lib.secpe_eval_argmax_packed(self.h, n, cin, _p(nb, C.c_int), _p(Ks, C.c_int),
+        self._check(self.lib.secpe_eval_argmax_packed(self.h, _owner(owner), n, cin, _p(nb, C.c_int), _p(Ks, C.c_int),
                                                       _p(Cs, C.c_int), _p(lo, C.c_double), _p(hi, C.c_double),
                                                       _p(sd, C.c_uint64), C.c_void_p(ws.data_ptr()), ws.numel() * 8,
                                                       cout))
@@ -446,7 +476,7 @@ class Context:
     def workspace(self, Ks, Cs):
         return self._empty(self.workspace_bytes(Ks, Cs))
 
-    def eval_argmax_batch(self, cts, Ks, Cs, d_min, d_max, seeds, ws=None, outs=None, graph=False):
+    def eval_argmax_batch(self, cts, Ks, Cs, d_min, d_max, seeds, ws=None, outs=None, graph=False, owner=None):
         n = len(cts)
         Ks = np.ascontiguousarray(Ks, dtype=np.int32)
         Cs = np.ascontiguousarray(Cs, dtype=np.int32)
@@ -459,7 +489,7 @@ class Context:
             outs = [self.new_ct() for _ in range(n)]
         cin = (_Ct * n)(*[c._c() for c in cts])
         cout = (_Ct * n)(*[c._c() for c in outs])
-        self._check(self.lib.secpe_eval_argmax_batch(self.h, n, cin, _p(Ks, C.c_int), _p(Cs, C.c_int),
+        self._check(self.lib.secpe_eval_argmax_batch(self.h, _owner(owner), n, cin, _p(Ks, C.c_int), _p(Cs, C.c_int),
                                                      _p(dmin, C.c_double), _p(dmax, C.c_double),
                                                      _p(sd, C.c_uint64), C.c_void_p(ws.data_ptr()),
                                                      ws.numel() * 8, cout, SECPE_GRAPH if graph else 0))
@@ -470,7 +500,7 @@ class Context:
     AUTOTUNE_CANDIDATES = [dict(modup_outputs_per_workgroup=2 if i & 1 else 4,
                                 ntt_job_group_mib=128 if i & 2 else None) for i in range(4)]
 
-    def autotune(self, cts, Ks, Cs, d_min, d_max, seeds, ws, outs):
+    def autotune(self, cts, Ks, Cs, d_min, d_max, seeds, ws, outs, owner=None):
         """Time the batch under each candidate schedule; the fastest stays set."""
         n = len(cts)
         Ks = np.ascontiguousarray(Ks, dtype=np.int32)
@@ -482,15 +512,15 @@ class Context:
         cout = (_Ct * n)(*[c._c() for c in outs])
         chosen = C.c_int(-1)
         ms = np.zeros(len(self.AUTOTUNE_CANDIDATES), dtype=np.float64)
-        self._check(self.lib.secpe_autotune(self.h, n, cin, _p(Ks, C.c_int), _p(Cs, C.c_int), _p(dmin, C.c_double),
+        self._check(self.lib.secpe_autotune(self.h, _owner(owner), n, cin, _p(Ks, C.c_int), _p(Cs, C.c_int), _p(dmin, C.c_double),
                                             _p(dmax, C.c_double), _p(sd, C.c_uint64), C.c_void_p(ws.data_ptr()),
                                             ws.numel() * 8, cout, C.byref(chosen), _p(ms, C.c_double), len(ms)))
         for o, c in zip(outs, cout):
             o.level, o.scale = c.level, c.scale
         return chosen.value, [dict(c, ms=round(float(t), 3)) for c, t in zip(self.AUTOTUNE_CANDIDATES, ms)]
 
-    def eval_argmax(self, ct, K, Cc, d_min, d_max, refresh_seed, ws=None):
-        return self.eval_argmax_batch([ct], [K], [Cc], [d_min], [d_max], [refresh_seed], ws=ws)[0]
+    def eval_argmax(self, ct, K, Cc, d_min, d_max, refresh_seed, ws=None, owner=None):
+        return self.eval_argmax_batch([ct], [K], [Cc], [d_min], [d_max], [refresh_seed], ws=ws, owner=owner)[0]
 
     def counters(self):
         out = np.zeros(8, dtype=np.int64)
@@ -503,7 +533,7 @@ class Context:
 
     # -- measurement -------------------------------------------------------------
     PROF = dict(ntt_fwd=0, ntt_inv=1, ew=2, modup=3, moddown=4, inner=5, auto=6, spread=7, ntt_fwd_col=8,
-                ntt_fwd_row=9)
+                ntt_fwd_row=9, segments=10)
 
     def profile_begin(self, kind):
         self._check(self.lib.secpe_profile_begin(self.h, self.PROF[kind] if isinstance(kind, str) else int(kind)))
@@ -512,8 +542,22 @@ class Context:
         n = C.c_int64(0)
         ms = C.c_double(0.0)
         u = C.c_int64(0)
-        self._check(self.lib.secpe_profile_end(self.h, C.byref(n), C.byref(ms), C.byref(u)))
-        return dict(launches=int(n.value), ms=float(ms.value), units=int(u.value))
+        us = C.c_int64(0)
+        self._check(self.lib.secpe_profile_end(self.h, C.byref(n), C.byref(ms), C.byref(u), C.byref(us)))
+        return dict(launches=int(n.value), ms=float(ms.value), units=int(u.value), units_shared=int(us.value))
+
+    def profile_segments(self):
+        """Milliseconds between consecutive events of the last 'segments' profile."""
+        ms = np.zeros(4096)
+        n = self.lib.secpe_profile_segments(self.h, _p(ms, C.c_double), len(ms))
+        self._check(min(n, 0))
+        return [float(v) for v in ms[:n]]
+
+    def keyswitch_traffic(self):
+        """Algorithmic HBM bytes of the last evaluation's key switches (keys once per launch)."""
+        b = C.c_int64(0)
+        self._check(self.lib.secpe_keyswitch_traffic(self.h, C.byref(b)))
+        return int(b.value)
 
     def ntt_cts(self, cts, inverse):
         arr = (_Ct * len(cts))(*[c._c() for c in cts])
@@ -609,8 +653,8 @@ class Context:
     def rotate(self, a, step):
         return self._op(self.lib.secpe_op_rotate, C.byref(a._c()), int(step))
 
-    def refresh(self, a, seed, index):
-        return self._op(self.lib.secpe_op_refresh, C.byref(a._c()), int(seed), int(index))
+    def refresh(self, a, seed, index, owner):
+        return self._op(self.lib.secpe_op_refresh, _owner(owner), C.byref(a._c()), int(seed), int(index))
 
     def eval_odd9(self, a, coef, gain, target):
         coef = np.ascontiguousarray(coef, dtype=np.float64)
@@ -653,13 +697,14 @@ class Context:
 class Server:
     """Continuous-batching request loop over one workspace (secpe_server_*)."""
 
-    def __init__(self, ctx, ws_bytes, max_active=256):
+    def __init__(self, ctx, ws_bytes, max_active=256, owner=None):
         self.ctx = ctx
         self.lib = ctx.lib
+        self.owner = owner
         self.ws = ctx._empty(ws_bytes)
         h = C.c_void_p()
-        ctx._check(self.lib.secpe_server_create(ctx.h, C.c_void_p(self.ws.data_ptr()), self.ws.numel() * 8,
-                                                int(max_active), C.byref(h)))
+        ctx._check(self.lib.secpe_server_create(ctx.h, _owner(owner), C.c_void_p(self.ws.data_ptr()),
+                                                self.ws.numel() * 8, int(max_active), C.byref(h)))
         self.h = h
         self.results = {}
         self._inputs = {}

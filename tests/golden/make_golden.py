@@ -6,16 +6,26 @@ coefficient domain (canonical residues, uint64 little-endian, [2][level+1][N]),
 its level and scale, the decrypted z and the operation counts.  The GPU parity
 test recomputes the same digest from the HIP path.
 
-Cases: config 1 (toy N=2^13, 8 x 30-bit primes, K=4, C=2; and on 36 primes,
-alpha = 4, with no refresh at all) and config 2
-(N=2^16, 24 x 50-bit primes, dnum 3, K=8, C=4, margin >= 0.05), plus one
-config-3 query.  Run from the repository root: python tests/golden/make_golden.py
+Cases:
+  config 1   toy N=2^13, 8 x 30-bit primes, K=4, C=2; and on 36 primes
+             (alpha = 4) with no refresh at all;
+  config 2   N=2^16, 24 x 50-bit primes, dnum 3, K=8, C=4, margin >= 0.05,
+             with the default evaluator and with the textbook one (every
+             product relinearised, then rescaled);
+  config 3   24 queries of the 256-query batch (N=2^16): the first two of
+             every padded shape (K', C') in {4, 8, 16} x {2, 4, 8, 16};
+  config 5   three requests of the serving mix at N=2^16 with K' or C' = 32.
+Each case keys its own oracle with the rotations its shape needs (a key
+depends only on the seed and its Galois element, so these equal the keys of
+any larger set).  Cases run in parallel processes.
+Run from the repository root: python tests/golden/make_golden.py [names...]
 """
 import hashlib
 import json
 import os
 import sys
 import time
+from concurrent.futures import ProcessPoolExecutor
 
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
@@ -25,29 +35,61 @@ from oracle.ckks import Oracle, argmax_rotation_steps  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "argmax_digests.json")
 
-CASES = [
-    # name, parameter set, workload config id, query index, rotation keys for (k_max, c_max)
-    ("config1_toy", "toy", 1, 0, (4, 2)),
+
+def _pow2(v):
+    return 1 << max(0, (v - 1).bit_length())
+
+
+def config3_sample(per_shape=2):
+    """The first per_shape queries of every padded shape in the 256-query batch."""
+    seen = {}
+    for q in range(256):
+        K, C = W.query_shape(3, q)
+        key = (_pow2(K), _pow2(C))
+        if len(seen.setdefault(key, [])) < per_shape:
+            seen[key].append(q)
+    return sorted(q for qs in seen.values() for q in qs)
+
+
+def config5_sample():
+    """Serving requests whose padded shape reaches 32: K' = C' = 32, C' = 32 only, K' = 32 only."""
+    want = [lambda k, c: k > 16 and c > 16, lambda k, c: k <= 16 and c > 16, lambda k, c: k > 16 and c <= 16]
+    out = []
+    for pred in want:
+        for q in range(4000):
+            K, C = W.query_shape(5, q)
+            if pred(K, C):
+                out.append(q)
+                break
+    return out
+
+
+# name -> (parameter set, workload config id, query index, evaluator)
+CASES = {
+    "config1_toy": ("toy", 1, 0, "merged"),
     # config 1 on a 36-prime chain: the whole of Algorithm 1 without a refresh
-    ("config1_toy_deep", "toy_deep", 1, 0, (4, 2)),
-    ("config2_full", "full", 2, 0, (16, 14)),
-    ("config3_full_q0", "full", 3, 0, (16, 14)),
-]
+    "config1_toy_deep": ("toy_deep", 1, 0, "merged"),
+    "config2_full": ("full", 2, 0, "merged"),
+    "config2_full_textbook": ("full", 2, 0, "textbook"),
+}
+for _q in config3_sample():
+    CASES[f"config3_full_q{_q}"] = ("full", 3, _q, "merged")
+for _q in config5_sample():
+    CASES[f"config5_full_q{_q}"] = ("full", 5, _q, "merged")
 
 
 def digest(arr):
     return hashlib.sha256(arr.astype("<u8").tobytes()).hexdigest()
 
 
-def run_case(name, pset, cfg, q, kc, orc_cache):
-    o = orc_cache.get(pset)
-    if o is None:
-        o = Oracle.from_params(W.PARAMS[pset])
-        t = time.time()
-        o.keygen(W.KEYGEN_SEED, argmax_rotation_steps(*kc, o.slots))
-        print(f"[{pset}] keygen {time.time() - t:.1f} s", flush=True)
-        orc_cache[pset] = o
+def run_case(name):
+    pset, cfg, q, evaluator = CASES[name]
     d = W.query(cfg, q)
+    o = Oracle.from_params(W.PARAMS[pset])
+    o.set_textbook(evaluator == "textbook")
+    t = time.time()
+    o.keygen(W.KEYGEN_SEED, argmax_rotation_steps(d["K"], d["C"], o.slots))
+    tk = time.time() - t
     ct = o.encrypt_logits(d["logits"], d["encrypt_seed"])
     o.reset_counters()
     t = time.time()
@@ -56,25 +98,29 @@ def run_case(name, pset, cfg, q, kc, orc_cache):
     arr = z.export()
     zz = o.decrypt_decode(z, d["C"])
     rec = {
-        "params": pset, "config": cfg, "query": q, "K": d["K"], "C": d["C"],
+        "params": pset, "config": cfg, "query": q, "K": d["K"], "C": d["C"], "evaluator": evaluator,
         "input_sha256": digest(ct.export()),
         "output_sha256": digest(arr), "level": z.level, "scale": z.scale,
         "z": [float(v) for v in zz], "counters": o.counters(), "oracle_seconds": round(dt, 1),
+        "secret_weight": int((o.secret() != 0).sum()),
     }
-    print(f"{name}: {dt:.1f} s, level {z.level}, z {zz}", flush=True)
-    return rec
+    print(f"{name}: keygen {tk:.1f} s, eval {dt:.1f} s, level {z.level}, z {zz}", flush=True)
+    return name, rec
 
 
 def main():
-    names = sys.argv[1:] or [c[0] for c in CASES]
+    names = sys.argv[1:] or list(CASES)
+    # longest first, so the pool stays busy to the end
+    cost = {"toy": 0, "toy_deep": 1}
+    names.sort(key=lambda n: (-CASES[n][1] if CASES[n][0] == "full" else cost.get(CASES[n][0], 0)))
     out = {}
     if os.path.exists(OUT):
         with open(OUT) as f:
             out = json.load(f)
-    cache = {}
-    for case in CASES:
-        if case[0] in names:
-            out[case[0]] = run_case(*case, cache)
+    workers = int(os.environ.get("GOLDEN_WORKERS", "8"))
+    with ProcessPoolExecutor(workers) as ex:
+        for name, rec in ex.map(run_case, names):
+            out[name] = rec
             with open(OUT, "w") as f:
                 json.dump(out, f, indent=1, sort_keys=True)
 

@@ -88,3 +88,21 @@ def test_server_and_key_sharing_refuse_null_handles(lib_path):
     fn.restype = ctypes.c_int
     fn.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     assert fn(None, None) < 0
+
+
+def test_strerror_and_key_owner_arguments(lib_path):
+    """Every status code has a fixed description; a key owner needs a context
+    and a secret, and evaluations check both before any device work."""
+    lib = ctypes.CDLL(lib_path)
+    lib.secpe_strerror.restype = ctypes.c_char_p
+    lib.secpe_strerror.argtypes = [ctypes.c_int]
+    texts = {c: lib.secpe_strerror(c).decode() for c in (0, -1, -2, -3, -4, -5, -99)}
+    assert len(set(texts.values())) == len(texts)
+    assert "key owner" in texts[-3]
+    fn = lib.secpe_key_owner_create
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    h = ctypes.c_void_p()
+    assert fn(None, None, ctypes.byref(h)) < 0 and not h.value
+    lib.secpe_key_owner_destroy.argtypes = [ctypes.c_void_p]
+    lib.secpe_key_owner_destroy(None)

@@ -40,6 +40,7 @@ def full_gpu():
     from paper_2502_00847_amd.secpe import Context
     g = Context(W.PARAMS["full"])
     g.keygen(W.KEYGEN_SEED, g.argmax_steps(16, 14))
+    g.owner = g.key_owner()
     return g
 
 
@@ -53,6 +54,7 @@ def full_pair():
     steps = [1, 4096]
     print("[full_pair] oracle keygen", flush=True)
     g.keygen(7, steps)
+    g.owner = g.key_owner()
     o.keygen(7, steps)
     return g, o
 
@@ -123,7 +125,7 @@ def test_full_refresh_and_poly(full_pair):
     ct = o.encrypt(o.encode(z, 2.0**50), 2.0**50, 6)
     low = o.lower(ct, 3)
     gl = g.import_(low.export(), low.scale)
-    _same(g, g.refresh(gl, 99, 1), o.refresh(low, 99, 1))
+    _same(g, g.refresh(gl, 99, 1, owner=g.owner), o.refresh(low, 99, 1))
 
 
 @pytest.mark.parametrize("level", [23, 12, 1])
@@ -163,7 +165,7 @@ def test_full_argmax_matches_oracle_digest(full_gpu, golden, case):
     d = W.query(rec["config"], rec["query"])
     ct = g.encrypt(d["logits"], d["encrypt_seed"])
     assert _digest(g.export(ct)) == rec["input_sha256"]
-    z = g.eval_argmax(ct, d["K"], d["C"], d["d_min"], d["d_max"], d["refresh_seed"])
+    z = g.eval_argmax(ct, d["K"], d["C"], d["d_min"], d["d_max"], d["refresh_seed"], owner=g.owner)
     assert (z.level, z.scale) == (rec["level"], rec["scale"])
     assert _digest(g.export(z)) == rec["output_sha256"]
     zz, idx = g.decrypt(z, d["C"])
@@ -174,15 +176,62 @@ def test_full_argmax_matches_oracle_digest(full_gpu, golden, case):
         assert cnt[k] == rec["counters"][k], k
 
 
+def _batch_digests(g, recs):
+    """Evaluate the golden cases in one batched launch; check each against the oracle's digest."""
+    ds = [W.query(r["config"], r["query"]) for r in recs]
+    cts = [g.encrypt(d["logits"], d["encrypt_seed"]) for d in ds]
+    for ct, r in zip(cts, recs):
+        assert _digest(g.export(ct)) == r["input_sha256"]
+    outs = g.eval_argmax_batch(cts, [d["K"] for d in ds], [d["C"] for d in ds], [d["d_min"] for d in ds],
+                               [d["d_max"] for d in ds], [d["refresh_seed"] for d in ds], owner=g.owner)
+    bad = []
+    for r, d, z in zip(recs, ds, outs):
+        ok = (z.level, z.scale) == (r["level"], r["scale"]) and _digest(g.export(z)) == r["output_sha256"]
+        zz, idx = g.decrypt(z, d["C"])
+        ok = ok and np.allclose(zz, r["z"], rtol=0, atol=1e-9)
+        i0, _, margin = sim.t0_argmax(d["logits"])
+        if margin / (d["d_max"] - d["d_min"]) >= 2.0**-10:
+            ok = ok and idx == i0
+        if not ok:
+            bad.append((r["config"], r["query"], d["K"], d["C"]))
+    assert not bad, bad
+
+
+def test_config3_sample_matches_oracle_digests_batched(full_gpu, golden):
+    """24 queries of the 256-query batch, two of every padded shape (K', C') in
+    {4, 8, 16} x {2, 4, 8, 16} (refreshes at level 14 for C' = 8, 16 included),
+    evaluated in one batched launch: every output ciphertext is bit-exact with
+    the oracle's."""
+    recs = [r for k, r in sorted(golden.items()) if k.startswith("config3_full_q")]
+    assert len(recs) >= 16
+    shapes = {(1 << (r["K"] - 1).bit_length(), 1 << (r["C"] - 1).bit_length()) for r in recs}
+    assert len(shapes) == 12
+    _batch_digests(full_gpu, recs)
+
+
+def test_config5_full_matches_oracle_digests():
+    """Serving-mix shapes at N = 2^16 with K' or C' = 32 (five prompt-sum
+    doublings, five QuickMax steps): bit-exact with the oracle's digests."""
+    from paper_2502_00847_amd.secpe import Context
+    with open(GOLDEN) as f:
+        recs = [r for k, r in sorted(json.load(f).items()) if k.startswith("config5_full_q")]
+    assert len(recs) == 3
+    g = Context(W.PARAMS["full"])
+    g.keygen(W.KEYGEN_SEED, g.argmax_steps(32, 20))
+    g.owner = g.key_owner()
+    _batch_digests(g, recs)
+
+
 def test_toy_argmax_matches_oracle_digest(golden):
     """Config 1: N=2^13, 8 x 30-bit primes + 1 special prime, scale 2^30, K=4, C=2."""
     from paper_2502_00847_amd.secpe import Context
     rec = golden["config1_toy"]
     g = Context(W.PARAMS["toy"])
     g.keygen(W.KEYGEN_SEED, g.argmax_steps(4, 2))
+    g.owner = g.key_owner()
     d = W.query(1, 0)
     ct = g.encrypt(d["logits"], d["encrypt_seed"])
-    z = g.eval_argmax(ct, d["K"], d["C"], d["d_min"], d["d_max"], d["refresh_seed"])
+    z = g.eval_argmax(ct, d["K"], d["C"], d["d_min"], d["d_max"], d["refresh_seed"], owner=g.owner)
     assert _digest(g.export(z)) == rec["output_sha256"]
     zz, idx = g.decrypt(z, 2)
     assert idx == sim.t0_argmax(d["logits"])[0]
@@ -195,9 +244,9 @@ def test_toy_deep_argmax_without_refresh(golden):
     rec = golden["config1_toy_deep"]
     g = Context(W.PARAMS["toy_deep"])
     g.keygen(W.KEYGEN_SEED, g.argmax_steps(4, 2))
-    g.set_refresh_key(None)
     d = W.query(1, 0)
     ct = g.encrypt(d["logits"], d["encrypt_seed"])
+    # no key owner: the evaluation is the server's alone
     z = g.eval_argmax(ct, d["K"], d["C"], d["d_min"], d["d_max"], d["refresh_seed"])
     assert z.level == rec["level"] and z.scale == rec["scale"]
     assert _digest(g.export(z)) == rec["output_sha256"]
@@ -222,7 +271,7 @@ def test_config3_batch_indices_and_bit_identity(full_gpu):
         grp = list(range(s, s + 64))
         outs += g.eval_argmax_batch([cts[i] for i in grp], [qs[i]["K"] for i in grp], [qs[i]["C"] for i in grp],
                                     [qs[i]["d_min"] for i in grp], [qs[i]["d_max"] for i in grp],
-                                    [qs[i]["refresh_seed"] for i in grp])
+                                    [qs[i]["refresh_seed"] for i in grp], owner=g.owner)
     bad = []
     for i, (q, o) in enumerate(zip(qs, outs)):
         z, idx = g.decrypt(o, q["C"])
@@ -231,7 +280,7 @@ def test_config3_batch_indices_and_bit_identity(full_gpu):
             bad.append(i)
     assert not bad, bad
     for i in (0, 37, 130, 255):
-        alone = g.eval_argmax(cts[i], qs[i]["K"], qs[i]["C"], qs[i]["d_min"], qs[i]["d_max"], qs[i]["refresh_seed"])
+        alone = g.eval_argmax(cts[i], qs[i]["K"], qs[i]["C"], qs[i]["d_min"], qs[i]["d_max"], qs[i]["refresh_seed"], owner=g.owner)
         assert np.array_equal(g.export(alone), g.export(outs[i]))
 
 
@@ -245,7 +294,7 @@ def test_config3_packed_indices(full_gpu):
     assert per == 128 and (kp, cp, bsz) == (16, 16, 256)
     groups = [shapes[i:i + per] for i in range(0, 256, per)]
     cts = [g.encrypt_packed([q["logits"] for q in qs[i:i + per]], 7000 + i) for i in range(0, 256, per)]
-    outs = g.eval_argmax_packed(cts, groups, [q["d_min"] for q in qs], [q["d_max"] for q in qs], [8000, 8001])
+    outs = g.eval_argmax_packed(cts, groups, [q["d_min"] for q in qs], [q["d_max"] for q in qs], [8000, 8001], owner=g.owner)
     bad = []
     for j, (ct, grp) in enumerate(zip(outs, groups)):
         for b, (zb, idx) in enumerate(g.decrypt_packed(ct, grp)):

@@ -41,6 +41,7 @@ def _pair(name, k_max=8, c_max=8):
     steps = g.argmax_steps(k_max, c_max) + EXTRA_STEPS
     print(f"[pair] {name} keygen {len(steps)} rotation keys", flush=True)
     g.keygen(SEED, steps)
+    g.owner = g.key_owner()
     o.keygen(SEED, steps)
     return g, o, steps
 
@@ -238,7 +239,7 @@ def test_refresh_bit_exact(tiny):
     g, o, _ = tiny
     a, _ = _rand_ct(o, 11, level=2)
     ga = g.import_(a.export(), a.scale)
-    _same(g, g.refresh(ga, 1234, 3), o.refresh(a, 1234, 3))
+    _same(g, g.refresh(ga, 1234, 3, owner=g.owner), o.refresh(a, 1234, 3))
 
 
 def test_eval_odd9_bit_exact(tiny):
@@ -257,7 +258,7 @@ def _argmax_pair(g, o, K, C, cfg=9, q=0):
     ct_o = o.encrypt_logits(y, enc)
     ct_g = g.encrypt(y, enc)
     zo = o.eval_argmax(ct_o, K, C, dmin, dmax, ref)
-    zg = g.eval_argmax(ct_g, K, C, dmin, dmax, ref)
+    zg = g.eval_argmax(ct_g, K, C, dmin, dmax, ref, owner=g.owner)
     return y, zo, zg
 
 
@@ -282,7 +283,7 @@ def test_argmax_refresh_below_top_bit_exact(name):
     ga = g.import_(a.export(), a.scale)
     r = o.refresh(a, 77, 2)
     assert r.level == 6
-    _same(g, g.refresh(ga, 77, 2), r)
+    _same(g, g.refresh(ga, 77, 2, owner=g.owner), r)
     y, zo, zg = _argmax_pair(g, o, 3, 5, q=5)
     _same(g, zg, zo)
 
@@ -311,11 +312,11 @@ def test_packed_argmax_bit_exact(name, tiny, p13):
         _same(g, gcts[-1], octs[-1])
     lo_all = [v for _, lo, _ in cases for v in lo]
     hi_all = [v for _, _, hi in cases for v in hi]
-    outs = g.eval_argmax_packed(gcts, groups, lo_all, hi_all, [60, 61])
+    outs = g.eval_argmax_packed(gcts, groups, lo_all, hi_all, [60, 61], owner=g.owner)
     for i, (blocks, lo, hi) in enumerate(cases):
         zo = o.eval_argmax_packed(octs[i], groups[i], lo, hi, 60 + i)
         _same(g, outs[i], zo)
-        alone = g.eval_argmax_packed([gcts[i]], [groups[i]], lo, hi, [60 + i])[0]
+        alone = g.eval_argmax_packed([gcts[i]], [groups[i]], lo, hi, [60 + i], owner=g.owner)[0]
         assert np.array_equal(g.export(alone), g.export(outs[i]))
         for (zb, idx), y, l, h in zip(g.decrypt_packed(outs[i], groups[i]), blocks, lo, hi):
             i0, _, margin = sim.t0_argmax(y)
@@ -341,6 +342,7 @@ def test_argmax_large_n_bit_exact(tiny):
     g, o = Context(p), Oracle.from_params(p)
     steps = g.argmax_steps(2, 256)
     g.keygen(SEED, steps)
+    g.owner = g.key_owner()
     o.keygen(SEED, steps)
     y, zo, zg = _argmax_pair(g, o, 2, 200, q=500)
     _same(g, zg, zo)
@@ -359,11 +361,12 @@ def test_phoenix_bit_exact(name, K, C):
     g, o = Context(p), Oracle.from_params(p)
     steps = g.phoenix_steps(K, C)
     g.keygen(SEED, steps)
+    g.owner = g.key_owner()
     o.keygen(SEED, steps)
     y = W.logits(9, 800 + C, K, C)
     lo, hi = W.d_bounds(K)
     enc, ref = W.query_seeds(9, 800 + C)
-    zg = g.eval_argmax_phoenix(g.encrypt(y, enc), K, C, lo, hi, ref)
+    zg = g.eval_argmax_phoenix(g.encrypt(y, enc), K, C, lo, hi, ref, owner=g.owner)
     zo = o.eval_argmax_phoenix(o.encrypt_logits(y, enc), K, C, lo, hi, ref)
     _same(g, zg, zo)
     cnt = g.counters()
@@ -398,9 +401,9 @@ def test_batch_equals_one_at_a_time(tiny):
         dmin.append(lo)
         dmax.append(hi)
         seeds.append(ref)
-    outs = g.eval_argmax_batch(cts, Ks, Cs, dmin, dmax, seeds)
+    outs = g.eval_argmax_batch(cts, Ks, Cs, dmin, dmax, seeds, owner=g.owner)
     for i in range(len(shapes)):
-        alone = g.eval_argmax(cts[i], Ks[i], Cs[i], dmin[i], dmax[i], seeds[i])
+        alone = g.eval_argmax(cts[i], Ks[i], Cs[i], dmin[i], dmax[i], seeds[i], owner=g.owner)
         assert outs[i].level == alone.level and outs[i].scale == alone.scale
         assert np.array_equal(g.export(outs[i]), g.export(alone))
 
@@ -414,12 +417,12 @@ def test_autotune_keeps_bits(p13):
     args = ([K for K, *_ in qs], [C for _, C, *_ in qs], [W.d_bounds(K)[0] for K, *_ in qs],
             [W.d_bounds(K)[1] for K, *_ in qs], [ref for *_, (_, ref) in qs])
     ws = g.workspace(args[0], args[1])
-    before = [g.export(z) for z in g.eval_argmax_batch(cts, *args, ws=ws)]
+    before = [g.export(z) for z in g.eval_argmax_batch(cts, *args, ws=ws, owner=g.owner)]
     outs = [g.new_ct() for _ in cts]
-    chosen, cands = g.autotune(cts, *args, ws=ws, outs=outs)
+    chosen, cands = g.autotune(cts, *args, ws=ws, outs=outs, owner=g.owner)
     assert 0 <= chosen < len(cands) and all(c["ms"] > 0 for c in cands)
     assert all(np.array_equal(g.export(a), b) for a, b in zip(outs, before))
-    after = [g.export(z) for z in g.eval_argmax_batch(cts, *args, ws=ws)]
+    after = [g.export(z) for z in g.eval_argmax_batch(cts, *args, ws=ws, owner=g.owner)]
     assert all(np.array_equal(a, b) for a, b in zip(after, before))
 
 
@@ -439,14 +442,115 @@ def test_graph_replay_is_deterministic(tiny):
         seeds.append(ref)
     ws = g.workspace(Ks, Cs)
     outs = [g.new_ct() for _ in shapes]
-    eager = [g.export(c) for c in g.eval_argmax_batch(cts, Ks, Cs, dmin, dmax, seeds, ws=ws, outs=outs)]
+    eager = [g.export(c) for c in g.eval_argmax_batch(cts, Ks, Cs, dmin, dmax, seeds, ws=ws, outs=outs, owner=g.owner)]
     for rep in range(3):
-        got = g.eval_argmax_batch(cts, Ks, Cs, dmin, dmax, seeds, ws=ws, outs=outs, graph=True)
+        got = g.eval_argmax_batch(cts, Ks, Cs, dmin, dmax, seeds, ws=ws, outs=outs, graph=True, owner=g.owner)
         g.sync()
         for e, c in zip(eager, got):
             assert np.array_equal(g.export(c), e)
         # eager work between replays
-        g.eval_argmax(cts[0], Ks[0], Cs[0], dmin[0], dmax[0], seeds[0])
+        g.eval_argmax(cts[0], Ks[0], Cs[0], dmin[0], dmax[0], seeds[0], owner=g.owner)
+
+
+def test_without_key_owner_the_evaluation_stops_at_a_refresh(tiny):
+    """Sec. 3.1: the server holds no secret.  An evaluation that needs a
+    refresh and has no key owner (and no bootstrapping) stops with
+    SECPE_ENOLEVEL before queuing work; the server refuses such a request at
+    submission; with the owner the same call runs."""
+    from paper_2502_00847_amd.secpe import SecpeError, Server
+    g, o, _ = tiny
+    K, C = 4, 3
+    y = W.logits(1, 0, K, C)
+    lo, hi = W.d_bounds(K)
+    ct = g.encrypt(y, 5)
+    with pytest.raises(SecpeError, match="error -3"):
+        g.eval_argmax(ct, K, C, lo, hi, 6)
+    with pytest.raises(SecpeError, match="error -3"):
+        g.eval_argmax_batch([ct, ct], [K, K], [C, C], [lo, lo], [hi, hi], [6, 7])
+    with pytest.raises(SecpeError, match="error -3"):
+        g.refresh(ct, 1, 0, owner=None)
+    srv = Server(g, 4 * g.workspace_bytes([K], [C]), max_active=4)
+    with pytest.raises(SecpeError, match="error -3"):
+        srv.submit(ct, K, C, lo, hi, 6)
+    z = g.eval_argmax(ct, K, C, lo, hi, 6, owner=g.owner)
+    assert g.counters()["refresh"] >= 1
+    assert g.decrypt(z, C)[1] == sim.t0_argmax(y)[0]
+
+
+def test_graph_is_recaptured_after_new_keys():
+    """A captured graph bakes in the key pointers: new keys (keygen) or another
+    key owner discard it, so a replay after them equals an eager evaluation
+    with the new keys."""
+    from paper_2502_00847_amd.secpe import Context
+    g = Context(_params("tiny"))
+    g.keygen(SEED, g.argmax_steps(4, 4))
+    owner = g.key_owner()
+    shapes = [(3, 3), (2, 4)]
+    ys = [W.logits(14, i, K, C) for i, (K, C) in enumerate(shapes)]
+    Ks, Cs = [K for K, _ in shapes], [C for _, C in shapes]
+    lo, hi = [W.d_bounds(K)[0] for K in Ks], [W.d_bounds(K)[1] for K in Ks]
+    ws = g.workspace(Ks, Cs)
+    outs = [g.new_ct() for _ in shapes]
+    cts = [g.encrypt(y, 40 + i) for i, y in enumerate(ys)]
+    first = [g.export(c) for c in g.eval_argmax_batch(cts, Ks, Cs, lo, hi, [50, 51], ws=ws, outs=outs, graph=True,
+                                                       owner=owner)]
+    g.sync()
+    old_sk = g.sk
+    g.keygen(SEED + 1, g.argmax_steps(4, 4))      # new secret and switching keys
+    owner2 = g.key_owner()
+    # the same input buffers now hold encryptions under the new secret
+    import torch
+    for i, y in enumerate(ys):
+        new = g.encrypt(y, 40 + i)
+        g.sync()                                  # encryption is asynchronous on the context's stream
+        cts[i].buf.copy_(new.buf)
+    torch.cuda.synchronize()
+    eager = [g.export(c) for c in g.eval_argmax_batch(cts, Ks, Cs, lo, hi, [50, 51], ws=ws, outs=outs,
+                                                       owner=owner2)]
+    for rep in range(2):
+        got = g.eval_argmax_batch(cts, Ks, Cs, lo, hi, [50, 51], ws=ws, outs=outs, graph=True, owner=owner2)
+        g.sync()
+        for e, c in zip(eager, got):
+            assert np.array_equal(g.export(c), e)
+    assert not all(np.array_equal(a, b) for a, b in zip(first, eager))
+    for (K, C), y, c in zip(shapes, ys, got):
+        assert g.decrypt(c, C)[1] == sim.t0_argmax(y)[0]
+    del old_sk
+
+
+def test_keyswitch_traffic_counts_each_key_once_per_launch(tiny):
+    """The algorithmic key-switch bytes of a launch: (l+1) limbs read and
+    2 (l+1) written per key switch, each distinct key's 2 dnum (l+1+alpha)
+    limbs once, however many key switches of the launch share it."""
+    g, o, _ = tiny
+    cts = [g.encrypt(np.zeros((2, 2)), 100 + i) for i in range(4)]
+    nc, alpha = g.n_q, g.n_p
+    nd = -(-nc // alpha)
+    limb = g.N * 8
+    key = 2 * nd * (nc + alpha)
+    g.rotate_batch(cts, [3, 3, 3, 3])
+    assert g.keyswitch_traffic() == (4 * 3 * nc + key) * limb
+    g.rotate_batch(cts, [3, 5, 3, 5])
+    assert g.keyswitch_traffic() == (4 * 3 * nc + 2 * key) * limb
+    g.sync()
+
+
+def test_segment_profile_alternates_computation_and_refresh(tiny):
+    """The segment profiler times an evaluation between refreshes: one
+    interval before the first refresh, then each refresh and the computation
+    after it."""
+    g, o, _ = tiny
+    K, C = 4, 3
+    y = W.logits(1, 3, K, C)
+    lo, hi = W.d_bounds(K)
+    ct = g.encrypt(y, 8)
+    g.profile_begin("segments")
+    g.eval_argmax(ct, K, C, lo, hi, 9, owner=g.owner)
+    prof = g.profile_end()
+    seg = g.profile_segments()
+    n_ref = g.counters()["refresh"]
+    assert n_ref >= 1 and len(seg) == 2 * n_ref + 1
+    assert all(t >= 0 for t in seg) and abs(sum(seg) - prof["ms"]) < 1e-6 * max(1.0, prof["ms"])
 
 
 def test_errors_are_reported(tiny):
@@ -456,9 +560,9 @@ def test_errors_are_reported(tiny):
     with pytest.raises(SecpeError):
         g.rotate(ct, 1000)          # no key for this rotation
     with pytest.raises(SecpeError):
-        g.eval_argmax(ct, 64, 64, -1, 1, 0)   # K' C' exceeds the slots
+        g.eval_argmax(ct, 64, 64, -1, 1, 0, owner=g.owner)   # K' C' exceeds the slots
     with pytest.raises(SecpeError):
-        g.eval_argmax(ct, 2, 2, 1.0, 1.0, 0)  # empty normalisation range
+        g.eval_argmax(ct, 2, 2, 1.0, 1.0, 0, owner=g.owner)  # empty normalisation range
     # slot-packed mode: too many blocks for the slots, bad shapes, bad bounds
     with pytest.raises(SecpeError):
         g.encrypt_packed([np.zeros((4, 8))] * 17, 1)          # 17 blocks of 32 > 512 slots
@@ -466,6 +570,6 @@ def test_errors_are_reported(tiny):
         g.packed_shape([(0, 2)])
     packed = g.encrypt_packed([np.zeros((2, 2))] * 2, 1)
     with pytest.raises(SecpeError):
-        g.eval_argmax_packed([packed], [[(2, 2)] * 200], [-1.0] * 200, [1.0] * 200, [0])
+        g.eval_argmax_packed([packed], [[(2, 2)] * 200], [-1.0] * 200, [1.0] * 200, [0], owner=g.owner)
     with pytest.raises(SecpeError):
-        g.eval_argmax_packed([packed], [[(2, 2), (2, 2)]], [-1.0, 1.0], [1.0, 1.0], [0])
+        g.eval_argmax_packed([packed], [[(2, 2), (2, 2)]], [-1.0, 1.0], [1.0, 1.0], [0], owner=g.owner)

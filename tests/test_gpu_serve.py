@@ -15,6 +15,7 @@ def tiny_ctx():
     from paper_2502_00847_amd.secpe import Context
     g = Context(W.PARAMS["tiny"])
     g.keygen(W.KEYGEN_SEED, g.argmax_steps(32, 20))
+    g.owner = g.key_owner()
     return g
 
 
@@ -31,7 +32,7 @@ def test_staggered_arrivals_match_alone(tiny_ctx):
     from paper_2502_00847_amd.secpe import Server
     g = tiny_ctx
     reqs = [_request(g, i) for i in range(12)]
-    srv = Server(g, 4 * g.workspace_bytes([r["K"] for r in reqs], [r["C"] for r in reqs]), max_active=64)
+    srv = Server(g, 4 * g.workspace_bytes([r["K"] for r in reqs], [r["C"] for r in reqs]), max_active=64, owner=g.owner)
     tickets = {}
     arrivals = {0: [0, 1, 2], 2: [3, 4], 5: [5, 6, 7], 9: [8], 14: [9, 10, 11]}
     step = 0
@@ -47,7 +48,7 @@ def test_staggered_arrivals_match_alone(tiny_ctx):
     assert max_active > 3   # requests overlapped on the device
     for i, r in enumerate(reqs):
         got = srv.results[tickets[i]]
-        alone = g.eval_argmax(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"])
+        alone = g.eval_argmax(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"], owner=g.owner)
         assert (got.level, got.scale) == (alone.level, alone.scale)
         assert np.array_equal(g.export(got), g.export(alone))
         z, idx = g.decrypt(got, r["C"])
@@ -63,7 +64,7 @@ def test_admission_by_memory_queues_requests(tiny_ctx):
     g = tiny_ctx
     reqs = [_request(g, 20 + i) for i in range(6)]
     one = max(g.lib.secpe_server_request_bytes(g.h, r["K"], r["C"]) for r in reqs)
-    srv = Server(g, int(2.2 * one), max_active=64)
+    srv = Server(g, int(2.2 * one), max_active=64, owner=g.owner)
     tickets = [srv.submit(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"]) for r in reqs]
     peak = 0
     saw_pending = False
@@ -76,7 +77,7 @@ def test_admission_by_memory_queues_requests(tiny_ctx):
     assert len(srv.results) == len(reqs)
     assert saw_pending and peak <= 2
     for t, r in zip(tickets, reqs):
-        alone = g.eval_argmax(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"])
+        alone = g.eval_argmax(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"], owner=g.owner)
         assert np.array_equal(g.export(srv.results[t]), g.export(alone))
 
 
@@ -84,7 +85,7 @@ def test_server_rejects_oversized_request(tiny_ctx):
     from paper_2502_00847_amd.secpe import SecpeError, Server
     g = tiny_ctx
     r = _request(g, 44)
-    srv = Server(g, g.ct_bytes() * 2, max_active=4)
+    srv = Server(g, g.ct_bytes() * 2, max_active=4, owner=g.owner)
     with pytest.raises(SecpeError):
         srv.submit(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"])
 
@@ -96,7 +97,7 @@ def test_lone_request_runs_many_rounds_per_step(tiny_ctx):
     from paper_2502_00847_amd.secpe import Server
     g = tiny_ctx
     r = _request(g, 44)
-    srv = Server(g, 2 * g.lib.secpe_server_request_bytes(g.h, r["K"], r["C"]), max_active=8)
+    srv = Server(g, 2 * g.lib.secpe_server_request_bytes(g.h, r["K"], r["C"]), max_active=8, owner=g.owner)
     t = srv.submit(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"])
     steps = 0
     while t not in srv.results:
@@ -104,7 +105,7 @@ def test_lone_request_runs_many_rounds_per_step(tiny_ctx):
         steps += 1
         assert steps < 200
     assert (r["K"], r["C"]) == (16, 16) and steps <= 18
-    alone = g.eval_argmax(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"])
+    alone = g.eval_argmax(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"], owner=g.owner)
     got = srv.results[t]
     assert (got.level, got.scale) == (alone.level, alone.scale)
     assert np.array_equal(g.export(got), g.export(alone))
@@ -119,9 +120,10 @@ def test_tenants_launch_then_collect(tiny_ctx):
     g0 = tiny_ctx
     g1 = Context(W.PARAMS["tiny"])
     g1.keygen(W.KEYGEN_SEED + 1, g1.argmax_steps(32, 20))
+    g1.owner = g1.key_owner()
     gs = [g0, g1]
     reqs = [(i % 2, _request(gs[i % 2], 60 + i)) for i in range(8)]
-    srvs = [Server(h, 4 * h.workspace_bytes([r["K"] for _, r in reqs], [r["C"] for _, r in reqs]), max_active=8)
+    srvs = [Server(h, 4 * h.workspace_bytes([r["K"] for _, r in reqs], [r["C"] for _, r in reqs]), max_active=8, owner=h.owner)
             for h in gs]
     tickets = {}
     for i, (k, r) in enumerate(reqs[:4]):
@@ -149,7 +151,7 @@ def test_tenants_launch_then_collect(tiny_ctx):
         assert step < 500
     for i, (k, r) in enumerate(reqs):
         got = srvs[k].results[tickets[i]]
-        alone = gs[k].eval_argmax(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"])
+        alone = gs[k].eval_argmax(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"], owner=gs[k].owner)
         assert (got.level, got.scale) == (alone.level, alone.scale)
         assert np.array_equal(gs[k].export(got), gs[k].export(alone))
 
@@ -160,7 +162,7 @@ def test_completions_beyond_cap_are_reported_later(tiny_ctx):
     from paper_2502_00847_amd.secpe import Server
     g = tiny_ctx
     r = _request(g, 44)
-    srv = Server(g, 6 * g.lib.secpe_server_request_bytes(g.h, r["K"], r["C"]), max_active=8)
+    srv = Server(g, 6 * g.lib.secpe_server_request_bytes(g.h, r["K"], r["C"]), max_active=8, owner=g.owner)
     tickets = [srv.submit(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"]) for _ in range(4)]
     seen = []
     for _ in range(400):
@@ -183,12 +185,13 @@ def test_shared_keys_servers_on_two_streams(tiny_ctx):
     g0 = tiny_ctx
     g1 = Context(W.PARAMS["tiny"])
     g1.share_keys(g0)
+    g1.owner = g1.key_owner()
     other = Context(W.PARAMS["mini"])
     with pytest.raises(SecpeError):
         other.share_keys(g0)
     gs = [g0, g1]
     reqs = [_request(g0, 80 + i) for i in range(6)]
-    srvs = [Server(h, 4 * h.workspace_bytes([r["K"] for r in reqs], [r["C"] for r in reqs]), max_active=8)
+    srvs = [Server(h, 4 * h.workspace_bytes([r["K"] for r in reqs], [r["C"] for r in reqs]), max_active=8, owner=h.owner)
             for h in gs]
     tickets = [(i % 2, srvs[i % 2].submit(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"]))
                for i, r in enumerate(reqs)]
@@ -201,6 +204,75 @@ def test_shared_keys_servers_on_two_streams(tiny_ctx):
             break
     for (k, t), r in zip(tickets, reqs):
         got = srvs[k].results[t]
-        alone = g0.eval_argmax(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"])
+        alone = g0.eval_argmax(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"], owner=g0.owner)
         assert (got.level, got.scale) == (alone.level, alone.scale)
         assert np.array_equal(g0.export(got), g0.export(alone))
+
+
+# config-5 shapes beyond 16 (K' or C' = 32: five prompt-sum doublings, five
+# QuickMax steps, 1024 slots) on an N = 2^13 set (4096 slots, two-pass NTT)
+P13 = dict(log_n=13, n_q=8, q_bits=36, n_p=2, p_bits=51, log_scale=36, dg=2, df=2, min_level=1)
+SHAPES_32 = [(32, 20), (17, 17), (4, 17), (26, 6), (32, 3)]
+
+
+def _oracle_argmax(args):
+    from oracle.ckks import Oracle
+    steps, K, C, y, enc, lo, hi, ref = args
+    o = Oracle.from_params(P13)
+    o.keygen(W.KEYGEN_SEED, steps)
+    z = o.eval_argmax(o.encrypt_logits(y, enc), K, C, lo, hi, ref)
+    return z.export(), z.level, z.scale, o.counters()
+
+
+def test_config5_shapes_bit_exact_alone_and_served():
+    """Shapes with K' = 32 or C' = 32, as the serving mix draws them: each
+    evaluated alone is bit-exact with the oracle (which runs in parallel
+    threads meanwhile), and the same requests through the server with
+    staggered arrivals give the same bits; indices match the plaintext
+    argmax at the stated margin."""
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_2502_00847_amd.secpe import Context, Server
+    g = Context(P13)
+    steps = g.argmax_steps(32, 20)
+    g.keygen(W.KEYGEN_SEED, steps)
+    owner = g.key_owner()
+    reqs = []
+    for i, (K, C) in enumerate(SHAPES_32):
+        y = W.logits(5, 5000 + i, K, C)
+        enc, ref = W.query_seeds(5, 5000 + i)
+        lo, hi = W.d_bounds(K)
+        reqs.append(dict(ct=g.encrypt(y, enc), K=K, C=C, d_min=lo, d_max=hi, seed=ref, y=y, enc=enc))
+    with ThreadPoolExecutor(len(reqs)) as ex:
+        futs = [ex.submit(_oracle_argmax, (steps, r["K"], r["C"], r["y"], r["enc"], r["d_min"], r["d_max"], r["seed"]))
+                for r in reqs]
+        alone = []
+        for r in reqs:
+            print(f"[cfg5] alone K={r['K']} C={r['C']}", flush=True)
+            alone.append(g.eval_argmax(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"], owner=owner))
+        srv = Server(g, 3 * g.workspace_bytes([r["K"] for r in reqs], [r["C"] for r in reqs]), max_active=8,
+                     owner=owner)
+        arrivals = {0: [0, 1], 3: [2], 6: [3, 4]}
+        tickets, step = {}, 0
+        while len(srv.results) < len(reqs):
+            for i in arrivals.get(step, []):
+                r = reqs[i]
+                tickets[i] = srv.submit(r["ct"], r["K"], r["C"], r["d_min"], r["d_max"], r["seed"])
+            srv.step()
+            step += 1
+            assert step < 400
+        oracle = [f.result() for f in futs]
+    for i, r in enumerate(reqs):
+        arr, level, scale, cnt = oracle[i]
+        a = alone[i]
+        assert (a.level, a.scale) == (level, scale)
+        assert np.array_equal(g.export(a), arr), (r["K"], r["C"])
+        got = srv.results[tickets[i]]
+        assert np.array_equal(g.export(got), arr)
+        lk, lc = (r["K"] - 1).bit_length(), (r["C"] - 1).bit_length()
+        assert cnt["rotate"] == lk + 1 + lc and cnt["max"] == lc
+        z, idx = g.decrypt(a, r["C"])
+        i0, _, margin = sim.t0_argmax(r["y"])
+        print(f"[cfg5] K={r['K']} C={r['C']} idx={idx} t0={i0} margin={margin / (r['d_max'] - r['d_min']):.2e}",
+              flush=True)
+        if margin / (r["d_max"] - r["d_min"]) >= 2.0**-10:
+            assert idx == i0
