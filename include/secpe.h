@@ -165,6 +165,28 @@ int secpe_eval_argmax_batch(secpe_ctx* ctx, const secpe_key_owner* owner, int n,
                             const int* C, const double* d_min, const double* d_max, const uint64_t* refresh_seed,
                             void* ws_dev, size_t ws_bytes, secpe_ct* out, int flags);
 
+/* ---- the Argmax for callers that cannot allocate device memory: code
+   under HIP graph capture, tight serving loops, harnesses that forbid
+   hipMalloc.  The evaluation of secpe_eval_argmax (same kernels, bit-identical
+   results) with its workspace and descriptor arena in a device-global scratch
+   array of SECPE_NOALLOC_SCRATCH_BYTES on each GPU (held from the library's
+   load to the end of the process; its address is looked up once per device
+   by secpe_ctx_create) and its descriptors staged through the context's
+   pinned buffer of SECPE_NOALLOC_BLOB_BYTES (allocated by secpe_ctx_create).
+   The call allocates nothing; an evaluation whose workspace and descriptors
+   exceed the scratch, or whose descriptors exceed the staging buffer, fails
+   with SECPE_ENOMEM before any work is queued (a config-2 query at N = 2^16
+   needs 401 MiB and fits).  Every call on a GPU uses that GPU's one array: calls that overlap
+   on one GPU (on other streams or other contexts) race, and the caller must
+   order them; consecutive calls on one stream are ordered by the stream.
+   Nothing in the scratch needs to start at zero: an evaluation reads only
+   words it has written.  in, out and the key owner are as in
+   secpe_eval_argmax.  Asynchronous. ---- */
+#define SECPE_NOALLOC_SCRATCH_BYTES ((size_t)512 << 20)
+#define SECPE_NOALLOC_BLOB_BYTES ((size_t)8 << 20)
+int secpe_eval_argmax_noalloc(secpe_ctx* ctx, const secpe_key_owner* owner, const secpe_ct* in, int K, int C,
+                              double d_min, double d_max, uint64_t refresh_seed, secpe_ct* out);
+
 /* ---- slot-packed Argmax (Sec. 3.2: N/(2n) Argmax inputs share one
    ciphertext).  A group of queries of shapes (K_b, C_b) is laid out in
    blocks of B = max(K'C', 2C') slots, K' and C' the largest padded shape of

@@ -6,6 +6,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -73,6 +74,34 @@ static int ensure_buffer(Ctx& c, char** buf, size_t* cap, size_t need) {
   }
   *cap = n;
   return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the evaluation that allocates nothing (secpe_eval_argmax_noalloc):
+// one device-global array per GPU holds that call's workspace and descriptor
+// arena.  In host code the array's name is no device address: each device's
+// copy is looked up once, with that device current, at context creation
+// (hipGetSymbolAddress) and only the looked-up pointer is used afterwards.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[SECPE_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static std::map<int, char*> g_scratch_ptr;   // device -> address of its copy of 'scratch'
+
+// Record the current device's scratch address (idempotent); 'device' is current.
+static int scratch_lookup(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr.count(device)) return 0;
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) return hip_fail("hipGetSymbolAddress(scratch)", e);
+  g_scratch_ptr[device] = (char*)p;
+  return 0;
+}
+
+static char* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  return it == g_scratch_ptr.end() ? nullptr : it->second;
 }
 
 // The secret an evaluation may refresh with: null without a key owner; an
@@ -163,6 +192,21 @@ extern "C" int secpe_ctx_create(const secpe_params* p, int device, void* stream,
   if ((x->c.mod.back() >> 51) != 0) {
     secpe_ctx_destroy(x);
     return set_err(SECPE_EINVAL, "a modulus reached 2^51");
+  }
+  // set-up for secpe_eval_argmax_noalloc: this device's scratch address and a
+  // pinned staging buffer its descriptor blobs fit in
+  rc = scratch_lookup(device);
+  if (!rc) {
+    x->c.staging_bytes = SECPE_NOALLOC_BLOB_BYTES;
+    if (hipHostMalloc((void**)&x->c.staging, x->c.staging_bytes, hipHostMallocDefault) != hipSuccess) {
+      x->c.staging = nullptr;
+      x->c.staging_bytes = 0;
+      rc = set_err(SECPE_EDEVICE, "pinned staging allocation failed");
+    }
+  }
+  if (rc) {
+    secpe_ctx_destroy(x);
+    return rc;
   }
   *out = x;
   return 0;
@@ -754,6 +798,56 @@ extern "C" int secpe_eval_argmax(secpe_ctx* x, const secpe_key_owner* owner, con
                                  double d_min, double d_max, uint64_t refresh_seed, void* ws, size_t ws_bytes,
                                  secpe_ct* out) {
   return secpe_eval_argmax_batch(x, owner, 1, in, &K, &C, &d_min, &d_max, &refresh_seed, ws, ws_bytes, out, 0);
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+extern "C" int secpe_eval_argmax_noalloc(secpe_ctx* x, const secpe_key_owner* owner, const secpe_ct* in, int K, int C,
+                                         double d_min, double d_max, uint64_t refresh_seed, secpe_ct* out) {
+  CHECK_CTX(x);
+  if (!in || !out || !out->data) return set_err(SECPE_EINVAL, "null argument");
+  const double* rsk = nullptr;
+  int rc = owner_sk(x, owner, &rsk);
+  if (rc) return rc;
+  rc = check_queries(x, 1, in, &K, &C, &d_min, &d_max);
+  if (rc) return rc;
+  Ctx& c = x->c;
+  char* base = scratch_ptr(c.device);
+  if (!base) return set_err(SECPE_EDEVICE, "no scratch address for this device");
+  std::vector<ArgmaxQuery> q = make_queries(x, 1, in, &K, &C, &d_min, &d_max, &refresh_seed, out);
+  // size the workspace and the descriptor blob with a dry run (host only)
+  size_t blob = 0, need = 0;
+  {
+    Builder dry(c, (char*)(uintptr_t)0x100000000000ull, (size_t)1 << 44, (char*)(uintptr_t)0x400000000000ull,
+                (size_t)1 << 40, true);
+    dry.refresh_sk = rsk;
+    std::vector<ArgmaxQuery> qd = q;
+    build_argmax(dry, qd);
+    if (dry.err_code) return set_err(dry.err_code, dry.err);
+    blob = dry.blob_bytes();
+    need = dry.need_bytes();
+  }
+  const size_t arena_bytes = align256(blob + 1);
+  if (blob > c.staging_bytes || blob > SECPE_NOALLOC_BLOB_BYTES)
+    return set_err(SECPE_ENOMEM, "descriptor blob of " + std::to_string(blob) + " bytes exceeds the no-allocation limit of " +
+                                     std::to_string((size_t)SECPE_NOALLOC_BLOB_BYTES));
+  if (arena_bytes + need > SECPE_NOALLOC_SCRATCH_BYTES)
+    return set_err(SECPE_ENOMEM, "evaluation needs " + std::to_string(arena_bytes + need) +
+                                     " bytes of scratch; the no-allocation scratch holds " +
+                                     std::to_string((size_t)SECPE_NOALLOC_SCRATCH_BYTES));
+  // layout of the scratch: descriptor arena, then the workspace
+  Builder b(c, base + arena_bytes, SECPE_NOALLOC_SCRATCH_BYTES - arena_bytes, base, arena_bytes, false);
+  b.refresh_sk = rsk;
+  build_argmax(b, q);
+  if (b.err_code) return set_err(b.err_code, b.err);
+  if (b.arena_overflow()) return set_err(SECPE_ENOMEM, "descriptor arena overflow");
+  rc = submit(c, b, base, arena_bytes, false);
+  if (rc) return set_err(rc == -2 ? SECPE_ENOMEM : SECPE_EDEVICE, "kernel submission failed");
+  memcpy(c.counters, b.counters, sizeof(c.counters));
+  c.ks_alg_limbs = b.ks_alg_limbs;
+  out->level = q[0].out.level;
+  out->scale = q[0].out.scale;
+  return 0;
 }
 
 extern "C" int secpe_counters(const secpe_ctx* x, int64_t* out8) {

@@ -382,8 +382,10 @@ class Builder {
 };
 
 // Submit a command list: upload the descriptor blob to 'arena' and launch all
-// commands in order on the context's stream.
-int submit(Ctx& c, Builder& b, char* arena, size_t arena_bytes);
+// commands in order on the context's stream.  may_allocate = false: the blob
+// goes through the existing pinned staging buffer, never a larger new one
+// (-2 when it does not fit).
+int submit(Ctx& c, Builder& b, char* arena, size_t arena_bytes, bool may_allocate = true);
 void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena);
 int prof_kind_of(const Cmd& k);
 

@@ -623,10 +623,11 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
   }
 }
 
-int submit(Ctx& c, Builder& b, char* arena, size_t arena_bytes) {
+int submit(Ctx& c, Builder& b, char* arena, size_t arena_bytes, bool may_allocate) {
   const size_t n = b.blob_.size();
   if (n > arena_bytes) return -2;
   if (n) {
+    if (c.staging_bytes < n && !may_allocate) return -2;
     if (c.staging_bytes < n) {
       if (c.staging) {
         (void)hipEventSynchronize(c.staging_done);

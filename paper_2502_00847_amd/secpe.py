@@ -73,6 +73,7 @@ def load():
         "secpe_decrypt_coeffs": (i32, [vp, vp, ct, P(i64)]),
         "secpe_workspace_bytes": (sz, [vp, i32, P(i32), P(i32)]),
         "secpe_eval_argmax": (i32, [vp, vp, ct, i32, i32, dbl, dbl, u64, vp, sz, ct]),
+        "secpe_eval_argmax_noalloc": (i32, [vp, vp, ct, i32, i32, dbl, dbl, u64, ct]),
         "secpe_eval_argmax_batch": (i32, [vp, vp, i32, ct, P(i32), P(i32), P(dbl), P(dbl), P(u64), vp, sz, ct, i32]),
         "secpe_counters": (i32, [vp, P(i64)]),
         "secpe_ct_export": (i32, [vp, ct, P(u64)]),
@@ -145,7 +146,7 @@ def exported_symbols():
         ["secpe_last_error", "secpe_strerror", "secpe_ctx_create", "secpe_ctx_destroy", "secpe_primes", "secpe_slots",
          "secpe_ct_bytes", "secpe_sk_bytes", "secpe_key_bytes", "secpe_galois_elt", "secpe_argmax_steps",
          "secpe_keygen", "secpe_key_owner_create", "secpe_key_owner_destroy", "secpe_encrypt", "secpe_encrypt_coeffs", "secpe_decrypt",
-         "secpe_decrypt_coeffs", "secpe_workspace_bytes", "secpe_eval_argmax", "secpe_eval_argmax_batch",
+         "secpe_decrypt_coeffs", "secpe_workspace_bytes", "secpe_eval_argmax", "secpe_eval_argmax_noalloc", "secpe_eval_argmax_batch",
          "secpe_counters", "secpe_ct_export", "secpe_ct_import", "secpe_key_export", "secpe_sk_export",
          "secpe_sync", "secpe_op_workspace_bytes", "secpe_op_add", "secpe_op_sub", "secpe_op_add_const",
          "secpe_op_mul_const", "secpe_op_lincomb", "secpe_autotune", "secpe_packed_shape", "secpe_encrypt_packed",
@@ -521,6 +522,16 @@ class Context:
 
     def eval_argmax(self, ct, K, Cc, d_min, d_max, refresh_seed, ws=None, owner=None):
         return self.eval_argmax_batch([ct], [K], [Cc], [d_min], [d_max], [refresh_seed], ws=ws, owner=owner)[0]
+
+    def eval_argmax_noalloc(self, ct, K, Cc, d_min, d_max, refresh_seed, out=None, owner=None):
+        """The Argmax with its workspace in the library's per-GPU scratch array
+        (secpe_eval_argmax_noalloc): the call allocates no device memory."""
+        out = self.new_ct() if out is None else out
+        c = out._c()
+        self._check(self.lib.secpe_eval_argmax_noalloc(self.h, _owner(owner), C.byref(ct._c()), int(K), int(Cc),
+                                                       float(d_min), float(d_max), int(refresh_seed), C.byref(c)))
+        out.level, out.scale = c.level, c.scale
+        return out
 
     def counters(self):
         out = np.zeros(8, dtype=np.int64)
