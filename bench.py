@@ -604,6 +604,8 @@ def main():
     ap.add_argument("--calib", type=int, default=0, help="copy 1 GiB first (counter calibration kernel)")
     ap.add_argument("--variants", type=int, default=1, help="precise-Sign and large-n single-query runs")
     ap.add_argument("--ntt-only", type=int, default=0, help="only the NTT microbenchmark (64 x 2 x 24 limbs)")
+    ap.add_argument("--keyswitch-only", type=int, default=0,
+                    help="only the rotation microbenchmark (64 random-step rotations, 64 keys, 24 limbs)")
     ap.add_argument("--boot-only", type=int, default=0,
                     help="only the bootstrapping run (its timed batch between marker fills of 28672 and 36864 doubles)")
     args = ap.parse_args()
@@ -618,6 +620,11 @@ def main():
 
     if args.boot_only:
         print(json.dumps({"bootstrapping": bootstrap_rate()}), flush=True)
+        return
+    if args.keyswitch_only:
+        g = Context(W.PARAMS["full"])
+        g.keygen(W.KEYGEN_SEED, [])
+        print(json.dumps({"keyswitch": keyswitch_rate(g, W.PARAMS["full"])}), flush=True)
         return
     if args.ntt_only:
         g = Context(W.PARAMS["full"])
@@ -726,6 +733,15 @@ def main():
         single.append((time.perf_counter() - ts) * 1e3)
     single = np.array(single[1:])
     zz, idx2 = g.decrypt(z2, d2["C"])
+    # the same query once more under the segment profiler: the computation
+    # between refreshes and each refresh, in order
+    g.profile_begin("segments")
+    g.eval_argmax(ct2, d2["K"], d2["C"], d2["d_min"], d2["d_max"], d2["refresh_seed"], ws=ws2, owner=g.owner)
+    g.profile_end()
+    seg2 = g.profile_segments()
+    onehot = np.zeros(d2["C"])
+    onehot[idx2] = 1.0
+    margin2 = plain_argmax(d2["logits"])[2]
 
     N = 1 << params["log_n"]
     unit_bytes = N * 8
@@ -791,7 +807,15 @@ def main():
                        "what": "completion time of each query from the start of a step"},
         "single_query_ms": {"p50": round(float(np.percentile(single, 50)), 3),
                             "p99": round(float(np.percentile(single, 99)), 3),
-                            "what": "config K=8, C=4 alone on the plain path", "index_ok": bool(idx2 == plain_argmax(d2["logits"])[0])},
+                            "what": "config K=8, C=4 alone on the plain path", "index_ok": bool(idx2 == plain_argmax(d2["logits"])[0]),
+                            "segments_ms": [round(t, 3) for t in seg2[0::2]],
+                            "refresh_ms": [round(t, 3) for t in seg2[1::2]],
+                            "segments_what": "computation between refreshes, then each refresh (key-owner stand-in), "
+                                             "in order, event-timed in one evaluation",
+                            "top2_margin": round(margin2, 4),
+                            "top2_margin_normalised": round(margin2 / (d2["d_max"] - d2["d_min"]), 6),
+                            "z": [round(float(v), 9) for v in zz],
+                            "z_minus_onehot_linf": float(np.abs(zz - onehot).max())},
         "index_ok": f"{ok}/{B}",
         "index_ok_at_margin_2^-10": f"{ok_margin}/{n_margin}",
         "roofline": roofline,
