@@ -271,14 +271,28 @@ int secpe_bootstrap(secpe_ctx* ctx, int n, const secpe_ct* in, void* ws_dev, siz
    ws sized by secpe_bootstrap_workspace_bytes(ctx, 1). */
 int secpe_op_boot_step(secpe_ctx* ctx, int step, const secpe_ct* a, void* ws_dev, size_t ws_bytes, secpe_ct* out);
 
-/* Autotuner for the batched path.  Evaluates the batch given (same arguments
-   as secpe_eval_argmax_batch, no graph) under each candidate schedule and
-   keeps the fastest in the context for later calls:
-     candidate i: output limbs per workgroup of the fused ModUp = (i & 1) ? 2 : 4,
-                  NTT passes issued in job groups of (i & 2) ? 128 MiB : all jobs.
-   Writes the chosen candidate to *chosen and, for i < cap, the measured
-   milliseconds of candidate i to ms[i].  Synchronous.  Returns 0 or an error. */
-#define SECPE_AUTOTUNE_CANDIDATES 4
+/* Autotuner for the batched path.  Times the batch given (same arguments
+   as secpe_eval_argmax_batch, no graph) under candidate schedules and keeps
+   the fastest in the context for later calls.  A candidate index is a set of
+   knob bits:
+     bit 0: output limbs per workgroup of the fused ModUp, 2 (set) or 4;
+     bit 1: NTT passes issued in job groups of 128 MiB (set) or all jobs at once;
+     bit 2: forward NTT column pass, two tiles per workgroup (set: the second
+            tile's loads in flight while the first transforms) or one;
+     bit 3: inverse NTT column pass, two tiles per workgroup (set) or one;
+     bit 4: forward NTT row pass (with its fused epilogues), two tiles per
+            workgroup (set) or one.
+   (The two-tile variants exist for N = 2^16; elsewhere bits 2-4 change nothing.)
+   Search: candidate 0, then each knob flipped in turn from the best so far
+   and kept when the batch is faster (coordinate descent; 1 + 5 candidates
+   timed, each the faster of two runs).  Writes the chosen candidate to
+   *chosen and, for i < cap, the milliseconds of candidate i to ms[i] (0 for
+   candidates not timed).  Synchronous.  Returns 0 or an error. */
+#define SECPE_AUTOTUNE_KNOBS 5
+/* Set a schedule (candidate index as above) without timing, e.g. one a
+   previous secpe_autotune chose.  Every schedule gives the same bits. */
+int secpe_set_schedule(secpe_ctx* ctx, int candidate);
+#define SECPE_AUTOTUNE_CANDIDATES 32
 int secpe_autotune(secpe_ctx* ctx, const secpe_key_owner* owner, int n, const secpe_ct* in, const int* K,
                    const int* C, const double* d_min, const double* d_max, const uint64_t* refresh_seed,
                    void* ws_dev, size_t ws_bytes, secpe_ct* out, int* chosen, double* ms, int cap);

@@ -1314,6 +1314,15 @@ extern "C" int secpe_profile_segments(const secpe_ctx* x, double* ms, int cap) {
 static void set_candidate(Ctx& c, int i) {
   c.modup_eg = (i & 1) ? 2 : 4;
   c.ntt_chunk_bytes = (i & 2) ? ((size_t)128 << 20) : 0;
+  c.ntt_tiles = (i >> 2) & 7;
+}
+
+extern "C" int secpe_set_schedule(secpe_ctx* x, int candidate) {
+  CHECK_CTX(x);
+  if (candidate < 0 || candidate >= SECPE_AUTOTUNE_CANDIDATES) return set_err(SECPE_EINVAL, "no such schedule");
+  drop_graphs(x->c);
+  set_candidate(x->c, candidate);
+  return 0;
 }
 
 extern "C" int secpe_autotune(secpe_ctx* x, const secpe_key_owner* owner, int n, const secpe_ct* in, const int* K,
@@ -1329,22 +1338,34 @@ extern "C" int secpe_autotune(secpe_ctx* x, const secpe_key_owner* owner, int n,
     if (e0) (void)hipEventDestroy(e0);
     return set_err(SECPE_EDEVICE, "hipEventCreate failed");
   }
-  int best = -1;
-  float best_ms = 0.0f;
+  for (int i = 0; ms && i < cap; ++i) ms[i] = 0.0;
   int rc = 0;
-  for (int i = 0; i < SECPE_AUTOTUNE_CANDIDATES && !rc; ++i) {
+  // the faster of two evaluations of the batch under candidate i
+  auto time_candidate = [&](int i, float* out_ms) {
     set_candidate(c, i);
-    float t = 0.0f;
+    float best = 0.0f;
     for (int rep = 0; rep < 2 && !rc; ++rep) {
+      float t = 0.0f;
       (void)hipEventRecord(e0, c.stream);
       rc = secpe_eval_argmax_batch(x, owner, n, in, K, C, dmin, dmax, rs, ws, ws_bytes, out, 0);
       (void)hipEventRecord(e1, c.stream);
       if (!rc && hipEventSynchronize(e1) == hipSuccess) (void)hipEventElapsedTime(&t, e0, e1);
+      if (rep == 0 || t < best) best = t;
     }
-    if (rc) break;
-    if (ms && i < cap) ms[i] = t;
-    if (best < 0 || t < best_ms) {
-      best = i;
+    *out_ms = best;
+    if (!rc && ms && i < cap) ms[i] = best;
+  };
+  // coordinate search: from the default schedule, each knob (one bit of the
+  // candidate index) is flipped in turn and kept when the batch gets faster
+  int best = 0;
+  float best_ms = 0.0f;
+  time_candidate(0, &best_ms);
+  for (int bit = 0; bit < SECPE_AUTOTUNE_KNOBS && !rc; ++bit) {
+    const int cand = best ^ (1 << bit);
+    float t = 0.0f;
+    time_candidate(cand, &t);
+    if (!rc && t < best_ms) {
+      best = cand;
       best_ms = t;
     }
   }

@@ -11,9 +11,13 @@ namespace secpe {
 // max_limbs bounds the limb count of any job in the launch (grid y).
 // The NTT runs as ntt_pass_count() launches (1 for N <= 2^12, else 2).
 int ntt_pass_count(const DevTables& T);
+// tiles_sched: passes run with two tiles per workgroup (where a variant
+// exists, N = 2^16): bit 0 forward column pass, bit 1 inverse column pass,
+// bit 2 forward row pass.
 void launch_ntt_pass(const DevTables& T, bool inverse, const NttJob* jobs, int n_jobs, int max_limbs, int pass,
-                     hipStream_t s);
-void launch_ntt(const DevTables& T, bool inverse, const NttJob* jobs, int n_jobs, int max_limbs, hipStream_t s);
+                     hipStream_t s, int tiles_sched = 0);
+void launch_ntt(const DevTables& T, bool inverse, const NttJob* jobs, int n_jobs, int max_limbs, hipStream_t s,
+                int tiles_sched = 0);
 // For N > 2^12 the key-switch inner product runs fused with the row pass of
 // the ModUp outputs' forward NTT (whose column pass ran as an ordinary launch).
 bool inner_row_fused(const DevTables& T);

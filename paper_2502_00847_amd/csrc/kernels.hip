@@ -506,9 +506,12 @@ __device__ __forceinline__ void inv_row_from_lds(double* lds, gdbl* dst, int row
 // tile allows (the compiler cannot see the dynamic LDS size and would
 // otherwise keep registers low for 8 and not hoist the twiddle loads); the
 // column passes measure best at the compiler's default.
-template <int LOGS, int G, int MODE, bool INV>
+// P (column passes): tiles per workgroup; the loads of all P tiles are
+// issued before the first is transformed, so that the later tiles' loads are
+// in flight while the earlier ones compute.
+template <int LOGS, int G, int MODE, bool INV, int P>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(MODE == NTT_ROW ? 4 : 1, MODE == NTT_ROW ? 4 : 8))) void k_ntt2(const NttJob* __restrict__ jobs, DevTables T, int second) {
+__attribute__((amdgpu_waves_per_eu(MODE == NTT_ROW ? (P == 1 ? 4 : 2) : 1, MODE == NTT_ROW ? 4 : 8))) void k_ntt2(const NttJob* __restrict__ jobs, DevTables T, int second) {
   extern __shared__ double lds[];
   constexpr int S = 1 << LOGS;
   constexpr int RB = LOGS - 4;         // bits of round B
@@ -545,6 +548,7 @@ __attribute__((amdgpu_waves_per_eu(MODE == NTT_ROW ? 4 : 1, MODE == NTT_ROW ? 4 
   // vectors), the row pass one per 16 elements (lanes run within a vector)
   auto lidx = [&](int vec, int v) -> int { return MODE == NTT_COL ? vec * (S + 1) + v : lpad(vec * S + v); };
   if (!INV && MODE == NTT_COL) {
+    if constexpr (P == 1) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) x[e] = src[gaddr(va, e * NB + la)];
     if (spread) {
@@ -552,7 +556,26 @@ __attribute__((amdgpu_waves_per_eu(MODE == NTT_ROW ? 4 : 1, MODE == NTT_ROW ? 4 
       for (int e = 0; e < 16; ++e) x[e] = spread_in(x[e], q_src, m);
     }
     fwd_col_from_regs<LOGS, G>(x, lds, dst, c0, k1, tw, twq, m);
+    } else {
+    double xs[P][16];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int cp = (blockIdx.x * P + p) * G;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) xs[p][e] = src[(size_t)(e * NB + la) * C + cp + va];
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      if (spread) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) xs[p][e] = spread_in(xs[p][e], q_src, m);
+      }
+      if (p) __syncthreads();   // the tile in LDS is read by every thread before it is reused
+      fwd_col_from_regs<LOGS, G>(xs[p], lds, dst, (blockIdx.x * P + p) * G, k1, tw, twq, m);
+    }
+    }
   } else if (!INV) {
+    if constexpr (P == 1) {
     // ---- round A straight from global memory
 #pragma unroll
     for (int e = 0; e < 16; ++e) x[e] = src[gaddr(va, e * NB + la)];
@@ -595,6 +618,53 @@ __attribute__((amdgpu_waves_per_eu(MODE == NTT_ROW ? 4 : 1, MODE == NTT_ROW ? 4 
         }
       }
     }
+    } else {
+    // (the forward row pass; P tiles of rows, every tile's loads issued first)
+    double xs[P][16];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int r0 = (blockIdx.x * P + p) * G;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) xs[p][e] = src[(size_t)(r0 + va) * S + e * NB + la];
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int r0 = (blockIdx.x * P + p) * G;
+      // ---- round A on the loaded elements
+      ntt_round<LOGS, 4, MODE, false>(xs[p], 0, RB, r0 + va, k1, tw, twq, m);
+      // the previous tile's LDS reads are done (at S = 256 every exchange stays inside a wave)
+      if (p) tile_sync<S>();
+#pragma unroll
+      for (int e = 0; e < 16; ++e) lds[lidx(va, e * NB + la)] = xs[p][e];
+      tile_sync<S>();
+      // ---- round B
+#pragma unroll
+      for (int gi = 0; gi < GB; ++gi) {
+        const int grp = t + gi * 256;
+        const int vb = grp / 16, hb = grp % 16;
+        double y[NB];
+#pragma unroll
+        for (int e = 0; e < NB; ++e) y[e] = lds[lidx(vb, hb * NB + e)];
+        ntt_round<LOGS, RB, MODE, false>(y, hb, 0, r0 + vb, k1, tw, twq, m);
+#pragma unroll
+        for (int e = 0; e < NB; ++e) lds[lidx(vb, hb * NB + e)] = y[e];
+      }
+      tile_sync<S>();
+      if (J.epi != EPI_NONE) {
+        row_epilogue<G * S / 2 / 256, S>(J, l, (size_t)l * N + (size_t)r0 * S, lds, m);
+      } else {
+        gdbl2* d2 = (gdbl2*)(dst + (size_t)r0 * S);
+#pragma unroll
+        for (int q = 0; q < G * S / 2 / 256; ++q) {
+          const int i = tile_pair<S>(q);
+          dv2 v;
+          v.x = canon(lds[lpad(2 * i)], m);
+          v.y = canon(lds[lpad(2 * i + 1)], m);
+          d2[i] = v;
+        }
+      }
+    }
+    }
   } else {
     // ---- round B first (low bits), loaded straight (column) or via LDS (row)
     if (MODE == NTT_ROW) {
@@ -621,6 +691,7 @@ __attribute__((amdgpu_waves_per_eu(MODE == NTT_ROW ? 4 : 1, MODE == NTT_ROW ? 4 
       inv_row_from_lds<LOGS, G>(lds, dst, row0, k1, tw, twq, m);
       return;
     }
+    if constexpr (P == 1) {
 #pragma unroll
     for (int gi = 0; gi < GB; ++gi) {
       const int grp = t + gi * 256;
@@ -647,6 +718,48 @@ __attribute__((amdgpu_waves_per_eu(MODE == NTT_ROW ? 4 : 1, MODE == NTT_ROW ? 4 
       double v = x[e];
       if (scale) v = J.ek ? mul_mod(red(v, m), ys, m) : mul_w(red(v, m), ni, niq, m.p);
       dst[gaddr(va, e * NB + la)] = canon(v, m);
+    }
+    } else {
+    // (the inverse column pass: every tile's loads are issued first)
+    double ys[P][GB][NB];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int cp = (blockIdx.x * P + p) * G;
+#pragma unroll
+      for (int gi = 0; gi < GB; ++gi) {
+        const int grp = t + gi * 256;
+        const int vb = grp % G, hb = grp / G;
+#pragma unroll
+        for (int e = 0; e < NB; ++e) ys[p][gi][e] = src[(size_t)(hb * NB + e) * C + cp + vb];
+      }
+    }
+    // J.ek set: the last pass multiplies by ek[l] (which includes N^-1) instead of N^-1
+    const double yk = (scale && J.ek) ? KPTR(J.ek)[l] : 0.0;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int cp = (blockIdx.x * P + p) * G;
+      if (p) __syncthreads();   // the previous tile's LDS reads are done
+#pragma unroll
+      for (int gi = 0; gi < GB; ++gi) {
+        const int grp = t + gi * 256;
+        const int vb = grp % G, hb = grp / G;
+        ntt_round<LOGS, RB, MODE, true>(ys[p][gi], hb, 0, row0 + vb, k1, tw, twq, m);
+        // each group is read and written back by its own thread: no barrier needed here
+#pragma unroll
+        for (int e = 0; e < NB; ++e) lds[lidx(vb, hb * NB + e)] = ys[p][gi][e];
+      }
+      __syncthreads();
+      // ---- round A, stored straight to global memory
+#pragma unroll
+      for (int e = 0; e < 16; ++e) x[e] = lds[lidx(va, e * NB + la)];
+      ntt_round<LOGS, 4, MODE, true>(x, 0, RB, row0 + va, k1, tw, twq, m);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        double v = x[e];
+        if (scale) v = J.ek ? mul_mod(red(v, m), yk, m) : mul_w(red(v, m), ni, niq, m.p);
+        dst[(size_t)(e * NB + la) * C + cp + va] = canon(v, m);
+      }
+    }
     }
   }
 }
@@ -908,16 +1021,18 @@ size_t ntt_lds_bytes(int logs, int g) {
 NTT_INST(10, 1, NTT_SINGLE)
 NTT_INST(11, 1, NTT_SINGLE)
 NTT_INST(12, 1, NTT_SINGLE)
-#define NTT2_INST(LOGS, G, MODE)                                                                  \
-  template __global__ void k_ntt2<LOGS, G, MODE, false>(const NttJob* __restrict__, DevTables, int); \
-  template __global__ void k_ntt2<LOGS, G, MODE, true>(const NttJob* __restrict__, DevTables, int);
-NTT2_INST(6, 64, NTT_COL)
-NTT2_INST(7, 32, NTT_COL)
-NTT2_INST(8, 16, NTT_COL)
-NTT2_INST(7, 32, NTT_ROW)
-NTT2_INST(8, 16, NTT_ROW)
+#define NTT2_INST(LOGS, G, MODE, P)                                                                  \
+  template __global__ void k_ntt2<LOGS, G, MODE, false, P>(const NttJob* __restrict__, DevTables, int); \
+  template __global__ void k_ntt2<LOGS, G, MODE, true, P>(const NttJob* __restrict__, DevTables, int);
+NTT2_INST(6, 64, NTT_COL, 1)
+NTT2_INST(7, 32, NTT_COL, 1)
+NTT2_INST(8, 16, NTT_COL, 1)
+NTT2_INST(8, 16, NTT_COL, 2)
+NTT2_INST(7, 32, NTT_ROW, 1)
+NTT2_INST(8, 16, NTT_ROW, 1)
+NTT2_INST(8, 16, NTT_ROW, 2)
 
-void* ntt_kernel(int logs, int mode, bool inv, int* g_out) {
+void* ntt_kernel(int logs, int mode, bool inv, int* g_out, int col_tiles) {
 #define PICK(LOGS, G, MODE)                                                                       \
   if (logs == LOGS && mode == MODE) {                                                             \
     *g_out = G;                                                                                   \
@@ -927,16 +1042,19 @@ void* ntt_kernel(int logs, int mode, bool inv, int* g_out) {
   PICK(11, 1, NTT_SINGLE)
   PICK(12, 1, NTT_SINGLE)
 #undef PICK
-#define PICK2(LOGS, G, MODE)                                                                      \
-  if (logs == LOGS && mode == MODE) {                                                             \
+#define PICK2(LOGS, G, MODE, P)                                                                   \
+  if (logs == LOGS && mode == MODE && col_tiles == P) {                                           \
     *g_out = G;                                                                                   \
-    return inv ? (void*)&k_ntt2<LOGS, G, MODE, true> : (void*)&k_ntt2<LOGS, G, MODE, false>;      \
+    return inv ? (void*)&k_ntt2<LOGS, G, MODE, true, P> : (void*)&k_ntt2<LOGS, G, MODE, false, P>; \
   }
-  PICK2(6, 64, NTT_COL)
-  PICK2(7, 32, NTT_COL)
-  PICK2(8, 16, NTT_COL)
-  PICK2(7, 32, NTT_ROW)
-  PICK2(8, 16, NTT_ROW)
+  PICK2(8, 16, NTT_COL, 2)
+  PICK2(8, 16, NTT_ROW, 2)
+  if (col_tiles != 1) col_tiles = 1;   // sizes without a multi-tile variant
+  PICK2(6, 64, NTT_COL, 1)
+  PICK2(7, 32, NTT_COL, 1)
+  PICK2(8, 16, NTT_COL, 1)
+  PICK2(7, 32, NTT_ROW, 1)
+  PICK2(8, 16, NTT_ROW, 1)
 #undef PICK2
   return nullptr;
 }
@@ -1585,7 +1703,7 @@ int ntt_pass_count(const DevTables& T) { return T.log_n <= 12 ? 1 : 2; }
 // then columns (inverse); the second pass works in place on what the first
 // wrote to dst
 void launch_ntt_pass(const DevTables& T, bool inverse, const NttJob* jobs, int n_jobs, int max_limbs, int pass,
-                     hipStream_t s) {
+                     hipStream_t s, int tiles_sched) {
   if (n_jobs <= 0 || max_limbs <= 0) return;
   const int log_n = T.log_n;
   const int N = 1 << log_n;
@@ -1602,8 +1720,11 @@ void launch_ntt_pass(const DevTables& T, bool inverse, const NttJob* jobs, int n
     mode = pass == 0 ? NTT_ROW : NTT_COL;
   }
   int g = 0;
-  void* fn = ntt_kernel(logs, mode, inverse, &g);
-  const int tiles = (N >> logs) / g;
+  // two tiles per workgroup where the schedule asks for it and a variant exists
+  const int bit = mode == NTT_COL ? (inverse ? 2 : 1) : (inverse ? 0 : 4);
+  int p = logs == 8 && (tiles_sched & bit) ? 2 : 1;
+  void* fn = ntt_kernel(logs, mode, inverse, &g, p);
+  const int tiles = (N >> logs) / g / p;
   // limb-major: consecutive workgroups transform the same limb (prime) of
   // successive jobs, so that prime's twiddles are reused from L2
   dim3 grid(tiles, n_jobs, max_limbs);
@@ -1647,8 +1768,9 @@ void launch_inner_row(const DevTables& T, const InnerJob* jobs, int n_jobs, int 
   else hipLaunchKernelGGL((k_inner_row<7, 32>), grid, dim3(256), ntt_lds_bytes(7, 32), s, jobs, T);
 }
 
-void launch_ntt(const DevTables& T, bool inverse, const NttJob* jobs, int n_jobs, int max_limbs, hipStream_t s) {
-  for (int p = 0; p < ntt_pass_count(T); ++p) launch_ntt_pass(T, inverse, jobs, n_jobs, max_limbs, p, s);
+void launch_ntt(const DevTables& T, bool inverse, const NttJob* jobs, int n_jobs, int max_limbs, hipStream_t s,
+                int tiles_sched) {
+  for (int p = 0; p < ntt_pass_count(T); ++p) launch_ntt_pass(T, inverse, jobs, n_jobs, max_limbs, p, s, tiles_sched);
 }
 
 void launch_ew(const DevTables& T, const EwJob* jobs, int n_jobs, int max_limbs, hipStream_t s) {

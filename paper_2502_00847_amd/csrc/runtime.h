@@ -79,6 +79,9 @@ struct Ctx {
   size_t ntt_chunk_bytes = 0;
   // output limbs per workgroup of the fused ModUp (2 or 4); set by the autotuner
   int modup_eg = 4;
+  // NTT passes with two tiles per workgroup (bit 0 forward column, bit 1
+  // inverse column, bit 2 forward row); set by the autotuner
+  int ntt_tiles = 0;
   int q_bits = 0, p_bits = 0, log_scale = 0, dg = 2, df = 2, min_level = 1;
   int refresh_level = 0;   // level a refreshed ciphertext is re-encrypted at
   int refresh_level_set = 0;  // the level the parameters asked for (bootstrapping may override it)

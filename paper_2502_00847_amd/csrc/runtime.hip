@@ -565,7 +565,7 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
             (void)hipEventRecord(e0, s);
             c.prof_launches++;
           }
-          launch_ntt_pass(T, k.inv, jobs + j0, nj, k.max_y, pass, s);
+          launch_ntt_pass(T, k.inv, jobs + j0, nj, k.max_y, pass, s, c.ntt_tiles);
           if (e0) {
             hipEvent_t e1 = prof_event(c);
             if (e1) (void)hipEventRecord(e1, s);
@@ -591,9 +591,9 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
       c.prof_units_shared += k.units_shared;
     }
     switch (k.kind) {
-      case C_NTT: launch_ntt(T, k.inv, (const NttJob*)j, k.n, k.max_y, s); break;
-      case C_NTT_FIRST: launch_ntt_pass(T, k.inv, (const NttJob*)j, k.n, k.max_y, 0, s); break;
-      case C_NTT_SECOND: launch_ntt_pass(T, k.inv, (const NttJob*)j, k.n, k.max_y, 1, s); break;
+      case C_NTT: launch_ntt(T, k.inv, (const NttJob*)j, k.n, k.max_y, s, c.ntt_tiles); break;
+      case C_NTT_FIRST: launch_ntt_pass(T, k.inv, (const NttJob*)j, k.n, k.max_y, 0, s, c.ntt_tiles); break;
+      case C_NTT_SECOND: launch_ntt_pass(T, k.inv, (const NttJob*)j, k.n, k.max_y, 1, s, c.ntt_tiles); break;
       case C_EW: launch_ew(T, (const EwJob*)j, k.n, k.max_y, s); break;
       case C_MODUP: launch_modup(T, (const ModUpJob*)j, k.n, s); break;
       case C_MODUP_COL: launch_modup_col(T, (const ModUpJob*)j, k.n, k.max_y, c.modup_eg, s); break;

@@ -111,6 +111,7 @@ def load():
         "secpe_profile_begin": (i32, [vp, i32]),
         "secpe_profile_end": (i32, [vp, P(i64), P(dbl), P(i64), P(i64)]),
         "secpe_keyswitch_traffic": (i32, [vp, P(i64)]),
+        "secpe_set_schedule": (i32, [vp, i32]),
         "secpe_profile_segments": (i32, [vp, P(dbl), i32]),
         "secpe_ntt_cts": (i32, [vp, ct, i32, i32]),
         "secpe_rotate_workspace_bytes": (sz, [vp, i32]),
@@ -149,7 +150,7 @@ def exported_symbols():
          "secpe_decrypt_coeffs", "secpe_workspace_bytes", "secpe_eval_argmax", "secpe_eval_argmax_noalloc", "secpe_eval_argmax_batch",
          "secpe_counters", "secpe_ct_export", "secpe_ct_import", "secpe_key_export", "secpe_sk_export",
          "secpe_sync", "secpe_op_workspace_bytes", "secpe_op_add", "secpe_op_sub", "secpe_op_add_const",
-         "secpe_op_mul_const", "secpe_op_lincomb", "secpe_autotune", "secpe_packed_shape", "secpe_encrypt_packed",
+         "secpe_op_mul_const", "secpe_op_lincomb", "secpe_autotune", "secpe_set_schedule", "secpe_packed_shape", "secpe_encrypt_packed",
          "secpe_packed_workspace_bytes", "secpe_eval_argmax_packed", "secpe_phoenix_steps",
          "secpe_phoenix_workspace_bytes", "secpe_eval_argmax_phoenix", "secpe_op_mul_plain", "secpe_op_rescale", "secpe_op_mul_relin",
          "secpe_op_mul_relin_rescale", "secpe_op_rotate", "secpe_op_refresh", "secpe_op_eval_odd9",
@@ -499,7 +500,10 @@ class Context:
         return outs
 
     AUTOTUNE_CANDIDATES = [dict(modup_outputs_per_workgroup=2 if i & 1 else 4,
-                                ntt_job_group_mib=128 if i & 2 else None) for i in range(4)]
+                                ntt_job_group_mib=128 if i & 2 else None,
+                                fwd_col_tiles_per_workgroup=2 if i & 4 else 1,
+                                inv_col_tiles_per_workgroup=2 if i & 8 else 1,
+                                fwd_row_tiles_per_workgroup=2 if i & 16 else 1) for i in range(32)]
 
     def autotune(self, cts, Ks, Cs, d_min, d_max, seeds, ws, outs, owner=None):
         """Time the batch under each candidate schedule; the fastest stays set."""
@@ -518,7 +522,13 @@ class Context:
                                             ws.numel() * 8, cout, C.byref(chosen), _p(ms, C.c_double), len(ms)))
         for o, c in zip(outs, cout):
             o.level, o.scale = c.level, c.scale
-        return chosen.value, [dict(c, ms=round(float(t), 3)) for c, t in zip(self.AUTOTUNE_CANDIDATES, ms)]
+        timed = [dict(c, index=i, ms=round(float(t), 3)) for i, (c, t) in enumerate(zip(self.AUTOTUNE_CANDIDATES, ms))
+                 if t > 0]
+        return chosen.value, timed
+
+    def set_schedule(self, candidate):
+        """Apply an autotuner candidate (knob bits) without timing."""
+        self._check(self.lib.secpe_set_schedule(self.h, int(candidate)))
 
     def eval_argmax(self, ct, K, Cc, d_min, d_max, refresh_seed, ws=None, owner=None):
         return self.eval_argmax_batch([ct], [K], [Cc], [d_min], [d_max], [refresh_seed], ws=ws, owner=owner)[0]

@@ -14,7 +14,11 @@ Cases:
              product relinearised, then rescaled);
   config 3   24 queries of the 256-query batch (N=2^16): the first two of
              every padded shape (K', C') in {4, 8, 16} x {2, 4, 8, 16};
-  config 5   three requests of the serving mix at N=2^16 with K' or C' = 32.
+  config 5   three requests of the serving mix at N=2^16 with K' or C' = 32;
+  boot13     bootstrapping at N=2^13 (the p13_boot set): one bootstrap of a
+             seeded level-3 ciphertext, and Algorithm 1 (K=2, C=2) with
+             every refresh a bootstrap (the oracle takes about ten minutes
+             per bootstrap here).
 Each case keys its own oracle with the rotations its shape needs (a key
 depends only on the seed and its Galois element, so these equal the keys of
 any larger set).  Cases run in parallel processes.
@@ -76,14 +80,70 @@ for _q in config3_sample():
     CASES[f"config3_full_q{_q}"] = ("full", 3, _q, "merged")
 for _q in config5_sample():
     CASES[f"config5_full_q{_q}"] = ("full", 5, _q, "merged")
+CASES["boot13_bootstrap"] = ("p13_boot", "bootstrap", 0, "merged")
+CASES["boot13_argmax"] = ("p13_boot", "argmax_boot", 0, "merged")
+
+BOOT_SEED = 0xB007
+
+
+def boot_steps(o, k_max, c_max):
+    return sorted(set(o.boot_steps()) | set(argmax_rotation_steps(k_max, c_max, o.slots)),
+                  key=lambda v: (v < 0, v))
+
+
+def boot_input(slots):
+    """The bootstrapped input: uniform slot values in [-1, 1] at scale 2^49,
+    encrypted with seed 7 and lowered to level 3."""
+    import numpy as np
+    return np.random.default_rng(5).uniform(-1, 1, slots), 2.0**49, 7, 3
+
+
+def argmax_boot_query():
+    K, C = 2, 2
+    y = W.logits(9, 5, K, C)
+    lo, hi = W.d_bounds(K)
+    return dict(K=K, C=C, logits=y, encrypt_seed=3, refresh_seed=4, d_min=lo, d_max=hi)
 
 
 def digest(arr):
     return hashlib.sha256(arr.astype("<u8").tobytes()).hexdigest()
 
 
+def run_boot_case(name):
+    pset, kind, _, _ = CASES[name]
+    o = Oracle.from_params(W.PARAMS[pset])
+    t = time.time()
+    o.keygen(BOOT_SEED, boot_steps(o, 4, 4))
+    tk = time.time() - t
+    t = time.time()
+    if kind == "bootstrap":
+        z, scale, seed, level = boot_input(o.slots)
+        ct = o.lower(o.encrypt(o.encode(z, scale), scale, seed), level)
+        out = o.bootstrap(ct)
+        zz = o.decrypt_decode(out, o.slots)
+        import numpy as np
+        extra = {"max_error_log2": float(np.log2(np.abs(zz - z).max()))}
+        zrec = []
+    else:
+        d = argmax_boot_query()
+        ct = o.encrypt_logits(d["logits"], d["encrypt_seed"])
+        o.reset_counters()
+        out = o.eval_argmax(ct, d["K"], d["C"], d["d_min"], d["d_max"], d["refresh_seed"])
+        zrec = [float(v) for v in o.decrypt_decode(out, d["C"])]
+        extra = {"K": d["K"], "C": d["C"], "counters": o.counters()}
+    dt = time.time() - t
+    rec = {"params": pset, "kind": kind, "input_sha256": digest(ct.export()), "output_sha256": digest(out.export()),
+           "level": out.level, "scale": out.scale, "z": zrec, "oracle_seconds": round(dt, 1),
+           "secret_weight": int((o.secret() != 0).sum())}
+    rec.update(extra)
+    print(f"{name}: keygen {tk:.1f} s, {dt:.1f} s, level {out.level}", flush=True)
+    return name, rec
+
+
 def run_case(name):
     pset, cfg, q, evaluator = CASES[name]
+    if pset == "p13_boot":
+        return run_boot_case(name)
     d = W.query(cfg, q)
     o = Oracle.from_params(W.PARAMS[pset])
     o.set_textbook(evaluator == "textbook")
@@ -111,7 +171,7 @@ def run_case(name):
 def main():
     names = sys.argv[1:] or list(CASES)
     # longest first, so the pool stays busy to the end
-    cost = {"toy": 0, "toy_deep": 1}
+    cost = {"toy": 0, "toy_deep": 1, "p13_boot": -10}
     names.sort(key=lambda n: (-CASES[n][1] if CASES[n][0] == "full" else cost.get(CASES[n][0], 0)))
     out = {}
     if os.path.exists(OUT):

@@ -254,3 +254,96 @@ def test_full_argmax_with_bootstrapping(full):
     assert idx == sim.t0_argmax(q["logits"])[0]
     zs = sim.t1_argmax(q["logits"], q["d_min"], q["d_max"], g.slots)[:q["C"]]
     assert np.abs(zz - zs).max() < 1e-2
+
+
+# N = 2^13 (p13_boot): the sizes at which the bootstrap takes the paths it takes
+# at N = 2^16 -- the two-pass NTT, the fused ModUp column pass and inner-product
+# row pass, and baby-step giant-step groups of n1 = 8 -- compared with digests
+# the oracle wrote (tests/golden/make_golden.py: about ten minutes of oracle
+# time per bootstrap at this size)
+@pytest.fixture(scope="module")
+def p13boot():
+    import json
+    import os
+    from paper_2502_00847_amd.secpe import Context
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "argmax_digests.json")) as f:
+        gold = json.load(f)
+    g = Context(W.PARAMS["p13_boot"])
+    steps = sorted(set(g.boot_steps()) | set(argmax_rotation_steps(4, 4, g.slots)), key=lambda v: (v < 0, v))
+    print(f"[boot13] keygen {len(steps)} keys", flush=True)
+    g.keygen(SEED, steps)
+    g.boot_setup()
+    return g, gold
+
+
+def _digest(arr):
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(arr).astype("<u8").tobytes()).hexdigest()
+
+
+def test_p13_bootstrap_matches_oracle_digest(p13boot):
+    g, gold = p13boot
+    rec = gold["boot13_bootstrap"]
+    assert np.count_nonzero(g.secret()) == rec["secret_weight"]
+    # the oracle's input: uniform slots at 2^49, encrypted with seed 7, lowered to level 3
+    z = np.random.default_rng(5).uniform(-1, 1, g.slots)
+    full = g.encrypt_coeffs(g.encode(z, 2.0**49), 2.0**49, 7)
+    ct = g.import_(g.export(full)[:, :4, :], full.scale)
+    assert _digest(g.export(ct)) == rec["input_sha256"]
+    [b] = g.bootstrap([ct])
+    assert (b.level, b.scale) == (rec["level"], rec["scale"])
+    assert _digest(g.export(b)) == rec["output_sha256"]
+    err = np.abs(g.decrypt(b, g.slots)[0] - z).max()
+    print(f"[boot13] bootstrap error 2^{np.log2(err):.1f}", flush=True)
+    assert err < 2.0**-16
+
+
+def test_p13_argmax_with_bootstrapping_matches_oracle_digest(p13boot):
+    """Algorithm 1 (K = 2, C = 2) with every refresh a bootstrap, no key owner."""
+    g, gold = p13boot
+    rec = gold["boot13_argmax"]
+    K, C = rec["K"], rec["C"]
+    y = W.logits(9, 5, K, C)
+    lo, hi = W.d_bounds(K)
+    ct = g.encrypt(y, 3)
+    assert _digest(g.export(ct)) == rec["input_sha256"]
+    z = g.eval_argmax(ct, K, C, lo, hi, 4)
+    assert (z.level, z.scale) == (rec["level"], rec["scale"])
+    assert _digest(g.export(z)) == rec["output_sha256"]
+    cnt = g.counters()
+    for k in ("sign", "rotate", "relin", "key_switch", "max"):
+        assert cnt[k] == rec["counters"][k], k
+    zz, idx = g.decrypt(z, C)
+    assert np.allclose(zz, rec["z"], rtol=0, atol=1e-9)
+    assert idx == sim.t0_argmax(y)[0]
+
+
+def test_paper_budget_set_bootstraps_within_its_bound():
+    """The paper's budget (Sec. 4.1): N = 2^16, L = 35 chain primes, log QP <=
+    1763 bits, 14 bootstrapping levels.  A bootstrap of a dense and of a
+    sparse slot vector stays within 2^-8.5 and the config-2 Argmax, with every
+    refresh a bootstrap and no key owner, returns the plaintext argmax."""
+    from paper_2502_00847_amd.secpe import Context
+    p = W.PARAMS["full_boot128"]
+    g = Context(p)
+    log_qp = sum(np.log2(float(v)) for v in g.primes)
+    assert g.n_q == 35 and log_qp <= 1763.0
+    assert g.boot_out_level == g.n_q - 1 - 14
+    steps = sorted(set(g.boot_steps()) | set(g.argmax_steps(8, 4)), key=lambda v: (v < 0, v))
+    print(f"[boot128] log QP {log_qp:.2f}, keygen {len(steps)} keys", flush=True)
+    g.keygen(SEED, steps)
+    g.boot_setup()
+    rng = np.random.default_rng(61)
+    dense = rng.uniform(-1, 1, g.slots)
+    sparse = np.zeros(g.slots)
+    sparse[:32] = rng.uniform(0, 1, 32)
+    for kind, z in (("dense", dense), ("sparse", sparse)):
+        [b] = g.bootstrap([g.encrypt(z.reshape(1, -1), 62 + len(kind))])
+        err = np.abs(g.decrypt(b, g.slots)[0] - z).max()
+        print(f"[boot128] {kind}: error 2^{np.log2(err):.2f}", flush=True)
+        assert b.level == g.boot_out_level and err < 2.0**-8.5
+    q = W.query(2, 0)
+    z = g.eval_argmax(g.encrypt(q["logits"], q["encrypt_seed"]), q["K"], q["C"], q["d_min"], q["d_max"],
+                      q["refresh_seed"])
+    assert g.counters()["refresh"] >= 1
+    assert g.decrypt(z, q["C"])[1] == sim.t0_argmax(q["logits"])[0]

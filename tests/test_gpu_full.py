@@ -222,6 +222,23 @@ def test_config5_full_matches_oracle_digests():
     _batch_digests(g, recs)
 
 
+def test_every_schedule_keeps_the_config2_bits(full_gpu, golden):
+    """Each knob of the autotuner on its own (two-tile column passes, forward
+    and inverse; two output limbs per ModUp workgroup; NTT job groups) gives
+    the oracle's config-2 ciphertext at N = 2^16."""
+    rec = golden["config2_full"]
+    g = full_gpu
+    d = W.query(2, 0)
+    ct = g.encrypt(d["logits"], d["encrypt_seed"])
+    try:
+        for cand in (1, 2, 4, 8, 16, 28, 31):
+            g.set_schedule(cand)
+            z = g.eval_argmax(ct, d["K"], d["C"], d["d_min"], d["d_max"], d["refresh_seed"], owner=g.owner)
+            assert _digest(g.export(z)) == rec["output_sha256"], cand
+    finally:
+        g.set_schedule(0)
+
+
 def test_toy_argmax_matches_oracle_digest(golden):
     """Config 1: N=2^13, 8 x 30-bit primes + 1 special prime, scale 2^30, K=4, C=2."""
     from paper_2502_00847_amd.secpe import Context
