@@ -59,6 +59,7 @@ def _load():
         "orc_mul_relin": (vp, [vp, vp, vp]),
         "orc_mul_relin_rescale": (vp, [vp, vp, vp]),
         "orc_rotate": (vp, [vp, vp, i64]),
+        "orc_rotate_hoisted": (None, [vp, vp, P(i64), ci, P(vp)]),
         "orc_refresh": (vp, [vp, vp, u64, u64]),
         "orc_key_switch": (None, [vp, u64, P(u64), ci, P(u64), P(u64)]),
         "orc_key_switch_raw": (None, [vp, u64, P(u64), ci, P(u64), P(u64)]),
@@ -368,6 +369,13 @@ class Oracle:
 
     def rotate(self, a, step):
         return self._wrap(self.lib.orc_rotate(self.h, a.h, int(step)))
+
+    def rotate_hoisted(self, a, steps):
+        """RotL(a, s) for every s in steps, sharing one ModUp of a's c1."""
+        st = np.ascontiguousarray(steps, dtype=np.int64)
+        out = (C.c_void_p * len(st))()
+        self.lib.orc_rotate_hoisted(self.h, a.h, _p(st, C.c_int64), len(st), out)
+        return [self._wrap(v) for v in out]
 
     def refresh(self, a, seed, index):
         return self._wrap(self.lib.orc_refresh(self.h, a.h, int(seed), int(index)))

@@ -822,18 +822,25 @@ static orc_ct* op_add_plain(orc_ctx* c, const orc_ct* a, const double* v, int ns
   return x;
 }
 
-/* first half of the hybrid key switch of d (coefficient domain, limbs 0..l)
-   with key k: ModUp of every digit and the inner product with the key,
-   returned in the coefficient domain over Q_l u P (limbs 0..l, then the
-   special primes): acc0 + acc1 s = P d s' + small  (mod Q_l P) */
-static void key_switch_raw(orc_ctx* c, const uint64_t* d, int l, const orc_key* k, uint64_t** acc0, uint64_t** acc1) {
+static uint64_t** alloc_limbs(int count, int n) {
+  uint64_t** a = (uint64_t**)xcalloc(count, sizeof(uint64_t*));
+  for (int e = 0; e < count; ++e) a[e] = (uint64_t*)xcalloc(n, 8);
+  return a;
+}
+static void free_limbs(uint64_t** a, int count) {
+  for (int e = 0; e < count; ++e) free(a[e]);
+  free(a);
+}
+
+/* ModUp of hybrid key switching: d (coefficient domain, limbs 0..l) split
+   into digits of alpha chain primes, each digit raised to Q_l u P (limbs
+   0..l, then the special primes).  ext[j][e] is digit j on extended limb e,
+   in the coefficient domain; on the digit's own primes it is d itself. */
+static uint64_t*** modup_digits(orc_ctx* c, const uint64_t* d, int l, int* dn_out) {
   int n = c->n, alpha = c->alpha, n_q = c->n_q, n_p = c->n_p;
   int n_ext = l + 1 + n_p;
-  int* ext = (int*)xcalloc(n_ext, sizeof(int));
-  for (int i = 0; i <= l; ++i) ext[i] = i;
-  for (int i = 0; i < n_p; ++i) ext[l + 1 + i] = n_q + i;
-  uint64_t* limb = (uint64_t*)xcalloc(n, 8);
   int dn = (l + 1 + alpha - 1) / alpha;
+  uint64_t*** ext = (uint64_t***)xcalloc(dn, sizeof(uint64_t**));
   for (int j = 0; j < dn; ++j) {
     int lo = j * alpha, hi = (j + 1) * alpha < l + 1 ? (j + 1) * alpha : l + 1;
     int sz = hi - lo;
@@ -849,13 +856,14 @@ static void key_switch_raw(orc_ctx* c, const uint64_t* d, int l, const orc_key* 
       const uint64_t* di = d + (size_t)(lo + i) * n;
       for (int x = 0; x < n; ++x) y[i][x] = mmul(di[x], inv, qi);
     }
+    ext[j] = alloc_limbs(n_ext, n);
     for (int e = 0; e < n_ext; ++e) {
-      int t = ext[e];
+      int t = e <= l ? e : n_q + (e - l - 1);
       uint64_t q = c->mod[t];
+      uint64_t* limb = ext[j][e];
       if (t >= lo && t < hi) {
         memcpy(limb, d + (size_t)t * n, 8 * (size_t)n);
       } else {
-        for (int x = 0; x < n; ++x) limb[x] = 0;
         for (int i = 0; i < sz; ++i) {
           uint64_t dhat = 1; /* (D/q_i) mod q */
           for (int i2 = 0; i2 < sz; ++i2)
@@ -863,22 +871,57 @@ static void key_switch_raw(orc_ctx* c, const uint64_t* d, int l, const orc_key* 
           for (int x = 0; x < n; ++x) limb[x] = madd(limb[x], mmul(y[i][x] % q, dhat, q), q);
         }
       }
+    }
+    for (int i = 0; i < sz; ++i) free(y[i]);
+    free(y);
+  }
+  *dn_out = dn;
+  return ext;
+}
+static void free_digits(uint64_t*** ext, int dn, int n_ext) {
+  for (int j = 0; j < dn; ++j) free_limbs(ext[j], n_ext);
+  free(ext);
+}
+
+/* inner product of the raised digits with key k, every digit limb first
+   taken through X -> X^g (g = 1: unchanged), over Q_l u P:
+   acc0 + acc1 s = P sigma_g(d) s' + small, returned in the coefficient domain */
+static void ks_inner(orc_ctx* c, uint64_t*** ext, int dn, int l, uint64_t g, const orc_key* k, uint64_t** acc0,
+                     uint64_t** acc1) {
+  int n = c->n, n_q = c->n_q, n_p = c->n_p;
+  int n_ext = l + 1 + n_p;
+  uint64_t* limb = (uint64_t*)xcalloc(n, 8);
+  for (int j = 0; j < dn; ++j) {
+    for (int e = 0; e < n_ext; ++e) {
+      int t = e <= l ? e : n_q + (e - l - 1);
+      uint64_t q = c->mod[t];
+      if (g == 1) memcpy(limb, ext[j][e], 8 * (size_t)n);
+      else automorph_mod(c, ext[j][e], g, q, limb);
       ntt_fwd(c, t, limb);
       for (int x = 0; x < n; ++x) {
         acc0[e][x] = madd(acc0[e][x], mmul(limb[x], k->b[j][t][x], q), q);
         acc1[e][x] = madd(acc1[e][x], mmul(limb[x], k->a[j][t][x], q), q);
       }
     }
-    for (int i = 0; i < sz; ++i) free(y[i]);
-    free(y);
   }
   for (int e = 0; e < n_ext; ++e) {
-    ntt_inv(c, ext[e], acc0[e]);
-    ntt_inv(c, ext[e], acc1[e]);
+    int t = e <= l ? e : n_q + (e - l - 1);
+    ntt_inv(c, t, acc0[e]);
+    ntt_inv(c, t, acc1[e]);
   }
   free(limb);
-  free(ext);
   c->counters[CNT_KS]++;
+}
+
+/* first half of the hybrid key switch of d (coefficient domain, limbs 0..l)
+   with key k: ModUp of every digit and the inner product with the key,
+   returned in the coefficient domain over Q_l u P (limbs 0..l, then the
+   special primes): acc0 + acc1 s = P d s' + small  (mod Q_l P) */
+static void key_switch_raw(orc_ctx* c, const uint64_t* d, int l, const orc_key* k, uint64_t** acc0, uint64_t** acc1) {
+  int dn;
+  uint64_t*** ext = modup_digits(c, d, l, &dn);
+  ks_inner(c, ext, dn, l, 1, k, acc0, acc1);
+  free_digits(ext, dn, l + 1 + c->n_p);
 }
 
 /* z in [0, b) read as its centred representative in (-b/2, b/2), reduced mod q */
@@ -888,24 +931,12 @@ static uint64_t centred_mod(uint64_t z, uint64_t b, uint64_t q) {
   return m ? q - m : 0;
 }
 
-static uint64_t** alloc_limbs(int count, int n) {
-  uint64_t** a = (uint64_t**)xcalloc(count, sizeof(uint64_t*));
-  for (int e = 0; e < count; ++e) a[e] = (uint64_t*)xcalloc(n, 8);
-  return a;
-}
-static void free_limbs(uint64_t** a, int count) {
-  for (int e = 0; e < count; ++e) free(a[e]);
-  free(a);
-}
 
-/* hybrid key switch of d (coefficient domain, limbs 0..l) with key k:
-   returns (u0, u1) in R_{Q_l} with u0 + u1 s ~ d s' */
-static void key_switch(orc_ctx* c, const uint64_t* d, int l, const orc_key* k, uint64_t* u0, uint64_t* u1) {
+/* ModDown of hybrid key switching: (acc0, acc1) over Q_l u P (coefficient
+   domain) divided by P with rounding -> (u0, u1) in R_{Q_l}; frees acc0, acc1 */
+static void mod_down(orc_ctx* c, uint64_t** acc0, uint64_t** acc1, int l, uint64_t* u0, uint64_t* u1) {
   int n = c->n, n_q = c->n_q, n_p = c->n_p;
   int n_ext = l + 1 + n_p;
-  uint64_t** acc0 = alloc_limbs(n_ext, n);
-  uint64_t** acc1 = alloc_limbs(n_ext, n);
-  key_switch_raw(c, d, l, k, acc0, acc1);
   /* ModDown: (u - Conv_{P->q}([u]_P)) * P^{-1} mod q, the conversion taking
      each [u (P/p)^{-1}]_p centred so the division rounds without bias */
   for (int which = 0; which < 2; ++which) {
@@ -939,6 +970,16 @@ static void key_switch(orc_ctx* c, const uint64_t* d, int l, const orc_key* k, u
   }
   free_limbs(acc0, n_ext);
   free_limbs(acc1, n_ext);
+}
+
+/* hybrid key switch of d (coefficient domain, limbs 0..l) with key k:
+   returns (u0, u1) in R_{Q_l} with u0 + u1 s ~ d s' */
+static void key_switch(orc_ctx* c, const uint64_t* d, int l, const orc_key* k, uint64_t* u0, uint64_t* u1) {
+  int n_ext = l + 1 + c->n_p;
+  uint64_t** acc0 = alloc_limbs(n_ext, c->n);
+  uint64_t** acc1 = alloc_limbs(n_ext, c->n);
+  key_switch_raw(c, d, l, k, acc0, acc1);
+  mod_down(c, acc0, acc1, l, u0, u1);
 }
 
 /* ct x ct: tensor, relinearise (key switch of the s^2 part); caller rescales */
@@ -1185,6 +1226,45 @@ static orc_ct* op_automorph_ks(orc_ctx* c, const orc_ct* a, uint64_t g) {
 /* RotL(x, step): slot j <- slot j+step (g = 5^step); the conjugation for CONJ_STEP */
 static orc_ct* op_rotate(orc_ctx* c, const orc_ct* a, int64_t step) { return op_automorph_ks(c, a, galois_elt(c, step)); }
 
+/* hoisted rotations of one ciphertext by several steps: the ModUp of c1 is
+   computed once and each rotation applies X -> X^g to the raised digits
+   (a signed permutation of coefficients, exact on every limb) before its own
+   inner product and ModDown.  The result differs from RotL's by the basis
+   extension's overshoot, a multiple of the digit modulus, which the key
+   switch divides by P like any other error. */
+static void op_rotate_hoisted(orc_ctx* c, const orc_ct* a, const int64_t* steps, int m, orc_ct** out) {
+  int l = a->level, n = c->n;
+  int n_ext = l + 1 + c->n_p;
+  int dn = 0;
+  uint64_t*** ext = NULL;
+  for (int s = 0; s < m; ++s) {
+    uint64_t g = galois_elt(c, steps[s]);
+    if (g == 1) {
+      out[s] = ct_copy(c, a, l);
+      continue;
+    }
+    orc_key* k = find_key(c, g);
+    if (!k) die("missing Galois key");
+    if (!ext) ext = modup_digits(c, a->c[1], l, &dn);
+    orc_ct* x = ct_new(c, l, a->scale);
+    uint64_t** acc0 = alloc_limbs(n_ext, n);
+    uint64_t** acc1 = alloc_limbs(n_ext, n);
+    ks_inner(c, ext, dn, l, g, k, acc0, acc1);
+    uint64_t* u0 = (uint64_t*)xcalloc((size_t)(l + 1) * n, 8);
+    mod_down(c, acc0, acc1, l, u0, x->c[1]);
+    for (int t = 0; t <= l; ++t) {
+      automorph_mod(c, LIMB(a, 0, t, n), g, c->mod[t], LIMB(x, 0, t, n));
+      uint64_t* o = LIMB(x, 0, t, n);
+      const uint64_t* u = u0 + (size_t)t * n;
+      for (int i = 0; i < n; ++i) o[i] = madd(o[i], u[i], c->mod[t]);
+    }
+    free(u0);
+    c->counters[CNT_ROT]++;
+    out[s] = x;
+  }
+  if (ext) free_digits(ext, dn, n_ext);
+}
+
 /* key-owner refresh, the stand-in for bootstrapping: decrypt, lift the message
    exactly and re-encrypt at the top level with fresh randomness; scale kept */
 static orc_ct* op_refresh(orc_ctx* c, const orc_ct* a, uint64_t seed, uint64_t index) {
@@ -1221,6 +1301,10 @@ ORC_API void* orc_mul_relin_rescale(void* h, const void* a, const void* b) {
   return op_mul_relin_rescale((orc_ctx*)h, (const orc_ct*)a, (const orc_ct*)b);
 }
 ORC_API void* orc_rotate(void* h, const void* a, int64_t step) { return op_rotate((orc_ctx*)h, (const orc_ct*)a, step); }
+/* hoisted rotations of a by steps[0..m): out[i] = RotL(a, steps[i]) sharing one ModUp */
+ORC_API void orc_rotate_hoisted(void* h, const void* a, const int64_t* steps, int m, void** out) {
+  op_rotate_hoisted((orc_ctx*)h, (const orc_ct*)a, steps, m, (orc_ct**)out);
+}
 ORC_API void* orc_refresh(void* h, const void* a, uint64_t seed, uint64_t index) {
   return op_refresh((orc_ctx*)h, (const orc_ct*)a, seed, index);
 }
@@ -1898,9 +1982,26 @@ static orc_ct* boot_apply_group(orc_ctx* c, const boot_group* G, int g, const or
     int64_t e = boot_e(G, d);
     used[e - G->n1 * floor_div(e, G->n1)] = 1;
   }
+  /* the baby steps share one ModUp (hoisted rotations) */
   orc_ct** xb = (orc_ct**)xcalloc(G->n1, sizeof(orc_ct*));
-  for (int b = 0; b < G->n1; ++b)
-    if (used[b]) xb[b] = b == 0 ? ct_copy(c, x, l) : op_rotate(c, x, (int64_t)G->delta * b);
+  int64_t* bst = (int64_t*)xcalloc(G->n1, sizeof(int64_t));
+  int* bidx = (int*)xcalloc(G->n1, sizeof(int));
+  orc_ct** bout = (orc_ct**)xcalloc(G->n1, sizeof(orc_ct*));
+  int nb = 0;
+  for (int b = 0; b < G->n1; ++b) {
+    if (!used[b]) continue;
+    if (b == 0) {
+      xb[0] = ct_copy(c, x, l);
+    } else {
+      bst[nb] = (int64_t)G->delta * b;
+      bidx[nb++] = b;
+    }
+  }
+  op_rotate_hoisted(c, x, bst, nb, bout);
+  for (int i = 0; i < nb; ++i) xb[bidx[i]] = bout[i];
+  free(bst);
+  free(bidx);
+  free(bout);
   orc_ct* out = NULL;
   /* the encoded diagonals are kept per (direction, group, plaintext scale) */
   struct boot_pt* cache = c->boot_cache;

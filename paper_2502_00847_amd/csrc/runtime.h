@@ -239,7 +239,9 @@ class Builder {
   void modup(const std::vector<ModUpJob>& v);
   void modup_col(const std::vector<ModUpJob>& v);
   void moddown(const std::vector<ModDownJob>& v);
-  void inner(const std::vector<InnerJob>& v);
+  // row_fused: with the two-pass NTT, the inner product runs the ext limbs'
+  // row pass (their inputs leave the ModUp after the column pass)
+  void inner(const std::vector<InnerJob>& v, bool row_fused = true);
   void automorph(const std::vector<AutoJob>& v);
   void lift(const std::vector<LiftJob>& v);
   void raise(const std::vector<RaiseJob>& v);
@@ -302,6 +304,19 @@ class Builder {
   // the fused inner product runs the first inverse NTT pass on those limbs
   void ks_front(const std::vector<KsItem>& items, std::vector<KsTmp>& tmp, bool merged);
   void key_switch(const std::vector<KsItem>& items);
+  // second half: ModDown by P of each accumulator, added to the item's base;
+  // first_pass_done: the inner product already ran the first inverse NTT pass
+  void ks_back(const std::vector<KsItem>& items, const std::vector<KsTmp>& tmp, bool first_pass_done);
+  // hoisted rotations: the ModUp of each input's c1 once (ext, NTT domain,
+  // in scratch until the caller releases it), then rotations of every input
+  // by any steps, each applying X -> X^g to the raised digits
+  struct Hoisted {
+    std::vector<CT> in;
+    std::vector<double*> ext;
+  };
+  Hoisted hoist(const std::vector<CT>& in);
+  // out[s * n + i] = RotL(in[i], steps[s])
+  std::vector<CT> rotate_hoisted(const Hoisted& h, const std::vector<int64_t>& steps);
   std::vector<Deg2> tensor2(const std::vector<TensorItem>& v);
   std::vector<CT> relin_rescale(const std::vector<Deg2>& xs);
   std::vector<CT> lincomb(const std::vector<LinItem>& v, bool do_rescale);

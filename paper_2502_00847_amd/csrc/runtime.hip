@@ -423,7 +423,7 @@ void Builder::moddown(const std::vector<ModDownJob>& v) {
   for (auto& j : v) units += j.n_chain + C.n_p + (j.first_prime >= 0 ? 1 : 0);
   PUSH_JOBS(C_MODDOWN, v, 1, false, units);
 }
-void Builder::inner(const std::vector<InnerJob>& v) {
+void Builder::inner(const std::vector<InnerJob>& v, bool row_fused) {
   int my = 0;
   int64_t units = 0, own = 0;
   // a key read by several jobs of the launch: the union of their key limbs,
@@ -440,7 +440,8 @@ void Builder::inner(const std::vector<InnerJob>& v) {
   for (auto& kv : key_limbs) shared += kv.second;
   if (v.empty()) return;
   const char* p = (const char*)put(v);
-  push(inner_row_fused(C.T) ? C_INNER_ROW : C_INNER, (int)v.size(), my, (size_t)(p - arena_), false, units, shared);
+  push(row_fused && inner_row_fused(C.T) ? C_INNER_ROW : C_INNER, (int)v.size(), my, (size_t)(p - arena_), false, units,
+       shared);
 }
 void Builder::automorph(const std::vector<AutoJob>& v) {
   int my = 0;
@@ -715,9 +716,13 @@ void Builder::ks_front(const std::vector<KsItem>& items, std::vector<KsTmp>& tmp
 
 // key switching (hybrid): front half, then ModDown by P
 void Builder::key_switch(const std::vector<KsItem>& items) {
-  const int N = C.N, n_p = C.n_p;
   std::vector<KsTmp> tmp;
   ks_front(items, tmp, false);
+  ks_back(items, tmp, inner_row_fused(C.T));
+}
+
+void Builder::ks_back(const std::vector<KsItem>& items, const std::vector<KsTmp>& tmp, bool first_pass_done) {
+  const int N = C.N, n_p = C.n_p;
   std::vector<NttJob> j_inv_acc, j_fwd_conv;
   std::vector<ModDownJob> j_down;
   for (size_t i = 0; i < items.size(); ++i) {
@@ -728,7 +733,6 @@ void Builder::key_switch(const std::vector<KsItem>& items) {
     for (int w = 0; w < 2; ++w) {
       double* aw = acc + (size_t)w * n_ext * N;
       double* sp = aw + (size_t)nc * N;
-      // (fused: the first pass already ran inside the inner product)
       j_inv_acc.push_back(NttJob{sp, sp, n_p, 0, 0, 0});
       double* cv = conv + (size_t)w * nc * N;
       j_down.push_back(ModDownJob{sp, cv, C.md_cinv, C.md_chat, nc, -1});
@@ -742,10 +746,112 @@ void Builder::key_switch(const std::vector<KsItem>& items) {
       j_fwd_conv.push_back(f);
     }
   }
-  ntt(j_inv_acc, true, inner_row_fused(C.T) ? 1 : -1);
+  ntt(j_inv_acc, true, first_pass_done ? 1 : -1);
   moddown(j_down);
   ntt(j_fwd_conv, false);
   counters[3] += (int64_t)items.size();
+}
+
+Builder::Hoisted Builder::hoist(const std::vector<CT>& in) {
+  const int N = C.N, alpha = C.alpha, n_p = C.n_p;
+  const bool fused = inner_row_fused(C.T);
+  Hoisted h;
+  h.in = in;
+  for (const CT& x : in) {
+    const int nc = x.level + 1, nd = (nc + alpha - 1) / alpha;
+    h.ext.push_back(scratch((size_t)nd * (nc + n_p) * N));
+  }
+  const size_t mark = scratch_mark();
+  std::vector<NttJob> j_inv, j_fwd_ext;
+  std::vector<ModUpJob> j_up;
+  for (size_t i = 0; i < in.size(); ++i) {
+    const CT& x = in[i];
+    const int l = x.level, nc = l + 1, n_ext = nc + n_p, nd = (nc + alpha - 1) / alpha;
+    double* dcoef = scratch((size_t)nc * N);
+    NttJob ji{c1(x), dcoef, nc, nc, 0, 0};
+    if (fused) ji.ek = C.ytab + (size_t)l * C.n_q;
+    j_inv.push_back(ji);
+    for (int j = 0; j < nd; ++j) {
+      const int lo = j * alpha, hi = std::min((j + 1) * alpha, nc);
+      const DigitTable& dt = C.digits.at({lo, hi - lo});
+      double* e = h.ext[i] + (size_t)j * n_ext * N;
+      j_up.push_back(ModUpJob{dcoef, e, dt.cinv, dt.chat, lo, hi, nc, n_ext});
+      j_fwd_ext.push_back(NttJob{e, e, n_ext, nc, lo, hi});
+    }
+  }
+  ntt(j_inv, true);
+  if (fused) {
+    // ModUp + column pass, then the row pass on its own: the automorphism
+    // needs each raised limb fully transformed
+    modup_col(j_up);
+    ntt(j_fwd_ext, false, 1);
+  } else {
+    modup(j_up);
+    ntt(j_fwd_ext, false);
+  }
+  scratch_release(mark);
+  return h;
+}
+
+// ext limbs on a digit's own primes are never written (the inner product
+// reads those from d); the automorphism permutes them along unread
+std::vector<CT> Builder::rotate_hoisted(const Hoisted& h, const std::vector<int64_t>& steps) {
+  const int N = C.N, alpha = C.alpha, n_p = C.n_p;
+  const size_t mark = scratch_mark();
+  std::vector<CT> out;
+  std::vector<AutoJob> j_a;
+  std::vector<InnerJob> j_in;
+  std::vector<KsItem> ks;
+  std::vector<KsTmp> tmp;
+  std::map<const double*, int64_t> key_limbs;
+  for (int64_t st : steps) {
+    const uint64_t g = C.galois(st);
+    const double* gk = nullptr;
+    if (g != 1) {
+      auto it = C.keys.find(g);
+      gk = it != C.keys.end() ? it->second : (dry ? C.T.mod : nullptr);
+      if (!gk) { fail(-4, "no Galois key for rotation " + std::to_string(st)); return {}; }
+    }
+    for (size_t i = 0; i < h.in.size(); ++i) {
+      const CT& x = h.in[i];
+      const int nc = x.level + 1, n_ext = nc + n_p, nd = (nc + alpha - 1) / alpha;
+      CT o = new_ct(x.level, x.scale);
+      if (g == 1) {
+        EwJob e{};
+        e.o0 = c0(o); e.o1 = c1(o); e.a0 = c0(x); e.a1 = c1(x);
+        e.n_limbs = nc; e.n_chain = nc; e.op = EW_COPY;
+        ew({e});
+        out.push_back(o);
+        continue;
+      }
+      double* d = scratch((size_t)nc * N);
+      double* es = scratch((size_t)nd * n_ext * N);
+      double* acc = scratch((size_t)2 * n_ext * N);
+      j_a.push_back(AutoJob{c0(x), c0(o), nc, nc, (uint32_t)g, 0});
+      j_a.push_back(AutoJob{c1(x), d, nc, nc, (uint32_t)g, 0});
+      j_a.push_back(AutoJob{h.ext[i], es, nd * n_ext, nd * n_ext, (uint32_t)g, 0});
+      InnerJob in{d, es, gk, acc, nullptr, nullptr, C.p_mod_q, nc, n_ext, nd, alpha};
+      in.inv_from = n_ext;
+      in.d_square = 0;
+      j_in.push_back(in);
+      ks.push_back(KsItem{d, x.level, gk, c0(o), nullptr, c0(o), c1(o), nullptr, nullptr, false});
+      tmp.push_back(KsTmp{nullptr, es, acc, n_ext});
+      // section (d) accounting: ciphertext limbs in and out, each key once
+      ks_alg_limbs += 3 * (int64_t)nc;
+      int64_t& kl = key_limbs[gk];
+      kl = std::max(kl, (int64_t)2 * nd * n_ext);
+      out.push_back(o);
+    }
+  }
+  for (auto& kv : key_limbs) ks_alg_limbs += kv.second;
+  if (!ks.empty()) {
+    automorph(j_a);
+    inner(j_in, false);
+    ks_back(ks, tmp, false);
+    counters[1] += (int64_t)ks.size();
+  }
+  scratch_release(mark);
+  return out;
 }
 
 // merged relinearise + rescale of degree-2 ciphertexts (d0, d1, d2) at level l:
@@ -1503,9 +1609,15 @@ std::vector<CT> Builder::boot_transform(const std::vector<CT>& in, bool inverse)
           rst.push_back((int64_t)G.delta * b);
         }
       }
+      // the baby steps share one ModUp per input (hoisted rotations)
       std::vector<CT> rb;
       if (!rin.empty()) {
-        rb = rotate(rin, rst);
+        std::vector<int64_t> bst;
+        for (size_t k = 0; k < rst.size(); k += n) bst.push_back(rst[k]);
+        const size_t hm = scratch_mark();
+        Hoisted hx = hoist(cur);
+        rb = rotate_hoisted(hx, bst);
+        scratch_release(hm);
         if (err_code) return {};
       }
       std::vector<BsgsJob> jb;
@@ -1536,6 +1648,12 @@ std::vector<CT> Builder::boot_transform(const std::vector<CT>& in, bool inverse)
       for (CT& v : rb) free_ct(v);
     } else {
       std::vector<char> have(n * ng, 0);
+      // the baby steps share one ModUp per input (hoisted rotations)
+      bool any_baby = false;
+      for (int64_t e : G.e) any_baby = any_baby || e != G.n1 * fdiv(e, G.n1);
+      const size_t hm = scratch_mark();
+      Hoisted hx;
+      if (any_baby) hx = hoist(cur);
       for (int b = 0; b < G.n1; ++b) {
         std::vector<size_t> di;
         for (size_t i = 0; i < G.e.size(); ++i)
@@ -1543,7 +1661,7 @@ std::vector<CT> Builder::boot_transform(const std::vector<CT>& in, bool inverse)
         if (di.empty()) continue;
         std::vector<CT> xb = cur;
         if (b > 0) {
-          xb = rotate(cur, std::vector<int64_t>(n, (int64_t)G.delta * b));
+          xb = rotate_hoisted(hx, {(int64_t)G.delta * b});
           if (err_code) return {};
         }
         // every accumulator gets at most one term per baby step: the first
@@ -1572,6 +1690,7 @@ std::vector<CT> Builder::boot_transform(const std::vector<CT>& in, bool inverse)
         if (b > 0)
           for (CT& v : xb) free_ct(v);
       }
+      scratch_release(hm);
     }
     // giant rotations, then the sum over giant steps
     std::vector<CT> rin;

@@ -445,6 +445,47 @@ def test_key_switch_error_bound(tiny):
             assert np.abs(e.astype(np.float64)).max() < 2**20
 
 
+def test_hoisted_rotation_decrypts_to_automorphism(tiny):
+    """Hoisted rotations (one ModUp of c1, then X -> X^g on every raised digit
+    before each inner product) decrypt to sigma_g(m) plus a key-switch error:
+    exact big-integer decryption against an automorphism written here, for
+    several steps sharing one ModUp, at the top level and at level 2.  Step 0
+    is a copy; the regular RotL lands within the same bound."""
+    o = tiny
+    s = o.secret()
+    D = 2.0**40
+    x = np.random.default_rng(11).uniform(-1, 1, o.slots)
+    steps = [0, 1, 3, 5, o.slots - 1]
+    n = o.n
+
+    def sigma(m, g):
+        out = [0] * n
+        for i, v in enumerate(m):
+            j = (i * g) % (2 * n)
+            if j < n:
+                out[j] = v
+            else:
+                out[j - n] = -v
+        return out
+
+    for level in [o.n_q - 1, 2]:
+        ct = o.lower(o.encrypt(o.encode(x, D), D, 5), level)
+        m = _dec_big(o, ct.export(), s, level)
+        outs = o.rotate_hoisted(ct, steps)
+        assert len(outs) == len(steps)
+        for st, r in zip(steps, outs):
+            assert r.level == level and r.scale == ct.scale
+            if st == 0:
+                assert np.array_equal(r.export(), ct.export())
+                continue
+            want = sigma(m, o.galois_elt(st))
+            got = _dec_big(o, r.export(), s, level)
+            assert max(abs(a - b) for a, b in zip(got, want)) < 2**20
+            reg = _dec_big(o, o.rotate(ct, st).export(), s, level)
+            assert max(abs(a - b) for a, b in zip(reg, want)) < 2**20
+            assert np.abs(o.decrypt_decode(r, 16) - np.roll(x, -st)[:16]).max() < 1e-8
+
+
 def test_refresh_preserves_message(tiny):
     """The refresh stand-in re-encrypts the exact message: decryptions differ by a fresh e, |e| <= 21."""
     o = tiny
