@@ -236,7 +236,18 @@ int secpe_eval_argmax_phoenix(secpe_ctx* ctx, const secpe_key_owner* owner, cons
    angles); recombination; SlotToCoeff with 2^ratio / (2 pi) folded in.  The
    output carries scale 2^log_scale at level
      n_q - 1 - (2 groups + log2(deg + 1) + 1 + r).
-   Inputs need |slot value| <= 1 (the sine is read as its argument). ---- */
+   Inputs need |slot value| <= 1 (the sine is read as its argument).
+
+   The sparse-slot bootstrap (sparse_slots = n > 0) keeps slots [0, n) only,
+   for ciphertexts whose other slots are never read again (the single-query
+   Argmax reads slots [0, 2C') after Eq. 5): the mask of slots [0, n) takes
+   the place of the scale-down constant; a trace at level 0 (sum of RotL by
+   n, 2n, ..., N/4) makes the message n-periodic; after ModRaise the trace
+   again; the n-slot special FFT as CoeffToSlot, its last group writing
+   [w, 0] with period 2n; [re, im] = (w + conj w) + RotR(-i (w - conj w), n)
+   so that ONE EvalMod serves both parts; the n-slot SlotToCoeff of
+   re + i im.  Same depth and output level as the full pipeline; the
+   output repeats slots [0, n) with period n. ---- */
 typedef struct secpe_boot_params {
   int secret_h;   /* > 0: sparse secret, coefficient nonzero w.p. h / N (0: uniform ternary) */
   int K;          /* EvalMod range |t / q_0| <= K + 1 (bound on the ModRaise overflow) */
@@ -245,6 +256,9 @@ typedef struct secpe_boot_params {
   int ratio;      /* log2(q_0 / T_b) */
   int groups;     /* levels (merged stage groups) of each linear transform */
   int refresh;    /* 1: every refresh of an evaluation is a bootstrap */
+  int sparse_slots; /* 0, or n: a power of two, 2n <= N/2, log2 n >= groups.
+                       Evaluations whose refresh reads at most n slots
+                       afterwards bootstrap sparsely. */
 } secpe_boot_params;
 /* the step value secpe_keygen takes as the conjugation key (X -> X^(2N-1)) */
 #define SECPE_STEP_CONJUGATE INT64_MIN
@@ -266,8 +280,14 @@ int secpe_boot_setup(secpe_ctx* ctx, void* buf_dev, size_t bytes);
    do the workspace sizes of evaluations that refresh by bootstrapping. */
 size_t secpe_bootstrap_workspace_bytes(secpe_ctx* ctx, int n);
 int secpe_bootstrap(secpe_ctx* ctx, int n, const secpe_ct* in, void* ws_dev, size_t ws_bytes, secpe_ct* out);
+/* The sparse-slot bootstrap of n ciphertexts (sparse_slots set, else
+   SECPE_EINVAL): slots [0, sparse_slots) of each input, repeated with that
+   period over the N/2 slots of the output.  Same workspace size. */
+int secpe_bootstrap_sparse(secpe_ctx* ctx, int n, const secpe_ct* in, void* ws_dev, size_t ws_bytes,
+                           secpe_ct* out);
 /* Single steps, for parity checks: step 0 ModRaise (level-0 input), 1
-   CoeffToSlot, 2 SlotToCoeff, 3 EvalMod, 4 slots times i, 5 slots times -i.
+   CoeffToSlot, 2 SlotToCoeff, 3 EvalMod, 4 slots times i, 5 slots times -i,
+   6 the sparse-slot CoeffToSlot, 7 the sparse-slot SlotToCoeff.
    ws sized by secpe_bootstrap_workspace_bytes(ctx, 1). */
 int secpe_op_boot_step(secpe_ctx* ctx, int step, const secpe_ct* a, void* ws_dev, size_t ws_bytes, secpe_ct* out);
 

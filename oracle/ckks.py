@@ -87,6 +87,10 @@ def _load():
         "orc_mul_monomial_half": (vp, [vp, vp, ci]),
         "orc_eval_mod": (vp, [vp, vp]),
         "orc_bootstrap": (vp, [vp, vp]),
+        "orc_bootstrap_sparse": (vp, [vp, vp]),
+        "orc_set_boot_sparse": (ci, [vp, ci]),
+        "orc_boot_sparse_apply": (None, [vp, ci, P(dbl), P(dbl), P(dbl), P(dbl)]),
+        "orc_boot_transform_sparse": (vp, [vp, vp, ci]),
         "orc_boot_transform": (vp, [vp, vp, ci]),
     }
     for name, (res, args) in sig.items():
@@ -158,6 +162,8 @@ class Oracle:
             o.set_boot(params.get("h", 0), params.get("boot_K", 0), params.get("boot_r", 0),
                        params.get("boot_deg", 1), params.get("boot_ratio", 1), params.get("boot_groups", 1),
                        params.get("boot_refresh", 0))
+            if params.get("boot_sparse", 0) and o.boot_out_level() >= 0:
+                o.set_boot_sparse(params["boot_sparse"])
         return o
 
     # -- bootstrapping -------------------------------------------------------
@@ -169,6 +175,12 @@ class Oracle:
         if mode and out >= 0:
             self.refresh_level = out
         return out
+
+    def set_boot_sparse(self, n):
+        """Slots [0, n) kept by the sparse-slot bootstrap (0: off); after set_boot."""
+        if self.lib.orc_set_boot_sparse(self.h, int(n)) != 0:
+            raise ValueError(f"sparse-slot bootstrap cannot take n = {n}")
+        self.boot_sparse = int(n)
 
     def boot_out_level(self):
         return self.lib.orc_boot_out_level(self.h)
@@ -192,6 +204,26 @@ class Oracle:
         self.lib.orc_boot_group_apply(self.h, int(inverse), int(g), _p(vr, C.c_double), _p(vi, C.c_double),
                                       _p(ore, C.c_double), _p(oim, C.c_double))
         return ore + 1j * oim
+
+    def boot_sparse_apply(self, inverse, v):
+        """The sparse-slot CoeffToSlot (1) or SlotToCoeff (0) as a slot map on one
+        2n period (v: 2n complex values)."""
+        v = np.asarray(v, dtype=np.complex128)
+        vr = np.ascontiguousarray(v.real)
+        vi = np.ascontiguousarray(v.imag)
+        ore = np.zeros(len(v))
+        oim = np.zeros(len(v))
+        self.lib.orc_boot_sparse_apply(self.h, int(inverse), _p(vr, C.c_double), _p(vi, C.c_double),
+                                       _p(ore, C.c_double), _p(oim, C.c_double))
+        return ore + 1j * oim
+
+    def boot_transform_sparse(self, ct, inverse):
+        """The sparse-slot CoeffToSlot (1) or SlotToCoeff (0), groups - 1 levels."""
+        return self._wrap(self.lib.orc_boot_transform_sparse(self.h, ct.h, int(inverse)))
+
+    def bootstrap_sparse(self, ct):
+        """Bootstrap keeping slots [0, n) (n = boot_sparse), repeated with period n."""
+        return self._wrap(self.lib.orc_bootstrap_sparse(self.h, ct.h))
 
     def mod_raise(self, ct):
         return self._wrap(self.lib.orc_mod_raise(self.h, ct.h))

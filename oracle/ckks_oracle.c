@@ -148,7 +148,7 @@ static uint64_t sample_uniform(uint64_t key, uint64_t i, uint64_t q) {
 /* ------------------------------------------------------------------------- */
 /* the encoded plaintexts of one linear-transform group at one plaintext scale */
 struct boot_pt {
-  int inverse, g;
+  int inverse, g, ns;   /* ns: slots of the transform (N/2, or the sparse n) */
   double pscale;
   int64_t** m;          /* [slot offset] encoded (pre-rotated) diagonal, or NULL */
   struct boot_pt* next;
@@ -173,6 +173,7 @@ typedef struct {
   int textbook;         /* 1: every product relinearised, then rescaled (no merged op) */
   int boot_K, boot_r, boot_deg, boot_ratio, boot_groups;
   int boot_out_level;   /* level of a bootstrapped ciphertext (-1: not set up) */
+  int boot_sparse;      /* n > 0: slots [0, n) kept by the sparse-slot bootstrap */
   double* boot_cheb;    /* Chebyshev coefficients c_0..c_deg of the scaled cosine */
   struct boot_pt* boot_cache; /* encoded diagonals, by (direction, group, scale) */
   uint64_t* mod;        /* n_q chain primes, then n_p special primes */
@@ -1461,14 +1462,17 @@ typedef struct {
   uint64_t next;
   uint64_t stride;
   uint64_t base;
+  int span;             /* > 0: only slots [0, span) matter from here on */
 } refresher;
 
 static orc_ct* bootstrap(orc_ctx* c, const orc_ct* x);
+static orc_ct* bootstrap_sparse(orc_ctx* c, const orc_ct* x);
 static orc_ct* maybe_refresh(orc_ctx* c, orc_ct* x, int need, refresher* rf) {
   if (x->level - need >= c->min_level) return x;
   if (c->refresh_level - need < c->min_level) die("modulus chain too short for one unit");
   if (c->boot_mode) {
-    orc_ct* b = bootstrap(c, x);
+    int sparse = c->boot_sparse > 0 && rf->span > 0 && rf->span <= c->boot_sparse;
+    orc_ct* b = sparse ? bootstrap_sparse(c, x) : bootstrap(c, x);
     ct_free(x);
     return b;
   }
@@ -1643,7 +1647,9 @@ static orc_ct* eval_argmax_core(orc_ctx* c, const orc_ct* ct_in, int lk, int lc,
   double delta = ldexp(1.0, c->log_scale);
   int cp = 1 << lc;
   int slots = c->n / 2;
-  refresher rf = {refresh_seed, 0, 1, 0};
+  /* after Eq. 5 only slots [0, 2C') of a single query's ciphertext are read
+     again (the duplicate of line 2 and the QuickMax windows stay inside) */
+  refresher rf = {refresh_seed, 0, 1, 0, packed ? 0 : 2 * cp};
   orc_ct* y = ct_copy(c, ct_in, ct_in->level);
   for (int i = 0; i < lk; ++i) {
     orc_ct* r = op_rotate(c, y, (int64_t)cp << i);
@@ -1727,7 +1733,7 @@ ORC_API void* orc_eval_argmax_phoenix(void* h, const void* ct_in, int K, int C, 
   int lk = ilog2_ceil(K), cp = 1 << ilog2_ceil(C);
   int slots = c->n / 2;
   if ((int64_t)(1 << lk) * cp > slots || 2 * C > slots) die("phoenix path: shape exceeds the slot count");
-  refresher rf0 = {refresh_seed, 0, PHOENIX_STRIDE, 0};
+  refresher rf0 = {refresh_seed, 0, PHOENIX_STRIDE, 0, 0};
   orc_ct* y = ct_copy(c, (const orc_ct*)ct_in, ((const orc_ct*)ct_in)->level);
   for (int i = 0; i < lk; ++i) {
     orc_ct* r = op_rotate(c, y, (int64_t)cp << i);
@@ -1748,7 +1754,7 @@ ORC_API void* orc_eval_argmax_phoenix(void* h, const void* ct_in, int K, int C, 
   ct_free(r); ct_free(yn);
   orc_ct* s = NULL;
   for (int i = 1; i < C; ++i) {
-    refresher rfi = {refresh_seed, 0, PHOENIX_STRIDE, (uint64_t)i};
+    refresher rfi = {refresh_seed, 0, PHOENIX_STRIDE, (uint64_t)i, 0};
     orc_ct* ri = op_rotate(c, yd, i);
     orc_ct* di = op_add(c, yd, ri, 1);
     orc_ct* si = eval_sign(c, di, 1.0, delta, 0, &rfi, NULL);
@@ -1852,16 +1858,18 @@ static cq* dm_at(diagmat* m, int off) {
   if (!m->d[off]) m->d[off] = (cq*)xcalloc(m->S, sizeof(cq));
   return m->d[off];
 }
-/* one radix-2 stage on blocks of m slots, D_m[j] = zeta^((S/m) 5^j):
+/* one radix-2 stage on blocks of m slots, D_m[j] = zeta^((N/2m) 5^j):
    forward  out[r] = in[r] + D[r] in[r+h],  out[r+h] = in[r] - D[r] in[r+h]   (h = m/2)
-   inverse  out[r] = (in[r] + in[r+h]) / 2, out[r+h] = conj(D[r]) (in[r] - in[r+h]) / 2 */
-static diagmat dm_stage(orc_ctx* c, int m, int inverse) {
-  int S = c->n / 2, h = m / 2;
+   inverse  out[r] = (in[r] + in[r+h]) / 2, out[r+h] = conj(D[r]) (in[r] - in[r+h]) / 2
+   as a map on S = ns slots.  The stages of the n-slot special FFT (root
+   zeta^(N/2n) of order 4n) have the same twiddles zeta^((N/2m) 5^j). */
+static diagmat dm_stage(orc_ctx* c, int m, int inverse, int ns) {
+  int S = ns, h = m / 2;
   diagmat A = dm_new(S);
   for (int p = 0; p < S; ++p) {
     int r = p % m;
     int j = r < h ? r : r - h;
-    cq D = zeta_pow(c, (uint64_t)(S / m) * c->rot_group[j]);
+    cq D = zeta_pow(c, (uint64_t)(c->n / 2 / m) * c->rot_group[j]);
     if (!inverse) {
       if (r < h) {
         dm_at(&A, 0)[p] = (cq){1, 0};
@@ -1917,35 +1925,40 @@ static int64_t floor_div(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a +
 
 typedef struct {
   int inverse, level;           /* level of the input ciphertext */
-  int delta, n1, E;             /* offsets are multiples of delta; E = S / delta */
+  int ns;                       /* slots of the transform: N/2, or n (sparse) */
+  int delta, n1, E;             /* offsets are multiples of delta; E = ns / delta */
   diagmat M;
 } boot_group;
 
-static boot_group boot_make_group(orc_ctx* c, int inverse, int g, int level) {
-  int S = c->n / 2, L = 0;
+/* group g of 'groups' over an ns-slot transform (ns = N/2: the full one) */
+static boot_group boot_make_group_ns(orc_ctx* c, int inverse, int g, int level, int ns, int groups) {
+  int S = ns, L = 0;
   while ((1 << L) < S) ++L;
   int first = 0;
-  for (int i = 0; i < g; ++i) first += boot_group_len(L, c->boot_groups, i);
-  int len = boot_group_len(L, c->boot_groups, g);
+  for (int i = 0; i < g; ++i) first += boot_group_len(L, groups, i);
+  int len = boot_group_len(L, groups, g);
   boot_group G;
   G.inverse = inverse;
   G.level = level;
+  G.ns = ns;
   int mmin = S;
-  diagmat M = dm_stage(c, boot_stage_m(L, inverse, first), inverse);
+  diagmat M = dm_stage(c, boot_stage_m(L, inverse, first), inverse, ns);
   if (boot_stage_m(L, inverse, first) < mmin) mmin = boot_stage_m(L, inverse, first);
   for (int i = 1; i < len; ++i) {
     int m = boot_stage_m(L, inverse, first + i);
     if (m < mmin) mmin = m;
-    diagmat St = dm_stage(c, m, inverse);
+    diagmat St = dm_stage(c, m, inverse, ns);
     diagmat R = dm_mul(&St, &M);
     dm_free(&St);
     dm_free(&M);
     M = R;
   }
-  /* constants folded into the first group applied */
+  /* constants folded into the first group applied; a sparse CoeffToSlot
+     also undoes the factor N/(2n) of the trace before it */
   if (g == 0) {
     __float128 k = inverse ? 1.0Q / (2.0Q * (__float128)(c->boot_K + 1))
                            : ldexpq(1.0Q, c->boot_ratio) / (2.0Q * M_PIq);
+    if (inverse) k = k * (__float128)ns / (__float128)(c->n / 2);
     for (int d = 0; d < S; ++d)
       if (M.d[d])
         for (int p = 0; p < S; ++p) { M.d[d][p].re *= k; M.d[d][p].im *= k; }
@@ -1955,6 +1968,9 @@ static boot_group boot_make_group(orc_ctx* c, int inverse, int g, int level) {
   G.E = S / G.delta;
   G.n1 = boot_n1(len, G.E);
   return G;
+}
+static boot_group boot_make_group(orc_ctx* c, int inverse, int g, int level) {
+  return boot_make_group_ns(c, inverse, g, level, c->n / 2, c->boot_groups);
 }
 
 /* centred multiple e of delta for slot offset d: e in [-E/2, E/2) */
@@ -1968,7 +1984,7 @@ static int64_t boot_e(const boot_group* G, int d) {
    pt_{G,b} = the diagonal of e = n1 G + b rotated right by delta n1 G, encoded at
    p = T q_l / s; the sum is rescaled once and carries scale T */
 static orc_ct* boot_apply_group(orc_ctx* c, const boot_group* G, int g, const orc_ct* x, double target) {
-  int S = c->n / 2, n = c->n, l = x->level;
+  int S = G->ns, SF = c->n / 2, n = c->n, l = x->level;
   if (l != G->level) die("boot group: level mismatch");
   double ql = (double)c->mod[l];
   double pscale = target * ql;
@@ -2005,18 +2021,20 @@ static orc_ct* boot_apply_group(orc_ctx* c, const boot_group* G, int g, const or
   orc_ct* out = NULL;
   /* the encoded diagonals are kept per (direction, group, plaintext scale) */
   struct boot_pt* cache = c->boot_cache;
-  while (cache && !(cache->inverse == G->inverse && cache->g == g && cache->pscale == pscale)) cache = cache->next;
+  while (cache && !(cache->inverse == G->inverse && cache->g == g && cache->ns == S && cache->pscale == pscale))
+    cache = cache->next;
   if (!cache) {
     cache = (struct boot_pt*)xcalloc(1, sizeof(struct boot_pt));
     cache->inverse = G->inverse;
     cache->g = g;
+    cache->ns = S;
     cache->pscale = pscale;
-    cache->m = (int64_t**)xcalloc(S, sizeof(int64_t*));
+    cache->m = (int64_t**)xcalloc(SF, sizeof(int64_t*));
     cache->next = c->boot_cache;
     c->boot_cache = cache;
   }
-  double* re = (double*)xcalloc(S, sizeof(double));
-  double* im = (double*)xcalloc(S, sizeof(double));
+  double* re = (double*)xcalloc(SF, sizeof(double));
+  double* im = (double*)xcalloc(SF, sizeof(double));
   int64_t* m = (int64_t*)xcalloc(n, 8);
   uint64_t* mp = (uint64_t*)xcalloc(n, 8);
   uint64_t* tmp = (uint64_t*)xcalloc(n, 8);
@@ -2029,14 +2047,15 @@ static orc_ct* boot_apply_group(orc_ctx* c, const boot_group* G, int g, const or
       if (floor_div(e, G->n1) != gg) continue;
       int b = (int)(e - G->n1 * gg);
       if (!cache->m[d]) {
+        /* the diagonal repeats with period ns over the N/2 slots */
         int64_t shift = ((G->delta * G->n1 * gg) % S + S) % S;
-        for (int p = 0; p < S; ++p) {
-          cq v = G->M.d[d][(p - shift + S) % S];
+        for (int p = 0; p < SF; ++p) {
+          cq v = G->M.d[d][((int64_t)(p % S) - shift + S) % S];
           re[p] = (double)v.re;
           im[p] = (double)v.im;
         }
         cache->m[d] = (int64_t*)xcalloc(n, 8);
-        encode_complex(c, re, im, S, pscale, cache->m[d]);
+        encode_complex(c, re, im, SF, pscale, cache->m[d]);
       }
       memcpy(m, cache->m[d], 8 * (size_t)n);
       if (!inner) inner = ct_new(c, l, x->scale * pscale);
@@ -2069,22 +2088,21 @@ static orc_ct* boot_apply_group(orc_ctx* c, const boot_group* G, int g, const or
   return out;
 }
 
-/* rotation steps one bootstrap uses (CONJ_STEP for the conjugation) */
-static int boot_steps(orc_ctx* c, int64_t* out, int cap) {
-  int S = c->n / 2, L = 0, k = 0;
-  while ((1 << L) < S) ++L;
-  int64_t* st = (int64_t*)xcalloc(4096, sizeof(int64_t));
+/* baby and giant steps of every group of an ns-slot transform (S-slot steps) */
+static int boot_transform_steps(orc_ctx* c, int ns, int groups, int64_t* st, int k) {
+  int S = c->n / 2, L = 0;
+  while ((1 << L) < ns) ++L;
   for (int inv = 0; inv < 2; ++inv)
-    for (int g = 0; g < c->boot_groups; ++g) {
+    for (int g = 0; g < groups; ++g) {
       int first = 0;
-      for (int i = 0; i < g; ++i) first += boot_group_len(L, c->boot_groups, i);
-      int len = boot_group_len(L, c->boot_groups, g);
-      int mmin = S;
+      for (int i = 0; i < g; ++i) first += boot_group_len(L, groups, i);
+      int len = boot_group_len(L, groups, g);
+      int mmin = ns;
       for (int i = 0; i < len; ++i) {
         int mm = boot_stage_m(L, inv, first + i);
         if (mm < mmin) mmin = mm;
       }
-      int delta = mmin / 2, E = S / delta, n1 = boot_n1(len, E);
+      int delta = mmin / 2, E = ns / delta, n1 = boot_n1(len, E);
       for (int b = 1; b < n1; ++b) st[k++] = (int64_t)delta * b % S;
       /* the group's offsets are delta e, |e| <= 2^len - 1, centred in [-E/2, E/2) */
       int64_t span = ((int64_t)1 << len) - 1;
@@ -2093,6 +2111,33 @@ static int boot_steps(orc_ctx* c, int64_t* out, int cap) {
       for (int64_t gg = gmin; gg <= gmax; ++gg)
         if (gg) st[k++] = (((int64_t)delta * n1 * gg) % S + S) % S;
     }
+  return k;
+}
+
+static boot_group boot_make_group_sparse(orc_ctx* c, int inverse, int g, int level);
+
+/* rotation steps one bootstrap uses (CONJ_STEP for the conjugation), and the
+   sparse-slot bootstrap's when it is set */
+static int boot_steps(orc_ctx* c, int64_t* out, int cap) {
+  int S = c->n / 2, k = 0;
+  int64_t* st = (int64_t*)xcalloc(8192, sizeof(int64_t));
+  k = boot_transform_steps(c, S, c->boot_groups, st, k);
+  if (c->boot_sparse > 0) {
+    /* the sparse groups' baby steps and the giant steps of the offsets present */
+    for (int inv = 0; inv < 2; ++inv)
+      for (int g = 0; g < c->boot_groups; ++g) {
+        boot_group G = boot_make_group_sparse(c, inv, g, 0);
+        for (int b = 1; b < G.n1; ++b) st[k++] = (int64_t)G.delta * b % S;
+        for (int d = 0; d < G.ns; ++d) {
+          if (!G.M.d[d]) continue;
+          int64_t gg = floor_div(boot_e(&G, d), G.n1);
+          if (gg) st[k++] = (((int64_t)G.delta * G.n1 * gg) % S + S) % S;
+        }
+        dm_free(&G.M);
+      }
+    for (int64_t r = c->boot_sparse; r < S; r *= 2) st[k++] = r;
+    st[k++] = S - c->boot_sparse;
+  }
   /* sort, unique, drop multiples of S */
   for (int i = 1; i < k; ++i)
     for (int j = i; j > 0 && st[j - 1] > st[j]; --j) { int64_t t = st[j]; st[j] = st[j - 1]; st[j - 1] = t; }
@@ -2350,21 +2395,24 @@ static int boot_levels(orc_ctx* c) {
 /* output scale of group g: CoeffToSlot keeps 2^5 Delta until its last group
    (its first groups carry the large ModRaise overflow, so their plaintexts
    get the larger scale), everything else Delta */
-static double boot_group_target(orc_ctx* c, int inverse, int g) {
-  if (inverse && g < c->boot_groups - 1) return ldexp(1.0, c->log_scale + 5);
+static double boot_group_target(orc_ctx* c, int inverse, int g, int groups) {
+  if (inverse && g < groups - 1) return ldexp(1.0, c->log_scale + 5);
   return ldexp(1.0, c->log_scale);
 }
-static orc_ct* boot_transform(orc_ctx* c, const orc_ct* x, int inverse) {
+static orc_ct* boot_transform_ns(orc_ctx* c, const orc_ct* x, int inverse, int ns, int groups) {
   orc_ct* y = ct_copy(c, x, x->level);
   int l0 = x->level;
-  for (int g = 0; g < c->boot_groups; ++g) {
-    boot_group G = boot_make_group(c, inverse, g, l0 - g);
-    orc_ct* t = boot_apply_group(c, &G, g, y, boot_group_target(c, inverse, g));
+  for (int g = 0; g < groups; ++g) {
+    boot_group G = boot_make_group_ns(c, inverse, g, l0 - g, ns, groups);
+    orc_ct* t = boot_apply_group(c, &G, g, y, boot_group_target(c, inverse, g, groups));
     dm_free(&G.M);
     ct_free(y);
     y = t;
   }
   return y;
+}
+static orc_ct* boot_transform(orc_ctx* c, const orc_ct* x, int inverse) {
+  return boot_transform_ns(c, x, inverse, c->n / 2, c->boot_groups);
 }
 static orc_ct* coeff_to_slot(orc_ctx* c, const orc_ct* x) { return boot_transform(c, x, 1); }
 static orc_ct* slot_to_coeff(orc_ctx* c, const orc_ct* x) { return boot_transform(c, x, 0); }
@@ -2406,12 +2454,155 @@ static orc_ct* bootstrap(orc_ctx* c, const orc_ct* x) {
 }
 ORC_API void* orc_bootstrap(void* h, const void* x) { return bootstrap((orc_ctx*)h, (const orc_ct*)x); }
 
+/* x + RotL(x, n) + RotL(x, 2n) + ... over every multiple of n: the trace onto
+   the subring Z[X^(N/2n)], whose slot vectors repeat with period n */
+static orc_ct* boot_subsum(orc_ctx* c, orc_ct* x, int n) {
+  for (int64_t r = n; r < c->n / 2; r *= 2) {
+    orc_ct* y = op_rotate(c, x, r);
+    orc_ct* z = op_add(c, x, y, 0);
+    ct_free(x);
+    ct_free(y);
+    x = z;
+  }
+  return x;
+}
+
+/* Group g of the sparse-slot transforms (n = boot_sparse slots, 'groups'
+   groups like the full ones), on n-periodic slot vectors, except:
+     the last CoeffToSlot group writes [w, 0] with period 2n: its diagonals
+       are those of the n-slot map on the lower n slots of each 2n period
+       and zero on the upper ones;
+     the first SlotToCoeff group reads u = [a, b] with period 2n and applies
+       the n-slot map to a + i b: each n-slot diagonal d becomes the 2n-slot
+       diagonals d and d + n, whose entry at p is D[d][p mod n] times 1 or i
+       as the slot it reads lies in the lower or the upper half. */
+static boot_group boot_make_group_sparse(orc_ctx* c, int inverse, int g, int level) {
+  int n = c->boot_sparse, groups = c->boot_groups;
+  boot_group G = boot_make_group_ns(c, inverse, g, level, n, groups);
+  int mask = inverse && g == groups - 1, join = !inverse && g == 0;
+  if (!mask && !join) return G;
+  int n2 = 2 * n;
+  diagmat M2 = dm_new(n2);
+  for (int d = 0; d < n; ++d) {
+    if (!G.M.d[d]) continue;
+    for (int p = 0; p < n2; ++p) {
+      cq v = G.M.d[d][p % n];
+      if (mask) {
+        /* offset d or d - n read the same slot of an n-periodic input: keep
+           the centred one, so the offsets stay those of the n-slot map */
+        int off = d < n / 2 ? d : d + n;
+        if (p < n) dm_at(&M2, off)[p] = v;
+        else dm_at(&M2, off);
+      } else {
+        for (int k = 0; k < 2; ++k) {
+          int off = (d + k * n) % n2;
+          int r = (p + off) % n2;
+          cq w = r < n ? v : (cq){-v.im, v.re};   /* times i on the upper half */
+          cq* dst = dm_at(&M2, off);
+          dst[p].re += w.re;
+          dst[p].im += w.im;
+        }
+      }
+    }
+  }
+  dm_free(&G.M);
+  G.M = M2;
+  G.ns = n2;
+  G.E = n2 / G.delta;
+  return G;
+}
+
+/* the sparse-slot CoeffToSlot (inverse = 1) or SlotToCoeff: every group, one level each */
+static orc_ct* boot_transform_sparse(orc_ctx* c, const orc_ct* x, int inverse) {
+  orc_ct* y = ct_copy(c, x, x->level);
+  int l0 = x->level;
+  for (int g = 0; g < c->boot_groups; ++g) {
+    boot_group G = boot_make_group_sparse(c, inverse, g, l0 - g);
+    orc_ct* t = boot_apply_group(c, &G, g, y, boot_group_target(c, inverse, g, c->boot_groups));
+    dm_free(&G.M);
+    ct_free(y);
+    y = t;
+  }
+  return y;
+}
+
+/* Sparse-slot bootstrap (n = boot_sparse slots, 2n <= N/2; the trace and the
+   n-slot transforms of Cheon, Han, Kim, Kim, Song 2018): only slots [0, n) of
+   the input count, and the output repeats them with period n.
+     scale-down   the constant of the full pipeline becomes the mask of
+                  slots [0, n), at the same level;
+     trace        at level 0, the sum over rotations by multiples of n makes
+                  the message a polynomial in Y = X^(N/2n) (slots of period
+                  n), so that it is unchanged by the trace after ModRaise;
+     ModRaise     t = m + q_0 I; the trace again (log2(N/2n) rotations)
+                  leaves (N/2n) (m + q_0 I'), I' the part of I in Z[Y];
+     CoeffToSlot  the n-slot special FFT (root zeta^(N/2n) of order 4n) with
+                  n/(N/2) folded into its first group; the last group writes
+                  [w, 0] with period 2n;
+     split        [re, 0] = w + conj(w), [im, 0] = -i (w - conj(w)), and
+                  u = [re, 0] + RotR([im, 0], n) = [re, im]: real parts in
+                  slots [0, n), imaginary parts in [n, 2n) of each period;
+     EvalMod      as in the full pipeline, once for both parts;
+     SlotToCoeff  the n-slot transform of re + i im, the first group
+                  reading the two halves.
+   Same depth as the full pipeline, so the same output level. */
+static orc_ct* bootstrap_sparse(orc_ctx* c, const orc_ct* x) {
+  int ns = c->boot_sparse, S = c->n / 2;
+  if (c->boot_out_level < 0 || ns <= 0) die("bootstrap_sparse: not set up");
+  if (x->level < 1) die("bootstrap: input needs level >= 1");
+  double tb = ldexp((double)c->mod[0], -c->boot_ratio);
+  double* mask = (double*)xcalloc(ns, sizeof(double));
+  for (int j = 0; j < ns; ++j) mask[j] = 1.0;
+  orc_ct* x1 = ct_copy(c, x, 1);
+  orc_ct* x0 = op_mul_plain(c, x1, mask, ns, tb);
+  ct_free(x1);
+  free(mask);
+  x0 = boot_subsum(c, x0, ns);
+  orc_ct* y0 = mod_raise(c, x0);
+  ct_free(x0);
+  y0 = boot_subsum(c, y0, ns);
+  orc_ct* w = boot_transform_sparse(c, y0, 1);
+  ct_free(y0);
+  orc_ct* wc = op_rotate(c, w, CONJ_STEP);
+  orc_ct* re = op_add(c, w, wc, 0);
+  orc_ct* df = op_add(c, w, wc, 1);
+  orc_ct* im = op_mul_monomial_half(c, df, 1);
+  ct_free(w); ct_free(wc); ct_free(df);
+  orc_ct* imr = op_rotate(c, im, (int64_t)S - ns);
+  orc_ct* u = op_add(c, re, imr, 0);
+  ct_free(re); ct_free(im); ct_free(imr);
+  orc_ct* e = eval_mod(c, u);
+  ct_free(u);
+  orc_ct* out = boot_transform_sparse(c, e, 0);
+  ct_free(e);
+  if (out->level != c->boot_out_level) die("bootstrap_sparse: level plan mismatch");
+  c->counters[CNT_REFRESH]++;
+  return out;
+}
+ORC_API void* orc_bootstrap_sparse(void* h, const void* x) {
+  return bootstrap_sparse((orc_ctx*)h, (const orc_ct*)x);
+}
+/* the sparse-slot bootstrap keeps slots [0, n): n a power of two with
+   2n <= N/2 and at least one radix-2 stage per group; 0 turns it off.
+   Returns 0, or -1 for an n it cannot take. */
+ORC_API int orc_set_boot_sparse(void* h, int n) {
+  orc_ctx* c = (orc_ctx*)h;
+  c->boot_sparse = 0;
+  if (n == 0) return 0;
+  int L = 0;
+  while ((1 << L) < n) ++L;
+  if (c->boot_out_level < 0 || n < 0 || (n & (n - 1)) || 2 * n > c->n / 2 || L < c->boot_groups) return -1;
+  c->boot_sparse = n;
+  return 0;
+}
+
 /* bootstrapping parameters; call before keygen (the secret weight h is used
    there).  mode 1 makes every refresh a bootstrap.  Returns the level of a
    bootstrapped ciphertext, or -1 when the chain is too short. */
 ORC_API int orc_set_boot(void* h, int secret_h, int K, int r, int deg, int ratio, int groups, int mode) {
   orc_ctx* c = (orc_ctx*)h;
   c->secret_h = secret_h;
+  c->boot_sparse = 0;
   if (c->boot_mode) c->refresh_level = c->refresh_level_set;
   if (K <= 0) { c->boot_out_level = -1; c->boot_mode = 0; return -1; }
   if (deg < 1 || ((deg + 1) & deg) || r < 0 || groups < 1 || ratio < 1) die("bad bootstrapping parameters");
@@ -2447,6 +2638,37 @@ ORC_API void orc_boot_group_apply(void* h, int inverse, int g, const double* vre
     oim[p] = (double)ai;
   }
   dm_free(&G.M);
+}
+/* the sparse-slot CoeffToSlot (inverse = 1) or SlotToCoeff, every group, as
+   slot maps applied to v (2n complex values: one 2n period of the slots) */
+ORC_API void orc_boot_sparse_apply(void* h, int inverse, const double* vre, const double* vim, double* ore,
+                                   double* oim) {
+  orc_ctx* c = (orc_ctx*)h;
+  int n2 = 2 * c->boot_sparse;
+  cq* v = (cq*)xcalloc(n2, sizeof(cq));
+  cq* o = (cq*)xcalloc(n2, sizeof(cq));
+  for (int p = 0; p < n2; ++p) v[p] = (cq){vre[p], vim[p]};
+  for (int g = 0; g < c->boot_groups; ++g) {
+    boot_group G = boot_make_group_sparse(c, inverse, g, 0);
+    for (int p = 0; p < n2; ++p) {
+      __float128 ar = 0, ai = 0;
+      for (int d = 0; d < G.ns; ++d) {
+        if (!G.M.d[d]) continue;
+        cq t = cq_mul(G.M.d[d][p % G.ns], v[(p + d) % n2]);
+        ar += t.re;
+        ai += t.im;
+      }
+      o[p] = (cq){ar, ai};
+    }
+    memcpy(v, o, sizeof(cq) * (size_t)n2);
+    dm_free(&G.M);
+  }
+  for (int p = 0; p < n2; ++p) { ore[p] = (double)v[p].re; oim[p] = (double)v[p].im; }
+  free(v);
+  free(o);
+}
+ORC_API void* orc_boot_transform_sparse(void* h, const void* x, int inverse) {
+  return boot_transform_sparse((orc_ctx*)h, (const orc_ct*)x, inverse);
 }
 ORC_API void* orc_mod_raise(void* h, const void* x) { return mod_raise((orc_ctx*)h, (const orc_ct*)x); }
 ORC_API void* orc_mul_monomial_half(void* h, const void* x, int neg) {

@@ -1676,14 +1676,15 @@ extern "C" int secpe_server_step(secpe_server* s, int cap, int* n_done, uint64_t
 // ---------------------------------------------------------------------------
 static int64_t floor_div64(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
-// levels, input scales and plaintext scales of every group (no slot vectors)
-static void boot_plan(Ctx& c) {
+// levels, input scales and plaintext scales of every group (no slot vectors);
+// the sparse-slot transforms (log_ns = log2 n) have the same levels and scales
+static void boot_plan_groups(Ctx& c, int log_ns, std::vector<BootGroup>& cts, std::vector<BootGroup>& stc) {
   const double delta = ldexp(1.0, c.log_scale);
   const int top = c.n_q - 1;
   int k = 0;
   while ((1 << k) < c.boot_deg + 1) ++k;
-  c.boot_cts.clear();
-  c.boot_stc.clear();
+  cts.clear();
+  stc.clear();
   for (int inv = 1; inv >= 0; --inv) {
     int lvl0 = top;
     double s0 = (double)c.mod[0];
@@ -1697,11 +1698,13 @@ static void boot_plan(Ctx& c) {
         --lvl0;
       }
     }
+    std::vector<BootGroup>& out = inv ? cts : stc;
     for (int g = 0; g < c.boot_groups; ++g) {
-      BootGroupTable t = boot_group_geometry(c.log_n, c.boot_groups, inv, g);
+      BootGroupTable t = boot_group_geometry(c.log_n, log_ns, c.boot_groups, inv, g);
       BootGroup G;
       G.inverse = inv;
       G.g = g;
+      G.log_ns = log_ns;
       G.level = lvl0 - g;
       G.delta = t.delta;
       G.n1 = t.n1;
@@ -1709,13 +1712,24 @@ static void boot_plan(Ctx& c) {
       // CoeffToSlot keeps 2^5 Delta until its last group: its first groups
       // carry the large ModRaise overflow, so their plaintexts get the larger scale
       G.out_scale = (inv && g < c.boot_groups - 1) ? ldexp(1.0, c.log_scale + 5) : delta;
-      G.in_scale = g == 0 ? s0 : (inv ? c.boot_cts : c.boot_stc).back().out_scale;
+      G.in_scale = g == 0 ? s0 : out.back().out_scale;
       double ps = G.out_scale * (double)c.mod[G.level];
       ps = ps / G.in_scale;
       G.pscale = ps;
-      (inv ? c.boot_cts : c.boot_stc).push_back(G);
+      out.push_back(G);
     }
   }
+}
+static int ilog2(int v) {
+  int k = 0;
+  while ((1 << k) < v) ++k;
+  return k;
+}
+static void boot_plan(Ctx& c) {
+  boot_plan_groups(c, c.log_n - 1, c.boot_cts, c.boot_stc);
+  c.boot_cts_sp.clear();
+  c.boot_stc_sp.clear();
+  if (c.boot_sparse > 0) boot_plan_groups(c, ilog2(c.boot_sparse), c.boot_cts_sp, c.boot_stc_sp);
 }
 
 extern "C" int secpe_set_boot(secpe_ctx* x, const secpe_boot_params* bp, int* out_level) {
@@ -1727,6 +1741,9 @@ extern "C" int secpe_set_boot(secpe_ctx* x, const secpe_boot_params* bp, int* ou
   c.secret_h = bp->secret_h;
   c.boot_cts.clear();
   c.boot_stc.clear();
+  c.boot_cts_sp.clear();
+  c.boot_stc_sp.clear();
+  c.boot_sparse = 0;
   c.boot_ready = false;
   c.boot_mono = nullptr;
   c.boot_mode = 0;
@@ -1737,6 +1754,10 @@ extern "C" int secpe_set_boot(secpe_ctx* x, const secpe_boot_params* bp, int* ou
   if (bp->deg < 1 || ((bp->deg + 1) & bp->deg) || bp->r < 0 || bp->groups < 1 || bp->groups > c.log_n - 1 ||
       bp->ratio < 1 || bp->ratio > 40)
     return set_err(SECPE_EINVAL, "bad bootstrapping parameters");
+  // the sparse-slot bootstrap: a power of two with 2n <= N/2 and a stage per group
+  const int sp = bp->sparse_slots;
+  if (sp != 0 && (sp < 0 || (sp & (sp - 1)) || 2 * sp > c.N / 2 || ilog2(sp) < bp->groups))
+    return set_err(SECPE_EINVAL, "sparse_slots must be 0 or a power of two n with 2n <= N/2 and log2 n >= groups");
   int k = 0;
   while ((1 << k) < bp->deg + 1) ++k;
   const int out = c.n_q - 1 - (2 * bp->groups + k + 1 + bp->r);
@@ -1750,6 +1771,7 @@ extern "C" int secpe_set_boot(secpe_ctx* x, const secpe_boot_params* bp, int* ou
   boot_cheb_coeffs(bp->K, bp->r, bp->deg, c.boot_cheb.data());
   c.boot_out_level = out;
   c.boot_mode = bp->refresh ? 1 : 0;
+  c.boot_sparse = sp;
   if (c.boot_mode) c.refresh_level = out;
   boot_plan(c);
   if (out_level) *out_level = out;
@@ -1764,7 +1786,7 @@ extern "C" int secpe_boot_steps(const secpe_ctx* x, int64_t* out, int cap) {
   std::vector<int64_t> st;
   for (int inv = 0; inv < 2; ++inv)
     for (int g = 0; g < c.boot_groups; ++g) {
-      BootGroupTable t = boot_group_geometry(c.log_n, c.boot_groups, inv, g);
+      BootGroupTable t = boot_group_geometry(c.log_n, c.log_n - 1, c.boot_groups, inv, g);
       for (int b = 1; b < t.n1; ++b) st.push_back((int64_t)t.delta * b % S);
       // offsets are delta e with |e| <= 2^len - 1, centred in [-E/2, E/2)
       const int64_t span = ((int64_t)1 << t.len) - 1;
@@ -1772,6 +1794,23 @@ extern "C" int secpe_boot_steps(const secpe_ctx* x, int64_t* out, int cap) {
       for (int64_t G = floor_div64(elo, t.n1); G <= floor_div64(ehi, t.n1); ++G)
         if (G) st.push_back((((int64_t)t.delta * t.n1 * G) % S + S) % S);
     }
+  if (c.boot_sparse > 0) {
+    // the sparse transforms: baby steps, and the giant steps of the offsets
+    // their (small) tables hold; the traces; RotR(n)
+    for (int inv = 0; inv < 2; ++inv)
+      for (int g = 0; g < c.boot_groups; ++g) {
+        BootGroupTable t = boot_group_table(c.log_n, ilog2(c.boot_sparse), c.boot_groups, c.boot_K, c.boot_ratio, inv, g);
+        for (int b = 1; b < t.n1; ++b) st.push_back((int64_t)t.delta * b % S);
+        for (const BootDiag& d : t.diags) {
+          int64_t e = d.off / t.delta;
+          if (e >= t.E / 2) e -= t.E;
+          const int64_t G = floor_div64(e, t.n1);
+          if (G) st.push_back((((int64_t)t.delta * t.n1 * G) % S + S) % S);
+        }
+      }
+    for (int64_t r = c.boot_sparse; r < S; r *= 2) st.push_back(r);
+    st.push_back(S - c.boot_sparse);
+  }
   std::sort(st.begin(), st.end());
   st.erase(std::unique(st.begin(), st.end()), st.end());
   st.erase(std::remove_if(st.begin(), st.end(), [&](int64_t v) { return v % S == 0; }), st.end());
@@ -1796,8 +1835,14 @@ extern "C" size_t secpe_boot_key_bytes(secpe_ctx* x) {
   size_t total = 2 * (size_t)c.n_q * c.limb_bytes();
   for (int inv = 0; inv < 2; ++inv)
     for (const BootGroup& G : inv ? c.boot_cts : c.boot_stc) {
-      const int len = boot_group_geometry(c.log_n, c.boot_groups, inv, G.g).len;
+      const int len = boot_group_geometry(c.log_n, c.log_n - 1, c.boot_groups, inv, G.g).len;
       total += boot_group_es(G, len).size() * (size_t)(G.level + 1) * c.limb_bytes();
+    }
+  for (int inv = 0; inv < 2; ++inv)
+    for (const BootGroup& G : inv ? c.boot_cts_sp : c.boot_stc_sp) {
+      const size_t nd =
+          boot_group_table(c.log_n, G.log_ns, c.boot_groups, c.boot_K, c.boot_ratio, inv, G.g).diags.size();
+      total += nd * (size_t)(G.level + 1) * c.limb_bytes();
     }
   return total;
 }
@@ -1828,9 +1873,12 @@ extern "C" int secpe_boot_setup(secpe_ctx* x, void* buf_dev, size_t bytes) {
     if (rc) return rc;
     c.boot_mono = mono;
   }
-  for (int inv = 1; inv >= 0; --inv)
-    for (BootGroup& G : inv ? c.boot_cts : c.boot_stc) {
-      BootGroupTable t = boot_group_table(c.log_n, c.boot_groups, c.boot_K, c.boot_ratio, inv, G.g);
+  for (int which = 0; which < 4; ++which) {
+    const int inv = which & 1 ? 0 : 1;
+    std::vector<BootGroup>& list = which < 2 ? (inv ? c.boot_cts : c.boot_stc) : (inv ? c.boot_cts_sp : c.boot_stc_sp);
+    for (BootGroup& G : list) {
+      BootGroupTable t = boot_group_table(c.log_n, G.log_ns, c.boot_groups, c.boot_K, c.boot_ratio, inv, G.g);
+      const int ns = t.ns;
       G.e.clear();
       G.pt.clear();
       // the nonzero entries of each pre-rotated diagonal as (5^slot mod 2N, re, im)
@@ -1842,11 +1890,12 @@ extern "C" int secpe_boot_setup(secpe_ctx* x, void* buf_dev, size_t bytes) {
         int64_t e = d.off / G.delta;
         if (e >= G.E / 2) e -= G.E;
         const int64_t gg = floor_div64(e, G.n1);
-        const int64_t shift = (((int64_t)G.delta * G.n1 * gg) % S + S) % S;
+        // the diagonal, pre-rotated by delta n1 gg, repeats with period ns
+        const int64_t shift = (((int64_t)G.delta * G.n1 * gg) % ns + ns) % ns;
         std::vector<double> r, i2;
         std::vector<uint32_t> gv;
         for (int p = 0; p < S; ++p) {
-          const int src = (int)(((int64_t)p - shift + S) % S);
+          const int src = (int)(((int64_t)(p % ns) - shift + ns) % ns);
           if (d.re[src] == 0.0 && d.im[src] == 0.0) continue;
           r.push_back(d.re[src]);
           i2.push_back(d.im[src]);
@@ -1919,6 +1968,7 @@ extern "C" int secpe_boot_setup(secpe_ctx* x, void* buf_dev, size_t bytes) {
       rc = sync(c);
       if (rc) return rc;
     }
+  }
   drop_graphs(c);
   c.boot_ready = true;
   return sync(c);
@@ -1938,30 +1988,37 @@ extern "C" size_t secpe_bootstrap_workspace_bytes(secpe_ctx* x, int n) {
   }
   Ctx& c = x->c;
   std::vector<secpe_ct> in(n, secpe_ct{(void*)(uintptr_t)0x200000000000ull, 1, ldexp(1.0, c.log_scale)});
-  Builder dry(c, (char*)(uintptr_t)0x100000000000ull, (size_t)1 << 44, (char*)(uintptr_t)0x400000000000ull,
-              (size_t)1 << 40, true);
-  std::vector<CT> v = boot_inputs(n, in.data());
-  // the dry build takes the set-up scales for granted
-  dry.bootstrap(v);
-  if (dry.err_code) {
-    set_err(dry.err_code, dry.err);
-    return 0;
+  size_t need = 0;
+  // the larger of the full and the sparse-slot pipelines
+  for (int sparse = 0; sparse < (c.boot_sparse > 0 ? 2 : 1); ++sparse) {
+    Builder dry(c, (char*)(uintptr_t)0x100000000000ull, (size_t)1 << 44, (char*)(uintptr_t)0x400000000000ull,
+                (size_t)1 << 40, true);
+    std::vector<CT> v = boot_inputs(n, in.data());
+    // the dry build takes the set-up scales for granted
+    dry.bootstrap(v, sparse != 0);
+    if (dry.err_code) {
+      set_err(dry.err_code, dry.err);
+      return 0;
+    }
+    need = std::max(need, dry.need_bytes());
   }
-  return dry.need_bytes() + 4096;
+  return need + 4096;
 }
 
-extern "C" int secpe_bootstrap(secpe_ctx* x, int n, const secpe_ct* in, void* ws, size_t ws_bytes, secpe_ct* out) {
+static int bootstrap_into(secpe_ctx* x, int n, const secpe_ct* in, void* ws, size_t ws_bytes, secpe_ct* out,
+                          bool sparse) {
   CHECK_CTX(x);
   Ctx& c = x->c;
   if (n < 1 || !in || !out || !ws) return set_err(SECPE_EINVAL, "bad bootstrap arguments");
   if (!c.boot_ready) return set_err(SECPE_EINVAL, "bootstrapping is not set up (secpe_boot_setup)");
+  if (sparse && c.boot_sparse <= 0) return set_err(SECPE_EINVAL, "sparse_slots is 0: no sparse-slot bootstrap");
   for (int i = 0; i < n; ++i) {
     if (!in[i].data || !out[i].data) return set_err(SECPE_EINVAL, "null ciphertext");
     if (in[i].level < 1 || in[i].level >= c.n_q) return set_err(SECPE_EINVAL, "bootstrap input needs level in [1, n_q)");
   }
   std::vector<CT> res;
   int rc = run_build(x, (char*)ws, ws_bytes, [&](Builder& b) {
-    std::vector<CT> r = b.bootstrap(boot_inputs(n, in));
+    std::vector<CT> r = b.bootstrap(boot_inputs(n, in), sparse);
     if (b.err_code) return;
     std::vector<EwJob> j;
     for (int i = 0; i < n; ++i) {
@@ -1986,13 +2043,23 @@ extern "C" int secpe_bootstrap(secpe_ctx* x, int n, const secpe_ct* in, void* ws
   return 0;
 }
 
+extern "C" int secpe_bootstrap(secpe_ctx* x, int n, const secpe_ct* in, void* ws, size_t ws_bytes, secpe_ct* out) {
+  return bootstrap_into(x, n, in, ws, ws_bytes, out, false);
+}
+
+extern "C" int secpe_bootstrap_sparse(secpe_ctx* x, int n, const secpe_ct* in, void* ws, size_t ws_bytes,
+                                      secpe_ct* out) {
+  return bootstrap_into(x, n, in, ws, ws_bytes, out, true);
+}
+
 extern "C" int secpe_op_boot_step(secpe_ctx* x, int step, const secpe_ct* a, void* ws, size_t ws_bytes, secpe_ct* out) {
   CHECK_CTX(x);
   if (!a || !a->data) return set_err(SECPE_EINVAL, "null input");
-  if (step < 0 || step > 5) return set_err(SECPE_EINVAL, "unknown bootstrapping step");
+  if (step < 0 || step > 7) return set_err(SECPE_EINVAL, "unknown bootstrapping step");
   // the linear transforms and the monomials need secpe_boot_setup; EvalMod the parameters
-  if ((step == 1 || step == 2 || step == 4 || step == 5) && !x->c.boot_ready)
+  if (step != 0 && step != 3 && !x->c.boot_ready)
     return set_err(SECPE_EINVAL, "bootstrapping is not set up (secpe_boot_setup)");
+  if (step >= 6 && x->c.boot_sparse <= 0) return set_err(SECPE_EINVAL, "sparse_slots is 0: no sparse-slot bootstrap");
   if (step == 3 && x->c.boot_out_level < 0) return set_err(SECPE_EINVAL, "bootstrapping is not configured");
   return op_to_out(x, ws, ws_bytes, out, [&](Builder& b) -> std::vector<CT> {
     const std::vector<CT> v{to_ct(a)};
@@ -2002,7 +2069,9 @@ extern "C" int secpe_op_boot_step(secpe_ctx* x, int step, const secpe_ct* a, voi
       case 2: return b.boot_transform(v, false);
       case 3: return b.eval_mod(v);
       case 4: return b.mul_monomial_half(v, false);
-      default: return b.mul_monomial_half(v, true);
+      case 5: return b.mul_monomial_half(v, true);
+      case 6: return b.boot_transform(v, true, true);
+      default: return b.boot_transform(v, false, true);
     }
   });
 }

@@ -52,6 +52,7 @@ static void maybe_refresh(Builder& b, std::vector<QState*>& qs, std::vector<CT*>
   std::vector<CT> in;
   std::vector<uint64_t> seed, index;
   std::vector<size_t> who;
+  std::vector<int> span;
   const int top = b.C.refresh_level;
   for (size_t i = 0; i < qs.size(); ++i) {
     CT& x = *cts[i];
@@ -61,9 +62,12 @@ static void maybe_refresh(Builder& b, std::vector<QState*>& qs, std::vector<CT*>
     seed.push_back(qs[i]->q->refresh_seed);
     index.push_back(qs[i]->rnext++);
     who.push_back(i);
+    // after Eq. 5 a single query reads only slots [0, 2C') again (the
+    // duplicate of line 2 and every QuickMax window stay inside)
+    span.push_back(qs[i]->bsz ? 0 : 2 * qs[i]->cp);
   }
   if (in.empty()) return;
-  std::vector<CT> out = b.refresh(in, seed, index);
+  std::vector<CT> out = b.refresh(in, seed, index, &span);
   if (b.err_code) return;
   for (size_t k = 0; k < who.size(); ++k) {
     CT& x = *cts[who[k]];

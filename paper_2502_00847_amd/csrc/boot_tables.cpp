@@ -4,7 +4,9 @@
 //    special FFT (Cheon, Han, Kim, Kim, Song, SAC 2018) on the N/2 slots
 //    (slot j <-> zeta^(5^j), zeta = e^(i pi / N)), merged into groups that
 //    each cost one level; CoeffToSlot applies the inverse stages m = S .. 2,
-//    SlotToCoeff the forward stages m = 2 .. S;
+//    SlotToCoeff the forward stages m = 2 .. S; the sparse-slot transforms
+//    are the same stages of the n-slot FFT (root zeta^(N/2n) of order 4n),
+//    on slot vectors of period n;
 //  * the Chebyshev interpolant of the scaled cosine that EvalMod evaluates
 //    (Han, Ki, CT-RSA 2020).
 #include <quadmath.h>
@@ -43,8 +45,10 @@ Q2 root(uint64_t t, int n) {
 // a slot map out[p] = sum_d A[d][p] in[(p + d) mod S], offsets d in [0, S)
 using DiagMap = std::map<int, std::vector<Q2>>;
 
-DiagMap stage(int n, int m, bool inverse) {
-  const int S = n / 2, h = m / 2;
+// one stage on ns slots (ns = N/2, or the sparse n): the n-slot FFT's twiddles
+// are the N/2-slot FFT's, zeta^((N/2m) 5^j)
+DiagMap stage(int n, int ns, int m, bool inverse) {
+  const int S = ns, h = m / 2;
   const uint64_t m2 = 2ull * (uint64_t)n;
   DiagMap A;
   auto at = [&](int d) -> std::vector<Q2>& {
@@ -52,11 +56,11 @@ DiagMap stage(int n, int m, bool inverse) {
     if (it == A.end()) it = A.emplace(d, std::vector<Q2>(S)).first;
     return it->second;
   };
-  // D_m[j] = zeta^((S/m) 5^j), j < m/2
+  // D_m[j] = zeta^((N/2m) 5^j), j < m/2
   std::vector<Q2> D_m(h);
   uint64_t g5 = 1;
   for (int j = 0; j < h; ++j) {
-    D_m[j] = root((uint64_t)(S / m) * g5, n);
+    D_m[j] = root((uint64_t)(n / 2 / m) * g5, n);
     g5 = g5 * 5 % m2;
   }
   for (int p = 0; p < S; ++p) {
@@ -111,8 +115,16 @@ DiagMap compose(const DiagMap& A, const DiagMap& B, int S) {
 
 int boot_group_len(int log_slots, int groups, int g) { return log_slots / groups + (g < log_slots % groups ? 1 : 0); }
 
-BootGroupTable boot_group_geometry(int log_n, int groups, int inverse, int g) {
-  const int S = 1 << (log_n - 1), L = log_n - 1;
+// The sparse transforms differ from the n-slot maps in two groups: the last
+// CoeffToSlot group writes [w, 0] with period 2n (the n-slot diagonal on the
+// lower half of each period, zero on the upper), and the first SlotToCoeff
+// group reads [a, b] with period 2n and transforms a + i b.
+static bool widened(int log_n, int log_ns, int groups, int inverse, int g) {
+  return log_ns < log_n - 1 && (inverse ? g == groups - 1 : g == 0);
+}
+
+BootGroupTable boot_group_geometry(int log_n, int log_ns, int groups, int inverse, int g) {
+  const int S = 1 << log_ns, L = log_ns;
   int first = 0;
   for (int i = 0; i < g; ++i) first += boot_group_len(L, groups, i);
   BootGroupTable t;
@@ -123,41 +135,71 @@ BootGroupTable boot_group_geometry(int log_n, int groups, int inverse, int g) {
     const int m = inverse ? 1 << (L - idx) : 1 << (idx + 1);
     if (m < mmin) mmin = m;
   }
+  t.ns = widened(log_n, log_ns, groups, inverse, g) ? 2 * S : S;
   t.delta = mmin / 2;
-  t.E = S / t.delta;
+  t.E = t.ns / t.delta;
   t.n1 = 1 << ((t.len + 2) / 2);
-  if (t.n1 > t.E) t.n1 = t.E;
+  if (t.n1 > S / t.delta) t.n1 = S / t.delta;
   return t;
 }
 
-BootGroupTable boot_group_table(int log_n, int groups, int K, int ratio, int inverse, int g) {
-  const int n = 1 << log_n, S = n / 2, L = log_n - 1;
-  BootGroupTable t = boot_group_geometry(log_n, groups, inverse, g);
+BootGroupTable boot_group_table(int log_n, int log_ns, int groups, int K, int ratio, int inverse, int g) {
+  const int n = 1 << log_n, S = 1 << log_ns, L = log_ns;
+  BootGroupTable t = boot_group_geometry(log_n, log_ns, groups, inverse, g);
   int first = 0;
   for (int i = 0; i < g; ++i) first += boot_group_len(L, groups, i);
   DiagMap M;
   for (int i = 0; i < t.len; ++i) {
     const int idx = first + i;
     const int m = inverse ? 1 << (L - idx) : 1 << (idx + 1);
-    DiagMap st = stage(n, m, inverse != 0);
+    DiagMap st = stage(n, S, m, inverse != 0);
     M = i == 0 ? st : compose(st, M, S);
   }
   if (g == 0) {
     // CoeffToSlot: 1 / (2 (K+1)) (the real/imaginary split doubles, EvalMod
-    // reads x / (K+1)); SlotToCoeff: 2^ratio / (2 pi) (back from sin(2 pi x))
-    const __float128 k = inverse ? 1.0Q / (2.0Q * (__float128)(K + 1)) : ldexpq(1.0Q, ratio) / (2.0Q * M_PIq);
+    // reads x / (K+1)), and for the sparse transform n / (N/2) against the
+    // trace's factor N/2n; SlotToCoeff: 2^ratio / (2 pi) (back from sin(2 pi x))
+    __float128 k = inverse ? 1.0Q / (2.0Q * (__float128)(K + 1)) : ldexpq(1.0Q, ratio) / (2.0Q * M_PIq);
+    if (inverse) k = k * (__float128)S / (__float128)(n / 2);
     for (auto& d : M)
       for (Q2& v : d.second) {
         v.re *= k;
         v.im *= k;
       }
   }
+  if (t.ns != S) {
+    const int S2 = t.ns;
+    DiagMap W;
+    for (const auto& d : M) {
+      if (inverse) {
+        // an n-periodic input reads the same slot at d and d - n: keep the
+        // centred offset; zero on the upper half of each 2n period
+        std::vector<Q2> v(S2);
+        for (int p = 0; p < S; ++p) v[p] = d.second[p];
+        W[d.first < S / 2 ? d.first : d.first + S] = std::move(v);
+      } else {
+        // offsets d and d + n; a slot read from the upper half is times i
+        for (int k = 0; k < 2; ++k) {
+          const int off = (d.first + k * S) % S2;
+          auto it = W.find(off);
+          if (it == W.end()) it = W.emplace(off, std::vector<Q2>(S2)).first;
+          for (int p = 0; p < S2; ++p) {
+            const Q2& v = d.second[p % S];
+            const bool upper = (p + off) % S2 >= S;
+            it->second[p].re += upper ? -v.im : v.re;
+            it->second[p].im += upper ? v.re : v.im;
+          }
+        }
+      }
+    }
+    M.swap(W);
+  }
   for (const auto& d : M) {
     BootDiag bd;
     bd.off = d.first;
-    bd.re.resize(S);
-    bd.im.resize(S);
-    for (int p = 0; p < S; ++p) {
+    bd.re.resize(t.ns);
+    bd.im.resize(t.ns);
+    for (int p = 0; p < t.ns; ++p) {
       bd.re[p] = (double)d.second[p].re;
       bd.im[p] = (double)d.second[p].im;
     }

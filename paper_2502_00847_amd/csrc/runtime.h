@@ -51,6 +51,7 @@ struct Ctx;
 // -delta n1 floor(e / n1) and encoded for an input of scale in_scale at 'level'
 struct BootGroup {
   int inverse = 0, g = 0, level = 0, delta = 0, n1 = 0, E = 0;
+  int log_ns = 0;                  // log2 of the transform's slot count (N/2 or the sparse n)
   double in_scale = 0.0, pscale = 0.0, out_scale = 0.0;
   std::vector<int64_t> e;          // centred offset multiple of each diagonal
   std::vector<const double*> pt;   // NTT domain, limbs 0..level
@@ -92,6 +93,8 @@ struct Ctx {
   int boot_out_level = -1;
   std::vector<double> boot_cheb;
   std::vector<BootGroup> boot_cts, boot_stc;   // CoeffToSlot, SlotToCoeff groups
+  int boot_sparse = 0;     // n > 0: the sparse-slot bootstrap keeps slots [0, n)
+  std::vector<BootGroup> boot_cts_sp, boot_stc_sp;   // its transforms
   const double* boot_mono = nullptr;            // X^(N/2), then -X^(N/2): [2][n_q][N], NTT domain
   bool boot_ready = false;
   int boot_chunk = 8;      // ciphertexts bootstrapped together in one pass
@@ -352,14 +355,18 @@ class Builder {
   std::vector<CT> add_plain_sparse(const std::vector<CT>& in, const std::vector<SparseSlots>& z);
   std::vector<CT> plain_op(const std::vector<CT>& in, const std::vector<std::vector<double>>* dense,
                            const std::vector<SparseSlots>* sparse, const std::vector<double>* target, bool product);
+  // span[i] > 0: only slots [0, span[i]) of item i are read again (a
+  // bootstrap may then keep just those); null: every slot
   std::vector<CT> refresh(const std::vector<CT>& in, const std::vector<uint64_t>& seed,
-                          const std::vector<uint64_t>& index);
+                          const std::vector<uint64_t>& index, const std::vector<int>* span = nullptr);
   std::vector<CT> eval_odd9(const std::vector<CT>& x, const std::vector<const double*>& coef,
                             const std::vector<double>& gain, const std::vector<double>& target);
   // bootstrapping steps (the groups' plaintexts come from secpe_boot_setup)
   std::vector<CT> mod_raise(const std::vector<CT>& in);                 // level 0 -> top, scale q_0
   std::vector<CT> mul_monomial_half(const std::vector<CT>& in, bool neg);  // slots times +-i
-  std::vector<CT> boot_transform(const std::vector<CT>& in, bool inverse);
+  // sparse: the sparse-slot transforms (the last CoeffToSlot group writes
+  // period 2n, the first SlotToCoeff group reads it)
+  std::vector<CT> boot_transform(const std::vector<CT>& in, bool inverse, bool sparse = false);
   std::vector<CT> eval_mod(const std::vector<CT>& u);
   std::vector<CT> relin(const std::vector<Deg2>& xs);        // relinearise, no rescale
   void cheb_basis_step(std::vector<std::vector<CT>>& T, std::vector<std::vector<CT>>& T2, int j);
@@ -368,8 +375,12 @@ class Builder {
   std::vector<CT> cheb_node(const std::vector<std::vector<CT>>& T, int B, int lb, const double* cf, int m,
                             const std::vector<double>& target);
   std::vector<CT> square_exact(const std::vector<CT>& xs);   // relinearise, then rescale
-  std::vector<CT> bootstrap(const std::vector<CT>& in);
+  // sparse: keep slots [0, boot_sparse), repeated with period boot_sparse
+  std::vector<CT> bootstrap(const std::vector<CT>& in, bool sparse = false);
   std::vector<CT> bootstrap_chunk(const std::vector<CT>& in);
+  std::vector<CT> bootstrap_sparse_chunk(const std::vector<CT>& in);
+  // x + RotL(x, n) + RotL(x, 2n) + ... over the multiples of n below N/2
+  std::vector<CT> subsum(const std::vector<CT>& in, int n);
   // client-side helpers
   void encrypt_into(const std::vector<const int64_t*>& m_dev, const std::vector<uint64_t>& seed, int purpose,
                     const std::vector<uint64_t>& sub, const double* sk, const std::vector<CT>& out);

@@ -1381,8 +1381,26 @@ void Builder::encrypt_into(const std::vector<const int64_t*>& m_dev, const std::
 // refresh stand-in: decrypt with the key owner's secret, lift m exactly from
 // limbs 0 and 1, re-encrypt at the refresh level; scale kept
 std::vector<CT> Builder::refresh(const std::vector<CT>& in, const std::vector<uint64_t>& seed,
-                                 const std::vector<uint64_t>& index) {
-  if (C.boot_mode) return bootstrap(in);
+                                 const std::vector<uint64_t>& index, const std::vector<int>* span) {
+  if (C.boot_mode) {
+    // items that read only slots [0, n) again take the sparse-slot bootstrap
+    std::vector<size_t> sp, fu;
+    for (size_t i = 0; i < in.size(); ++i) {
+      const int w = span ? (*span)[i] : 0;
+      (C.boot_sparse > 0 && w > 0 && w <= C.boot_sparse ? sp : fu).push_back(i);
+    }
+    std::vector<CT> out(in.size());
+    for (int pass = 0; pass < 2; ++pass) {
+      const std::vector<size_t>& idx = pass ? fu : sp;
+      if (idx.empty()) continue;
+      std::vector<CT> part;
+      for (size_t i : idx) part.push_back(in[i]);
+      std::vector<CT> o = bootstrap(part, pass == 0);
+      if (err_code) return {};
+      for (size_t k = 0; k < idx.size(); ++k) out[idx[k]] = o[k];
+    }
+    return out;
+  }
   mark();
   const int N = C.N, L = C.refresh_level + 1;
   const double* rsk = refresh_sk ? refresh_sk : (dry ? C.T.mod : nullptr);
@@ -1575,8 +1593,9 @@ static int64_t fdiv(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 
 // all groups of one direction; group g: out = sum_G RotL(sum_b pt_{G,b} * RotL(x, delta b), delta n1 G),
 // rescaled once, scale := the group's output scale.  Inner sums are accumulated baby step by baby
 // step, so one rotated copy of each input is alive at a time.
-std::vector<CT> Builder::boot_transform(const std::vector<CT>& in, bool inverse) {
-  const std::vector<BootGroup>& groups = inverse ? C.boot_cts : C.boot_stc;
+std::vector<CT> Builder::boot_transform(const std::vector<CT>& in, bool inverse, bool sparse) {
+  const std::vector<BootGroup>& groups =
+      sparse ? (inverse ? C.boot_cts_sp : C.boot_stc_sp) : (inverse ? C.boot_cts : C.boot_stc);
   if (groups.empty() || (!C.boot_ready && !dry)) { fail(-1, "bootstrapping is not set up"); return {}; }
   std::vector<CT> cur = in;
   bool own = false;
@@ -2034,17 +2053,120 @@ std::vector<CT> Builder::eval_mod(const std::vector<CT>& us) {
 // the whole bootstrap of ciphertexts at level >= 1 with slot values |z| <= 1;
 // results at boot_out_level with scale Delta.  Items run in chunks of
 // boot_chunk so the temporaries of one chunk bound the workspace.
-std::vector<CT> Builder::bootstrap(const std::vector<CT>& all) {
+std::vector<CT> Builder::bootstrap(const std::vector<CT>& all, bool sparse) {
   if (C.boot_out_level < 0 || (!C.boot_ready && !dry)) { fail(-1, "bootstrapping is not set up"); return {}; }
+  if (sparse && C.boot_sparse <= 0) { fail(-1, "sparse-slot bootstrapping is not set up"); return {}; }
   std::vector<CT> res;
   const size_t chunk = (size_t)std::max(1, C.boot_chunk);
   for (size_t c0 = 0; c0 < all.size(); c0 += chunk) {
     std::vector<CT> part(all.begin() + c0, all.begin() + std::min(all.size(), c0 + chunk));
-    std::vector<CT> o = bootstrap_chunk(part);
+    std::vector<CT> o = sparse ? bootstrap_sparse_chunk(part) : bootstrap_chunk(part);
     if (err_code) return {};
     res.insert(res.end(), o.begin(), o.end());
   }
   return res;
+}
+
+std::vector<CT> Builder::subsum(const std::vector<CT>& in, int n) {
+  std::vector<CT> cur = in;
+  bool own = false;
+  for (int64_t r = n; r < C.N / 2; r *= 2) {
+    std::vector<CT> rot = rotate(cur, std::vector<int64_t>(cur.size(), r));
+    if (err_code) return {};
+    std::vector<std::pair<CT, CT>> pr;
+    for (size_t i = 0; i < cur.size(); ++i) pr.push_back({cur[i], rot[i]});
+    std::vector<CT> nx = add(pr, false);
+    if (err_code) return {};
+    for (CT& v : rot) free_ct(v);
+    if (own)
+      for (CT& v : cur) free_ct(v);
+    cur = nx;
+    own = true;
+  }
+  if (!own) {
+    // n = N/2: nothing to sum; hand back copies the caller owns
+    std::vector<std::pair<CT, CT>> pr;
+    std::vector<CT> z;
+    for (const CT& x : cur) {
+      EwJob e{};
+      CT o = new_ct(x.level, x.scale);
+      e.o0 = c0(o); e.o1 = c1(o); e.a0 = c0(x); e.a1 = c1(x);
+      e.n_limbs = x.level + 1; e.n_chain = x.level + 1; e.op = EW_COPY;
+      ew({e});
+      z.push_back(o);
+    }
+    cur = z;
+  }
+  return cur;
+}
+
+// Sparse-slot bootstrap of n = boot_sparse slots: the mask of slots [0, n)
+// replaces the scale-down constant; the trace at level 0 makes the message
+// n-periodic; ModRaise; the trace again; the n-slot CoeffToSlot, whose last
+// group writes [w, 0] with period 2n; [re, 0] = w + conj(w) and [im, 0] =
+// -i (w - conj(w)) join as [re, im] = [re, 0] + RotR([im, 0], n); one EvalMod;
+// the n-slot SlotToCoeff of re + i im.  Same depth as the full pipeline.
+std::vector<CT> Builder::bootstrap_sparse_chunk(const std::vector<CT>& in) {
+  const size_t n = in.size();
+  const int ns = C.boot_sparse, S = C.N / 2;
+  const double tb = ldexp((double)C.mod[0], -C.boot_ratio);
+  std::vector<CT> x1;
+  std::vector<std::vector<double>> mask;
+  std::vector<double> tg;
+  for (const CT& x : in) {
+    if (x.level < 1) { fail(-3, "bootstrap: input needs level >= 1"); return {}; }
+    CT v = x;
+    v.level = 1;
+    v.slot = -1;
+    x1.push_back(v);
+    mask.push_back(std::vector<double>(ns, 1.0));
+    tg.push_back(tb);
+  }
+  std::vector<CT> x0 = mul_plain(x1, mask, tg);
+  if (err_code) return {};
+  std::vector<CT> t0 = subsum(x0, ns);
+  if (err_code) return {};
+  for (CT& v : x0) free_ct(v);
+  std::vector<CT> r = mod_raise(t0);
+  if (err_code) return {};
+  for (CT& v : t0) free_ct(v);
+  std::vector<CT> rt = subsum(r, ns);
+  if (err_code) return {};
+  for (CT& v : r) free_ct(v);
+  std::vector<CT> y = boot_transform(rt, true, true);
+  if (err_code) return {};
+  for (CT& v : rt) free_ct(v);
+  std::vector<CT> yc = rotate(y, std::vector<int64_t>(n, kConjStep));
+  if (err_code) return {};
+  std::vector<std::pair<CT, CT>> pr;
+  for (size_t i = 0; i < n; ++i) pr.push_back({y[i], yc[i]});
+  std::vector<CT> re, df;
+  add_sub(pr, df, re);
+  if (err_code) return {};
+  for (CT& v : y) free_ct(v);
+  for (CT& v : yc) free_ct(v);
+  std::vector<CT> im = mul_monomial_half(df, true);
+  if (err_code) return {};
+  for (CT& v : df) free_ct(v);
+  std::vector<CT> imr = rotate(im, std::vector<int64_t>(n, (int64_t)S - ns));
+  if (err_code) return {};
+  for (CT& v : im) free_ct(v);
+  pr.clear();
+  for (size_t i = 0; i < n; ++i) pr.push_back({re[i], imr[i]});
+  std::vector<CT> u = add(pr, false);
+  if (err_code) return {};
+  for (CT& v : re) free_ct(v);
+  for (CT& v : imr) free_ct(v);
+  std::vector<CT> e = eval_mod(u);
+  if (err_code) return {};
+  for (CT& v : u) free_ct(v);
+  std::vector<CT> out = boot_transform(e, false, true);
+  if (err_code) return {};
+  for (CT& v : e) free_ct(v);
+  for (const CT& v : out)
+    if (v.level != C.boot_out_level) { fail(-1, "bootstrap: level plan mismatch"); return {}; }
+  counters[4] += (int64_t)n;
+  return out;
 }
 
 std::vector<CT> Builder::bootstrap_chunk(const std::vector<CT>& in) {

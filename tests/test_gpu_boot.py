@@ -109,8 +109,45 @@ def test_bootstrap_batch_equals_single(pair):
         _same(g, b, o.bootstrap(c))
 
 
+def test_sparse_transforms_bit_exact(pair):
+    """The sparse-slot CoeffToSlot (its last group writing period 2n) and
+    SlotToCoeff (its first group reading it), one call each."""
+    g, o = pair
+    n = P["boot_sparse"]
+    z = np.random.default_rng(13).uniform(-1, 1, g.slots)
+    ct = _enc(o, z, 2.0**50, 15, 1)
+    tb = float(o.primes[0]) * 2.0 ** -P["boot_ratio"]
+    r = o.mod_raise(o.lincomb(ct, 1.0, None, 0.0, tb, 1))
+    _same(g, g.boot_step(6, g.import_(r.export(), r.scale)), o.boot_transform_sparse(r, 1))
+    # SlotToCoeff's input: [a, b] with period 2n, at the level and scale EvalMod leaves
+    ev = o.eval_mod(_enc(o, np.zeros(g.slots), 2.0 ** P["log_scale"], 17, g.n_q - 1 - P["boot_groups"]))
+    ab = np.tile(np.random.default_rng(14).uniform(-0.01, 0.01, 2 * n), g.slots // (2 * n))
+    e = _enc(o, ab, ev.scale, 16, ev.level)
+    _same(g, g.boot_step(7, g.import_(e.export(), e.scale)), o.boot_transform_sparse(e, 0))
+
+
+@pytest.mark.parametrize("level", [1, 4])
+def test_sparse_bootstrap_bit_exact(pair, level):
+    """The sparse-slot bootstrap (slots [0, n) kept, repeated with period n),
+    alone and for two inputs in one call."""
+    g, o = pair
+    n = P["boot_sparse"]
+    zs = [np.random.default_rng(40 + level + i).uniform(-1, 1, g.slots) for i in range(2)]
+    cts = [_enc(o, z, 2.0**49, 41 + i, level) for i, z in enumerate(zs)]
+    bo = [o.bootstrap_sparse(c) for c in cts]
+    bg = g.bootstrap([g.import_(c.export(), c.scale) for c in cts], sparse=True)
+    for a, b in zip(bg, bo):
+        _same(g, a, b)
+    [b1] = g.bootstrap([g.import_(cts[0].export(), cts[0].scale)], sparse=True)
+    _same(g, b1, bo[0])
+    for b, z in zip(bo, zs):
+        assert np.abs(o.decrypt_decode(b, g.slots) - np.tile(z[:n], g.slots // n)).max() < 2.0**-16
+
+
 def test_argmax_with_bootstrapping_bit_exact(pair):
-    """Algorithm 1 refreshing by bootstrapping, on the GPU and in the oracle."""
+    """Algorithm 1 refreshing by bootstrapping, on the GPU and in the oracle; a
+    single query reads slots [0, 2C') after Eq. 5, so both take the
+    sparse-slot bootstrap."""
     g, o = pair
     K, C = 2, 4
     y = W.logits(9, 5, K, C)
@@ -241,9 +278,27 @@ def test_full_bootstrap_precision(full):
         assert err < 2.0**-12
 
 
+def test_full_sparse_bootstrap_precision(full):
+    """N = 2^16: the sparse-slot bootstrap (n = 64) returns slots [0, n) of its
+    input, repeated with period n, within 2^-12, whatever the other slots hold."""
+    g = full
+    n = W.PARAMS["full_boot"]["boot_sparse"]
+    rng = np.random.default_rng(7)
+    for kind in ("uniform", "few"):
+        z = rng.uniform(-1, 1, g.slots)
+        if kind == "few":
+            z[8:n] = 0.0
+        [b] = g.bootstrap([g.encrypt(z.reshape(1, -1), 50 + len(kind))], sparse=True)
+        assert b.level == g.n_q - 1 - 16 and b.scale == 2.0**50
+        got, _ = g.decrypt(b, g.slots)
+        err = np.abs(got - np.tile(z[:n], g.slots // n)).max()
+        print(f"[boot] full sparse {kind}: max error 2^{np.log2(err):.1f}", flush=True)
+        assert err < 2.0**-12
+
+
 def test_full_argmax_with_bootstrapping(full):
-    """Config 2 (K = 8, C = 4) with every refresh a bootstrap: the index is the
-    plaintext argmax and z follows the FP64 simulation."""
+    """Config 2 (K = 8, C = 4) with every refresh a (sparse-slot) bootstrap: the
+    index is the plaintext argmax and z follows the FP64 simulation."""
     g = full
     q = W.query(2, 0)
     z = g.eval_argmax(g.encrypt(q["logits"], q["encrypt_seed"]), q["K"], q["C"], q["d_min"], q["d_max"],
@@ -295,6 +350,23 @@ def test_p13_bootstrap_matches_oracle_digest(p13boot):
     assert _digest(g.export(b)) == rec["output_sha256"]
     err = np.abs(g.decrypt(b, g.slots)[0] - z).max()
     print(f"[boot13] bootstrap error 2^{np.log2(err):.1f}", flush=True)
+    assert err < 2.0**-16
+
+
+def test_p13_sparse_bootstrap_matches_oracle_digest(p13boot):
+    """The sparse-slot bootstrap (n = 32) of the same input as the full one."""
+    g, gold = p13boot
+    rec = gold["boot13_sparse"]
+    z = np.random.default_rng(5).uniform(-1, 1, g.slots)
+    full = g.encrypt_coeffs(g.encode(z, 2.0**49), 2.0**49, 7)
+    ct = g.import_(g.export(full)[:, :4, :], full.scale)
+    assert _digest(g.export(ct)) == rec["input_sha256"]
+    [b] = g.bootstrap([ct], sparse=True)
+    assert (b.level, b.scale) == (rec["level"], rec["scale"])
+    assert _digest(g.export(b)) == rec["output_sha256"]
+    n = W.PARAMS["p13_boot"]["boot_sparse"]
+    err = np.abs(g.decrypt(b, g.slots)[0] - np.tile(z[:n], g.slots // n)).max()
+    print(f"[boot13] sparse bootstrap error 2^{np.log2(err):.1f}", flush=True)
     assert err < 2.0**-16
 
 

@@ -222,3 +222,114 @@ def test_argmax_with_bootstrapping(boot):
     zs = sim.t1_argmax(y, lo, hi, o.slots)[:C]
     assert np.abs(z - zs).max() < 1e-3
     assert int(np.argmax(z)) == sim.t0_argmax(y)[0]
+
+
+# ---------------------------------------------------------------------------
+# sparse-slot bootstrapping: n slots kept, the n-slot special FFT
+SPARSE_N = 32
+
+
+def _embedding_n(n):
+    """U'_jk = xi^(5^j k), j, k < n, xi = e^(i pi / 2n): the slots of a polynomial in
+    Y = X^(N/2n) with coefficients t_k + i t_(k+n) (xi^n = i and 5^j = 1 mod 4)."""
+    m4 = 4 * n
+    g5 = np.array([pow(5, j, m4) for j in range(n)], dtype=np.int64)
+    k = np.arange(n, dtype=np.int64)
+    return np.exp(2j * np.pi * ((g5[:, None] * k[None, :]) % m4) / m4)
+
+
+def test_sparse_transforms_are_the_n_slot_embedding():
+    """On one 2n period of the slots: the sparse CoeffToSlot maps an n-periodic
+    z to [P U'^-1 z (n / (N/2)) / (2 (K+1)), 0], and the sparse SlotToCoeff
+    maps [a, b] to U' P^-1 (a + i b) 2^ratio / (2 pi), repeated with period n;
+    U' is the n-slot embedding written here."""
+    o = make_oracle("tiny_boot")
+    n = SPARSE_N
+    o.set_boot_sparse(n)
+    U = _embedding_n(n)
+    rng = np.random.default_rng(21)
+    z = rng.normal(size=n) + 1j * rng.normal(size=n)
+    v = o.boot_sparse_apply(1, np.tile(z, 2))
+    ref = np.linalg.solve(U, z)[_bitrev(n)] / (2 * (P["boot_K"] + 1)) * n / o.slots
+    assert np.abs(v[:n] - ref).max() < 1e-12 * np.abs(ref).max() * n
+    assert np.abs(v[n:]).max() == 0.0
+    a, b = rng.normal(size=n), rng.normal(size=n)
+    w = o.boot_sparse_apply(0, np.concatenate([a, b]))
+    zn = np.empty(n, dtype=complex)
+    zn[_bitrev(n)] = a + 1j * b
+    ref = U @ zn * 2.0 ** P["boot_ratio"] / (2 * np.pi)
+    assert np.abs(w[:n] - ref).max() < 1e-12 * np.abs(ref).max() * n
+    assert np.abs(w[n:] - ref).max() < 1e-12 * np.abs(ref).max() * n
+    # U' is the embedding restricted to the subring: a polynomial in X^(N/2n)
+    # has these slot values at the first n roots, repeated with period n
+    E = _embedding(o)
+    t = rng.normal(size=2 * n)
+    poly = np.zeros(o.n)
+    poly[:: o.n // (2 * n)] = t
+    full = E @ poly
+    assert np.abs(full[:n] - U @ (t[:n] + 1j * t[n:])).max() < 1e-9
+    assert np.abs(full[n: 2 * n] - full[:n]).max() < 1e-9
+
+
+@pytest.fixture(scope="module")
+def sparse_boot():
+    o = make_oracle("tiny_boot")
+    o.set_boot_sparse(SPARSE_N)
+    steps = sorted(set(o.boot_steps()) | set(argmax_rotation_steps(4, 4, o.slots)))
+    o.keygen(77, steps)
+    return o
+
+
+def test_sparse_bootstrap_parameters_are_checked():
+    o = make_oracle("tiny_boot")
+    # a power of two, 2n <= N/2, at least one radix-2 stage per group
+    for bad in [3, 24, 4, o.slots, 2 * o.slots]:
+        with pytest.raises(ValueError):
+            o.set_boot_sparse(bad)
+    o.set_boot_sparse(8)
+    # the trace steps n, 2n, ..., N/4 and RotR(n) are among the bootstrapping steps
+    st = set(o.boot_steps())
+    assert all(r in st for r in (8 << k for k in range(int(np.log2(o.slots // 8)))))
+    assert o.slots - 8 in st
+
+
+@pytest.mark.parametrize("kind", ["uniform", "few"])
+def test_sparse_bootstrap_keeps_the_first_slots(sparse_boot, kind):
+    """Slots [0, n) of the input come back, repeated with period n over all N/2
+    slots, whatever the other slots held; same level and scale as the full
+    pipeline, within 2^-16 on N = 2^10."""
+    o = sparse_boot
+    n = SPARSE_N
+    rng = np.random.default_rng(31)
+    z = rng.uniform(-1, 1, o.slots)
+    if kind == "few":
+        z[5:n] = 0.0
+    sc = 2.0**49
+    ct = o.lower(o.encrypt(o.encode(z, sc), sc, 13), 1)
+    o.reset_counters()
+    b = o.bootstrap_sparse(ct)
+    assert b.level == o.boot_out_level() and b.scale == 2.0 ** P["log_scale"]
+    got = o.decrypt_decode(b, o.slots)
+    assert np.abs(got - np.tile(z[:n], o.slots // n)).max() < 2.0**-16
+    cnt = o.counters()
+    # two traces of log2(N/2n) rotations, conjugation, the join rotation, and the
+    # linear transforms' baby and giant steps; EvalMod's products once, not twice
+    assert cnt["refresh"] == 1
+    assert cnt["rotate"] >= 2 * int(np.log2(o.slots // n)) + 2
+
+
+def test_argmax_with_sparse_bootstrapping(sparse_boot):
+    """Algorithm 1 (single query, C' = 4 so slots [0, 8) are live) with every
+    refresh a sparse-slot bootstrap returns the plaintext argmax, and z follows
+    the FP64 simulation."""
+    o = sparse_boot
+    K, C = 2, 4
+    y = W.logits(9, 5, K, C)
+    lo, hi = W.d_bounds(K)
+    o.reset_counters()
+    z = o.decrypt_decode(o.eval_argmax(o.encrypt_logits(y, 3), K, C, lo, hi, 4), C)
+    cnt = o.counters()
+    assert cnt["refresh"] >= 1 and cnt["sign"] == 3
+    zs = sim.t1_argmax(y, lo, hi, o.slots)[:C]
+    assert np.abs(z - zs).max() < 1e-3
+    assert int(np.argmax(z)) == sim.t0_argmax(y)[0]

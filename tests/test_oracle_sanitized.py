@@ -89,15 +89,19 @@ DRIVER = r"""
 #include <cstdio>
 #include "boot_tables.h"
 int main() {
-  // every group of both transforms at N = 2^10 and N = 2^12, 2 and 3 groups
+  // every group of both transforms at N = 2^10 and N = 2^12, 2 and 3 groups,
+  // full-slot and sparse-slot (n = 8 and 32: the widened groups included)
   double cheb[64];
   for (int log_n : {10, 12})
-    for (int groups : {2, 3})
-      for (int inverse : {0, 1})
-        for (int g = 0; g < groups; ++g) {
-          secpe::BootGroupTable t = secpe::boot_group_table(log_n, groups, 12, 8, inverse, g);
-          if (t.diags.empty()) return 2;
-        }
+    for (int log_ns : {log_n - 1, 3, 5})
+      for (int groups : {2, 3})
+        for (int inverse : {0, 1})
+          for (int g = 0; g < groups; ++g) {
+            secpe::BootGroupTable t = secpe::boot_group_table(log_n, log_ns, groups, 12, 8, inverse, g);
+            if (t.diags.empty()) return 2;
+            for (const secpe::BootDiag& d : t.diags)
+              if ((int)d.re.size() != t.ns || d.off < 0 || d.off >= t.ns) return 3;
+          }
   secpe::boot_cheb_coeffs(24, 4, 31, cheb);
   std::printf("tables ok %.3f\n", cheb[1]);
   return 0;

@@ -36,26 +36,33 @@ PARAMS = {
     # Bootstrapping sets: sparse secret of expected weight h; EvalMod on
     # |t / q_0| <= boot_K + 1 with a degree-boot_deg Chebyshev interpolant and
     # boot_r double angles; q_0 / T_b = 2^boot_ratio; boot_groups levels for each
-    # linear transform; boot_refresh = 1 makes every refresh a bootstrap.
+    # linear transform; boot_refresh = 1 makes every refresh a bootstrap;
+    # boot_sparse = n adds the sparse-slot bootstrap of slots [0, n), which
+    # refreshes of a single query take (it reads slots [0, 2C') only).
     # 2 * 3 + 6 + 3 = 15 levels on N = 2^10 (a bootstrapped ciphertext has 10 left)
     "tiny_boot": dict(log_n=10, n_q=26, q_bits=50, n_p=8, p_bits=51, log_scale=50, dg=2, df=2, min_level=1,
-                      h=64, boot_K=12, boot_r=3, boot_deg=31, boot_ratio=8, boot_groups=3, boot_refresh=1),
+                      h=64, boot_K=12, boot_r=3, boot_deg=31, boot_ratio=8, boot_groups=3, boot_refresh=1,
+                      boot_sparse=32),
     # the tiny_boot chain at N = 2^13: the two-pass NTT, the fused ModUp /
     # inner-product kernels and baby-step giant-step groups of n1 = 8 baby
     # steps, as at N = 2^16 (a bootstrapped ciphertext has 10 levels left)
     "p13_boot": dict(log_n=13, n_q=26, q_bits=50, n_p=8, p_bits=51, log_scale=50, dg=2, df=2, min_level=1,
-                     h=64, boot_K=12, boot_r=3, boot_deg=31, boot_ratio=8, boot_groups=3, boot_refresh=1),
+                     h=64, boot_K=12, boot_r=3, boot_deg=31, boot_ratio=8, boot_groups=3, boot_refresh=1,
+                     boot_sparse=32),
     # L = 35 chain primes as in the paper (Sec. 4.1); 2 * 3 + 6 + 4 = 16 levels,
-    # a bootstrapped ciphertext has 18 left
+    # a bootstrapped ciphertext has 18 left.  boot_sparse: the sparse-slot
+    # bootstrap keeps slots [0, 64), enough for a single query up to C' = 32
     "full_boot": dict(log_n=16, n_q=35, q_bits=50, n_p=12, p_bits=51, log_scale=50, dg=2, df=2, min_level=1,
-                      h=192, boot_K=24, boot_r=4, boot_deg=31, boot_ratio=8, boot_groups=3, boot_refresh=1),
+                      h=192, boot_K=24, boot_r=4, boot_deg=31, boot_ratio=8, boot_groups=3, boot_refresh=1,
+                      boot_sparse=64),
     # The paper's budget (Sec. 4.1): N = 2^16, L = 35 chain primes, log QP <=
     # 1763 bits, 14 levels for bootstrapping.  35 primes of ~47 bits and 2
     # special primes below 2^51 (dnum 18) make log QP = 1747; 2 + 2 groups,
     # degree 31 and 4 double angles make 2 * 2 + 6 + 4 = 14 levels, leaving a
     # bootstrapped ciphertext 20 levels.
     "full_boot128": dict(log_n=16, n_q=35, q_bits=47, n_p=2, p_bits=51, log_scale=47, dg=2, df=2, min_level=1,
-                         h=192, boot_K=24, boot_r=4, boot_deg=31, boot_ratio=8, boot_groups=2, boot_refresh=1),
+                         h=192, boot_K=24, boot_r=4, boot_deg=31, boot_ratio=8, boot_groups=2, boot_refresh=1,
+                         boot_sparse=64),
 }
 
 CLIP = 6.0
