@@ -128,7 +128,34 @@ def tenant_contexts(g, params, n_tenants):
     return gs
 
 
-def serve(gs, n, warm, qps=None, frac=0.7, max_active=96, distinct=256):
+def _pshape(K, C):
+    return (1 << max(0, (K - 1).bit_length()), 1 << max(0, (C - 1).bit_length()))
+
+
+def alone_latency_ms(g, distinct=256):
+    """Latency of each padded shape (K', C') of the config-5 mix alone on the
+    plain path (one query of the shape, the faster of two runs): the yardstick
+    of a served request's slowdown."""
+    out = {}
+    for i in range(distinct):
+        q = W.query(5, i)
+        sh = _pshape(q["K"], q["C"])
+        if sh in out:
+            continue
+        ct = g.encrypt(q["logits"], q["encrypt_seed"])
+        best = None
+        for _ in range(2):
+            g.sync()
+            t0 = time.perf_counter()
+            g.eval_argmax(ct, q["K"], q["C"], q["d_min"], q["d_max"], q["refresh_seed"], owner=g.owner)
+            g.sync()
+            t = (time.perf_counter() - t0) * 1e3
+            best = t if best is None else min(best, t)
+        out[sh] = best
+    return out
+
+
+def serve(gs, n, warm, qps=None, frac=0.7, max_active=96, distinct=256, alone=None):
     """Config 5 mix (K ~ U{4..32}, C ~ U{2..20}) over len(gs) tenants.  Query
     i is config-5 query i mod 'distinct', encrypted under the keys of tenant
     (i mod distinct) mod len(gs) and served by that tenant's server.  The
@@ -220,6 +247,14 @@ def serve(gs, n, warm, qps=None, frac=0.7, max_active=96, distinct=256):
     del keep
     lat = np.array([(finish[t] - arrive[t]) * 1e3 for t in order])
     span = max(finish[t] for t in order) - min(arrive[t] for t in order)
+    slow = None
+    if alone:
+        # each request against its own padded shape alone: the mix's spread of
+        # shapes (one to five QuickMax steps) is taken out of the latency
+        sd = np.array([(finish[t] - arrive[t]) * 1e3 / alone[_pshape(qs[served[t][0]]["K"], qs[served[t][0]]["C"])]
+                       for t in order])
+        slow = {"p50": round(float(np.percentile(sd, 50)), 2), "p99": round(float(np.percentile(sd, 99)), 2),
+                "what": "served latency over the latency of the same padded shape alone on the plain path"}
     return {
         "workload": "config5_poisson", "tenants": T, "servers": T, "requests": n, "warmup_requests": warm,
         "distinct_queries": nd, "qps": round(qps, 2),
@@ -229,6 +264,7 @@ def serve(gs, n, warm, qps=None, frac=0.7, max_active=96, distinct=256):
         "max_active": cap * T,
         "index_ok": f"{ok}/{len(served)}", "index_ok_at_margin_2^-10": f"{ok_m}/{n_m}",
         "index_what": "every served result (warm-up included) decrypted after the run, against the plaintext argmax",
+        "slowdown_vs_alone": slow,
     }
 
 
@@ -893,13 +929,16 @@ def main():
         result["keyswitch"] = keyswitch_rate(g, params)
     if args.serve:
         gs = tenant_contexts(g, params, args.tenants)
+        alone = alone_latency_ms(g)
+        _log(f"alone latency per padded shape (ms): {sorted((k, round(v, 1)) for k, v in alone.items())}")
         _log(f"serving run: {args.tenants} tenants, {args.serve} + {args.serve // 10} warm-up requests, "
              f"Poisson arrivals at 0.7x the saturated rate")
-        result["serving"] = serve(gs, args.serve, args.serve // 10)
+        result["serving"] = serve(gs, args.serve, args.serve // 10, alone=alone)
+        result["serving"]["alone_ms_by_shape"] = {f"{k[0]}x{k[1]}": round(v, 2) for k, v in sorted(alone.items())}
         sat = result["serving"]["saturated_argmax_per_s"]
         sweep = []
         for frac in (0.25, 0.5, 0.9):
-            r = serve(gs, 160, 20, qps=frac * sat)
+            r = serve(gs, 160, 20, qps=frac * sat, alone=alone)
             r["load"] = frac
             sweep.append(r)
         result["serving_sweep"] = {"what": "the same mix at fractions of the saturated rate", "runs": sweep}
@@ -913,7 +952,7 @@ def main():
             h.share_keys(g)
             h.owner = h.key_owner()
             shared.append(h)
-        r = serve(shared, 500, 50)
+        r = serve(shared, 500, 50, alone=alone)
         r["tenants"] = 1
         r["what"] = "one key owner, 4 servers on 4 streams sharing its keys (secpe_keys_share), load 0.7"
         result["serving_one_owner_4_streams"] = r
