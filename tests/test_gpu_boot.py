@@ -244,6 +244,39 @@ def test_bootstrap_errors_are_reported(pair):
         g.boot_step(9, g.import_(ct.export(), ct.scale))
 
 
+def test_sparse_bootstrap_parameters_and_errors():
+    """sparse_slots must be a power of two n with 2n <= N/2 and log2 n >= groups;
+    without it the sparse-slot entry points refuse (SECPE_EINVAL) and every
+    refresh takes the full-slot bootstrap."""
+    from paper_2502_00847_amd.secpe import Context, SecpeError
+    g = Context(dict(P, boot_sparse=0))
+    for bad in (3, 4, 24, g.slots):
+        with pytest.raises(SecpeError):
+            g.set_boot(P["h"], P["boot_K"], P["boot_r"], P["boot_deg"], P["boot_ratio"], P["boot_groups"],
+                       P["boot_refresh"], bad)
+    g.set_boot(P["h"], P["boot_K"], P["boot_r"], P["boot_deg"], P["boot_ratio"], P["boot_groups"],
+               P["boot_refresh"], 0)
+    o = Oracle.from_params(dict(P, boot_sparse=0))
+    steps = sorted(set(g.boot_steps()) | set(argmax_rotation_steps(4, 4, g.slots)), key=lambda v: (v < 0, v))
+    assert steps == sorted(set(o.boot_steps()) | set(argmax_rotation_steps(4, 4, g.slots)),
+                           key=lambda v: (v < 0, v))
+    g.keygen(SEED, steps)
+    o.keygen(SEED, steps)
+    g.boot_setup()
+    ct = _enc(o, np.random.default_rng(3).uniform(-1, 1, g.slots), 2.0**50, 8, 2)
+    with pytest.raises(SecpeError):
+        g.bootstrap([g.import_(ct.export(), ct.scale)], sparse=True)
+    with pytest.raises(SecpeError):
+        g.boot_step(6, g.import_(ct.export(), ct.scale))
+    # a single query's refreshes take the full-slot bootstrap here, as in the oracle
+    K, C = 2, 4
+    y = W.logits(9, 5, K, C)
+    lo, hi = W.d_bounds(K)
+    zo = o.eval_argmax(o.encrypt_logits(y, 3), K, C, lo, hi, 4)
+    zg = g.eval_argmax(g.encrypt(y, 3), K, C, lo, hi, 4)
+    _same(g, zg, zo)
+
+
 @pytest.fixture(scope="module")
 def full():
     from paper_2502_00847_amd.secpe import Context
