@@ -2068,6 +2068,7 @@ std::vector<CT> Builder::bootstrap(const std::vector<CT>& all, bool sparse) {
 }
 
 std::vector<CT> Builder::subsum(const std::vector<CT>& in, int n) {
+  if (n < 1 || 2 * n > C.N / 2) { fail(-1, "subsum: n must satisfy 2n <= N/2"); return {}; }
   std::vector<CT> cur = in;
   bool own = false;
   for (int64_t r = n; r < C.N / 2; r *= 2) {
@@ -2082,20 +2083,6 @@ std::vector<CT> Builder::subsum(const std::vector<CT>& in, int n) {
       for (CT& v : cur) free_ct(v);
     cur = nx;
     own = true;
-  }
-  if (!own) {
-    // n = N/2: nothing to sum; hand back copies the caller owns
-    std::vector<std::pair<CT, CT>> pr;
-    std::vector<CT> z;
-    for (const CT& x : cur) {
-      EwJob e{};
-      CT o = new_ct(x.level, x.scale);
-      e.o0 = c0(o); e.o1 = c1(o); e.a0 = c0(x); e.a1 = c1(x);
-      e.n_limbs = x.level + 1; e.n_chain = x.level + 1; e.op = EW_COPY;
-      ew({e});
-      z.push_back(o);
-    }
-    cur = z;
   }
   return cur;
 }
