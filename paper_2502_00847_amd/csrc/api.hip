@@ -328,6 +328,7 @@ extern "C" int secpe_keygen(secpe_ctx* x, uint64_t seed, const int64_t* steps, i
   if (rc) return rc;
   drop_graphs(c);
   c.keys.clear();
+  c.keys_perm.clear();
   x->key_list.clear();
   x->evk = evk;
   for (int kk = 0; kk <= n_steps; ++kk) {
@@ -349,6 +350,7 @@ extern "C" int secpe_keys_share(secpe_ctx* dst, const secpe_ctx* src) {
   if (a.keys.empty()) return set_err(SECPE_EINVAL, "key source has no keys");
   drop_graphs(b);
   b.keys = a.keys;
+  b.keys_perm.clear();
   dst->evk = src->evk;
   dst->key_list = src->key_list;
   return 0;
@@ -1744,6 +1746,7 @@ extern "C" int secpe_set_boot(secpe_ctx* x, const secpe_boot_params* bp, int* ou
   c.boot_cts_sp.clear();
   c.boot_stc_sp.clear();
   c.boot_sparse = 0;
+  c.keys_perm.clear();
   c.boot_ready = false;
   c.boot_mono = nullptr;
   c.boot_mode = 0;
@@ -1829,6 +1832,28 @@ static std::vector<int64_t> boot_group_es(const BootGroup& G, int len) {
   return es;
 }
 
+// Galois elements of the sparse-slot transforms' baby steps that have a key
+static std::vector<uint64_t> sparse_baby_galois(const Ctx& c) {
+  std::vector<uint64_t> gs;
+  const int64_t S = c.N / 2;
+  for (const std::vector<BootGroup>* list : {&c.boot_cts_sp, &c.boot_stc_sp})
+    for (const BootGroup& G : *list)
+      for (int b = 1; b < G.n1; ++b) {
+        const uint64_t g = c.galois((int64_t)G.delta * b % S);
+        if (c.keys.count(g)) gs.push_back(g);
+      }
+  std::sort(gs.begin(), gs.end());
+  gs.erase(std::unique(gs.begin(), gs.end()), gs.end());
+  return gs;
+}
+
+// g^-1 mod 2N for odd g (Newton's iteration doubles the correct low bits)
+static uint64_t galois_inverse(uint64_t g, uint64_t m2n) {
+  uint64_t v = g;
+  for (int i = 0; i < 6; ++i) v *= 2 - g * v;
+  return v & (m2n - 1);
+}
+
 extern "C" size_t secpe_boot_key_bytes(secpe_ctx* x) {
   if (!x || x->c.boot_out_level < 0) return 0;
   Ctx& c = x->c;
@@ -1844,6 +1869,8 @@ extern "C" size_t secpe_boot_key_bytes(secpe_ctx* x) {
           boot_group_table(c.log_n, G.log_ns, c.boot_groups, c.boot_K, c.boot_ratio, inv, G.g).diags.size();
       total += nd * (size_t)(G.level + 1) * c.limb_bytes();
     }
+  // the permuted keys of the sparse transforms' baby steps
+  total += sparse_baby_galois(c).size() * c.key_bytes();
   return total;
 }
 
@@ -1909,6 +1936,7 @@ extern "C" int secpe_boot_setup(secpe_ctx* x, void* buf_dev, size_t bytes) {
         G.e.push_back(e);
         G.pt.push_back(cur);
         cur += (size_t)(G.level + 1) * N;
+        if ((char*)cur > (char*)buf_dev + bytes) return set_err(SECPE_EINVAL, "boot key buffer too small");
         re.push_back(std::move(r));
         im.push_back(std::move(i2));
         gs.push_back(std::move(gv));
@@ -1967,6 +1995,34 @@ extern "C" int secpe_boot_setup(secpe_ctx* x, void* buf_dev, size_t bytes) {
       if (rc) return rc;
       rc = sync(c);
       if (rc) return rc;
+    }
+  }
+  // each sparse baby step's key with every limb taken through X -> X^(g^-1);
+  // destinations are laid out here, once (run_client builds fn twice: a dry
+  // run to size the workspace, then the real one)
+  c.keys_perm.clear();
+  {
+    const std::vector<uint64_t> gs = sparse_baby_galois(c);
+    const int nl = c.dnum * 2 * c.n_mod;
+    std::vector<std::pair<uint64_t, double*>> made;
+    for (uint64_t g : gs) {
+      made.push_back({g, cur});
+      cur += (size_t)nl * N;
+    }
+    if ((char*)cur > (char*)buf_dev + bytes) return set_err(SECPE_EINVAL, "boot key buffer too small");
+    auto fn = [&](Builder& b) {
+      std::vector<AutoJob> j;
+      for (auto& kv : made)
+        j.push_back(AutoJob{c.keys.at(kv.first), kv.second, nl, nl,
+                            (uint32_t)galois_inverse(kv.first, 2ull * (uint64_t)N), 0});
+      b.automorph(j);
+    };
+    if (!gs.empty()) {
+      int rc = run_client(x, fn);
+      if (rc) return rc;
+      rc = sync(c);
+      if (rc) return rc;
+      for (auto& kv : made) c.keys_perm[kv.first] = kv.second;
     }
   }
   drop_graphs(c);

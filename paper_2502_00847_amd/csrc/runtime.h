@@ -120,6 +120,10 @@ struct Ctx {
   double q0inv_q1 = 0.0;
   // keys
   std::map<uint64_t, const double*> keys;  // Galois element -> key; 0 = relinearisation
+  // Galois element g -> its key with every limb taken through X -> X^(g^-1)
+  // (NTT-domain permutation), for the hoisted baby steps of the sparse-slot
+  // transforms; built by secpe_boot_setup in its buffer, cleared with the keys
+  std::map<uint64_t, const double*> keys_perm;
   // descriptor arena
   char* arena = nullptr;
   size_t arena_bytes = 0;

@@ -687,7 +687,7 @@ void Builder::ks_front(const std::vector<KsItem>& items, std::vector<KsTmp>& tmp
       j_fwd_ext.push_back(NttJob{e, e, n_ext, nc, lo, hi});
     }
     InnerJob in{it.d, t.ext, it.key, t.acc, it.top0, it.top1, C.p_mod_q, nc, n_ext, nd, alpha};
-    // section (d) accounting: ciphertext limbs in and out
+    // algorithmic-byte accounting: ciphertext limbs in and out
     ks_alg_limbs += 3 * (int64_t)nc;
     in.inv_from = fused ? (merged ? l : l + 1) : n_ext;
     in.d_square = it.square ? 1 : 0;
@@ -794,12 +794,19 @@ Builder::Hoisted Builder::hoist(const std::vector<CT>& in) {
 }
 
 // ext limbs on a digit's own primes are never written (the inner product
-// reads those from d); the automorphism permutes them along unread
+// reads those from d); the automorphism permutes them along unread.
+// With a permuted key (keys_perm) the raised digits are not permuted at all:
+// sum_j X^g(ext_j) key_j = X^g(sum_j ext_j X^(g^-1)(key_j)), and the ModDown
+// commutes with X -> X^g residue for residue (the inverse and forward
+// transforms, the centred conversion and the division by P all do), so the
+// inner product of the unpermuted digits with the permuted key, the ModDown
+// onto c0, and one permutation of the two result polynomials give the same
+// residues as permuting the digits first.
 std::vector<CT> Builder::rotate_hoisted(const Hoisted& h, const std::vector<int64_t>& steps) {
   const int N = C.N, alpha = C.alpha, n_p = C.n_p;
   const size_t mark = scratch_mark();
   std::vector<CT> out;
-  std::vector<AutoJob> j_a;
+  std::vector<AutoJob> j_a, j_post;
   std::vector<InnerJob> j_in;
   std::vector<KsItem> ks;
   std::vector<KsTmp> tmp;
@@ -807,10 +814,13 @@ std::vector<CT> Builder::rotate_hoisted(const Hoisted& h, const std::vector<int6
   for (int64_t st : steps) {
     const uint64_t g = C.galois(st);
     const double* gk = nullptr;
+    const double* pk = nullptr;
     if (g != 1) {
       auto it = C.keys.find(g);
       gk = it != C.keys.end() ? it->second : (dry ? C.T.mod : nullptr);
       if (!gk) { fail(-4, "no Galois key for rotation " + std::to_string(st)); return {}; }
+      auto pit = C.keys_perm.find(g);
+      if (pit != C.keys_perm.end()) pk = pit->second;
     }
     for (size_t i = 0; i < h.in.size(); ++i) {
       const CT& x = h.in[i];
@@ -824,19 +834,31 @@ std::vector<CT> Builder::rotate_hoisted(const Hoisted& h, const std::vector<int6
         out.push_back(o);
         continue;
       }
-      double* d = scratch((size_t)nc * N);
-      double* es = scratch((size_t)nd * n_ext * N);
       double* acc = scratch((size_t)2 * n_ext * N);
-      j_a.push_back(AutoJob{c0(x), c0(o), nc, nc, (uint32_t)g, 0});
-      j_a.push_back(AutoJob{c1(x), d, nc, nc, (uint32_t)g, 0});
-      j_a.push_back(AutoJob{h.ext[i], es, nd * n_ext, nd * n_ext, (uint32_t)g, 0});
-      InnerJob in{d, es, gk, acc, nullptr, nullptr, C.p_mod_q, nc, n_ext, nd, alpha};
-      in.inv_from = n_ext;
-      in.d_square = 0;
-      j_in.push_back(in);
-      ks.push_back(KsItem{d, x.level, gk, c0(o), nullptr, c0(o), c1(o), nullptr, nullptr, false});
-      tmp.push_back(KsTmp{nullptr, es, acc, n_ext});
-      // section (d) accounting: ciphertext limbs in and out, each key once
+      if (pk) {
+        double* r = scratch((size_t)2 * nc * N);
+        InnerJob in{c1(x), h.ext[i], pk, acc, nullptr, nullptr, C.p_mod_q, nc, n_ext, nd, alpha};
+        in.inv_from = n_ext;
+        in.d_square = 0;
+        j_in.push_back(in);
+        ks.push_back(KsItem{c1(x), x.level, pk, c0(x), nullptr, r, r + (size_t)nc * N, nullptr, nullptr, false});
+        tmp.push_back(KsTmp{nullptr, h.ext[i], acc, n_ext});
+        j_post.push_back(AutoJob{r, c0(o), nc, nc, (uint32_t)g, 0});
+        j_post.push_back(AutoJob{r + (size_t)nc * N, c1(o), nc, nc, (uint32_t)g, 0});
+      } else {
+        double* d = scratch((size_t)nc * N);
+        double* es = scratch((size_t)nd * n_ext * N);
+        j_a.push_back(AutoJob{c0(x), c0(o), nc, nc, (uint32_t)g, 0});
+        j_a.push_back(AutoJob{c1(x), d, nc, nc, (uint32_t)g, 0});
+        j_a.push_back(AutoJob{h.ext[i], es, nd * n_ext, nd * n_ext, (uint32_t)g, 0});
+        InnerJob in{d, es, gk, acc, nullptr, nullptr, C.p_mod_q, nc, n_ext, nd, alpha};
+        in.inv_from = n_ext;
+        in.d_square = 0;
+        j_in.push_back(in);
+        ks.push_back(KsItem{d, x.level, gk, c0(o), nullptr, c0(o), c1(o), nullptr, nullptr, false});
+        tmp.push_back(KsTmp{nullptr, es, acc, n_ext});
+      }
+      // algorithmic-byte accounting: ciphertext limbs in and out, each key once
       ks_alg_limbs += 3 * (int64_t)nc;
       int64_t& kl = key_limbs[gk];
       kl = std::max(kl, (int64_t)2 * nd * n_ext);
@@ -848,6 +870,7 @@ std::vector<CT> Builder::rotate_hoisted(const Hoisted& h, const std::vector<int6
     automorph(j_a);
     inner(j_in, false);
     ks_back(ks, tmp, false);
+    automorph(j_post);
     counters[1] += (int64_t)ks.size();
   }
   scratch_release(mark);
