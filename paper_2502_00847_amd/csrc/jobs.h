@@ -117,11 +117,14 @@ struct ModUpJob {
 
 // Conv_{B->Q} with centred digits: src = the limbs of B (coefficient domain) ->
 // dst chain limbs 0..n_chain-1.  B is the special primes (first_prime < 0) or
-// prime first_prime followed by the special primes.
+// prime first_prime followed by the special primes.  With cinv null, src
+// already holds the canonical y_b = [x_b (B/b)^-1]_b (the inverse transform's
+// last pass scaled by them).  The column-fused kernel writes dst after the
+// forward transform's column pass.
 struct ModDownJob {
   const double* src;    // [|B|][N]
   double* dst;          // [n_chain][N]
-  const double* cinv;   // [|B|] (B/b)^-1 mod b
+  const double* cinv;   // [|B|] (B/b)^-1 mod b, or null (see above)
   const double* chat;   // [n_chain][|B|] (B/b) mod q_i
   int n_chain, first_prime;
 };

@@ -26,6 +26,10 @@ void launch_inner_row(const DevTables& T, const InnerJob* jobs, int n_jobs, int 
 // source is the digit-scaled inverse transform (NttJob::ek on the inverse).
 // eg: output limbs per workgroup (2 or 4; a tunable)
 void launch_modup_col(const DevTables& T, const ModUpJob* jobs, int n_jobs, int max_ext, int eg, hipStream_t s);
+// The ModDown's centred conversion fused with the column pass of its outputs'
+// forward NTT (source prescaled by the inverse transform: ModDownJob::cinv
+// null); the row pass, with the combine as its epilogue, follows as a launch.
+void launch_moddown_col(const DevTables& T, const ModDownJob* jobs, int n_jobs, int max_chain, hipStream_t s);
 void launch_ew(const DevTables& T, const EwJob* jobs, int n_jobs, int max_limbs, hipStream_t s);
 void launch_modup(const DevTables& T, const ModUpJob* jobs, int n_jobs, hipStream_t s);
 void launch_moddown_conv(const DevTables& T, const ModDownJob* jobs, int n_jobs, hipStream_t s);

@@ -1001,6 +1001,80 @@ __global__ __launch_bounds__(256) void k_modup_col(const ModUpJob* __restrict__ 
     __syncthreads();
   }
 }
+// The centred conversion B -> Q_l of the ModDown fused with the column pass
+// of the forward transform of its outputs (N > 2^12): src holds the canonical
+// y_b = [x_b (B/b)^-1]_b (the inverse transform's last pass applied (B/b)^-1),
+// taken centred in (-b/2, b/2]; a workgroup owns one column tile and a group
+// of EG chain limbs t, streams the |B| source limbs through registers once,
+// accumulating out_t = sum_b y_b (B/b) mod q_t for the group, and runs the
+// column pass on each out_t into dst limb t.  The forward transform's row pass
+// follows with the ModDown or merged combine as its epilogue.  Grid (tile,
+// group, job) as for the ModUp: the groups of a tile share an XCD's L2.
+template <int LOGS, int G, int EG>
+__global__ __launch_bounds__(256) void k_moddown_col(const ModDownJob* __restrict__ jobs, DevTables T) {
+  extern __shared__ double lds[];
+  constexpr int RB = LOGS - 4;
+  constexpr int NB = 1 << RB;
+  const ModDownJob J = jobs[blockIdx.z];
+  const int g0 = blockIdx.y * EG;
+  if (g0 >= J.n_chain) return;
+  const int ng = min(EG, J.n_chain - g0);
+  const int extra = J.first_prime >= 0 ? 1 : 0;
+  const int nb = T.n_p + extra;
+  const int log_n = T.log_n;
+  const int N = 1 << log_n;
+  const int k1 = log_n - LOGS;
+  const int C = N >> LOGS;
+  const int t = threadIdx.x;
+  const int va = t % G, la = t / G;
+  const int c0 = blockIdx.x * G;
+  int ee[EG];
+  Mod me[EG];
+#pragma unroll
+  for (int g = 0; g < EG; ++g) {
+    ee[g] = min(g0 + g, J.n_chain - 1);
+    me[g] = Mod{KPTR(T.mod)[ee[g]], KPTR(T.minv)[ee[g]]};
+  }
+  double acc[EG][16];
+#pragma unroll
+  for (int g = 0; g < EG; ++g)
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[g][k] = 0.0;
+  for (int i = 0; i < nb; ++i) {
+    const int pr = i < extra ? J.first_prime : T.n_q + i - extra;
+    const double b = KPTR(T.mod)[pr];
+    double y[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) y[k] = CGPTR(J.src)[(size_t)i * N + (size_t)(k * NB + la) * C + c0 + va];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) y[k] = 2.0 * y[k] > b ? y[k] - b : y[k];
+#pragma unroll
+    for (int g = 0; g < EG; ++g) {
+      const double c = KPTR(J.chat)[(size_t)ee[g] * nb + i];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        acc[g][k] += mul_mod(y[k], c, me[g]);
+        if (i & 1) acc[g][k] = red(acc[g][k], me[g]);
+      }
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < EG; ++g) {
+    if (g >= ng) break;
+    kdbl* tw = KPTR(T.psi) + (size_t)ee[g] * N;
+    kdbl* twq = KPTR(T.psiq) + (size_t)ee[g] * N;
+    double x[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) x[k] = red(acc[g][k], me[g]);
+    fwd_col_from_regs<LOGS, G>(x, lds, GPTR(J.dst) + (size_t)ee[g] * N, c0, k1, tw, twq, me[g]);
+    // the next limb's column pass reuses the LDS tile
+    __syncthreads();
+  }
+}
+template __global__ void k_moddown_col<8, 16, 4>(const ModDownJob* __restrict__, DevTables);
+template __global__ void k_moddown_col<7, 32, 4>(const ModDownJob* __restrict__, DevTables);
+template __global__ void k_moddown_col<6, 64, 4>(const ModDownJob* __restrict__, DevTables);
+
 #define MODUP_INST(EG)                                                              \
   template __global__ void k_modup_col<8, 16, EG>(const ModUpJob* __restrict__, DevTables); \
   template __global__ void k_modup_col<7, 32, EG>(const ModUpJob* __restrict__, DevTables); \
@@ -1287,7 +1361,7 @@ __global__ __launch_bounds__(256) void k_moddown_conv(const ModDownJob* __restri
     if (i < nb) {
       const int pr = i < extra ? J.first_prime : T.n_q + i - extra;
       const Mod mi{KPTR(T.mod)[pr], KPTR(T.minv)[pr]};
-      const double z = canon(mul_mod(y[i], KPTR(J.cinv)[i], mi), mi);
+      const double z = J.cinv ? canon(mul_mod(y[i], KPTR(J.cinv)[i], mi), mi) : y[i];
       y[i] = 2.0 * z > mi.p ? z - mi.p : z;
     }
   }
@@ -1756,6 +1830,19 @@ void launch_modup_col(const DevTables& T, const ModUpJob* jobs, int n_jobs, int 
     LAUNCH_MODUP(4)
   }
 #undef LAUNCH_MODUP
+}
+
+void launch_moddown_col(const DevTables& T, const ModDownJob* jobs, int n_jobs, int max_chain, hipStream_t s) {
+  if (n_jobs <= 0 || max_chain <= 0) return;
+  const int log_n = T.log_n;
+  const int k1 = log_n / 2;   // column length of the two-pass split
+  const int g = k1 == 8 ? 16 : k1 == 7 ? 32 : 64;
+  constexpr int eg = 4;
+  dim3 grid((1 << (log_n - k1)) / g, (max_chain + eg - 1) / eg, n_jobs);
+  const size_t lds = ntt_lds_bytes(k1, g);
+  if (k1 == 8) hipLaunchKernelGGL((k_moddown_col<8, 16, eg>), grid, dim3(256), lds, s, jobs, T);
+  else if (k1 == 7) hipLaunchKernelGGL((k_moddown_col<7, 32, eg>), grid, dim3(256), lds, s, jobs, T);
+  else hipLaunchKernelGGL((k_moddown_col<6, 64, eg>), grid, dim3(256), lds, s, jobs, T);
 }
 
 void launch_inner_row(const DevTables& T, const InnerJob* jobs, int n_jobs, int max_ext, hipStream_t s) {

@@ -116,6 +116,11 @@ struct Ctx {
   const double* rr_cinv = nullptr;   // [n_q][alpha+1] (B/b)^-1 mod b
   const double* rr_chat = nullptr;   // [n_q][n_q][alpha+1] (B/b) mod q_t
   const double* rr_inv = nullptr;    // [n_q][n_q] (P q_l)^-1 mod q_t
+  // the inverse transform feeding a conversion from B scales limb b by
+  // N^-1 (B/b)^-1 mod b: B = P at [k] (special prime k), B = {q_l} u P at
+  // [l][l + i] (i = 0: q_l; i = 1 + k: special prime k)
+  const double* md_ytab = nullptr;   // [alpha]
+  const double* rr_ytab = nullptr;   // [n_q][n_q + alpha]
   const double* crt_tab = nullptr;   // [n_q][2]
   double q0inv_q1 = 0.0;
   // keys
@@ -163,7 +168,7 @@ void drop_graphs(Ctx& c);
 // ---------------------------------------------------------------------------
 // command list: descriptors in one blob, launches replayed in order
 // ---------------------------------------------------------------------------
-enum CmdKind { C_NTT, C_NTT_FIRST, C_NTT_SECOND, C_EW, C_MODUP, C_MODUP_COL, C_MODDOWN, C_INNER, C_INNER_ROW, C_AUTO, C_LIFT, C_SAMPLE, C_INTSPREAD, C_ENCODE, C_DECODE, C_RAISE, C_BSGS, C_FFTENC,
+enum CmdKind { C_NTT, C_NTT_FIRST, C_NTT_SECOND, C_EW, C_MODUP, C_MODUP_COL, C_MODDOWN, C_MODDOWN_COL, C_INNER, C_INNER_ROW, C_AUTO, C_LIFT, C_SAMPLE, C_INTSPREAD, C_ENCODE, C_DECODE, C_RAISE, C_BSGS, C_FFTENC,
                C_MARK /* no launch: a segment boundary for the segment profiler */ };
 
 struct Cmd {
@@ -246,6 +251,7 @@ class Builder {
   void modup(const std::vector<ModUpJob>& v);
   void modup_col(const std::vector<ModUpJob>& v);
   void moddown(const std::vector<ModDownJob>& v);
+  void moddown_col(const std::vector<ModDownJob>& v);
   // row_fused: with the two-pass NTT, the inner product runs the ext limbs'
   // row pass (their inputs leave the ModUp after the column pass)
   void inner(const std::vector<InnerJob>& v, bool row_fused = true);

@@ -229,6 +229,19 @@ int build_context(Ctx& c, int log_n, int n_q, int q_bits, int n_p, int p_bits, i
       h[o_rri + (size_t)l * n_q + t] = (double)hinv(all, q);
     }
   }
+  // the inverse transform feeding a conversion from B also applies (B/b)^-1:
+  // limb b is scaled by N^-1 (B/b)^-1 mod b
+  size_t o_mdy = alloc(c.alpha), o_rry = alloc((size_t)n_q * (n_q + c.alpha));
+  for (int k = 0; k < c.alpha; ++k) {
+    const uint64_t pk = c.mod[n_q + k];
+    h[o_mdy + k] = (double)hmul((uint64_t)h[o_mdc + k], hinv((uint64_t)c.N % pk, pk), pk);
+  }
+  for (int l = 1; l < n_q; ++l)
+    for (int i = 0; i < nb; ++i) {
+      const uint64_t b = c.mod[i == 0 ? l : n_q + i - 1];
+      h[o_rry + (size_t)l * (n_q + c.alpha) + l + i] =
+          (double)hmul((uint64_t)h[o_rrc + (size_t)l * nb + i], hinv((uint64_t)c.N % b, b), b);
+    }
   // rescale: q_l^-1 mod q_i
   size_t o_rs = alloc((size_t)n_q * n_q);
   for (int l = 1; l < n_q; ++l)
@@ -272,6 +285,8 @@ int build_context(Ctx& c, int log_n, int n_q, int q_bits, int n_p, int p_bits, i
   c.rr_cinv = B + o_rrc;
   c.rr_chat = B + o_rrh;
   c.rr_inv = B + o_rri;
+  c.md_ytab = B + o_mdy;
+  c.rr_ytab = B + o_rry;
   c.crt_tab = B + o_crt;
   HIPCHK(hipEventCreateWithFlags(&c.staging_done, hipEventDisableTiming));
   return 0;
@@ -423,6 +438,15 @@ void Builder::moddown(const std::vector<ModDownJob>& v) {
   for (auto& j : v) units += j.n_chain + C.n_p + (j.first_prime >= 0 ? 1 : 0);
   PUSH_JOBS(C_MODDOWN, v, 1, false, units);
 }
+void Builder::moddown_col(const std::vector<ModDownJob>& v) {
+  int my = 0;
+  int64_t units = 0;
+  for (auto& j : v) {
+    my = std::max(my, j.n_chain);
+    units += j.n_chain + C.n_p + (j.first_prime >= 0 ? 1 : 0);
+  }
+  PUSH_JOBS(C_MODDOWN_COL, v, my, false, units);
+}
 void Builder::inner(const std::vector<InnerJob>& v, bool row_fused) {
   int my = 0;
   int64_t units = 0, own = 0;
@@ -503,7 +527,8 @@ int prof_kind_of(const Cmd& k) {
     case C_EW: return PROF_EW;
     case C_MODUP:
     case C_MODUP_COL: return PROF_MODUP;
-    case C_MODDOWN: return PROF_MODDOWN;
+    case C_MODDOWN:
+    case C_MODDOWN_COL: return PROF_MODDOWN;
     case C_INNER:
     case C_INNER_ROW: return PROF_INNER;
     case C_AUTO: return PROF_AUTO;
@@ -599,6 +624,7 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
       case C_MODUP: launch_modup(T, (const ModUpJob*)j, k.n, s); break;
       case C_MODUP_COL: launch_modup_col(T, (const ModUpJob*)j, k.n, k.max_y, c.modup_eg, s); break;
       case C_MODDOWN: launch_moddown_conv(T, (const ModDownJob*)j, k.n, s); break;
+      case C_MODDOWN_COL: launch_moddown_col(T, (const ModDownJob*)j, k.n, k.max_y, s); break;
       case C_INNER: launch_inner(T, (const InnerJob*)j, k.n, k.max_y, s); break;
       case C_INNER_ROW: launch_inner_row(T, (const InnerJob*)j, k.n, k.max_y, s); break;
       case C_AUTO: launch_automorph(T, (const AutoJob*)j, k.n, k.max_y, s); break;
@@ -733,9 +759,12 @@ void Builder::ks_back(const std::vector<KsItem>& items, const std::vector<KsTmp>
     for (int w = 0; w < 2; ++w) {
       double* aw = acc + (size_t)w * n_ext * N;
       double* sp = aw + (size_t)nc * N;
-      j_inv_acc.push_back(NttJob{sp, sp, n_p, 0, 0, 0});
+      // the inverse transform's last pass applies (P/p_k)^-1 for the conversion
+      NttJob ji{sp, sp, n_p, 0, 0, 0};
+      ji.ek = C.md_ytab;
+      j_inv_acc.push_back(ji);
       double* cv = conv + (size_t)w * nc * N;
-      j_down.push_back(ModDownJob{sp, cv, C.md_cinv, C.md_chat, nc, -1});
+      j_down.push_back(ModDownJob{sp, cv, nullptr, C.md_chat, nc, -1});
       // out_w = base_w + (acc_w - NTT(conv_w)) P^-1, fused into the transform
       NttJob f{cv, cv, nc, nc, 0, 0};
       f.epi = EPI_MODDOWN;
@@ -747,8 +776,14 @@ void Builder::ks_back(const std::vector<KsItem>& items, const std::vector<KsTmp>
     }
   }
   ntt(j_inv_acc, true, first_pass_done ? 1 : -1);
-  moddown(j_down);
-  ntt(j_fwd_conv, false);
+  if (inner_row_fused(C.T)) {
+    // conversion + column pass in one kernel; the row pass carries the combine
+    moddown_col(j_down);
+    ntt(j_fwd_conv, false, 1);
+  } else {
+    moddown(j_down);
+    ntt(j_fwd_conv, false);
+  }
   counters[3] += (int64_t)items.size();
 }
 
@@ -909,10 +944,12 @@ std::vector<CT> Builder::relin_rescale(const std::vector<Deg2>& xs) {
     for (int w = 0; w < 2; ++w) {
       double* aw = acc + (size_t)w * n_ext * N;
       // limbs l .. l+n_p of the extended basis: q_l, then the special primes
-      j_inv_acc.push_back(NttJob{aw, aw, n_ext, nc, 0, l});
+      // (its last pass also applies (B/b)^-1 for the conversion)
+      NttJob ji{aw, aw, n_ext, nc, 0, l};
+      ji.ek = C.rr_ytab + (size_t)l * (n_q + n_p);
+      j_inv_acc.push_back(ji);
       double* cv = conv + (size_t)w * l * N;
-      j_conv.push_back(ModDownJob{aw + (size_t)l * N, cv, C.rr_cinv + (size_t)l * nb,
-                                  C.rr_chat + (size_t)l * n_q * nb, l, l});
+      j_conv.push_back(ModDownJob{aw + (size_t)l * N, cv, nullptr, C.rr_chat + (size_t)l * n_q * nb, l, l});
       // out_w = (P d_w + acc_w - NTT(conv_w)) (P q_l)^-1, fused into the transform
       NttJob f{cv, cv, l, l, 0, 0};
       f.epi = EPI_RRCOMB;
@@ -934,8 +971,13 @@ std::vector<CT> Builder::relin_rescale(const std::vector<Deg2>& xs) {
   }
   // (fused: the first inverse pass already ran inside the inner product)
   ntt(j_inv_acc, true, inner_row_fused(C.T) ? 1 : -1);
-  moddown(j_conv);
-  ntt(j_fwd_conv, false);
+  if (inner_row_fused(C.T)) {
+    moddown_col(j_conv);
+    ntt(j_fwd_conv, false, 1);
+  } else {
+    moddown(j_conv);
+    ntt(j_fwd_conv, false);
+  }
   counters[2] += (int64_t)xs.size();
   counters[3] += (int64_t)xs.size();
   return out;
