@@ -295,7 +295,8 @@ int secpe_op_boot_step(secpe_ctx* ctx, int step, const secpe_ct* a, void* ws_dev
    as secpe_eval_argmax_batch, no graph) under candidate schedules and keeps
    the fastest in the context for later calls.  A candidate index is a set of
    knob bits:
-     bit 0: output limbs per workgroup of the fused ModUp, 2 (set) or 4;
+     bit 0: output limbs per workgroup of the column-fused base conversions
+            (ModUp and ModDown), 2 (set) or 4;
      bit 1: NTT passes issued in job groups of 128 MiB (set) or all jobs at once;
      bit 2: forward NTT column pass, two tiles per workgroup (set: the second
             tile's loads in flight while the first transforms) or one;

@@ -940,8 +940,10 @@ template __global__ void k_inner_row<7, 32>(const InnerJob* __restrict__, DevTab
 // (ready for the row pass, which the inner product does) goes to dst limb e.
 // Grid (tile, group, job): with a multiple of 8 tiles, every group of a tile
 // runs on the same XCD and rereads the digit's tile from its L2.
+// (two output limbs per workgroup fit 3 waves per SIMD without spilling; the
+// compiler's default aims at 2)
 template <int LOGS, int G, int EG>
-__global__ __launch_bounds__(256) void k_modup_col(const ModUpJob* __restrict__ jobs, DevTables T) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EG == 2 ? 3 : 1, 8))) void k_modup_col(const ModUpJob* __restrict__ jobs, DevTables T) {
   extern __shared__ double lds[];
   constexpr int RB = LOGS - 4;
   constexpr int NB = 1 << RB;
@@ -1011,7 +1013,7 @@ __global__ __launch_bounds__(256) void k_modup_col(const ModUpJob* __restrict__ 
 // follows with the ModDown or merged combine as its epilogue.  Grid (tile,
 // group, job) as for the ModUp: the groups of a tile share an XCD's L2.
 template <int LOGS, int G, int EG>
-__global__ __launch_bounds__(256) void k_moddown_col(const ModDownJob* __restrict__ jobs, DevTables T) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EG == 2 ? 3 : 1, 8))) void k_moddown_col(const ModDownJob* __restrict__ jobs, DevTables T) {
   extern __shared__ double lds[];
   constexpr int RB = LOGS - 4;
   constexpr int NB = 1 << RB;
@@ -1071,9 +1073,12 @@ __global__ __launch_bounds__(256) void k_moddown_col(const ModDownJob* __restric
     __syncthreads();
   }
 }
-template __global__ void k_moddown_col<8, 16, 4>(const ModDownJob* __restrict__, DevTables);
-template __global__ void k_moddown_col<7, 32, 4>(const ModDownJob* __restrict__, DevTables);
-template __global__ void k_moddown_col<6, 64, 4>(const ModDownJob* __restrict__, DevTables);
+#define MODDOWN_INST(EG)                                                                   \
+  template __global__ void k_moddown_col<8, 16, EG>(const ModDownJob* __restrict__, DevTables); \
+  template __global__ void k_moddown_col<7, 32, EG>(const ModDownJob* __restrict__, DevTables); \
+  template __global__ void k_moddown_col<6, 64, EG>(const ModDownJob* __restrict__, DevTables);
+MODDOWN_INST(2)
+MODDOWN_INST(4)
 
 #define MODUP_INST(EG)                                                              \
   template __global__ void k_modup_col<8, 16, EG>(const ModUpJob* __restrict__, DevTables); \
@@ -1832,17 +1837,25 @@ void launch_modup_col(const DevTables& T, const ModUpJob* jobs, int n_jobs, int 
 #undef LAUNCH_MODUP
 }
 
-void launch_moddown_col(const DevTables& T, const ModDownJob* jobs, int n_jobs, int max_chain, hipStream_t s) {
+void launch_moddown_col(const DevTables& T, const ModDownJob* jobs, int n_jobs, int max_chain, int eg,
+                        hipStream_t s) {
   if (n_jobs <= 0 || max_chain <= 0) return;
   const int log_n = T.log_n;
   const int k1 = log_n / 2;   // column length of the two-pass split
   const int g = k1 == 8 ? 16 : k1 == 7 ? 32 : 64;
-  constexpr int eg = 4;
+  eg = eg == 2 ? 2 : 4;
   dim3 grid((1 << (log_n - k1)) / g, (max_chain + eg - 1) / eg, n_jobs);
   const size_t lds = ntt_lds_bytes(k1, g);
-  if (k1 == 8) hipLaunchKernelGGL((k_moddown_col<8, 16, eg>), grid, dim3(256), lds, s, jobs, T);
-  else if (k1 == 7) hipLaunchKernelGGL((k_moddown_col<7, 32, eg>), grid, dim3(256), lds, s, jobs, T);
-  else hipLaunchKernelGGL((k_moddown_col<6, 64, eg>), grid, dim3(256), lds, s, jobs, T);
+#define LAUNCH_MODDOWN(EG)                                                                          \
+  if (k1 == 8) hipLaunchKernelGGL((k_moddown_col<8, 16, EG>), grid, dim3(256), lds, s, jobs, T);     \
+  else if (k1 == 7) hipLaunchKernelGGL((k_moddown_col<7, 32, EG>), grid, dim3(256), lds, s, jobs, T); \
+  else hipLaunchKernelGGL((k_moddown_col<6, 64, EG>), grid, dim3(256), lds, s, jobs, T);
+  if (eg == 2) {
+    LAUNCH_MODDOWN(2)
+  } else {
+    LAUNCH_MODDOWN(4)
+  }
+#undef LAUNCH_MODDOWN
 }
 
 void launch_inner_row(const DevTables& T, const InnerJob* jobs, int n_jobs, int max_ext, hipStream_t s) {
