@@ -295,25 +295,26 @@ int secpe_op_boot_step(secpe_ctx* ctx, int step, const secpe_ct* a, void* ws_dev
    as secpe_eval_argmax_batch, no graph) under candidate schedules and keeps
    the fastest in the context for later calls.  A candidate index is a set of
    knob bits:
-     bit 0: output limbs per workgroup of the column-fused base conversions
-            (ModUp and ModDown), 2 (set) or 4;
+     bit 0: output limbs per workgroup of the fused ModUp, 2 (set) or 4;
      bit 1: NTT passes issued in job groups of 128 MiB (set) or all jobs at once;
      bit 2: forward NTT column pass, two tiles per workgroup (set: the second
             tile's loads in flight while the first transforms) or one;
      bit 3: inverse NTT column pass, two tiles per workgroup (set) or one;
      bit 4: forward NTT row pass (with its fused epilogues), two tiles per
-            workgroup (set) or one.
+            workgroup (set) or one;
+     bit 5: output limbs per workgroup of the fused ModDown conversion, 2 (set)
+            or 4.
    (The two-tile variants exist for N = 2^16; elsewhere bits 2-4 change nothing.)
    Search: candidate 0, then each knob flipped in turn from the best so far
-   and kept when the batch is faster (coordinate descent; 1 + 5 candidates
+   and kept when the batch is faster (coordinate descent; 1 + 6 candidates
    timed, each the faster of two runs).  Writes the chosen candidate to
    *chosen and, for i < cap, the milliseconds of candidate i to ms[i] (0 for
    candidates not timed).  Synchronous.  Returns 0 or an error. */
-#define SECPE_AUTOTUNE_KNOBS 5
+#define SECPE_AUTOTUNE_KNOBS 6
 /* Set a schedule (candidate index as above) without timing, e.g. one a
    previous secpe_autotune chose.  Every schedule gives the same bits. */
 int secpe_set_schedule(secpe_ctx* ctx, int candidate);
-#define SECPE_AUTOTUNE_CANDIDATES 32
+#define SECPE_AUTOTUNE_CANDIDATES 64
 int secpe_autotune(secpe_ctx* ctx, const secpe_key_owner* owner, int n, const secpe_ct* in, const int* K,
                    const int* C, const double* d_min, const double* d_max, const uint64_t* refresh_seed,
                    void* ws_dev, size_t ws_bytes, secpe_ct* out, int* chosen, double* ms, int cap);

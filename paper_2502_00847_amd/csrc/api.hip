@@ -1317,6 +1317,7 @@ static void set_candidate(Ctx& c, int i) {
   c.modup_eg = (i & 1) ? 2 : 4;
   c.ntt_chunk_bytes = (i & 2) ? ((size_t)128 << 20) : 0;
   c.ntt_tiles = (i >> 2) & 7;
+  c.moddown_eg = (i & 32) ? 2 : 4;
 }
 
 extern "C" int secpe_set_schedule(secpe_ctx* x, int candidate) {

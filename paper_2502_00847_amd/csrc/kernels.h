@@ -29,7 +29,7 @@ void launch_modup_col(const DevTables& T, const ModUpJob* jobs, int n_jobs, int 
 // The ModDown's centred conversion fused with the column pass of its outputs'
 // forward NTT (source prescaled by the inverse transform: ModDownJob::cinv
 // null); the row pass, with the combine as its epilogue, follows as a launch.
-// eg: output limbs per workgroup (2 or 4; the same tunable as the ModUp's)
+// eg: output limbs per workgroup (2 or 4; a tunable)
 void launch_moddown_col(const DevTables& T, const ModDownJob* jobs, int n_jobs, int max_chain, int eg,
                         hipStream_t s);
 void launch_ew(const DevTables& T, const EwJob* jobs, int n_jobs, int max_limbs, hipStream_t s);

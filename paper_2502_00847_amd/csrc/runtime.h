@@ -78,9 +78,9 @@ struct Ctx {
   // two-pass NTT launches are issued in job groups of at most this many bytes
   // of limb data (0 = one group); SECPE_NTT_CHUNK_MB overrides the default
   size_t ntt_chunk_bytes = 0;
-  // output limbs per workgroup of the column-fused base conversions (ModUp
-  // and ModDown; 2 or 4); set by the autotuner
-  int modup_eg = 4;
+  // output limbs per workgroup of the column-fused base conversions, ModUp
+  // and ModDown (2 or 4 each); set by the autotuner
+  int modup_eg = 4, moddown_eg = 4;
   // NTT passes with two tiles per workgroup (bit 0 forward column, bit 1
   // inverse column, bit 2 forward row); set by the autotuner
   int ntt_tiles = 0;

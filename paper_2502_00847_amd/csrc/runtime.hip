@@ -624,7 +624,7 @@ void launch_cmds(Ctx& c, const std::vector<Cmd>& cmds, char* arena) {
       case C_MODUP: launch_modup(T, (const ModUpJob*)j, k.n, s); break;
       case C_MODUP_COL: launch_modup_col(T, (const ModUpJob*)j, k.n, k.max_y, c.modup_eg, s); break;
       case C_MODDOWN: launch_moddown_conv(T, (const ModDownJob*)j, k.n, s); break;
-      case C_MODDOWN_COL: launch_moddown_col(T, (const ModDownJob*)j, k.n, k.max_y, c.modup_eg, s); break;
+      case C_MODDOWN_COL: launch_moddown_col(T, (const ModDownJob*)j, k.n, k.max_y, c.moddown_eg, s); break;
       case C_INNER: launch_inner(T, (const InnerJob*)j, k.n, k.max_y, s); break;
       case C_INNER_ROW: launch_inner_row(T, (const InnerJob*)j, k.n, k.max_y, s); break;
       case C_AUTO: launch_automorph(T, (const AutoJob*)j, k.n, k.max_y, s); break;

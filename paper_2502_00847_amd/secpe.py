@@ -504,11 +504,12 @@ class Context:
             o.level, o.scale = c.level, c.scale
         return outs
 
-    AUTOTUNE_CANDIDATES = [dict(conversion_outputs_per_workgroup=2 if i & 1 else 4,
+    AUTOTUNE_CANDIDATES = [dict(modup_outputs_per_workgroup=2 if i & 1 else 4,
                                 ntt_job_group_mib=128 if i & 2 else None,
                                 fwd_col_tiles_per_workgroup=2 if i & 4 else 1,
                                 inv_col_tiles_per_workgroup=2 if i & 8 else 1,
-                                fwd_row_tiles_per_workgroup=2 if i & 16 else 1) for i in range(32)]
+                                fwd_row_tiles_per_workgroup=2 if i & 16 else 1,
+                                moddown_outputs_per_workgroup=2 if i & 32 else 4) for i in range(64)]
 
     def autotune(self, cts, Ks, Cs, d_min, d_max, seeds, ws, outs, owner=None):
         """Time the batch under each candidate schedule; the fastest stays set."""

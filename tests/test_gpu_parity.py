@@ -421,7 +421,7 @@ def test_autotune_keeps_bits(p13):
     outs = [g.new_ct() for _ in cts]
     chosen, cands = g.autotune(cts, *args, ws=ws, outs=outs, owner=g.owner)
     assert chosen in [c["index"] for c in cands] and all(c["ms"] > 0 for c in cands)
-    assert len(cands) == 6   # the default and each of the five knobs flipped in turn
+    assert len(cands) == 7   # the default and each of the six knobs flipped in turn
     assert all(np.array_equal(g.export(a), b) for a, b in zip(outs, before))
     after = [g.export(z) for z in g.eval_argmax_batch(cts, *args, ws=ws, owner=g.owner)]
     assert all(np.array_equal(a, b) for a, b in zip(after, before))
