@@ -3,8 +3,8 @@ same seeded inputs (coefficient-domain residues compared element by element),
 through the C ABI (include/secpe.h) via its Python binding.
 
 Parameter sets: 'tiny' (N=2^10, single-pass NTT), 'p13' (N=2^13, the toy's
-two-pass NTT split 2^6 x 2^7), 'p14' (2^7 x 2^7).  Full N=2^16 lives in
-test_gpu_full.py.
+two-pass NTT split 2^6 x 2^7), 'p14' (2^7 x 2^7), 'p15' (2^7 x 2^8).  Full
+N=2^16 lives in test_gpu_full.py.
 """
 import numpy as np
 import pytest
@@ -30,6 +30,8 @@ def _params(name):
         return dict(_params("p13"), refresh_level=6)
     if name == "p14":
         return dict(log_n=14, n_q=8, q_bits=40, n_p=3, p_bits=51, log_scale=40, dg=2, df=2, min_level=1)
+    if name == "p15":
+        return dict(log_n=15, n_q=8, q_bits=40, n_p=3, p_bits=51, log_scale=40, dg=2, df=2, min_level=1)
     return dict(W.PARAMS[name])
 
 
@@ -233,6 +235,31 @@ def test_key_switch_bit_exact(tiny, level):
     gu = g.key_switch(0, d)
     ou = o.key_switch(0, d)
     assert np.array_equal(gu[0], ou[0]) and np.array_equal(gu[1], ou[1])
+
+
+@pytest.mark.parametrize("name", ["p14", "p15"])
+def test_two_pass_sizes_key_switching_bit_exact(name):
+    """N = 2^14 (2^7 x 2^7) and 2^15 (2^7 x 2^8) run their own shapes of the
+    column-fused ModUp and ModDown and of the inner product's row pass: key
+    switches at full and ragged digit counts, the merged relinearise + rescale,
+    rotations and a whole Algorithm 1 match the oracle bit for bit."""
+    g, o, steps = _pair(name, 2, 2)
+    rng = np.random.default_rng(14)
+    primes = [int(v) for v in o.primes]
+    for level in (7, 4, 0):
+        d = np.stack([rng.integers(0, primes[t], o.n, dtype=np.uint64) for t in range(level + 1)])
+        gu, ou = g.key_switch(0, d), o.key_switch(0, d)
+        assert np.array_equal(gu[0], ou[0]) and np.array_equal(gu[1], ou[1]), level
+    a, _ = _rand_ct(o, 41)
+    b, _ = _rand_ct(o, 42, level=5)
+    ga, gb = g.import_(a.export(), a.scale), g.import_(b.export(), b.scale)
+    _same(g, g.mul_relin_rescale(ga, gb), o.mul_relin_rescale(a, b))
+    _same(g, g.mul_relin_rescale(ga, ga), o.mul_relin_rescale(a, a))
+    for st in (1, 3):
+        _same(g, g.rotate(gb, st), o.rotate(b, st))
+    print(f"[{name}] Algorithm 1, K = C = 2 (oracle and GPU)", flush=True)
+    y, zo, zg = _argmax_pair(g, o, 2, 2, q=7)
+    _same(g, zg, zo)
 
 
 def test_refresh_bit_exact(tiny):
