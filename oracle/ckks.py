@@ -88,6 +88,7 @@ def _load():
         "orc_eval_mod": (vp, [vp, vp]),
         "orc_bootstrap": (vp, [vp, vp]),
         "orc_bootstrap_sparse": (vp, [vp, vp]),
+        "orc_bootstrap_packed": (None, [vp, P(vp), ci, P(vp)]),
         "orc_set_boot_sparse": (ci, [vp, ci]),
         "orc_boot_sparse_apply": (None, [vp, ci, P(dbl), P(dbl), P(dbl), P(dbl)]),
         "orc_boot_transform_sparse": (vp, [vp, vp, ci]),
@@ -224,6 +225,16 @@ class Oracle:
     def bootstrap_sparse(self, ct):
         """Bootstrap keeping slots [0, n) (n = boot_sparse), repeated with period n."""
         return self._wrap(self.lib.orc_bootstrap_sparse(self.h, ct.h))
+
+    def bootstrap_packed(self, cts):
+        """Refresh several ciphertexts read only on slots [0, W) (W = boot_sparse)
+        through shared full-slot bootstraps: output j holds input j's slots
+        [0, W) there and the other inputs' windows elsewhere."""
+        k = len(cts)
+        arr = (C.c_void_p * k)(*[c.h for c in cts])
+        out = (C.c_void_p * k)()
+        self.lib.orc_bootstrap_packed(self.h, arr, k, out)
+        return [self._wrap(out[i]) for i in range(k)]
 
     def mod_raise(self, ct):
         return self._wrap(self.lib.orc_mod_raise(self.h, ct.h))

@@ -2420,17 +2420,11 @@ ORC_API void* orc_boot_transform(void* h, const void* x, int inverse) {
   return boot_transform((orc_ctx*)h, (const orc_ct*)x, inverse);
 }
 
-/* the whole bootstrap of a ciphertext at level >= 1 with slot values |z| <= 1;
-   the result is at boot_out_level with scale Delta */
-static orc_ct* bootstrap(orc_ctx* c, const orc_ct* x) {
-  if (c->boot_out_level < 0) die("bootstrap: not set up");
-  if (x->level < 1) die("bootstrap: input needs level >= 1");
-  double tb = ldexp((double)c->mod[0], -c->boot_ratio);
-  orc_ct* x1 = ct_copy(c, x, 1);
-  orc_ct* x0 = op_lincomb(c, x1, 1.0, NULL, 0.0, tb, 1);
-  ct_free(x1);
+/* the full pipeline after the scale-down: a level-0 ciphertext at scale
+   q_0 / 2^ratio through ModRaise, CoeffToSlot, the split into real and
+   imaginary parts, EvalMod on each, their join and SlotToCoeff */
+static orc_ct* boot_core_full(orc_ctx* c, const orc_ct* x0) {
   orc_ct* y0 = mod_raise(c, x0);
-  ct_free(x0);
   orc_ct* y = coeff_to_slot(c, y0);
   ct_free(y0);
   /* real and imaginary parts: w + conj(w), -i (w - conj(w)) */
@@ -2447,8 +2441,21 @@ static orc_ct* bootstrap(orc_ctx* c, const orc_ct* x) {
   ct_free(re2); ct_free(im2); ct_free(imi);
   orc_ct* w2 = slot_to_coeff(c, w);
   ct_free(w);
-  w = w2;
-  if (w->level != c->boot_out_level) die("bootstrap: level plan mismatch");
+  if (w2->level != c->boot_out_level) die("bootstrap: level plan mismatch");
+  return w2;
+}
+
+/* the whole bootstrap of a ciphertext at level >= 1 with slot values |z| <= 1;
+   the result is at boot_out_level with scale Delta */
+static orc_ct* bootstrap(orc_ctx* c, const orc_ct* x) {
+  if (c->boot_out_level < 0) die("bootstrap: not set up");
+  if (x->level < 1) die("bootstrap: input needs level >= 1");
+  double tb = ldexp((double)c->mod[0], -c->boot_ratio);
+  orc_ct* x1 = ct_copy(c, x, 1);
+  orc_ct* x0 = op_lincomb(c, x1, 1.0, NULL, 0.0, tb, 1);
+  ct_free(x1);
+  orc_ct* w = boot_core_full(c, x0);
+  ct_free(x0);
   c->counters[CNT_REFRESH]++;
   return w;
 }
@@ -2582,6 +2589,82 @@ static orc_ct* bootstrap_sparse(orc_ctx* c, const orc_ct* x) {
 ORC_API void* orc_bootstrap_sparse(void* h, const void* x) {
   return bootstrap_sparse((orc_ctx*)h, (const orc_ct*)x);
 }
+/* Window-packed bootstrap: a refresh of k single-query ciphertexts that each
+   read only slots [0, W) afterwards (W = boot_sparse) shares full-slot
+   bootstraps.  A design of this implementation (the method bootstraps each
+   ciphertext); groups of m <= N/2W inputs in order, each group:
+     scale-down   as in the sparse-slot bootstrap: the mask of slots [0, W)
+                  at scale q_0 / 2^ratio, down to level 0, giving v_j;
+     pack         T = sum_i RotL(z_i, i W) with z_i = v_(m-1-i), by pairs:
+                  at round b, node t = node 2t + RotL(node 2t+1, 2^b W)
+                  (an odd last node passes through); then
+                  P = RotL(T, ((N/2W - m + 1) mod N/2W) W), one rotation by
+                  2^b W for each set bit b, lowest first.  P holds v_j's
+                  slots [0, W) at [jW, jW + W) and zeros elsewhere;
+     bootstrap    the full pipeline from ModRaise on (boot_core_full);
+     unpack       U_0 = P'; at round b = 0, 1, ... every U_o with o < 2^b
+                  gives U_(o + 2^b) = RotL(U_o, 2^b W) while o + 2^b < m, so
+                  U_j = RotL(P', j W) holds input j's slots [0, W) at [0, W)
+                  (and the other inputs' windows elsewhere).
+   Every rotation is by a power-of-two multiple of W below N/2, the same
+   steps as the sparse-slot trace, so no other key is needed. */
+static void bootstrap_packed(orc_ctx* c, orc_ct* const* xs, int k, orc_ct** out) {
+  int W = c->boot_sparse, S = c->n / 2;
+  if (c->boot_out_level < 0 || W <= 0) die("bootstrap_packed: not set up");
+  int per = S / W;
+  double tb = ldexp((double)c->mod[0], -c->boot_ratio);
+  double* mask = (double*)xcalloc(W, sizeof(double));
+  for (int j = 0; j < W; ++j) mask[j] = 1.0;
+  for (int p0 = 0; p0 < k; p0 += per) {
+    int m = k - p0 < per ? k - p0 : per;
+    orc_ct** z = (orc_ct**)xcalloc(m, sizeof(orc_ct*));
+    for (int i = 0; i < m; ++i) {
+      const orc_ct* x = xs[p0 + m - 1 - i];
+      if (x->level < 1) die("bootstrap: input needs level >= 1");
+      orc_ct* x1 = ct_copy(c, x, 1);
+      z[i] = op_mul_plain(c, x1, mask, W, tb);
+      ct_free(x1);
+    }
+    int cnt = m;
+    for (int b = 0; cnt > 1; ++b) {
+      int nc = 0;
+      for (int t = 0; 2 * t < cnt; ++t) {
+        if (2 * t + 1 < cnt) {
+          orc_ct* r = op_rotate(c, z[2 * t + 1], (int64_t)W << b);
+          orc_ct* u = op_add(c, z[2 * t], r, 0);
+          ct_free(r);
+          ct_free(z[2 * t]);
+          ct_free(z[2 * t + 1]);
+          z[nc++] = u;
+        } else {
+          z[nc++] = z[2 * t];
+        }
+      }
+      cnt = nc;
+    }
+    orc_ct* P = z[0];
+    int shift = (per - m + 1) % per;
+    for (int b = 0; (1 << b) <= shift; ++b)
+      if (shift & (1 << b)) {
+        orc_ct* r = op_rotate(c, P, (int64_t)W << b);
+        ct_free(P);
+        P = r;
+      }
+    orc_ct* Pb = boot_core_full(c, P);
+    ct_free(P);
+    orc_ct** u = out + p0;
+    u[0] = Pb;
+    for (int b = 0; (1 << b) < m; ++b)
+      for (int o = 0; o < (1 << b) && o + (1 << b) < m; ++o) u[o + (1 << b)] = op_rotate(c, u[o], (int64_t)W << b);
+    free(z);
+    c->counters[CNT_REFRESH] += m;
+  }
+  free(mask);
+}
+ORC_API void orc_bootstrap_packed(void* h, void* const* xs, int k, void** out) {
+  bootstrap_packed((orc_ctx*)h, (orc_ct* const*)xs, k, (orc_ct**)out);
+}
+
 /* the sparse-slot bootstrap keeps slots [0, n): n a power of two with
    2n <= N/2 and at least one radix-2 stage per group; 0 turns it off.
    Returns 0, or -1 for an n it cannot take. */

@@ -333,3 +333,38 @@ def test_argmax_with_sparse_bootstrapping(sparse_boot):
     zs = sim.t1_argmax(y, lo, hi, o.slots)[:C]
     assert np.abs(z - zs).max() < 1e-3
     assert int(np.argmax(z)) == sim.t0_argmax(y)[0]
+
+
+@pytest.mark.parametrize("k", [1, 3, 19])
+def test_packed_bootstrap_returns_every_window(sparse_boot, k):
+    """Window-packed refresh of k ciphertexts (W = n slots each, N/2W per full
+    bootstrap): output j holds input j's slots [0, W) at [0, W), whatever the
+    inputs held elsewhere, and in window i the window of input j + i of its
+    group, cyclically within the group's N/2W windows (zero past its last
+    input).  That is the packing sum_j RotR(v_j, jW) and the unpacking
+    RotL(P', jW) written out; output level and scale as the full pipeline,
+    within the full bootstrap's 2^-16 on N = 2^10."""
+    o = sparse_boot
+    W, S = SPARSE_N, o.slots
+    per = S // W
+    rng = np.random.default_rng(40 + k)
+    zs, cts = [], []
+    sc = 2.0**49
+    for j in range(k):
+        z = rng.uniform(-1, 1, S)
+        zs.append(z)
+        cts.append(o.lower(o.encrypt(o.encode(z, sc), sc, 100 + j), 1 + j % 3))
+    o.reset_counters()
+    outs = o.bootstrap_packed(cts)
+    assert o.counters()["refresh"] == k
+    for j, b in enumerate(outs):
+        assert b.level == o.boot_out_level() and b.scale == 2.0 ** P["log_scale"]
+        p0 = j - j % per
+        m = min(per, k - p0)
+        want = np.zeros(S)
+        for i in range(per):
+            src = (j - p0 + i) % per
+            if src < m:
+                want[i * W:(i + 1) * W] = zs[p0 + src][:W]
+        got = o.decrypt_decode(b, S)
+        assert np.abs(got - want).max() < 2.0**-16, j
