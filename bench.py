@@ -653,6 +653,16 @@ def bootstrap_rate(n_batch=8, n_queries=32, pset="full_boot", packed=True, compa
     batch = batch_rate(g)
     if nsp:
         batch["bootstrap"] = f"sparse-slot, n = {nsp} (a single query reads slots [0, 2C') after Eq. 5)"
+        # the same batch with every refresh of two or more queries window-packed,
+        # n slots each, into shared full-slot bootstraps (same keys)
+        gp = Context(dict(p, boot_pack_min=2))
+        gp.keygen(W.KEYGEN_SEED, steps)
+        gp.owner = gp.key_owner()
+        gp.boot_setup()
+        batch["window_packed"] = batch_rate(gp)
+        batch["window_packed"]["bootstrap"] = (f"refreshes of 2 or more queries packed, {nsp} slots each, "
+                                               f"{g.slots // nsp} per full-slot bootstrap")
+        del gp
     if nsp and compare_full:
         # the same batch with every bootstrap full-slot, on a context without the sparse path
         pf = dict(p, boot_sparse=0)

@@ -259,6 +259,10 @@ typedef struct secpe_boot_params {
   int sparse_slots; /* 0, or n: a power of two, 2n <= N/2, log2 n >= groups.
                        Evaluations whose refresh reads at most n slots
                        afterwards bootstrap sparsely. */
+  int pack_min;   /* 0, or k >= 2 (needs sparse_slots): when at least k such
+                     ciphertexts refresh together they are packed, n slots
+                     each, into shared full-slot bootstraps
+                     (secpe_bootstrap_packed) instead */
 } secpe_boot_params;
 /* the step value secpe_keygen takes as the conjugation key (X -> X^(2N-1)) */
 #define SECPE_STEP_CONJUGATE INT64_MIN
@@ -284,6 +288,19 @@ int secpe_bootstrap(secpe_ctx* ctx, int n, const secpe_ct* in, void* ws_dev, siz
    SECPE_EINVAL): slots [0, sparse_slots) of each input, repeated with that
    period over the N/2 slots of the output.  Same workspace size. */
 int secpe_bootstrap_sparse(secpe_ctx* ctx, int n, const secpe_ct* in, void* ws_dev, size_t ws_bytes,
+                           secpe_ct* out);
+/* The window-packed bootstrap of n ciphertexts that are read only on slots
+   [0, W) afterwards (W = sparse_slots; SECPE_EINVAL without it).  A design of
+   this library, not of the paper (which bootstraps each ciphertext): in
+   groups of m <= N/2W, taken in order, each input is masked to [0, W) at the
+   scale-down, the group is packed by rotations into one ciphertext holding
+   input j's window at slots [jW, jW + W), that ciphertext takes the
+   full-slot bootstrap, and output j is it rotated left by jW: input j's
+   slots [0, W) at [0, W), the windows of the inputs after it (cyclically
+   within the group) beyond.  Every rotation is by a power-of-two multiple of
+   W, the sparse-slot bootstrap's own steps.  Same level, scale and
+   workspace size as secpe_bootstrap; in[i] and out[i] are the caller's. */
+int secpe_bootstrap_packed(secpe_ctx* ctx, int n, const secpe_ct* in, void* ws_dev, size_t ws_bytes,
                            secpe_ct* out);
 /* Single steps, for parity checks: step 0 ModRaise (level-0 input), 1
    CoeffToSlot, 2 SlotToCoeff, 3 EvalMod, 4 slots times i, 5 slots times -i,

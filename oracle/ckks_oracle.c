@@ -644,6 +644,7 @@ ORC_API int orc_get_key(void* h, uint64_t g, int digit, int which, int t, uint64
 /* ------------------------------------------------------------------------- */
 /* secret-key encryption of integer plaintext m at level 'level' */
 static orc_ct* encrypt_int(orc_ctx* c, const i128* m, double scale, uint64_t seed, int purpose, uint64_t sub, int level) {
+  if (!c->s) die("encrypt: no secret (keygen first)");
   int n = c->n;
   orc_ct* x = ct_new(c, level, scale);
   uint64_t ekey = sm_key(seed, make_tag((uint64_t)purpose, 0, sub, LIMB_NONE));

@@ -1747,6 +1747,7 @@ extern "C" int secpe_set_boot(secpe_ctx* x, const secpe_boot_params* bp, int* ou
   c.boot_cts_sp.clear();
   c.boot_stc_sp.clear();
   c.boot_sparse = 0;
+  c.boot_pack_min = 0;
   c.keys_perm.clear();
   c.boot_ready = false;
   c.boot_mono = nullptr;
@@ -1762,6 +1763,8 @@ extern "C" int secpe_set_boot(secpe_ctx* x, const secpe_boot_params* bp, int* ou
   const int sp = bp->sparse_slots;
   if (sp != 0 && (sp < 0 || (sp & (sp - 1)) || 2 * sp > c.N / 2 || ilog2(sp) < bp->groups))
     return set_err(SECPE_EINVAL, "sparse_slots must be 0 or a power of two n with 2n <= N/2 and log2 n >= groups");
+  if (bp->pack_min != 0 && (bp->pack_min < 2 || sp == 0))
+    return set_err(SECPE_EINVAL, "pack_min must be 0, or at least 2 with sparse_slots set");
   int k = 0;
   while ((1 << k) < bp->deg + 1) ++k;
   const int out = c.n_q - 1 - (2 * bp->groups + k + 1 + bp->r);
@@ -1776,6 +1779,7 @@ extern "C" int secpe_set_boot(secpe_ctx* x, const secpe_boot_params* bp, int* ou
   c.boot_out_level = out;
   c.boot_mode = bp->refresh ? 1 : 0;
   c.boot_sparse = sp;
+  c.boot_pack_min = bp->pack_min;
   if (c.boot_mode) c.refresh_level = out;
   boot_plan(c);
   if (out_level) *out_level = out;
@@ -2046,13 +2050,14 @@ extern "C" size_t secpe_bootstrap_workspace_bytes(secpe_ctx* x, int n) {
   Ctx& c = x->c;
   std::vector<secpe_ct> in(n, secpe_ct{(void*)(uintptr_t)0x200000000000ull, 1, ldexp(1.0, c.log_scale)});
   size_t need = 0;
-  // the larger of the full and the sparse-slot pipelines
-  for (int sparse = 0; sparse < (c.boot_sparse > 0 ? 2 : 1); ++sparse) {
+  // the largest of the full, the sparse-slot and the packed pipelines
+  for (int mode = 0; mode < (c.boot_sparse > 0 ? 3 : 1); ++mode) {
     Builder dry(c, (char*)(uintptr_t)0x100000000000ull, (size_t)1 << 44, (char*)(uintptr_t)0x400000000000ull,
                 (size_t)1 << 40, true);
     std::vector<CT> v = boot_inputs(n, in.data());
     // the dry build takes the set-up scales for granted
-    dry.bootstrap(v, sparse != 0);
+    if (mode == 2) dry.bootstrap_packed(v);
+    else dry.bootstrap(v, mode == 1);
     if (dry.err_code) {
       set_err(dry.err_code, dry.err);
       return 0;
@@ -2062,20 +2067,21 @@ extern "C" size_t secpe_bootstrap_workspace_bytes(secpe_ctx* x, int n) {
   return need + 4096;
 }
 
+// mode 0: full-slot, 1: sparse-slot, 2: window-packed
 static int bootstrap_into(secpe_ctx* x, int n, const secpe_ct* in, void* ws, size_t ws_bytes, secpe_ct* out,
-                          bool sparse) {
+                          int mode) {
   CHECK_CTX(x);
   Ctx& c = x->c;
   if (n < 1 || !in || !out || !ws) return set_err(SECPE_EINVAL, "bad bootstrap arguments");
   if (!c.boot_ready) return set_err(SECPE_EINVAL, "bootstrapping is not set up (secpe_boot_setup)");
-  if (sparse && c.boot_sparse <= 0) return set_err(SECPE_EINVAL, "sparse_slots is 0: no sparse-slot bootstrap");
+  if (mode && c.boot_sparse <= 0) return set_err(SECPE_EINVAL, "sparse_slots is 0: no sparse-slot bootstrap");
   for (int i = 0; i < n; ++i) {
     if (!in[i].data || !out[i].data) return set_err(SECPE_EINVAL, "null ciphertext");
     if (in[i].level < 1 || in[i].level >= c.n_q) return set_err(SECPE_EINVAL, "bootstrap input needs level in [1, n_q)");
   }
   std::vector<CT> res;
   int rc = run_build(x, (char*)ws, ws_bytes, [&](Builder& b) {
-    std::vector<CT> r = b.bootstrap(boot_inputs(n, in), sparse);
+    std::vector<CT> r = mode == 2 ? b.bootstrap_packed(boot_inputs(n, in)) : b.bootstrap(boot_inputs(n, in), mode == 1);
     if (b.err_code) return;
     std::vector<EwJob> j;
     for (int i = 0; i < n; ++i) {
@@ -2101,12 +2107,17 @@ static int bootstrap_into(secpe_ctx* x, int n, const secpe_ct* in, void* ws, siz
 }
 
 extern "C" int secpe_bootstrap(secpe_ctx* x, int n, const secpe_ct* in, void* ws, size_t ws_bytes, secpe_ct* out) {
-  return bootstrap_into(x, n, in, ws, ws_bytes, out, false);
+  return bootstrap_into(x, n, in, ws, ws_bytes, out, 0);
 }
 
 extern "C" int secpe_bootstrap_sparse(secpe_ctx* x, int n, const secpe_ct* in, void* ws, size_t ws_bytes,
                                       secpe_ct* out) {
-  return bootstrap_into(x, n, in, ws, ws_bytes, out, true);
+  return bootstrap_into(x, n, in, ws, ws_bytes, out, 1);
+}
+
+extern "C" int secpe_bootstrap_packed(secpe_ctx* x, int n, const secpe_ct* in, void* ws, size_t ws_bytes,
+                                      secpe_ct* out) {
+  return bootstrap_into(x, n, in, ws, ws_bytes, out, 2);
 }
 
 extern "C" int secpe_op_boot_step(secpe_ctx* x, int step, const secpe_ct* a, void* ws, size_t ws_bytes, secpe_ct* out) {

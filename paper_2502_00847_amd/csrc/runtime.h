@@ -99,6 +99,9 @@ struct Ctx {
   const double* boot_mono = nullptr;            // X^(N/2), then -X^(N/2): [2][n_q][N], NTT domain
   bool boot_ready = false;
   int boot_chunk = 8;      // ciphertexts bootstrapped together in one pass
+  // k >= 2: a refresh of at least k ciphertexts that read only slots
+  // [0, boot_sparse) again packs them into shared full-slot bootstraps
+  int boot_pack_min = 0;
   std::vector<uint64_t> mod;
   int device = 0;
   hipStream_t stream = nullptr;
@@ -390,6 +393,12 @@ class Builder {
   std::vector<CT> bootstrap(const std::vector<CT>& in, bool sparse = false);
   std::vector<CT> bootstrap_chunk(const std::vector<CT>& in);
   std::vector<CT> bootstrap_sparse_chunk(const std::vector<CT>& in);
+  // the full pipeline after the scale-down (level-0 inputs at scale
+  // q_0 / 2^ratio); frees its inputs
+  std::vector<CT> boot_core_full(std::vector<CT> x0);
+  // inputs read only on slots [0, W) again (W = boot_sparse), N/2W per
+  // shared full-slot bootstrap: output j holds input j's window at [0, W)
+  std::vector<CT> bootstrap_packed(const std::vector<CT>& in);
   // x + RotL(x, n) + RotL(x, 2n) + ... over the multiples of n below N/2
   std::vector<CT> subsum(const std::vector<CT>& in, int n);
   // client-side helpers

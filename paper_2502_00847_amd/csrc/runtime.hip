@@ -1460,7 +1460,9 @@ std::vector<CT> Builder::refresh(const std::vector<CT>& in, const std::vector<ui
       if (idx.empty()) continue;
       std::vector<CT> part;
       for (size_t i : idx) part.push_back(in[i]);
-      std::vector<CT> o = bootstrap(part, pass == 0);
+      // several such items: packed into shared full-slot bootstraps
+      const bool pack = pass == 0 && C.boot_pack_min > 1 && idx.size() >= (size_t)C.boot_pack_min;
+      std::vector<CT> o = pack ? bootstrap_packed(part) : bootstrap(part, pass == 0);
       if (err_code) return {};
       for (size_t k = 0; k < idx.size(); ++k) out[idx[k]] = o[k];
     }
@@ -2237,6 +2239,14 @@ std::vector<CT> Builder::bootstrap_chunk(const std::vector<CT>& in) {
   }
   std::vector<CT> x0 = lincomb(li, true);
   if (err_code) return {};
+  std::vector<CT> out = boot_core_full(x0);
+  if (err_code) return {};
+  counters[4] += (int64_t)n;
+  return out;
+}
+
+std::vector<CT> Builder::boot_core_full(std::vector<CT> x0) {
+  const size_t n = x0.size();
   std::vector<CT> r = mod_raise(x0);
   if (err_code) return {};
   for (CT& v : x0) free_ct(v);
@@ -2274,7 +2284,131 @@ std::vector<CT> Builder::bootstrap_chunk(const std::vector<CT>& in) {
   for (CT& v : w) free_ct(v);
   for (const CT& v : out)
     if (v.level != C.boot_out_level) { fail(-1, "bootstrap: level plan mismatch"); return {}; }
-  counters[4] += (int64_t)n;
+  return out;
+}
+
+// Window-packed bootstrap: ciphertexts that are read only on slots [0, W)
+// again (W = boot_sparse) share full-slot bootstraps, N/2W per bootstrap, in
+// groups of m taken in order.  Per group:
+//   scale-down  the sparse-slot mask of [0, W) at q_0 / 2^ratio, to level 0;
+//   pack        T = sum_i RotL(z_i, i W), z_i = v_(m-1-i): at round b node t
+//               becomes node 2t + RotL(node 2t+1, 2^b W) (an odd last node
+//               passes through); P = RotL(T, ((N/2W - m + 1) mod N/2W) W), one
+//               rotation by 2^b W per set bit, lowest first; P holds input
+//               j's window at slots [jW, jW + W), zeros elsewhere;
+//   bootstrap   the full pipeline from ModRaise on;
+//   unpack      U_0 = P'; at round b each U_o, o < 2^b, gives
+//               U_(o + 2^b) = RotL(U_o, 2^b W) while o + 2^b < m.
+// Every rotation is by a power-of-two multiple of W below N/2: the keys of
+// the sparse-slot trace.  A round's rotations share one key, so each round
+// is one batched key switch over every group.
+std::vector<CT> Builder::bootstrap_packed(const std::vector<CT>& in) {
+  if (C.boot_out_level < 0 || (!C.boot_ready && !dry)) { fail(-1, "bootstrapping is not set up"); return {}; }
+  const int W = C.boot_sparse, S = C.N / 2;
+  if (W <= 0) { fail(-1, "packed bootstrapping needs the sparse-slot width"); return {}; }
+  const int per = S / W;
+  const size_t k = in.size();
+  const double tb = ldexp((double)C.mod[0], -C.boot_ratio);
+  std::vector<CT> x1;
+  std::vector<std::vector<double>> mask;
+  std::vector<double> tg;
+  for (const CT& x : in) {
+    if (x.level < 1) { fail(-3, "bootstrap: input needs level >= 1"); return {}; }
+    CT v = x;
+    v.level = 1;
+    v.slot = -1;
+    x1.push_back(v);
+    mask.push_back(std::vector<double>(W, 1.0));
+    tg.push_back(tb);
+  }
+  std::vector<CT> v = mul_plain(x1, mask, tg);
+  if (err_code) return {};
+  std::vector<std::vector<CT>> z;
+  std::vector<int> gm;
+  for (size_t p0 = 0; p0 < k; p0 += per) {
+    const int m = (int)std::min<size_t>(per, k - p0);
+    std::vector<CT> zz;
+    for (int i = 0; i < m; ++i) zz.push_back(v[p0 + m - 1 - i]);
+    z.push_back(zz);
+    gm.push_back(m);
+  }
+  const size_t ng = z.size();
+  for (int b = 0;; ++b) {
+    std::vector<CT> rin;
+    for (size_t g = 0; g < ng; ++g)
+      for (size_t t = 0; 2 * t + 1 < z[g].size(); ++t) rin.push_back(z[g][2 * t + 1]);
+    if (rin.empty()) break;
+    std::vector<CT> r = rotate(rin, std::vector<int64_t>(rin.size(), (int64_t)W << b));
+    if (err_code) return {};
+    std::vector<std::pair<CT, CT>> pr;
+    size_t q = 0;
+    for (size_t g = 0; g < ng; ++g)
+      for (size_t t = 0; 2 * t + 1 < z[g].size(); ++t) pr.push_back({z[g][2 * t], r[q++]});
+    std::vector<CT> sum = add(pr, false);
+    if (err_code) return {};
+    for (CT& c : r) free_ct(c);
+    q = 0;
+    for (size_t g = 0; g < ng; ++g) {
+      std::vector<CT> nz;
+      for (size_t t = 0; 2 * t < z[g].size(); ++t) {
+        if (2 * t + 1 < z[g].size()) {
+          free_ct(z[g][2 * t]);
+          free_ct(z[g][2 * t + 1]);
+          nz.push_back(sum[q++]);
+        } else {
+          nz.push_back(z[g][2 * t]);
+        }
+      }
+      z[g] = nz;
+    }
+  }
+  std::vector<CT> P;
+  for (size_t g = 0; g < ng; ++g) P.push_back(z[g][0]);
+  for (int b = 0; (1 << b) < per; ++b) {
+    std::vector<CT> rin;
+    std::vector<size_t> who;
+    for (size_t g = 0; g < ng; ++g)
+      if (((per - gm[g] + 1) % per) & (1 << b)) {
+        rin.push_back(P[g]);
+        who.push_back(g);
+      }
+    if (rin.empty()) continue;
+    std::vector<CT> r = rotate(rin, std::vector<int64_t>(rin.size(), (int64_t)W << b));
+    if (err_code) return {};
+    for (size_t i = 0; i < who.size(); ++i) {
+      free_ct(P[who[i]]);
+      P[who[i]] = r[i];
+    }
+  }
+  std::vector<CT> Pb;
+  const size_t chunk = (size_t)std::max(1, C.boot_chunk);
+  for (size_t c0 = 0; c0 < ng; c0 += chunk) {
+    std::vector<CT> part(P.begin() + c0, P.begin() + std::min(ng, c0 + chunk));
+    std::vector<CT> o = boot_core_full(part);
+    if (err_code) return {};
+    Pb.insert(Pb.end(), o.begin(), o.end());
+  }
+  std::vector<std::vector<CT>> U(ng);
+  for (size_t g = 0; g < ng; ++g) {
+    U[g].resize(gm[g]);
+    U[g][0] = Pb[g];
+  }
+  for (int b = 0; (1 << b) < per; ++b) {
+    std::vector<CT> rin;
+    std::vector<std::pair<size_t, int>> who;
+    for (size_t g = 0; g < ng; ++g)
+      for (int o = 0; o < (1 << b) && o + (1 << b) < gm[g]; ++o) {
+        rin.push_back(U[g][o]);
+        who.push_back({g, o + (1 << b)});
+      }
+    if (rin.empty()) break;
+    std::vector<CT> r = rotate(rin, std::vector<int64_t>(rin.size(), (int64_t)W << b));
+    if (err_code) return {};
+    for (size_t i = 0; i < who.size(); ++i) U[who[i].first][who[i].second] = r[i];
+  }
+  std::vector<CT> out;
+  for (size_t g = 0; g < ng; ++g) out.insert(out.end(), U[g].begin(), U[g].end());
+  counters[4] += (int64_t)k;
   return out;
 }
 

@@ -26,7 +26,8 @@ class _Params(C.Structure):
 
 
 class _BootParams(C.Structure):
-    _fields_ = [(n, C.c_int) for n in ("secret_h", "K", "r", "deg", "ratio", "groups", "refresh", "sparse_slots")]
+    _fields_ = [(n, C.c_int) for n in ("secret_h", "K", "r", "deg", "ratio", "groups", "refresh", "sparse_slots",
+                                       "pack_min")]
 
 
 # the step value keygen takes for the conjugation key
@@ -132,6 +133,7 @@ def load():
         "secpe_bootstrap_workspace_bytes": (sz, [vp, i32]),
         "secpe_bootstrap": (i32, [vp, i32, ct, vp, sz, ct]),
         "secpe_bootstrap_sparse": (i32, [vp, i32, ct, vp, sz, ct]),
+        "secpe_bootstrap_packed": (i32, [vp, i32, ct, vp, sz, ct]),
         "secpe_op_boot_step": (i32, [vp, i32, ct, vp, sz, ct]),
     }
     for name, (res, args) in sig.items():
@@ -160,7 +162,7 @@ def exported_symbols():
          "secpe_server_create", "secpe_server_destroy", "secpe_server_request_bytes", "secpe_server_submit",
          "secpe_server_step", "secpe_server_launch", "secpe_server_ready", "secpe_keys_share",
          "secpe_server_collect", "secpe_set_boot", "secpe_boot_steps", "secpe_boot_key_bytes", "secpe_boot_setup",
-         "secpe_bootstrap_workspace_bytes", "secpe_bootstrap", "secpe_bootstrap_sparse", "secpe_op_boot_step"])
+         "secpe_bootstrap_workspace_bytes", "secpe_bootstrap", "secpe_bootstrap_sparse", "secpe_bootstrap_packed", "secpe_op_boot_step"])
 
 
 def _p(arr, ctype):
@@ -227,7 +229,7 @@ class Context:
         if params.get("h", 0) or params.get("boot_K", 0):
             self.set_boot(params.get("h", 0), params.get("boot_K", 0), params.get("boot_r", 0),
                           params.get("boot_deg", 1), params.get("boot_ratio", 1), params.get("boot_groups", 1),
-                          params.get("boot_refresh", 0), params.get("boot_sparse", 0))
+                          params.get("boot_refresh", 0), params.get("boot_sparse", 0), params.get("boot_pack_min", 0))
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -289,10 +291,13 @@ class Context:
         self.sk, self.evk, self.steps = other.sk, other.evk, other.steps
 
     # -- bootstrapping -----------------------------------------------------------
-    def set_boot(self, h, K, r, deg, ratio, groups, refresh, sparse_slots=0):
+    def set_boot(self, h, K, r, deg, ratio, groups, refresh, sparse_slots=0, pack_min=0):
         """Sparse secret weight and bootstrapping parameters (before keygen);
-        sparse_slots = n > 0 adds the sparse-slot bootstrap of slots [0, n)."""
-        bp = _BootParams(int(h), int(K), int(r), int(deg), int(ratio), int(groups), int(refresh), int(sparse_slots))
+        sparse_slots = n > 0 adds the sparse-slot bootstrap of slots [0, n);
+        pack_min = k >= 2 packs refreshes of at least k such ciphertexts into
+        shared full-slot bootstraps."""
+        bp = _BootParams(int(h), int(K), int(r), int(deg), int(ratio), int(groups), int(refresh), int(sparse_slots),
+                         int(pack_min))
         lvl = C.c_int(-1)
         self._check(self.lib.secpe_set_boot(self.h, C.byref(bp), C.byref(lvl)))
         self.boot_out_level = lvl.value
@@ -317,14 +322,16 @@ class Context:
             raise SecpeError(self.lib.secpe_last_error().decode())
         return self._empty(nb)
 
-    def bootstrap(self, cts, ws=None, outs=None, sparse=False):
-        """Bootstrap every ciphertext; sparse: keep slots [0, sparse_slots) only."""
+    def bootstrap(self, cts, ws=None, outs=None, sparse=False, packed=False):
+        """Bootstrap every ciphertext; sparse: keep slots [0, sparse_slots) only;
+        packed: the window-packed bootstrap (secpe_bootstrap_packed)."""
         n = len(cts)
         ws = self.bootstrap_workspace(n) if ws is None else ws
         outs = [self.new_ct() for _ in range(n)] if outs is None else outs
         ins = (_Ct * n)(*[c._c() for c in cts])
         os_ = (_Ct * n)(*[o._c() for o in outs])
-        fn = self.lib.secpe_bootstrap_sparse if sparse else self.lib.secpe_bootstrap
+        fn = (self.lib.secpe_bootstrap_packed if packed else
+              self.lib.secpe_bootstrap_sparse if sparse else self.lib.secpe_bootstrap)
         self._check(fn(self.h, n, ins, C.c_void_p(ws.data_ptr()), ws.numel() * 8, os_))
         for o, c in zip(outs, os_):
             o.level, o.scale = c.level, c.scale

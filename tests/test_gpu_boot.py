@@ -187,6 +187,78 @@ def test_packed_argmax_with_bootstrapping_bit_exact(pair):
             assert idx == i0
 
 
+@pytest.mark.parametrize("k", [1, 3, 19])
+def test_packed_bootstrap_bit_exact(pair, k):
+    """The window-packed bootstrap (inputs read only on slots [0, W), W =
+    sparse_slots, N/2W per full-slot bootstrap): a single group, a ragged one,
+    and a full group plus a ragged one, at mixed input levels."""
+    g, o = pair
+    cts = [_enc(o, np.random.default_rng(60 + k + j).uniform(-1, 1, g.slots), 2.0**49, 61 + j, 1 + j % 3)
+           for j in range(k)]
+    bo = o.bootstrap_packed(cts)
+    bg = g.bootstrap([g.import_(c.export(), c.scale) for c in cts], packed=True)
+    for a, b in zip(bg, bo):
+        _same(g, a, b)
+
+
+@pytest.fixture(scope="module")
+def packed_pair():
+    """tiny_boot with pack_min = 2: refreshes of two or more single queries
+    share full-slot bootstraps."""
+    from paper_2502_00847_amd.secpe import Context
+    g = Context(dict(P, boot_pack_min=2))
+    steps = sorted(set(g.boot_steps()) | set(argmax_rotation_steps(4, 4, g.slots)), key=lambda v: (v < 0, v))
+    g.keygen(SEED, steps)
+    g.boot_setup()
+    return g
+
+
+def test_argmax_batch_with_packed_refreshes(packed_pair, pair):
+    """A batch whose refreshes pack its queries into shared bootstraps returns
+    every plaintext index, and z follows the FP64 simulation; a query alone
+    (a refresh of one) keeps the sparse-slot bootstrap and the bits of the
+    context without packing."""
+    gp = packed_pair
+    g, _ = pair
+    qs = _boot_queries(gp, 6)
+    args = ([q["ct"] for q in qs], [q["K"] for q in qs], [q["C"] for q in qs], [q["d_min"] for q in qs],
+            [q["d_max"] for q in qs], [q["seed"] for q in qs])
+    ws = gp.workspace(args[1], args[2])
+    outs = [gp.new_ct() for _ in qs]
+    got = gp.eval_argmax_batch(*args, ws=ws, outs=outs)
+    assert gp.counters()["refresh"] >= len(qs)
+    for q, z_ct in zip(qs, got):
+        z, idx = gp.decrypt(z_ct, q["C"])
+        i0, _, margin = sim.t0_argmax(q["y"])
+        if margin / (q["d_max"] - q["d_min"]) >= 2.0**-10:
+            assert idx == i0
+        assert np.abs(z - sim.t1_argmax(q["y"], q["d_min"], q["d_max"], gp.slots)[:q["C"]]).max() < 1e-3
+    q = qs[1]
+    a = gp.eval_argmax(q["ct"], q["K"], q["C"], q["d_min"], q["d_max"], q["seed"])
+    ct = g.import_(gp.export(q["ct"]), q["ct"].scale)
+    b = g.eval_argmax(ct, q["K"], q["C"], q["d_min"], q["d_max"], q["seed"])
+    assert np.array_equal(gp.export(a), g.export(b))
+
+
+def test_packed_bootstrap_parameters_are_checked():
+    """pack_min is 0, or at least 2 with sparse_slots set; the packed entry
+    point refuses without sparse_slots."""
+    from paper_2502_00847_amd.secpe import Context, SecpeError
+    g = Context(dict(P, boot_sparse=0))
+    args = (P["h"], P["boot_K"], P["boot_r"], P["boot_deg"], P["boot_ratio"], P["boot_groups"], P["boot_refresh"])
+    with pytest.raises(SecpeError):
+        g.set_boot(*args, 0, 2)
+    with pytest.raises(SecpeError):
+        g.set_boot(*args, P["boot_sparse"], 1)
+    assert g.set_boot(*args, P["boot_sparse"], 2) > 0
+    g.set_boot(*args, 0, 0)
+    g.keygen(SEED, g.boot_steps())
+    g.boot_setup()
+    ct = g.encrypt(np.zeros((1, 4)), 8)
+    with pytest.raises(SecpeError):
+        g.bootstrap([ct], packed=True)
+
+
 def _boot_queries(g, n):
     qs = []
     for i in range(n):
