@@ -321,6 +321,8 @@ int secpe_op_boot_step(secpe_ctx* ctx, int step, const secpe_ct* a, void* ws_dev
             workgroup (set) or one;
      bit 5: output limbs per workgroup of the fused ModDown conversion, 2 (set)
             or 4.
+   (Bits 0 and 5 apply to launches of at least two workgroups per CU; a
+   smaller launch, such as one query's, takes one limb per workgroup.)
    (The two-tile variants exist for N = 2^16; elsewhere bits 2-4 change nothing.)
    Search: candidate 0, then each knob flipped in turn from the best so far
    and kept when the batch is faster (coordinate descent; 1 + 6 candidates

@@ -940,10 +940,10 @@ template __global__ void k_inner_row<7, 32>(const InnerJob* __restrict__, DevTab
 // (ready for the row pass, which the inner product does) goes to dst limb e.
 // Grid (tile, group, job): with a multiple of 8 tiles, every group of a tile
 // runs on the same XCD and rereads the digit's tile from its L2.
-// (two output limbs per workgroup fit 3 waves per SIMD without spilling; the
-// compiler's default aims at 2)
+// (one or two output limbs per workgroup fit 3 waves per SIMD without
+// spilling; the compiler's default aims at 2)
 template <int LOGS, int G, int EG>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EG == 2 ? 3 : 1, 8))) void k_modup_col(const ModUpJob* __restrict__ jobs, DevTables T) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EG <= 2 ? 3 : 1, 8))) void k_modup_col(const ModUpJob* __restrict__ jobs, DevTables T) {
   extern __shared__ double lds[];
   constexpr int RB = LOGS - 4;
   constexpr int NB = 1 << RB;
@@ -1013,7 +1013,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EG == 2 ? 3
 // follows with the ModDown or merged combine as its epilogue.  Grid (tile,
 // group, job) as for the ModUp: the groups of a tile share an XCD's L2.
 template <int LOGS, int G, int EG>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EG == 2 ? 3 : 1, 8))) void k_moddown_col(const ModDownJob* __restrict__ jobs, DevTables T) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EG <= 2 ? 3 : 1, 8))) void k_moddown_col(const ModDownJob* __restrict__ jobs, DevTables T) {
   extern __shared__ double lds[];
   constexpr int RB = LOGS - 4;
   constexpr int NB = 1 << RB;
@@ -1077,6 +1077,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EG == 2 ? 3
   template __global__ void k_moddown_col<8, 16, EG>(const ModDownJob* __restrict__, DevTables); \
   template __global__ void k_moddown_col<7, 32, EG>(const ModDownJob* __restrict__, DevTables); \
   template __global__ void k_moddown_col<6, 64, EG>(const ModDownJob* __restrict__, DevTables);
+MODDOWN_INST(1)
 MODDOWN_INST(2)
 MODDOWN_INST(4)
 
@@ -1084,6 +1085,7 @@ MODDOWN_INST(4)
   template __global__ void k_modup_col<8, 16, EG>(const ModUpJob* __restrict__, DevTables); \
   template __global__ void k_modup_col<7, 32, EG>(const ModUpJob* __restrict__, DevTables); \
   template __global__ void k_modup_col<6, 64, EG>(const ModUpJob* __restrict__, DevTables);
+MODUP_INST(1)
 MODUP_INST(2)
 MODUP_INST(4)
 
@@ -1816,12 +1818,22 @@ void launch_ntt_pass(const DevTables& T, bool inverse, const NttJob* jobs, int n
 
 bool inner_row_fused(const DevTables& T) { return T.log_n > 12; }
 
+// A column-fused base conversion whose grid (tile, output group, job) would
+// hold fewer than two workgroups per CU at eg output limbs per workgroup takes
+// one limb per workgroup instead: a single query's conversions then still fill
+// the chip (the source tiles, read once per group, are few and stay in L2).
+// Every eg gives the same residues.
+static int conv_eg(int eg, int tiles, int max_out, int n_jobs) {
+  eg = eg == 2 ? 2 : 4;
+  return (long)tiles * ((max_out + eg - 1) / eg) * n_jobs < 512 ? 1 : eg;
+}
+
 void launch_modup_col(const DevTables& T, const ModUpJob* jobs, int n_jobs, int max_ext, int eg, hipStream_t s) {
   if (n_jobs <= 0 || max_ext <= 0) return;
   const int log_n = T.log_n;
   const int k1 = log_n / 2;   // column length of the two-pass split
   const int g = k1 == 8 ? 16 : k1 == 7 ? 32 : 64;
-  eg = eg == 2 ? 2 : 4;
+  eg = conv_eg(eg, (1 << (log_n - k1)) / g, max_ext, n_jobs);
   // max_ext bounds the output limbs of a job (n_ext minus its digit)
   dim3 grid((1 << (log_n - k1)) / g, (max_ext + eg - 1) / eg, n_jobs);
   const size_t lds = ntt_lds_bytes(k1, g);
@@ -1829,7 +1841,9 @@ void launch_modup_col(const DevTables& T, const ModUpJob* jobs, int n_jobs, int 
   if (k1 == 8) hipLaunchKernelGGL((k_modup_col<8, 16, EG>), grid, dim3(256), lds, s, jobs, T);     \
   else if (k1 == 7) hipLaunchKernelGGL((k_modup_col<7, 32, EG>), grid, dim3(256), lds, s, jobs, T); \
   else hipLaunchKernelGGL((k_modup_col<6, 64, EG>), grid, dim3(256), lds, s, jobs, T);
-  if (eg == 2) {
+  if (eg == 1) {
+    LAUNCH_MODUP(1)
+  } else if (eg == 2) {
     LAUNCH_MODUP(2)
   } else {
     LAUNCH_MODUP(4)
@@ -1843,14 +1857,16 @@ void launch_moddown_col(const DevTables& T, const ModDownJob* jobs, int n_jobs, 
   const int log_n = T.log_n;
   const int k1 = log_n / 2;   // column length of the two-pass split
   const int g = k1 == 8 ? 16 : k1 == 7 ? 32 : 64;
-  eg = eg == 2 ? 2 : 4;
+  eg = conv_eg(eg, (1 << (log_n - k1)) / g, max_chain, n_jobs);
   dim3 grid((1 << (log_n - k1)) / g, (max_chain + eg - 1) / eg, n_jobs);
   const size_t lds = ntt_lds_bytes(k1, g);
 #define LAUNCH_MODDOWN(EG)                                                                          \
   if (k1 == 8) hipLaunchKernelGGL((k_moddown_col<8, 16, EG>), grid, dim3(256), lds, s, jobs, T);     \
   else if (k1 == 7) hipLaunchKernelGGL((k_moddown_col<7, 32, EG>), grid, dim3(256), lds, s, jobs, T); \
   else hipLaunchKernelGGL((k_moddown_col<6, 64, EG>), grid, dim3(256), lds, s, jobs, T);
-  if (eg == 2) {
+  if (eg == 1) {
+    LAUNCH_MODDOWN(1)
+  } else if (eg == 2) {
     LAUNCH_MODDOWN(2)
   } else {
     LAUNCH_MODDOWN(4)

@@ -257,6 +257,18 @@ def test_two_pass_sizes_key_switching_bit_exact(name):
     _same(g, g.mul_relin_rescale(ga, ga), o.mul_relin_rescale(a, a))
     for st in (1, 3):
         _same(g, g.rotate(gb, st), o.rotate(b, st))
+    # 32 rotations in one launch: enough workgroups for the grouped base
+    # conversions (a single key switch takes one output limb per workgroup);
+    # uniform residues, since a key switch needs no encodable plaintext
+    cs = []
+    for i in range(32):
+        lv = 7 - i % 3
+        data = np.stack([np.stack([rng.integers(0, primes[t], o.n, dtype=np.uint64) for t in range(lv + 1)])
+                         for _ in range(2)])
+        cs.append(o.ct_import(data, 2.0**40))
+    gs = g.rotate_batch([g.import_(c.export(), c.scale) for c in cs], [1 + 2 * (i % 2) for i in range(32)])
+    for i, (gc, c) in enumerate(zip(gs, cs)):
+        _same(g, gc, o.rotate(c, 1 + 2 * (i % 2)))
     print(f"[{name}] Algorithm 1, K = C = 2 (oracle and GPU)", flush=True)
     y, zo, zg = _argmax_pair(g, o, 2, 2, q=7)
     _same(g, zg, zo)
