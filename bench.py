@@ -876,7 +876,21 @@ def main():
         g.sync()
         single.append((time.perf_counter() - ts) * 1e3)
     single = np.array(single[1:])
+    launches2 = g.counters()["launches"]
     zz, idx2 = g.decrypt(z2, d2["C"])
+    # the same query replayed from a captured hipGraph (its launches recorded
+    # by the first call; bit-identical results)
+    gout = [g.new_ct()]
+    gsingle = []
+    for r in range(6):
+        g.sync()
+        ts = time.perf_counter()
+        zg2 = g.eval_argmax_batch([ct2], [d2["K"]], [d2["C"]], [d2["d_min"]], [d2["d_max"]], [d2["refresh_seed"]],
+                                  ws=ws2, outs=gout, graph=True, owner=g.owner)[0]
+        g.sync()
+        gsingle.append((time.perf_counter() - ts) * 1e3)
+    gsingle = np.array(gsingle[1:])
+    graph_same = bool(np.array_equal(g.export(zg2), g.export(z2)))
     # the same query once more under the segment profiler: the computation
     # between refreshes and each refresh, in order
     g.profile_begin("segments")
@@ -963,7 +977,10 @@ def main():
                             "top2_margin": round(margin2, 4),
                             "top2_margin_normalised": round(margin2 / (d2["d_max"] - d2["d_min"]), 6),
                             "z": [round(float(v), 9) for v in zz],
-                            "z_minus_onehot_linf": float(np.abs(zz - onehot).max())},
+                            "z_minus_onehot_linf": float(np.abs(zz - onehot).max()),
+                            "kernel_launches": launches2,
+                            "graph_replay_p50": round(float(np.percentile(gsingle, 50)), 3),
+                            "graph_replay_bits_equal": graph_same},
         "index_ok": f"{ok}/{B}",
         "index_ok_at_margin_2^-10": f"{ok_margin}/{n_margin}",
         "roofline": roofline,
