@@ -240,6 +240,43 @@ def test_argmax_batch_with_packed_refreshes(packed_pair, pair):
     assert np.array_equal(gp.export(a), g.export(b))
 
 
+def test_packed_refreshes_under_graph_replay_and_the_server(packed_pair):
+    """With packed refreshes, hipGraph replays of a batch give the eager
+    batch's bits (with other work between the replays), and the
+    continuous-batching server, with staggered arrivals, returns every
+    plaintext index."""
+    from paper_2502_00847_amd.secpe import Server
+    gp = packed_pair
+    qs = _boot_queries(gp, 5)
+    args = ([q["ct"] for q in qs], [q["K"] for q in qs], [q["C"] for q in qs], [q["d_min"] for q in qs],
+            [q["d_max"] for q in qs], [q["seed"] for q in qs])
+    ws = gp.workspace(args[1], args[2])
+    outs = [gp.new_ct() for _ in qs]
+    eager = [gp.export(c) for c in gp.eval_argmax_batch(*args, ws=ws, outs=outs)]
+    for rep in range(3):
+        got = gp.eval_argmax_batch(*args, ws=ws, outs=outs, graph=True)
+        gp.sync()
+        for a, c in zip(eager, got):
+            assert np.array_equal(gp.export(c), a), rep
+        gp.eval_argmax(qs[0]["ct"], qs[0]["K"], qs[0]["C"], qs[0]["d_min"], qs[0]["d_max"], qs[0]["seed"])
+    srv = Server(gp, 3 * gp.workspace_bytes(args[1], args[2]), max_active=8)
+    tickets = {}
+    arrivals = {0: [0, 1, 2], 2: [3], 3: [4]}
+    step = 0
+    while len(srv.results) < len(qs):
+        for i in arrivals.get(step, []):
+            q = qs[i]
+            tickets[i] = srv.submit(q["ct"], q["K"], q["C"], q["d_min"], q["d_max"], q["seed"])
+        srv.step()
+        step += 1
+        assert step < 500
+    for i, q in enumerate(qs):
+        z, idx = gp.decrypt(srv.results[tickets[i]], q["C"])
+        i0, _, margin = sim.t0_argmax(q["y"])
+        if margin / (q["d_max"] - q["d_min"]) >= 2.0**-10:
+            assert idx == i0, i
+
+
 def test_packed_bootstrap_parameters_are_checked():
     """pack_min is 0, or at least 2 with sparse_slots set; the packed entry
     point refuses without sparse_slots."""
