@@ -19,7 +19,8 @@ Cases:
              seeded level-3 ciphertext, the sparse-slot bootstrap (n = 32) of
              the same ciphertext, and Algorithm 1 (K=2, C=2) with every
              refresh a (sparse-slot) bootstrap (the oracle takes about ten
-             minutes per full bootstrap here).
+             minutes per full bootstrap here); and the window-packed
+             bootstrap of three seeded ciphertexts at levels 3, 2, 3.
 Each case keys its own oracle with the rotations its shape needs (a key
 depends only on the seed and its Galois element, so these equal the keys of
 any larger set).  Cases run in parallel processes.
@@ -84,6 +85,7 @@ for _q in config5_sample():
 CASES["boot13_bootstrap"] = ("p13_boot", "bootstrap", 0, "merged")
 CASES["boot13_sparse"] = ("p13_boot", "bootstrap_sparse", 0, "merged")
 CASES["boot13_argmax"] = ("p13_boot", "argmax_boot", 0, "merged")
+CASES["boot13_packed"] = ("p13_boot", "bootstrap_packed", 0, "merged")
 
 BOOT_SEED = 0xB007
 
@@ -98,6 +100,14 @@ def boot_input(slots):
     encrypted with seed 7 and lowered to level 3."""
     import numpy as np
     return np.random.default_rng(5).uniform(-1, 1, slots), 2.0**49, 7, 3
+
+
+def packed_inputs(slots):
+    """The window-packed case: three inputs, uniform slot values in [-1, 1]
+    (generators 5, 6, 7) at scale 2^49, encrypted with seeds 7, 8, 9 and
+    lowered to levels 3, 2, 3."""
+    import numpy as np
+    return [(np.random.default_rng(5 + j).uniform(-1, 1, slots), 2.0**49, 7 + j, 3 - j % 2) for j in range(3)]
 
 
 def argmax_boot_query():
@@ -131,6 +141,21 @@ def run_boot_case(name):
         zz = o.decrypt_decode(out, o.slots)
         extra = {"max_error_log2": float(np.log2(np.abs(zz - want).max()))}
         zrec = []
+    elif kind == "bootstrap_packed":
+        import numpy as np
+        ins = [o.lower(o.encrypt(o.encode(z, sc), sc, sd), lv) for z, sc, sd, lv in packed_inputs(o.slots)]
+        outs = o.bootstrap_packed(ins)
+        W_ = o.boot_sparse
+        err = max(float(np.abs(o.decrypt_decode(b, o.slots)[:W_] - z[:W_]).max())
+                  for b, (z, _, _, _) in zip(outs, packed_inputs(o.slots)))
+        rec = {"params": pset, "kind": kind,
+               "input_sha256": digest(np.concatenate([c.export().ravel() for c in ins])),
+               "output_sha256": digest(np.concatenate([c.export().ravel() for c in outs])),
+               "level": outs[0].level, "scale": outs[0].scale, "z": [],
+               "oracle_seconds": round(time.time() - t, 1), "secret_weight": int((o.secret() != 0).sum()),
+               "max_error_log2": float(np.log2(err))}
+        print(f"{name}: keygen {tk:.1f} s, {rec['oracle_seconds']:.1f} s, level {rec['level']}", flush=True)
+        return name, rec
     else:
         d = argmax_boot_query()
         ct = o.encrypt_logits(d["logits"], d["encrypt_seed"])

@@ -512,6 +512,23 @@ def test_p13_sparse_bootstrap_matches_oracle_digest(p13boot):
     assert err < 2.0**-16
 
 
+def test_p13_packed_bootstrap_matches_oracle_digest(p13boot):
+    """The window-packed bootstrap (W = 32: 128 inputs per full-slot
+    bootstrap) of three inputs at levels 3, 2, 3, at the two-pass NTT size."""
+    g, gold = p13boot
+    rec = gold["boot13_packed"]
+    cts = []
+    for j in range(3):
+        z = np.random.default_rng(5 + j).uniform(-1, 1, g.slots)
+        full = g.encrypt_coeffs(g.encode(z, 2.0**49), 2.0**49, 7 + j)
+        lv = 3 - j % 2
+        cts.append(g.import_(g.export(full)[:, :lv + 1, :], full.scale))
+    assert _digest(np.concatenate([g.export(c).ravel() for c in cts])) == rec["input_sha256"]
+    outs = g.bootstrap(cts, packed=True)
+    assert all((b.level, b.scale) == (rec["level"], rec["scale"]) for b in outs)
+    assert _digest(np.concatenate([g.export(b).ravel() for b in outs])) == rec["output_sha256"]
+
+
 def test_p13_argmax_with_bootstrapping_matches_oracle_digest(p13boot):
     """Algorithm 1 (K = 2, C = 2) with every refresh a bootstrap, no key owner."""
     g, gold = p13boot
