@@ -438,6 +438,28 @@ def test_full_sparse_bootstrap_precision(full):
         assert err < 2.0**-12
 
 
+def test_full_packed_bootstrap_precision(full):
+    """N = 2^16: the window-packed bootstrap of five ciphertexts (W = 64, 512 per
+    full-slot bootstrap) returns each input's slots [0, W) at [0, W) and the
+    next inputs' windows after them, within 2^-12, whatever the inputs held
+    outside their windows."""
+    g = full
+    W_ = W.PARAMS["full_boot"]["boot_sparse"]
+    rng = np.random.default_rng(8)
+    zs = [rng.uniform(-1, 1, g.slots) for _ in range(5)]
+    cts = [g.encrypt(z.reshape(1, -1), 60 + j) for j, z in enumerate(zs)]
+    outs = g.bootstrap(cts, packed=True)
+    err = 0.0
+    for j, b in enumerate(outs):
+        assert b.level == g.n_q - 1 - 16 and b.scale == 2.0**50
+        got, _ = g.decrypt(b, g.slots)
+        for i in range(5 - j):
+            err = max(err, float(np.abs(got[i * W_:(i + 1) * W_] - zs[j + i][:W_]).max()))
+        assert np.abs(got[(5 - j) * W_:(6 - j) * W_]).max() < 2.0**-12   # past the group's last input
+    print(f"[boot] full packed: max error 2^{np.log2(err):.1f}", flush=True)
+    assert err < 2.0**-12
+
+
 def test_full_argmax_with_bootstrapping(full):
     """Config 2 (K = 8, C = 4) with every refresh a (sparse-slot) bootstrap: the
     index is the plaintext argmax and z follows the FP64 simulation."""
