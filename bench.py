@@ -742,6 +742,8 @@ def main():
     ap.add_argument("--keyswitch", type=int, default=1, help="time 64 random-step rotations at 24 limbs")
     ap.add_argument("--calib", type=int, default=0, help="copy 1 GiB first (counter calibration kernel)")
     ap.add_argument("--variants", type=int, default=1, help="precise-Sign and large-n single-query runs")
+    ap.add_argument("--schedule", type=int, default=-1,
+                    help="apply this autotuner candidate instead of searching (-1: search)")
     ap.add_argument("--ntt-only", type=int, default=0, help="only the NTT microbenchmark (64 x 2 x 24 limbs)")
     ap.add_argument("--keyswitch-only", type=int, default=0,
                     help="only the rotation microbenchmark (64 random-step rotations, 64 keys, 24 limbs)")
@@ -817,9 +819,15 @@ def main():
 
     # autotuner: schedule candidates timed on the first chunk; the fastest stays set
     grp = groups[0]
-    chosen, cands = g.autotune([cts[i] for i in grp], [Ks[i] for i in grp], [Cs[i] for i in grp],
-                               [qs[i]["d_min"] for i in grp], [qs[i]["d_max"] for i in grp],
-                               [qs[i]["refresh_seed"] for i in grp], ws=ws, outs=[outs[i] for i in grp], owner=g.owner)
+    if args.schedule >= 0:
+        # a fixed schedule (e.g. so that separate profiler runs issue the same kernels)
+        g.set_schedule(args.schedule)
+        chosen, cands = args.schedule, [dict(g.AUTOTUNE_CANDIDATES[args.schedule], index=args.schedule, ms=None)]
+    else:
+        chosen, cands = g.autotune([cts[i] for i in grp], [Ks[i] for i in grp], [Cs[i] for i in grp],
+                                   [qs[i]["d_min"] for i in grp], [qs[i]["d_max"] for i in grp],
+                                   [qs[i]["refresh_seed"] for i in grp], ws=ws, outs=[outs[i] for i in grp],
+                                   owner=g.owner)
     _log(f"autotune: candidate {chosen} of {cands}")
     for w in range(args.warmup):
         run_step(bool(args.graph))
@@ -985,7 +993,8 @@ def main():
         "index_ok_at_margin_2^-10": f"{ok_margin}/{n_margin}",
         "roofline": roofline,
         "autotune": {"chosen": next(c for c in cands if c["index"] == chosen), "candidates": cands,
-                     "what": "batch of the first chunk timed under each schedule; the fastest is used"},
+                     "what": ("batch of the first chunk timed under each schedule; the fastest is used"
+                              if args.schedule < 0 else "fixed by --schedule, not searched")},
     }
     result["plain_path"] = plain_path_rate(g, qs, cts)
     result["plain_path"]["batched_speedup"] = round(value / result["plain_path"]["argmax_per_s"], 2)
