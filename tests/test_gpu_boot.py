@@ -460,6 +460,33 @@ def test_full_packed_bootstrap_precision(full):
     assert err < 2.0**-12
 
 
+def test_full_packed_refreshes_at_the_window_limit():
+    """N = 2^16, C' = 32: every refresh reads 2C' = 64 = W slots, the widest
+    span the sparse-slot and window-packed bootstraps take.  A batch of three
+    such queries with packed refreshes returns every plaintext index, and z
+    follows the FP64 simulation."""
+    from paper_2502_00847_amd.secpe import Context
+    p = dict(W.PARAMS["full_boot"], boot_pack_min=2)
+    g = Context(p)
+    steps = sorted(set(g.boot_steps()) | set(g.argmax_steps(8, 32)), key=lambda v: (v < 0, v))
+    print(f"[boot] window-limit keygen {len(steps)} keys", flush=True)
+    g.keygen(SEED, steps)
+    g.boot_setup()
+    shapes = [(4, 17), (8, 20), (5, 32)]
+    ys = [W.logits(14, i, K, C) for i, (K, C) in enumerate(shapes)]
+    cts = [g.encrypt(y, 500 + i) for i, y in enumerate(ys)]
+    lo = [W.d_bounds(K)[0] for K, _ in shapes]
+    hi = [W.d_bounds(K)[1] for K, _ in shapes]
+    zs = g.eval_argmax_batch(cts, [K for K, _ in shapes], [C for _, C in shapes], lo, hi, [600, 601, 602])
+    assert g.counters()["refresh"] >= len(shapes)
+    for (K, C), y, z_ct, l, h in zip(shapes, ys, zs, lo, hi):
+        z, idx = g.decrypt(z_ct, C)
+        i0, _, margin = sim.t0_argmax(y)
+        if margin / (h - l) >= 2.0**-10:
+            assert idx == i0, (K, C)
+        assert np.abs(z - sim.t1_argmax(y, l, h, g.slots)[:C]).max() < 1e-3, (K, C)
+
+
 def test_full_argmax_with_bootstrapping(full):
     """Config 2 (K = 8, C = 4) with every refresh a (sparse-slot) bootstrap: the
     index is the plaintext argmax and z follows the FP64 simulation."""
