@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <tuple>
 
 extern "C" void secpe_cos_table_dd(int log_n, double* hi, double* lo);
 
@@ -1343,6 +1344,8 @@ std::vector<CT> Builder::plain_op(const std::vector<CT>& in, const std::vector<s
   std::vector<IntSpreadJob> j_sp;
   std::vector<NttJob> j_ntt;
   std::vector<EwJob> j_op;
+  // items with the same values, plaintext scale and level share one encoding
+  std::map<std::tuple<int, double, std::vector<double>, std::vector<int>>, double*> done;
   for (size_t i = 0; i < in.size(); ++i) {
     const CT& x = in[i];
     const int nl = x.level + 1;
@@ -1352,32 +1355,41 @@ std::vector<CT> Builder::plain_op(const std::vector<CT>& in, const std::vector<s
       ps = (*target)[i] * ql;
       ps = ps / x.scale;
     }
-    int64_t* m = (int64_t*)scratch(N);
-    double* pt = scratch((size_t)nl * N);
-    EncodeJob ej{};
-    if (sparse) {
-      const SparseSlots& sp = (*sparse)[i];
-      std::vector<uint32_t> g(sp.slot.size());
-      for (size_t j = 0; j < sp.slot.size(); ++j) {
-        // 5^slot mod 2N
-        uint64_t r = 1, b = 5;
-        for (uint32_t e = (uint32_t)sp.slot[j]; e; e >>= 1, b = b * b % m2n)
-          if (e & 1) r = r * b % m2n;
-        g[j] = (uint32_t)r;
-      }
-      ej.z = put(sp.val);
-      ej.gs = put(g);
-      ej.nnz = (int)sp.val.size();
+    const auto key = sparse ? std::make_tuple(x.level, ps, (*sparse)[i].val, (*sparse)[i].slot)
+                            : std::make_tuple(x.level, ps, (*dense)[i], std::vector<int>());
+    double* pt = nullptr;
+    auto hit = done.find(key);
+    if (hit != done.end()) {
+      pt = hit->second;
     } else {
-      ej.z = put((*dense)[i]);
-      ej.nnz = (int)(*dense)[i].size();
+      int64_t* m = (int64_t*)scratch(N);
+      pt = scratch((size_t)nl * N);
+      done.emplace(key, pt);
+      EncodeJob ej{};
+      if (sparse) {
+        const SparseSlots& sp = (*sparse)[i];
+        std::vector<uint32_t> g(sp.slot.size());
+        for (size_t j = 0; j < sp.slot.size(); ++j) {
+          // 5^slot mod 2N
+          uint64_t r = 1, b = 5;
+          for (uint32_t e = (uint32_t)sp.slot[j]; e; e >>= 1, b = b * b % m2n)
+            if (e & 1) r = r * b % m2n;
+          g[j] = (uint32_t)r;
+        }
+        ej.z = put(sp.val);
+        ej.gs = put(g);
+        ej.nnz = (int)sp.val.size();
+      } else {
+        ej.z = put((*dense)[i]);
+        ej.nnz = (int)(*dense)[i].size();
+      }
+      ej.m = m;
+      ej.scale_hi = ps * 2.0 / (double)N;
+      ej.scale_lo = 0.0;
+      j_enc.push_back(ej);
+      j_sp.push_back(IntSpreadJob{m, pt, nl, nl});
+      j_ntt.push_back(NttJob{pt, pt, nl, nl, 0, 0});
     }
-    ej.m = m;
-    ej.scale_hi = ps * 2.0 / (double)N;
-    ej.scale_lo = 0.0;
-    j_enc.push_back(ej);
-    j_sp.push_back(IntSpreadJob{m, pt, nl, nl});
-    j_ntt.push_back(NttJob{pt, pt, nl, nl, 0, 0});
     CT o = new_ct(x.level, x.scale);
     EwJob e{};
     e.o0 = c0(o); e.o1 = c1(o); e.a0 = c0(x); e.a1 = c1(x); e.b0 = pt;
