@@ -52,7 +52,8 @@ struct NttJob {
   double* dst;
   int n_limbs, n_chain, skip_lo, skip_hi;
   int spread_from, epi;
-  int sq, pad;
+  int sq;
+  int centre;   // inverse transform: store the last pass centred, in (-p/2, p/2]
   const double* ea;
   const double* eb;
   const double* ebase;
@@ -118,9 +119,10 @@ struct ModUpJob {
 // Conv_{B->Q} with centred digits: src = the limbs of B (coefficient domain) ->
 // dst chain limbs 0..n_chain-1.  B is the special primes (first_prime < 0) or
 // prime first_prime followed by the special primes.  With cinv null, src
-// already holds the canonical y_b = [x_b (B/b)^-1]_b (the inverse transform's
-// last pass scaled by them).  The column-fused kernel writes dst after the
-// forward transform's column pass.
+// already holds y_b = [x_b (B/b)^-1]_b (the inverse transform's last pass
+// scaled by them), canonical or centred.  The column-fused kernel takes it
+// centred (NttJob::centre on that pass) and writes dst after the forward
+// transform's column pass.
 struct ModDownJob {
   const double* src;    // [|B|][N]
   double* dst;          // [n_chain][N]

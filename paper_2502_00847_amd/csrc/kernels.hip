@@ -48,6 +48,12 @@ __device__ __forceinline__ void tile_sync() {
   }
 }
 
+// canonical residue, or centred in (-p/2, p/2] (the digits of a centred base conversion)
+__device__ __forceinline__ double canon_out(double v, const Mod& m, int centre) {
+  const double c = canon(v, m);
+  return centre && 2.0 * c > m.p ? c - m.p : c;
+}
+
 __device__ __forceinline__ double2 ld2(const double* p, size_t o) {
   const dv2 v = *(cgdbl2*)(CGPTR(p) + o);
   return make_double2(v.x, v.y);
@@ -376,7 +382,7 @@ __global__ __launch_bounds__(256) void k_ntt(const NttJob* __restrict__ jobs, De
         b = mul_w(red(b, m), ni, niq, m.p);
       }
       if (epi) ntt_epilogue(J, l, (size_t)l * N + (size_t)row0 * S + 2 * i, a, b, m);
-      else d2[i] = make_double2(canon(a, m), canon(b, m));
+      else d2[i] = make_double2(canon_out(a, m, J.centre), canon_out(b, m, J.centre));
     }
   }
 }
@@ -717,7 +723,7 @@ __attribute__((amdgpu_waves_per_eu(MODE == NTT_ROW ? (P == 1 ? 4 : 2) : 1, MODE 
     for (int e = 0; e < 16; ++e) {
       double v = x[e];
       if (scale) v = J.ek ? mul_mod(red(v, m), ys, m) : mul_w(red(v, m), ni, niq, m.p);
-      dst[gaddr(va, e * NB + la)] = canon(v, m);
+      dst[gaddr(va, e * NB + la)] = canon_out(v, m, J.centre);
     }
     } else {
     // (the inverse column pass: every tile's loads are issued first)
@@ -757,7 +763,7 @@ __attribute__((amdgpu_waves_per_eu(MODE == NTT_ROW ? (P == 1 ? 4 : 2) : 1, MODE 
       for (int e = 0; e < 16; ++e) {
         double v = x[e];
         if (scale) v = J.ek ? mul_mod(red(v, m), yk, m) : mul_w(red(v, m), ni, niq, m.p);
-        dst[(size_t)(e * NB + la) * C + cp + va] = canon(v, m);
+        dst[(size_t)(e * NB + la) * C + cp + va] = canon_out(v, m, J.centre);
       }
     }
     }
@@ -1004,14 +1010,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EG <= 2 ? 3
   }
 }
 // The centred conversion B -> Q_l of the ModDown fused with the column pass
-// of the forward transform of its outputs (N > 2^12): src holds the canonical
-// y_b = [x_b (B/b)^-1]_b (the inverse transform's last pass applied (B/b)^-1),
-// taken centred in (-b/2, b/2]; a workgroup owns one column tile and a group
-// of EG chain limbs t, streams the |B| source limbs through registers once,
-// accumulating out_t = sum_b y_b (B/b) mod q_t for the group, and runs the
-// column pass on each out_t into dst limb t.  The forward transform's row pass
-// follows with the ModDown or merged combine as its epilogue.  Grid (tile,
-// group, job) as for the ModUp: the groups of a tile share an XCD's L2.
+// of the forward transform of its outputs (N > 2^12): src holds
+// y_b = [x_b (B/b)^-1]_b centred in (-b/2, b/2] (the inverse transform's last
+// pass applied (B/b)^-1 and centred its output); a workgroup owns one column
+// tile and a group of EG chain limbs t, streams the |B| source limbs through
+// registers once, accumulating out_t = sum_b y_b (B/b) mod q_t for the group,
+// and runs the column pass on each out_t into dst limb t.  The forward
+// transform's row pass follows with the ModDown or merged combine as its
+// epilogue.  Grid (tile, group, job) as for the ModUp: the groups of a tile
+// share an XCD's L2.
 template <int LOGS, int G, int EG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EG <= 2 ? 3 : 1, 8))) void k_moddown_col(const ModDownJob* __restrict__ jobs, DevTables T) {
   extern __shared__ double lds[];
@@ -1043,13 +1050,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EG <= 2 ? 3
 #pragma unroll
     for (int k = 0; k < 16; ++k) acc[g][k] = 0.0;
   for (int i = 0; i < nb; ++i) {
-    const int pr = i < extra ? J.first_prime : T.n_q + i - extra;
-    const double b = KPTR(T.mod)[pr];
     double y[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) y[k] = CGPTR(J.src)[(size_t)i * N + (size_t)(k * NB + la) * C + c0 + va];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) y[k] = 2.0 * y[k] > b ? y[k] - b : y[k];
 #pragma unroll
     for (int g = 0; g < EG; ++g) {
       const double c = KPTR(J.chat)[(size_t)ee[g] * nb + i];

@@ -763,6 +763,7 @@ void Builder::ks_back(const std::vector<KsItem>& items, const std::vector<KsTmp>
       // the inverse transform's last pass applies (P/p_k)^-1 for the conversion
       NttJob ji{sp, sp, n_p, 0, 0, 0};
       ji.ek = C.md_ytab;
+      ji.centre = 1;
       j_inv_acc.push_back(ji);
       double* cv = conv + (size_t)w * nc * N;
       j_down.push_back(ModDownJob{sp, cv, nullptr, C.md_chat, nc, -1});
@@ -948,6 +949,7 @@ std::vector<CT> Builder::relin_rescale(const std::vector<Deg2>& xs) {
       // (its last pass also applies (B/b)^-1 for the conversion)
       NttJob ji{aw, aw, n_ext, nc, 0, l};
       ji.ek = C.rr_ytab + (size_t)l * (n_q + n_p);
+      ji.centre = 1;
       j_inv_acc.push_back(ji);
       double* cv = conv + (size_t)w * l * N;
       j_conv.push_back(ModDownJob{aw + (size_t)l * N, cv, nullptr, C.rr_chat + (size_t)l * n_q * nb, l, l});
