@@ -2,9 +2,9 @@
 same seeded inputs (coefficient-domain residues compared element by element),
 through the C ABI (include/secpe.h) via its Python binding.
 
-Parameter sets: 'tiny' (N=2^10, single-pass NTT), 'p13' (N=2^13, the toy's
-two-pass NTT split 2^6 x 2^7), 'p14' (2^7 x 2^7), 'p15' (2^7 x 2^8).  Full
-N=2^16 lives in test_gpu_full.py.
+Parameter sets: 'tiny' (N=2^10, single-pass NTT), 'p11' and 'p12' (the other
+single-pass sizes), 'p13' (N=2^13, the toy's two-pass NTT split 2^6 x 2^7),
+'p14' (2^7 x 2^7), 'p15' (2^7 x 2^8).  Full N=2^16 lives in test_gpu_full.py.
 """
 import numpy as np
 import pytest
@@ -32,6 +32,8 @@ def _params(name):
         return dict(log_n=14, n_q=8, q_bits=40, n_p=3, p_bits=51, log_scale=40, dg=2, df=2, min_level=1)
     if name == "p15":
         return dict(log_n=15, n_q=8, q_bits=40, n_p=3, p_bits=51, log_scale=40, dg=2, df=2, min_level=1)
+    if name in ("p11", "p12"):
+        return dict(log_n=int(name[1:]), n_q=8, q_bits=40, n_p=3, p_bits=51, log_scale=40, dg=2, df=2, min_level=1)
     return dict(W.PARAMS[name])
 
 
@@ -237,12 +239,13 @@ def test_key_switch_bit_exact(tiny, level):
     assert np.array_equal(gu[0], ou[0]) and np.array_equal(gu[1], ou[1])
 
 
-@pytest.mark.parametrize("name", ["p14", "p15"])
-def test_two_pass_sizes_key_switching_bit_exact(name):
-    """N = 2^14 (2^7 x 2^7) and 2^15 (2^7 x 2^8) run their own shapes of the
-    column-fused ModUp and ModDown and of the inner product's row pass: key
-    switches at full and ragged digit counts, the merged relinearise + rescale,
-    rotations and a whole Algorithm 1 match the oracle bit for bit."""
+@pytest.mark.parametrize("name", ["p11", "p12", "p14", "p15"])
+def test_other_sizes_key_switching_bit_exact(name):
+    """N = 2^11 and 2^12 (the single-pass NTT of a whole limb per workgroup),
+    2^14 (2^7 x 2^7) and 2^15 (2^7 x 2^8; their own shapes of the
+    column-fused ModUp and ModDown and of the inner product's row pass): key
+    switches at full and ragged digit counts, the merged relinearise +
+    rescale, rotations and a whole Algorithm 1 match the oracle bit for bit."""
     g, o, steps = _pair(name, 2, 2)
     rng = np.random.default_rng(14)
     primes = [int(v) for v in o.primes]
