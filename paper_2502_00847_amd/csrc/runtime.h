@@ -326,7 +326,8 @@ class Builder {
   void ks_back(const std::vector<KsItem>& items, const std::vector<KsTmp>& tmp, bool first_pass_done);
   // hoisted rotations: the ModUp of each input's c1 once (ext, NTT domain,
   // in scratch until the caller releases it), then rotations of every input
-  // by any steps, each applying X -> X^g to the raised digits
+  // by any steps, each applying X -> X^g to the raised digits (or, for a step
+  // with a permuted key, to the two results after the ModDown)
   struct Hoisted {
     std::vector<CT> in;
     std::vector<double*> ext;
