@@ -634,7 +634,7 @@ def bootstrap_rate(n_batch=8, n_queries=32, pset="full_boot", packed=True, compa
     del ws
     qs = [W.query(3, i) for i in range(n_queries)]
 
-    def batch_rate(gc, qs=qs):
+    def batch_rate(gc, qs=qs, marks=None):
         n_queries = len(qs)
         qcts = [gc.encrypt(q["logits"], q["encrypt_seed"]) for q in qs]
         Ks, Cs = [q["K"] for q in qs], [q["C"] for q in qs]
@@ -642,10 +642,18 @@ def bootstrap_rate(n_batch=8, n_queries=32, pset="full_boot", packed=True, compa
         args = ([q["d_min"] for q in qs], [q["d_max"] for q in qs], [q["refresh_seed"] for q in qs])
         gc.eval_argmax_batch(qcts, Ks, Cs, *args, ws=wsb, owner=gc.owner)
         gc.sync()
+        if marks:
+            # fills of distinctive sizes mark the timed batch in a profiler's kernel trace
+            mk = torch.empty(max(marks), dtype=torch.float64, device="cuda")
+            mk[:marks[0]].fill_(1.0)
+            torch.cuda.synchronize()
         ta = time.perf_counter()
         zo = gc.eval_argmax_batch(qcts, Ks, Cs, *args, ws=wsb, owner=gc.owner)
         gc.sync()
         tb = time.perf_counter() - ta
+        if marks:
+            mk[:marks[1]].fill_(2.0)
+            torch.cuda.synchronize()
         cntb = gc.counters()
         ok = sum(int(gc.decrypt(z, q["C"])[1] == plain_argmax(q["logits"])[0]) for z, q in zip(zo, qs))
         return {"queries": n_queries, "argmax_per_s": round(n_queries / tb, 2), "bootstraps": cntb["refresh"],
@@ -666,7 +674,8 @@ def bootstrap_rate(n_batch=8, n_queries=32, pset="full_boot", packed=True, compa
         if big_batch:
             # the headline's 256 config-3 queries in one batch, refreshes window-packed
             try:
-                batch["window_packed_256"] = batch_rate(gp, [W.query(3, i) for i in range(256)])
+                batch["window_packed_256"] = batch_rate(gp, [W.query(3, i) for i in range(256)],
+                                                        marks=(4096 * 15, 4096 * 17))
             except (RuntimeError, SecpeError) as e:
                 batch["window_packed_256"] = {"error": str(e)[:200]}
             _log(f"256 queries, window-packed refreshes: {batch['window_packed_256']}")
@@ -690,6 +699,25 @@ def bootstrap_rate(n_batch=8, n_queries=32, pset="full_boot", packed=True, compa
                              "index_ok": bool(idx2 == plain_argmax(d2["logits"])[0])}
     out["argmax_config3_batch"] = batch
     _log(f"argmax with bootstrapping: {out['argmax_config2']} {out['argmax_config3_batch']}")
+    return out
+
+
+def serve_bootstrapped(n, max_active=32):
+    """The config-5 serving mix on one tenant of the bootstrapping set
+    (full_boot, N = 2^16, 35 chain primes), every refresh a bootstrap and
+    refreshes of two or more single queries window-packed: the server alone,
+    no key owner anywhere."""
+    from paper_2502_00847_amd.secpe import Context
+    g = Context(dict(W.PARAMS["full_boot"], boot_pack_min=2))
+    steps = sorted(set(g.boot_steps()) | set(g.argmax_steps(32, 20)), key=lambda v: (v < 0, v))
+    g.keygen(W.KEYGEN_SEED, steps)
+    g.owner = None
+    g.boot_setup()
+    per = max(g.lib.secpe_server_request_bytes(g.h, q["K"], q["C"]) for q in [W.query(5, i) for i in range(64)])
+    _log(f"bootstrapped serving: {per / 2**30:.2f} GiB per request, {max_active} outstanding at most")
+    out = serve([g], n, n // 10, max_active=max_active, distinct=64)
+    out["what"] = ("config-5 mix on the bootstrapping set (full_boot), one tenant, every refresh a bootstrap, "
+                   "window-packed; no key owner")
     return out
 
 
@@ -742,6 +770,9 @@ def main():
     ap.add_argument("--keyswitch", type=int, default=1, help="time 64 random-step rotations at 24 limbs")
     ap.add_argument("--calib", type=int, default=0, help="copy 1 GiB first (counter calibration kernel)")
     ap.add_argument("--variants", type=int, default=1, help="precise-Sign and large-n single-query runs")
+    ap.add_argument("--serve-boot", type=int, default=0,
+                    help="requests of a serving run where every refresh is a bootstrap (0 = skip)")
+    ap.add_argument("--serve-boot-active", type=int, default=96, help="outstanding requests in that run at most")
     ap.add_argument("--schedule", type=int, default=-1,
                     help="apply this autotuner candidate instead of searching (-1: search)")
     ap.add_argument("--ntt-only", type=int, default=0, help="only the NTT microbenchmark (64 x 2 x 24 limbs)")
@@ -769,6 +800,10 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.serve_boot:
+        print(json.dumps({"serving_bootstrapped": serve_bootstrapped(args.serve_boot, args.serve_boot_active)}),
+              flush=True)
+        return
     if args.boot_only:
         budget = bootstrap_rate(pset="full_boot128", packed=False, compare_full=False, big_batch=False)
         print(json.dumps({"bootstrapping": bootstrap_rate(), "bootstrapping_paper_budget": budget}), flush=True)
