@@ -772,7 +772,7 @@ def main():
     ap.add_argument("--variants", type=int, default=1, help="precise-Sign and large-n single-query runs")
     ap.add_argument("--serve-boot", type=int, default=0,
                     help="requests of a serving run where every refresh is a bootstrap (0 = skip)")
-    ap.add_argument("--serve-boot-active", type=int, default=96, help="outstanding requests in that run at most")
+    ap.add_argument("--serve-boot-active", type=int, default=192, help="outstanding requests in that run at most")
     ap.add_argument("--schedule", type=int, default=-1,
                     help="apply this autotuner candidate instead of searching (-1: search)")
     ap.add_argument("--ntt-only", type=int, default=0, help="only the NTT microbenchmark (64 x 2 x 24 limbs)")
